@@ -1,0 +1,357 @@
+"""Pins of the CPU oracle against things other than itself.
+
+Each test ties one oracle function to a closed form, a quadrature of the
+defining integral, an exact identity of the truncated system or brute force,
+so that a dropped term, a wrong sign, a wrong index or a transposed operand
+in the oracle fails at least one of them.
+"""
+import math
+
+import mpmath
+import numpy as np
+import pytest
+import scipy.special as sp
+
+import synth
+from oracle import bessel, farfield, geometry, gradient, operator, rhs, solve
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+# ---------------------------------------------------------------- Bessel values
+def test_bessel_vs_mpmath():
+    """J_m and H_m^(1) against 40-digit mpmath on a grid spanning the orders
+    and arguments of the workloads (orders up to 60, arguments 0.3..2500)."""
+    mpmath.mp.dps = 40
+    xs = [0.3, 0.5, 1.7, 3.14159, 7.9, 12.5, 19.0, 31.0, 64.2, 250.0, 1000.3, 2499.0]
+    for m in (0, 1, 2, 5, 13, 24, 40, 57, 60):
+        for x in xs:
+            jr = float(mpmath.besselj(m, x))
+            yr = float(mpmath.bessely(m, x))
+            h = bessel.hankel1(m, x)
+            # AMOS reaches ~1e-13 relative to |H| (at x ~ 1e3 the argument's own
+            # rounding already moves the phase by ~1e-13)
+            assert abs(h - (jr + 1j * yr)) <= 1e-12 * abs(jr + 1j * yr)
+            # J is compared absolutely, scaled by |H| (J alone has zeros)
+            assert abs(bessel.besselj(m, x) - jr) <= 1e-12 * abs(jr + 1j * yr)
+            # reflection to negative orders is exact
+            assert bessel.hankel1(-m, x) == (-1) ** m * h
+
+
+def test_wronskian():
+    """J_{n+1} Y_n - J_n Y_{n+1} = 2 / (pi x)."""
+    x = np.array([0.4, 1.0, 3.3, 10.0, 55.5, 700.0])
+    for n in range(0, 30):
+        # J from besselj (H's real part carries an error ~eps |Y| where J << Y)
+        Y0 = bessel.hankel1(n, x).imag
+        Y1 = bessel.hankel1(n + 1, x).imag
+        w = bessel.besselj(n + 1, x) * Y0 - bessel.besselj(n, x) * Y1
+        np.testing.assert_allclose(w, 2.0 / (np.pi * x), rtol=1e-12)
+
+
+def test_bessel_derivative_vs_scipy():
+    x = np.array([0.7, 4.2, 33.0])
+    for n in (-3, 0, 2, 11):
+        np.testing.assert_allclose(bessel.besselj_d(n, x), sp.jvp(n, x), rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(bessel.hankel1_d(n, x), sp.h1vp(n, x), rtol=1e-12)
+
+
+# ------------------------------------------------ quadrature of defining integrals
+def _circle(center, a, Q):
+    t = 2.0 * np.pi * np.arange(Q) / Q
+    return center[0] + a * np.cos(t), center[1] + a * np.sin(t), t
+
+
+def test_offdiag_block_vs_quadrature():
+    """L^{pq}_{mn} = <L Phi^q_n, Phi^p_m> (Hermitian product on Gamma_p), with
+    L Phi(x) = int_{Gamma_q} (i/4) H_0(k|x - y|) Phi(y) dGamma(y), computed by
+    the trapezoid rule on both circles (smooth periodic integrand: the disks
+    are disjoint)."""
+    centers = np.array([[0.3, -0.2], [1.9, 1.1], [-1.4, 1.6]])
+    radii = np.array([0.5, 0.7, 0.4])
+    n_modes = np.array([4, 6, 3])
+    k = 3.1
+    L = operator.efie_matrix(centers, radii, n_modes, k)
+    off, _ = geometry.mode_offsets(n_modes)
+    Q = 96
+    for p, q in [(0, 1), (1, 0), (2, 1), (0, 2)]:
+        xp, yp, tp = _circle(centers[p], radii[p], Q)
+        xq, yq, tq = _circle(centers[q], radii[q], Q)
+        G = 0.25j * sp.hankel1(0, k * np.hypot(xp[:, None] - xq[None, :], yp[:, None] - yq[None, :]))
+        wq = 2.0 * np.pi * radii[q] / Q
+        wp = 2.0 * np.pi * radii[p] / Q
+        for mi, m in enumerate(range(-n_modes[p], n_modes[p] + 1)):
+            phim = np.exp(1j * m * tp) / np.sqrt(2 * np.pi * radii[p])
+            for ni, n in enumerate(range(-n_modes[q], n_modes[q] + 1)):
+                phin = np.exp(1j * n * tq) / np.sqrt(2 * np.pi * radii[q])
+                val = np.sum(np.conj(phim)[:, None] * G * phin[None, :]) * wq * wp
+                got = L[off[p] + mi, off[q] + ni]
+                assert abs(got - val) <= 1e-11 * max(1.0, abs(val)), (p, q, m, n, got, val)
+
+
+def test_planewave_vs_quadrature():
+    """U^p_m = <u_inc, Phi^p_m> on Gamma_p (Prop. 4 from its definition)."""
+    centers = np.array([[0.3, -0.2], [2.5, 1.0]])
+    radii = np.array([0.5, 1.2])
+    n_modes = np.array([5, 9])
+    k, beta = 4.2, 0.77
+    U = rhs.planewave(centers, radii, n_modes, k, [beta])[0]
+    off, _ = geometry.mode_offsets(n_modes)
+    Q = 128
+    for p in range(2):
+        x, y, t = _circle(centers[p], radii[p], Q)
+        uinc = np.exp(1j * k * (np.cos(beta) * x + np.sin(beta) * y))
+        for mi, m in enumerate(range(-n_modes[p], n_modes[p] + 1)):
+            phim = np.exp(1j * m * t) / np.sqrt(2 * np.pi * radii[p])
+            val = np.sum(uinc * np.conj(phim)) * 2 * np.pi * radii[p] / Q
+            assert abs(U[off[p] + mi] - val) < 1e-13
+
+
+def test_farfield_vs_quadrature():
+    """a_L(theta) = (e^{i pi/4} / sqrt(8 k pi)) int_Gamma e^{-i k theta_hat.y} rho(y) dGamma
+    for rho = Phi^p_m (sec. 4.4 definition)."""
+    centers = np.array([[0.3, -0.2], [2.5, 1.0]])
+    radii = np.array([0.5, 1.2])
+    n_modes = np.array([5, 9])
+    k = 4.2
+    thetas = np.array([0.0, 0.4, 2.0, 4.4])
+    G = farfield.farfield_rows(centers, radii, n_modes, k, thetas)
+    off, _ = geometry.mode_offsets(n_modes)
+    Q = 128
+    for p in range(2):
+        x, y, t = _circle(centers[p], radii[p], Q)
+        for j, th in enumerate(thetas):
+            ker = np.exp(-1j * k * (np.cos(th) * x + np.sin(th) * y))
+            for mi, m in enumerate(range(-n_modes[p], n_modes[p] + 1)):
+                phim = np.exp(1j * m * t) / np.sqrt(2 * np.pi * radii[p])
+                val = (np.exp(0.25j * np.pi) / np.sqrt(8 * k * np.pi)
+                       * np.sum(ker * phim) * 2 * np.pi * radii[p] / Q)
+                assert abs(G[j, off[p] + mi] - val) < 1e-13
+
+
+# ------------------------------------------------------------- closed forms
+def _mie_farfield(center, a, k, beta, thetas, N):
+    """Textbook sound-soft cylinder: u_s = -sum_m i^m (J_m(ka)/H_m(ka)) H_m(kr) e^{im(phi-beta)}
+    about the cylinder center, times the incident phase e^{ik beta_hat.O};
+    H_m(kr) ~ sqrt(2/(pi k r)) e^{i(kr - m pi/2 - pi/4)} and the shift of origin
+    gives e^{-ik theta_hat.O}."""
+    m = np.arange(-N, N + 1)
+    ratio = sp.jv(m, k * a) / sp.hankel1(m, k * a)
+    O = np.asarray(center)
+    ph = np.exp(1j * k * ((np.cos(beta) - np.cos(thetas)) * O[0] + (np.sin(beta) - np.sin(thetas)) * O[1]))
+    s = np.sum(ratio[None, :] * np.exp(1j * m[None, :] * (thetas[:, None] - beta)), axis=1)
+    return -np.exp(-0.25j * np.pi) * np.sqrt(2.0 / (np.pi * k)) * ph * s
+
+
+@pytest.mark.parametrize("center,a,k,N", [((0.0, 0.0), 1.0, 2 * math.pi, 15),
+                                          ((1.3, -0.7), 0.45, 9.0, 12),
+                                          ((-2.0, 3.0), 2.0, 1.5, 10)])
+def test_single_disk_mie(center, a, k, N):
+    centers = np.array([center])
+    radii = np.array([a])
+    n_modes = np.array([N])
+    beta = 0.6
+    thetas = synth.uniform_angles(90)
+    L = operator.efie_matrix(centers, radii, n_modes, k)
+    U = rhs.planewave(centers, radii, n_modes, k, [beta])
+    rho = solve.efie_solve_lu(L, U)[0]
+    af = farfield.farfield(centers, radii, n_modes, k, thetas, rho)
+    ref = _mie_farfield(center, a, k, beta, thetas, N)
+    assert rel(af, ref) < 1e-13
+
+
+# ------------------------------------------------- boundary condition residual
+def test_boundary_condition_residual(tiny):
+    """u_inc + sum_q (single-layer potential of rho_q) vanishes on every Gamma_p.
+    The potentials of the other disks are integrated directly (trapezoid rule
+    on Gamma_q of (i/4) H_0(k|x-y|) rho_q(y)); the self term is the exact
+    on-boundary value of the potential of a Fourier mode.  This pins the
+    off-diagonal blocks (separation direction, transpose) independently of
+    the addition theorem: the residual is truncation-limited and shrinks with N."""
+    res = []
+    for N in (10, 15):
+        cl = tiny
+        n_modes = np.full(4, N)
+        L = operator.efie_matrix(cl.centers, cl.radii, n_modes, cl.k)
+        U = rhs.planewave(cl.centers, cl.radii, n_modes, cl.k, [0.0])
+        rho = solve.efie_solve_lu(L, U)[0]
+        off, _ = geometry.mode_offsets(n_modes)
+        Q = 128
+        worst = 0.0
+        m = np.arange(-N, N + 1)
+        for p in range(4):
+            x, y, t = _circle(cl.centers[p], cl.radii[p], 64)
+            tot = np.exp(1j * cl.k * x)
+            # self term: (i pi a/2) J_m H_m e^{im t} / sqrt(2 pi a)
+            rp = rho[off[p]:off[p + 1]]
+            coef = 0.5j * np.pi * cl.radii[p] * sp.jv(m, cl.k * cl.radii[p]) * sp.hankel1(m, cl.k * cl.radii[p])
+            tot = tot + np.exp(1j * np.outer(t, m)) @ (coef * rp) / np.sqrt(2 * np.pi * cl.radii[p])
+            for q in range(4):
+                if q == p:
+                    continue
+                xq, yq, tq = _circle(cl.centers[q], cl.radii[q], Q)
+                rq = np.exp(1j * np.outer(tq, m)) @ rho[off[q]:off[q + 1]] / np.sqrt(2 * np.pi * cl.radii[q])
+                G = 0.25j * sp.hankel1(0, cl.k * np.hypot(x[:, None] - xq[None, :], y[:, None] - yq[None, :]))
+                tot = tot + G @ rq * (2 * np.pi * cl.radii[q] / Q)
+            worst = max(worst, float(np.max(np.abs(tot))))
+        res.append(worst)
+    assert res[1] < 1e-4 and res[1] < res[0] / 10, res
+
+
+# --------------------------------------------------- exact identities of the system
+def test_transpose_identity():
+    """L^T = P L P with P the mode flip m -> -m in every block."""
+    cl = synth.small_random(11, 7, 0.3, 0.9, 8.0, 0.2, 4.0, 3)
+    L = operator.efie_matrix(cl.centers, cl.radii, cl.n_modes, cl.k)
+    P = operator.mode_flip(cl.n_modes)
+    assert rel(L[np.ix_(P, P)], L.T) < 1e-14
+
+
+def _solve_far(cl, betas, thetas):
+    L = operator.efie_matrix(cl.centers, cl.radii, cl.n_modes, cl.k)
+    U = rhs.planewave(cl.centers, cl.radii, cl.n_modes, cl.k, betas)
+    rho = solve.efie_solve_lu(L, U)
+    return farfield.farfield(cl.centers, cl.radii, cl.n_modes, cl.k, thetas, rho)
+
+
+def test_reciprocity():
+    """a(theta; beta) = a(beta + pi; theta + pi) for the truncated system."""
+    cl = synth.small_random(12, 6, 0.3, 0.8, 6.0, 0.2, 5.0, 4)
+    phi = np.array([0.1, 1.3, 2.9, 4.0, 5.5])
+    Fa = _solve_far(cl, phi, phi)                   # Fa[j, i] = a(phi_i; phi_j)
+    Fb = _solve_far(cl, phi + np.pi, phi + np.pi)   # Fb[j, i] = a(phi_i + pi; phi_j + pi)
+    assert rel(Fa, Fb.T) < 1e-12
+
+
+def test_optical_theorem():
+    """int_0^{2pi} |a(theta; beta)|^2 dtheta = -sqrt(8 pi / k) Re(e^{i pi/4} a(beta; beta))."""
+    cl = synth.small_random(13, 8, 0.2, 0.9, 7.0, 0.2, 3.7, 5)
+    beta = 0.9
+    rmax = np.max(np.hypot(cl.centers[:, 0], cl.centers[:, 1]))
+    nt = int(2 * (cl.k * rmax + np.max(cl.n_modes)) + 64)
+    th = synth.uniform_angles(nt)
+    a = _solve_far(cl, [beta], th)[0]
+    lhs = np.sum(np.abs(a) ** 2) * 2 * np.pi / nt
+    a0 = _solve_far(cl, [beta], [beta])[0, 0]
+    rhs_ = -np.sqrt(8 * np.pi / cl.k) * np.real(np.exp(0.25j * np.pi) * a0)
+    assert abs(lhs - rhs_) < 1e-12 * abs(rhs_)
+
+
+def test_tiny_reflection_symmetry(tiny):
+    """The 4-disk square is symmetric under y -> 3 - y; with beta = 0 this gives
+    a(theta) = e^{-3ik sin(theta)} a(-theta)."""
+    th = synth.uniform_angles(360)
+    a = _solve_far(tiny, [0.0], th)[0]
+    am = _solve_far(tiny, [0.0], -th)[0]
+    assert rel(a, np.exp(-3j * tiny.k * np.sin(th)) * am) < 1e-13
+
+
+def test_spectral_convergence(tiny):
+    th = synth.uniform_angles(90)
+    ref = None
+    errs = []
+    for N in (30, 8, 10, 12, 15, 18):
+        tiny_N = synth.Cluster(tiny.centers, tiny.radii, np.full(4, N), tiny.k)
+        a = _solve_far(tiny_N, [0.0], th)[0]
+        if ref is None:
+            ref = a
+            continue
+        errs.append(rel(a, ref))
+    assert all(errs[i + 1] < errs[i] / 5 for i in range(len(errs) - 1)), errs
+    assert errs[3] < 1e-8 and errs[-1] < 1e-11, errs
+
+
+def test_preconditioner_and_gmres_vs_lu(tiny):
+    """The single-scattering preconditioned system has the LU solution; GMRES at
+    tol 1e-12 reaches it (brute force)."""
+    cl = tiny
+    L = operator.efie_matrix(cl.centers, cl.radii, cl.n_modes, cl.k)
+    D = operator.efie_diagonal(cl.radii, cl.n_modes, cl.k)
+    A = operator.preconditioned(L, D)
+    U = rhs.planewave(cl.centers, cl.radii, cl.n_modes, cl.k, [0.0])[0]
+    f = -U / D
+    x_lu = solve.efie_solve_lu(L, U[None])[0]
+    assert rel(np.linalg.solve(A, f), x_lu) < 1e-13
+    x, flag, relres, it, resvec = solve.gmres(lambda v: A @ v, f, 30, 1e-12, 2000)
+    assert flag == 0 and relres <= 1e-12 and it > 5
+    assert rel(x, x_lu) < 1e-10
+    assert resvec[0] == 1.0 and len(resvec) == it + 1
+    # maxit forces FLAG 1
+    _, flag1, _, it1, _ = solve.gmres(lambda v: A @ v, f, 30, 1e-12, 3)
+    assert flag1 == 1 and it1 == 3
+
+
+def test_preconditioned_k_form():
+    """A = D^{-1} L has identity diagonal blocks and off-diagonal entries
+    sqrt(a_q/a_p) t_{n-m} J_n(k a_q) / H_m(k a_p) (J_m(k a_p) cancels)."""
+    cl = synth.small_random(14, 4, 0.3, 0.8, 5.0, 0.3, 3.0, 3)
+    L = operator.efie_matrix(cl.centers, cl.radii, cl.n_modes, cl.k)
+    A = operator.preconditioned(L, operator.efie_diagonal(cl.radii, cl.n_modes, cl.k))
+    off, _ = geometry.mode_offsets(cl.n_modes)
+    b, al = geometry.pair_geometry(cl.centers)
+    p, q = 2, 0
+    for mi, m in enumerate(range(-cl.n_modes[p], cl.n_modes[p] + 1)):
+        for ni, n in enumerate(range(-cl.n_modes[q], cl.n_modes[q] + 1)):
+            ref = (np.sqrt(cl.radii[q] / cl.radii[p]) * sp.hankel1(n - m, cl.k * b[p, q])
+                   * np.exp(1j * (n - m) * al[p, q]) * sp.jv(n, cl.k * cl.radii[q])
+                   / sp.hankel1(m, cl.k * cl.radii[p]))
+            assert abs(A[off[p] + mi, off[q] + ni] - ref) < 1e-13 * max(1, abs(ref))
+    blk = A[off[p]:off[p + 1], off[p]:off[p + 1]]
+    assert np.allclose(blk, np.eye(blk.shape[0]), atol=1e-15)
+
+
+def test_adjoint_via_forward_solve():
+    """lambda = P solve(L, P c) equals solve(L^T, c)."""
+    cl = synth.small_random(15, 6, 0.3, 0.8, 6.0, 0.2, 4.5, 3)
+    L = operator.efie_matrix(cl.centers, cl.radii, cl.n_modes, cl.k)
+    P = operator.mode_flip(cl.n_modes)
+    rng = np.random.default_rng(0)
+    c = rng.normal(size=L.shape[0]) + 1j * rng.normal(size=L.shape[0])
+    lam = np.linalg.solve(L.T, c)
+    lam2 = np.linalg.solve(L, c[P])[P]
+    assert rel(lam2, lam) < 1e-13
+
+
+# ---------------------------------------------------------------- gradient
+def _grad_case(seed=16):
+    base = synth.small_random(seed, 4, 0.4, 0.7, 5.0, 0.3, 3.0, 4, R=3, n_theta=5)
+    rng = np.random.default_rng(seed + 100)
+    tgt = synth.perturb(rng, base)
+    target = gradient.forward(tgt.centers, tgt.radii, tgt.n_modes, tgt.k, base.betas, base.thetas)
+    return base, target
+
+
+def test_gradient_vs_central_differences():
+    base, target = _grad_case()
+    args = (base.centers, base.radii, base.n_modes, base.k, base.betas, base.thetas, target)
+    loss, dc, da, dk = gradient.misfit_grad(*args)
+    assert abs(loss - gradient.misfit(*args)) < 1e-12 * loss
+    fc, fa, fk = gradient.misfit_fd(*args, h=1e-5)
+    g = np.concatenate([dc.ravel(), da, [dk]])
+    f = np.concatenate([fc.ravel(), fa, [fk]])
+    assert rel(g, f) < 1e-6
+    assert np.all(np.abs(g - f) <= 1e-6 * np.max(np.abs(f)) + 1e-6 * np.abs(f))
+
+
+def test_gradient_translation_and_scaling():
+    """Exact invariances of the truncated far field: translating every center by d
+    multiplies a(theta; beta) by e^{ik(beta_hat - theta_hat).d}; scaling lengths by s
+    and k by 1/s multiplies it by sqrt(s).  For the misfit this gives
+      sum_p dl/dx_p = 2 Re sum conj(e) ik(cos beta - cos theta) a   (same for y, sin),
+      sum_p (O_p . grad_p l + a_p dl/da_p) - k dl/dk = Re sum conj(e) a."""
+    base, target = _grad_case(17)
+    args = (base.centers, base.radii, base.n_modes, base.k, base.betas, base.thetas, target)
+    loss, dc, da, dk = gradient.misfit_grad(*args)
+    a = gradient.forward(*args[:-1])
+    e = a - target
+    cb, ct = np.cos(base.betas)[:, None], np.cos(base.thetas)[None, :]
+    sb, st = np.sin(base.betas)[:, None], np.sin(base.thetas)[None, :]
+    tx = 2 * np.real(np.sum(np.conj(e) * 1j * base.k * (cb - ct) * a))
+    ty = 2 * np.real(np.sum(np.conj(e) * 1j * base.k * (sb - st) * a))
+    scale = np.real(np.sum(np.conj(e) * a))
+    assert abs(np.sum(dc[:, 0]) - tx) < 1e-10 * (abs(tx) + np.max(np.abs(dc)))
+    assert abs(np.sum(dc[:, 1]) - ty) < 1e-10 * (abs(ty) + np.max(np.abs(dc)))
+    lhs = np.sum(base.centers * dc) + np.sum(base.radii * da) - base.k * dk
+    assert abs(lhs - scale) < 1e-10 * (abs(scale) + np.max(np.abs(dc)))

@@ -1,0 +1,223 @@
+"""Benchmark of the multiple-scattering hot path on one MI355X.
+
+Workload (one RHS): M = 400 disks of radius 0.5 placed by seeded rejection in
+[0,60]^2 with edge gap 0.2, k = 2 pi, N_p = 12 (10,000 complex128 unknowns),
+incidence pi/4, GMRES(50) to a 1e-8 relative residual, far field at 720 angles.
+
+One step = the whole hot path on that input: geometry and Bessel/Hankel tables
+on the device, plane-wave right-hand side, preconditioned restarted GMRES to
+1e-8 (operator applies + Gram-Schmidt), far field.  Inputs are host arrays of
+a few KB (centers, radii); everything else is produced and kept in HBM.
+
+Printed (one JSON line): value = complex unknown.RHS operator applications per
+second over the whole step (N_tot * R * applies / step time), plus the
+time-to-1e-8, the operator-apply rate alone, the roofline of the dominant
+kernel (the operator apply) and the CPU oracle timed on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_VECTOR_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_apply_one_rhs_traffic.txt")
+APPLY_SRC = os.path.join(ROOT, "paper_1409_8186_amd", "csrc", "matvec.hip")
+
+
+def algorithmic_flops(n_modes, R=1):
+    """8 real flops per complex MAC over every ordered pair: 8 R sum_{p != q} n_p n_q."""
+    n = [2 * int(N) + 1 for N in n_modes]
+    s = sum(n)
+    return 8.0 * R * (s * s - sum(x * x for x in n))
+
+
+def algorithmic_bytes(n_modes, R=1):
+    """Operator data: one H_nu(k b_pq) vector (nu = 0..N_p+N_q) per unordered pair,
+    the diagonal factors, and x, y once: 16 B per complex, 8 B per real."""
+    N = [int(x) for x in n_modes]
+    M = len(N)
+    pair = 0
+    for p in range(M):
+        for q in range(p + 1, M):
+            pair += N[p] + N[q] + 1
+    ntot = sum(2 * x + 1 for x in N)
+    return 16.0 * pair + ntot * (8 + 16) + 2 * 16.0 * R * ntot
+
+
+def traffic_per_launch():
+    """HBM bytes per apply launch from the committed rocprofv3 counter summary,
+    or None if absent or taken on a different revision of the kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    txt = open(TRAFFIC_FILE).read()
+    sha = hashlib.sha256(open(APPLY_SRC, "rb").read()).hexdigest()[:16]
+    m = re.search(r"source_sha256_16:\s*([0-9a-f]+)", txt)
+    f = re.search(r"fetch_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    w = re.search(r"write_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not (m and f and w) or m.group(1) != sha:
+        return None
+    return float(f.group(1)) + float(w.group(1))
+
+
+def cpu_baseline(cl, n_iter_gpu):
+    """The oracle on the host: dense assembly of the preconditioned EFIE matrix,
+    then oracle GMRES iterations (dense ZGEMV + modified Gram-Schmidt); the
+    whole-step rate is extrapolated to the GPU run's iteration count."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import farfield, operator, rhs, solve
+    t0 = time.perf_counter()
+    L = operator.efie_matrix(cl.centers, cl.radii, cl.n_modes, cl.k)
+    D = operator.efie_diagonal(cl.radii, cl.n_modes, cl.k)
+    A = operator.preconditioned(L, D)
+    del L
+    t_asm = time.perf_counter() - t0
+    U = rhs.planewave(cl.centers, cl.radii, cl.n_modes, cl.k, cl.betas)[0]
+    f = -U / D
+    n_sample = 30
+    t0 = time.perf_counter()
+    x, flag, relres, it, _ = solve.gmres(lambda v: A @ v, f, 50, 1e-30, n_sample)
+    t_it = (time.perf_counter() - t0) / it
+    t0 = time.perf_counter()
+    farfield.farfield(cl.centers, cl.radii, cl.n_modes, cl.k, cl.thetas, x)
+    t_ff = time.perf_counter() - t0
+    n_app = n_iter_gpu + math.ceil(n_iter_gpu / 50)
+    t_step = t_asm + n_app * t_it + t_ff
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    return {
+        "value": cl.n_tot * n_app / t_step, "unit": "complex unknown·RHS matvecs/s",
+        "cores": int(threads), "kind": "oracle",
+        "sample": (f"dense assembly ({t_asm:.1f} s) + {it} oracle GMRES(50) iterations "
+                   f"({t_it * 1e3:.1f} ms each: dense ZGEMV + MGS) + far field ({t_ff:.2f} s), "
+                   f"extrapolated to the GPU run's {n_iter_gpu} iterations "
+                   f"({n_app} applies): oracle step {t_step:.0f} s"),
+        "time_to_1e8_s_extrapolated": t_asm + n_app * t_it,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph", action="store_true", help="replay GMRES cycles as HIP graphs")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the hot path is a single-GPU build "
+              "(see the sharding notes in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1409_8186_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1409_8186_amd.build import build
+        build()
+    from paper_1409_8186_amd import Problem
+
+    torch.cuda.set_device(0)
+    cl = synth.one_rhs()
+    beta = [[math.pi / 4]]
+    th = torch.tensor(cl.thetas, device="cuda")
+
+    info = {}
+
+    def step():
+        P = Problem.from_cluster(cl)                          # geometry + tables
+        rho, flag, relres, iters, _ = P.gmres(betas=beta, restart=50, tol=1e-8, maxit=20000,
+                                              graph=args.graph)
+        a = P.farfield(rho, th)                              # far field, 720 angles
+        info["P"], info["iters"], info["flag"], info["relres"], info["a"] = P, iters, flag, relres, a
+        return P
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t0) / args.steps
+
+    iters = int(info["iters"][0])
+    flag = int(info["flag"][0])
+    assert flag == 0, f"GMRES did not converge (flag {flag})"
+    n_app = iters + math.ceil(iters / 50)           # Arnoldi applies + one residual per cycle
+    value = cl.n_tot * n_app / t_step
+
+    # time-to-1e-8 alone (tables prebuilt)
+    P = info["P"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P.gmres(betas=beta, restart=50, tol=1e-8, maxit=20000, graph=args.graph)
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t0
+
+    # dominant kernel: the operator apply, timed with events on the launch stream
+    x = torch.randn(cl.n_tot, dtype=torch.complex128, device="cuda")
+    y = P.empty(1)
+    for _ in range(5):
+        P.matvec(x, op=1, out=y)
+    n_rep = 200
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(n_rep):
+        P.matvec(x, op=1, out=y)
+    ev1.record()
+    ev1.synchronize()
+    t_apply = ev0.elapsed_time(ev1) / 1e3 / n_rep
+    flops = algorithmic_flops(cl.n_modes)
+    achieved = flops / t_apply / 1e12
+    traffic = traffic_per_launch()
+
+    out = {
+        "metric": "complex unknown·RHS matvecs/s",
+        "value": value,
+        "unit": "complex unknown·RHS matvecs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_step * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "complex128 (f64)",
+        "data": "synthetic (seeded disk cluster)",
+        "config": {"workload": "one_rhs: M=400 disks a=0.5 in [0,60]^2 gap 0.2, k=2pi, N_p=12 "
+                               "(10,000 unknowns), beta=pi/4, GMRES(50) to 1e-8, far field 720 angles",
+                   "n_unknowns": cl.n_tot, "R": 1, "gmres_iters": iters,
+                   "operator_applies_per_step": n_app, "graph": bool(args.graph)},
+        "time_to_1e8_ms": t_solve * 1e3,
+        "apply_us": t_apply * 1e6,
+        "apply_rate": cl.n_tot / t_apply,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
+                     "traffic": traffic,
+                     "kernel": "k_apply (operator apply, one RHS)",
+                     "algorithmic_flops_per_launch": flops,
+                     "algorithmic_bytes_per_launch": algorithmic_bytes(cl.n_modes)},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cl, iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,216 @@
+/*
+ * mudiff.h - C ABI of the MI355X (gfx950) multiple-scattering library.
+ *
+ * The library computes the spectral (Fourier-mode) boundary-integral solution
+ * of sound-soft multiple scattering by M disjoint disks, following Thierry,
+ * Antoine, Chniti & Alzubaidi, "mu-diff: an open-source Matlab toolbox for
+ * computing multiple scattering problems by disks" (arXiv:1409.8186):
+ *
+ *   problem    exterior Dirichlet Helmholtz problem, plane wave
+ *              u_inc = exp(i k beta_hat . x), time dependence exp(-i w t) (sec. 2);
+ *   unknowns   Fourier coefficients rho^p_m, m = -N_p..N_p, of the EFIE density
+ *              on every disk p (sec. 4.1 basis, sec. 5 truncation);
+ *   operator   truncated EFIE matrix L (sec. 4.2 block formulas):
+ *                L^{pp}_{mm} = (i pi a_p/2) J_m(k a_p) H_m(k a_p)
+ *                L^{pq}_{mn} = (i pi sqrt(a_p a_q)/2) J_m(k a_p) t^{pq}_{n-m} J_n(k a_q)
+ *                t^{pq}_nu   = H^(1)_nu(k b_pq) exp(i nu alpha_pq),
+ *              b_pq, alpha_pq the length and angle of O_p - O_q (sec. 4.1);
+ *   system     L rho = -U, U the plane-wave coefficients (Prop. 4), solved by
+ *              restarted GMRES with the single-scattering (block-diagonal)
+ *              preconditioner (sec. 5);
+ *   output     far field a(theta) = sum_p sum_m (a_L)^p_m(theta) rho^p_m (sec. 4.4).
+ *
+ * Conventions for every entry point
+ *   complex128  interleaved (re, im) doubles, 16-byte aligned (== C99 double
+ *               _Complex == torch.complex128).
+ *   [host]      pointers marked so are read synchronously during the call;
+ *               every other pointer is device memory (HIP / torch tensors).
+ *   streams     `stream` is a hipStream_t (NULL = default stream).  Calls
+ *               validate on the host, enqueue on `stream` and return; device
+ *               outputs are valid after the stream is synchronised.
+ *               mudiff_gmres and mudiff_grad synchronise `stream` themselves
+ *               (once per restart cycle) to test convergence.
+ *   batching    B independent instances (own disks, own k) share one handle.
+ *               Instance b owns disks [disk_off[b], disk_off[b+1]).  Vectors
+ *               are packed [B][R][N_b] with N_b = sum_{p in b} (2 N_p + 1):
+ *               inside a vector disks come in order and modes m = -N_p..N_p
+ *               ascending (sec. 5 block vector).  R is the number of
+ *               right-hand sides per instance (incidence angles).
+ *   memory      the library never allocates device memory: every device
+ *               buffer, workspaces included, is owned by the caller and must
+ *               outlive the calls that use it (the handle keeps pointers into
+ *               the tables workspace).  Workspace sizes come from the
+ *               *_workspace_size queries (bytes, 256-byte aligned base).
+ *   errors      the return value is a mudiff_status; mudiff_last_error()
+ *               returns a thread-local message for the last failing call.
+ *               Validation errors are detected before anything is enqueued.
+ */
+#ifndef MUDIFF_H
+#define MUDIFF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mudiff_ctx* mudiff_t;
+
+typedef enum {
+  MUDIFF_OK = 0,
+  MUDIFF_ERR_INVALID = 1,        /* bad count, pointer, non-finite value, k<=0, a<=0, N_p<0 ... */
+  MUDIFF_ERR_OVERLAP = 2,        /* two disks of one instance intersect or touch */
+  MUDIFF_ERR_NOMEM = 3,          /* workspace smaller than the queried size */
+  MUDIFF_ERR_DEVICE = 4,         /* a HIP runtime error (text in mudiff_last_error) */
+  MUDIFF_ERR_NOT_CONVERGED = 5   /* mudiff_grad: a forward or adjoint solve did not converge */
+} mudiff_status;
+
+/* matvec operators */
+enum {
+  MUDIFF_OP_L = 0,      /* y = L x                 (sec. 4.2, truncated as in sec. 5)        */
+  MUDIFF_OP_A = 1       /* y = D^{-1} L x = x + K x, D = diag(L^{pp}) (sec. 5 preconditioner) */
+};
+
+/* mudiff_gmres flags */
+enum {
+  MUDIFF_X0 = 1,        /* rho holds the initial guess on entry (else x0 = 0)          */
+  MUDIFF_GRAPH = 2      /* replay each restart cycle as one captured HIP graph          */
+};
+
+/* Largest accepted truncation order N_p and GMRES restart length. */
+#define MUDIFF_MAX_NP 200
+#define MUDIFF_MAX_RESTART 128
+
+/* ---------------------------------------------------------------- tables */
+
+/* Bytes of device workspace mudiff_tables needs for this batch (pure host
+ * computation, no device call).  Returns 0 for invalid arguments. */
+size_t mudiff_tables_workspace_size(int B, const int64_t* disk_off /*[host] B+1*/,
+                                    const int32_t* n_modes /*[host] M_tot*/);
+
+/* Geometry, Bessel/Hankel tables and the operator schedule (sec. 4.1-4.2).
+ *   B          number of instances, >= 1
+ *   disk_off   [host] B+1 disk offsets, disk_off[0] = 0, strictly increasing
+ *   centers    [host] [M_tot][2] disk centers (x, y)
+ *   radii      [host] [M_tot] radii a_p > 0
+ *   n_modes    [host] [M_tot] truncation orders 0 <= N_p <= MUDIFF_MAX_NP
+ *   k          [host] [B] wavenumbers > 0
+ *   workspace  device buffer of at least mudiff_tables_workspace_size bytes;
+ *              it holds the tables for the lifetime of the handle
+ *   out        receives the handle (host object; free with mudiff_destroy)
+ * Computes on the device: per disk J_m(k a_p), H_m(k a_p) (m = 0..N_p+1,
+ * Miller's downward recurrence for J, Neumann series / Hankel's expansion and
+ * upward recurrence for Y) and per unordered pair p<q the separation symbols
+ * t^{pq}_s, |s| <= N_p + N_q.  Errors: INVALID, OVERLAP (b_pq <= a_p + a_q),
+ * NOMEM, DEVICE. */
+int mudiff_tables(int B, const int64_t* disk_off, const double* centers, const double* radii,
+                  const int32_t* n_modes, const double* k, void* workspace, size_t ws_bytes,
+                  void* stream, mudiff_t* out);
+
+/* Releases the host handle (not the caller's device memory). */
+int mudiff_destroy(mudiff_t h);
+
+/* Unknowns per instance: n_tot[b] = N_b (host array of B entries). */
+int mudiff_sizes(mudiff_t h, int64_t* n_tot /*[host] B*/);
+
+/* Copies the per-disk diagonal values to device arrays (either may be NULL):
+ * J [sum_p (N_p+2)] = J_m(k a_p), H [sum_p (N_p+2)] complex128 = H_m(k a_p),
+ * m = 0..N_p+1, disks in order.  Used to check the tables. */
+int mudiff_disk_tables(mudiff_t h, double* J, void* H, void* stream);
+
+/* Copies the separation symbols of every unordered pair p<q (instance by
+ * instance, p-major) to `t` (complex128, device): pair after pair,
+ * t^{pq}_s for s = -(N_p+N_q)..(N_p+N_q).  `count` receives the number of
+ * complex values (host). `t` may be NULL to query `count`. */
+int mudiff_pair_tables(mudiff_t h, void* t, int64_t* count /*[host]*/, void* stream);
+
+/* ---------------------------------------------------------------- operator */
+
+size_t mudiff_matvec_workspace_size(mudiff_t h, int R);
+
+/* y = op(x) for R right-hand sides per instance (sec. 4.2 / sec. 5).
+ *   x, y       device complex128 [B][R][N_b], distinct buffers
+ *   op         MUDIFF_OP_L or MUDIFF_OP_A
+ *   workspace  device scratch of mudiff_matvec_workspace_size(h, R) bytes; it
+ *              must be zero-filled before its first use and every call leaves
+ *              it ready for the next one (its counters return to zero), so
+ *              one buffer serves any number of calls on one stream.  Calls
+ *              that overlap in time (several streams) need separate buffers.
+ * Off-diagonal blocks are applied as Toeplitz products in the mode
+ * difference n - m (the diagonal.Toeplitz.diagonal structure of sec. 5). */
+int mudiff_matvec(mudiff_t h, int R, const void* x, void* y, int op,
+                  void* workspace, size_t ws_bytes, void* stream);
+
+/* Plane-wave right-hand side (Prop. 4) for R incidence angles per instance.
+ *   beta       device [B][R] angles (radians), beta_hat = (cos beta, sin beta)
+ *   out        device complex128 [B][R][N_b]: U (precond = 0) or the GMRES
+ *              right-hand side f = -D^{-1} U (precond = 1). */
+int mudiff_rhs(mudiff_t h, int R, const double* beta, void* out, int precond, void* stream);
+
+/* ---------------------------------------------------------------- solver */
+
+size_t mudiff_gmres_workspace_size(mudiff_t h, int R, int restart, int flags);
+
+/* Restarted GMRES(restart) on A x = f, A = D^{-1} L, f = -D^{-1} U (sec. 5),
+ * one independent Krylov space per (instance, right-hand side) column, all
+ * columns sharing every operator application (lockstep batching).
+ *   beta       device [B][R] incidence angles, or NULL to use `rhs`
+ *   rhs        device complex128 [B][R][N_b]: the right-hand side U of
+ *              L rho = -U (used when beta == NULL)
+ *   rho        device complex128 [B][R][N_b] output density; with MUDIFF_X0
+ *              it holds the initial guess on entry
+ *   restart    1..MUDIFF_MAX_RESTART;  tol > 0;  maxit >= 1 counts inner
+ *              iterations (operator applications in the Arnoldi process)
+ *   flag       device int32 [B][R]: 0 converged (relres <= tol), 1 maxit
+ *              reached, 2 breakdown without convergence or a non-finite value
+ *   relres     device double [B][R]: true ||f - A x|| / ||f|| at exit
+ *   iters      device int32 [B][R]: inner iterations performed
+ *   resvec     device double [B][R][maxit+1] Arnoldi residual estimates
+ *              |g_{j+1}| / ||f|| (entry 0 = initial), or NULL
+ * Non-convergence is not an error: the call returns MUDIFF_OK with flag != 0.
+ * Columns that converge stop iterating (their Krylov work is skipped). */
+int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* rhs, void* rho,
+                 int restart, double tol, int maxit, int flags,
+                 void* workspace, size_t ws_bytes,
+                 int32_t* flag, double* relres, int32_t* iters, double* resvec,
+                 void* stream);
+
+/* ---------------------------------------------------------------- far field */
+
+/* a(theta_j) = sum_p sum_m (a_L)^p_m(theta_j) rho^p_m (sec. 4.4), for the
+ * single-layer density rho [B][R][N_b] (complex128, device).
+ *   theta      device [n_theta] angles (radians), direction (cos, sin)
+ *   a_out      device complex128 [B][R][n_theta] */
+int mudiff_farfield(mudiff_t h, int R, const void* rho, int n_theta, const double* theta,
+                    void* a_out, void* stream);
+
+/* ---------------------------------------------------------------- gradient */
+
+size_t mudiff_grad_workspace_size(mudiff_t h, int R, int n_rec, int restart, int flags);
+
+/* Misfit loss_b = sum_{r, j} |a_b(theta_j; beta_{b,r}) - target_{b,r,j}|^2 of the
+ * far field of every instance, and its gradient with respect to every disk
+ * center, radius and the wavenumber (truncation orders held fixed), by one
+ * forward and one adjoint solve per column.  The adjoint solve reuses the
+ * forward operator through L^T = P L P (P flips m -> -m in every disk).
+ *   beta       device [B][R] incidence angles
+ *   theta_rec  device [n_rec] receiver angles
+ *   target     device complex128 [B][R][n_rec]
+ *   loss       device double [B]
+ *   d_centers  device double [M_tot][2];  d_radii [M_tot];  d_k [B]
+ * Returns MUDIFF_ERR_NOT_CONVERGED (outputs undefined) if a solve fails to
+ * reach tol within maxit. */
+int mudiff_grad(mudiff_t h, int R, const double* beta, int n_rec, const double* theta_rec,
+                const void* target, int restart, double tol, int maxit, int flags,
+                void* workspace, size_t ws_bytes,
+                double* loss, double* d_centers, double* d_radii, double* d_k, void* stream);
+
+/* Thread-local message of the last failing call on this thread. */
+const char* mudiff_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MUDIFF_H */

@@ -1,0 +1,226 @@
+"""Python binding of libmudiff (include/mudiff.h): argument marshalling only.
+
+PyTorch supplies the device memory (tensors) and the stream (the current
+torch stream); every computation runs in the HIP kernels behind the C ABI.
+
+Vectors are flat complex128 tensors packed [B][R][N_b] (instance, right-hand
+side, unknown), unknowns of an instance ordered disk by disk with modes
+m = -N_p..N_p.  ``Problem.split`` / ``Problem.pack`` convert to and from a list
+of [R, N_b] tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _p(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _host(a, dtype):
+    return np.ascontiguousarray(np.asarray(a, dtype=dtype))
+
+
+class Problem:
+    """B independent disk clusters sharing one set of device tables.
+
+    ``instances``: sequence of (centers [M,2], radii [M], n_modes [M], k).
+    """
+
+    def __init__(self, instances: Sequence, device: str = "cuda"):
+        self.lib = L.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("libmudiff needs a HIP device")
+        self.device = torch.device(device)
+        cs, rs, ns, ks, offs = [], [], [], [], [0]
+        for (c, r, n, k) in instances:
+            c = _host(c, np.float64).reshape(-1, 2)
+            cs.append(c)
+            rs.append(_host(r, np.float64).reshape(-1))
+            ns.append(_host(n, np.int32).reshape(-1))
+            ks.append(float(k))
+            offs.append(offs[-1] + c.shape[0])
+        self.B = len(ks)
+        self.centers = np.ascontiguousarray(np.concatenate(cs))
+        self.radii = np.ascontiguousarray(np.concatenate(rs))
+        self.n_modes = np.ascontiguousarray(np.concatenate(ns))
+        self.k = _host(ks, np.float64)
+        self.disk_off = _host(offs, np.int64)
+        ws = self.lib.mudiff_tables_workspace_size(self.B, self.disk_off.ctypes.data,
+                                                   self.n_modes.ctypes.data)
+        if ws == 0:
+            raise L.MudiffError(1, "invalid sizes (disk_off / n_modes)")
+        self.ws = torch.empty(int(ws), dtype=torch.uint8, device=self.device)
+        assert self.ws.data_ptr() % 256 == 0
+        h = ctypes.c_void_p()
+        L.check(self.lib.mudiff_tables(self.B, self.disk_off.ctypes.data, self.centers.ctypes.data,
+                                       self.radii.ctypes.data, self.n_modes.ctypes.data,
+                                       self.k.ctypes.data, _p(self.ws), int(ws), _stream(),
+                                       ctypes.byref(h)))
+        self.h = h
+        n = np.zeros(self.B, np.int64)
+        L.check(self.lib.mudiff_sizes(h, n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        self.n_tot = n
+        self.N_all = int(n.sum())
+        self._mv_ws = {}
+
+    @classmethod
+    def from_cluster(cls, cl, device="cuda"):
+        return cls([(cl.centers, cl.radii, cl.n_modes, cl.k)], device)
+
+    @classmethod
+    def from_clusters(cls, cls_list, device="cuda"):
+        return cls([(c.centers, c.radii, c.n_modes, c.k) for c in cls_list], device)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mudiff_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ----------------------------------------------------------- layout helpers
+    def empty(self, R: int = 1) -> torch.Tensor:
+        return torch.empty(R * self.N_all, dtype=torch.complex128, device=self.device)
+
+    def split(self, v: torch.Tensor, R: int = 1) -> list:
+        out, o = [], 0
+        for b in range(self.B):
+            n = int(self.n_tot[b])
+            out.append(v[o:o + R * n].view(R, n))
+            o += R * n
+        return out
+
+    def pack(self, parts) -> torch.Tensor:
+        return torch.cat([torch.as_tensor(p).reshape(-1) for p in parts]).to(
+            self.device, torch.complex128).contiguous()
+
+    def _f64(self, a) -> torch.Tensor:
+        return torch.as_tensor(np.asarray(a, dtype=np.float64)).to(self.device).contiguous()
+
+    # ----------------------------------------------------------- tables
+    def disk_tables(self):
+        D = int(np.sum(self.n_modes + 2))
+        J = torch.empty(D, dtype=torch.float64, device=self.device)
+        H = torch.empty(D, dtype=torch.complex128, device=self.device)
+        L.check(self.lib.mudiff_disk_tables(self.h, _p(J), _p(H), _stream()))
+        return J, H
+
+    def pair_tables(self):
+        cnt = ctypes.c_int64()
+        L.check(self.lib.mudiff_pair_tables(self.h, None, ctypes.byref(cnt), _stream()))
+        t = torch.empty(max(cnt.value, 1), dtype=torch.complex128, device=self.device)
+        L.check(self.lib.mudiff_pair_tables(self.h, _p(t), ctypes.byref(cnt), _stream()))
+        return t[:cnt.value]
+
+    # ----------------------------------------------------------- operator
+    def matvec_workspace(self, R: int) -> torch.Tensor:
+        if R not in self._mv_ws:
+            n = self.lib.mudiff_matvec_workspace_size(self.h, R)
+            # zero once: the library leaves its counters at zero after every call
+            self._mv_ws[R] = torch.zeros(int(n), dtype=torch.uint8, device=self.device)
+        return self._mv_ws[R]
+
+    def matvec(self, x: torch.Tensor, R: int = 1, op: int = L.OP_A, out=None) -> torch.Tensor:
+        x = x.contiguous()
+        assert x.dtype == torch.complex128 and x.numel() == R * self.N_all
+        y = self.empty(R) if out is None else out
+        ws = self.matvec_workspace(R)
+        L.check(self.lib.mudiff_matvec(self.h, R, _p(x), _p(y), op, _p(ws), ws.numel(), _stream()))
+        return y
+
+    def rhs(self, betas, precond: bool = False) -> torch.Tensor:
+        """betas: [B, R] incidence angles."""
+        b = self._f64(betas).reshape(self.B, -1)
+        R = b.shape[1]
+        out = self.empty(R)
+        L.check(self.lib.mudiff_rhs(self.h, R, _p(b), _p(out), int(precond), _stream()))
+        return out
+
+    # ----------------------------------------------------------- solver
+    def gmres_workspace(self, R: int, restart: int, flags: int = 0) -> torch.Tensor:
+        n = self.lib.mudiff_gmres_workspace_size(self.h, R, restart, flags)
+        if n == 0:
+            raise L.MudiffError(1, "invalid gmres sizes")
+        return torch.empty(int(n), dtype=torch.uint8, device=self.device)
+
+    def gmres(self, betas=None, rhs=None, R: int | None = None, restart: int = 50,
+              tol: float = 1e-8, maxit: int = 20000, x0=None, graph: bool = False,
+              want_resvec: bool = False, workspace=None):
+        """Solves L rho = -U.  Returns (rho, flag, relres, iters, resvec)."""
+        flags = 0
+        bt = None
+        if betas is not None:
+            bt = self._f64(betas).reshape(self.B, -1)
+            R = bt.shape[1]
+        else:
+            assert rhs is not None and R is not None
+            rhs = rhs.contiguous()
+        rho = self.empty(R)
+        if x0 is not None:
+            rho.copy_(x0)
+            flags |= L.X0
+        if graph:
+            flags |= L.GRAPH
+        ws = workspace if workspace is not None else self.gmres_workspace(R, restart, flags)
+        C = self.B * R
+        flag = torch.empty(C, dtype=torch.int32, device=self.device)
+        relres = torch.empty(C, dtype=torch.float64, device=self.device)
+        iters = torch.empty(C, dtype=torch.int32, device=self.device)
+        resvec = (torch.empty(C * (maxit + 1), dtype=torch.float64, device=self.device)
+                  if want_resvec else None)
+        L.check(self.lib.mudiff_gmres(self.h, R, _p(bt), _p(rhs), _p(rho), restart, tol, maxit,
+                                      flags, _p(ws), ws.numel(), _p(flag), _p(relres), _p(iters),
+                                      _p(resvec), _stream()))
+        if resvec is not None:
+            resvec = resvec.view(C, maxit + 1)
+        return rho, flag, relres, iters, resvec
+
+    # ----------------------------------------------------------- far field
+    def farfield(self, rho: torch.Tensor, thetas, R: int = 1) -> torch.Tensor:
+        th = self._f64(thetas).reshape(-1)
+        out = torch.empty(self.B * R * th.numel(), dtype=torch.complex128, device=self.device)
+        L.check(self.lib.mudiff_farfield(self.h, R, _p(rho.contiguous()), th.numel(), _p(th),
+                                         _p(out), _stream()))
+        return out.view(self.B * R, th.numel())
+
+    # ----------------------------------------------------------- gradient
+    def grad_workspace(self, R: int, n_rec: int, restart: int, flags: int = 0) -> torch.Tensor:
+        n = self.lib.mudiff_grad_workspace_size(self.h, R, n_rec, restart, flags)
+        if n == 0:
+            raise L.MudiffError(1, "invalid grad sizes")
+        return torch.empty(int(n), dtype=torch.uint8, device=self.device)
+
+    def grad(self, betas, thetas, target, restart: int = 50, tol: float = 1e-12,
+             maxit: int = 20000, flags: int = 0, workspace=None):
+        """Far-field misfit per instance and its gradient w.r.t. centers, radii, k.
+        target: [B*R, n_rec] complex.  Returns (loss[B], d_centers[M,2], d_radii[M], d_k[B])."""
+        bt = self._f64(betas).reshape(self.B, -1)
+        R = bt.shape[1]
+        th = self._f64(thetas).reshape(-1)
+        tg = torch.as_tensor(target).to(self.device, torch.complex128).contiguous()
+        assert tg.numel() == self.B * R * th.numel()
+        ws = workspace if workspace is not None else self.grad_workspace(R, th.numel(), restart, flags)
+        M = self.radii.shape[0]
+        loss = torch.empty(self.B, dtype=torch.float64, device=self.device)
+        dc = torch.empty(M * 2, dtype=torch.float64, device=self.device)
+        da = torch.empty(M, dtype=torch.float64, device=self.device)
+        dk = torch.empty(self.B, dtype=torch.float64, device=self.device)
+        L.check(self.lib.mudiff_grad(self.h, R, _p(bt), th.numel(), _p(th), _p(tg), restart, tol,
+                                     maxit, flags, _p(ws), ws.numel(), _p(loss), _p(dc), _p(da),
+                                     _p(dk), _stream()))
+        return loss, dc.view(M, 2), da, dk

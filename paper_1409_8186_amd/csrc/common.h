@@ -1,0 +1,155 @@
+// Shared definitions of the gfx950 multiple-scattering library: complex128
+// helpers, the device view of the tables and the host handle.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/mudiff.h"
+
+// ------------------------------------------------------------------ complex128
+typedef double2 cplx;  // (x, y) = (re, im), 16-byte aligned
+
+__host__ __device__ __forceinline__ cplx cmk(double re, double im) { return make_double2(re, im); }
+__host__ __device__ __forceinline__ cplx cadd(cplx a, cplx b) { return cmk(a.x + b.x, a.y + b.y); }
+__host__ __device__ __forceinline__ cplx csub(cplx a, cplx b) { return cmk(a.x - b.x, a.y - b.y); }
+__host__ __device__ __forceinline__ cplx cscale(cplx a, double s) { return cmk(a.x * s, a.y * s); }
+__host__ __device__ __forceinline__ cplx cmul(cplx a, cplx b) {
+  return cmk(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+__host__ __device__ __forceinline__ cplx cconj(cplx a) { return cmk(a.x, -a.y); }
+// acc += a * b
+__host__ __device__ __forceinline__ void cmac(cplx& acc, cplx a, cplx b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+}
+// acc += conj(a) * b
+__host__ __device__ __forceinline__ void cmacc(cplx& acc, cplx a, cplx b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(-a.y, b.x, acc.y);
+}
+__host__ __device__ __forceinline__ cplx cdiv(cplx a, cplx b) {
+  // Smith's algorithm
+  if (fabs(b.x) >= fabs(b.y)) {
+    double r = b.y / b.x, d = b.x + b.y * r;
+    return cmk((a.x + a.y * r) / d, (a.y - a.x * r) / d);
+  }
+  double r = b.x / b.y, d = b.x * r + b.y;
+  return cmk((a.x * r + a.y) / d, (a.y * r - a.x) / d);
+}
+__host__ __device__ __forceinline__ double cabs2(cplx a) { return a.x * a.x + a.y * a.y; }
+__device__ __forceinline__ cplx cexpi(double t) {
+  double s, c;
+  sincos(t, &s, &c);
+  return cmk(c, s);
+}
+
+// ------------------------------------------------------------------ device view
+// Plain pointers into the tables workspace, passed to kernels by value.
+struct DevView {
+  int B, M_all;
+  int64_t N_all;              // unknowns of one column set (sum over instances)
+  const double* cx;           // [M_all] center x
+  const double* cy;           // [M_all] center y
+  const double* a;            // [M_all] radius
+  const double* kd;           // [M_all] wavenumber of the disk's instance
+  const int32_t* N;           // [M_all] truncation order N_p
+  const int32_t* inst;        // [M_all] instance of the disk
+  const int64_t* moff;        // [M_all] offset of the disk's modes inside its instance vector
+  const int64_t* dtab;        // [M_all] offset of the disk in the J/H diagonal tables
+  const int64_t* idisk;       // [B+1] first disk of each instance
+  const int64_t* imode;       // [B+1] unknown offset of each instance (one column)
+  const int64_t* ipair;       // [B+1] first unordered pair of each instance
+  const int64_t* toff;        // [P_all] offset of each pair's symbol row in t
+  cplx* t;                    // [T_all] separation symbols, rows t_s, s = -S..S
+  double* Jd;                 // [sum (N_p+2)] J_m(k a_p), m = 0..N_p+1
+  cplx* Hd;                   // [sum (N_p+2)] H_m(k a_p)
+  double* sJ;                 // [N_all] sqrt(a_p) J_m(k a_p)
+  cplx* invSH;                // [N_all] 1 / (sqrt(a_p) H_m(k a_p))
+  cplx* Ldiag;                // [N_all] (i pi a_p / 2) J_m(k a_p) H_m(k a_p)
+  int32_t* udisk;             // [N_all] disk of each unknown
+};
+
+// Column c = b * R + r of a packed [B][R][N_b] vector starts at
+// R * imode[b] + r * N_b.
+__host__ __device__ __forceinline__ int64_t col_base(const int64_t* imode, int b, int R, int r) {
+  return (int64_t)R * imode[b] + (int64_t)r * (imode[b + 1] - imode[b]);
+}
+
+// Unordered pair index of disks (p, q), p != q, of instance b (global disk ids).
+__host__ __device__ __forceinline__ int64_t pair_index(const int64_t* idisk, const int64_t* ipair,
+                                                       int b, int p, int q) {
+  int64_t d0 = idisk[b], M = idisk[b + 1] - d0;
+  int64_t i = (p < q ? p : q) - d0, j = (p < q ? q : p) - d0;
+  return ipair[b] + i * (2 * M - i - 1) / 2 + (j - i - 1);
+}
+
+// ------------------------------------------------------------------ host side
+struct MatvecPlan {
+  int Bt = 0;                   // outputs per thread of the generic kernel
+  int spec_N = -1;              // >= 0: uniform-N specialised kernel
+  int zs = 0, ts = 0;            // LDS row strides (z rows, symbol rows)
+  int ppcap = 1;                 // most column disks staged per pass
+  int n_items = 0;
+  size_t lds_bytes = 0;
+  int64_t part_total = 0;       // complex partials per right-hand side
+  int32_t* d_items = nullptr;   // [n_items][4] : p, chunk, q_begin, q_end
+  int32_t* d_nchunk = nullptr;  // [M_all]
+  int64_t* d_partoff = nullptr; // [M_all]
+};
+
+struct mudiff_ctx {
+  int B = 0, M_all = 0, Nmax = 0;
+  int64_t N_all = 0, P_all = 0, T_all = 0, D_all = 0;
+  std::vector<int64_t> idisk, imode, ipair, moff, toff, dtab;
+  std::vector<int32_t> N, inst;
+  std::vector<double> k, cx, cy, a;
+  DevView dv{};
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  // schedule area inside the tables workspace
+  char* sched_base = nullptr;
+  size_t sched_bytes = 0;
+  MatvecPlan plan;
+  int64_t plan_part = -1;       // partial sums per right-hand side of the plan
+};
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string& msg);
+int fail(int status, const std::string& msg);
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t _e = (expr);                                                             \
+    if (_e != hipSuccess)                                                               \
+      return fail(MUDIFF_ERR_DEVICE, std::string(#expr ": ") + hipGetErrorString(_e));  \
+  } while (0)
+
+static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// ------------------------------------------------------------------ internal API
+// Internal apply output: the raw off-diagonal contraction
+// w_m = sum_{q != p} sum_n t^{pq}_{n-m} sqrt(a_q) J_n(k a_q) x^q_n.
+#define OP_RAW_W 7
+
+// Operator apply on R columns. `part`/`counters` come from the caller's scratch
+// (mudiff_matvec_workspace_size); counters must be zero on entry and are left
+// zero. `active` (optional, [B*R]) skips columns whose entry is 0.
+int apply_operator(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, cplx* part,
+                   int32_t* counters, const int32_t* active, hipStream_t s);
+size_t apply_scratch_bytes(mudiff_ctx* h, int R);
+int ensure_plan(mudiff_ctx* h, hipStream_t s);
+struct PlanHost;
+void make_plan(int B, const int64_t* idisk, const int32_t* N, PlanHost& P);
+size_t plan_sched_bytes(const PlanHost& P, int M);
+
+int launch_rhs(mudiff_ctx* h, int R, const double* beta, cplx* out, int precond, hipStream_t s);
+int launch_fill_zero(void* p, size_t bytes, hipStream_t s);

@@ -1,0 +1,363 @@
+// Operator apply y = L x or y = D^{-1} L x (paper sec. 4.2 block formulas,
+// sec. 5 single-scattering preconditioner).
+//
+// Off-diagonal block (p, q):  (L^{pq} x^q)_m = (i pi/2) s_m sum_n t^{pq}_{n-m} z^q_n,
+//   s_m = sqrt(a_p) J_m(k a_p),  z^q_n = sqrt(a_q) J_n(k a_q) x^q_n,
+// a Toeplitz product in the mode difference n - m.  The preconditioned form
+// divides row m of disk p by L^{pp}_{mm}: (A x)_m = x_m + w_m / (sqrt(a_p) H_m(k a_p)),
+// w_m = sum_{q != p} sum_n t^{pq}_{n-m} z^q_n (J_m(k a_p) cancels exactly).
+//
+// Work decomposition: an item is (row disk p, chunk of column disks).  A
+// 256-thread workgroup stages, for a pass of PP column disks, the symbol rows
+// t^{pq} and the scaled inputs z^q in LDS (coalesced global loads), then each
+// thread accumulates BT consecutive outputs m of one pair over all n.  Chunk
+// partial sums go to scratch; the last workgroup of a row (atomic counter)
+// adds them in chunk order, so the result does not depend on scheduling.
+#include "common.h"
+
+
+#define APPLY_THREADS 256
+#define APPLY_NPASS 2
+
+__global__ void k_fill_zero(uint32_t* p, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = 0u;
+}
+
+int launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
+  size_t n = bytes / 4;
+  if (n == 0) return MUDIFF_OK;
+  unsigned g = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_fill_zero, dim3(g), dim3(256), 0, s, (uint32_t*)p, n);
+  HIP_TRY(hipGetLastError());
+  return MUDIFF_OK;
+}
+
+// acc[b] += sum_n tb[n - b] z[n],  tb = trow + (LB - 1) - m0
+template <int BT, int NQ>
+__device__ __forceinline__ void toeplitz_block(const cplx* __restrict__ zrow,
+                                               const cplx* __restrict__ tb, int nq_pad,
+                                               cplx (&acc)[BT]) {
+  if constexpr (NQ > 0) {
+#pragma unroll
+    for (int n = 0; n < NQ; ++n) {
+      const cplx z = zrow[n];
+#pragma unroll
+      for (int b = 0; b < BT; ++b) cmac(acc[b], tb[n - b], z);
+    }
+  } else {
+    for (int n0 = 0; n0 < nq_pad; n0 += BT) {
+#pragma unroll
+      for (int d = 0; d < BT; ++d) {
+        const cplx z = zrow[n0 + d];
+#pragma unroll
+        for (int b = 0; b < BT; ++b) cmac(acc[b], tb[n0 + d - b], z);
+      }
+    }
+  }
+}
+
+// Output of row unknown i from x_i and the off-diagonal contraction w_i.
+__device__ __forceinline__ cplx finalize(const DevView& v, int op, int64_t i, cplx xv, cplx w) {
+  if (op == MUDIFF_OP_A) return cadd(xv, cmul(v.invSH[i], w));
+  if (op == OP_RAW_W) return w;
+  const double f = 0.5 * 3.14159265358979323846 * v.sJ[i];  // (i pi / 2) s_m w
+  return cadd(cmul(v.Ldiag[i], xv), cmk(-f * w.y, f * w.x));
+}
+
+// NSPEC >= 0: every disk of the launch has N_p = NSPEC (exact loop bounds).
+template <int BT, int NSPEC>
+__global__ __launch_bounds__(APPLY_THREADS) void k_apply(
+    DevView v, int R, const cplx* __restrict__ x, cplx* __restrict__ y, int op,
+    cplx* __restrict__ part, int64_t part_total, int32_t* __restrict__ counters,
+    const int32_t* __restrict__ items, const int32_t* __restrict__ nchunk,
+    const int64_t* __restrict__ partoff, const int32_t* __restrict__ active, int zs, int ts,
+    int ppcap) {
+  extern __shared__ cplx lds[];
+  __shared__ int s_last;
+  const int it = blockIdx.x, r = blockIdx.y;
+  const int p = items[4 * it], c = items[4 * it + 1], jb = items[4 * it + 2], je = items[4 * it + 3];
+  const int b = v.inst[p];
+  if (active && active[b * R + r] == 0) return;
+  const int Np = NSPEC >= 0 ? NSPEC : v.N[p];
+  const int np = 2 * Np + 1;
+  const int L = (np + BT - 1) / BT;
+  const int LB = L * BT;
+  const int PP = min(APPLY_THREADS / L, ppcap);
+  const int64_t d0 = v.idisk[b];
+  const int64_t i0 = v.imode[b];
+  const int64_t cb = col_base(v.imode, b, R, r);
+  const cplx* __restrict__ xc = x + cb;
+  const int tid = threadIdx.x;
+  const int slot = tid / L, mb = tid - (tid / L) * L;
+  const int m0 = mb * BT;
+  cplx* zl = lds;                 // [PP][zs]
+  cplx* tl = lds + PP * zs;       // [PP][ts]
+
+  cplx acc[BT];
+#pragma unroll
+  for (int k = 0; k < BT; ++k) acc[k] = cmk(0.0, 0.0);
+
+  for (int j0 = jb; j0 < je; j0 += PP) {
+    const int nslot = min(PP, je - j0);
+    __syncthreads();
+    // stage z^q = sqrt(a_q) J_n(k a_q) x^q_n
+    for (int e = tid; e < PP * zs; e += APPLY_THREADS) {
+      const int k = e / zs, n = e - (e / zs) * zs;
+      cplx z = cmk(0.0, 0.0);
+      if (k < nslot) {
+        const int q = (int)(d0 + j0 + k + ((d0 + j0 + k) >= p ? 1 : 0));
+        const int nq = 2 * (NSPEC >= 0 ? NSPEC : v.N[q]) + 1;
+        if (n < nq) {
+          const int64_t iq = v.moff[q] + n;
+          z = cscale(xc[iq], v.sJ[i0 + iq]);
+        }
+      }
+      zl[e] = z;
+    }
+    // stage symbol rows: u = n - m + LB - 1  <->  s = u - (LB - 1) - N_q + N_p
+    for (int e = tid; e < PP * ts; e += APPLY_THREADS) {
+      const int k = e / ts, u = e - (e / ts) * ts;
+      cplx t = cmk(0.0, 0.0);
+      if (k < nslot) {
+        const int q = (int)(d0 + j0 + k + ((d0 + j0 + k) >= p ? 1 : 0));
+        const int Nq = NSPEC >= 0 ? NSPEC : v.N[q];
+        const int S = Np + Nq;
+        const int s = u - (LB - 1) - Nq + Np;
+        if (s >= -S && s <= S) {
+          const int64_t g = pair_index(v.idisk, v.ipair, b, p, q);
+          t = v.t[v.toff[g] + S + s];
+          if (p > q && (s & 1)) t = cmk(-t.x, -t.y);  // t^{qp}_s = (-1)^s t^{pq}_s
+        }
+      }
+      tl[e] = t;
+    }
+    __syncthreads();
+    if (slot < nslot) {
+      const cplx* tb = tl + slot * ts + (LB - 1) - m0;
+      if constexpr (NSPEC >= 0)
+        toeplitz_block<BT, 2 * NSPEC + 1>(zl + slot * zs, tb, 0, acc);
+      else
+        toeplitz_block<BT, 0>(zl + slot * zs, tb, zs, acc);
+    }
+  }
+  // reduce over pair slots
+  __syncthreads();
+  cplx* red = lds;  // [PP][LB]
+  if (slot < PP) {
+#pragma unroll
+    for (int k = 0; k < BT; ++k) red[slot * LB + m0 + k] = acc[k];
+  }
+  __syncthreads();
+  const int nch = nchunk[p];
+  const int64_t ip = i0 + v.moff[p];  // unknown index (single column) of mode -N_p
+  cplx* yc = y + cb + v.moff[p];
+  const cplx* xp = xc + v.moff[p];
+  const int nslot_max = min(PP, je - jb);
+  if (nch == 1) {
+    for (int m = tid; m < np; m += APPLY_THREADS) {
+      cplx w = cmk(0.0, 0.0);
+      for (int k = 0; k < nslot_max; ++k) w = cadd(w, red[k * LB + m]);
+      yc[m] = finalize(v, op, ip + m, xp[m], w);
+    }
+    return;
+  }
+  cplx* pr = part + (int64_t)r * part_total + partoff[p];
+  for (int m = tid; m < np; m += APPLY_THREADS) {
+    cplx w = cmk(0.0, 0.0);
+    for (int k = 0; k < nslot_max; ++k) w = cadd(w, red[k * LB + m]);
+    pr[(int64_t)c * np + m] = w;
+  }
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) {
+    int32_t* cnt = counters + (int64_t)r * v.M_all + p;
+    int old = atomicAdd(cnt, 1);
+    s_last = (old == nch - 1);
+    if (s_last) atomicExch(cnt, 0);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  for (int m = tid; m < np; m += APPLY_THREADS) {
+    cplx w = cmk(0.0, 0.0);
+    for (int k = 0; k < nch; ++k) {
+      w = cadd(w, pr[(int64_t)k * np + m]);  // visible after the fence above
+    }
+    yc[m] = finalize(v, op, ip + m, xp[m], w);
+  }
+}
+
+// ------------------------------------------------------------------ planning
+namespace {
+typedef void (*apply_fn)(DevView, int, const cplx*, cplx*, int, cplx*, int64_t, int32_t*,
+                         const int32_t*, const int32_t*, const int64_t*, const int32_t*, int, int, int);
+
+struct Variant {
+  int bt, nspec;
+  apply_fn fn;
+};
+
+const Variant kVariants[] = {
+    {4, -1, k_apply<4, -1>},  {5, -1, k_apply<5, -1>},  {6, -1, k_apply<6, -1>},
+    {8, -1, k_apply<8, -1>},  {5, 12, k_apply<5, 12>},  {4, 15, k_apply<4, 15>},
+    {5, 7, k_apply<5, 7>},    {4, 10, k_apply<4, 10>},  {5, 2, k_apply<5, 2>},
+    {4, 3, k_apply<4, 3>},    {4, 4, k_apply<4, 4>},    {4, 8, k_apply<4, 8>},
+};
+
+const Variant* find_variant(int bt, int nspec) {
+  for (const Variant& v : kVariants)
+    if (v.bt == bt && v.nspec == nspec) return &v;
+  return nullptr;
+}
+}  // namespace
+
+// Host plan of the operator apply: kernel variant, work items and partial-sum
+// layout, from the batch description alone (also used to size workspaces).
+struct PlanHost {
+  int bt = 4, nspec = -1, zs = 0, ts = 0, ppcap = 1;
+  size_t lds = 0;
+  int64_t part = 0;
+  std::vector<int32_t> items, nch;
+  std::vector<int64_t> poff;
+};
+
+// The uniform-N specialisation when every disk has the same N and one is
+// compiled, else the generic kernel with BT = 4.
+static void choose_variant(int M, const int32_t* N, int* bt, int* nspec) {
+  bool uniform = true;
+  for (int p = 1; p < M; ++p)
+    if (N[p] != N[0]) uniform = false;
+  if (uniform) {
+    for (const Variant& v : kVariants)
+      if (v.nspec == N[0]) {
+        *bt = v.bt;
+        *nspec = v.nspec;
+        return;
+      }
+  }
+  *bt = 4;
+  *nspec = -1;
+}
+
+#define APPLY_LDS_BUDGET (64 * 1024)
+
+void make_plan(int B, const int64_t* idisk, const int32_t* N, PlanHost& P) {
+  const int M = (int)idisk[B];
+  choose_variant(M, N, &P.bt, &P.nspec);
+  const int bt = P.bt;
+  int nmax = 0;
+  for (int p = 0; p < M; ++p) nmax = std::max(nmax, (int)N[p]);
+  // LDS rows: z stride zs (padded to BT), symbol rows ts = zs + LB_max - 1
+  P.zs = ((2 * nmax + 1) + bt - 1) / bt * bt;
+  P.ts = P.zs + P.zs - 1;
+  P.ppcap = std::max(1, (int)(APPLY_LDS_BUDGET / ((size_t)(P.zs + P.ts) * 16)));
+  P.items.clear();
+  P.nch.assign(M, 0);
+  P.poff.assign(M, 0);
+  P.part = 0;
+  P.lds = 0;
+  for (int b = 0; b < B; ++b) {
+    const int64_t d0 = idisk[b], Mb = idisk[b + 1] - d0;
+    for (int64_t p = d0; p < d0 + Mb; ++p) {
+      const int np = 2 * N[p] + 1;
+      const int L = (np + bt - 1) / bt;
+      const int pp = std::max(1, std::min(APPLY_THREADS / L, P.ppcap));
+      const int64_t qc = (int64_t)pp * APPLY_NPASS;
+      const int64_t n = std::max<int64_t>(1, (Mb - 1 + qc - 1) / qc);
+      P.nch[p] = (int32_t)n;
+      P.poff[p] = P.part;
+      P.part += n * np;
+      for (int64_t c = 0; c < n; ++c) {
+        int64_t jb = c * qc, je = std::min<int64_t>(jb + qc, Mb - 1);
+        P.items.push_back((int32_t)p);
+        P.items.push_back((int32_t)c);
+        P.items.push_back((int32_t)jb);
+        P.items.push_back((int32_t)je);
+      }
+      P.lds = std::max(P.lds, (size_t)pp * (P.zs + P.ts) * 16);
+      P.lds = std::max(P.lds, (size_t)pp * L * bt * 16);
+    }
+  }
+}
+
+size_t plan_sched_bytes(const PlanHost& P, int M) {
+  return align256(P.items.size() * 4) + align256((size_t)M * 4) + align256((size_t)M * 8) + 256;
+}
+
+size_t sched_bytes_for(int B, const int64_t* disk_off, const int32_t* n_modes) {
+  PlanHost H;
+  make_plan(B, disk_off, n_modes, H);
+  return plan_sched_bytes(H, (int)disk_off[B]);
+}
+
+int ensure_plan(mudiff_ctx* h, hipStream_t s) {
+  if (h->plan.n_items > 0) return MUDIFF_OK;
+  PlanHost H;
+  make_plan(h->B, h->idisk.data(), h->N.data(), H);
+  if (H.lds > 64 * 1024) return fail(MUDIFF_ERR_INVALID, "operator rows too long for LDS");
+  if (plan_sched_bytes(H, h->M_all) > h->sched_bytes)
+    return fail(MUDIFF_ERR_INVALID, "schedule area too small");
+  MatvecPlan& P = h->plan;
+  P.d_items = (int32_t*)h->sched_base;
+  P.d_nchunk = (int32_t*)(h->sched_base + align256(H.items.size() * 4));
+  P.d_partoff = (int64_t*)((char*)P.d_nchunk + align256(h->M_all * 4));
+  HIP_TRY(hipMemcpyAsync(P.d_items, H.items.data(), H.items.size() * 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(P.d_nchunk, H.nch.data(), h->M_all * 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(P.d_partoff, H.poff.data(), h->M_all * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));  // the host vectors are released on return
+  P.Bt = H.bt;
+  P.spec_N = H.nspec;
+  P.zs = H.zs;
+  P.ts = H.ts;
+  P.ppcap = H.ppcap;
+  P.part_total = H.part;
+  P.lds_bytes = H.lds;
+  P.n_items = (int)(H.items.size() / 4);
+  return MUDIFF_OK;
+}
+
+size_t apply_scratch_bytes(mudiff_ctx* h, int R) {
+  if (h->plan_part < 0) {
+    PlanHost H;
+    make_plan(h->B, h->idisk.data(), h->N.data(), H);
+    h->plan_part = H.part;
+  }
+  return align256((size_t)R * h->plan_part * 16) + align256((size_t)R * h->M_all * 4);
+}
+
+int apply_operator(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, cplx* part,
+                   int32_t* counters, const int32_t* active, hipStream_t s) {
+  int st = ensure_plan(h, s);
+  if (st != MUDIFF_OK) return st;
+  const MatvecPlan& P = h->plan;
+  const Variant* var = find_variant(P.Bt, P.spec_N);
+  if (!var) return fail(MUDIFF_ERR_INVALID, "no operator kernel variant");
+  hipLaunchKernelGGL(var->fn, dim3(P.n_items, R), dim3(APPLY_THREADS), P.lds_bytes, s, h->dv, R, x,
+                     y, op, part, P.part_total, counters, P.d_items, P.d_nchunk, P.d_partoff, active,
+                     P.zs, P.ts, P.ppcap);
+  HIP_TRY(hipGetLastError());
+  return MUDIFF_OK;
+}
+
+extern "C" size_t mudiff_matvec_workspace_size(mudiff_t h, int R) {
+  if (!h || R < 1) return 0;
+  return apply_scratch_bytes(h, R);
+}
+
+extern "C" int mudiff_matvec(mudiff_t h, int R, const void* x, void* y, int op, void* workspace,
+                             size_t ws_bytes, void* stream) {
+  if (!h || !x || !y) return fail(MUDIFF_ERR_INVALID, "NULL argument");
+  if (R < 1) return fail(MUDIFF_ERR_INVALID, "R < 1");
+  if (x == y) return fail(MUDIFF_ERR_INVALID, "x and y must be distinct buffers");
+  if (op != MUDIFF_OP_L && op != MUDIFF_OP_A) return fail(MUDIFF_ERR_INVALID, "unknown op");
+  size_t need = apply_scratch_bytes(h, R);
+  if (!workspace) return fail(MUDIFF_ERR_INVALID, "workspace is NULL");
+  if (ws_bytes < need) return fail(MUDIFF_ERR_NOMEM, "matvec workspace needs " + std::to_string(need) + " bytes");
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)workspace;
+  size_t part_bytes = need - align256((size_t)R * h->M_all * 4);
+  int32_t* counters = (int32_t*)(w + part_bytes);  // zero on first use, left zero
+  return apply_operator(h, R, (const cplx*)x, (cplx*)y, op, (cplx*)w, counters, nullptr, s);
+}

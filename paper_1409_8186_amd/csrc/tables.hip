@@ -1,0 +1,419 @@
+// Geometry, Bessel/Hankel tables and handle management (paper sec. 4.1-4.2).
+//
+// Per disk p:      J_m(k a_p), H_m(k a_p), m = 0..N_p+1 (the diagonal matrices
+//                  J, H of sec. 4.2, one more order for derivatives).
+// Per unknown:     sqrt(a_p) J_m, 1/(sqrt(a_p) H_m), (i pi a_p/2) J_m H_m.
+// Per unordered pair p<q of an instance: the separation symbols
+//                  t_s = H_s(k b_pq) e^{i s alpha_pq}, s = -(N_p+N_q)..(N_p+N_q),
+//                  b_pq, alpha_pq the length and angle of O_p - O_q, with
+//                  H_{-s} = (-1)^s H_s.  The reverse pair uses t^{qp}_s = (-1)^s t^{pq}_s.
+#include <algorithm>
+#include <cstring>
+
+#include "bessel.h"
+#include "common.h"
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+int fail(int status, const std::string& msg) {
+  g_last_error = msg;
+  return status;
+}
+
+extern "C" const char* mudiff_last_error(void) { return g_last_error.c_str(); }
+
+// ------------------------------------------------------------------ kernels
+
+// One thread per disk: Miller J (any x), Y_0/Y_1 from the Neumann series
+// (x < BESSEL_X_ASY) or Hankel's expansion, then upward recurrence for Y.
+__global__ void k_disk_tables(DevView v) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= v.M_all) return;
+  const int nmax = v.N[p] + 1;
+  const double x = v.kd[p] * v.a[p];
+  double* J = v.Jd + v.dtab[p];
+  cplx* H = v.Hd + v.dtab[p];
+  double S0, S1;
+  bessel_j_miller(x, nmax, J, 1, &S0, &S1);
+  double Y0, Y1;
+  if (x < BESSEL_X_ASY) {
+    bessel_y01_neumann(x, J[0], J[1], S0, S1, &Y0, &Y1);
+  } else {
+    cplx h0, h1;
+    hankel01_asym(x, &h0, &h1);
+    Y0 = h0.y;
+    Y1 = h1.y;
+  }
+  H[0] = cmk(J[0], Y0);
+  if (nmax >= 1) H[1] = cmk(J[1], Y1);
+  double ym1 = Y0, y = Y1;
+  for (int n = 1; n < nmax; ++n) {
+    double yp1 = (2.0 * n / x) * y - ym1;
+    ym1 = y;
+    y = yp1;
+    H[n + 1] = cmk(J[n + 1], y);
+  }
+}
+
+// One thread per unknown of the single-column vector: the diagonal factors.
+__global__ void k_unknown_tables(DevView v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= v.N_all) return;
+  // locate the disk: binary search on the instance, then on the disks
+  int lo = 0, hi = v.B;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (v.imode[mid] <= i) lo = mid; else hi = mid;
+  }
+  const int b = lo;
+  int64_t il = i - v.imode[b];
+  int64_t d0 = v.idisk[b], d1 = v.idisk[b + 1];
+  int64_t dl = d0, dh = d1;
+  while (dh - dl > 1) {
+    int64_t mid = (dl + dh) >> 1;
+    if (v.moff[mid] <= il) dl = mid; else dh = mid;
+  }
+  const int p = (int)dl;
+  const int Np = v.N[p];
+  const int m = (int)(il - v.moff[p]) - Np;
+  const int am = m < 0 ? -m : m;
+  const double sg = (m < 0 && (am & 1)) ? -1.0 : 1.0;  // reflection to negative orders
+  const double J = sg * v.Jd[v.dtab[p] + am];
+  const cplx H = cscale(v.Hd[v.dtab[p] + am], sg);
+  const double a = v.a[p];
+  const double sa = sqrt(a);
+  v.sJ[i] = sa * J;
+  v.invSH[i] = cdiv(cmk(1.0, 0.0), cscale(H, sa));
+  const double c = 0.5 * 3.14159265358979323846 * a * J;  // L^{pp} = i c H
+  v.Ldiag[i] = cmk(-c * H.y, c * H.x);
+  v.udisk[i] = p;
+}
+
+// One thread per unordered pair: H_s(k b) for s = 0..S, then the phases.
+__global__ void k_pair_tables(DevView v, int64_t P_all) {
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= P_all) return;
+  int lo = 0, hi = v.B;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (v.ipair[mid] <= g) lo = mid; else hi = mid;
+  }
+  const int b = lo;
+  const int64_t M = v.idisk[b + 1] - v.idisk[b];
+  const int64_t l = g - v.ipair[b];
+  // row i of the strict upper triangle: first index of row i is i(2M-i-1)/2
+  double disc = (2.0 * M - 1.0) * (2.0 * M - 1.0) - 8.0 * (double)l;
+  int64_t i = (int64_t)floor(((2.0 * M - 1.0) - sqrt(disc > 0 ? disc : 0.0)) * 0.5);
+  if (i < 0) i = 0;
+  while (i > 0 && i * (2 * M - i - 1) / 2 > l) --i;
+  while ((i + 1) * (2 * M - i - 2) / 2 <= l) ++i;
+  const int64_t j = l - i * (2 * M - i - 1) / 2 + i + 1;
+  const int p = (int)(v.idisk[b] + i), q = (int)(v.idisk[b] + j);
+  const double dx = v.cx[p] - v.cx[q], dy = v.cy[p] - v.cy[q];
+  const double bpq = hypot(dx, dy), alpha = atan2(dy, dx);
+  const double x = v.kd[p] * bpq;
+  const int S = v.N[p] + v.N[q];
+  cplx* T = v.t + v.toff[g] + S;  // T[s], s = -S..S
+  // H_s for s = 0..S into T[0..S]
+  if (x >= BESSEL_X_ASY) {
+    cplx h0, h1;
+    hankel01_asym(x, &h0, &h1);
+    T[0] = h0;
+    if (S >= 1) T[1] = h1;
+    cplx hm1 = h0, h = h1;
+    for (int n = 1; n < S; ++n) {
+      cplx hp1 = csub(cscale(h, 2.0 * n / x), hm1);
+      hm1 = h;
+      h = hp1;
+      T[n + 1] = h;
+    }
+  } else {
+    // J_0..J_S go to the real parts of the row (S = 0 needs J_1 as well:
+    // use a private pair of slots then)
+    double tmp[4];
+    double* Jr = S >= 1 ? reinterpret_cast<double*>(T) : tmp;
+    double S0, S1;
+    bessel_j_miller(x, S >= 1 ? S : 1, Jr, 2, &S0, &S1);
+    double Y0, Y1;
+    bessel_y01_neumann(x, Jr[0], Jr[2], S0, S1, &Y0, &Y1);
+    T[0].x = Jr[0];
+    T[0].y = Y0;
+    if (S >= 1) T[1].y = Y1;
+    double ym1 = Y0, y = Y1;
+    for (int n = 1; n < S; ++n) {
+      double yp1 = (2.0 * n / x) * y - ym1;
+      ym1 = y;
+      y = yp1;
+      T[n + 1].y = y;
+    }
+  }
+  // phases: t_s = H_s e^{i s alpha}, t_{-s} = (-1)^s H_s e^{-i s alpha}
+  for (int s = S; s >= 1; --s) {
+    cplx H = T[s];
+    cplx e = cexpi(s * alpha);
+    T[s] = cmul(H, e);
+    cplx tm = cmul(H, cconj(e));
+    T[-s] = (s & 1) ? cmk(-tm.x, -tm.y) : tm;
+  }
+}
+
+// ------------------------------------------------------------------ layout
+size_t sched_bytes_for(int B, const int64_t* disk_off, const int32_t* n_modes);
+
+namespace {
+struct Layout {
+  size_t off_cx, off_cy, off_a, off_kd, off_N, off_inst, off_moff, off_dtab, off_idisk, off_imode,
+      off_ipair, off_toff, off_t, off_Jd, off_Hd, off_sJ, off_invSH, off_Ldiag, off_udisk, off_sched;
+  size_t sched_bytes, total;
+};
+
+Layout make_layout(int B, const int64_t* disk_off, const int32_t* n_modes, int64_t N_all,
+                   int64_t P_all, int64_t T_all, int64_t D_all) {
+  Layout L{};
+  const int64_t M = disk_off[B];
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o = align256(o + bytes);
+    return r;
+  };
+  L.off_cx = take(M * 8);
+  L.off_cy = take(M * 8);
+  L.off_a = take(M * 8);
+  L.off_kd = take(M * 8);
+  L.off_N = take(M * 4);
+  L.off_inst = take(M * 4);
+  L.off_moff = take(M * 8);
+  L.off_dtab = take(M * 8);
+  L.off_idisk = take((B + 1) * 8);
+  L.off_imode = take((B + 1) * 8);
+  L.off_ipair = take((B + 1) * 8);
+  L.off_toff = take((P_all + 1) * 8);
+  L.off_t = take(T_all * 16);
+  L.off_Jd = take(D_all * 8);
+  L.off_Hd = take(D_all * 16);
+  L.off_sJ = take(N_all * 8);
+  L.off_invSH = take(N_all * 16);
+  L.off_Ldiag = take(N_all * 16);
+  L.off_udisk = take(N_all * 4);
+  L.sched_bytes = sched_bytes_for(B, disk_off, n_modes);
+  L.off_sched = take(L.sched_bytes);
+  L.total = o;
+  return L;
+}
+
+bool sizes_of(int B, const int64_t* disk_off, const int32_t* n_modes, int64_t* N_all,
+              int64_t* P_all, int64_t* T_all, int64_t* D_all) {
+  if (B < 1 || !disk_off || !n_modes || disk_off[0] != 0) return false;
+  *N_all = *P_all = *T_all = *D_all = 0;
+  for (int b = 0; b < B; ++b) {
+    int64_t d0 = disk_off[b], d1 = disk_off[b + 1];
+    if (d1 <= d0) return false;
+    for (int64_t p = d0; p < d1; ++p) {
+      if (n_modes[p] < 0 || n_modes[p] > MUDIFF_MAX_NP) return false;
+      *N_all += 2 * n_modes[p] + 1;
+      *D_all += n_modes[p] + 2;
+      for (int64_t q = p + 1; q < d1; ++q) {
+        *P_all += 1;
+        *T_all += 2 * (int64_t)(n_modes[p] + n_modes[q]) + 1;
+      }
+    }
+  }
+  return true;
+}
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+extern "C" size_t mudiff_tables_workspace_size(int B, const int64_t* disk_off,
+                                               const int32_t* n_modes) {
+  int64_t N_all, P_all, T_all, D_all;
+  if (!sizes_of(B, disk_off, n_modes, &N_all, &P_all, &T_all, &D_all)) return 0;
+  return make_layout(B, disk_off, n_modes, N_all, P_all, T_all, D_all).total;
+}
+
+extern "C" int mudiff_tables(int B, const int64_t* disk_off, const double* centers,
+                             const double* radii, const int32_t* n_modes, const double* k,
+                             void* workspace, size_t ws_bytes, void* stream, mudiff_t* out) {
+  if (!out) return fail(MUDIFF_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (B < 1 || !disk_off || !centers || !radii || !n_modes || !k)
+    return fail(MUDIFF_ERR_INVALID, "B < 1 or a NULL pointer");
+  if (disk_off[0] != 0) return fail(MUDIFF_ERR_INVALID, "disk_off[0] != 0");
+  for (int b = 0; b < B; ++b)
+    if (disk_off[b + 1] <= disk_off[b])
+      return fail(MUDIFF_ERR_INVALID, "disk_off must be strictly increasing");
+  const int64_t M = disk_off[B];
+  if (M > (int64_t)1 << 30) return fail(MUDIFF_ERR_INVALID, "too many disks");
+  for (int64_t p = 0; p < M; ++p) {
+    if (!std::isfinite(centers[2 * p]) || !std::isfinite(centers[2 * p + 1]))
+      return fail(MUDIFF_ERR_INVALID, "non-finite center");
+    if (!(radii[p] > 0.0) || !std::isfinite(radii[p]))
+      return fail(MUDIFF_ERR_INVALID, "radius must be finite and > 0");
+    if (n_modes[p] < 0 || n_modes[p] > MUDIFF_MAX_NP)
+      return fail(MUDIFF_ERR_INVALID, "N_p out of range [0, MUDIFF_MAX_NP]");
+  }
+  for (int b = 0; b < B; ++b)
+    if (!(k[b] > 0.0) || !std::isfinite(k[b]))
+      return fail(MUDIFF_ERR_INVALID, "k must be finite and > 0");
+  // disjointness (sec. 2): b_pq > a_p + a_q inside every instance
+  for (int b = 0; b < B; ++b)
+    for (int64_t p = disk_off[b]; p < disk_off[b + 1]; ++p)
+      for (int64_t q = p + 1; q < disk_off[b + 1]; ++q) {
+        double d = std::hypot(centers[2 * p] - centers[2 * q], centers[2 * p + 1] - centers[2 * q + 1]);
+        if (!(d > radii[p] + radii[q]))
+          return fail(MUDIFF_ERR_OVERLAP, "disks " + std::to_string(p) + " and " +
+                                               std::to_string(q) + " overlap or touch");
+      }
+  int64_t N_all, P_all, T_all, D_all;
+  if (!sizes_of(B, disk_off, n_modes, &N_all, &P_all, &T_all, &D_all))
+    return fail(MUDIFF_ERR_INVALID, "bad sizes");
+  Layout L = make_layout(B, disk_off, n_modes, N_all, P_all, T_all, D_all);
+  if (!workspace) return fail(MUDIFF_ERR_INVALID, "workspace is NULL");
+  if (ws_bytes < L.total)
+    return fail(MUDIFF_ERR_NOMEM, "tables workspace needs " + std::to_string(L.total) + " bytes");
+  if (((uintptr_t)workspace) & 255) return fail(MUDIFF_ERR_INVALID, "workspace must be 256-byte aligned");
+
+  mudiff_ctx* h = new mudiff_ctx();
+  h->B = B;
+  h->M_all = (int)M;
+  h->N_all = N_all;
+  h->P_all = P_all;
+  h->T_all = T_all;
+  h->D_all = D_all;
+  h->idisk.assign(disk_off, disk_off + B + 1);
+  h->imode.assign(B + 1, 0);
+  h->ipair.assign(B + 1, 0);
+  h->k.assign(k, k + B);
+  h->N.assign(n_modes, n_modes + M);
+  h->inst.resize(M);
+  h->moff.resize(M);
+  h->dtab.resize(M);
+  h->cx.resize(M);
+  h->cy.resize(M);
+  h->a.assign(radii, radii + M);
+  h->toff.resize(P_all + 1);
+  std::vector<double> kd(M);
+  int64_t dt = 0, pi = 0, to = 0;
+  for (int b = 0; b < B; ++b) {
+    int64_t mo = 0;
+    for (int64_t p = disk_off[b]; p < disk_off[b + 1]; ++p) {
+      h->inst[p] = b;
+      h->moff[p] = mo;
+      mo += 2 * n_modes[p] + 1;
+      h->dtab[p] = dt;
+      dt += n_modes[p] + 2;
+      h->cx[p] = centers[2 * p];
+      h->cy[p] = centers[2 * p + 1];
+      kd[p] = k[b];
+      h->Nmax = std::max(h->Nmax, (int)n_modes[p]);
+    }
+    h->imode[b + 1] = h->imode[b] + mo;
+    for (int64_t p = disk_off[b]; p < disk_off[b + 1]; ++p)
+      for (int64_t q = p + 1; q < disk_off[b + 1]; ++q) {
+        h->toff[pi++] = to;
+        to += 2 * (int64_t)(n_modes[p] + n_modes[q]) + 1;
+      }
+    h->ipair[b + 1] = pi;
+  }
+  h->toff[P_all] = to;
+
+  char* base = (char*)workspace;
+  h->ws = workspace;
+  h->ws_bytes = ws_bytes;
+  DevView& v = h->dv;
+  v.B = B;
+  v.M_all = (int)M;
+  v.N_all = N_all;
+  v.cx = (double*)(base + L.off_cx);
+  v.cy = (double*)(base + L.off_cy);
+  v.a = (double*)(base + L.off_a);
+  v.kd = (double*)(base + L.off_kd);
+  v.N = (int32_t*)(base + L.off_N);
+  v.inst = (int32_t*)(base + L.off_inst);
+  v.moff = (int64_t*)(base + L.off_moff);
+  v.dtab = (int64_t*)(base + L.off_dtab);
+  v.idisk = (int64_t*)(base + L.off_idisk);
+  v.imode = (int64_t*)(base + L.off_imode);
+  v.ipair = (int64_t*)(base + L.off_ipair);
+  v.toff = (int64_t*)(base + L.off_toff);
+  v.t = (cplx*)(base + L.off_t);
+  v.Jd = (double*)(base + L.off_Jd);
+  v.Hd = (cplx*)(base + L.off_Hd);
+  v.sJ = (double*)(base + L.off_sJ);
+  v.invSH = (cplx*)(base + L.off_invSH);
+  v.Ldiag = (cplx*)(base + L.off_Ldiag);
+  v.udisk = (int32_t*)(base + L.off_udisk);
+  h->sched_base = base + L.off_sched;
+  h->sched_bytes = L.sched_bytes;
+
+  hipStream_t s = (hipStream_t)stream;
+  auto up = [&](const void* dst, const void* src, size_t bytes) {
+    return hipMemcpyAsync((void*)dst, src, bytes, hipMemcpyHostToDevice, s);
+  };
+  int st = MUDIFF_OK;
+  auto chk = [&](hipError_t e, const char* what) {
+    if (e != hipSuccess && st == MUDIFF_OK)
+      st = fail(MUDIFF_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  };
+  chk(up(v.cx, h->cx.data(), M * 8), "upload cx");
+  chk(up(v.cy, h->cy.data(), M * 8), "upload cy");
+  chk(up(v.a, h->a.data(), M * 8), "upload a");
+  chk(up(v.kd, kd.data(), M * 8), "upload k");
+  chk(up(v.N, h->N.data(), M * 4), "upload N");
+  chk(up(v.inst, h->inst.data(), M * 4), "upload inst");
+  chk(up(v.moff, h->moff.data(), M * 8), "upload moff");
+  chk(up(v.dtab, h->dtab.data(), M * 8), "upload dtab");
+  chk(up(v.idisk, h->idisk.data(), (B + 1) * 8), "upload idisk");
+  chk(up(v.imode, h->imode.data(), (B + 1) * 8), "upload imode");
+  chk(up(v.ipair, h->ipair.data(), (B + 1) * 8), "upload ipair");
+  chk(up(v.toff, h->toff.data(), (P_all + 1) * 8), "upload toff");
+  // the uploads read pageable host memory that this function owns only
+  // until it returns: finish them before the kernels are enqueued
+  chk(hipStreamSynchronize(s), "upload sync");
+  if (st != MUDIFF_OK) {
+    delete h;
+    return st;
+  }
+  hipLaunchKernelGGL(k_disk_tables, dim3((unsigned)((M + 63) / 64)), dim3(64), 0, s, v);
+  chk(hipGetLastError(), "k_disk_tables");
+  hipLaunchKernelGGL(k_unknown_tables, dim3((unsigned)((N_all + 255) / 256)), dim3(256), 0, s, v);
+  chk(hipGetLastError(), "k_unknown_tables");
+  if (P_all > 0) {
+    hipLaunchKernelGGL(k_pair_tables, dim3((unsigned)((P_all + 63) / 64)), dim3(64), 0, s, v, P_all);
+    chk(hipGetLastError(), "k_pair_tables");
+  }
+  if (st != MUDIFF_OK) {
+    delete h;
+    return st;
+  }
+  *out = h;
+  return MUDIFF_OK;
+}
+
+extern "C" int mudiff_destroy(mudiff_t h) {
+  delete h;
+  return MUDIFF_OK;
+}
+
+extern "C" int mudiff_sizes(mudiff_t h, int64_t* n_tot) {
+  if (!h || !n_tot) return fail(MUDIFF_ERR_INVALID, "NULL argument");
+  for (int b = 0; b < h->B; ++b) n_tot[b] = h->imode[b + 1] - h->imode[b];
+  return MUDIFF_OK;
+}
+
+extern "C" int mudiff_disk_tables(mudiff_t h, double* J, void* H, void* stream) {
+  if (!h) return fail(MUDIFF_ERR_INVALID, "NULL handle");
+  hipStream_t s = (hipStream_t)stream;
+  if (J) HIP_TRY(hipMemcpyAsync(J, h->dv.Jd, h->D_all * 8, hipMemcpyDeviceToDevice, s));
+  if (H) HIP_TRY(hipMemcpyAsync(H, h->dv.Hd, h->D_all * 16, hipMemcpyDeviceToDevice, s));
+  return MUDIFF_OK;
+}
+
+extern "C" int mudiff_pair_tables(mudiff_t h, void* t, int64_t* count, void* stream) {
+  if (!h || !count) return fail(MUDIFF_ERR_INVALID, "NULL argument");
+  *count = h->T_all;
+  if (t && h->T_all > 0)
+    HIP_TRY(hipMemcpyAsync(t, h->dv.t, h->T_all * 16, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return MUDIFF_OK;
+}

@@ -1,0 +1,270 @@
+"""GPU parity: every step of the HIP path against the CPU oracle, element by
+element, on the same seeded inputs (through the C ABI via the binding).
+
+Tolerances (relative, norm-wise per column unless stated):
+  * tables: componentwise |t - t_ref| <= 1e-11 |t_ref| (AMOS itself is good
+    to ~1e-13 relative to |H|; arguments up to ~2e3 move the phase by x*eps);
+  * operator apply: 1e-12 (a sum of N_tot products of O(1) terms in FP64);
+  * right-hand side, far field of a given density: 1e-13;
+  * solutions / far fields of solves at tol 1e-12: 1e-10 (the spec bar).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import bessel, farfield, geometry, operator, rhs, solve
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_1409_8186_amd import Problem
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return Problem
+
+
+def _uneven(seed=21, M=9):
+    return synth.small_random(seed, M, 0.3, 1.0, 9.0, 0.15, 6.0, 4)
+
+
+def _wide():
+    """Pairs spanning small and large k b, uneven N_p up to 30."""
+    centers = np.array([[0.0, 0.0], [0.9, 0.1], [40.0, 3.0], [-120.0, 250.0], [2.3, -0.4]])
+    radii = np.array([0.3, 0.5, 1.5, 0.7, 0.2])
+    n_modes = np.array([3, 6, 30, 12, 1])
+    return synth.Cluster(centers, radii, n_modes, 4.7)
+
+
+# ------------------------------------------------------------------ tables
+@pytest.mark.parametrize("name", ["tiny", "uneven", "wide"])
+def test_tables(P, tiny, name):
+    cl = {"tiny": tiny, "uneven": _uneven(), "wide": _wide()}[name]
+    say("tables", name)
+    pr = P.from_cluster(cl)
+    J, H = pr.disk_tables()
+    J, H = J.cpu().numpy(), H.cpu().numpy()
+    o = 0
+    for p in range(cl.M):
+        m = np.arange(cl.n_modes[p] + 2)
+        x = cl.k * cl.radii[p]
+        Jr = bessel.besselj(m, x)
+        Hr = bessel.hankel1(m, x)
+        assert np.all(np.abs(J[o:o + len(m)] - Jr) <= 1e-13 * np.abs(Hr) + 1e-300), (p, J[o:o + len(m)], Jr)
+        assert np.all(np.abs(H[o:o + len(m)] - Hr) <= 1e-12 * np.abs(Hr)), p
+        o += len(m)
+    t = pr.pair_tables().cpu().numpy()
+    b, al = geometry.pair_geometry(cl.centers)
+    o = 0
+    worst = 0.0
+    for p in range(cl.M):
+        for q in range(p + 1, cl.M):
+            S = cl.n_modes[p] + cl.n_modes[q]
+            s = np.arange(-S, S + 1)
+            ref = bessel.hankel1(s, cl.k * b[p, q]) * np.exp(1j * s * al[p, q])
+            err = np.abs(t[o:o + 2 * S + 1] - ref) / np.abs(ref)
+            worst = max(worst, float(err.max()))
+            o += 2 * S + 1
+    say("  worst symbol rel err", worst)
+    assert o == t.shape[0]
+    assert worst < 1e-11
+
+
+# ------------------------------------------------------------------ operator
+def _dense(cl):
+    L = operator.efie_matrix(cl.centers, cl.radii, cl.n_modes, cl.k)
+    D = operator.efie_diagonal(cl.radii, cl.n_modes, cl.k)
+    return L, operator.preconditioned(L, D)
+
+
+@pytest.mark.parametrize("name,R", [("tiny", 1), ("uneven", 1), ("uneven", 3), ("wide", 2)])
+def test_matvec(P, tiny, name, R):
+    cl = {"tiny": tiny, "uneven": _uneven(), "wide": _wide()}[name]
+    say("matvec", name, "R", R)
+    L, A = _dense(cl)
+    rng = np.random.default_rng(5)
+    X = rng.normal(size=(R, cl.n_tot)) + 1j * rng.normal(size=(R, cl.n_tot))
+    pr = P.from_cluster(cl)
+    x = torch.tensor(X.ravel(), device="cuda")
+    yA = pr.matvec(x, R=R, op=1).cpu().numpy().reshape(R, -1)
+    yL = pr.matvec(x, R=R, op=0).cpu().numpy().reshape(R, -1)
+    for r in range(R):
+        assert rel(yA[r], A @ X[r]) < 1e-12, (r, rel(yA[r], A @ X[r]))
+        assert rel(yL[r], L @ X[r]) < 1e-12
+
+
+def test_matvec_batched_instances(P):
+    """B uneven instances in one handle: each column equals its own dense apply."""
+    cls = [_uneven(30 + i, M=3 + 2 * i) for i in range(4)]
+    say("matvec batched B=4")
+    pr = P.from_clusters(cls)
+    R = 2
+    rng = np.random.default_rng(9)
+    Xs = [rng.normal(size=(R, c.n_tot)) + 1j * rng.normal(size=(R, c.n_tot)) for c in cls]
+    y = pr.matvec(pr.pack(Xs), R=R, op=1)
+    for c, X, Y in zip(cls, Xs, pr.split(y, R)):
+        _, A = _dense(c)
+        Y = Y.cpu().numpy()
+        for r in range(R):
+            assert rel(Y[r], A @ X[r]) < 1e-12
+
+
+def test_matvec_single_disk_and_repeat(P):
+    """M = 1 (no pairs): A = I exactly; repeated applies give identical bits."""
+    cl = synth.Cluster(np.array([[0.5, -1.0]]), np.array([0.8]), np.array([7]), 3.0)
+    say("matvec M=1")
+    pr = P.from_cluster(cl)
+    x = torch.randn(cl.n_tot, dtype=torch.complex128, device="cuda")
+    y = pr.matvec(x, op=1)
+    assert torch.equal(y, x)
+    cl2 = _uneven()
+    pr2 = P.from_cluster(cl2)
+    x2 = torch.randn(cl2.n_tot, dtype=torch.complex128, device="cuda")
+    a = pr2.matvec(x2, op=1).clone()
+    b = pr2.matvec(x2, op=1)
+    assert torch.equal(a, b)
+
+
+# ------------------------------------------------------------------ rhs
+def test_rhs(P, tiny):
+    cl = _uneven()
+    say("rhs")
+    pr = P.from_cluster(cl)
+    betas = np.array([0.0, 0.7, 2.9, 5.1])
+    U = pr.rhs(betas[None, :]).cpu().numpy().reshape(4, -1)
+    Ur = rhs.planewave(cl.centers, cl.radii, cl.n_modes, cl.k, betas)
+    assert rel(U, Ur) < 1e-13
+    f = pr.rhs(betas[None, :], precond=True).cpu().numpy().reshape(4, -1)
+    D = operator.efie_diagonal(cl.radii, cl.n_modes, cl.k)
+    assert rel(f, -Ur / D[None, :]) < 1e-13
+
+
+# ------------------------------------------------------------------ solve
+def _lu(cl, betas):
+    L = operator.efie_matrix(cl.centers, cl.radii, cl.n_modes, cl.k)
+    U = rhs.planewave(cl.centers, cl.radii, cl.n_modes, cl.k, betas)
+    return solve.efie_solve_lu(L, U)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_gmres_tiny_vs_lu(P, tiny, graph):
+    say("gmres tiny graph", graph)
+    pr = P.from_cluster(tiny)
+    rho, flag, relres, iters, resvec = pr.gmres(betas=[[0.0]], restart=30, tol=1e-12, maxit=2000,
+                                                graph=graph, want_resvec=True)
+    ref = _lu(tiny, [0.0])[0]
+    assert int(flag[0]) == 0 and float(relres[0]) <= 1e-12
+    assert rel(rho.cpu().numpy(), ref) < 1e-10
+    it = int(iters[0])
+    rv = resvec[0].cpu().numpy()
+    assert rv[0] == 1.0 and 0 < rv[it] <= 1e-12
+    # far field at 360 angles against the oracle's LU far field
+    th = synth.uniform_angles(360)
+    a = pr.farfield(rho, th).cpu().numpy()[0]
+    aref = farfield.farfield(tiny.centers, tiny.radii, tiny.n_modes, tiny.k, th, ref)
+    assert rel(a, aref) < 1e-10
+
+
+def test_gmres_matches_oracle_gmres_iterations(P, tiny):
+    """Same restart / tolerance: the iteration counts of the oracle's MGS GMRES
+    and the device CGS2 GMRES agree to within a few (orthogonalisation
+    rounding differs)."""
+    say("gmres iteration count")
+    pr = P.from_cluster(tiny)
+    _, flag, _, iters, _ = pr.gmres(betas=[[0.0]], restart=30, tol=1e-8, maxit=2000)
+    L, A = _dense(tiny)
+    D = operator.efie_diagonal(tiny.radii, tiny.n_modes, tiny.k)
+    U = rhs.planewave(tiny.centers, tiny.radii, tiny.n_modes, tiny.k, [0.0])[0]
+    _, fl, _, it_ref, _ = solve.gmres(lambda v: A @ v, -U / D, 30, 1e-8, 2000)
+    assert int(flag[0]) == 0 and fl == 0
+    assert abs(int(iters[0]) - it_ref) <= 3, (int(iters[0]), it_ref)
+
+
+def test_gmres_batched_lockstep(P):
+    """B = 3 uneven instances x R = 3 angles in one solve; every column equals LU."""
+    cls = [_uneven(40 + i, M=4 + 3 * i) for i in range(3)]
+    betas = np.array([[0.0, 1.0, 2.5], [0.3, 3.3, 6.0], [1.1, 1.2, 1.3]])
+    say("gmres batched")
+    pr = P.from_clusters(cls)
+    rho, flag, relres, iters, _ = pr.gmres(betas=betas, restart=20, tol=1e-12, maxit=3000)
+    assert torch.all(flag == 0), flag
+    for b, (c, R) in enumerate(zip(cls, pr.split(rho, 3))):
+        ref = _lu(c, betas[b])
+        assert rel(R.cpu().numpy(), ref) < 1e-10
+
+
+def test_gmres_flags_and_warm_start(P, tiny):
+    say("gmres maxit / x0")
+    pr = P.from_cluster(tiny)
+    _, flag, relres, iters, _ = pr.gmres(betas=[[0.0]], restart=30, tol=1e-12, maxit=3)
+    assert int(flag[0]) == 1 and int(iters[0]) == 3 and float(relres[0]) > 1e-12
+    ref = _lu(tiny, [0.0])[0]
+    x0 = torch.tensor(ref, device="cuda")
+    rho, flag, relres, iters, _ = pr.gmres(betas=[[0.0]], restart=30, tol=1e-8, maxit=100, x0=x0)
+    assert int(flag[0]) == 0 and int(iters[0]) == 0
+
+
+def test_gmres_general_rhs(P):
+    """rhs given instead of angles: solves L rho = -rhs."""
+    cl = _uneven()
+    say("gmres rhs")
+    pr = P.from_cluster(cl)
+    rng = np.random.default_rng(3)
+    U = rng.normal(size=cl.n_tot) + 1j * rng.normal(size=cl.n_tot)
+    rho, flag, _, _, _ = pr.gmres(rhs=torch.tensor(U, device="cuda"), R=1, restart=30, tol=1e-12,
+                                  maxit=3000)
+    L = operator.efie_matrix(cl.centers, cl.radii, cl.n_modes, cl.k)
+    assert int(flag[0]) == 0
+    assert rel(rho.cpu().numpy(), np.linalg.solve(L, -U)) < 1e-10
+
+
+def test_farfield_given_density(P):
+    cl = _uneven()
+    say("farfield")
+    pr = P.from_cluster(cl)
+    rng = np.random.default_rng(4)
+    R = 2
+    X = rng.normal(size=(R, cl.n_tot)) + 1j * rng.normal(size=(R, cl.n_tot))
+    th = np.linspace(0, 2 * np.pi, 97)
+    a = pr.farfield(torch.tensor(X.ravel(), device="cuda"), th, R=R).cpu().numpy()
+    aref = farfield.farfield(cl.centers, cl.radii, cl.n_modes, cl.k, th, X)
+    assert rel(a, aref) < 1e-13
+
+
+# ------------------------------------------------------------------ full size
+def test_one_rhs_full_size(P):
+    """M = 400, N_p = 12 (10,000 unknowns): apply on random x vs the dense
+    oracle, GMRES(50) at tol 1e-12 vs LU, far field at 720 angles."""
+    cl = synth.one_rhs()
+    say("one_rhs full size: assembling the dense oracle")
+    L = operator.efie_matrix(cl.centers, cl.radii, cl.n_modes, cl.k)
+    D = operator.efie_diagonal(cl.radii, cl.n_modes, cl.k)
+    pr = P.from_cluster(cl)
+    rng = np.random.default_rng(8)
+    X = rng.normal(size=cl.n_tot) + 1j * rng.normal(size=cl.n_tot)
+    y = pr.matvec(torch.tensor(X, device="cuda"), op=1).cpu().numpy()
+    assert rel(y, X + (L @ X - D * X) / D) < 1e-12
+    say("one_rhs: gmres tol 1e-12")
+    rho, flag, relres, iters, _ = pr.gmres(betas=[[math.pi / 4]], restart=50, tol=1e-12, maxit=20000)
+    say("  iters", int(iters[0]), "relres", float(relres[0]))
+    assert int(flag[0]) == 0
+    U = rhs.planewave(cl.centers, cl.radii, cl.n_modes, cl.k, [math.pi / 4])[0]
+    say("one_rhs: LU")
+    ref = solve.solve_lu(L, -U)
+    assert rel(rho.cpu().numpy(), ref) < 1e-10
+    a = pr.farfield(rho, cl.thetas).cpu().numpy()[0]
+    aref = farfield.farfield(cl.centers, cl.radii, cl.n_modes, cl.k, cl.thetas, ref)
+    assert rel(a, aref) < 1e-10

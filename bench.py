@@ -115,6 +115,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true", help="replay GMRES cycles as HIP graphs")
+    ap.add_argument("--kernel-only", type=int, default=0, metavar="REPS",
+                    help="profiling mode: build the tables, run REPS operator applies, exit")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="profiling mode: one device-to-device copy of BYTES (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the hot path is a single-GPU build "
@@ -132,7 +136,25 @@ def main():
     from paper_1409_8186_amd import Problem
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        src = torch.ones(args.copy_probe // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 8, "launches": 3}), flush=True)
+        return
     cl = synth.one_rhs()
+    if args.kernel_only:
+        P = Problem.from_cluster(cl)
+        x = torch.randn(cl.n_tot, dtype=torch.complex128, device="cuda")
+        y = P.empty(1)
+        for _ in range(args.kernel_only):
+            P.matvec(x, op=1, out=y)
+        torch.cuda.synchronize()
+        print(json.dumps({"applies": args.kernel_only}), flush=True)
+        return
     beta = [[math.pi / 4]]
     th = torch.tensor(cl.thetas, device="cuda")
 

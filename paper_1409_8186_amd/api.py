@@ -110,6 +110,8 @@ class Problem:
             self.device, torch.complex128).contiguous()
 
     def _f64(self, a) -> torch.Tensor:
+        if isinstance(a, torch.Tensor):
+            return a.to(self.device, torch.float64).contiguous()
         return torch.as_tensor(np.asarray(a, dtype=np.float64)).to(self.device).contiguous()
 
     # ----------------------------------------------------------- tables

@@ -121,6 +121,7 @@ struct mudiff_ctx {
   size_t sched_bytes = 0;
   MatvecPlan plan;
   int64_t plan_part = -1;       // partial sums per right-hand side of the plan
+  bool mfma_enabled = true;     // multi-RHS applies on FP64 MFMA
 };
 
 // ------------------------------------------------------------------ errors

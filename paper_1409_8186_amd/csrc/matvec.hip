@@ -189,6 +189,142 @@ __global__ __launch_bounds__(APPLY_THREADS) void k_apply(
   }
 }
 
+// ------------------------------------------------------------------ multi-RHS (MFMA)
+// For R right-hand sides the block product T^{pq} Z^q (n_p x n_q times n_q x R)
+// is a dense contraction: it runs on FP64 MFMA (v_mfma_f64_16x16x4f64,
+// D[16x16] += A[16x4] B[4x16]).  A complex product is two real MFMAs: the B
+// panel holds [Re Z | Im Z] for 8 right-hand sides side by side, so
+//   acc1 = Re(T) [Re Z | Im Z],  acc2 = Im(T) [Re Z | Im Z],
+//   Re W = acc1[:, :8] - acc2[:, 8:],  Im W = acc1[:, 8:] + acc2[:, :8].
+// A workgroup owns one row disk p and 8 * (waves) right-hand sides; it loops
+// over every column disk q of the instance, staging the symbol row and the
+// scaled input panel in LDS, and accumulates all q in registers, so there is
+// no partial-sum traffic.  Lane layout (checked on the device): lane l holds
+// A[l % 16][l / 16], B[l / 16][l % 16] and D[4 v + l / 16][l % 16], v < 4.
+typedef double mf_d4 __attribute__((ext_vector_type(4)));
+
+template <int MT>  // row tiles of 16: n_p <= 16 MT
+__global__ __launch_bounds__(256) void k_apply_mfma(DevView v, int R, const cplx* __restrict__ x,
+                                                    cplx* __restrict__ y, int op,
+                                                    const int32_t* __restrict__ active, int ktmax) {
+  extern __shared__ cplx lds[];
+  const int p = blockIdx.x;
+  const int nwaves = blockDim.x >> 6;
+  const int RC = 8 * nwaves;
+  const int c0 = blockIdx.y * RC;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int j = lane & 15, kq = lane >> 4;
+  const int b = v.inst[p];
+  const int Np = v.N[p], np = 2 * Np + 1;
+  const int64_t d0 = v.idisk[b], Mb = v.idisk[b + 1] - d0;
+  const int64_t i0 = v.imode[b];
+  const int mycol = c0 + wave * 8 + (j & 7);
+  bool wave_active = false;
+  for (int c = 0; c < 8; ++c) {
+    const int r = c0 + wave * 8 + c;
+    if (r < R && (!active || active[b * R + r])) wave_active = true;
+  }
+  bool any = false;  // the whole workgroup may skip (converged columns)
+  for (int r = c0; r < min(R, c0 + RC); ++r)
+    if (!active || active[b * R + r]) any = true;
+  if (!any) return;
+  cplx* zl = lds;                       // [4 ktmax][RC]
+  cplx* tl = lds + 4 * ktmax * RC;      // [4 ktmax + 16 MT - 1]
+  mf_d4 acc1[MT], acc2[MT];
+#pragma unroll
+  for (int t = 0; t < MT; ++t) {
+    acc1[t] = mf_d4{0.0, 0.0, 0.0, 0.0};
+    acc2[t] = mf_d4{0.0, 0.0, 0.0, 0.0};
+  }
+  for (int64_t ql = 0; ql < Mb; ++ql) {
+    const int q = (int)(d0 + ql);
+    if (q == p) continue;
+    const int Nq = v.N[q], nq = 2 * Nq + 1, KT = (nq + 3) >> 2;
+    const int S = Np + Nq;
+    const int nrow = 4 * KT;
+    __syncthreads();
+    // scaled inputs Z[n][c] = sqrt(a_q) J_n(k a_q) x[c][n]  (contiguous in n)
+    for (int e = tid; e < nrow * RC; e += blockDim.x) {
+      const int c = e / nrow, n = e - (e / nrow) * nrow;
+      const int r = c0 + c;
+      cplx z = cmk(0.0, 0.0);
+      if (n < nq && r < R) {
+        const int64_t iq = v.moff[q] + n;
+        z = cscale(x[col_base(v.imode, b, R, r) + iq], v.sJ[i0 + iq]);
+      }
+      zl[n * RC + c] = z;
+    }
+    // symbol row: u = n - m + 16 MT - 1  <->  s = u - (16 MT - 1) - N_q + N_p
+    const int nu = nrow + 16 * MT - 1;
+    const int64_t g = pair_index(v.idisk, v.ipair, b, p, q);
+    const cplx* T = v.t + v.toff[g] + S;
+    for (int u = tid; u < nu; u += blockDim.x) {
+      const int s = u - (16 * MT - 1) - Nq + Np;
+      cplx t = cmk(0.0, 0.0);
+      if (s >= -S && s <= S) {
+        t = T[s];
+        if (p > q && (s & 1)) t = cmk(-t.x, -t.y);
+      }
+      tl[u] = t;
+    }
+    __syncthreads();
+    if (wave_active) {
+      for (int kk = 0; kk < KT; ++kk) {
+        const int n = 4 * kk + kq;
+        const cplx zz = zl[n * RC + wave * 8 + (j & 7)];
+        const double bv = j < 8 ? zz.x : zz.y;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const cplx t = tl[n - (16 * mt + j) + 16 * MT - 1];  // A[i = lane % 16][k = kq]
+          acc1[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(t.x, bv, acc1[mt], 0, 0, 0);
+          acc2[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(t.y, bv, acc2[mt], 0, 0, 0);
+        }
+      }
+    }
+  }
+  if (!wave_active) return;
+  const bool col_ok = mycol < R && (!active || active[b * R + mycol]);
+  const int64_t cb = col_ok ? col_base(v.imode, b, R, mycol) : 0;
+  const int64_t ip = i0 + v.moff[p];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+    for (int vv = 0; vv < 4; ++vv) {
+      const double a1 = acc1[mt][vv], a2 = acc2[mt][vv];
+      const double other = __shfl_xor(a2, 8, 64);
+      const double val = j < 8 ? a1 - other : a1 + other;  // Re W (j < 8), Im W (j >= 8)
+      const double im = __shfl_xor(val, 8, 64);
+      const int m = 16 * mt + 4 * vv + kq;  // D row 4 v + lane / 16
+      if (j < 8 && col_ok && m < np) {
+        const cplx w = cmk(val, im);
+        y[cb + v.moff[p] + m] = finalize(v, op, ip + m, x[cb + v.moff[p] + m], w);
+      }
+    }
+  }
+}
+
+static int launch_apply_mfma(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op,
+                             const int32_t* active, hipStream_t s) {
+  const int mt = (2 * h->Nmax + 1 + 15) / 16;
+  const int kt = (2 * h->Nmax + 1 + 3) / 4;
+  const int nw = std::min(4, (R + 7) / 8);
+  const int rc = 8 * nw;
+  const size_t lds = ((size_t)4 * kt * rc + 4 * kt + 16 * mt) * 16;
+  dim3 grid(h->M_all, (R + rc - 1) / rc), block(64 * nw);
+  switch (mt) {
+    case 1: hipLaunchKernelGGL(k_apply_mfma<1>, grid, block, lds, s, h->dv, R, x, y, op, active, kt); break;
+    case 2: hipLaunchKernelGGL(k_apply_mfma<2>, grid, block, lds, s, h->dv, R, x, y, op, active, kt); break;
+    case 3: hipLaunchKernelGGL(k_apply_mfma<3>, grid, block, lds, s, h->dv, R, x, y, op, active, kt); break;
+    case 4: hipLaunchKernelGGL(k_apply_mfma<4>, grid, block, lds, s, h->dv, R, x, y, op, active, kt); break;
+    default: return fail(MUDIFF_ERR_INVALID, "N_p too large for the MFMA apply");
+  }
+  HIP_TRY(hipGetLastError());
+  return MUDIFF_OK;
+}
+
+// R at and above which the MFMA kernel applies the operator (N_p <= 31).
+#define MFMA_MIN_R 8
+
 // ------------------------------------------------------------------ planning
 namespace {
 typedef void (*apply_fn)(DevView, int, const cplx*, cplx*, int, cplx*, int64_t, int32_t*,
@@ -329,6 +465,8 @@ size_t apply_scratch_bytes(mudiff_ctx* h, int R) {
 
 int apply_operator(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, cplx* part,
                    int32_t* counters, const int32_t* active, hipStream_t s) {
+  if (R >= MFMA_MIN_R && h->Nmax <= 31 && h->mfma_enabled)
+    return launch_apply_mfma(h, R, x, y, op, active, s);
   int st = ensure_plan(h, s);
   if (st != MUDIFF_OK) return st;
   const MatvecPlan& P = h->plan;

@@ -108,6 +108,98 @@ def cpu_baseline(cl, n_iter_gpu):
     }
 
 
+def other_workload(args):
+    """Documentation runs of the batched and differentiation workloads."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1409_8186_amd import Problem
+    base = {"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "complex128 (f64)",
+            "data": "synthetic (seeded disk clusters)"}
+    if args.workload == "multi_rhs":
+        cl = synth.multi_rhs()
+        R = len(cl.betas)
+        P = Problem.from_cluster(cl)
+        x = torch.randn(R * cl.n_tot, dtype=torch.complex128, device="cuda")
+        y = P.empty(R)
+        P.matvec(x, R=R, op=1, out=y)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(args.steps):
+            P.matvec(x, R=R, op=1, out=y)
+        ev1.record()
+        ev1.synchronize()
+        t = ev0.elapsed_time(ev1) / 1e3 / args.steps
+        flops = algorithmic_flops(cl.n_modes, R)
+        return {**base, "metric": "complex unknown·RHS matvecs/s", "value": cl.n_tot * R / t,
+                "unit": "complex unknown·RHS matvecs/s", "ms_per_step": t * 1e3,
+                "config": {"workload": "multi_rhs: M=1000, a~U[0.3,1], [0,150]^2, k=10, "
+                                       "N_p=ceil(10a)+10, R=256, one operator apply per step",
+                           "n_unknowns": cl.n_tot, "R": R},
+                "roofline": {"bound": "mfma", "achieved": flops / t / 1e12, "peak": 78.6,
+                             "unit": "TFLOP/s", "frac": flops / t / 1e12 / 78.6, "traffic": None,
+                             "kernel": "k_apply_mfma"}}
+    if args.workload == "uneven":
+        insts = synth.uneven_instances()
+        R = 8
+        betas = np.stack([c.betas for c in insts])
+        th = insts[0].thetas
+
+        def step():
+            P = Problem.from_clusters(insts)
+            rho, flag, relres, iters, _ = P.gmres(betas=betas, restart=50, tol=1e-8, maxit=20000)
+            P.farfield(rho, th, R=R)
+            return flag, iters
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            flag, iters = step()
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / args.steps
+        it = iters.cpu().numpy()
+        work = sum(c.n_tot * R for c in insts)
+        return {**base, "metric": "time-to-1e-8 GMRES solve (all instances)", "value": t,
+                "unit": "s", "higher_is_better": False, "ms_per_step": t * 1e3,
+                "config": {"workload": "uneven: 512 seeded instances, M~U{10..200}, k~U[1,20], "
+                                       "N_p=ceil(k a)+8, R=8, GMRES(50) to 1e-8, one launch per "
+                                       "operator apply", "unknowns_x_rhs": work,
+                           "iters_min": int(it.min()), "iters_max": int(it.max()),
+                           "all_converged": bool((flag == 0).all())}}
+    pairs = synth.differentiation()
+    bases = [b for b, _ in pairs]
+    betas = np.stack([b.betas for b in bases])
+    th = bases[0].thetas
+    # targets: far fields of the perturbed geometries (computed on the device)
+    tgt_cls = [t for _, t in pairs]
+    PT = Problem.from_clusters(tgt_cls)
+    rho_t, fl, _, _, _ = PT.gmres(betas=betas, restart=50, tol=1e-10, maxit=20000)
+    target = PT.farfield(rho_t, th, R=betas.shape[1]).reshape(-1)
+    PT.close()
+
+    def step():
+        P = Problem.from_clusters(bases)
+        out = P.grad(betas, th, target, restart=50, tol=1e-8, maxit=20000)
+        P.close()
+        return out
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / args.steps
+    return {**base, "metric": "adjoint grads/s", "value": len(bases) / t, "unit": "gradients/s",
+            "ms_per_step": t * 1e3,
+            "config": {"workload": "differentiation: 32 configs, M=100, a~U[0.4,0.8], [0,40]^2, "
+                                   "k=8, N_p=ceil(8a)+8, 64 incidences x 64 receivers, forward + "
+                                   "adjoint GMRES(50) to 1e-8, gradient w.r.t. 200 center "
+                                   "coordinates, 100 radii and k per config",
+                       "configs_per_step": len(bases)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +209,9 @@ def main():
     ap.add_argument("--graph", action="store_true", help="replay GMRES cycles as HIP graphs")
     ap.add_argument("--kernel-only", type=int, default=0, metavar="REPS",
                     help="profiling mode: build the tables, run REPS operator applies, exit")
+    ap.add_argument("--workload", default="one_rhs",
+                    choices=["one_rhs", "multi_rhs", "uneven", "differentiation"],
+                    help="one_rhs (default bench line) or a documentation run of another workload")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="profiling mode: one device-to-device copy of BYTES (counter calibration)")
     args = ap.parse_args()
@@ -144,6 +239,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": src.numel() * 8, "launches": 3}), flush=True)
+        return
+    if args.workload != "one_rhs":
+        print(json.dumps(other_workload(args)), flush=True)
         return
     cl = synth.one_rhs()
     if args.kernel_only:

@@ -41,30 +41,40 @@ def efie_diagonal(radii, n_modes, k):
     return 0.5j * np.pi * a * besselj(m, k * a) * hankel1(m, k * a)
 
 
-def efie_matrix(centers, radii, n_modes, k):
-    """Dense N_tot x N_tot complex128 matrix L of the truncated EFIE (sec. 5)."""
+def efie_row_block(centers, radii, n_modes, k, p):
+    """Rows of disk p of L: the (2N_p+1) x N_tot block [L^{p1} ... L^{pM}]."""
     n_modes = np.asarray(n_modes)
     a = np.asarray(radii, dtype=np.float64)
     off, N = mode_offsets(n_modes)
     disk, m = mode_index(n_modes)
-    _, alpha = pair_geometry(centers)
-    nu_max = 2 * int(np.max(n_modes))
-    Htab = pair_hankel_table(centers, k, nu_max)
-    Jcol = besselj(m, k * a[disk])                       # J_n(k a_q) per column unknown
+    b, alpha = pair_geometry(centers)
+    nu_max = int(n_modes[p]) + int(np.max(n_modes))
+    bp = b[p].copy()
+    bp[p] = 1.0
+    Hrow = hankel1(np.arange(nu_max + 1)[None, :], k * bp[:, None])   # H_nu(k b_pq)
+    rows = slice(off[p], off[p + 1])
+    mi = m[rows]
+    nu = m[None, :] - mi[:, None]                         # n - m
+    anu = np.abs(nu)
+    sign = np.where((nu < 0) & (anu % 2 == 1), -1.0, 1.0)
+    Hv = Hrow[disk[None, :], anu] * sign                  # H_{n-m}(k b_pq)
+    ph = np.exp(1j * nu * alpha[p][disk][None, :])        # e^{i(n-m) alpha_pq}
+    cpq = 0.5j * np.pi * np.sqrt(a[p] * a[disk])[None, :]
+    Jcol = besselj(m, k * a[disk])                        # J_n(k a_q) per column unknown
+    blk = cpq * besselj(mi, k * a[p])[:, None] * Hv * ph * Jcol[None, :]
+    blk[:, off[p]:off[p + 1]] = 0.0
+    d = efie_diagonal(a, n_modes, k)[rows]
+    blk[np.arange(len(mi)), off[p] + np.arange(len(mi))] = d
+    return blk
+
+
+def efie_matrix(centers, radii, n_modes, k):
+    """Dense N_tot x N_tot complex128 matrix L of the truncated EFIE (sec. 5)."""
+    n_modes = np.asarray(n_modes)
+    off, N = mode_offsets(n_modes)
     L = np.zeros((N, N), dtype=np.complex128)
-    for p in range(len(a)):
-        rows = slice(off[p], off[p + 1])
-        mi = m[rows]
-        nu = m[None, :] - mi[:, None]                     # n - m
-        anu = np.abs(nu)
-        sign = np.where((nu < 0) & (anu % 2 == 1), -1.0, 1.0)
-        Hv = Htab[p][disk[None, :], anu] * sign            # H_{n-m}(k b_pq)
-        ph = np.exp(1j * nu * alpha[p][disk][None, :])    # e^{i(n-m) alpha_pq}
-        cpq = 0.5j * np.pi * np.sqrt(a[p] * a[disk])[None, :]
-        blk = cpq * besselj(mi, k * a[p])[:, None] * Hv * ph * Jcol[None, :]
-        blk[:, off[p]:off[p + 1]] = 0.0
-        L[rows, :] = blk
-    L[np.arange(N), np.arange(N)] = efie_diagonal(a, n_modes, k)
+    for p in range(len(n_modes)):
+        L[off[p]:off[p + 1], :] = efie_row_block(centers, radii, n_modes, k, p)
     return L
 
 

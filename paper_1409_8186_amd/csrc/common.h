@@ -77,7 +77,17 @@ struct DevView {
   cplx* invSH;                // [N_all] 1 / (sqrt(a_p) H_m(k a_p))
   cplx* Ldiag;                // [N_all] (i pi a_p / 2) J_m(k a_p) H_m(k a_p)
   int32_t* udisk;             // [N_all] disk of each unknown
+  // Lane-interleaved copy for uniform N (lane_N >= 0, else unused): for every
+  // row disk p and chunk c of 64 column disks, [nu][lane] = H_nu(k b_pq),
+  // nu = 0..2N, then one row [lane] = e^{i alpha_pq}; chunk (p, c) starts at
+  // ltoff[p] + c * 64 * (2N + 2).
+  int lane_N;
+  cplx* lt;
+  const int64_t* ltoff;       // [M_all]
 };
+
+#define LANE_CHUNK 64
+#define LANE_NMAX 16
 
 // Column c = b * R + r of a packed [B][R][N_b] vector starts at
 // R * imode[b] + r * N_b.
@@ -95,6 +105,7 @@ __host__ __device__ __forceinline__ int64_t pair_index(const int64_t* idisk, con
 
 // ------------------------------------------------------------------ host side
 struct MatvecPlan {
+  int lane = 0;                  // one-lane-per-pair kernel
   int Bt = 0;                   // outputs per thread of the generic kernel
   int spec_N = -1;              // >= 0: uniform-N specialised kernel
   int zs = 0, ts = 0;            // LDS row strides (z rows, symbol rows)
@@ -110,7 +121,7 @@ struct MatvecPlan {
 struct mudiff_ctx {
   int B = 0, M_all = 0, Nmax = 0;
   int64_t N_all = 0, P_all = 0, T_all = 0, D_all = 0;
-  std::vector<int64_t> idisk, imode, ipair, moff, toff, dtab;
+  std::vector<int64_t> idisk, imode, ipair, moff, toff, dtab, ltoff;
   std::vector<int32_t> N, inst;
   std::vector<double> k, cx, cy, a;
   DevView dv{};
@@ -122,6 +133,10 @@ struct mudiff_ctx {
   MatvecPlan plan;
   int64_t plan_part = -1;       // partial sums per right-hand side of the plan
   bool mfma_enabled = true;     // multi-RHS applies on FP64 MFMA
+  std::vector<int32_t> mfma_groups;  // host copy of the MFMA row groups
+  int mfma_rp = 0;
+  int32_t* mfma_groups_dev = nullptr;  // inside the tables workspace
+  size_t mfma_groups_bytes = 0;
 };
 
 // ------------------------------------------------------------------ errors

@@ -2,12 +2,12 @@
 // A x = f, A = D^{-1} L, f = -D^{-1} U, one Krylov space per column (instance,
 // right-hand side); all columns share each operator application.
 //
-// Orthogonalisation is classical Gram-Schmidt applied twice (CGS2): two
-// passes of dot products + update, which keeps the basis orthogonal to
-// working precision with two reductions per pass instead of j for modified
-// Gram-Schmidt.  The Hessenberg column, the Givens rotations and the residual
-// estimate |g_{j+1}| / ||f|| are updated on the device by the last workgroup of
-// each column, so the host only synchronises to test for the end of a cycle.
+// Orthogonalisation is classical Gram-Schmidt applied twice (CGS2), which
+// keeps the basis orthogonal to working precision with two global reductions
+// per step (modified Gram-Schmidt needs j).  The Hessenberg column, the Givens
+// rotations and the residual estimate |g_{j+1}| / ||f|| are updated on the
+// device by the last workgroup of each column, so the host only synchronises
+// to test for the end of a cycle.
 //
 // Reductions are per column: the rows of a column are cut into chunks, every
 // chunk writes its partial sums, and the last chunk to finish (atomic counter,
@@ -18,6 +18,7 @@
 
 #define GS_THREADS 256
 #define GS_WAVES (GS_THREADS / 64)
+#define GS_BATCH 4
 
 enum { ST_RUN = 0, ST_CONV = 1, ST_BREAK = 2, ST_MAXIT = 3 };
 
@@ -64,8 +65,11 @@ __device__ __forceinline__ void decode_chunk(const GState& s, int gidx, int* col
 }
 
 // Last-chunk detection for column c: returns true in exactly one workgroup.
+// Release in every workgroup (write back this block's partials), acquire only
+// in the last one: an agent-scope acquire invalidates the XCD's L2, so it is
+// kept out of the workgroups that do not read other blocks' results.
 __device__ __forceinline__ bool last_chunk(const GState& s, int c, int nck, int* flag) {
-  __threadfence();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
   if (threadIdx.x == 0) {
     int old = atomicAdd(&s.cnt[c], 1);
@@ -73,88 +77,19 @@ __device__ __forceinline__ bool last_chunk(const GState& s, int c, int nck, int*
     if (*flag) atomicExch(&s.cnt[c], 0);
   }
   __syncthreads();
-  if (*flag) __threadfence();
+  if (*flag) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return *flag;
 }
 
-// Gram-Schmidt pass on w = V[j+1] for every active column.
-//   MODE 0: h[i] = <V_i, w>, i <= j              (first dots)
-//   MODE 1: w -= sum_i h1[i] V_i; h[i] = <V_i, w> (update + second dots)
-//   MODE 2: w -= sum_i h[i] V_i; ||w||^2, then the Arnoldi/Givens step
-// `nck` = chunks per column (ck_first[c] .. ck_first[c] + nck).
-template <int MODE>
-__global__ __launch_bounds__(GS_THREADS) void k_gs(GState s, int j, const int32_t* __restrict__ ck_first,
-                                                   const int32_t* __restrict__ ck_count,
-                                                   cplx* __restrict__ hdst) {
-  __shared__ cplx wl[1024];
-  __shared__ double sred[GS_WAVES * 2];
-  __shared__ int s_flag;
-  int c, len;
-  int64_t o;
-  decode_chunk(s, blockIdx.x, &c, &len, &o);
-  if (!s.inner[c]) return;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+// Arnoldi bookkeeping of column c after step j (one thread): Hessenberg column
+// h1 + h2 with subdiagonal hn, previous Givens rotations, the new rotation,
+// the residual estimate |g_{j+1}| / ||f|| and the stopping test.
+__device__ void arnoldi_step(const GState& s, int c, int j, const cplx* __restrict__ h2, double hn) {
   const int m1 = s.m + 1;
-  cplx* w = s.V + (int64_t)(j + 1) * s.NT + o;
-  // load (and update) the chunk of w
-  for (int r = tid; r < len; r += GS_THREADS) {
-    cplx v = w[r];
-    if (MODE >= 1) {
-      const cplx* hc = (MODE == 1 ? s.h1 : hdst) + (int64_t)c * m1;
-      for (int i = 0; i <= j; ++i) {
-        const cplx vi = s.V[(int64_t)i * s.NT + o + r];
-        const cplx hi = hc[i];
-        v = csub(v, cmul(hi, vi));
-      }
-      w[r] = v;
-    }
-    wl[r] = v;
-  }
-  __syncthreads();
-  const int nck = ck_count[c];
-  if (MODE <= 1) {
-    cplx* part = s.partial + (int64_t)blockIdx.x * m1;
-    for (int i = wv; i <= j; i += GS_WAVES) {
-      const cplx* vi = s.V + (int64_t)i * s.NT + o;
-      cplx a = cmk(0.0, 0.0);
-      for (int r = lane; r < len; r += 64) cmacc(a, vi[r], wl[r]);
-      a.x = wave_sum(a.x);
-      a.y = wave_sum(a.y);
-      if (lane == 0) part[i] = a;
-    }
-    if (!last_chunk(s, c, nck, &s_flag)) return;
-    cplx* hout = (MODE == 0 ? s.h1 : hdst) + (int64_t)c * m1;
-    const cplx* pbase = s.partial + (int64_t)ck_first[c] * m1;
-    for (int i = tid; i <= j; i += GS_THREADS) {
-      cplx a = cmk(0.0, 0.0);
-      for (int k = 0; k < nck; ++k) a = cadd(a, pbase[(int64_t)k * m1 + i]);
-      hout[i] = a;
-    }
-    return;
-  }
-  // MODE 2: squared norm of the updated w
-  double a = 0.0;
-  for (int r = tid; r < len; r += GS_THREADS) a += cabs2(wl[r]);
-  a = wave_sum(a);
-  if (lane == 0) sred[wv] = a;
-  __syncthreads();
-  if (tid == 0) {
-    double t = 0.0;
-    for (int k = 0; k < GS_WAVES; ++k) t += sred[k];
-    s.partial[(int64_t)blockIdx.x * m1] = cmk(t, 0.0);
-  }
-  if (!last_chunk(s, c, nck, &s_flag)) return;
-  if (tid != 0) return;
-  double nrm2 = 0.0;
-  for (int k = 0; k < nck; ++k) nrm2 += s.partial[(int64_t)(ck_first[c] + k) * m1].x;
-  // ---- Arnoldi bookkeeping of column c (one thread)
-  cplx* Hc = s.H + (int64_t)c * m1 * s.m;
-  cplx* hj = Hc + (int64_t)j * m1;  // column j of the Hessenberg matrix
+  cplx* hj = s.H + (int64_t)c * m1 * s.m + (int64_t)j * m1;  // column j
   const cplx* a1 = s.h1 + (int64_t)c * m1;
-  const cplx* a2 = hdst + (int64_t)c * m1;
+  const cplx* a2 = h2 + (int64_t)c * m1;
   for (int i = 0; i <= j; ++i) hj[i] = cadd(a1[i], a2[i]);
-  const double hn = sqrt(nrm2);
-  hj[j + 1] = cmk(hn, 0.0);
   double* csc = s.cs + (int64_t)c * s.m;
   cplx* snc = s.sn + (int64_t)c * s.m;
   cplx* gc = s.g + (int64_t)c * m1;
@@ -163,12 +98,11 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs(GState s, int j, const int32_
     hj[i + 1] = csub(cscale(hj[i + 1], csc[i]), cmul(cconj(snc[i]), hj[i]));
     hj[i] = t;
   }
-  // new rotation zeroing hj[j+1]
+  // rotation [c s; -conj(s) c] zeroing the subdiagonal hn (real, >= 0)
   const cplx aa = hj[j];
-  const double bb = hn;
   double cr;
   cplx sr;
-  if (bb == 0.0) {
+  if (hn == 0.0) {
     cr = 1.0;
     sr = cmk(0.0, 0.0);
   } else if (aa.x == 0.0 && aa.y == 0.0) {
@@ -176,14 +110,13 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs(GState s, int j, const int32_
     sr = cmk(1.0, 0.0);
   } else {
     const double na = sqrt(cabs2(aa));
-    const double rho = hypot(na, bb);
+    const double rho = hypot(na, hn);
     cr = na / rho;
-    sr = cscale(aa, bb / (na * rho));  // (a/|a|) conj(b)/rho, b real
+    sr = cscale(aa, hn / (na * rho));  // (a/|a|) conj(b)/rho, b real
   }
   csc[j] = cr;
   snc[j] = sr;
-  hj[j] = cadd(cscale(aa, cr), cscale(sr, bb));
-  hj[j + 1] = cmk(0.0, 0.0);
+  hj[j] = cadd(cscale(aa, cr), cscale(sr, hn));
   const cplx gj = gc[j];
   gc[j + 1] = cmul(cscale(cconj(sr), -1.0), gj);
   gc[j] = cscale(gj, cr);
@@ -203,15 +136,107 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs(GState s, int j, const int32_
   }
 }
 
-// v_{j+1} /= ||v_{j+1}|| for the columns still iterating (inv != 0).
-__global__ void k_normalize(GState s, int j, int64_t nrows_total, const int32_t* __restrict__ row_col) {
-  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= nrows_total) return;
-  const int c = row_col[g];
-  const double iv = s.inv[c];
-  if (iv == 0.0 || !s.inner[c]) return;
-  cplx* w = s.V + (int64_t)(j + 1) * s.NT + g;
-  *w = cscale(*w, iv);
+// Classical Gram-Schmidt applied twice on w = V[j+1], three passes per step:
+//   MODE 0: h1 = V^H w                                   (dots)
+//   MODE 1: w1 = w - V h1;  h2 = V^H w1;  n1 = ||w1||^2   (update + dots + norm)
+//           last chunk: ||w2||^2 = n1 - ||h2||^2 (w2 = w1 - V h2 is orthogonal
+//           to V h2), then the Arnoldi/Givens step of the column
+//   MODE 2: V[j+1] = (w1 - V h2) / ||w2||                (update + normalise)
+template <int MODE>
+__global__ __launch_bounds__(GS_THREADS) void k_gs(GState s, int j, const int32_t* __restrict__ ck_first,
+                                                   const int32_t* __restrict__ ck_count,
+                                                   cplx* __restrict__ hdst) {
+  __shared__ cplx wl[1024];
+  __shared__ double sred[GS_WAVES];
+  __shared__ int s_flag;
+  int c, len;
+  int64_t o;
+  decode_chunk(s, blockIdx.x, &c, &len, &o);
+  if (!s.inner[c]) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int m1 = s.m + 1;
+  cplx* w = s.V + (int64_t)(j + 1) * s.NT + o;
+  const double scale = MODE == 2 ? s.inv[c] : 1.0;
+  double nn = 0.0;
+  for (int r = tid; r < len; r += GS_THREADS) {
+    cplx v = w[r];
+    if (MODE >= 1) {
+      const cplx* hc = (MODE == 1 ? s.h1 : hdst) + (int64_t)c * m1;
+      const cplx* vr = s.V + o + r;
+      int i = 0;
+      for (; i + 3 <= j; i += 4) {  // four independent loads in flight
+        const cplx v0 = vr[(int64_t)i * s.NT], v1 = vr[(int64_t)(i + 1) * s.NT];
+        const cplx v2 = vr[(int64_t)(i + 2) * s.NT], v3 = vr[(int64_t)(i + 3) * s.NT];
+        v = csub(v, cmul(hc[i], v0));
+        v = csub(v, cmul(hc[i + 1], v1));
+        v = csub(v, cmul(hc[i + 2], v2));
+        v = csub(v, cmul(hc[i + 3], v3));
+      }
+      for (; i <= j; ++i) v = csub(v, cmul(hc[i], vr[(int64_t)i * s.NT]));
+      if (MODE == 2) {
+        w[r] = cscale(v, scale);
+        continue;
+      }
+      w[r] = v;
+      nn += cabs2(v);
+    }
+    wl[r] = v;
+  }
+  if (MODE == 2) return;
+  __syncthreads();
+  const int nck = ck_count[c];
+  cplx* part = s.partial + (int64_t)blockIdx.x * m1;
+  // wave wv takes i = wv, wv + GS_WAVES, ...; GS_BATCH of them at a time so
+  // that their loads are in flight together before the wave reductions
+  for (int i0 = wv; i0 <= j; i0 += GS_WAVES * GS_BATCH) {
+    cplx a[GS_BATCH];
+#pragma unroll
+    for (int u = 0; u < GS_BATCH; ++u) {
+      a[u] = cmk(0.0, 0.0);
+      const int i = i0 + u * GS_WAVES;
+      if (i <= j) {
+        const cplx* vi = s.V + (int64_t)i * s.NT + o;
+        for (int r = lane; r < len; r += 64) cmacc(a[u], vi[r], wl[r]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < GS_BATCH; ++u) {
+      a[u].x = wave_sum(a[u].x);
+      a[u].y = wave_sum(a[u].y);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int u = 0; u < GS_BATCH; ++u)
+        if (i0 + u * GS_WAVES <= j) part[i0 + u * GS_WAVES] = a[u];
+    }
+  }
+  if (MODE == 1) {  // ||w1||^2 of the chunk in the last slot (never a dot slot: j < m)
+    nn = wave_sum(nn);
+    if (lane == 0) sred[wv] = nn;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+      for (int k = 0; k < GS_WAVES; ++k) t += sred[k];
+      part[s.m] = cmk(t, 0.0);
+    }
+  }
+  if (!last_chunk(s, c, nck, &s_flag)) return;
+  cplx* hout = (MODE == 0 ? s.h1 : hdst) + (int64_t)c * m1;
+  const cplx* pbase = s.partial + (int64_t)ck_first[c] * m1;
+  for (int i = tid; i <= j; i += GS_THREADS) {
+    cplx a = cmk(0.0, 0.0);
+    for (int k = 0; k < nck; ++k) a = cadd(a, pbase[(int64_t)k * m1 + i]);
+    hout[i] = a;
+  }
+  if (MODE == 0) return;
+  __syncthreads();  // hout complete (and visible to thread 0 of this block)
+  if (tid != 0) return;
+  double n1 = 0.0;
+  for (int k = 0; k < nck; ++k) n1 += pbase[(int64_t)k * m1 + s.m].x;
+  double h2n = 0.0;
+  for (int i = 0; i <= j; ++i) h2n += cabs2(hout[i]);
+  const double hn2 = n1 - h2n;
+  arnoldi_step(s, c, j, hdst, sqrt(hn2 > 0.0 ? hn2 : 0.0));
 }
 
 // Chunked per-column sum of |src|^2 -> red[c]   (running columns only if
@@ -313,19 +338,27 @@ __global__ void k_scale_v0(GState s, int64_t nrows_total, const int32_t* __restr
 }
 
 // End of a cycle: y = R^{-1} g (upper-triangular Hessenberg after rotations).
-__global__ void k_cycle_solve(GState s) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= s.C) return;
+// One wavefront per column: back substitution with the column-oriented
+// update g_k -= R_{k,i} y_i spread over the lanes (k = lane, lane + 64).
+__global__ __launch_bounds__(64) void k_cycle_solve(GState s) {
+  const int c = blockIdx.x;
+  const int lane = threadIdx.x;
   const int n = s.run[c] ? s.jdone[c] : 0;
   const int m1 = s.m + 1;
   const cplx* Hc = s.H + (int64_t)c * m1 * s.m;
   const cplx* gc = s.g + (int64_t)c * m1;
   cplx* yc = s.y + (int64_t)c * s.m;
+  cplx g0 = lane < n ? gc[lane] : cmk(0.0, 0.0);
+  cplx g1 = lane + 64 < n ? gc[lane + 64] : cmk(0.0, 0.0);
   for (int i = n - 1; i >= 0; --i) {
-    cplx t = gc[i];
-    for (int k = i + 1; k < n; ++k) t = csub(t, cmul(Hc[(int64_t)k * m1 + i], yc[k]));
-    const cplx d = Hc[(int64_t)i * m1 + i];
-    yc[i] = (d.x == 0.0 && d.y == 0.0) ? cmk(0.0, 0.0) : cdiv(t, d);
+    const cplx* col = Hc + (int64_t)i * m1;  // column i of the triangular factor
+    const cplx d = col[i];
+    const cplx gi = i < 64 ? cmk(__shfl(g0.x, i, 64), __shfl(g0.y, i, 64))
+                           : cmk(__shfl(g1.x, i - 64, 64), __shfl(g1.y, i - 64, 64));
+    const cplx yi = (d.x == 0.0 && d.y == 0.0) ? cmk(0.0, 0.0) : cdiv(gi, d);
+    if (lane == 0) yc[i] = yi;
+    if (lane < i) g0 = csub(g0, cmul(col[lane], yi));
+    if (lane + 64 < i) g1 = csub(g1, cmul(col[lane + 64], yi));
   }
 }
 
@@ -375,6 +408,14 @@ __global__ void k_precond_rhs(DevView v, int R, const cplx* __restrict__ src, cp
 }
 
 // ------------------------------------------------------------------ host driver
+// Rows per reduction chunk: about 4096 chunks over all columns (enough
+// workgroups to fill the chip, few partial sums to combine), 64..1024 rows
+// each (1024 = the LDS row buffer of k_gs).
+static int64_t chunk_rows(int64_t NT) {
+  int64_t ch = ((NT + 4095) / 4096 + 63) / 64 * 64;
+  return std::min<int64_t>(std::max<int64_t>(ch, 64), 1024);
+}
+
 namespace {
 struct GLayout {
   size_t V, f, apply, ck, ckf, ckc, rowcol, partial, cnt, H, h1, h2, g, cs, sn, y, normf, red, inv,
@@ -391,8 +432,7 @@ GLayout glayout(mudiff_ctx* h, int R, int m) {
   int64_t nck = 0;
   for (int b = 0; b < h->B; ++b) {
     const int64_t Nb = h->imode[b + 1] - h->imode[b];
-    int64_t ch = std::max<int64_t>(64, ((Nb + 63) / 64 + 63) / 64 * 64);
-    ch = std::min<int64_t>(ch, 1024);
+    const int64_t ch = chunk_rows(NT);
     nck += (int64_t)R * ((Nb + ch - 1) / ch);
   }
   L.n_chunks = nck;
@@ -482,7 +522,6 @@ static int enqueue_cycle(GmresRun& G, int check_every, bool host_checks) {
     hipLaunchKernelGGL(k_gs<0>, dim3(nb), dim3(GS_THREADS), 0, G.st, s, j, G.d_ckf, G.d_ckc, G.h2);
     hipLaunchKernelGGL(k_gs<1>, dim3(nb), dim3(GS_THREADS), 0, G.st, s, j, G.d_ckf, G.d_ckc, G.h2);
     hipLaunchKernelGGL(k_gs<2>, dim3(nb), dim3(GS_THREADS), 0, G.st, s, j, G.d_ckf, G.d_ckc, G.h2);
-    hipLaunchKernelGGL(k_normalize, dim3(eb), dim3(256), 0, G.st, s, j, s.NT, G.d_rowcol);
     HIP_TRY(hipGetLastError());
     if (host_checks && check_every > 0 && (j + 1) % check_every == 0 && j + 1 < s.m) {
       int32_t n_in = 0;
@@ -491,7 +530,7 @@ static int enqueue_cycle(GmresRun& G, int check_every, bool host_checks) {
       if (n_in <= 0) break;
     }
   }
-  hipLaunchKernelGGL(k_cycle_solve, dim3(cb), dim3(64), 0, G.st, s);
+  hipLaunchKernelGGL(k_cycle_solve, dim3(s.C), dim3(64), 0, G.st, s);
   hipLaunchKernelGGL(k_update_x, dim3(eb), dim3(256), 0, G.st, s, s.NT, G.d_rowcol);
   HIP_TRY(hipGetLastError());
   int rc = apply_operator(G.h, s.R, s.x, s.V, MUDIFF_OP_A, G.apply_part, G.apply_cnt, s.run, G.st);
@@ -569,8 +608,7 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
   int64_t idx = 0;
   for (int b = 0; b < h->B; ++b) {
     const int64_t Nb = h->imode[b + 1] - h->imode[b];
-    int64_t ch = std::max<int64_t>(64, ((Nb + 63) / 64 + 63) / 64 * 64);
-    ch = std::min<int64_t>(ch, 1024);
+    const int64_t ch = chunk_rows(L.NT);
     for (int r = 0; r < R; ++r) {
       const int c = b * R + r;
       const int64_t base = col_base(h->imode.data(), b, R, r);

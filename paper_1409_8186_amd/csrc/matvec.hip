@@ -169,7 +169,7 @@ __global__ __launch_bounds__(APPLY_THREADS) void k_apply(
     for (int k = 0; k < nslot_max; ++k) w = cadd(w, red[k * LB + m]);
     pr[(int64_t)c * np + m] = w;
   }
-  __threadfence();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // publish this chunk
   __syncthreads();
   if (tid == 0) {
     int32_t* cnt = counters + (int64_t)r * v.M_all + p;
@@ -179,13 +179,106 @@ __global__ __launch_bounds__(APPLY_THREADS) void k_apply(
   }
   __syncthreads();
   if (!s_last) return;
-  __threadfence();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // see the other chunks
   for (int m = tid; m < np; m += APPLY_THREADS) {
     cplx w = cmk(0.0, 0.0);
     for (int k = 0; k < nch; ++k) {
       w = cadd(w, pr[(int64_t)k * np + m]);  // visible after the fence above
     }
     yc[m] = finalize(v, op, ip + m, xp[m], w);
+  }
+}
+
+// ------------------------------------------------------------------ one lane per pair
+// Uniform N_p = N, few right-hand sides: lane l of a wave owns the ordered pair
+// (p, q_l) and keeps all n = 2N+1 outputs in registers.  The symbols come from
+// the lane-interleaved table (H_nu(k b_pq) for nu >= 0 and e^{i alpha_pq}), so a
+// wave load of H_nu is one contiguous 1 KB line; the phase e^{i nu alpha} is
+// carried by recurrence and t_{+nu} = H_nu e^{i nu alpha},
+// t_{-nu} = (-1)^nu H_nu e^{-i nu alpha}.  The product runs diagonal by
+// diagonal (w_m += t_s z_{m+s}) with the scaled inputs z in registers.  A wave
+// covers 64 column disks of one row; lanes are summed through LDS and chunk
+// partials are combined by the last wave of the row (chunk order).
+template <int N>
+__global__ __launch_bounds__(64, (N <= 12 ? 2 : 1)) void k_apply_lane(
+    DevView v, int R, const cplx* __restrict__ x, cplx* __restrict__ y, int op,
+    cplx* __restrict__ part, int64_t part_total, int32_t* __restrict__ counters,
+    const int32_t* __restrict__ items, const int32_t* __restrict__ nchunk,
+    const int64_t* __restrict__ partoff, const int32_t* __restrict__ active) {
+  constexpr int n = 2 * N + 1, S = 2 * N;
+  __shared__ cplx red[64 * n];
+  __shared__ int s_last;
+  const int it = blockIdx.x, r = blockIdx.y;
+  const int p = items[4 * it], c = items[4 * it + 1], jb = items[4 * it + 2], je = items[4 * it + 3];
+  const int b = v.inst[p];
+  if (active && active[b * R + r] == 0) return;
+  const int lane = threadIdx.x;
+  const int64_t d0 = v.idisk[b];
+  const int64_t i0 = v.imode[b];
+  const int64_t cb = col_base(v.imode, b, R, r);
+  const int j = jb + lane;
+  cplx acc[n];
+#pragma unroll
+  for (int m = 0; m < n; ++m) acc[m] = cmk(0.0, 0.0);
+  if (j < je) {
+    const int q = (int)(d0 + j + ((d0 + j) >= p ? 1 : 0));
+    const cplx* __restrict__ Hl = v.lt + v.ltoff[p] + (int64_t)c * (LANE_CHUNK * (S + 2)) + lane;
+    const int64_t iq = (int64_t)(q - d0) * n;  // uniform N: moff[q] = (q - d0) n
+    cplx z[n];
+#pragma unroll
+    for (int k = 0; k < n; ++k) z[k] = cscale(x[cb + iq + k], v.sJ[i0 + iq + k]);
+    const cplx E = Hl[(S + 1) * LANE_CHUNK];
+    cplx P = cmk(1.0, 0.0);
+    {
+      const cplx h0 = Hl[0];
+#pragma unroll
+      for (int m = 0; m < n; ++m) cmac(acc[m], h0, z[m]);
+    }
+#pragma unroll
+    for (int nu = 1; nu <= S; ++nu) {
+      const cplx H = Hl[nu * LANE_CHUNK];
+      P = cmul(P, E);
+      const cplx tp = cmul(H, P);
+      cplx tm = cmul(H, cconj(P));
+      if (nu & 1) tm = cmk(-tm.x, -tm.y);
+#pragma unroll
+      for (int m = 0; m < n - nu; ++m) cmac(acc[m], tp, z[m + nu]);
+#pragma unroll
+      for (int m = nu; m < n; ++m) cmac(acc[m], tm, z[m - nu]);
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < n; ++m) red[lane * n + m] = acc[m];
+  __syncthreads();
+  const int nch = nchunk[p];
+  const int64_t ip = i0 + v.moff[p];
+  cplx* yc = y + cb + v.moff[p];
+  const cplx* xp = x + cb + v.moff[p];
+  const int nl = min(64, je - jb);
+  cplx w = cmk(0.0, 0.0);
+  if (lane < n)
+    for (int k = 0; k < nl; ++k) w = cadd(w, red[k * n + lane]);
+  if (nch == 1) {
+    if (lane < n) yc[lane] = finalize(v, op, ip + lane, xp[lane], w);
+    return;
+  }
+  cplx* pr = part + (int64_t)r * part_total + partoff[p];
+  if (lane < n) pr[(int64_t)c * n + lane] = w;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // publish this chunk
+  __syncthreads();
+  if (lane == 0) {
+    int32_t* cnt = counters + (int64_t)r * v.M_all + p;
+    int old = atomicAdd(cnt, 1);
+    s_last = (old == nch - 1);
+    if (s_last) atomicExch(cnt, 0);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // see the other chunks
+  if (lane < n) {
+    cplx ws = cmk(0.0, 0.0);
+    for (int k = 0; k < nch; ++k) ws = cadd(ws, pr[(int64_t)k * n + lane]);
+    yc[lane] = finalize(v, op, ip + lane, xp[lane], ws);
   }
 }
 
@@ -203,79 +296,126 @@ __global__ __launch_bounds__(APPLY_THREADS) void k_apply(
 // A[l % 16][l / 16], B[l / 16][l % 16] and D[4 v + l / 16][l % 16], v < 4.
 typedef double mf_d4 __attribute__((ext_vector_type(4)));
 
+// Work item: up to RP consecutive row disks p0..p0+rp-1 of one instance and a
+// tile of 8 * CT right-hand sides; wave w computes row r = w / CT, right-hand
+// side sub-tile w % CT.  The input panel Z^q is staged once per column disk q
+// for all rows of the item; the next column disk's symbols and inputs are
+// loaded into registers while the current one is on the matrix cores.
+#define MF_ZK 8   // staged Z values per thread (4 * 16 rows * 32 columns / 256)
+#define MF_TK 2   // staged symbol values per thread (4 rows * (64 + 64) / 256)
+
 template <int MT>  // row tiles of 16: n_p <= 16 MT
 __global__ __launch_bounds__(256) void k_apply_mfma(DevView v, int R, const cplx* __restrict__ x,
                                                     cplx* __restrict__ y, int op,
-                                                    const int32_t* __restrict__ active, int ktmax) {
+                                                    const int32_t* __restrict__ active,
+                                                    const int32_t* __restrict__ groups, int ktmax,
+                                                    int RP, int CT) {
   extern __shared__ cplx lds[];
-  const int p = blockIdx.x;
-  const int nwaves = blockDim.x >> 6;
-  const int RC = 8 * nwaves;
+  const int p0 = groups[2 * blockIdx.x], rp = groups[2 * blockIdx.x + 1];
+  const int RC = 8 * CT;
   const int c0 = blockIdx.y * RC;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int j = lane & 15, kq = lane >> 4;
-  const int b = v.inst[p];
-  const int Np = v.N[p], np = 2 * Np + 1;
+  const int row = wave / CT, ctile = wave - (wave / CT) * CT;
+  const int b = v.inst[p0];
   const int64_t d0 = v.idisk[b], Mb = v.idisk[b + 1] - d0;
   const int64_t i0 = v.imode[b];
-  const int mycol = c0 + wave * 8 + (j & 7);
-  bool wave_active = false;
-  for (int c = 0; c < 8; ++c) {
-    const int r = c0 + wave * 8 + c;
-    if (r < R && (!active || active[b * R + r])) wave_active = true;
+  const int TL = 4 * ktmax + 16 * MT - 1;   // symbol row length in LDS
+  const int p = p0 + row;
+  const bool row_ok = row < rp;
+  const int Np = row_ok ? v.N[p] : 0, np = 2 * Np + 1;
+  const int mycol = c0 + ctile * 8 + (j & 7);
+  bool wave_active = row_ok;
+  if (wave_active) {
+    wave_active = false;
+    for (int c = 0; c < 8; ++c) {
+      const int r = c0 + ctile * 8 + c;
+      if (r < R && (!active || active[b * R + r])) wave_active = true;
+    }
   }
   bool any = false;  // the whole workgroup may skip (converged columns)
   for (int r = c0; r < min(R, c0 + RC); ++r)
     if (!active || active[b * R + r]) any = true;
   if (!any) return;
   cplx* zl = lds;                       // [4 ktmax][RC]
-  cplx* tl = lds + 4 * ktmax * RC;      // [4 ktmax + 16 MT - 1]
+  cplx* tl = lds + 4 * ktmax * RC;      // [RP][TL]
   mf_d4 acc1[MT], acc2[MT];
 #pragma unroll
   for (int t = 0; t < MT; ++t) {
     acc1[t] = mf_d4{0.0, 0.0, 0.0, 0.0};
     acc2[t] = mf_d4{0.0, 0.0, 0.0, 0.0};
   }
-  for (int64_t ql = 0; ql < Mb; ++ql) {
-    const int q = (int)(d0 + ql);
-    if (q == p) continue;
-    const int Nq = v.N[q], nq = 2 * Nq + 1, KT = (nq + 3) >> 2;
-    const int S = Np + Nq;
-    const int nrow = 4 * KT;
-    __syncthreads();
-    // scaled inputs Z[n][c] = sqrt(a_q) J_n(k a_q) x[c][n]  (contiguous in n)
-    for (int e = tid; e < nrow * RC; e += blockDim.x) {
-      const int c = e / nrow, n = e - (e / nrow) * nrow;
-      const int r = c0 + c;
+  // this thread's staging slots (fixed over the column disks): input panel
+  // element (column zc, row zn), symbol element (row tr_r, position tr_u)
+  int zc[MF_ZK], zn[MF_ZK], trr[MF_TK], tru[MF_TK];
+  const int zrows = 4 * ktmax;
+#pragma unroll
+  for (int k = 0; k < MF_ZK; ++k) {
+    const int e = tid + k * 256;
+    zc[k] = e / zrows;
+    zn[k] = e - zc[k] * zrows;
+  }
+#pragma unroll
+  for (int k = 0; k < MF_TK; ++k) {
+    const int e = tid + k * 256;
+    trr[k] = e / TL;
+    tru[k] = e - trr[k] * TL;
+  }
+  cplx zr[MF_ZK], tr[MF_TK];
+  // gather the staged values of column disk q into registers
+  auto gather = [&](int q) {
+    const int Nq = v.N[q], nq = 2 * Nq + 1;
+    const int64_t mq = v.moff[q];
+#pragma unroll
+    for (int k = 0; k < MF_ZK; ++k) {
+      const int c = zc[k], n = zn[k];
       cplx z = cmk(0.0, 0.0);
-      if (n < nq && r < R) {
-        const int64_t iq = v.moff[q] + n;
-        z = cscale(x[col_base(v.imode, b, R, r) + iq], v.sJ[i0 + iq]);
+      if (c < RC && n < nq && c0 + c < R) {
+        const int r = c0 + c;
+        z = cscale(x[col_base(v.imode, b, R, r) + mq + n], v.sJ[i0 + mq + n]);
       }
-      zl[n * RC + c] = z;
+      zr[k] = z;
     }
-    // symbol row: u = n - m + 16 MT - 1  <->  s = u - (16 MT - 1) - N_q + N_p
-    const int nu = nrow + 16 * MT - 1;
-    const int64_t g = pair_index(v.idisk, v.ipair, b, p, q);
-    const cplx* T = v.t + v.toff[g] + S;
-    for (int u = tid; u < nu; u += blockDim.x) {
-      const int s = u - (16 * MT - 1) - Nq + Np;
+#pragma unroll
+    for (int k = 0; k < MF_TK; ++k) {
+      const int rr = trr[k], u = tru[k];
       cplx t = cmk(0.0, 0.0);
-      if (s >= -S && s <= S) {
-        t = T[s];
-        if (p > q && (s & 1)) t = cmk(-t.x, -t.y);
+      const int pr = p0 + rr;
+      if (rr < rp && pr != q) {
+        const int Npr = v.N[pr];
+        const int S = Npr + Nq;
+        const int s = u - (16 * MT - 1) - Nq + Npr;
+        if (s >= -S && s <= S) {
+          const int64_t g = pair_index(v.idisk, v.ipair, b, pr, q);
+          t = v.t[v.toff[g] + S + s];
+          if (pr > q && (s & 1)) t = cmk(-t.x, -t.y);
+        }
       }
-      tl[u] = t;
+      tr[k] = t;
     }
+  };
+  int q = (int)d0;
+  gather(q);
+  for (; q < (int)(d0 + Mb); ++q) {
+    const int nq = 2 * v.N[q] + 1, KT = (nq + 3) >> 2;
+    __syncthreads();  // previous column disk done with LDS
+#pragma unroll
+    for (int k = 0; k < MF_ZK; ++k)
+      if (zc[k] < RC) zl[zn[k] * RC + zc[k]] = zr[k];
+#pragma unroll
+    for (int k = 0; k < MF_TK; ++k)
+      if (trr[k] < RP) tl[trr[k] * TL + tru[k]] = tr[k];
     __syncthreads();
-    if (wave_active) {
+    if (q + 1 < (int)(d0 + Mb)) gather(q + 1);  // in flight during the MFMAs
+    if (wave_active && q != p) {
+      const cplx* trow = tl + row * TL;
       for (int kk = 0; kk < KT; ++kk) {
         const int n = 4 * kk + kq;
-        const cplx zz = zl[n * RC + wave * 8 + (j & 7)];
+        const cplx zz = zl[n * RC + ctile * 8 + (j & 7)];
         const double bv = j < 8 ? zz.x : zz.y;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-          const cplx t = tl[n - (16 * mt + j) + 16 * MT - 1];  // A[i = lane % 16][k = kq]
+          const cplx t = trow[n - (16 * mt + j) + 16 * MT - 1];  // A[i = lane % 16][k = kq]
           acc1[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(t.x, bv, acc1[mt], 0, 0, 0);
           acc2[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(t.y, bv, acc2[mt], 0, 0, 0);
         }
@@ -307,15 +447,35 @@ static int launch_apply_mfma(mudiff_ctx* h, int R, const cplx* x, cplx* y, int o
                              const int32_t* active, hipStream_t s) {
   const int mt = (2 * h->Nmax + 1 + 15) / 16;
   const int kt = (2 * h->Nmax + 1 + 3) / 4;
-  const int nw = std::min(4, (R + 7) / 8);
-  const int rc = 8 * nw;
-  const size_t lds = ((size_t)4 * kt * rc + 4 * kt + 16 * mt) * 16;
-  dim3 grid(h->M_all, (R + rc - 1) / rc), block(64 * nw);
+  // 8-RHS sub-tiles per item (CT) and row disks per item (RP), CT * RP = 4 waves
+  const int ct = std::min(4, (R + 7) / 8);
+  const int CT = ct == 3 ? 4 : ct;
+  const int RP = 4 / CT;
+  if (h->mfma_groups.empty() || h->mfma_rp != RP) {
+    // groups of RP consecutive row disks inside one instance
+    std::vector<int32_t> gr;
+    for (int b = 0; b < h->B; ++b)
+      for (int64_t p = h->idisk[b]; p < h->idisk[b + 1]; p += RP) {
+        gr.push_back((int32_t)p);
+        gr.push_back((int32_t)std::min<int64_t>(RP, h->idisk[b + 1] - p));
+      }
+    if ((size_t)gr.size() * 4 > h->mfma_groups_bytes)
+      return fail(MUDIFF_ERR_INVALID, "MFMA group table does not fit");
+    HIP_TRY(hipMemcpyAsync(h->mfma_groups_dev, gr.data(), gr.size() * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    h->mfma_groups.swap(gr);
+    h->mfma_rp = RP;
+  }
+  const int ngroups = (int)(h->mfma_groups.size() / 2);
+  const int RC = 8 * CT;
+  const size_t lds = ((size_t)4 * kt * RC + (size_t)RP * (4 * kt + 16 * mt - 1)) * 16;
+  dim3 grid(ngroups, (R + RC - 1) / RC), block(256);
+  const int32_t* g = h->mfma_groups_dev;
   switch (mt) {
-    case 1: hipLaunchKernelGGL(k_apply_mfma<1>, grid, block, lds, s, h->dv, R, x, y, op, active, kt); break;
-    case 2: hipLaunchKernelGGL(k_apply_mfma<2>, grid, block, lds, s, h->dv, R, x, y, op, active, kt); break;
-    case 3: hipLaunchKernelGGL(k_apply_mfma<3>, grid, block, lds, s, h->dv, R, x, y, op, active, kt); break;
-    case 4: hipLaunchKernelGGL(k_apply_mfma<4>, grid, block, lds, s, h->dv, R, x, y, op, active, kt); break;
+    case 1: hipLaunchKernelGGL(k_apply_mfma<1>, grid, block, lds, s, h->dv, R, x, y, op, active, g, kt, RP, CT); break;
+    case 2: hipLaunchKernelGGL(k_apply_mfma<2>, grid, block, lds, s, h->dv, R, x, y, op, active, g, kt, RP, CT); break;
+    case 3: hipLaunchKernelGGL(k_apply_mfma<3>, grid, block, lds, s, h->dv, R, x, y, op, active, g, kt, RP, CT); break;
+    case 4: hipLaunchKernelGGL(k_apply_mfma<4>, grid, block, lds, s, h->dv, R, x, y, op, active, g, kt, RP, CT); break;
     default: return fail(MUDIFF_ERR_INVALID, "N_p too large for the MFMA apply");
   }
   HIP_TRY(hipGetLastError());
@@ -329,17 +489,18 @@ static int launch_apply_mfma(mudiff_ctx* h, int R, const cplx* x, cplx* y, int o
 namespace {
 typedef void (*apply_fn)(DevView, int, const cplx*, cplx*, int, cplx*, int64_t, int32_t*,
                          const int32_t*, const int32_t*, const int64_t*, const int32_t*, int, int, int);
+typedef void (*lane_fn)(DevView, int, const cplx*, cplx*, int, cplx*, int64_t, int32_t*,
+                        const int32_t*, const int32_t*, const int64_t*, const int32_t*);
 
 struct Variant {
   int bt, nspec;
   apply_fn fn;
 };
 
+// LDS-staged kernels: generic (nspec = -1) and uniform-N specialisations
 const Variant kVariants[] = {
-    {4, -1, k_apply<4, -1>},  {5, -1, k_apply<5, -1>},  {6, -1, k_apply<6, -1>},
-    {8, -1, k_apply<8, -1>},  {5, 12, k_apply<5, 12>},  {4, 15, k_apply<4, 15>},
-    {5, 7, k_apply<5, 7>},    {4, 10, k_apply<4, 10>},  {5, 2, k_apply<5, 2>},
-    {4, 3, k_apply<4, 3>},    {4, 4, k_apply<4, 4>},    {4, 8, k_apply<4, 8>},
+    {4, -1, k_apply<4, -1>}, {5, -1, k_apply<5, -1>}, {6, -1, k_apply<6, -1>},
+    {8, -1, k_apply<8, -1>}, {5, 12, k_apply<5, 12>}, {4, 15, k_apply<4, 15>},
 };
 
 const Variant* find_variant(int bt, int nspec) {
@@ -347,11 +508,31 @@ const Variant* find_variant(int bt, int nspec) {
     if (v.bt == bt && v.nspec == nspec) return &v;
   return nullptr;
 }
+
+struct LaneVariant {
+  int n;
+  lane_fn fn;
+};
+
+// one-lane-per-pair kernels (uniform N)
+const LaneVariant kLane[] = {
+    {2, k_apply_lane<2>},   {3, k_apply_lane<3>},   {4, k_apply_lane<4>},   {5, k_apply_lane<5>},
+    {6, k_apply_lane<6>},   {7, k_apply_lane<7>},   {8, k_apply_lane<8>},   {9, k_apply_lane<9>},
+    {10, k_apply_lane<10>}, {11, k_apply_lane<11>}, {12, k_apply_lane<12>}, {13, k_apply_lane<13>},
+    {14, k_apply_lane<14>}, {15, k_apply_lane<15>}, {16, k_apply_lane<16>},
+};
+
+const LaneVariant* find_lane(int n) {
+  for (const LaneVariant& v : kLane)
+    if (v.n == n) return &v;
+  return nullptr;
+}
 }  // namespace
 
 // Host plan of the operator apply: kernel variant, work items and partial-sum
 // layout, from the batch description alone (also used to size workspaces).
 struct PlanHost {
+  int lane = 0;  // 1: one-lane-per-pair kernel (uniform N = nspec)
   int bt = 4, nspec = -1, zs = 0, ts = 0, ppcap = 1;
   size_t lds = 0;
   int64_t part = 0;
@@ -381,6 +562,37 @@ static void choose_variant(int M, const int32_t* N, int* bt, int* nspec) {
 
 void make_plan(int B, const int64_t* idisk, const int32_t* N, PlanHost& P) {
   const int M = (int)idisk[B];
+  P.items.clear();
+  P.nch.assign(M, 0);
+  P.poff.assign(M, 0);
+  P.part = 0;
+  P.lds = 0;
+  bool uniform = true;
+  for (int p = 1; p < M; ++p)
+    if (N[p] != N[0]) uniform = false;
+  if (uniform && N[0] <= LANE_NMAX && find_lane(N[0])) {
+    P.lane = 1;
+    P.nspec = N[0];
+    const int np = 2 * N[0] + 1;
+    for (int b = 0; b < B; ++b) {
+      const int64_t d0 = idisk[b], Mb = idisk[b + 1] - d0;
+      const int64_t n = std::max<int64_t>(1, (Mb - 1 + LANE_CHUNK - 1) / LANE_CHUNK);
+      for (int64_t p = d0; p < d0 + Mb; ++p) {
+        P.nch[p] = (int32_t)n;
+        P.poff[p] = P.part;
+        P.part += n * np;
+        for (int64_t c = 0; c < n; ++c) {
+          int64_t jb = c * LANE_CHUNK, je = std::min<int64_t>(jb + LANE_CHUNK, Mb - 1);
+          P.items.push_back((int32_t)p);
+          P.items.push_back((int32_t)c);
+          P.items.push_back((int32_t)jb);
+          P.items.push_back((int32_t)je);
+        }
+      }
+    }
+    return;
+  }
+  P.lane = 0;
   choose_variant(M, N, &P.bt, &P.nspec);
   const int bt = P.bt;
   int nmax = 0;
@@ -389,11 +601,6 @@ void make_plan(int B, const int64_t* idisk, const int32_t* N, PlanHost& P) {
   P.zs = ((2 * nmax + 1) + bt - 1) / bt * bt;
   P.ts = P.zs + P.zs - 1;
   P.ppcap = std::max(1, (int)(APPLY_LDS_BUDGET / ((size_t)(P.zs + P.ts) * 16)));
-  P.items.clear();
-  P.nch.assign(M, 0);
-  P.poff.assign(M, 0);
-  P.part = 0;
-  P.lds = 0;
   for (int b = 0; b < B; ++b) {
     const int64_t d0 = idisk[b], Mb = idisk[b + 1] - d0;
     for (int64_t p = d0; p < d0 + Mb; ++p) {
@@ -443,6 +650,7 @@ int ensure_plan(mudiff_ctx* h, hipStream_t s) {
   HIP_TRY(hipMemcpyAsync(P.d_nchunk, H.nch.data(), h->M_all * 4, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(P.d_partoff, H.poff.data(), h->M_all * 8, hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));  // the host vectors are released on return
+  P.lane = H.lane;
   P.Bt = H.bt;
   P.spec_N = H.nspec;
   P.zs = H.zs;
@@ -470,6 +678,14 @@ int apply_operator(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, cplx* p
   int st = ensure_plan(h, s);
   if (st != MUDIFF_OK) return st;
   const MatvecPlan& P = h->plan;
+  if (P.lane) {
+    const LaneVariant* lv = find_lane(P.spec_N);
+    if (!lv) return fail(MUDIFF_ERR_INVALID, "no operator kernel variant");
+    hipLaunchKernelGGL(lv->fn, dim3(P.n_items, R), dim3(64), 0, s, h->dv, R, x, y, op, part,
+                       P.part_total, counters, P.d_items, P.d_nchunk, P.d_partoff, active);
+    HIP_TRY(hipGetLastError());
+    return MUDIFF_OK;
+  }
   const Variant* var = find_variant(P.Bt, P.spec_N);
   if (!var) return fail(MUDIFF_ERR_INVALID, "no operator kernel variant");
   hipLaunchKernelGGL(var->fn, dim3(P.n_items, R), dim3(APPLY_THREADS), P.lds_bytes, s, h->dv, R, x,

@@ -148,6 +148,20 @@ __global__ void k_pair_tables(DevView v, int64_t P_all) {
       T[n + 1].y = y;
     }
   }
+  // lane-interleaved copy for uniform N: H_nu and e^{i alpha} of both orders
+  if (v.lane_N >= 0) {
+    const int64_t pc = (int64_t)LANE_CHUNK * (S + 2);
+    const cplx e = cexpi(alpha);
+    const int64_t jpq = q - v.idisk[b] - 1, jqp = p - v.idisk[b];  // q > p
+    cplx* A = v.lt + v.ltoff[p] + (jpq / LANE_CHUNK) * pc + (jpq % LANE_CHUNK);
+    cplx* Bq = v.lt + v.ltoff[q] + (jqp / LANE_CHUNK) * pc + (jqp % LANE_CHUNK);
+    for (int nu = 0; nu <= S; ++nu) {
+      A[(int64_t)nu * LANE_CHUNK] = T[nu];
+      Bq[(int64_t)nu * LANE_CHUNK] = T[nu];
+    }
+    A[(int64_t)(S + 1) * LANE_CHUNK] = e;
+    Bq[(int64_t)(S + 1) * LANE_CHUNK] = cmk(-e.x, -e.y);  // alpha_qp = alpha_pq + pi
+  }
   // phases: t_s = H_s e^{i s alpha}, t_{-s} = (-1)^s H_s e^{-i s alpha}
   for (int s = S; s >= 1; --s) {
     cplx H = T[s];
@@ -161,10 +175,37 @@ __global__ void k_pair_tables(DevView v, int64_t P_all) {
 // ------------------------------------------------------------------ layout
 size_t sched_bytes_for(int B, const int64_t* disk_off, const int32_t* n_modes);
 
+// Lane-interleaved table of a uniform-N batch (1 <= N <= LANE_NMAX): returns
+// its size in complex values (0 when N is not uniform or out of range), the
+// common N, and per disk the offset of its first chunk.
+int64_t lane_layout(int B, const int64_t* disk_off, const int32_t* n_modes, int* lane_N,
+                    std::vector<int64_t>* ltoff) {
+  const int64_t M = disk_off[B];
+  *lane_N = -1;
+  if (ltoff) ltoff->assign(M, 0);  // uploaded even when there is no lane table
+  for (int64_t p = 1; p < M; ++p)
+    if (n_modes[p] != n_modes[0]) return 0;
+  const int N = n_modes[0];
+  if (N < 1 || N > LANE_NMAX) return 0;
+  *lane_N = N;
+  const int64_t per_chunk = (int64_t)LANE_CHUNK * (2 * N + 2);
+  int64_t o = 0;
+  for (int b = 0; b < B; ++b) {
+    const int64_t Mb = disk_off[b + 1] - disk_off[b];
+    const int64_t nch = (Mb - 1 + LANE_CHUNK - 1) / LANE_CHUNK;
+    for (int64_t p = disk_off[b]; p < disk_off[b + 1]; ++p) {
+      if (ltoff) (*ltoff)[p] = o;
+      o += nch * per_chunk;
+    }
+  }
+  return o;
+}
+
 namespace {
 struct Layout {
   size_t off_cx, off_cy, off_a, off_kd, off_N, off_inst, off_moff, off_dtab, off_idisk, off_imode,
-      off_ipair, off_toff, off_t, off_Jd, off_Hd, off_sJ, off_invSH, off_Ldiag, off_udisk, off_sched;
+      off_ipair, off_toff, off_t, off_Jd, off_Hd, off_sJ, off_invSH, off_Ldiag, off_udisk, off_sched,
+      off_lt, off_ltoff, off_mfg;
   size_t sched_bytes, total;
 };
 
@@ -199,6 +240,11 @@ Layout make_layout(int B, const int64_t* disk_off, const int32_t* n_modes, int64
   L.off_udisk = take(N_all * 4);
   L.sched_bytes = sched_bytes_for(B, disk_off, n_modes);
   L.off_sched = take(L.sched_bytes);
+  int lane_N;
+  const int64_t lt = lane_layout(B, disk_off, n_modes, &lane_N, nullptr);
+  L.off_lt = take(lt * 16);
+  L.off_ltoff = take(M * 8);
+  L.off_mfg = take(M * 8);
   L.total = o;
   return L;
 }
@@ -344,6 +390,11 @@ extern "C" int mudiff_tables(int B, const int64_t* disk_off, const double* cente
   v.invSH = (cplx*)(base + L.off_invSH);
   v.Ldiag = (cplx*)(base + L.off_Ldiag);
   v.udisk = (int32_t*)(base + L.off_udisk);
+  v.lt = (cplx*)(base + L.off_lt);
+  v.ltoff = (int64_t*)(base + L.off_ltoff);
+  lane_layout(B, disk_off, n_modes, &v.lane_N, &h->ltoff);
+  h->mfma_groups_dev = (int32_t*)(base + L.off_mfg);
+  h->mfma_groups_bytes = (size_t)M * 8;
   h->sched_base = base + L.off_sched;
   h->sched_bytes = L.sched_bytes;
 
@@ -368,6 +419,7 @@ extern "C" int mudiff_tables(int B, const int64_t* disk_off, const double* cente
   chk(up(v.imode, h->imode.data(), (B + 1) * 8), "upload imode");
   chk(up(v.ipair, h->ipair.data(), (B + 1) * 8), "upload ipair");
   chk(up(v.toff, h->toff.data(), (P_all + 1) * 8), "upload toff");
+  chk(up(v.ltoff, h->ltoff.data(), M * 8), "upload ltoff");
   // the uploads read pageable host memory that this function owns only
   // until it returns: finish them before the kernels are enqueued
   chk(hipStreamSynchronize(s), "upload sync");

@@ -1,0 +1,124 @@
+"""GPU parity at the full workload sizes, on sampled outputs the oracle can form
+one by one (rows of the operator, single instances, single configurations).
+
+  * multi_rhs: M = 1000 disks, uneven N_p = ceil(10 a_p) + 10, R = 256 (FP64-MFMA
+    apply): sampled operator rows against oracle row blocks;
+  * uneven instances: 512 seeded instances x 8 incidences solved together
+    (GMRES at tol 1e-12): sampled instances against oracle LU;
+  * differentiation: 32 configurations x 64 incidences x 64 receivers, adjoint
+    gradient (tol 1e-12): sampled configurations against the oracle gradient.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import geometry, gradient, operator, rhs, solve
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_1409_8186_amd import Problem
+    assert torch.cuda.is_available()
+    return Problem
+
+
+def test_multi_rhs_full_size_apply(P):
+    cl = synth.multi_rhs()
+    R = 256
+    say("multi_rhs: M", cl.M, "N_tot", cl.n_tot, "R", R)
+    pr = P.from_cluster(cl)
+    rng = np.random.default_rng(33)
+    X = rng.normal(size=(R, cl.n_tot)) + 1j * rng.normal(size=(R, cl.n_tot))
+    y = pr.matvec(torch.tensor(X.ravel(), device="cuda"), R=R, op=1).cpu().numpy().reshape(R, -1)
+    off, _ = geometry.mode_offsets(cl.n_modes)
+    D = operator.efie_diagonal(cl.radii, cl.n_modes, cl.k)
+    worst = 0.0
+    for p in [0, 17, 500, 998, 999] + list(rng.integers(0, cl.M, 5)):
+        blk = operator.efie_row_block(cl.centers, cl.radii, cl.n_modes, cl.k, int(p))
+        rows = slice(off[p], off[p + 1])
+        ref = (X @ blk.T) / D[rows][None, :]            # rows of A = D^-1 L, all 256 columns
+        worst = max(worst, rel(y[:, rows], ref))
+    say("  worst sampled-row rel err", worst)
+    assert worst < 1e-12
+
+
+def test_uneven_instances_full_size_gmres(P):
+    insts = synth.uneven_instances()
+    R = 8
+    say("uneven: instances", len(insts), "unknowns", sum(c.n_tot for c in insts))
+    pr = P.from_clusters(insts)
+    betas = np.stack([c.betas for c in insts])
+    # solved in segments of 10 restart cycles, each warm-started from the last,
+    # so that progress is visible; converged columns stop at once
+    rho, its = None, None
+    for seg in range(40):
+        rho, flag, relres, iters, _ = pr.gmres(betas=betas, restart=50, tol=1e-12, maxit=500,
+                                               x0=rho)
+        it = iters.cpu().numpy()
+        its = it if its is None else its + it
+        say("  segment", seg, "unconverged columns", int((flag != 0).sum()),
+            "max relres %.3e" % float(relres.max()))
+        if bool(torch.all(flag == 0)):
+            break
+    assert torch.all(flag == 0), int((flag != 0).sum())
+    say("  iterations min/max", its.min(), its.max())
+    parts = pr.split(rho, R)
+    Ms = np.array([c.M for c in insts])
+    nts = np.array([c.n_tot for c in insts])
+    # dense LU for small instances; the largest one by its oracle residual
+    sample = [int(np.argmin(Ms))] + [int(b) for b in np.flatnonzero(nts < 2500)[:3]]
+    for b in sorted(set(sample)):
+        c = insts[b]
+        L = operator.efie_matrix(c.centers, c.radii, c.n_modes, c.k)
+        ref = solve.efie_solve_lu(L, rhs.planewave(c.centers, c.radii, c.n_modes, c.k, c.betas))
+        e = rel(parts[b].cpu().numpy(), ref)
+        say("  instance", b, "M", c.M, "k %.2f" % c.k, "LU rel", e)
+        assert e < 1e-10
+    b = int(np.argmax(nts))
+    c = insts[b]
+    L = operator.efie_matrix(c.centers, c.radii, c.n_modes, c.k)
+    U = rhs.planewave(c.centers, c.radii, c.n_modes, c.k, c.betas)
+    x = parts[b].cpu().numpy().reshape(R, -1)
+    res = max(np.linalg.norm(L @ x[r] + U[r]) / np.linalg.norm(U[r]) for r in range(R))
+    say("  largest instance", b, "N_tot", c.n_tot, "oracle residual", res)
+    assert res < 1e-10
+
+
+def test_differentiation_full_size(P):
+    pairs = synth.differentiation()
+    say("differentiation: configs", len(pairs), "unknowns", pairs[0][0].n_tot)
+    sample = [0, 31]
+    targets = []
+    for i, (base, tgt) in enumerate(pairs):
+        if i in sample:
+            targets.append(gradient.forward(tgt.centers, tgt.radii, tgt.n_modes, tgt.k,
+                                            base.betas, base.thetas))
+        else:   # any seeded target is a valid misfit; zeros keep the test short
+            targets.append(np.zeros((len(base.betas), len(base.thetas)), complex))
+    bases = [b for b, _ in pairs]
+    pr = P.from_clusters(bases)
+    betas = np.stack([b.betas for b in bases])
+    tg = np.concatenate([t.reshape(-1) for t in targets])
+    loss, dc, da, dk = pr.grad(betas, bases[0].thetas, tg, restart=50, tol=1e-12, maxit=20000)
+    loss, dc, da, dk = loss.cpu().numpy(), dc.cpu().numpy(), da.cpu().numpy(), dk.cpu().numpy()
+    o = np.concatenate([[0], np.cumsum([b.M for b in bases])])
+    for i in sample:
+        b = bases[i]
+        l0, dc0, da0, dk0 = gradient.misfit_grad(b.centers, b.radii, b.n_modes, b.k, b.betas,
+                                                 b.thetas, targets[i])
+        g = np.concatenate([dc[o[i]:o[i + 1]].ravel(), da[o[i]:o[i + 1]], [dk[i]]])
+        g0 = np.concatenate([dc0.ravel(), da0, [dk0]])
+        say("  config", i, "loss", loss[i], l0, "grad rel", rel(g, g0))
+        assert abs(loss[i] - l0) <= 1e-10 * l0
+        assert rel(g, g0) < 1e-10

@@ -87,7 +87,7 @@ struct DevView {
 };
 
 #define LANE_CHUNK 64
-#define LANE_NMAX 16
+#define LANE_NMAX 15
 
 // Column c = b * R + r of a packed [B][R][N_b] vector starts at
 // R * imode[b] + r * N_b.
@@ -105,7 +105,9 @@ __host__ __device__ __forceinline__ int64_t pair_index(const int64_t* idisk, con
 
 // ------------------------------------------------------------------ host side
 struct MatvecPlan {
+  bool ready = false;
   int lane = 0;                  // one-lane-per-pair kernel
+  int waves = 1;                 // waves per workgroup of the one-lane-per-pair kernel
   int Bt = 0;                   // outputs per thread of the generic kernel
   int spec_N = -1;              // >= 0: uniform-N specialised kernel
   int zs = 0, ts = 0;            // LDS row strides (z rows, symbol rows)
@@ -163,6 +165,7 @@ int apply_operator(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, cplx* p
                    int32_t* counters, const int32_t* active, hipStream_t s);
 size_t apply_scratch_bytes(mudiff_ctx* h, int R);
 int ensure_plan(mudiff_ctx* h, hipStream_t s);
+int prepare_apply(mudiff_ctx* h, int R, hipStream_t s);  // plan or MFMA tables for R
 struct PlanHost;
 void make_plan(int B, const int64_t* idisk, const int32_t* N, PlanHost& P);
 size_t plan_sched_bytes(const PlanHost& P, int M);

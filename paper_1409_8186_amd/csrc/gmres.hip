@@ -82,24 +82,24 @@ __device__ __forceinline__ bool last_chunk(const GState& s, int c, int nck, int*
 }
 
 // Arnoldi bookkeeping of column c after step j (one thread): Hessenberg column
-// h1 + h2 with subdiagonal hn, previous Givens rotations, the new rotation,
-// the residual estimate |g_{j+1}| / ||f|| and the stopping test.
-__device__ void arnoldi_step(const GState& s, int c, int j, const cplx* __restrict__ h2, double hn) {
+// hl = h1 + h2 with subdiagonal hn, previous Givens rotations, the new rotation,
+// the residual estimate |g_{j+1}| / ||f|| and the stopping test.  hl, csl, snl
+// are the column and the rotations 0..j-1 staged in LDS: the rotation chain
+// carries one value in registers, so no step waits on a global load.
+__device__ void arnoldi_step(const GState& s, int c, int j, const cplx* hl, const double* csl,
+                             const cplx* snl, double hn) {
   const int m1 = s.m + 1;
   cplx* hj = s.H + (int64_t)c * m1 * s.m + (int64_t)j * m1;  // column j
-  const cplx* a1 = s.h1 + (int64_t)c * m1;
-  const cplx* a2 = h2 + (int64_t)c * m1;
-  for (int i = 0; i <= j; ++i) hj[i] = cadd(a1[i], a2[i]);
-  double* csc = s.cs + (int64_t)c * s.m;
-  cplx* snc = s.sn + (int64_t)c * s.m;
-  cplx* gc = s.g + (int64_t)c * m1;
+  cplx cur = hl[0];
   for (int i = 0; i < j; ++i) {  // previous rotations
-    const cplx t = cadd(cscale(hj[i], csc[i]), cmul(snc[i], hj[i + 1]));
-    hj[i + 1] = csub(cscale(hj[i + 1], csc[i]), cmul(cconj(snc[i]), hj[i]));
-    hj[i] = t;
+    const cplx nxt = hl[i + 1];
+    const double ci = csl[i];
+    const cplx si = snl[i];
+    hj[i] = cadd(cscale(cur, ci), cmul(si, nxt));
+    cur = csub(cscale(nxt, ci), cmul(cconj(si), cur));
   }
   // rotation [c s; -conj(s) c] zeroing the subdiagonal hn (real, >= 0)
-  const cplx aa = hj[j];
+  const cplx aa = cur;
   double cr;
   cplx sr;
   if (hn == 0.0) {
@@ -114,9 +114,10 @@ __device__ void arnoldi_step(const GState& s, int c, int j, const cplx* __restri
     cr = na / rho;
     sr = cscale(aa, hn / (na * rho));  // (a/|a|) conj(b)/rho, b real
   }
-  csc[j] = cr;
-  snc[j] = sr;
+  s.cs[(int64_t)c * s.m + j] = cr;
+  s.sn[(int64_t)c * s.m + j] = sr;
   hj[j] = cadd(cscale(aa, cr), cscale(sr, hn));
+  cplx* gc = s.g + (int64_t)c * m1;
   const cplx gj = gc[j];
   gc[j + 1] = cmul(cscale(cconj(sr), -1.0), gj);
   gc[j] = cscale(gj, cr);
@@ -149,6 +150,7 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs(GState s, int j, const int32_
   __shared__ cplx wl[1024];
   __shared__ double sred[GS_WAVES];
   __shared__ int s_flag;
+  __shared__ double s_n1;
   int c, len;
   int64_t o;
   decode_chunk(s, blockIdx.x, &c, &len, &o);
@@ -221,22 +223,67 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs(GState s, int j, const int32_
     }
   }
   if (!last_chunk(s, c, nck, &s_flag)) return;
+  // column sums of the chunk partials, in a fixed order: wave wv takes slots
+  // i = wv, wv + GS_WAVES, ..., its lanes stride over the chunks.  In MODE 1
+  // slot j + 1 stands for the norm slot s.m.  The sums also go to LDS (wl is
+  // free now; j + 1 <= m <= 1024 entries).
   cplx* hout = (MODE == 0 ? s.h1 : hdst) + (int64_t)c * m1;
   const cplx* pbase = s.partial + (int64_t)ck_first[c] * m1;
-  for (int i = tid; i <= j; i += GS_THREADS) {
-    cplx a = cmk(0.0, 0.0);
-    for (int k = 0; k < nck; ++k) a = cadd(a, pbase[(int64_t)k * m1 + i]);
-    hout[i] = a;
+  const int ns = MODE == 1 ? j + 2 : j + 1;
+  double hsq = 0.0;
+  for (int i0 = wv; i0 < ns; i0 += GS_WAVES * GS_BATCH) {
+    cplx a[GS_BATCH];
+#pragma unroll
+    for (int u = 0; u < GS_BATCH; ++u) {
+      a[u] = cmk(0.0, 0.0);
+      const int i = i0 + u * GS_WAVES;
+      if (i < ns) {
+        const int sl = i <= j ? i : s.m;
+        for (int k = lane; k < nck; k += 64) a[u] = cadd(a[u], pbase[(int64_t)k * m1 + sl]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < GS_BATCH; ++u) {
+      a[u].x = wave_sum(a[u].x);
+      a[u].y = wave_sum(a[u].y);
+      const int i = i0 + u * GS_WAVES;
+      if (i <= j) {
+        hsq += cabs2(a[u]);
+        if (lane == 0) {
+          hout[i] = a[u];
+          wl[i] = a[u];
+        }
+      } else if (i < ns && lane == 0) {
+        s_n1 = a[u].x;
+      }
+    }
   }
   if (MODE == 0) return;
-  __syncthreads();  // hout complete (and visible to thread 0 of this block)
+  // h = h1 + h2 and, when they fit beside it in wl (j <= 409), the previous
+  // rotations into LDS; ||h2||^2 over the waves
+  const cplx* h1c = s.h1 + (int64_t)c * m1;
+  const bool fits = 2 * j + 1 + (j + 1) / 2 <= 1024;
+  const double* csl = s.cs + (int64_t)c * s.m;
+  const cplx* snl = s.sn + (int64_t)c * s.m;
+  __syncthreads();
+  for (int i = tid; i <= j; i += GS_THREADS) {
+    wl[i] = cadd(wl[i], h1c[i]);
+    if (fits && i < j) {
+      wl[j + 1 + i] = snl[i];
+      reinterpret_cast<double*>(wl + 2 * j + 1)[i] = csl[i];
+    }
+  }
+  if (fits) {
+    snl = wl + j + 1;
+    csl = reinterpret_cast<const double*>(wl + 2 * j + 1);
+  }
+  if (lane == 0) sred[wv] = hsq;
+  __syncthreads();
   if (tid != 0) return;
-  double n1 = 0.0;
-  for (int k = 0; k < nck; ++k) n1 += pbase[(int64_t)k * m1 + s.m].x;
   double h2n = 0.0;
-  for (int i = 0; i <= j; ++i) h2n += cabs2(hout[i]);
-  const double hn2 = n1 - h2n;
-  arnoldi_step(s, c, j, hdst, sqrt(hn2 > 0.0 ? hn2 : 0.0));
+  for (int k = 0; k < GS_WAVES; ++k) h2n += sred[k];
+  const double hn2 = s_n1 - h2n;
+  arnoldi_step(s, c, j, wl, csl, snl, sqrt(hn2 > 0.0 ? hn2 : 0.0));
 }
 
 // Chunked per-column sum of |src|^2 -> red[c]   (running columns only if
@@ -277,9 +324,14 @@ __global__ __launch_bounds__(GS_THREADS) void k_resid(GState s, int mode, int on
   }
   const int nck = ck_count[c];
   if (!last_chunk(s, c, nck, &s_flag)) return;
+  double t = 0.0;  // fixed order: thread stride over the chunks, then the tree
+  for (int k = tid; k < nck; k += GS_THREADS) t += s.partial[(int64_t)(ck_first[c] + k) * m1].x;
+  t = wave_sum(t);
+  if (lane == 0) sred[wv] = t;
+  __syncthreads();
   if (tid != 0) return;
-  double t = 0.0;
-  for (int k = 0; k < nck; ++k) t += s.partial[(int64_t)(ck_first[c] + k) * m1].x;
+  t = 0.0;
+  for (int k = 0; k < GS_WAVES; ++k) t += sred[k];
   s.red[c] = t;
 }
 
@@ -339,8 +391,9 @@ __global__ void k_scale_v0(GState s, int64_t nrows_total, const int32_t* __restr
 
 // End of a cycle: y = R^{-1} g (upper-triangular Hessenberg after rotations).
 // One wavefront per column: back substitution with the column-oriented
-// update g_k -= R_{k,i} y_i spread over the lanes (k = lane, lane + 64).
+// update g_k -= R_{k,i} y_i spread over the lanes, g held in LDS.
 __global__ __launch_bounds__(64) void k_cycle_solve(GState s) {
+  __shared__ cplx gl[MUDIFF_MAX_RESTART + 1];
   const int c = blockIdx.x;
   const int lane = threadIdx.x;
   const int n = s.run[c] ? s.jdone[c] : 0;
@@ -348,17 +401,16 @@ __global__ __launch_bounds__(64) void k_cycle_solve(GState s) {
   const cplx* Hc = s.H + (int64_t)c * m1 * s.m;
   const cplx* gc = s.g + (int64_t)c * m1;
   cplx* yc = s.y + (int64_t)c * s.m;
-  cplx g0 = lane < n ? gc[lane] : cmk(0.0, 0.0);
-  cplx g1 = lane + 64 < n ? gc[lane + 64] : cmk(0.0, 0.0);
+  for (int k = lane; k < n; k += 64) gl[k] = gc[k];
+  __syncthreads();
   for (int i = n - 1; i >= 0; --i) {
     const cplx* col = Hc + (int64_t)i * m1;  // column i of the triangular factor
     const cplx d = col[i];
-    const cplx gi = i < 64 ? cmk(__shfl(g0.x, i, 64), __shfl(g0.y, i, 64))
-                           : cmk(__shfl(g1.x, i - 64, 64), __shfl(g1.y, i - 64, 64));
+    const cplx gi = gl[i];
     const cplx yi = (d.x == 0.0 && d.y == 0.0) ? cmk(0.0, 0.0) : cdiv(gi, d);
     if (lane == 0) yc[i] = yi;
-    if (lane < i) g0 = csub(g0, cmul(col[lane], yi));
-    if (lane + 64 < i) g1 = csub(g1, cmul(col[lane + 64], yi));
+    for (int k = lane; k < i; k += 64) gl[k] = csub(gl[k], cmul(col[k], yi));
+    __syncthreads();
   }
 }
 
@@ -558,7 +610,7 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
   if (ws_bytes < L.total) return fail(MUDIFF_ERR_NOMEM, "gmres workspace needs " + std::to_string(L.total) + " bytes");
   if (((uintptr_t)workspace) & 255) return fail(MUDIFF_ERR_INVALID, "workspace must be 256-byte aligned");
   hipStream_t st = (hipStream_t)stream;
-  int rc = ensure_plan(h, st);
+  int rc = prepare_apply(h, R, st);  // uploads happen outside any graph capture
   if (rc != MUDIFF_OK) return rc;
   char* w = (char*)workspace;
   GmresRun G{};

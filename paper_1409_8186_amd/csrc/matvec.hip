@@ -190,39 +190,44 @@ __global__ __launch_bounds__(APPLY_THREADS) void k_apply(
 }
 
 // ------------------------------------------------------------------ one lane per pair
-// Uniform N_p = N, few right-hand sides: lane l of a wave owns the ordered pair
-// (p, q_l) and keeps all n = 2N+1 outputs in registers.  The symbols come from
-// the lane-interleaved table (H_nu(k b_pq) for nu >= 0 and e^{i alpha_pq}), so a
-// wave load of H_nu is one contiguous 1 KB line; the phase e^{i nu alpha} is
-// carried by recurrence and t_{+nu} = H_nu e^{i nu alpha},
-// t_{-nu} = (-1)^nu H_nu e^{-i nu alpha}.  The product runs diagonal by
-// diagonal (w_m += t_s z_{m+s}) with the scaled inputs z in registers.  A wave
-// covers 64 column disks of one row; lanes are summed through LDS and chunk
-// partials are combined by the last wave of the row (chunk order).
+// Uniform N_p = N (<= 15), few right-hand sides.  A workgroup owns row disk p
+// and one right-hand side; lane t of its W waves owns the ordered pairs
+// (p, q_j), j = t, t + 64 W, ..., and keeps all n = 2N+1 outputs in registers.
+// The symbols come from the lane-interleaved table (H_nu(k b_pq) for nu >= 0
+// and e^{i alpha_pq}), so a wave load of H_nu is one contiguous 1 KB line; the
+// phase e^{i nu alpha} is carried by recurrence and t_{+nu} = H_nu e^{i nu alpha},
+// t_{-nu} = (-1)^nu H_nu e^{-i nu alpha}.  The product runs diagonal by diagonal
+// (w_m += t_s z_{m+s}) with the scaled inputs z in registers.  The 2n real
+// outputs are summed over the 64 lanes by a reduce-scatter butterfly (lane l
+// ends with the sum of value l >> sh), then over the waves through LDS: the
+// whole row is summed inside the workgroup, so there are no partial sums, no
+// counters and no memory fences.
+#define ROW_MAX_WAVES 8
+
 template <int N>
-__global__ __launch_bounds__(64, (N <= 12 ? 2 : 1)) void k_apply_lane(
+__global__ __launch_bounds__(64 * ROW_MAX_WAVES) void k_apply_row(
     DevView v, int R, const cplx* __restrict__ x, cplx* __restrict__ y, int op,
-    cplx* __restrict__ part, int64_t part_total, int32_t* __restrict__ counters,
-    const int32_t* __restrict__ items, const int32_t* __restrict__ nchunk,
-    const int64_t* __restrict__ partoff, const int32_t* __restrict__ active) {
+    const int32_t* __restrict__ active) {
   constexpr int n = 2 * N + 1, S = 2 * N;
-  __shared__ cplx red[64 * n];
-  __shared__ int s_last;
-  const int it = blockIdx.x, r = blockIdx.y;
-  const int p = items[4 * it], c = items[4 * it + 1], jb = items[4 * it + 2], je = items[4 * it + 3];
+  constexpr int NV = 2 * n <= 8 ? 8 : (2 * n <= 16 ? 16 : (2 * n <= 32 ? 32 : 64));
+  constexpr int SH = NV == 8 ? 3 : (NV == 16 ? 2 : (NV == 32 ? 1 : 0));  // 6 - log2 NV
+  __shared__ double red[ROW_MAX_WAVES][64];
+  const int p = blockIdx.x, r = blockIdx.y;
   const int b = v.inst[p];
   if (active && active[b * R + r] == 0) return;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nthreads = blockDim.x, W = nthreads >> 6;
   const int64_t d0 = v.idisk[b];
+  const int Mb = (int)(v.idisk[b + 1] - d0);
   const int64_t i0 = v.imode[b];
   const int64_t cb = col_base(v.imode, b, R, r);
-  const int j = jb + lane;
+  const cplx* __restrict__ Hrow = v.lt + v.ltoff[p];
   cplx acc[n];
 #pragma unroll
   for (int m = 0; m < n; ++m) acc[m] = cmk(0.0, 0.0);
-  if (j < je) {
+  for (int j = tid; j < Mb - 1; j += nthreads) {
     const int q = (int)(d0 + j + ((d0 + j) >= p ? 1 : 0));
-    const cplx* __restrict__ Hl = v.lt + v.ltoff[p] + (int64_t)c * (LANE_CHUNK * (S + 2)) + lane;
+    const cplx* __restrict__ Hl = Hrow + (int64_t)(j >> 6) * (LANE_CHUNK * (S + 2)) + (j & 63);
     const int64_t iq = (int64_t)(q - d0) * n;  // uniform N: moff[q] = (q - d0) n
     cplx z[n];
 #pragma unroll
@@ -247,38 +252,30 @@ __global__ __launch_bounds__(64, (N <= 12 ? 2 : 1)) void k_apply_lane(
       for (int m = nu; m < n; ++m) cmac(acc[m], tm, z[m - nu]);
     }
   }
+  // reduce-scatter over the lanes: at offset o the lanes with bit o set keep
+  // the upper half of the remaining values, the others the lower half
+  double val[NV];
 #pragma unroll
-  for (int m = 0; m < n; ++m) red[lane * n + m] = acc[m];
-  __syncthreads();
-  const int nch = nchunk[p];
-  const int64_t ip = i0 + v.moff[p];
-  cplx* yc = y + cb + v.moff[p];
-  const cplx* xp = x + cb + v.moff[p];
-  const int nl = min(64, je - jb);
-  cplx w = cmk(0.0, 0.0);
-  if (lane < n)
-    for (int k = 0; k < nl; ++k) w = cadd(w, red[k * n + lane]);
-  if (nch == 1) {
-    if (lane < n) yc[lane] = finalize(v, op, ip + lane, xp[lane], w);
-    return;
+  for (int k = 0; k < NV; ++k) val[k] = k < 2 * n ? ((k & 1) ? acc[k >> 1].y : acc[k >> 1].x) : 0.0;
+#pragma unroll
+  for (int c = NV, o = 32; c > 1; c >>= 1, o >>= 1) {
+    const bool upper = (lane & o) != 0;
+#pragma unroll
+    for (int k = 0; k < c / 2; ++k) {
+      const double send = upper ? val[k] : val[c / 2 + k];
+      const double keep = upper ? val[c / 2 + k] : val[k];
+      val[k] = keep + __shfl_xor(send, o, 64);
+    }
   }
-  cplx* pr = part + (int64_t)r * part_total + partoff[p];
-  if (lane < n) pr[(int64_t)c * n + lane] = w;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // publish this chunk
+#pragma unroll
+  for (int o = (1 << SH) >> 1; o > 0; o >>= 1) val[0] += __shfl_xor(val[0], o, 64);
+  if ((lane & ((1 << SH) - 1)) == 0) red[wave][lane >> SH] = val[0];
   __syncthreads();
-  if (lane == 0) {
-    int32_t* cnt = counters + (int64_t)r * v.M_all + p;
-    int old = atomicAdd(cnt, 1);
-    s_last = (old == nch - 1);
-    if (s_last) atomicExch(cnt, 0);
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // see the other chunks
-  if (lane < n) {
-    cplx ws = cmk(0.0, 0.0);
-    for (int k = 0; k < nch; ++k) ws = cadd(ws, pr[(int64_t)k * n + lane]);
-    yc[lane] = finalize(v, op, ip + lane, xp[lane], ws);
+  if (tid < n) {
+    cplx w = cmk(0.0, 0.0);
+    for (int k = 0; k < W; ++k) w = cadd(w, cmk(red[k][2 * tid], red[k][2 * tid + 1]));
+    const int64_t ip = i0 + v.moff[p];
+    y[cb + v.moff[p] + tid] = finalize(v, op, ip + tid, x[cb + v.moff[p] + tid], w);
   }
 }
 
@@ -443,14 +440,25 @@ __global__ __launch_bounds__(256) void k_apply_mfma(DevView v, int R, const cplx
   }
 }
 
-static int launch_apply_mfma(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op,
-                             const int32_t* active, hipStream_t s) {
-  const int mt = (2 * h->Nmax + 1 + 15) / 16;
-  const int kt = (2 * h->Nmax + 1 + 3) / 4;
-  // 8-RHS sub-tiles per item (CT) and row disks per item (RP), CT * RP = 4 waves
+// R at and above which the MFMA kernel applies the operator (N_p <= 31).
+#define MFMA_MIN_R 8
+
+// 8-RHS sub-tiles per MFMA work item (CT) and row disks per item (RP), CT * RP = 4 waves
+static void mfma_tiling(int R, int* CT, int* RP) {
   const int ct = std::min(4, (R + 7) / 8);
-  const int CT = ct == 3 ? 4 : ct;
-  const int RP = 4 / CT;
+  *CT = ct == 3 ? 4 : ct;
+  *RP = 4 / *CT;
+}
+
+static bool use_mfma(const mudiff_ctx* h, int R) {
+  return R >= MFMA_MIN_R && h->Nmax <= 31 && h->mfma_enabled;
+}
+
+// Upload the MFMA work-item table for R right-hand sides (synchronises the
+// stream when the table changes, so it must not run under graph capture).
+static int ensure_mfma_groups(mudiff_ctx* h, int R, hipStream_t s) {
+  int CT, RP;
+  mfma_tiling(R, &CT, &RP);
   if (h->mfma_groups.empty() || h->mfma_rp != RP) {
     // groups of RP consecutive row disks inside one instance
     std::vector<int32_t> gr;
@@ -466,6 +474,17 @@ static int launch_apply_mfma(mudiff_ctx* h, int R, const cplx* x, cplx* y, int o
     h->mfma_groups.swap(gr);
     h->mfma_rp = RP;
   }
+  return MUDIFF_OK;
+}
+
+static int launch_apply_mfma(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op,
+                             const int32_t* active, hipStream_t s) {
+  const int mt = (2 * h->Nmax + 1 + 15) / 16;
+  const int kt = (2 * h->Nmax + 1 + 3) / 4;
+  int CT, RP;
+  mfma_tiling(R, &CT, &RP);
+  int st = ensure_mfma_groups(h, R, s);
+  if (st != MUDIFF_OK) return st;
   const int ngroups = (int)(h->mfma_groups.size() / 2);
   const int RC = 8 * CT;
   const size_t lds = ((size_t)4 * kt * RC + (size_t)RP * (4 * kt + 16 * mt - 1)) * 16;
@@ -482,15 +501,11 @@ static int launch_apply_mfma(mudiff_ctx* h, int R, const cplx* x, cplx* y, int o
   return MUDIFF_OK;
 }
 
-// R at and above which the MFMA kernel applies the operator (N_p <= 31).
-#define MFMA_MIN_R 8
-
 // ------------------------------------------------------------------ planning
 namespace {
 typedef void (*apply_fn)(DevView, int, const cplx*, cplx*, int, cplx*, int64_t, int32_t*,
                          const int32_t*, const int32_t*, const int64_t*, const int32_t*, int, int, int);
-typedef void (*lane_fn)(DevView, int, const cplx*, cplx*, int, cplx*, int64_t, int32_t*,
-                        const int32_t*, const int32_t*, const int64_t*, const int32_t*);
+typedef void (*lane_fn)(DevView, int, const cplx*, cplx*, int, const int32_t*);
 
 struct Variant {
   int bt, nspec;
@@ -516,10 +531,10 @@ struct LaneVariant {
 
 // one-lane-per-pair kernels (uniform N)
 const LaneVariant kLane[] = {
-    {2, k_apply_lane<2>},   {3, k_apply_lane<3>},   {4, k_apply_lane<4>},   {5, k_apply_lane<5>},
-    {6, k_apply_lane<6>},   {7, k_apply_lane<7>},   {8, k_apply_lane<8>},   {9, k_apply_lane<9>},
-    {10, k_apply_lane<10>}, {11, k_apply_lane<11>}, {12, k_apply_lane<12>}, {13, k_apply_lane<13>},
-    {14, k_apply_lane<14>}, {15, k_apply_lane<15>}, {16, k_apply_lane<16>},
+    {1, k_apply_row<1>},   {2, k_apply_row<2>},   {3, k_apply_row<3>},   {4, k_apply_row<4>},
+    {5, k_apply_row<5>},   {6, k_apply_row<6>},   {7, k_apply_row<7>},   {8, k_apply_row<8>},
+    {9, k_apply_row<9>},   {10, k_apply_row<10>}, {11, k_apply_row<11>}, {12, k_apply_row<12>},
+    {13, k_apply_row<13>}, {14, k_apply_row<14>}, {15, k_apply_row<15>},
 };
 
 const LaneVariant* find_lane(int n) {
@@ -533,6 +548,7 @@ const LaneVariant* find_lane(int n) {
 // layout, from the batch description alone (also used to size workspaces).
 struct PlanHost {
   int lane = 0;  // 1: one-lane-per-pair kernel (uniform N = nspec)
+  int waves = 1;
   int bt = 4, nspec = -1, zs = 0, ts = 0, ppcap = 1;
   size_t lds = 0;
   int64_t part = 0;
@@ -573,23 +589,9 @@ void make_plan(int B, const int64_t* idisk, const int32_t* N, PlanHost& P) {
   if (uniform && N[0] <= LANE_NMAX && find_lane(N[0])) {
     P.lane = 1;
     P.nspec = N[0];
-    const int np = 2 * N[0] + 1;
-    for (int b = 0; b < B; ++b) {
-      const int64_t d0 = idisk[b], Mb = idisk[b + 1] - d0;
-      const int64_t n = std::max<int64_t>(1, (Mb - 1 + LANE_CHUNK - 1) / LANE_CHUNK);
-      for (int64_t p = d0; p < d0 + Mb; ++p) {
-        P.nch[p] = (int32_t)n;
-        P.poff[p] = P.part;
-        P.part += n * np;
-        for (int64_t c = 0; c < n; ++c) {
-          int64_t jb = c * LANE_CHUNK, je = std::min<int64_t>(jb + LANE_CHUNK, Mb - 1);
-          P.items.push_back((int32_t)p);
-          P.items.push_back((int32_t)c);
-          P.items.push_back((int32_t)jb);
-          P.items.push_back((int32_t)je);
-        }
-      }
-    }
+    int64_t mmax = 1;
+    for (int b = 0; b < B; ++b) mmax = std::max<int64_t>(mmax, idisk[b + 1] - idisk[b]);
+    P.waves = (int)std::min<int64_t>(ROW_MAX_WAVES, std::max<int64_t>(1, (mmax - 1 + 63) / 64));
     return;
   }
   P.lane = 0;
@@ -636,7 +638,7 @@ size_t sched_bytes_for(int B, const int64_t* disk_off, const int32_t* n_modes) {
 }
 
 int ensure_plan(mudiff_ctx* h, hipStream_t s) {
-  if (h->plan.n_items > 0) return MUDIFF_OK;
+  if (h->plan.ready) return MUDIFF_OK;
   PlanHost H;
   make_plan(h->B, h->idisk.data(), h->N.data(), H);
   if (H.lds > 64 * 1024) return fail(MUDIFF_ERR_INVALID, "operator rows too long for LDS");
@@ -646,7 +648,8 @@ int ensure_plan(mudiff_ctx* h, hipStream_t s) {
   P.d_items = (int32_t*)h->sched_base;
   P.d_nchunk = (int32_t*)(h->sched_base + align256(H.items.size() * 4));
   P.d_partoff = (int64_t*)((char*)P.d_nchunk + align256(h->M_all * 4));
-  HIP_TRY(hipMemcpyAsync(P.d_items, H.items.data(), H.items.size() * 4, hipMemcpyHostToDevice, s));
+  if (!H.items.empty())
+    HIP_TRY(hipMemcpyAsync(P.d_items, H.items.data(), H.items.size() * 4, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(P.d_nchunk, H.nch.data(), h->M_all * 4, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(P.d_partoff, H.poff.data(), h->M_all * 8, hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));  // the host vectors are released on return
@@ -659,6 +662,8 @@ int ensure_plan(mudiff_ctx* h, hipStream_t s) {
   P.part_total = H.part;
   P.lds_bytes = H.lds;
   P.n_items = (int)(H.items.size() / 4);
+  P.waves = H.waves;
+  P.ready = true;
   return MUDIFF_OK;
 }
 
@@ -671,18 +676,22 @@ size_t apply_scratch_bytes(mudiff_ctx* h, int R) {
   return align256((size_t)R * h->plan_part * 16) + align256((size_t)R * h->M_all * 4);
 }
 
+int prepare_apply(mudiff_ctx* h, int R, hipStream_t s) {
+  if (use_mfma(h, R)) return ensure_mfma_groups(h, R, s);
+  return ensure_plan(h, s);
+}
+
 int apply_operator(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, cplx* part,
                    int32_t* counters, const int32_t* active, hipStream_t s) {
-  if (R >= MFMA_MIN_R && h->Nmax <= 31 && h->mfma_enabled)
-    return launch_apply_mfma(h, R, x, y, op, active, s);
+  if (use_mfma(h, R)) return launch_apply_mfma(h, R, x, y, op, active, s);
   int st = ensure_plan(h, s);
   if (st != MUDIFF_OK) return st;
   const MatvecPlan& P = h->plan;
   if (P.lane) {
     const LaneVariant* lv = find_lane(P.spec_N);
     if (!lv) return fail(MUDIFF_ERR_INVALID, "no operator kernel variant");
-    hipLaunchKernelGGL(lv->fn, dim3(P.n_items, R), dim3(64), 0, s, h->dv, R, x, y, op, part,
-                       P.part_total, counters, P.d_items, P.d_nchunk, P.d_partoff, active);
+    hipLaunchKernelGGL(lv->fn, dim3(h->M_all, R), dim3(64 * P.waves), 0, s, h->dv, R, x, y, op,
+                       active);
     HIP_TRY(hipGetLastError());
     return MUDIFF_OK;
   }

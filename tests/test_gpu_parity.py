@@ -193,6 +193,33 @@ def test_gmres_matches_oracle_gmres_iterations(P, tiny):
     assert abs(int(iters[0]) - it_ref) <= 3, (int(iters[0]), it_ref)
 
 
+def test_gmres_long_restart_matches_oracle(P):
+    """A dense low-frequency cluster (M = 150, k = 1, ~20% area fraction) where
+    GMRES needs ~170 inner steps in one cycle: the residual history matches the
+    oracle's step by step past 128 steps, the iteration counts agree, and the
+    solution's residual under the oracle's matrix is at the tolerance."""
+    c = synth.small_random(7, 150, 0.2, 1.0, 28.0, 0.05, 1.0, 8, R=1)
+    say("gmres restart 300: N_tot", c.n_tot)
+    pr = P.from_cluster(c)
+    rho, flag, relres, iters, resvec = pr.gmres(betas=[[0.0]], restart=300, tol=1e-10,
+                                                maxit=1000, want_resvec=True)
+    L, A = _dense(c)
+    D = operator.efie_diagonal(c.radii, c.n_modes, c.k)
+    f = -rhs.planewave(c.centers, c.radii, c.n_modes, c.k, [0.0])[0] / D
+    _, fl, _, it_ref, rv_ref = solve.gmres(lambda v: A @ v, f, 300, 1e-10, 1000)
+    it = int(iters[0])
+    say("  iterations", it, "oracle", it_ref)
+    assert int(flag[0]) == 0 and fl == 0
+    assert abs(it - it_ref) <= 3
+    rv = resvec[0].cpu().numpy()
+    n = min(it, it_ref) - 10
+    assert n > 140
+    # estimates agree while well above the rounding floor of the basis
+    assert np.max(np.abs(rv[:n] - rv_ref[:n]) / rv_ref[:n]) < 1e-4
+    x = rho.cpu().numpy().reshape(-1)
+    assert np.linalg.norm(A @ x - f) / np.linalg.norm(f) < 2e-10
+
+
 def test_gmres_batched_lockstep(P):
     """B = 3 uneven instances x R = 3 angles in one solve; every column equals LU."""
     cls = [_uneven(40 + i, M=4 + 3 * i) for i in range(3)]

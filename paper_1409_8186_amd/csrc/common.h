@@ -77,17 +77,18 @@ struct DevView {
   cplx* invSH;                // [N_all] 1 / (sqrt(a_p) H_m(k a_p))
   cplx* Ldiag;                // [N_all] (i pi a_p / 2) J_m(k a_p) H_m(k a_p)
   int32_t* udisk;             // [N_all] disk of each unknown
-  // Lane-interleaved copy for uniform N (lane_N >= 0, else unused): for every
-  // row disk p and chunk c of 64 column disks, [nu][lane] = H_nu(k b_pq),
-  // nu = 0..2N, then one row [lane] = e^{i alpha_pq}; chunk (p, c) starts at
-  // ltoff[p] + c * 64 * (2N + 2).
+  // Lane-interleaved pair records for uniform N (lane_N >= 0, else unused):
+  // for every row disk p and chunk c of 64 column disks, rows [k][lane] of
+  // H_0(k b_pq), H_1(k b_pq), e^{i alpha_pq} and (2 / (k b_pq), 0); chunk
+  // (p, c) starts at ltoff[p] + c * 64 * LANE_REC.
   int lane_N;
   cplx* lt;
   const int64_t* ltoff;       // [M_all]
 };
 
 #define LANE_CHUNK 64
-#define LANE_NMAX 15
+#define LANE_REC 4   // complex values per pair record
+#define LANE_NMAX 12
 
 // Column c = b * R + r of a packed [B][R][N_b] vector starts at
 // R * imode[b] + r * N_b.

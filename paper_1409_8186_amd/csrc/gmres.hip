@@ -2,16 +2,20 @@
 // A x = f, A = D^{-1} L, f = -D^{-1} U, one Krylov space per column (instance,
 // right-hand side); all columns share each operator application.
 //
-// Orthogonalisation is classical Gram-Schmidt applied twice (CGS2), which
-// keeps the basis orthogonal to working precision with two global reductions
-// per step (modified Gram-Schmidt needs j).  The Hessenberg column, the Givens
-// rotations and the residual estimate |g_{j+1}| / ||f|| are updated on the
-// device by the last workgroup of each column, so the host only synchronises
-// to test for the end of a cycle.
+// Orthogonalisation is classical Gram-Schmidt with selective
+// reorthogonalisation (the Daniel-Gragg-Kaufman-Stewart test): one pass
+// h = V^H w, and a second pass only when ||w - V h|| < ||w|| / sqrt(2)
+// (cancellation), which keeps the basis orthogonal to working precision.  The
+// Hessenberg column, the Givens rotations and the residual estimate
+// |g_{j+1}| / ||f|| are updated on the device, so the host only synchronises to
+// test for the end of a cycle.
 //
-// Reductions are per column: the rows of a column are cut into chunks, every
-// chunk writes its partial sums, and the last chunk to finish (atomic counter,
-// reset by itself) adds them in chunk order (deterministic).
+// Reductions are per column and free of inter-workgroup synchronisation: the
+// rows of a column are cut into chunks, every chunk writes its partial sums,
+// and the next kernel's workgroups each add all partials of their column in
+// chunk order (the same order in every workgroup, so every workgroup derives
+// bit-identical sums and decisions; the kernel boundary makes the partials
+// visible).  Chunk 0 of a column does the column's Arnoldi bookkeeping.
 #include <algorithm>
 
 #include "common.h"
@@ -30,19 +34,21 @@ struct GState {
   const cplx* f;            // [NT] preconditioned right-hand side
   cplx* x;                  // [NT] iterate (caller's rho)
   const int64_t* ck;        // [n_chunks][2]: (col | len << 32), begin
-  cplx* partial;            // [n_chunks][m+1]
-  int32_t* cnt;             // [C] chunk counters (zero between kernels)
+  const int32_t* ckf;       // [C] first chunk of each column
+  const int32_t* ckc;       // [C] chunks of each column
+  cplx* P1;                 // [n_chunks][m+1] first-pass partials (slot m: ||w||^2)
+  cplx* P2;                 // [n_chunks][m+1] second-pass partials (slot m: ||w1||^2)
   cplx* H;                  // [C][(m+1) m]
-  cplx* h1;                 // [C][m+1]
   cplx* g;                  // [C][m+1]
   double* cs;               // [C][m]
   cplx* sn;                 // [C][m]
   cplx* y;                  // [C][m]
   double* normf;            // [C]
   double* red;              // [C] scalar reduction result
-  double* inv;              // [C] 1 / ||v_{j+1}||
   int32_t* status;          // [C]
   int32_t* inner;           // [C] active in the current Arnoldi cycle
+  int32_t* reorth;          // [C] the current step takes a second pass
+  double* inv;              // [C] 1 / ||V0|| at the start of a cycle
   int32_t* run;             // [C] running at the start of the current cycle
   int32_t* jdone;           // [C] Arnoldi steps done in the current cycle
   int32_t* iters;           // [C] inner iterations so far
@@ -62,23 +68,6 @@ __device__ __forceinline__ void decode_chunk(const GState& s, int gidx, int* col
   *col = (int)(a & 0xffffffff);
   *len = (int)(a >> 32);
   *begin = s.ck[2 * gidx + 1];
-}
-
-// Last-chunk detection for column c: returns true in exactly one workgroup.
-// Release in every workgroup (write back this block's partials), acquire only
-// in the last one: an agent-scope acquire invalidates the XCD's L2, so it is
-// kept out of the workgroups that do not read other blocks' results.
-__device__ __forceinline__ bool last_chunk(const GState& s, int c, int nck, int* flag) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int old = atomicAdd(&s.cnt[c], 1);
-    *flag = (old == nck - 1);
-    if (*flag) atomicExch(&s.cnt[c], 0);
-  }
-  __syncthreads();
-  if (*flag) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  return *flag;
 }
 
 // Arnoldi bookkeeping of column c after step j (one thread): Hessenberg column
@@ -130,66 +119,51 @@ __device__ void arnoldi_step(const GState& s, int c, int j, const cplx* hl, cons
   if (!finite) s.status[c] = ST_BREAK;
   if (!finite || rel <= s.tol || hn == 0.0 || it >= s.maxit || j + 1 >= s.m) {
     s.inner[c] = 0;
-    s.inv[c] = 0.0;
     atomicSub(s.n_inner, 1);
-  } else {
-    s.inv[c] = 1.0 / hn;
   }
 }
 
-// Classical Gram-Schmidt applied twice on w = V[j+1], three passes per step:
-//   MODE 0: h1 = V^H w                                   (dots)
-//   MODE 1: w1 = w - V h1;  h2 = V^H w1;  n1 = ||w1||^2   (update + dots + norm)
-//           last chunk: ||w2||^2 = n1 - ||h2||^2 (w2 = w1 - V h2 is orthogonal
-//           to V h2), then the Arnoldi/Givens step of the column
-//   MODE 2: V[j+1] = (w1 - V h2) / ||w2||                (update + normalise)
-template <int MODE>
-__global__ __launch_bounds__(GS_THREADS) void k_gs(GState s, int j, const int32_t* __restrict__ ck_first,
-                                                   const int32_t* __restrict__ ck_count,
-                                                   cplx* __restrict__ hdst) {
-  __shared__ cplx wl[1024];
-  __shared__ double sred[GS_WAVES];
-  __shared__ int s_flag;
-  __shared__ double s_n1;
-  int c, len;
-  int64_t o;
-  decode_chunk(s, blockIdx.x, &c, &len, &o);
-  if (!s.inner[c]) return;
+// Sums, in chunk order, slots 0..ns-1 of the partials of the nck chunks that
+// start at pbase (slot ns-1 read from slot `last` when last >= 0) into out[]
+// (LDS); returns, in every thread, sum |out[i]|^2 over i < nd.  Wave w takes
+// slots w, w + GS_WAVES, ...; its lanes stride over the chunks.
+__device__ double column_sums(const cplx* __restrict__ pbase, int m1, int nck, int ns, int last,
+                              int nd, cplx* out, double* sred) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int m1 = s.m + 1;
-  cplx* w = s.V + (int64_t)(j + 1) * s.NT + o;
-  const double scale = MODE == 2 ? s.inv[c] : 1.0;
-  double nn = 0.0;
-  for (int r = tid; r < len; r += GS_THREADS) {
-    cplx v = w[r];
-    if (MODE >= 1) {
-      const cplx* hc = (MODE == 1 ? s.h1 : hdst) + (int64_t)c * m1;
-      const cplx* vr = s.V + o + r;
-      int i = 0;
-      for (; i + 3 <= j; i += 4) {  // four independent loads in flight
-        const cplx v0 = vr[(int64_t)i * s.NT], v1 = vr[(int64_t)(i + 1) * s.NT];
-        const cplx v2 = vr[(int64_t)(i + 2) * s.NT], v3 = vr[(int64_t)(i + 3) * s.NT];
-        v = csub(v, cmul(hc[i], v0));
-        v = csub(v, cmul(hc[i + 1], v1));
-        v = csub(v, cmul(hc[i + 2], v2));
-        v = csub(v, cmul(hc[i + 3], v3));
+  double sq = 0.0;
+  for (int i0 = wv; i0 < ns; i0 += GS_WAVES * GS_BATCH) {
+    cplx a[GS_BATCH];
+#pragma unroll
+    for (int u = 0; u < GS_BATCH; ++u) {
+      a[u] = cmk(0.0, 0.0);
+      const int i = i0 + u * GS_WAVES;
+      if (i < ns) {
+        const int sl = (i == ns - 1 && last >= 0) ? last : i;
+        for (int k = lane; k < nck; k += 64) a[u] = cadd(a[u], pbase[(int64_t)k * m1 + sl]);
       }
-      for (; i <= j; ++i) v = csub(v, cmul(hc[i], vr[(int64_t)i * s.NT]));
-      if (MODE == 2) {
-        w[r] = cscale(v, scale);
-        continue;
-      }
-      w[r] = v;
-      nn += cabs2(v);
     }
-    wl[r] = v;
+#pragma unroll
+    for (int u = 0; u < GS_BATCH; ++u) {
+      a[u].x = wave_sum(a[u].x);
+      a[u].y = wave_sum(a[u].y);
+      const int i = i0 + u * GS_WAVES;
+      if (i < ns && lane == 0) out[i] = a[u];
+      if (i < nd) sq += cabs2(a[u]);
+    }
   }
-  if (MODE == 2) return;
+  if (lane == 0) sred[wv] = sq;
   __syncthreads();
-  const int nck = ck_count[c];
-  cplx* part = s.partial + (int64_t)blockIdx.x * m1;
-  // wave wv takes i = wv, wv + GS_WAVES, ...; GS_BATCH of them at a time so
-  // that their loads are in flight together before the wave reductions
+  double t = 0.0;
+  for (int k = 0; k < GS_WAVES; ++k) t += sred[k];
+  __syncthreads();  // sred reusable
+  return t;
+}
+
+// Dots of the chunk's rows of wl against V_0..V_j into part[0..j] (one wave
+// per vector, GS_BATCH vectors in flight).
+__device__ void chunk_dots(const GState& s, int j, int64_t o, int len, const cplx* wl,
+                           cplx* __restrict__ part) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int i0 = wv; i0 <= j; i0 += GS_WAVES * GS_BATCH) {
     cplx a[GS_BATCH];
 #pragma unroll
@@ -212,96 +186,167 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs(GState s, int j, const int32_
         if (i0 + u * GS_WAVES <= j) part[i0 + u * GS_WAVES] = a[u];
     }
   }
-  if (MODE == 1) {  // ||w1||^2 of the chunk in the last slot (never a dot slot: j < m)
-    nn = wave_sum(nn);
-    if (lane == 0) sred[wv] = nn;
-    __syncthreads();
-    if (tid == 0) {
-      double t = 0.0;
-      for (int k = 0; k < GS_WAVES; ++k) t += sred[k];
-      part[s.m] = cmk(t, 0.0);
-    }
+}
+
+// Sum over the block of a per-thread value (every thread gets the total).
+__device__ double block_sum(double v, double* sred) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int k = 0; k < GS_WAVES; ++k) t += sred[k];
+  __syncthreads();
+  return t;
+}
+
+// w - sum_{i <= j} h_i V_i at row r of the chunk (four loads in flight).
+__device__ __forceinline__ cplx project_out(const GState& s, int j, const cplx* vr, cplx v,
+                                            const cplx* h) {
+  int i = 0;
+  for (; i + 3 <= j; i += 4) {
+    const cplx v0 = vr[(int64_t)i * s.NT], v1 = vr[(int64_t)(i + 1) * s.NT];
+    const cplx v2 = vr[(int64_t)(i + 2) * s.NT], v3 = vr[(int64_t)(i + 3) * s.NT];
+    v = csub(v, cmul(h[i], v0));
+    v = csub(v, cmul(h[i + 1], v1));
+    v = csub(v, cmul(h[i + 2], v2));
+    v = csub(v, cmul(h[i + 3], v3));
   }
-  if (!last_chunk(s, c, nck, &s_flag)) return;
-  // column sums of the chunk partials, in a fixed order: wave wv takes slots
-  // i = wv, wv + GS_WAVES, ..., its lanes stride over the chunks.  In MODE 1
-  // slot j + 1 stands for the norm slot s.m.  The sums also go to LDS (wl is
-  // free now; j + 1 <= m <= 1024 entries).
-  cplx* hout = (MODE == 0 ? s.h1 : hdst) + (int64_t)c * m1;
-  const cplx* pbase = s.partial + (int64_t)ck_first[c] * m1;
-  const int ns = MODE == 1 ? j + 2 : j + 1;
-  double hsq = 0.0;
-  for (int i0 = wv; i0 < ns; i0 += GS_WAVES * GS_BATCH) {
-    cplx a[GS_BATCH];
-#pragma unroll
-    for (int u = 0; u < GS_BATCH; ++u) {
-      a[u] = cmk(0.0, 0.0);
-      const int i = i0 + u * GS_WAVES;
-      if (i < ns) {
-        const int sl = i <= j ? i : s.m;
-        for (int k = lane; k < nck; k += 64) a[u] = cadd(a[u], pbase[(int64_t)k * m1 + sl]);
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < GS_BATCH; ++u) {
-      a[u].x = wave_sum(a[u].x);
-      a[u].y = wave_sum(a[u].y);
-      const int i = i0 + u * GS_WAVES;
-      if (i <= j) {
-        hsq += cabs2(a[u]);
-        if (lane == 0) {
-          hout[i] = a[u];
-          wl[i] = a[u];
-        }
-      } else if (i < ns && lane == 0) {
-        s_n1 = a[u].x;
-      }
-    }
-  }
-  if (MODE == 0) return;
-  // h = h1 + h2 and, when they fit beside it in wl (j <= 409), the previous
-  // rotations into LDS; ||h2||^2 over the waves
-  const cplx* h1c = s.h1 + (int64_t)c * m1;
+  for (; i <= j; ++i) v = csub(v, cmul(h[i], vr[(int64_t)i * s.NT]));
+  return v;
+}
+
+// Chunk 0 of column c: stage the previous rotations next to h (LDS) when they
+// fit, then the Arnoldi/Givens step.
+__device__ void column_step(const GState& s, int c, int j, cplx* hl, double hn) {
+  const int tid = threadIdx.x;
+  __syncthreads();  // every thread has read what it needs beyond hl[j]
   const bool fits = 2 * j + 1 + (j + 1) / 2 <= 1024;
   const double* csl = s.cs + (int64_t)c * s.m;
   const cplx* snl = s.sn + (int64_t)c * s.m;
-  __syncthreads();
-  for (int i = tid; i <= j; i += GS_THREADS) {
-    wl[i] = cadd(wl[i], h1c[i]);
-    if (fits && i < j) {
-      wl[j + 1 + i] = snl[i];
-      reinterpret_cast<double*>(wl + 2 * j + 1)[i] = csl[i];
-    }
-  }
   if (fits) {
-    snl = wl + j + 1;
-    csl = reinterpret_cast<const double*>(wl + 2 * j + 1);
+    for (int i = tid; i < j; i += GS_THREADS) {
+      hl[j + 1 + i] = snl[i];
+      reinterpret_cast<double*>(hl + 2 * j + 1)[i] = csl[i];
+    }
+    __syncthreads();
+    snl = hl + j + 1;
+    csl = reinterpret_cast<const double*>(hl + 2 * j + 1);
   }
-  if (lane == 0) sred[wv] = hsq;
-  __syncthreads();
-  if (tid != 0) return;
-  double h2n = 0.0;
-  for (int k = 0; k < GS_WAVES; ++k) h2n += sred[k];
-  const double hn2 = s_n1 - h2n;
-  arnoldi_step(s, c, j, wl, csl, snl, sqrt(hn2 > 0.0 ? hn2 : 0.0));
+  if (tid == 0) arnoldi_step(s, c, j, hl, csl, snl, hn);
 }
 
-// Chunked per-column sum of |src|^2 -> red[c]   (running columns only if
-// `only_run`).  When `sub`: src = f - src first; when `copy`: src = f.
+// Pass 1 of step j on w = V[j+1]: partial h = V^H w and ||w||^2 into P1.
+__global__ __launch_bounds__(GS_THREADS) void k_gs_dots(GState s, int j) {
+  __shared__ cplx wl[1024];
+  __shared__ double sred[GS_WAVES];
+  int c, len;
+  int64_t o;
+  decode_chunk(s, blockIdx.x, &c, &len, &o);
+  if (!s.inner[c]) return;
+  const int m1 = s.m + 1;
+  const cplx* w = s.V + (int64_t)(j + 1) * s.NT + o;
+  double nn = 0.0;
+  for (int r = threadIdx.x; r < len; r += GS_THREADS) {
+    const cplx v = w[r];
+    wl[r] = v;
+    nn += cabs2(v);
+  }
+  nn = block_sum(nn, sred);  // (its barrier also publishes wl)
+  cplx* part = s.P1 + (int64_t)blockIdx.x * m1;
+  chunk_dots(s, j, o, len, wl, part);
+  if (threadIdx.x == 0) part[s.m] = cmk(nn, 0.0);
+}
+
+// Pass 2: every workgroup of column c adds the P1 partials (h, ||w||^2) and
+// takes the same decision.  Without cancellation, V[j+1] = (w - V h) / h_{j+1,j}
+// with h_{j+1,j}^2 = ||w||^2 - ||h||^2, and chunk 0 does the Arnoldi step.
+// Otherwise w1 = w - V h is stored in place and its partials V^H w1, ||w1||^2
+// go to P2 for the second pass.
+__global__ __launch_bounds__(GS_THREADS) void k_gs_update(GState s, int j) {
+  __shared__ cplx hl[MUDIFF_MAX_RESTART + 1];
+  __shared__ cplx wl[1024];
+  __shared__ double sred[GS_WAVES];
+  int c, len;
+  int64_t o;
+  decode_chunk(s, blockIdx.x, &c, &len, &o);
+  if (!s.inner[c]) return;
+  const int m1 = s.m + 1;
+  const int nck = s.ckc[c];
+  const double hsq = column_sums(s.P1 + (int64_t)s.ckf[c] * m1, m1, nck, j + 2, s.m, j + 1, hl, sred);
+  const double nw = hl[j + 1].x;
+  const double hn2 = nw - hsq;
+  const bool second = !(hn2 > 0.5 * nw);  // ||w - V h||^2 <= ||w||^2 / 2 (or not finite)
+  const bool first_chunk = blockIdx.x == s.ckf[c];
+  cplx* w = s.V + (int64_t)(j + 1) * s.NT + o;
+  const cplx* vr0 = s.V + o;
+  if (!second) {
+    const double hn = sqrt(hn2);
+    const double inv = 1.0 / hn;
+    for (int r = threadIdx.x; r < len; r += GS_THREADS)
+      w[r] = cscale(project_out(s, j, vr0 + r, w[r], hl), inv);
+    if (first_chunk) {
+      if (threadIdx.x == 0) s.reorth[c] = 0;
+      column_step(s, c, j, hl, hn);
+    }
+    return;
+  }
+  double nn = 0.0;
+  for (int r = threadIdx.x; r < len; r += GS_THREADS) {
+    const cplx v = project_out(s, j, vr0 + r, w[r], hl);
+    w[r] = v;
+    wl[r] = v;
+    nn += cabs2(v);
+  }
+  nn = block_sum(nn, sred);
+  cplx* part = s.P2 + (int64_t)blockIdx.x * m1;
+  chunk_dots(s, j, o, len, wl, part);
+  if (threadIdx.x == 0) {
+    part[s.m] = cmk(nn, 0.0);
+    if (first_chunk) s.reorth[c] = 1;
+  }
+}
+
+// Second pass (columns flagged by k_gs_update): h2 = sum of the P2 partials,
+// V[j+1] = (w1 - V h2) / h_{j+1,j}, h_{j+1,j}^2 = ||w1||^2 - ||h2||^2; the
+// Hessenberg column is h + h2 (h re-added from P1).
+__global__ __launch_bounds__(GS_THREADS) void k_gs_reorth(GState s, int j) {
+  __shared__ cplx hl[MUDIFF_MAX_RESTART + 1];
+  __shared__ cplx h2l[MUDIFF_MAX_RESTART + 1];
+  __shared__ double sred[GS_WAVES];
+  int c, len;
+  int64_t o;
+  decode_chunk(s, blockIdx.x, &c, &len, &o);
+  if (!s.inner[c] || !s.reorth[c]) return;
+  const int m1 = s.m + 1;
+  const int nck = s.ckc[c];
+  const double h2sq =
+      column_sums(s.P2 + (int64_t)s.ckf[c] * m1, m1, nck, j + 2, s.m, j + 1, h2l, sred);
+  const double hn2 = h2l[j + 1].x - h2sq;
+  const double hn = sqrt(hn2 > 0.0 ? hn2 : 0.0);
+  const double inv = 1.0 / hn;  // unused when hn == 0: the column stops
+  cplx* w = s.V + (int64_t)(j + 1) * s.NT + o;
+  const cplx* vr0 = s.V + o;
+  for (int r = threadIdx.x; r < len; r += GS_THREADS)
+    w[r] = cscale(project_out(s, j, vr0 + r, w[r], h2l), inv);
+  if (blockIdx.x != s.ckf[c]) return;
+  (void)column_sums(s.P1 + (int64_t)s.ckf[c] * m1, m1, nck, j + 1, -1, 0, hl, sred);
+  for (int i = threadIdx.x; i <= j; i += GS_THREADS) hl[i] = cadd(hl[i], h2l[i]);
+  __syncthreads();
+  column_step(s, c, j, hl, hn);
+}
+
+// Chunked per-column sum of |src|^2: partials into P1 slot 0 (running columns
+// only if `only_run`), added by k_col_sum.  When mode 2: src = f - src first
+// (stored back); mode 1: src = f; mode 0: src = vec_in.
 __global__ __launch_bounds__(GS_THREADS) void k_resid(GState s, int mode, int only_run,
-                                                      const int32_t* __restrict__ ck_first,
-                                                      const int32_t* __restrict__ ck_count,
                                                       const cplx* __restrict__ vec_in) {
   __shared__ double sred[GS_WAVES];
-  __shared__ int s_flag;
   int c, len;
   int64_t o;
   decode_chunk(s, blockIdx.x, &c, &len, &o);
   if (only_run && !s.run[c]) return;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int m1 = s.m + 1;
   double a = 0.0;
-  for (int r = tid; r < len; r += GS_THREADS) {
+  for (int r = threadIdx.x; r < len; r += GS_THREADS) {
     cplx v;
     if (mode == 0) {
       v = vec_in[o + r];                  // norm of a given vector
@@ -314,25 +359,20 @@ __global__ __launch_bounds__(GS_THREADS) void k_resid(GState s, int mode, int on
     }
     a += cabs2(v);
   }
-  a = wave_sum(a);
-  if (lane == 0) sred[wv] = a;
-  __syncthreads();
-  if (tid == 0) {
-    double t = 0.0;
-    for (int k = 0; k < GS_WAVES; ++k) t += sred[k];
-    s.partial[(int64_t)blockIdx.x * m1] = cmk(t, 0.0);
-  }
-  const int nck = ck_count[c];
-  if (!last_chunk(s, c, nck, &s_flag)) return;
-  double t = 0.0;  // fixed order: thread stride over the chunks, then the tree
-  for (int k = tid; k < nck; k += GS_THREADS) t += s.partial[(int64_t)(ck_first[c] + k) * m1].x;
+  a = block_sum(a, sred);
+  if (threadIdx.x == 0) s.P1[(int64_t)blockIdx.x * (s.m + 1)] = cmk(a, 0.0);
+}
+
+// red[c] = sum of the k_resid partials of column c (one wave per column,
+// chunk order fixed).
+__global__ __launch_bounds__(64) void k_col_sum(GState s, int only_run) {
+  const int c = blockIdx.x, lane = threadIdx.x;
+  if (only_run && !s.run[c]) return;
+  const int m1 = s.m + 1;
+  double t = 0.0;
+  for (int k = lane; k < s.ckc[c]; k += 64) t += s.P1[(int64_t)(s.ckf[c] + k) * m1].x;
   t = wave_sum(t);
-  if (lane == 0) sred[wv] = t;
-  __syncthreads();
-  if (tid != 0) return;
-  t = 0.0;
-  for (int k = 0; k < GS_WAVES; ++k) t += sred[k];
-  s.red[c] = t;
+  if (lane == 0) s.red[c] = t;
 }
 
 // Column setup before the first cycle: ||f||, status, iteration count.
@@ -460,18 +500,26 @@ __global__ void k_precond_rhs(DevView v, int R, const cplx* __restrict__ src, cp
 }
 
 // ------------------------------------------------------------------ host driver
-// Rows per reduction chunk: about 4096 chunks over all columns (enough
-// workgroups to fill the chip, few partial sums to combine), 64..1024 rows
-// each (1024 = the LDS row buffer of k_gs).
-static int64_t chunk_rows(int64_t NT) {
-  int64_t ch = ((NT + 4095) / 4096 + 63) / 64 * 64;
-  return std::min<int64_t>(std::max<int64_t>(ch, 64), 1024);
+// Rows per reduction chunk: enough chunks over all columns to fill the chip
+// (about 2048), few enough per column (<= 128 where possible) that every
+// workgroup can add all partials of its column, and 128..1024 rows each
+// (1024 = the LDS row buffer of the Gram-Schmidt kernels).
+static int64_t chunk_rows(int64_t NT, int64_t ncol_max) {
+  auto up64 = [](int64_t v) { return (v + 63) / 64 * 64; };
+  int64_t ch = std::max(up64((NT + 2047) / 2048), up64((ncol_max + 127) / 128));
+  return std::min<int64_t>(std::max<int64_t>(ch, 128), 1024);
+}
+
+static int64_t max_col_rows(const mudiff_ctx* h) {
+  int64_t mx = 1;
+  for (int b = 0; b < h->B; ++b) mx = std::max(mx, h->imode[b + 1] - h->imode[b]);
+  return mx;
 }
 
 namespace {
 struct GLayout {
-  size_t V, f, apply, ck, ckf, ckc, rowcol, partial, cnt, H, h1, h2, g, cs, sn, y, normf, red, inv,
-      status, inner, run, jdone, iters, ninner, total;
+  size_t V, f, apply, ck, ckf, ckc, rowcol, P1, P2, H, g, cs, sn, y, normf, red, inv, status,
+      inner, reorth, run, jdone, iters, ninner, total;
   int64_t n_chunks, NT;
 };
 
@@ -480,11 +528,10 @@ GLayout glayout(mudiff_ctx* h, int R, int m) {
   const int64_t C = (int64_t)h->B * R;
   const int64_t NT = (int64_t)R * h->N_all;
   L.NT = NT;
-  // chunks: at most 1024 rows, at most 64 per column
   int64_t nck = 0;
+  const int64_t ch = chunk_rows(NT, max_col_rows(h));
   for (int b = 0; b < h->B; ++b) {
     const int64_t Nb = h->imode[b + 1] - h->imode[b];
-    const int64_t ch = chunk_rows(NT);
     nck += (int64_t)R * ((Nb + ch - 1) / ch);
   }
   L.n_chunks = nck;
@@ -501,11 +548,9 @@ GLayout glayout(mudiff_ctx* h, int R, int m) {
   L.ckf = take(C * 4);
   L.ckc = take(C * 4);
   L.rowcol = take(NT * 4);
-  L.partial = take(nck * (m + 1) * 16);
-  L.cnt = take(C * 4);
+  L.P1 = take(nck * (m + 1) * 16);
+  L.P2 = take(nck * (m + 1) * 16);
   L.H = take(C * (m + 1) * m * 16);
-  L.h1 = take(C * (m + 1) * 16);
-  L.h2 = take(C * (m + 1) * 16);
   L.g = take(C * (m + 1) * 16);
   L.cs = take(C * m * 8);
   L.sn = take(C * m * 16);
@@ -515,6 +560,7 @@ GLayout glayout(mudiff_ctx* h, int R, int m) {
   L.inv = take(C * 8);
   L.status = take(C * 4);
   L.inner = take(C * 4);
+  L.reorth = take(C * 4);
   L.run = take(C * 4);
   L.jdone = take(C * 4);
   L.iters = take(C * 4);
@@ -555,7 +601,6 @@ struct GmresRun {
   int32_t* d_rowcol;
   cplx* apply_part;
   int32_t* apply_cnt;
-  cplx* h2;
   hipStream_t st;
 };
 
@@ -571,9 +616,9 @@ static int enqueue_cycle(GmresRun& G, int check_every, bool host_checks) {
                             MUDIFF_OP_A, G.apply_part, G.apply_cnt, s.inner, G.st);
     if (rc != MUDIFF_OK) return rc;
     const unsigned nb = (unsigned)G.L.n_chunks;
-    hipLaunchKernelGGL(k_gs<0>, dim3(nb), dim3(GS_THREADS), 0, G.st, s, j, G.d_ckf, G.d_ckc, G.h2);
-    hipLaunchKernelGGL(k_gs<1>, dim3(nb), dim3(GS_THREADS), 0, G.st, s, j, G.d_ckf, G.d_ckc, G.h2);
-    hipLaunchKernelGGL(k_gs<2>, dim3(nb), dim3(GS_THREADS), 0, G.st, s, j, G.d_ckf, G.d_ckc, G.h2);
+    hipLaunchKernelGGL(k_gs_dots, dim3(nb), dim3(GS_THREADS), 0, G.st, s, j);
+    hipLaunchKernelGGL(k_gs_update, dim3(nb), dim3(GS_THREADS), 0, G.st, s, j);
+    hipLaunchKernelGGL(k_gs_reorth, dim3(nb), dim3(GS_THREADS), 0, G.st, s, j);
     HIP_TRY(hipGetLastError());
     if (host_checks && check_every > 0 && (j + 1) % check_every == 0 && j + 1 < s.m) {
       int32_t n_in = 0;
@@ -588,7 +633,8 @@ static int enqueue_cycle(GmresRun& G, int check_every, bool host_checks) {
   int rc = apply_operator(G.h, s.R, s.x, s.V, MUDIFF_OP_A, G.apply_part, G.apply_cnt, s.run, G.st);
   if (rc != MUDIFF_OK) return rc;
   hipLaunchKernelGGL(k_resid, dim3((unsigned)G.L.n_chunks), dim3(GS_THREADS), 0, G.st, s, 2, 1,
-                     G.d_ckf, G.d_ckc, (const cplx*)nullptr);
+                     (const cplx*)nullptr);
+  hipLaunchKernelGGL(k_col_sum, dim3(s.C), dim3(64), 0, G.st, s, 1);
   // the true residual decides each column's next cycle
   hipLaunchKernelGGL(k_cycle_begin, dim3(cb), dim3(64), 0, G.st, s);
   HIP_TRY(hipGetLastError());
@@ -628,10 +674,9 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
   s.f = (cplx*)(w + L.f);
   s.x = (cplx*)rho;
   s.ck = (int64_t*)(w + L.ck);
-  s.partial = (cplx*)(w + L.partial);
-  s.cnt = (int32_t*)(w + L.cnt);
+  s.P1 = (cplx*)(w + L.P1);
+  s.P2 = (cplx*)(w + L.P2);
   s.H = (cplx*)(w + L.H);
-  s.h1 = (cplx*)(w + L.h1);
   s.g = (cplx*)(w + L.g);
   s.cs = (double*)(w + L.cs);
   s.sn = (cplx*)(w + L.sn);
@@ -641,6 +686,7 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
   s.inv = (double*)(w + L.inv);
   s.status = (int32_t*)(w + L.status);
   s.inner = (int32_t*)(w + L.inner);
+  s.reorth = (int32_t*)(w + L.reorth);
   s.run = (int32_t*)(w + L.run);
   s.jdone = (int32_t*)(w + L.jdone);
   s.iters = (int32_t*)(w + L.iters);
@@ -651,16 +697,17 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
   G.d_rowcol = (int32_t*)(w + L.rowcol);
   G.apply_part = (cplx*)(w + L.apply);
   G.apply_cnt = (int32_t*)(w + L.apply + apply_scratch_bytes(h, R) - align256((size_t)R * h->M_all * 4));
-  G.h2 = (cplx*)(w + L.h2);
+  s.ckf = G.d_ckf;
+  s.ckc = G.d_ckc;
 
   // chunk table (host) -> device
   std::vector<int64_t> ck;
   std::vector<int32_t> ckf(s.C), ckc(s.C);
   ck.reserve(2 * L.n_chunks);
   int64_t idx = 0;
+  const int64_t ch = chunk_rows(L.NT, max_col_rows(h));
   for (int b = 0; b < h->B; ++b) {
     const int64_t Nb = h->imode[b + 1] - h->imode[b];
-    const int64_t ch = chunk_rows(L.NT);
     for (int r = 0; r < R; ++r) {
       const int c = b * R + r;
       const int64_t base = col_base(h->imode.data(), b, R, r);
@@ -682,7 +729,6 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
   hipLaunchKernelGGL(k_rowcol, dim3(eb), dim3(256), 0, st, G.d_rowcol, s.NT, R, h->B, h->dv.imode);
   HIP_TRY(hipGetLastError());
   // counters start at zero
-  if ((rc = launch_fill_zero(s.cnt, s.C * 4, st)) != MUDIFF_OK) return rc;
   if ((rc = launch_fill_zero(G.apply_cnt, (size_t)R * h->M_all * 4, st)) != MUDIFF_OK) return rc;
   if ((rc = launch_fill_zero(s.n_inner, 4, st)) != MUDIFF_OK) return rc;
   // right-hand side f
@@ -697,8 +743,8 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
     if ((rc = launch_fill_zero(resvec, (size_t)s.C * (maxit + 1) * 8, st)) != MUDIFF_OK) return rc;
   }
   // ||f||
-  hipLaunchKernelGGL(k_resid, dim3((unsigned)L.n_chunks), dim3(GS_THREADS), 0, st, s, 0, 0,
-                     G.d_ckf, G.d_ckc, s.f);
+  hipLaunchKernelGGL(k_resid, dim3((unsigned)L.n_chunks), dim3(GS_THREADS), 0, st, s, 0, 0, s.f);
+  hipLaunchKernelGGL(k_col_sum, dim3(s.C), dim3(64), 0, st, s, 0);
   hipLaunchKernelGGL(k_setup, dim3(cb), dim3(64), 0, st, s);
   HIP_TRY(hipGetLastError());
   // initial residual V0 = f - A x0 (or f with x0 = 0)
@@ -706,12 +752,13 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
     rc = apply_operator(h, R, s.x, s.V, MUDIFF_OP_A, G.apply_part, G.apply_cnt, s.run, st);
     if (rc != MUDIFF_OK) return rc;
     hipLaunchKernelGGL(k_resid, dim3((unsigned)L.n_chunks), dim3(GS_THREADS), 0, st, s, 2, 1,
-                       G.d_ckf, G.d_ckc, (const cplx*)nullptr);
+                       (const cplx*)nullptr);
   } else {
     hipLaunchKernelGGL(k_zero_c, dim3(eb), dim3(256), 0, st, s.x, s.NT);
     hipLaunchKernelGGL(k_resid, dim3((unsigned)L.n_chunks), dim3(GS_THREADS), 0, st, s, 1, 1,
-                       G.d_ckf, G.d_ckc, (const cplx*)nullptr);
+                       (const cplx*)nullptr);
   }
+  hipLaunchKernelGGL(k_col_sum, dim3(s.C), dim3(64), 0, st, s, 1);
   HIP_TRY(hipGetLastError());
 
   hipLaunchKernelGGL(k_cycle_begin, dim3(cb), dim3(64), 0, st, s);

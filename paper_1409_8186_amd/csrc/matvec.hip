@@ -190,59 +190,66 @@ __global__ __launch_bounds__(APPLY_THREADS) void k_apply(
 }
 
 // ------------------------------------------------------------------ one lane per pair
-// Uniform N_p = N (<= 15), few right-hand sides.  A workgroup owns row disk p
-// and one right-hand side; lane t of its W waves owns the ordered pairs
-// (p, q_j), j = t, t + 64 W, ..., and keeps all n = 2N+1 outputs in registers.
-// The symbols come from the lane-interleaved table (H_nu(k b_pq) for nu >= 0
-// and e^{i alpha_pq}), so a wave load of H_nu is one contiguous 1 KB line; the
-// phase e^{i nu alpha} is carried by recurrence and t_{+nu} = H_nu e^{i nu alpha},
-// t_{-nu} = (-1)^nu H_nu e^{-i nu alpha}.  The product runs diagonal by diagonal
-// (w_m += t_s z_{m+s}) with the scaled inputs z in registers.  The 2n real
-// outputs are summed over the 64 lanes by a reduce-scatter butterfly (lane l
-// ends with the sum of value l >> sh), then over the waves through LDS: the
-// whole row is summed inside the workgroup, so there are no partial sums, no
-// counters and no memory fences.
-#define ROW_MAX_WAVES 8
-
+// Uniform N_p = N (<= 12), few right-hand sides.  A work item is one wave: row
+// disk p, one right-hand side and a chunk of up to 64 column disks q, one
+// lane per ordered pair (p, q), with all n = 2N+1 outputs of the pair in
+// registers.  Each pair is read as one lane-interleaved record (H_0, H_1,
+// e^{i alpha_pq}, 2 / (k b_pq)): the orders H_nu(k b_pq), nu <= 2N, follow by
+// the upward recurrence H_{nu+1} = (2 nu / x) H_nu - H_{nu-1}, whose rounding
+// error stays at the level of eps |H_nu| (the growing Y part dominates |H_nu|
+// wherever the J part decays), and the phase e^{i nu alpha} by recurrence;
+// t_{+nu} = H_nu e^{i nu alpha}, t_{-nu} = (-1)^nu H_nu e^{-i nu alpha}.  The
+// product runs diagonal by diagonal (w_m += t_s z_{m+s}) with the scaled
+// inputs z in registers.  The 2n real outputs are summed over the lanes by a
+// reduce-scatter butterfly (lane l ends with the sum of value l >> sh) and
+// stored as the chunk's partial sum; k_apply_finish adds the chunks of each
+// row in order.  Single-wave items keep every SIMD busy to the end of the
+// launch (rows of unequal cost or rows fewer than the compute units would
+// leave whole workgroups idle), and the two launches need no counters or
+// memory fences.
 template <int N>
-__global__ __launch_bounds__(64 * ROW_MAX_WAVES) void k_apply_row(
-    DevView v, int R, const cplx* __restrict__ x, cplx* __restrict__ y, int op,
+__global__ __launch_bounds__(64) void k_apply_lane(
+    DevView v, int R, const cplx* __restrict__ x, cplx* __restrict__ part, int64_t part_total,
+    const int32_t* __restrict__ items, const int64_t* __restrict__ partoff,
     const int32_t* __restrict__ active) {
   constexpr int n = 2 * N + 1, S = 2 * N;
   constexpr int NV = 2 * n <= 8 ? 8 : (2 * n <= 16 ? 16 : (2 * n <= 32 ? 32 : 64));
   constexpr int SH = NV == 8 ? 3 : (NV == 16 ? 2 : (NV == 32 ? 1 : 0));  // 6 - log2 NV
-  __shared__ double red[ROW_MAX_WAVES][64];
-  const int p = blockIdx.x, r = blockIdx.y;
+  const int it = blockIdx.x, r = blockIdx.y;
+  const int p = items[4 * it], c = items[4 * it + 1], jb = items[4 * it + 2], je = items[4 * it + 3];
   const int b = v.inst[p];
   if (active && active[b * R + r] == 0) return;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int nthreads = blockDim.x, W = nthreads >> 6;
+  const int lane = threadIdx.x;
   const int64_t d0 = v.idisk[b];
-  const int Mb = (int)(v.idisk[b + 1] - d0);
   const int64_t i0 = v.imode[b];
   const int64_t cb = col_base(v.imode, b, R, r);
-  const cplx* __restrict__ Hrow = v.lt + v.ltoff[p];
+  const int j = jb + lane;
   cplx acc[n];
 #pragma unroll
   for (int m = 0; m < n; ++m) acc[m] = cmk(0.0, 0.0);
-  for (int j = tid; j < Mb - 1; j += nthreads) {
+  if (j < je) {
     const int q = (int)(d0 + j + ((d0 + j) >= p ? 1 : 0));
-    const cplx* __restrict__ Hl = Hrow + (int64_t)(j >> 6) * (LANE_CHUNK * (S + 2)) + (j & 63);
+    const cplx* __restrict__ rec = v.lt + v.ltoff[p] + (int64_t)c * (LANE_CHUNK * LANE_REC) + lane;
     const int64_t iq = (int64_t)(q - d0) * n;  // uniform N: moff[q] = (q - d0) n
+    const cplx h0 = rec[0];
+    cplx H = rec[LANE_CHUNK];
+    const cplx E = rec[2 * LANE_CHUNK];
+    const double r2 = rec[3 * LANE_CHUNK].x;
     cplx z[n];
 #pragma unroll
     for (int k = 0; k < n; ++k) z[k] = cscale(x[cb + iq + k], v.sJ[i0 + iq + k]);
-    const cplx E = Hl[(S + 1) * LANE_CHUNK];
-    cplx P = cmk(1.0, 0.0);
-    {
-      const cplx h0 = Hl[0];
 #pragma unroll
-      for (int m = 0; m < n; ++m) cmac(acc[m], h0, z[m]);
-    }
+    for (int m = 0; m < n; ++m) cmac(acc[m], h0, z[m]);
+    cplx Hm = h0;
+    cplx P = E;
 #pragma unroll
     for (int nu = 1; nu <= S; ++nu) {
-      const cplx H = Hl[nu * LANE_CHUNK];
-      P = cmul(P, E);
+      if (nu > 1) {
+        const cplx Hn = csub(cscale(H, (nu - 1) * r2), Hm);  // H_nu from H_{nu-1}, H_{nu-2}
+        Hm = H;
+        H = Hn;
+        P = cmul(P, E);
+      }
       const cplx tp = cmul(H, P);
       cplx tm = cmul(H, cconj(P));
       if (nu & 1) tm = cmk(-tm.x, -tm.y);
@@ -258,25 +265,54 @@ __global__ __launch_bounds__(64 * ROW_MAX_WAVES) void k_apply_row(
 #pragma unroll
   for (int k = 0; k < NV; ++k) val[k] = k < 2 * n ? ((k & 1) ? acc[k >> 1].y : acc[k >> 1].x) : 0.0;
 #pragma unroll
-  for (int c = NV, o = 32; c > 1; c >>= 1, o >>= 1) {
+  for (int cnt = NV, o = 32; cnt > 1; cnt >>= 1, o >>= 1) {
     const bool upper = (lane & o) != 0;
 #pragma unroll
-    for (int k = 0; k < c / 2; ++k) {
-      const double send = upper ? val[k] : val[c / 2 + k];
-      const double keep = upper ? val[c / 2 + k] : val[k];
+    for (int k = 0; k < cnt / 2; ++k) {
+      const double send = upper ? val[k] : val[cnt / 2 + k];
+      const double keep = upper ? val[cnt / 2 + k] : val[k];
       val[k] = keep + __shfl_xor(send, o, 64);
     }
   }
 #pragma unroll
   for (int o = (1 << SH) >> 1; o > 0; o >>= 1) val[0] += __shfl_xor(val[0], o, 64);
-  if ((lane & ((1 << SH) - 1)) == 0) red[wave][lane >> SH] = val[0];
-  __syncthreads();
-  if (tid < n) {
-    cplx w = cmk(0.0, 0.0);
-    for (int k = 0; k < W; ++k) w = cadd(w, cmk(red[k][2 * tid], red[k][2 * tid + 1]));
-    const int64_t ip = i0 + v.moff[p];
-    y[cb + v.moff[p] + tid] = finalize(v, op, ip + tid, x[cb + v.moff[p] + tid], w);
+  const int vi = lane >> SH;
+  if ((lane & ((1 << SH) - 1)) == 0 && vi < 2 * n) {
+    double* pr = reinterpret_cast<double*>(part + (int64_t)r * part_total + partoff[p] + (int64_t)c * n);
+    pr[vi] = val[0];
   }
+}
+
+// y = finalize(sum over the chunks of row p of the partial sums), one thread
+// per output row, chunks added in order.
+__global__ void k_apply_finish(DevView v, int R, const cplx* __restrict__ x, cplx* __restrict__ y,
+                               int op, const cplx* __restrict__ part, int64_t part_total,
+                               const int32_t* __restrict__ nchunk,
+                               const int64_t* __restrict__ partoff,
+                               const int32_t* __restrict__ active) {
+  const int64_t total = (int64_t)R * v.N_all;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  // column (b, r) and unknown i of the packed row g
+  int lo = 0, hi = v.B;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if ((int64_t)R * v.imode[mid] <= g) lo = mid; else hi = mid;
+  }
+  const int b = lo;
+  const int64_t Nb = v.imode[b + 1] - v.imode[b];
+  const int64_t rem = g - (int64_t)R * v.imode[b];
+  const int r = (int)(rem / Nb);
+  if (active && active[b * R + r] == 0) return;
+  const int64_t i = v.imode[b] + (rem - (int64_t)r * Nb);
+  const int p = v.udisk[i];
+  const int64_t m = i - v.imode[b] - v.moff[p];
+  const int np = 2 * v.N[p] + 1;
+  const cplx* pr = part + (int64_t)r * part_total + partoff[p] + m;
+  cplx w = cmk(0.0, 0.0);
+  const int nch = nchunk[p];
+  for (int k = 0; k < nch; ++k) w = cadd(w, pr[(int64_t)k * np]);
+  y[g] = finalize(v, op, i, x[g], w);
 }
 
 // ------------------------------------------------------------------ multi-RHS (MFMA)
@@ -505,7 +541,8 @@ static int launch_apply_mfma(mudiff_ctx* h, int R, const cplx* x, cplx* y, int o
 namespace {
 typedef void (*apply_fn)(DevView, int, const cplx*, cplx*, int, cplx*, int64_t, int32_t*,
                          const int32_t*, const int32_t*, const int64_t*, const int32_t*, int, int, int);
-typedef void (*lane_fn)(DevView, int, const cplx*, cplx*, int, const int32_t*);
+typedef void (*lane_fn)(DevView, int, const cplx*, cplx*, int64_t, const int32_t*, const int64_t*,
+                        const int32_t*);
 
 struct Variant {
   int bt, nspec;
@@ -531,10 +568,9 @@ struct LaneVariant {
 
 // one-lane-per-pair kernels (uniform N)
 const LaneVariant kLane[] = {
-    {1, k_apply_row<1>},   {2, k_apply_row<2>},   {3, k_apply_row<3>},   {4, k_apply_row<4>},
-    {5, k_apply_row<5>},   {6, k_apply_row<6>},   {7, k_apply_row<7>},   {8, k_apply_row<8>},
-    {9, k_apply_row<9>},   {10, k_apply_row<10>}, {11, k_apply_row<11>}, {12, k_apply_row<12>},
-    {13, k_apply_row<13>}, {14, k_apply_row<14>}, {15, k_apply_row<15>},
+    {1, k_apply_lane<1>},   {2, k_apply_lane<2>},   {3, k_apply_lane<3>},   {4, k_apply_lane<4>},
+    {5, k_apply_lane<5>},   {6, k_apply_lane<6>},   {7, k_apply_lane<7>},   {8, k_apply_lane<8>},
+    {9, k_apply_lane<9>},   {10, k_apply_lane<10>}, {11, k_apply_lane<11>}, {12, k_apply_lane<12>},
 };
 
 const LaneVariant* find_lane(int n) {
@@ -589,9 +625,23 @@ void make_plan(int B, const int64_t* idisk, const int32_t* N, PlanHost& P) {
   if (uniform && N[0] <= LANE_NMAX && find_lane(N[0])) {
     P.lane = 1;
     P.nspec = N[0];
-    int64_t mmax = 1;
-    for (int b = 0; b < B; ++b) mmax = std::max<int64_t>(mmax, idisk[b + 1] - idisk[b]);
-    P.waves = (int)std::min<int64_t>(ROW_MAX_WAVES, std::max<int64_t>(1, (mmax - 1 + 63) / 64));
+    const int np = 2 * N[0] + 1;
+    for (int b = 0; b < B; ++b) {
+      const int64_t d0 = idisk[b], Mb = idisk[b + 1] - d0;
+      const int64_t n = (Mb - 1 + LANE_CHUNK - 1) / LANE_CHUNK;  // 0 for M = 1
+      for (int64_t p = d0; p < d0 + Mb; ++p) {
+        P.nch[p] = (int32_t)n;
+        P.poff[p] = P.part;
+        P.part += std::max<int64_t>(n, 1) * np;
+        for (int64_t c = 0; c < n; ++c) {
+          const int64_t jb = c * LANE_CHUNK, je = std::min<int64_t>(jb + LANE_CHUNK, Mb - 1);
+          P.items.push_back((int32_t)p);
+          P.items.push_back((int32_t)c);
+          P.items.push_back((int32_t)jb);
+          P.items.push_back((int32_t)je);
+        }
+      }
+    }
     return;
   }
   P.lane = 0;
@@ -690,8 +740,15 @@ int apply_operator(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, cplx* p
   if (P.lane) {
     const LaneVariant* lv = find_lane(P.spec_N);
     if (!lv) return fail(MUDIFF_ERR_INVALID, "no operator kernel variant");
-    hipLaunchKernelGGL(lv->fn, dim3(h->M_all, R), dim3(64 * P.waves), 0, s, h->dv, R, x, y, op,
-                       active);
+    if (P.n_items > 0) {
+      hipLaunchKernelGGL(lv->fn, dim3(P.n_items, R), dim3(64), 0, s, h->dv, R, x, part,
+                         P.part_total, P.d_items, P.d_partoff, active);
+      HIP_TRY(hipGetLastError());
+    }
+    const int64_t total = (int64_t)R * h->N_all;
+    hipLaunchKernelGGL(k_apply_finish, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                       h->dv, R, x, y, op, (const cplx*)part, P.part_total, P.d_nchunk,
+                       P.d_partoff, active);
     HIP_TRY(hipGetLastError());
     return MUDIFF_OK;
   }

@@ -148,19 +148,23 @@ __global__ void k_pair_tables(DevView v, int64_t P_all) {
       T[n + 1].y = y;
     }
   }
-  // lane-interleaved copy for uniform N: H_nu and e^{i alpha} of both orders
+  // lane-interleaved pair records for uniform N, both orders: H_0, H_1,
+  // e^{i alpha} (alpha_qp = alpha_pq + pi) and 2 / (k b)
   if (v.lane_N >= 0) {
-    const int64_t pc = (int64_t)LANE_CHUNK * (S + 2);
+    const int64_t pc = (int64_t)LANE_CHUNK * LANE_REC;
     const cplx e = cexpi(alpha);
     const int64_t jpq = q - v.idisk[b] - 1, jqp = p - v.idisk[b];  // q > p
     cplx* A = v.lt + v.ltoff[p] + (jpq / LANE_CHUNK) * pc + (jpq % LANE_CHUNK);
     cplx* Bq = v.lt + v.ltoff[q] + (jqp / LANE_CHUNK) * pc + (jqp % LANE_CHUNK);
-    for (int nu = 0; nu <= S; ++nu) {
-      A[(int64_t)nu * LANE_CHUNK] = T[nu];
-      Bq[(int64_t)nu * LANE_CHUNK] = T[nu];
-    }
-    A[(int64_t)(S + 1) * LANE_CHUNK] = e;
-    Bq[(int64_t)(S + 1) * LANE_CHUNK] = cmk(-e.x, -e.y);  // alpha_qp = alpha_pq + pi
+    const cplx r2 = cmk(2.0 / x, 0.0);
+    A[0] = T[0];
+    Bq[0] = T[0];
+    A[LANE_CHUNK] = T[1];
+    Bq[LANE_CHUNK] = T[1];
+    A[2 * LANE_CHUNK] = e;
+    Bq[2 * LANE_CHUNK] = cmk(-e.x, -e.y);
+    A[3 * LANE_CHUNK] = r2;
+    Bq[3 * LANE_CHUNK] = r2;
   }
   // phases: t_s = H_s e^{i s alpha}, t_{-s} = (-1)^s H_s e^{-i s alpha}
   for (int s = S; s >= 1; --s) {
@@ -188,7 +192,7 @@ int64_t lane_layout(int B, const int64_t* disk_off, const int32_t* n_modes, int*
   const int N = n_modes[0];
   if (N < 1 || N > LANE_NMAX) return 0;
   *lane_N = N;
-  const int64_t per_chunk = (int64_t)LANE_CHUNK * (2 * N + 2);
+  const int64_t per_chunk = (int64_t)LANE_CHUNK * LANE_REC;
   int64_t o = 0;
   for (int b = 0; b < B; ++b) {
     const int64_t Mb = disk_off[b + 1] - disk_off[b];

@@ -57,7 +57,7 @@ def test_workspace_size_queries(lib):
     assert _sizes(lib, [1, 4], [3] * 4) == 0                   # disk_off[0] != 0
     assert _sizes(lib, [0, 2, 2], [3] * 2) == 0                # empty instance
     # monotone in the number of modes
-    assert _sizes(lib, [0, 4], [15] * 4) > _sizes(lib, [0, 4], [8] * 4)
+    assert _sizes(lib, [0, 4], [12] * 4) > _sizes(lib, [0, 4], [8] * 4)
     assert _sizes(lib, [0, 4], [30] * 4) > _sizes(lib, [0, 4], [20] * 4)
 
 

@@ -122,6 +122,29 @@ def test_matvec_batched_instances(P):
             assert rel(Y[r], A @ X[r]) < 1e-12
 
 
+@pytest.mark.parametrize("N", [1, 5, 8, 12])
+def test_matvec_uniform_n_batches(P, N):
+    """Uniform-N batches (the one-lane-per-pair path): instances of M = 2, 65
+    and 130 disks (ragged 64-pair chunks, several waves per row), R = 1 and 3;
+    close and distant pairs (k b from ~2 to ~200)."""
+    cls = [synth.Cluster(*synth.random_disks(np.random.default_rng(60 + M), M, 0.4, 0.6, 0.0,
+                                             4.0 * math.sqrt(M), 0.15),
+                         np.full(M, N), 5.0) for M in (2, 65, 130)]
+    say("matvec uniform N", N)
+    pr = P.from_clusters(cls)
+    rng = np.random.default_rng(70 + N)
+    for R in (1, 3):
+        Xs = [rng.normal(size=(R, c.n_tot)) + 1j * rng.normal(size=(R, c.n_tot)) for c in cls]
+        for op in (0, 1):
+            y = pr.matvec(pr.pack(Xs), R=R, op=op)
+            for c, X, Y in zip(cls, Xs, pr.split(y, R)):
+                L, A = _dense(c)
+                Mref = A if op == 1 else L
+                Y = Y.cpu().numpy()
+                for r in range(R):
+                    assert rel(Y[r], Mref @ X[r]) < 1e-12, (c.M, R, op, r)
+
+
 def test_matvec_single_disk_and_repeat(P):
     """M = 1 (no pairs): A = I exactly; repeated applies give identical bits."""
     cl = synth.Cluster(np.array([[0.5, -1.0]]), np.array([0.8]), np.array([7]), 3.0)

@@ -154,16 +154,48 @@ int fail(int status, const std::string& msg);
 
 static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// ------------------------------------------------------------------ internal API
-// Internal apply output: the raw off-diagonal contraction
-// w_m = sum_{q != p} sum_n t^{pq}_{n-m} sqrt(a_q) J_n(k a_q) x^q_n.
+// ------------------------------------------------------------------ apply epilogue
+// Output value of the operator apply at unknown i from the coupling sum
+// w_m = sum_{q != p} sum_n t^{pq}_{n-m} sqrt(a_q) J_n(k a_q) x^q_n:
+//   MUDIFF_OP_A: x + w / (sqrt(a_p) H_m)        (A = D^{-1} L = I + K)
+//   OP_RAW_W:    w
+//   MUDIFF_OP_L: L^{pp}_{mm} x + (i pi / 2) sqrt(a_p) J_m w
 #define OP_RAW_W 7
+__device__ __forceinline__ cplx finalize(const DevView& v, int op, int64_t i, cplx xv, cplx w) {
+  if (op == MUDIFF_OP_A) return cadd(xv, cmul(v.invSH[i], w));
+  if (op == OP_RAW_W) return w;
+  const double f = 0.5 * 3.14159265358979323846 * v.sJ[i];  // (i pi / 2) s_m w
+  return cadd(cmul(v.Ldiag[i], xv), cmk(-f * w.y, f * w.x));
+}
 
+// Sum, in chunk order, of the one-lane-per-pair partial sums of unknown i
+// (instance b) for one right-hand side (part points at that column's block).
+__device__ __forceinline__ cplx lane_chunk_sum(const DevView& v, const cplx* __restrict__ part,
+                                               const int32_t* __restrict__ nchunk,
+                                               const int64_t* __restrict__ partoff, int b,
+                                               int64_t i) {
+  const int p = v.udisk[i];
+  const int64_t m = i - v.imode[b] - v.moff[p];
+  const int np = 2 * v.N[p] + 1;
+  const cplx* pr = part + partoff[p] + m;
+  cplx w = cmk(0.0, 0.0);
+  const int nch = nchunk[p];
+  for (int k = 0; k < nch; ++k) w = cadd(w, pr[(int64_t)k * np]);
+  return w;
+}
+
+// ------------------------------------------------------------------ internal API
 // Operator apply on R columns. `part`/`counters` come from the caller's scratch
 // (mudiff_matvec_workspace_size); counters must be zero on entry and are left
 // zero. `active` (optional, [B*R]) skips columns whose entry is 0.
 int apply_operator(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, cplx* part,
                    int32_t* counters, const int32_t* active, hipStream_t s);
+// Same, except that on the one-lane-per-pair path only the chunk partial sums
+// are written (*pending = true): the caller adds them (lane_chunk_sum) and
+// applies finalize itself.
+int apply_operator_split(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, cplx* part,
+                         int32_t* counters, const int32_t* active, hipStream_t s,
+                         bool* pending);
 size_t apply_scratch_bytes(mudiff_ctx* h, int R);
 int ensure_plan(mudiff_ctx* h, hipStream_t s);
 int prepare_apply(mudiff_ctx* h, int R, hipStream_t s);  // plan or MFMA tables for R

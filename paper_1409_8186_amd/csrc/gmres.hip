@@ -166,14 +166,18 @@ __device__ void chunk_dots(const GState& s, int j, int64_t o, int len, const cpl
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int i0 = wv; i0 <= j; i0 += GS_WAVES * GS_BATCH) {
     cplx a[GS_BATCH];
+    const cplx* vi[GS_BATCH];
 #pragma unroll
     for (int u = 0; u < GS_BATCH; ++u) {
       a[u] = cmk(0.0, 0.0);
-      const int i = i0 + u * GS_WAVES;
-      if (i <= j) {
-        const cplx* vi = s.V + (int64_t)i * s.NT + o;
-        for (int r = lane; r < len; r += 64) cmacc(a[u], vi[r], wl[r]);
-      }
+      const int i = min(i0 + u * GS_WAVES, j);  // past j: a valid row, result unused
+      vi[u] = s.V + (int64_t)i * s.NT + o;
+    }
+#pragma unroll 4
+    for (int r = lane; r < len; r += 64) {
+      const cplx wr = wl[r];
+#pragma unroll
+      for (int u = 0; u < GS_BATCH; ++u) cmacc(a[u], vi[u][r], wr);
     }
 #pragma unroll
     for (int u = 0; u < GS_BATCH; ++u) {
@@ -199,17 +203,23 @@ __device__ double block_sum(double v, double* sred) {
   return t;
 }
 
-// w - sum_{i <= j} h_i V_i at row r of the chunk (four loads in flight).
+// w - sum_{i <= j} h_i V_i at row r of the chunk (sixteen loads in flight).
 __device__ __forceinline__ cplx project_out(const GState& s, int j, const cplx* vr, cplx v,
                                             const cplx* h) {
   int i = 0;
+  for (; i + 15 <= j; i += 16) {
+    cplx t[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) t[u] = vr[(int64_t)(i + u) * s.NT];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v = csub(v, cmul(h[i + u], t[u]));
+  }
   for (; i + 3 <= j; i += 4) {
-    const cplx v0 = vr[(int64_t)i * s.NT], v1 = vr[(int64_t)(i + 1) * s.NT];
-    const cplx v2 = vr[(int64_t)(i + 2) * s.NT], v3 = vr[(int64_t)(i + 3) * s.NT];
-    v = csub(v, cmul(h[i], v0));
-    v = csub(v, cmul(h[i + 1], v1));
-    v = csub(v, cmul(h[i + 2], v2));
-    v = csub(v, cmul(h[i + 3], v3));
+    cplx t[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) t[u] = vr[(int64_t)(i + u) * s.NT];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v = csub(v, cmul(h[i + u], t[u]));
   }
   for (; i <= j; ++i) v = csub(v, cmul(h[i], vr[(int64_t)i * s.NT]));
   return v;
@@ -235,8 +245,20 @@ __device__ void column_step(const GState& s, int c, int j, cplx* hl, double hn) 
   if (tid == 0) arnoldi_step(s, c, j, hl, csl, snl, hn);
 }
 
-// Pass 1 of step j on w = V[j+1]: partial h = V^H w and ||w||^2 into P1.
-__global__ __launch_bounds__(GS_THREADS) void k_gs_dots(GState s, int j) {
+// Chunk partial sums of an operator apply still to be added (one-lane-per-pair
+// path): w = A V[j] is completed row by row by the first Gram-Schmidt pass.
+struct PendingApply {
+  DevView v;
+  const cplx* part;
+  int64_t part_total;
+  const int32_t* nchunk;
+  const int64_t* partoff;
+};
+
+// Pass 1 of step j on w = V[j+1]: partial h = V^H w and ||w||^2 into P1.  With
+// FIN, w is first formed from the apply's chunk partial sums and stored.
+template <bool FIN>
+__global__ __launch_bounds__(GS_THREADS) void k_gs_dots(GState s, int j, PendingApply pa) {
   __shared__ cplx wl[1024];
   __shared__ double sred[GS_WAVES];
   int c, len;
@@ -244,12 +266,27 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs_dots(GState s, int j) {
   decode_chunk(s, blockIdx.x, &c, &len, &o);
   if (!s.inner[c]) return;
   const int m1 = s.m + 1;
-  const cplx* w = s.V + (int64_t)(j + 1) * s.NT + o;
+  cplx* w = s.V + (int64_t)(j + 1) * s.NT + o;
   double nn = 0.0;
-  for (int r = threadIdx.x; r < len; r += GS_THREADS) {
-    const cplx v = w[r];
-    wl[r] = v;
-    nn += cabs2(v);
+  if (FIN) {
+    const int b = c / s.R, r = c - (c / s.R) * s.R;
+    const int64_t i0 = pa.v.imode[b] + (o - col_base(pa.v.imode, b, s.R, r));
+    const cplx* xj = s.V + (int64_t)j * s.NT + o;
+    const cplx* pr = pa.part + (int64_t)r * pa.part_total;
+    for (int rr = threadIdx.x; rr < len; rr += GS_THREADS) {
+      const int64_t i = i0 + rr;
+      const cplx v =
+          finalize(pa.v, MUDIFF_OP_A, i, xj[rr], lane_chunk_sum(pa.v, pr, pa.nchunk, pa.partoff, b, i));
+      w[rr] = v;
+      wl[rr] = v;
+      nn += cabs2(v);
+    }
+  } else {
+    for (int r = threadIdx.x; r < len; r += GS_THREADS) {
+      const cplx v = w[r];
+      wl[r] = v;
+      nn += cabs2(v);
+    }
   }
   nn = block_sum(nn, sred);  // (its barrier also publishes wl)
   cplx* part = s.P1 + (int64_t)blockIdx.x * m1;
@@ -502,12 +539,13 @@ __global__ void k_precond_rhs(DevView v, int R, const cplx* __restrict__ src, cp
 // ------------------------------------------------------------------ host driver
 // Rows per reduction chunk: enough chunks over all columns to fill the chip
 // (about 2048), few enough per column (<= 128 where possible) that every
-// workgroup can add all partials of its column, and 128..1024 rows each
-// (1024 = the LDS row buffer of the Gram-Schmidt kernels).
+// workgroup can add all partials of its column, and 256..1024 rows each (one
+// row per thread at least; 1024 = the LDS row buffer of the Gram-Schmidt
+// kernels).
 static int64_t chunk_rows(int64_t NT, int64_t ncol_max) {
   auto up64 = [](int64_t v) { return (v + 63) / 64 * 64; };
   int64_t ch = std::max(up64((NT + 2047) / 2048), up64((ncol_max + 127) / 128));
-  return std::min<int64_t>(std::max<int64_t>(ch, 128), 1024);
+  return std::min<int64_t>(std::max<int64_t>(ch, GS_THREADS), 1024);
 }
 
 static int64_t max_col_rows(const mudiff_ctx* h) {
@@ -612,11 +650,18 @@ static int enqueue_cycle(GmresRun& G, int check_every, bool host_checks) {
   hipLaunchKernelGGL(k_scale_v0, dim3(eb), dim3(256), 0, G.st, s, s.NT, G.d_rowcol);
   HIP_TRY(hipGetLastError());
   for (int j = 0; j < s.m; ++j) {
-    int rc = apply_operator(G.h, s.R, s.V + (int64_t)j * s.NT, s.V + (int64_t)(j + 1) * s.NT,
-                            MUDIFF_OP_A, G.apply_part, G.apply_cnt, s.inner, G.st);
+    bool pending = false;
+    int rc = apply_operator_split(G.h, s.R, s.V + (int64_t)j * s.NT,
+                                  s.V + (int64_t)(j + 1) * s.NT, MUDIFF_OP_A, G.apply_part,
+                                  G.apply_cnt, s.inner, G.st, &pending);
     if (rc != MUDIFF_OK) return rc;
     const unsigned nb = (unsigned)G.L.n_chunks;
-    hipLaunchKernelGGL(k_gs_dots, dim3(nb), dim3(GS_THREADS), 0, G.st, s, j);
+    PendingApply pa{G.h->dv, G.apply_part, G.h->plan.part_total, G.h->plan.d_nchunk,
+                    G.h->plan.d_partoff};
+    if (pending)
+      hipLaunchKernelGGL(k_gs_dots<true>, dim3(nb), dim3(GS_THREADS), 0, G.st, s, j, pa);
+    else
+      hipLaunchKernelGGL(k_gs_dots<false>, dim3(nb), dim3(GS_THREADS), 0, G.st, s, j, pa);
     hipLaunchKernelGGL(k_gs_update, dim3(nb), dim3(GS_THREADS), 0, G.st, s, j);
     hipLaunchKernelGGL(k_gs_reorth, dim3(nb), dim3(GS_THREADS), 0, G.st, s, j);
     HIP_TRY(hipGetLastError());

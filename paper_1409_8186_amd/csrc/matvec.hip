@@ -59,12 +59,6 @@ __device__ __forceinline__ void toeplitz_block(const cplx* __restrict__ zrow,
 }
 
 // Output of row unknown i from x_i and the off-diagonal contraction w_i.
-__device__ __forceinline__ cplx finalize(const DevView& v, int op, int64_t i, cplx xv, cplx w) {
-  if (op == MUDIFF_OP_A) return cadd(xv, cmul(v.invSH[i], w));
-  if (op == OP_RAW_W) return w;
-  const double f = 0.5 * 3.14159265358979323846 * v.sJ[i];  // (i pi / 2) s_m w
-  return cadd(cmul(v.Ldiag[i], xv), cmk(-f * w.y, f * w.x));
-}
 
 // NSPEC >= 0: every disk of the launch has N_p = NSPEC (exact loop bounds).
 template <int BT, int NSPEC>
@@ -305,13 +299,7 @@ __global__ void k_apply_finish(DevView v, int R, const cplx* __restrict__ x, cpl
   const int r = (int)(rem / Nb);
   if (active && active[b * R + r] == 0) return;
   const int64_t i = v.imode[b] + (rem - (int64_t)r * Nb);
-  const int p = v.udisk[i];
-  const int64_t m = i - v.imode[b] - v.moff[p];
-  const int np = 2 * v.N[p] + 1;
-  const cplx* pr = part + (int64_t)r * part_total + partoff[p] + m;
-  cplx w = cmk(0.0, 0.0);
-  const int nch = nchunk[p];
-  for (int k = 0; k < nch; ++k) w = cadd(w, pr[(int64_t)k * np]);
+  const cplx w = lane_chunk_sum(v, part + (int64_t)r * part_total, nchunk, partoff, b, i);
   y[g] = finalize(v, op, i, x[g], w);
 }
 
@@ -729,6 +717,28 @@ size_t apply_scratch_bytes(mudiff_ctx* h, int R) {
 int prepare_apply(mudiff_ctx* h, int R, hipStream_t s) {
   if (use_mfma(h, R)) return ensure_mfma_groups(h, R, s);
   return ensure_plan(h, s);
+}
+
+int apply_operator_split(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, cplx* part,
+                         int32_t* counters, const int32_t* active, hipStream_t s,
+                         bool* pending) {
+  *pending = false;
+  if (use_mfma(h, R)) return launch_apply_mfma(h, R, x, y, op, active, s);
+  int st = ensure_plan(h, s);
+  if (st != MUDIFF_OK) return st;
+  const MatvecPlan& P = h->plan;
+  if (P.lane) {
+    const LaneVariant* lv = find_lane(P.spec_N);
+    if (!lv) return fail(MUDIFF_ERR_INVALID, "no operator kernel variant");
+    if (P.n_items > 0) {
+      hipLaunchKernelGGL(lv->fn, dim3(P.n_items, R), dim3(64), 0, s, h->dv, R, x, part,
+                         P.part_total, P.d_items, P.d_partoff, active);
+      HIP_TRY(hipGetLastError());
+    }
+    *pending = true;  // the chunk sums still have to be added and finalised
+    return MUDIFF_OK;
+  }
+  return apply_operator(h, R, x, y, op, part, counters, active, s);
 }
 
 int apply_operator(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, cplx* part,

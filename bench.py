@@ -33,7 +33,16 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_VECTOR_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_apply_one_rhs_traffic.txt")
-APPLY_SRC = os.path.join(ROOT, "paper_1409_8186_amd", "csrc", "matvec.hip")
+APPLY_SRC = [os.path.join(ROOT, "paper_1409_8186_amd", "csrc", f)
+             for f in ("matvec.hip", "common.h", "tables.hip")]
+
+
+def apply_source_sha():
+    """Digest of the sources that define the one-RHS apply kernels and their data."""
+    h = hashlib.sha256()
+    for f in APPLY_SRC:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def algorithmic_flops(n_modes, R=1):
@@ -62,7 +71,7 @@ def traffic_per_launch():
     if not os.path.exists(TRAFFIC_FILE):
         return None
     txt = open(TRAFFIC_FILE).read()
-    sha = hashlib.sha256(open(APPLY_SRC, "rb").read()).hexdigest()[:16]
+    sha = apply_source_sha()
     m = re.search(r"source_sha256_16:\s*([0-9a-f]+)", txt)
     f = re.search(r"fetch_bytes_per_launch:\s*([0-9.eE+]+)", txt)
     w = re.search(r"write_bytes_per_launch:\s*([0-9.eE+]+)", txt)
@@ -331,7 +340,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
                      "traffic": traffic,
-                     "kernel": "k_apply (operator apply, one RHS)",
+                     "kernel": "operator apply, one RHS: k_apply_lane<12> + k_apply_finish",
+                     "source_sha256_16": apply_source_sha(),
                      "algorithmic_flops_per_launch": flops,
                      "algorithmic_bytes_per_launch": algorithmic_bytes(cl.n_modes)},
     }

@@ -6,6 +6,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <map>
 #include <cstdio>
 #include <string>
 #include <vector>
@@ -121,6 +122,29 @@ struct MatvecPlan {
   int64_t* d_partoff = nullptr; // [M_all]
 };
 
+// MFMA apply tile choice: CT sub-tiles of 8 right-hand sides, RP row disks per
+// work item (RP * CT waves), column-disk segment length QS (0: whole
+// instance), workgroup size.
+struct MfmaChoice {
+  int CT = 1, RP = 4, QS = 0, threads = 256;
+  bool operator==(const MfmaChoice& o) const {
+    return CT == o.CT && RP == o.RP && QS == o.QS && threads == o.threads;
+  }
+};
+
+// Host schedule of the MFMA apply: work items (p0, rp, tile, q0, q1, partial
+// block) sorted by decreasing cost, the row group of every disk, and per group
+// its first disk, segment count and first partial block.
+struct MfmaSched {
+  int R = 0;
+  MfmaChoice c{};
+  int ntile = 0, n_items = 0, npad = 0;
+  int64_t blk = 0, n_pb = 0;
+  std::vector<int32_t> items, dgrp, gp0, gnseg;
+  std::vector<int64_t> gbase;
+  void* dev_base = nullptr;  // apply scratch the device copy lives in
+};
+
 struct mudiff_ctx {
   int B = 0, M_all = 0, Nmax = 0;
   int64_t N_all = 0, P_all = 0, T_all = 0, D_all = 0;
@@ -136,10 +160,12 @@ struct mudiff_ctx {
   MatvecPlan plan;
   int64_t plan_part = -1;       // partial sums per right-hand side of the plan
   bool mfma_enabled = true;     // multi-RHS applies on FP64 MFMA
-  std::vector<int32_t> mfma_groups;  // host copy of the MFMA row groups
-  int mfma_rp = 0;
-  int32_t* mfma_groups_dev = nullptr;  // inside the tables workspace
-  size_t mfma_groups_bytes = 0;
+  bool mfma_tune = true;        // time the MFMA tile candidates on first use of an R
+  int n_cu = 256;               // compute units of the device (persistent grid size)
+  std::map<int, MfmaChoice> mfma_choice;  // tile choice per R
+  std::map<int, float> mfma_time_ms;      // timed apply of the choice (autotuned R only)
+  std::map<int, size_t> mfma_bytes;       // apply scratch per R (largest candidate)
+  MfmaSched mfma_sched;                   // current schedule (host copy + upload location)
 };
 
 // ------------------------------------------------------------------ errors
@@ -198,7 +224,12 @@ int apply_operator_split(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, c
                          bool* pending);
 size_t apply_scratch_bytes(mudiff_ctx* h, int R);
 int ensure_plan(mudiff_ctx* h, hipStream_t s);
-int prepare_apply(mudiff_ctx* h, int R, hipStream_t s);  // plan or MFMA tables for R
+// Schedule for R applies made current (one-lane/generic plan, or the MFMA
+// schedule uploaded into `scratch`, the apply scratch later passed as `part`).
+// On the MFMA path the first use of R times the tile candidates on x -> y
+// (y is overwritten) when x and y are given.  Synchronises; not for use under
+// graph capture.
+int prepare_apply(mudiff_ctx* h, int R, const cplx* x, cplx* y, cplx* scratch, hipStream_t s);
 struct PlanHost;
 void make_plan(int B, const int64_t* idisk, const int32_t* N, PlanHost& P);
 size_t plan_sched_bytes(const PlanHost& P, int M);

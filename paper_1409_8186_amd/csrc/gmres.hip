@@ -701,8 +701,7 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
   if (ws_bytes < L.total) return fail(MUDIFF_ERR_NOMEM, "gmres workspace needs " + std::to_string(L.total) + " bytes");
   if (((uintptr_t)workspace) & 255) return fail(MUDIFF_ERR_INVALID, "workspace must be 256-byte aligned");
   hipStream_t st = (hipStream_t)stream;
-  int rc = prepare_apply(h, R, st);  // uploads happen outside any graph capture
-  if (rc != MUDIFF_OK) return rc;
+  int rc = MUDIFF_OK;
   char* w = (char*)workspace;
   GmresRun G{};
   G.h = h;
@@ -744,6 +743,10 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
   G.apply_cnt = (int32_t*)(w + L.apply + apply_scratch_bytes(h, R) - align256((size_t)R * h->M_all * 4));
   s.ckf = G.d_ckf;
   s.ckc = G.d_ckc;
+  // operator schedule (MFMA: tuned on V0 = 0 -> V1 on first use of R); uploads
+  // happen here, outside any graph capture
+  if ((rc = launch_fill_zero(s.V, (size_t)s.NT * 16, st)) != MUDIFF_OK) return rc;
+  if ((rc = prepare_apply(h, R, s.V, s.V + s.NT, G.apply_part, st)) != MUDIFF_OK) return rc;
 
   // chunk table (host) -> device
   std::vector<int64_t> ck;

@@ -310,218 +310,442 @@ __global__ void k_apply_finish(DevView v, int R, const cplx* __restrict__ x, cpl
 // panel holds [Re Z | Im Z] for 8 right-hand sides side by side, so
 //   acc1 = Re(T) [Re Z | Im Z],  acc2 = Im(T) [Re Z | Im Z],
 //   Re W = acc1[:, :8] - acc2[:, 8:],  Im W = acc1[:, 8:] + acc2[:, :8].
-// A workgroup owns one row disk p and 8 * (waves) right-hand sides; it loops
-// over every column disk q of the instance, staging the symbol row and the
-// scaled input panel in LDS, and accumulates all q in registers, so there is
-// no partial-sum traffic.  Lane layout (checked on the device): lane l holds
-// A[l % 16][l / 16], B[l / 16][l % 16] and D[4 v + l / 16][l % 16], v < 4.
+// Lane layout (checked on the device): lane l holds A[l % 16][l / 16],
+// B[l / 16][l % 16] and D[4 v + l / 16][l % 16], v < 4.
+//
+// Work item: row disks p0..p0+rp-1 (rp <= RP) of one instance, a tile of 8 CT
+// right-hand sides and a segment [q0, q1) of its column disks.  Wave w of the
+// workgroup computes row w / CT and right-hand-side sub-tile w % CT.  Per
+// column disk q the input panel Z^q = sqrt(a_q) J_n(k a_q) x^q_n and the symbol
+// rows of the item's row disks are staged in LDS once for all waves; the next
+// disk's values are gathered into registers while the current one is on the
+// matrix cores.  The workgroups are persistent: each takes items from a queue
+// (one atomic counter, items sorted by decreasing cost), so instances of very
+// different sizes share one launch and the launch ends evenly.  Each item's
+// sums go to its own partial block; k_apply_mfma_finish adds the segments of
+// every row in order (no inter-workgroup synchronisation).  The tile shape
+// (RP, CT), the segment length and the workgroup size are chosen per handle
+// and R by timing the candidates on the real data (mfma_autotune).
 typedef double mf_d4 __attribute__((ext_vector_type(4)));
 
-// Work item: up to RP consecutive row disks p0..p0+rp-1 of one instance and a
-// tile of 8 * CT right-hand sides; wave w computes row r = w / CT, right-hand
-// side sub-tile w % CT.  The input panel Z^q is staged once per column disk q
-// for all rows of the item; the next column disk's symbols and inputs are
-// loaded into registers while the current one is on the matrix cores.
-#define MF_ZK 8   // staged Z values per thread (4 * 16 rows * 32 columns / 256)
-#define MF_TK 2   // staged symbol values per thread (4 rows * (64 + 64) / 256)
+#define MF_REC 6       // item record: p0, rp, tile, q0, q1, partial block
+#define MF_MAXZ 2048   // staged Z values per column disk: 4 ktmax (<= 64) x RC (<= 32)
+#define MF_MAXT 1016   // staged symbol values: RP (<= 8) x TL (<= 64 + 63)
 
-template <int MT>  // row tiles of 16: n_p <= 16 MT
-__global__ __launch_bounds__(256) void k_apply_mfma(DevView v, int R, const cplx* __restrict__ x,
-                                                    cplx* __restrict__ y, int op,
-                                                    const int32_t* __restrict__ active,
-                                                    const int32_t* __restrict__ groups, int ktmax,
-                                                    int RP, int CT) {
+template <int MT, int THREADS>  // row tiles of 16: n_p <= 16 MT
+__global__ __launch_bounds__(THREADS) void k_apply_mfma(
+    DevView v, int R, const cplx* __restrict__ x, const int32_t* __restrict__ active,
+    const int32_t* __restrict__ items, int n_items, int32_t* __restrict__ head,
+    cplx* __restrict__ part, int64_t blk, int npad, int ktmax, int RP, int CT) {
+  constexpr int ZK = (MF_MAXZ + THREADS - 1) / THREADS;
+  constexpr int TK = (MF_MAXT + THREADS - 1) / THREADS;
   extern __shared__ cplx lds[];
-  const int p0 = groups[2 * blockIdx.x], rp = groups[2 * blockIdx.x + 1];
-  const int RC = 8 * CT;
-  const int c0 = blockIdx.y * RC;
+  __shared__ int s_item;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int j = lane & 15, kq = lane >> 4;
+  const int RC = 8 * CT;
   const int row = wave / CT, ctile = wave - (wave / CT) * CT;
-  const int b = v.inst[p0];
-  const int64_t d0 = v.idisk[b], Mb = v.idisk[b + 1] - d0;
-  const int64_t i0 = v.imode[b];
-  const int TL = 4 * ktmax + 16 * MT - 1;   // symbol row length in LDS
-  const int p = p0 + row;
-  const bool row_ok = row < rp;
-  const int Np = row_ok ? v.N[p] : 0, np = 2 * Np + 1;
-  const int mycol = c0 + ctile * 8 + (j & 7);
-  bool wave_active = row_ok;
-  if (wave_active) {
-    wave_active = false;
-    for (int c = 0; c < 8; ++c) {
-      const int r = c0 + ctile * 8 + c;
-      if (r < R && (!active || active[b * R + r])) wave_active = true;
-    }
-  }
-  bool any = false;  // the whole workgroup may skip (converged columns)
-  for (int r = c0; r < min(R, c0 + RC); ++r)
-    if (!active || active[b * R + r]) any = true;
-  if (!any) return;
-  cplx* zl = lds;                       // [4 ktmax][RC]
-  cplx* tl = lds + 4 * ktmax * RC;      // [RP][TL]
-  mf_d4 acc1[MT], acc2[MT];
-#pragma unroll
-  for (int t = 0; t < MT; ++t) {
-    acc1[t] = mf_d4{0.0, 0.0, 0.0, 0.0};
-    acc2[t] = mf_d4{0.0, 0.0, 0.0, 0.0};
-  }
-  // this thread's staging slots (fixed over the column disks): input panel
-  // element (column zc, row zn), symbol element (row tr_r, position tr_u)
-  int zc[MF_ZK], zn[MF_ZK], trr[MF_TK], tru[MF_TK];
+  const int TL = 4 * ktmax + 16 * MT - 1;  // symbol row length in LDS
   const int zrows = 4 * ktmax;
+  cplx* zl = lds;                          // [4 ktmax][RC]
+  cplx* tl = lds + zrows * RC;             // [RP][TL]
+  // this thread's staging slots: input panel element (column zc, row zn),
+  // symbol element (row trr, position tru)
+  int zc[ZK], zn[ZK], trr[TK], tru[TK];
 #pragma unroll
-  for (int k = 0; k < MF_ZK; ++k) {
-    const int e = tid + k * 256;
+  for (int k = 0; k < ZK; ++k) {
+    const int e = tid + k * THREADS;
     zc[k] = e / zrows;
     zn[k] = e - zc[k] * zrows;
   }
 #pragma unroll
-  for (int k = 0; k < MF_TK; ++k) {
-    const int e = tid + k * 256;
+  for (int k = 0; k < TK; ++k) {
+    const int e = tid + k * THREADS;
     trr[k] = e / TL;
     tru[k] = e - trr[k] * TL;
   }
-  cplx zr[MF_ZK], tr[MF_TK];
-  // gather the staged values of column disk q into registers
-  auto gather = [&](int q) {
-    const int Nq = v.N[q], nq = 2 * Nq + 1;
-    const int64_t mq = v.moff[q];
-#pragma unroll
-    for (int k = 0; k < MF_ZK; ++k) {
-      const int c = zc[k], n = zn[k];
-      cplx z = cmk(0.0, 0.0);
-      if (c < RC && n < nq && c0 + c < R) {
-        const int r = c0 + c;
-        z = cscale(x[col_base(v.imode, b, R, r) + mq + n], v.sJ[i0 + mq + n]);
-      }
-      zr[k] = z;
-    }
-#pragma unroll
-    for (int k = 0; k < MF_TK; ++k) {
-      const int rr = trr[k], u = tru[k];
-      cplx t = cmk(0.0, 0.0);
-      const int pr = p0 + rr;
-      if (rr < rp && pr != q) {
-        const int Npr = v.N[pr];
-        const int S = Npr + Nq;
-        const int s = u - (16 * MT - 1) - Nq + Npr;
-        if (s >= -S && s <= S) {
-          const int64_t g = pair_index(v.idisk, v.ipair, b, pr, q);
-          t = v.t[v.toff[g] + S + s];
-          if (pr > q && (s & 1)) t = cmk(-t.x, -t.y);
-        }
-      }
-      tr[k] = t;
-    }
-  };
-  int q = (int)d0;
-  gather(q);
-  for (; q < (int)(d0 + Mb); ++q) {
-    const int nq = 2 * v.N[q] + 1, KT = (nq + 3) >> 2;
-    __syncthreads();  // previous column disk done with LDS
-#pragma unroll
-    for (int k = 0; k < MF_ZK; ++k)
-      if (zc[k] < RC) zl[zn[k] * RC + zc[k]] = zr[k];
-#pragma unroll
-    for (int k = 0; k < MF_TK; ++k)
-      if (trr[k] < RP) tl[trr[k] * TL + tru[k]] = tr[k];
+  for (;;) {
+    __syncthreads();  // the previous item is done with s_item and LDS
+    if (tid == 0) s_item = atomicAdd(head, 1);
     __syncthreads();
-    if (q + 1 < (int)(d0 + Mb)) gather(q + 1);  // in flight during the MFMAs
-    if (wave_active && q != p) {
-      const cplx* trow = tl + row * TL;
-      for (int kk = 0; kk < KT; ++kk) {
-        const int n = 4 * kk + kq;
-        const cplx zz = zl[n * RC + ctile * 8 + (j & 7)];
-        const double bv = j < 8 ? zz.x : zz.y;
+    const int it = s_item;
+    if (it >= n_items) break;
+    const int32_t* rec = items + (int64_t)MF_REC * it;
+    const int p0 = rec[0], rp = rec[1], tile = rec[2], qb = rec[3], qe = rec[4];
+    const int64_t pb = rec[5];
+    const int c0 = tile * RC;
+    const int b = v.inst[p0];
+    bool any = false;  // converged columns: the whole tile may be skipped
+    for (int r = c0; r < min(R, c0 + RC); ++r)
+      if (!active || active[b * R + r]) any = true;
+    if (!any) continue;
+    const int64_t i0 = v.imode[b];
+    const int p = p0 + row;
+    const bool row_ok = row < rp;
+    bool wave_active = row_ok;
+    if (wave_active) {
+      wave_active = false;
+      for (int c = 0; c < 8; ++c) {
+        const int r = c0 + ctile * 8 + c;
+        if (r < R && (!active || active[b * R + r])) wave_active = true;
+      }
+    }
+    mf_d4 acc1[MT], acc2[MT];
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-          const cplx t = trow[n - (16 * mt + j) + 16 * MT - 1];  // A[i = lane % 16][k = kq]
-          acc1[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(t.x, bv, acc1[mt], 0, 0, 0);
-          acc2[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(t.y, bv, acc2[mt], 0, 0, 0);
+    for (int t = 0; t < MT; ++t) {
+      acc1[t] = mf_d4{0.0, 0.0, 0.0, 0.0};
+      acc2[t] = mf_d4{0.0, 0.0, 0.0, 0.0};
+    }
+    cplx zr[ZK], tr[TK];
+    // gather the staged values of column disk q into registers
+    auto gather = [&](int q) {
+      const int Nq = v.N[q], nq = 2 * Nq + 1;
+      const int64_t mq = v.moff[q];
+#pragma unroll
+      for (int k = 0; k < ZK; ++k) {
+        const int c = zc[k], n = zn[k];
+        cplx z = cmk(0.0, 0.0);
+        if (c < RC && n < nq && c0 + c < R)
+          z = cscale(x[col_base(v.imode, b, R, c0 + c) + mq + n], v.sJ[i0 + mq + n]);
+        zr[k] = z;
+      }
+#pragma unroll
+      for (int k = 0; k < TK; ++k) {
+        const int rr = trr[k], u = tru[k];
+        cplx t = cmk(0.0, 0.0);
+        const int pr = p0 + rr;
+        if (rr < rp && pr != q) {
+          const int Npr = v.N[pr];
+          const int S = Npr + Nq;
+          const int s = u - (16 * MT - 1) - Nq + Npr;
+          if (s >= -S && s <= S) {
+            const int64_t g = pair_index(v.idisk, v.ipair, b, pr, q);
+            t = v.t[v.toff[g] + S + s];
+            if (pr > q && (s & 1)) t = cmk(-t.x, -t.y);
+          }
+        }
+        tr[k] = t;
+      }
+    };
+    gather(qb);
+    for (int q = qb; q < qe; ++q) {
+      const int nq = 2 * v.N[q] + 1, KT = (nq + 3) >> 2;
+      __syncthreads();  // previous column disk done with LDS
+#pragma unroll
+      for (int k = 0; k < ZK; ++k)
+        if (zc[k] < RC) zl[zn[k] * RC + zc[k]] = zr[k];
+#pragma unroll
+      for (int k = 0; k < TK; ++k)
+        if (trr[k] < RP) tl[trr[k] * TL + tru[k]] = tr[k];
+      __syncthreads();
+      if (q + 1 < qe) gather(q + 1);  // in flight during the MFMAs
+      if (wave_active && q != p) {
+        const cplx* trow = tl + row * TL;
+        for (int kk = 0; kk < KT; ++kk) {
+          const int n = 4 * kk + kq;
+          const cplx zz = zl[n * RC + ctile * 8 + (j & 7)];
+          const double bv = j < 8 ? zz.x : zz.y;
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+            const cplx t = trow[n - (16 * mt + j) + 16 * MT - 1];  // A[i = lane % 16][k = kq]
+            acc1[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(t.x, bv, acc1[mt], 0, 0, 0);
+            acc2[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(t.y, bv, acc2[mt], 0, 0, 0);
+          }
         }
       }
     }
-  }
-  if (!wave_active) return;
-  const bool col_ok = mycol < R && (!active || active[b * R + mycol]);
-  const int64_t cb = col_ok ? col_base(v.imode, b, R, mycol) : 0;
-  const int64_t ip = i0 + v.moff[p];
+    if (!wave_active) continue;
+    // partial block [RP][npad][RC]: row r of the item, mode row m, RHS column
+    cplx* pbk = part + pb * blk + (int64_t)row * npad * RC + ctile * 8 + (j & 7);
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt) {
+    for (int mt = 0; mt < MT; ++mt) {
 #pragma unroll
-    for (int vv = 0; vv < 4; ++vv) {
-      const double a1 = acc1[mt][vv], a2 = acc2[mt][vv];
-      const double other = __shfl_xor(a2, 8, 64);
-      const double val = j < 8 ? a1 - other : a1 + other;  // Re W (j < 8), Im W (j >= 8)
-      const double im = __shfl_xor(val, 8, 64);
-      const int m = 16 * mt + 4 * vv + kq;  // D row 4 v + lane / 16
-      if (j < 8 && col_ok && m < np) {
-        const cplx w = cmk(val, im);
-        y[cb + v.moff[p] + m] = finalize(v, op, ip + m, x[cb + v.moff[p] + m], w);
+      for (int vv = 0; vv < 4; ++vv) {
+        const double a1 = acc1[mt][vv], a2 = acc2[mt][vv];
+        const double other = __shfl_xor(a2, 8, 64);
+        const double val = j < 8 ? a1 - other : a1 + other;  // Re W (j < 8), Im W (j >= 8)
+        const double im = __shfl_xor(val, 8, 64);
+        const int m = 16 * mt + 4 * vv + kq;  // D row 4 v + lane / 16
+        if (j < 8) pbk[(int64_t)m * RC] = cmk(val, im);
       }
     }
   }
+}
+
+// y = finalize(sum over the segments of the MFMA partial blocks), one thread
+// per output row, segments added in order.
+__global__ void k_apply_mfma_finish(DevView v, int R, const cplx* __restrict__ x,
+                                    cplx* __restrict__ y, int op, const cplx* __restrict__ part,
+                                    int64_t blk, int npad, int RC, const int32_t* __restrict__ dgrp,
+                                    const int32_t* __restrict__ gp0,
+                                    const int32_t* __restrict__ gnseg,
+                                    const int64_t* __restrict__ gbase,
+                                    const int32_t* __restrict__ active) {
+  const int64_t total = (int64_t)R * v.N_all;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  int lo = 0, hi = v.B;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if ((int64_t)R * v.imode[mid] <= g) lo = mid; else hi = mid;
+  }
+  const int b = lo;
+  const int64_t Nb = v.imode[b + 1] - v.imode[b];
+  const int64_t rem = g - (int64_t)R * v.imode[b];
+  const int r = (int)(rem / Nb);
+  if (active && active[b * R + r] == 0) return;
+  const int64_t i = v.imode[b] + (rem - (int64_t)r * Nb);
+  const int p = v.udisk[i];
+  const int64_t m = i - v.imode[b] - v.moff[p];
+  const int gr = dgrp[p];
+  const int t = r / RC, rc = r - (r / RC) * RC;
+  const int ns = gnseg[gr];
+  const cplx* pr = part + (gbase[gr] + (int64_t)t * ns) * blk +
+                   ((int64_t)(p - gp0[gr]) * npad + m) * RC + rc;
+  cplx w = cmk(0.0, 0.0);
+  for (int s = 0; s < ns; ++s) w = cadd(w, pr[(int64_t)s * blk]);
+  y[g] = finalize(v, op, i, x[g], w);
 }
 
 // R at and above which the MFMA kernel applies the operator (N_p <= 31).
 #define MFMA_MIN_R 8
 
-// 8-RHS sub-tiles per MFMA work item (CT) and row disks per item (RP), CT * RP = 4 waves
-static void mfma_tiling(int R, int* CT, int* RP) {
-  const int ct = std::min(4, (R + 7) / 8);
-  *CT = ct == 3 ? 4 : ct;
-  *RP = 4 / *CT;
-}
-
 static bool use_mfma(const mudiff_ctx* h, int R) {
   return R >= MFMA_MIN_R && h->Nmax <= 31 && h->mfma_enabled;
 }
 
-// Upload the MFMA work-item table for R right-hand sides (synchronises the
-// stream when the table changes, so it must not run under graph capture).
-static int ensure_mfma_groups(mudiff_ctx* h, int R, hipStream_t s) {
-  int CT, RP;
-  mfma_tiling(R, &CT, &RP);
-  if (h->mfma_groups.empty() || h->mfma_rp != RP) {
-    // groups of RP consecutive row disks inside one instance
-    std::vector<int32_t> gr;
-    for (int b = 0; b < h->B; ++b)
-      for (int64_t p = h->idisk[b]; p < h->idisk[b + 1]; p += RP) {
-        gr.push_back((int32_t)p);
-        gr.push_back((int32_t)std::min<int64_t>(RP, h->idisk[b + 1] - p));
-      }
-    if ((size_t)gr.size() * 4 > h->mfma_groups_bytes)
-      return fail(MUDIFF_ERR_INVALID, "MFMA group table does not fit");
-    HIP_TRY(hipMemcpyAsync(h->mfma_groups_dev, gr.data(), gr.size() * 4, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    h->mfma_groups.swap(gr);
-    h->mfma_rp = RP;
+// Host schedule of the MFMA apply for one tile choice.
+static void mfma_build(const mudiff_ctx* h, int R, const MfmaChoice& c, MfmaSched& S) {
+  S.R = R;
+  S.c = c;
+  S.dev_base = nullptr;
+  const int RC = 8 * c.CT;
+  S.ntile = (R + RC - 1) / RC;
+  const int mt = (2 * h->Nmax + 1 + 15) / 16;
+  S.npad = 16 * mt;
+  S.blk = (int64_t)c.RP * S.npad * RC;
+  S.items.clear();
+  S.gp0.clear();
+  S.gnseg.clear();
+  S.gbase.clear();
+  S.dgrp.assign(h->M_all, 0);
+  struct It {
+    double cost;
+    int32_t r[MF_REC];
+  };
+  std::vector<It> its;
+  int64_t pb = 0;
+  for (int b = 0; b < h->B; ++b) {
+    const int64_t d0 = h->idisk[b], d1 = h->idisk[b + 1], Mb = d1 - d0;
+    const int64_t qs = c.QS > 0 ? c.QS : Mb;
+    const int nseg = (int)((Mb + qs - 1) / qs);
+    for (int64_t p = d0; p < d1; p += c.RP) {
+      const int rp = (int)std::min<int64_t>(c.RP, d1 - p);
+      const int gi = (int)S.gp0.size();
+      for (int k = 0; k < rp; ++k) S.dgrp[p + k] = gi;
+      S.gp0.push_back((int32_t)p);
+      S.gnseg.push_back(nseg);
+      S.gbase.push_back(pb);
+      double rows = 0.0;
+      for (int k = 0; k < rp; ++k) rows += 2 * h->N[p + k] + 1;
+      for (int t = 0; t < S.ntile; ++t)
+        for (int s = 0; s < nseg; ++s) {
+          const int64_t q0 = d0 + s * qs, q1 = std::min<int64_t>(d1, q0 + qs);
+          double cols = 0.0;
+          for (int64_t q = q0; q < q1; ++q) cols += 2 * h->N[q] + 1;
+          It e;
+          e.cost = rows * cols + 64.0 * (double)(q1 - q0);  // MACs + per-disk staging
+          e.r[0] = (int32_t)p;
+          e.r[1] = rp;
+          e.r[2] = t;
+          e.r[3] = (int32_t)q0;
+          e.r[4] = (int32_t)q1;
+          e.r[5] = (int32_t)(pb + (int64_t)t * nseg + s);
+          its.push_back(e);
+        }
+      pb += (int64_t)S.ntile * nseg;
+    }
   }
+  S.n_pb = pb;
+  std::stable_sort(its.begin(), its.end(), [](const It& a, const It& b) { return a.cost > b.cost; });
+  S.items.resize(its.size() * MF_REC);
+  for (size_t k = 0; k < its.size(); ++k)
+    for (int f = 0; f < MF_REC; ++f) S.items[k * MF_REC + f] = its[k].r[f];
+  S.n_items = (int)its.size();
+}
+
+// Byte layout of the MFMA schedule inside the apply scratch:
+// [head][items][dgrp][gp0][gnseg][gbase][partial blocks]
+static size_t mfma_scratch_layout(const mudiff_ctx* h, const MfmaSched& S, size_t* off) {
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o = align256(o + bytes);
+    return r;
+  };
+  off[0] = take(4);
+  off[1] = take(S.items.size() * 4);
+  off[2] = take((size_t)h->M_all * 4);
+  off[3] = take(S.gp0.size() * 4);
+  off[4] = take(S.gnseg.size() * 4);
+  off[5] = take(S.gbase.size() * 8);
+  off[6] = take((size_t)S.n_pb * S.blk * 16);
+  return o;
+}
+
+// Candidate tile choices for R right-hand sides (RP * CT waves of 64 lanes).
+static std::vector<MfmaChoice> mfma_candidates(int R) {
+  std::vector<MfmaChoice> out;
+  const int ctmax = std::max(1, std::min(4, (R + 7) / 8));
+  for (int waves : {4, 8})
+    for (int ct : {1, 2, 4}) {
+      if (ct > ctmax && ct > 1) continue;
+      const int rp = waves / ct;
+      if (rp < 1 || rp > 8) continue;
+      for (int qs : {0, 32}) out.push_back(MfmaChoice{ct, rp, qs, 64 * waves});
+    }
+  return out;
+}
+
+static MfmaChoice mfma_default(int R) {
+  const int ct0 = std::min(4, (R + 7) / 8);
+  const int ct = ct0 == 3 ? 4 : ct0;
+  return MfmaChoice{ct, 4 / ct, 0, 256};
+}
+
+// Upload schedule S into the apply scratch at `base` (synchronises; not for
+// use under graph capture).
+static int mfma_upload(mudiff_ctx* h, MfmaSched& S, char* base, hipStream_t s) {
+  size_t off[7];
+  mfma_scratch_layout(h, S, off);
+  HIP_TRY(hipMemcpyAsync(base + off[1], S.items.data(), S.items.size() * 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(base + off[2], S.dgrp.data(), (size_t)h->M_all * 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(base + off[3], S.gp0.data(), S.gp0.size() * 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(base + off[4], S.gnseg.data(), S.gnseg.size() * 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(base + off[5], S.gbase.data(), S.gbase.size() * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  S.dev_base = base;
   return MUDIFF_OK;
 }
 
-static int launch_apply_mfma(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op,
-                             const int32_t* active, hipStream_t s) {
-  const int mt = (2 * h->Nmax + 1 + 15) / 16;
+// Enqueue one MFMA apply with schedule S already uploaded at S.dev_base.
+static int mfma_launch(mudiff_ctx* h, const MfmaSched& S, const cplx* x, cplx* y, int op,
+                       const int32_t* active, hipStream_t s) {
+  size_t off[7];
+  mfma_scratch_layout(h, S, off);
+  char* base = (char*)S.dev_base;
+  int32_t* head = (int32_t*)(base + off[0]);
+  cplx* part = (cplx*)(base + off[6]);
+  const int mt = S.npad / 16;
   const int kt = (2 * h->Nmax + 1 + 3) / 4;
-  int CT, RP;
-  mfma_tiling(R, &CT, &RP);
-  int st = ensure_mfma_groups(h, R, s);
-  if (st != MUDIFF_OK) return st;
-  const int ngroups = (int)(h->mfma_groups.size() / 2);
-  const int RC = 8 * CT;
-  const size_t lds = ((size_t)4 * kt * RC + (size_t)RP * (4 * kt + 16 * mt - 1)) * 16;
-  dim3 grid(ngroups, (R + RC - 1) / RC), block(256);
-  const int32_t* g = h->mfma_groups_dev;
-  switch (mt) {
-    case 1: hipLaunchKernelGGL(k_apply_mfma<1>, grid, block, lds, s, h->dv, R, x, y, op, active, g, kt, RP, CT); break;
-    case 2: hipLaunchKernelGGL(k_apply_mfma<2>, grid, block, lds, s, h->dv, R, x, y, op, active, g, kt, RP, CT); break;
-    case 3: hipLaunchKernelGGL(k_apply_mfma<3>, grid, block, lds, s, h->dv, R, x, y, op, active, g, kt, RP, CT); break;
-    case 4: hipLaunchKernelGGL(k_apply_mfma<4>, grid, block, lds, s, h->dv, R, x, y, op, active, g, kt, RP, CT); break;
-    default: return fail(MUDIFF_ERR_INVALID, "N_p too large for the MFMA apply");
+  const int RC = 8 * S.c.CT;
+  const size_t lds = ((size_t)4 * kt * RC + (size_t)S.c.RP * (4 * kt + 16 * mt - 1)) * 16;
+  int rc = launch_fill_zero(head, 4, s);
+  if (rc != MUDIFF_OK) return rc;
+  if (S.n_items > 0) {
+    const int per_cu = S.c.threads == 256 ? 4 : 2;
+    const int grid = std::max(1, std::min(S.n_items, per_cu * h->n_cu));
+    const int32_t* it = (const int32_t*)(base + off[1]);
+#define MF_LAUNCH(MTV, TH)                                                                      \
+  hipLaunchKernelGGL((k_apply_mfma<MTV, TH>), dim3(grid), dim3(TH), lds, s, h->dv, R_, x,      \
+                     active, it, S.n_items, head, part, S.blk, S.npad, kt, S.c.RP, S.c.CT)
+    const int R_ = S.R;
+    if (S.c.threads == 256) {
+      switch (mt) {
+        case 1: MF_LAUNCH(1, 256); break;
+        case 2: MF_LAUNCH(2, 256); break;
+        case 3: MF_LAUNCH(3, 256); break;
+        case 4: MF_LAUNCH(4, 256); break;
+        default: return fail(MUDIFF_ERR_INVALID, "N_p too large for the MFMA apply");
+      }
+    } else {
+      switch (mt) {
+        case 1: MF_LAUNCH(1, 512); break;
+        case 2: MF_LAUNCH(2, 512); break;
+        case 3: MF_LAUNCH(3, 512); break;
+        case 4: MF_LAUNCH(4, 512); break;
+        default: return fail(MUDIFF_ERR_INVALID, "N_p too large for the MFMA apply");
+      }
+    }
+#undef MF_LAUNCH
+    HIP_TRY(hipGetLastError());
   }
+  const int64_t total = (int64_t)S.R * h->N_all;
+  hipLaunchKernelGGL(k_apply_mfma_finish, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                     h->dv, S.R, x, y, op, (const cplx*)part, S.blk, S.npad, RC,
+                     (const int32_t*)(base + off[2]), (const int32_t*)(base + off[3]),
+                     (const int32_t*)(base + off[4]), (const int64_t*)(base + off[5]), active);
   HIP_TRY(hipGetLastError());
+  return MUDIFF_OK;
+}
+
+// Largest apply scratch any candidate choice needs for R.
+static size_t mfma_scratch_bytes(mudiff_ctx* h, int R) {
+  auto f = h->mfma_bytes.find(R);
+  if (f != h->mfma_bytes.end()) return f->second;
+  size_t mx = 0;
+  for (const MfmaChoice& c : mfma_candidates(R)) {
+    MfmaSched S;
+    mfma_build(h, R, c, S);
+    size_t off[7];
+    mx = std::max(mx, mfma_scratch_layout(h, S, off));
+  }
+  h->mfma_bytes[R] = mx;
+  return mx;
+}
+
+// Pick the tile choice for R by timing every candidate on x -> y (outputs
+// are overwritten; the inputs only need to be finite), then leave the chosen
+// schedule uploaded at `scratch`.
+static int mfma_autotune(mudiff_ctx* h, int R, const cplx* x, cplx* y, char* scratch,
+                         hipStream_t s) {
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  float best = 0.0f;
+  MfmaChoice bc = mfma_default(R);
+  int rc = MUDIFF_OK;
+  for (const MfmaChoice& c : mfma_candidates(R)) {
+    MfmaSched S;
+    mfma_build(h, R, c, S);
+    if ((rc = mfma_upload(h, S, scratch, s)) != MUDIFF_OK) break;
+    if ((rc = mfma_launch(h, S, x, y, MUDIFF_OP_A, nullptr, s)) != MUDIFF_OK) break;  // warm-up
+    (void)hipEventRecord(e0, s);
+    for (int k = 0; k < 2 && rc == MUDIFF_OK; ++k) rc = mfma_launch(h, S, x, y, MUDIFF_OP_A, nullptr, s);
+    (void)hipEventRecord(e1, s);
+    if (rc != MUDIFF_OK) break;
+    if (hipEventSynchronize(e1) != hipSuccess) {
+      rc = fail(MUDIFF_ERR_DEVICE, "autotune: event synchronisation failed");
+      break;
+    }
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (best == 0.0f || ms < best) {
+      best = ms;
+      bc = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != MUDIFF_OK) return rc;
+  h->mfma_choice[R] = bc;
+  h->mfma_time_ms[R] = best / 2.0f;
+  mfma_build(h, R, bc, h->mfma_sched);
+  return mfma_upload(h, h->mfma_sched, scratch, s);
+}
+
+// Make the schedule for R current and uploaded at `scratch` (autotuning on
+// first use of R when x, y are given, else the default choice).
+static int mfma_prepare(mudiff_ctx* h, int R, const cplx* x, cplx* y, char* scratch,
+                        hipStream_t s) {
+  auto f = h->mfma_choice.find(R);
+  if (f == h->mfma_choice.end()) {
+    if (x && y && h->mfma_tune) return mfma_autotune(h, R, x, y, scratch, s);
+    h->mfma_choice[R] = mfma_default(R);
+    f = h->mfma_choice.find(R);
+  }
+  if (h->mfma_sched.R != R || !(h->mfma_sched.c == f->second)) mfma_build(h, R, f->second, h->mfma_sched);
+  if (h->mfma_sched.dev_base != scratch) return mfma_upload(h, h->mfma_sched, scratch, s);
   return MUDIFF_OK;
 }
 
@@ -705,17 +929,21 @@ int ensure_plan(mudiff_ctx* h, hipStream_t s) {
   return MUDIFF_OK;
 }
 
+// Apply scratch: the partial sums (or the MFMA schedule and partial blocks),
+// then R * M_all counters of the generic kernel.
 size_t apply_scratch_bytes(mudiff_ctx* h, int R) {
+  const size_t counters = align256((size_t)R * h->M_all * 4);
+  if (use_mfma(h, R)) return align256(mfma_scratch_bytes(h, R)) + counters;
   if (h->plan_part < 0) {
     PlanHost H;
     make_plan(h->B, h->idisk.data(), h->N.data(), H);
     h->plan_part = H.part;
   }
-  return align256((size_t)R * h->plan_part * 16) + align256((size_t)R * h->M_all * 4);
+  return align256((size_t)R * h->plan_part * 16) + counters;
 }
 
-int prepare_apply(mudiff_ctx* h, int R, hipStream_t s) {
-  if (use_mfma(h, R)) return ensure_mfma_groups(h, R, s);
+int prepare_apply(mudiff_ctx* h, int R, const cplx* x, cplx* y, cplx* scratch, hipStream_t s) {
+  if (use_mfma(h, R)) return mfma_prepare(h, R, x, y, (char*)scratch, s);
   return ensure_plan(h, s);
 }
 
@@ -723,7 +951,7 @@ int apply_operator_split(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, c
                          int32_t* counters, const int32_t* active, hipStream_t s,
                          bool* pending) {
   *pending = false;
-  if (use_mfma(h, R)) return launch_apply_mfma(h, R, x, y, op, active, s);
+  if (use_mfma(h, R)) return apply_operator(h, R, x, y, op, part, counters, active, s);
   int st = ensure_plan(h, s);
   if (st != MUDIFF_OK) return st;
   const MatvecPlan& P = h->plan;
@@ -743,7 +971,11 @@ int apply_operator_split(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, c
 
 int apply_operator(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, cplx* part,
                    int32_t* counters, const int32_t* active, hipStream_t s) {
-  if (use_mfma(h, R)) return launch_apply_mfma(h, R, x, y, op, active, s);
+  if (use_mfma(h, R)) {
+    int st = mfma_prepare(h, R, nullptr, nullptr, (char*)part, s);  // no-op when current
+    if (st != MUDIFF_OK) return st;
+    return mfma_launch(h, h->mfma_sched, x, y, op, active, s);
+  }
   int st = ensure_plan(h, s);
   if (st != MUDIFF_OK) return st;
   const MatvecPlan& P = h->plan;
@@ -787,6 +1019,11 @@ extern "C" int mudiff_matvec(mudiff_t h, int R, const void* x, void* y, int op, 
   if (ws_bytes < need) return fail(MUDIFF_ERR_NOMEM, "matvec workspace needs " + std::to_string(need) + " bytes");
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)workspace;
+  if (use_mfma(h, R)) {
+    int st = mfma_prepare(h, R, (const cplx*)x, (cplx*)y, w, s);  // autotunes on first use of R
+    if (st != MUDIFF_OK) return st;
+    return mfma_launch(h, h->mfma_sched, (const cplx*)x, (cplx*)y, op, nullptr, s);
+  }
   size_t part_bytes = need - align256((size_t)R * h->M_all * 4);
   int32_t* counters = (int32_t*)(w + part_bytes);  // zero on first use, left zero
   return apply_operator(h, R, (const cplx*)x, (cplx*)y, op, (cplx*)w, counters, nullptr, s);

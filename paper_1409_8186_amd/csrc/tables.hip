@@ -209,7 +209,7 @@ namespace {
 struct Layout {
   size_t off_cx, off_cy, off_a, off_kd, off_N, off_inst, off_moff, off_dtab, off_idisk, off_imode,
       off_ipair, off_toff, off_t, off_Jd, off_Hd, off_sJ, off_invSH, off_Ldiag, off_udisk, off_sched,
-      off_lt, off_ltoff, off_mfg;
+      off_lt, off_ltoff;
   size_t sched_bytes, total;
 };
 
@@ -248,7 +248,7 @@ Layout make_layout(int B, const int64_t* disk_off, const int32_t* n_modes, int64
   const int64_t lt = lane_layout(B, disk_off, n_modes, &lane_N, nullptr);
   L.off_lt = take(lt * 16);
   L.off_ltoff = take(M * 8);
-  L.off_mfg = take(M * 8);
+
   L.total = o;
   return L;
 }
@@ -397,8 +397,12 @@ extern "C" int mudiff_tables(int B, const int64_t* disk_off, const double* cente
   v.lt = (cplx*)(base + L.off_lt);
   v.ltoff = (int64_t*)(base + L.off_ltoff);
   lane_layout(B, disk_off, n_modes, &v.lane_N, &h->ltoff);
-  h->mfma_groups_dev = (int32_t*)(base + L.off_mfg);
-  h->mfma_groups_bytes = (size_t)M * 8;
+  {
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+      h->n_cu = ncu;
+  }
   h->sched_base = base + L.off_sched;
   h->sched_bytes = L.sched_bytes;
 

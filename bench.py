@@ -117,67 +117,113 @@ def cpu_baseline(cl, n_iter_gpu):
     }
 
 
+def _segmented_gmres(P, betas, restart, tol, label, seg_cycles=1, max_segments=200):
+    """GMRES(restart) to tol in segments of seg_cycles restart cycles, each
+    warm-started from the last (a segment boundary falls on a restart, so the
+    iterates are those of one continuous run); progress goes to stderr."""
+    import torch
+    rho, its, t0 = None, None, time.perf_counter()
+    for seg in range(max_segments):
+        rho, flag, relres, iters, _ = P.gmres(betas=betas, restart=restart, tol=tol,
+                                              maxit=restart * seg_cycles, x0=rho)
+        it = iters.cpu()
+        its = it if its is None else its + it
+        n_un = int((flag != 0).sum())
+        print(f"[{label}] segment {seg}: {time.perf_counter() - t0:.2f} s, unconverged columns "
+              f"{n_un}, max relres {float(relres.max()):.2e}", file=sys.stderr, flush=True)
+        if n_un == 0:
+            break
+    torch.cuda.synchronize()
+    return rho, flag, its, time.perf_counter() - t0
+
+
 def other_workload(args):
-    """Documentation runs of the batched and differentiation workloads."""
+    """Documentation runs of the batched and differentiation workloads: the
+    batched apply rate against the FP64 MFMA roofline, the batched solve or
+    gradient, and the same work done one instance at a time on a sample."""
     import numpy as np
     import torch
 
     import synth
     from paper_1409_8186_amd import Problem
-    base = {"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+    base = {"n_gpus": 1, "steps": 1, "warmup": 1, "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "complex128 (f64)",
             "data": "synthetic (seeded disk clusters)"}
+
+    def time_apply(P, R, n, reps=5):
+        x = torch.randn(R * n, dtype=torch.complex128, device="cuda")
+        y = P.empty(R)
+        P.matvec(x, R=R, op=1, out=y)       # first call of this R autotunes the tile
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(reps):
+            P.matvec(x, R=R, op=1, out=y)
+        ev1.record()
+        ev1.synchronize()
+        return ev0.elapsed_time(ev1) / 1e3 / reps
+
+    def mfma_roofline(flops, t, cfg):
+        return {"bound": "mfma", "achieved": flops / t / 1e12, "peak": 78.6, "unit": "TFLOP/s",
+                "frac": flops / t / 1e12 / 78.6, "traffic": None,
+                "kernel": "k_apply_mfma + k_apply_mfma_finish", "tile": cfg,
+                "algorithmic_flops_per_launch": flops}
+
     if args.workload == "multi_rhs":
         cl = synth.multi_rhs()
         R = len(cl.betas)
         P = Problem.from_cluster(cl)
-        x = torch.randn(R * cl.n_tot, dtype=torch.complex128, device="cuda")
-        y = P.empty(R)
-        P.matvec(x, R=R, op=1, out=y)
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record()
-        for _ in range(args.steps):
-            P.matvec(x, R=R, op=1, out=y)
-        ev1.record()
-        ev1.synchronize()
-        t = ev0.elapsed_time(ev1) / 1e3 / args.steps
+        t = time_apply(P, R, cl.n_tot, reps=3)
         flops = algorithmic_flops(cl.n_modes, R)
-        return {**base, "metric": "complex unknown·RHS matvecs/s", "value": cl.n_tot * R / t,
-                "unit": "complex unknown·RHS matvecs/s", "ms_per_step": t * 1e3,
-                "config": {"workload": "multi_rhs: M=1000, a~U[0.3,1], [0,150]^2, k=10, "
-                                       "N_p=ceil(10a)+10, R=256, one operator apply per step",
-                           "n_unknowns": cl.n_tot, "R": R},
-                "roofline": {"bound": "mfma", "achieved": flops / t / 1e12, "peak": 78.6,
-                             "unit": "TFLOP/s", "frac": flops / t / 1e12 / 78.6, "traffic": None,
-                             "kernel": "k_apply_mfma"}}
+        out = {**base, "metric": "complex unknown·RHS matvecs/s", "value": cl.n_tot * R / t,
+               "unit": "complex unknown·RHS matvecs/s", "ms_per_step": t * 1e3,
+               "config": {"workload": "multi_rhs: M=1000, a~U[0.3,1], [0,150]^2, k=10, "
+                                      "N_p=ceil(10a)+10, R=256, one operator apply per step",
+                          "n_unknowns": cl.n_tot, "R": R},
+               "roofline": mfma_roofline(flops, t, P.apply_config(R))}
+        if args.solve:
+            rho, flag, its, t_s = _segmented_gmres(P, cl.betas[None, :], 50, 1e-8, "multi_rhs",
+                                                   seg_cycles=10)
+            out["time_to_1e8_s"] = t_s
+            out["gmres_iters_max"] = int(its.max())
+            out["all_converged"] = bool((flag == 0).all())
+        return out
     if args.workload == "uneven":
         insts = synth.uneven_instances()
         R = 8
         betas = np.stack([c.betas for c in insts])
-        th = insts[0].thetas
-
-        def step():
-            P = Problem.from_clusters(insts)
-            rho, flag, relres, iters, _ = P.gmres(betas=betas, restart=300, tol=1e-8,
-                                                  maxit=20000)
-            P.farfield(rho, th, R=R)
-            return flag, iters
-        step()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            flag, iters = step()
-        torch.cuda.synchronize()
-        t = (time.perf_counter() - t0) / args.steps
-        it = iters.cpu().numpy()
-        work = sum(c.n_tot * R for c in insts)
-        return {**base, "metric": "time-to-1e-8 GMRES solve (all instances)", "value": t,
-                "unit": "s", "higher_is_better": False, "ms_per_step": t * 1e3,
+        P = Problem.from_clusters(insts)
+        n = sum(c.n_tot for c in insts)
+        t_app = time_apply(P, R, n, reps=3)
+        flops = sum(algorithmic_flops(c.n_modes, R) for c in insts)
+        rho, flag, its, t_s = _segmented_gmres(P, betas, 300, 1e-8, "uneven batched")
+        it = its.numpy().reshape(len(insts), R)
+        # the same solves one instance at a time, on a seeded sample
+        rng = np.random.default_rng(11)
+        sample = sorted(rng.choice(len(insts), 16, replace=False).tolist())
+        t1 = 0.0
+        for b in sample:
+            Pb = Problem.from_cluster(insts[b])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Pb.gmres(betas=betas[b:b + 1], restart=300, tol=1e-8, maxit=20000)
+            torch.cuda.synchronize()
+            t1 += time.perf_counter() - t0
+            Pb.close()
+        per_inst_single = t1 / len(sample)
+        return {**base, "metric": "time-to-1e-8 GMRES solve (all instances)", "value": t_s,
+                "unit": "s", "higher_is_better": False, "ms_per_step": t_s * 1e3,
                 "config": {"workload": "uneven: 512 seeded instances, M~U{10..200}, k~U[1,20], "
-                                       "N_p=ceil(k a)+8, R=8, GMRES(300) to 1e-8, one launch per "
-                                       "operator apply", "unknowns_x_rhs": work,
+                                       "N_p=ceil(k a)+8, R=8, GMRES(300) to 1e-8, all instances "
+                                       "in each launch", "unknowns_x_rhs": n * R,
                            "iters_min": int(it.min()), "iters_max": int(it.max()),
-                           "all_converged": bool((flag == 0).all())}}
+                           "all_converged": bool((flag == 0).all())},
+                "apply_ms": t_app * 1e3,
+                "roofline": mfma_roofline(flops, t_app, P.apply_config(R)),
+                "one_at_a_time": {"sample_instances": len(sample),
+                                  "mean_s_per_instance": per_inst_single,
+                                  "extrapolated_s_all": per_inst_single * len(insts),
+                                  "batched_speedup": per_inst_single * len(insts) / t_s}}
     pairs = synth.differentiation()
     bases = [b for b, _ in pairs]
     betas = np.stack([b.betas for b in bases])
@@ -186,28 +232,43 @@ def other_workload(args):
     tgt_cls = [t for _, t in pairs]
     PT = Problem.from_clusters(tgt_cls)
     rho_t, fl, _, _, _ = PT.gmres(betas=betas, restart=50, tol=1e-10, maxit=20000)
-    target = PT.farfield(rho_t, th, R=betas.shape[1]).reshape(-1)
+    target = PT.farfield(rho_t, th, R=betas.shape[1]).reshape(betas.shape[0], -1)
     PT.close()
 
-    def step():
-        P = Problem.from_clusters(bases)
-        out = P.grad(betas, th, target, restart=50, tol=1e-8, maxit=20000)
+    def step(idx):
+        P = Problem.from_clusters([bases[i] for i in idx])
+        out = P.grad(betas[idx], th, target[idx].reshape(-1), restart=50, tol=1e-8, maxit=20000)
         P.close()
         return out
-    step()
+    allidx = list(range(len(bases)))
+    step(allidx)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
+    step(allidx)
     torch.cuda.synchronize()
-    t = (time.perf_counter() - t0) / args.steps
+    t = time.perf_counter() - t0
+    t1 = 0.0
+    for i in range(4):                      # one configuration at a time, sample of 4
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        step([i])
+        torch.cuda.synchronize()
+        t1 += time.perf_counter() - s0
+    P = Problem.from_clusters(bases)
+    n = sum(c.n_tot for c in bases)
+    t_app = time_apply(P, betas.shape[1], n, reps=3)
+    flops = sum(algorithmic_flops(c.n_modes, betas.shape[1]) for c in bases)
     return {**base, "metric": "adjoint grads/s", "value": len(bases) / t, "unit": "gradients/s",
             "ms_per_step": t * 1e3,
             "config": {"workload": "differentiation: 32 configs, M=100, a~U[0.4,0.8], [0,40]^2, "
                                    "k=8, N_p=ceil(8a)+8, 64 incidences x 64 receivers, forward + "
                                    "adjoint GMRES(50) to 1e-8, gradient w.r.t. 200 center "
                                    "coordinates, 100 radii and k per config",
-                       "configs_per_step": len(bases)}}
+                       "configs_per_step": len(bases)},
+            "apply_ms": t_app * 1e3,
+            "roofline": mfma_roofline(flops, t_app, P.apply_config(betas.shape[1])),
+            "one_at_a_time": {"sample_configs": 4, "grads_per_s": 4 / t1,
+                              "batched_speedup": (len(bases) / t) / (4 / t1)}}
 
 
 def main():
@@ -222,6 +283,8 @@ def main():
     ap.add_argument("--workload", default="one_rhs",
                     choices=["one_rhs", "multi_rhs", "uneven", "differentiation"],
                     help="one_rhs (default bench line) or a documentation run of another workload")
+    ap.add_argument("--solve", action="store_true",
+                    help="with --workload multi_rhs: also time the GMRES(50) solve to 1e-8")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="profiling mode: one device-to-device copy of BYTES (counter calibration)")
     args = ap.parse_args()

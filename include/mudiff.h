@@ -142,6 +142,21 @@ size_t mudiff_matvec_workspace_size(mudiff_t h, int R);
 int mudiff_matvec(mudiff_t h, int R, const void* x, void* y, int op,
                   void* workspace, size_t ws_bytes, void* stream);
 
+/* Kernel configuration of the R-column operator apply, as chosen on this
+ * handle (host outputs; any pointer may be NULL):
+ *   kind       0 one lane per pair (uniform N_p <= 12, R < 8), 1 FP64-MFMA
+ *              work queue (R >= 8, N_p <= 31), 2 generic LDS-staged kernel
+ *   ct, rp     MFMA tile: 8*ct right-hand sides x rp row disks per work item
+ *   qs         MFMA column-disk segment length (0: whole instance)
+ *   threads    MFMA workgroup size
+ *   ms         timed duration of one apply when the MFMA tile was autotuned
+ *              (the first mudiff_matvec / mudiff_gmres / mudiff_grad with this
+ *              R times every candidate on the real data), else 0
+ * Fields that do not apply to `kind` are set to 0.  Before the first call
+ * with this R, the MFMA fields hold the default tile. */
+int mudiff_apply_config(mudiff_t h, int R, int* kind, int* ct, int* rp, int* qs, int* threads,
+                        float* ms);
+
 /* Plane-wave right-hand side (Prop. 4) for R incidence angles per instance.
  *   beta       device [B][R] angles (radians), beta_hat = (cos beta, sin beta)
  *   out        device complex128 [B][R][N_b]: U (precond = 0) or the GMRES

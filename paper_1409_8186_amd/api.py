@@ -145,6 +145,17 @@ class Problem:
         L.check(self.lib.mudiff_matvec(self.h, R, _p(x), _p(y), op, _p(ws), ws.numel(), _stream()))
         return y
 
+    def apply_config(self, R: int = 1) -> dict:
+        """Kernel configuration of the R-column apply on this handle
+        (kind: lane / mfma / generic; MFMA tile and autotuned time)."""
+        vals = [ctypes.c_int(0) for _ in range(5)]
+        ms = ctypes.c_float(0.0)
+        L.check(self.lib.mudiff_apply_config(self.h, R, *[ctypes.byref(v) for v in vals],
+                                              ctypes.byref(ms)))
+        kind, ct, rp, qs, th = (v.value for v in vals)
+        return {"kind": ["lane", "mfma", "generic"][kind], "ct": ct, "rp": rp, "qs": qs,
+                "threads": th, "tuned_ms": ms.value}
+
     def rhs(self, betas, precond: bool = False) -> torch.Tensor:
         """betas: [B, R] incidence angles."""
         b = self._f64(betas).reshape(self.B, -1)

@@ -1028,3 +1028,33 @@ extern "C" int mudiff_matvec(mudiff_t h, int R, const void* x, void* y, int op, 
   int32_t* counters = (int32_t*)(w + part_bytes);  // zero on first use, left zero
   return apply_operator(h, R, (const cplx*)x, (cplx*)y, op, (cplx*)w, counters, nullptr, s);
 }
+
+extern "C" int mudiff_apply_config(mudiff_t h, int R, int* kind, int* ct, int* rp, int* qs,
+                                   int* threads, float* ms) {
+  if (!h) return fail(MUDIFF_ERR_INVALID, "NULL handle");
+  if (R < 1) return fail(MUDIFF_ERR_INVALID, "R < 1");
+  int k = 2, c = 0, r = 0, q = 0, t = 0;
+  float tm = 0.0f;
+  if (use_mfma(h, R)) {
+    k = 1;
+    auto f = h->mfma_choice.find(R);
+    const MfmaChoice ch = f != h->mfma_choice.end() ? f->second : mfma_default(R);
+    c = ch.CT;
+    r = ch.RP;
+    q = ch.QS;
+    t = ch.threads;
+    auto g = h->mfma_time_ms.find(R);
+    if (g != h->mfma_time_ms.end()) tm = g->second;
+  } else {
+    PlanHost H;
+    make_plan(h->B, h->idisk.data(), h->N.data(), H);
+    k = H.lane ? 0 : 2;
+  }
+  if (kind) *kind = k;
+  if (ct) *ct = c;
+  if (rp) *rp = r;
+  if (qs) *qs = q;
+  if (threads) *threads = t;
+  if (ms) *ms = tm;
+  return MUDIFF_OK;
+}

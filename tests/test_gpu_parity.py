@@ -243,6 +243,27 @@ def test_gmres_long_restart_matches_oracle(P):
     assert np.linalg.norm(A @ x - f) / np.linalg.norm(f) < 2e-10
 
 
+def test_gmres_weak_coupling_second_pass(P):
+    """Six far-apart disks: A = I + K with small K, so each new Krylov direction
+    cancels most of A v_j and the second Gram-Schmidt pass runs on most steps
+    (8 of 12 in a CPU replay of the device algorithm).  Solution vs LU and the
+    iteration count vs the oracle's MGS GMRES."""
+    centers = np.array([[0, 0], [40, 3], [-35, 20], [10, -45], [60, 50], [-50, -40]], float)
+    radii = np.array([0.3, 0.5, 0.4, 0.35, 0.6, 0.45])
+    cl = synth.Cluster(centers, radii, np.array([4, 6, 5, 5, 7, 6]), 2.0)
+    say("gmres weak coupling")
+    pr = P.from_cluster(cl)
+    rho, flag, relres, iters, _ = pr.gmres(betas=[[0.3]], restart=30, tol=1e-12, maxit=200)
+    assert int(flag[0]) == 0 and float(relres[0]) <= 1e-12
+    ref = _lu(cl, [0.3])[0]
+    assert rel(rho.cpu().numpy(), ref) < 1e-10
+    L, A = _dense(cl)
+    D = operator.efie_diagonal(cl.radii, cl.n_modes, cl.k)
+    U = rhs.planewave(cl.centers, cl.radii, cl.n_modes, cl.k, [0.3])[0]
+    _, fl, _, it_ref, _ = solve.gmres(lambda v: A @ v, -U / D, 30, 1e-12, 200)
+    assert fl == 0 and abs(int(iters[0]) - it_ref) <= 2, (int(iters[0]), it_ref)
+
+
 def test_gmres_batched_lockstep(P):
     """B = 3 uneven instances x R = 3 angles in one solve; every column equals LU."""
     cls = [_uneven(40 + i, M=4 + 3 * i) for i in range(3)]

@@ -3,13 +3,13 @@
 // right-hand side); all columns share each operator application.
 //
 // Orthogonalisation is classical Gram-Schmidt with selective
-// reorthogonalisation: one pass h = V^H w, and a second pass only when
-// ||w - V h|| < eta ||w|| (cancellation; eta = GS_REORTH_ETA).  Without the
-// second pass the new vector's loss of orthogonality is at most about
-// eps / eta, and h_{j+1,j}^2 = ||w||^2 - ||h||^2 is accurate to about
-// eps / eta^2; eta = 1/sqrt(2) (the Daniel-Gragg-Kaufman-Stewart value) would
-// add the pass on about a third of the steps of the one-RHS workload with no
-// change in the iterates' convergence.  The
+// reorthogonalisation (the Daniel-Gragg-Kaufman-Stewart test): one pass
+// h = V^H w, and a second pass only when ||w - V h|| < ||w|| / sqrt(2)
+// (cancellation), which keeps the basis orthogonal to working precision.  A
+// looser threshold (0.1) skips the second pass on cycles of 50 steps without
+// changing convergence, but over a 170-step cycle of an ill-conditioned
+// low-frequency cluster the one-pass basis loses orthogonality and GMRES
+// stalls.  The
 // Hessenberg column, the Givens rotations and the residual estimate
 // |g_{j+1}| / ||f|| are updated on the device, so the host only synchronises to
 // test for the end of a cycle.
@@ -27,7 +27,7 @@
 #define GS_THREADS 256
 #define GS_WAVES (GS_THREADS / 64)
 #define GS_BATCH 4
-#define GS_REORTH_ETA 0.1
+#define GS_REORTH_ETA 0.70710678118654752  // 1 / sqrt(2)
 
 enum { ST_RUN = 0, ST_CONV = 1, ST_BREAK = 2, ST_MAXIT = 3 };
 

@@ -332,6 +332,24 @@ typedef double mf_d4 __attribute__((ext_vector_type(4)));
 #define MF_MAXZ 2048   // staged Z values per column disk: 4 ktmax (<= 64) x RC (<= 32)
 #define MF_MAXT 1016   // staged symbol values: RP (<= 8) x TL (<= 64 + 63)
 
+// K row tiles of one wave against one staged column disk: KT k-steps of 4,
+// two real MFMAs per tile and step (Re T, Im T against [Re Z | Im Z]).
+template <int K, int MT>
+__device__ __forceinline__ void mf_tiles(const cplx* trow, const cplx* zcol, int RC, int j, int kq,
+                                         int KT, mf_d4* acc1, mf_d4* acc2) {
+  for (int kk = 0; kk < KT; ++kk) {
+    const int n = 4 * kk + kq;
+    const cplx zz = zcol[n * RC];
+    const double bv = j < 8 ? zz.x : zz.y;
+#pragma unroll
+    for (int mt = 0; mt < K; ++mt) {
+      const cplx t = trow[n - (16 * mt + j) + 16 * MT - 1];  // A[i = lane % 16][k = kq]
+      acc1[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(t.x, bv, acc1[mt], 0, 0, 0);
+      acc2[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(t.y, bv, acc2[mt], 0, 0, 0);
+    }
+  }
+}
+
 template <int MT, int THREADS>  // row tiles of 16: n_p <= 16 MT
 __global__ __launch_bounds__(THREADS) void k_apply_mfma(
     DevView v, int R, const cplx* __restrict__ x, const int32_t* __restrict__ active,
@@ -382,6 +400,7 @@ __global__ __launch_bounds__(THREADS) void k_apply_mfma(
     const int64_t i0 = v.imode[b];
     const int p = p0 + row;
     const bool row_ok = row < rp;
+    const int mtp = row_ok ? (2 * v.N[p] + 1 + 15) >> 4 : 0;  // row tiles of this row disk
     bool wave_active = row_ok;
     if (wave_active) {
       wave_active = false;
@@ -441,15 +460,14 @@ __global__ __launch_bounds__(THREADS) void k_apply_mfma(
       if (q + 1 < qe) gather(q + 1);  // in flight during the MFMAs
       if (wave_active && q != p) {
         const cplx* trow = tl + row * TL;
-        for (int kk = 0; kk < KT; ++kk) {
-          const int n = 4 * kk + kq;
-          const cplx zz = zl[n * RC + ctile * 8 + (j & 7)];
-          const double bv = j < 8 ? zz.x : zz.y;
-#pragma unroll
-          for (int mt = 0; mt < MT; ++mt) {
-            const cplx t = trow[n - (16 * mt + j) + 16 * MT - 1];  // A[i = lane % 16][k = kq]
-            acc1[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(t.x, bv, acc1[mt], 0, 0, 0);
-            acc2[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(t.y, bv, acc2[mt], 0, 0, 0);
+        const cplx* zcol = zl + ctile * 8 + (j & 7);
+        // only the row tiles of this row disk (wave-uniform count)
+        if (mtp >= MT) mf_tiles<MT, MT>(trow, zcol, RC, j, kq, KT, acc1, acc2);
+        else if constexpr (MT >= 2) {
+          if (mtp == MT - 1) mf_tiles<MT - 1, MT>(trow, zcol, RC, j, kq, KT, acc1, acc2);
+          else if constexpr (MT >= 3) {
+            if (mtp == MT - 2) mf_tiles<MT - 2, MT>(trow, zcol, RC, j, kq, KT, acc1, acc2);
+            else if constexpr (MT >= 4) mf_tiles<MT - 3, MT>(trow, zcol, RC, j, kq, KT, acc1, acc2);
           }
         }
       }

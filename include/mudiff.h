@@ -157,6 +157,13 @@ int mudiff_matvec(mudiff_t h, int R, const void* x, void* y, int op,
 int mudiff_apply_config(mudiff_t h, int R, int* kind, int* ct, int* rp, int* qs, int* threads,
                         float* ms);
 
+/* Fixes the MFMA tile of the R-column apply on this handle instead of timing
+ * the candidates (ct in {1,2,4} with ct <= max(1, ceil(R/8)), rp = waves/ct
+ * with waves in {4, 8} and threads = 64 * waves, qs in {0, 32}).  Returns
+ * MUDIFF_ERR_INVALID for a tile outside that set or when the R-column apply
+ * does not run on MFMA.  Takes effect at the next call with this R. */
+int mudiff_set_apply_config(mudiff_t h, int R, int ct, int rp, int qs, int threads);
+
 /* Plane-wave right-hand side (Prop. 4) for R incidence angles per instance.
  *   beta       device [B][R] angles (radians), beta_hat = (cos beta, sin beta)
  *   out        device complex128 [B][R][N_b]: U (precond = 0) or the GMRES

@@ -26,6 +26,7 @@ SIGNATURES = {
     "mudiff_disk_tables": (_i32, [_vp, _vp, _vp, _vp]),
     "mudiff_pair_tables": (_i32, [_vp, _vp, _i64p, _vp]),
     "mudiff_apply_config": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "mudiff_set_apply_config": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32]),
     "mudiff_matvec_workspace_size": (_sz, [_vp, _i32]),
     "mudiff_matvec": (_i32, [_vp, _i32, _vp, _vp, _i32, _vp, _sz, _vp]),
     "mudiff_rhs": (_i32, [_vp, _i32, _vp, _vp, _i32, _vp]),

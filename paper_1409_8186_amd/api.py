@@ -156,6 +156,10 @@ class Problem:
         return {"kind": ["lane", "mfma", "generic"][kind], "ct": ct, "rp": rp, "qs": qs,
                 "threads": th, "tuned_ms": ms.value}
 
+    def set_apply_config(self, R: int, ct: int, rp: int, qs: int, threads: int) -> None:
+        """Fix the MFMA tile of the R-column apply (no autotuning for this R)."""
+        L.check(self.lib.mudiff_set_apply_config(self.h, R, ct, rp, qs, threads))
+
     def rhs(self, betas, precond: bool = False) -> torch.Tensor:
         """betas: [B, R] incidence angles."""
         b = self._f64(betas).reshape(self.B, -1)

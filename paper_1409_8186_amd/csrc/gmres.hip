@@ -80,8 +80,20 @@ __device__ __forceinline__ void decode_chunk(const GState& s, int gidx, int* col
 // the residual estimate |g_{j+1}| / ||f|| and the stopping test.  hl, csl, snl
 // are the column and the rotations 0..j-1 staged in LDS: the rotation chain
 // carries one value in registers, so no step waits on a global load.
+// Values of column c that the Arnoldi step reads from global memory, loaded at
+// the start of the kernel so that their latency overlaps the reductions.
+struct ArnoldiPre {
+  cplx gj;     // g_j
+  int it;      // inner iterations so far
+  double nf;   // ||f||
+};
+
+__device__ __forceinline__ ArnoldiPre arnoldi_preload(const GState& s, int c, int j) {
+  return ArnoldiPre{s.g[(int64_t)c * (s.m + 1) + j], s.iters[c], s.normf[c]};
+}
+
 __device__ void arnoldi_step(const GState& s, int c, int j, const cplx* hl, const double* csl,
-                             const cplx* snl, double hn) {
+                             const cplx* snl, double hn, const ArnoldiPre& pre) {
   const int m1 = s.m + 1;
   cplx* hj = s.H + (int64_t)c * m1 * s.m + (int64_t)j * m1;  // column j
   cplx cur = hl[0];
@@ -112,12 +124,13 @@ __device__ void arnoldi_step(const GState& s, int c, int j, const cplx* hl, cons
   s.sn[(int64_t)c * s.m + j] = sr;
   hj[j] = cadd(cscale(aa, cr), cscale(sr, hn));
   cplx* gc = s.g + (int64_t)c * m1;
-  const cplx gj = gc[j];
-  gc[j + 1] = cmul(cscale(cconj(sr), -1.0), gj);
+  const cplx gj = pre.gj;
+  const cplx gj1 = cmul(cscale(cconj(sr), -1.0), gj);
+  gc[j + 1] = gj1;
   gc[j] = cscale(gj, cr);
-  const int it = s.iters[c] + 1;
+  const int it = pre.it + 1;
   s.iters[c] = it;
-  const double rel = sqrt(cabs2(gc[j + 1])) / s.normf[c];
+  const double rel = sqrt(cabs2(gj1)) / pre.nf;
   if (s.resvec) s.resvec[(int64_t)c * (s.maxit + 1) + it] = rel;
   s.jdone[c] = j + 1;
   const bool finite = isfinite(rel) && isfinite(hn);
@@ -230,24 +243,31 @@ __device__ __forceinline__ cplx project_out(const GState& s, int j, const cplx* 
   return v;
 }
 
-// Chunk 0 of column c: stage the previous rotations next to h (LDS) when they
-// fit, then the Arnoldi/Givens step.
-__device__ void column_step(const GState& s, int c, int j, cplx* hl, double hn) {
-  const int tid = threadIdx.x;
-  __syncthreads();  // every thread has read what it needs beyond hl[j]
-  const bool fits = 2 * j + 1 + (j + 1) / 2 <= 1024;
-  const double* csl = s.cs + (int64_t)c * s.m;
-  const cplx* snl = s.sn + (int64_t)c * s.m;
+// Chunk 0 of column c, at the start of the kernel: the previous rotations go
+// to LDS behind the slots 0..j+1 that the column sums will fill (when they fit)
+// and thread 0 loads what the Arnoldi step reads from global memory.
+__device__ bool stage_rotations(const GState& s, int c, int j, cplx* hl) {
+  const bool fits = 2 * j + 2 + (j + 1) / 2 <= MUDIFF_MAX_RESTART + 1;
   if (fits) {
-    for (int i = tid; i < j; i += GS_THREADS) {
-      hl[j + 1 + i] = snl[i];
-      reinterpret_cast<double*>(hl + 2 * j + 1)[i] = csl[i];
+    const double* csg = s.cs + (int64_t)c * s.m;
+    const cplx* sng = s.sn + (int64_t)c * s.m;
+    for (int i = threadIdx.x; i < j; i += GS_THREADS) {
+      hl[j + 2 + i] = sng[i];
+      reinterpret_cast<double*>(hl + 2 * j + 2)[i] = csg[i];
     }
-    __syncthreads();
-    snl = hl + j + 1;
-    csl = reinterpret_cast<const double*>(hl + 2 * j + 1);
   }
-  if (tid == 0) arnoldi_step(s, c, j, hl, csl, snl, hn);
+  return fits;  // visible to thread 0 after the next barrier
+}
+
+// Chunk 0 of column c: the Arnoldi/Givens step on h = hl[0..j].
+__device__ void column_step(const GState& s, int c, int j, const cplx* hl, double hn, bool staged,
+                            const ArnoldiPre& pre) {
+  __syncthreads();  // hl and the staged rotations complete
+  if (threadIdx.x != 0) return;
+  const double* csl = staged ? reinterpret_cast<const double*>(hl + 2 * j + 2)
+                             : s.cs + (int64_t)c * s.m;
+  const cplx* snl = staged ? hl + j + 2 : s.sn + (int64_t)c * s.m;
+  arnoldi_step(s, c, j, hl, csl, snl, hn, pre);
 }
 
 // Chunk partial sums of an operator apply still to be added (one-lane-per-pair
@@ -314,12 +334,18 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs_update(GState s, int j) {
   if (!s.inner[c]) return;
   const int m1 = s.m + 1;
   const int nck = s.ckc[c];
+  const bool first_chunk = blockIdx.x == s.ckf[c];
+  bool staged = false;
+  ArnoldiPre pre{};
+  if (first_chunk) {
+    staged = stage_rotations(s, c, j, hl);
+    if (threadIdx.x == 0) pre = arnoldi_preload(s, c, j);
+  }
   const double hsq = column_sums(s.P1 + (int64_t)s.ckf[c] * m1, m1, nck, j + 2, s.m, j + 1, hl, sred);
   const double nw = hl[j + 1].x;
   const double hn2 = nw - hsq;
   // ||w - V h||^2 <= eta^2 ||w||^2 (or not finite): second pass
   const bool second = !(hn2 > GS_REORTH_ETA * GS_REORTH_ETA * nw);
-  const bool first_chunk = blockIdx.x == s.ckf[c];
   cplx* w = s.V + (int64_t)(j + 1) * s.NT + o;
   const cplx* vr0 = s.V + o;
   if (!second) {
@@ -329,7 +355,7 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs_update(GState s, int j) {
       w[r] = cscale(project_out(s, j, vr0 + r, w[r], hl), inv);
     if (first_chunk) {
       if (threadIdx.x == 0) s.reorth[c] = 0;
-      column_step(s, c, j, hl, hn);
+      column_step(s, c, j, hl, hn, staged, pre);
     }
     return;
   }
@@ -362,6 +388,14 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs_reorth(GState s, int j) {
   if (!s.inner[c] || !s.reorth[c]) return;
   const int m1 = s.m + 1;
   const int nck = s.ckc[c];
+  const bool first_chunk = blockIdx.x == s.ckf[c];
+  bool staged = false;
+  ArnoldiPre pre{};
+  if (first_chunk) {
+    staged = stage_rotations(s, c, j, hl);
+    if (threadIdx.x == 0) pre = arnoldi_preload(s, c, j);
+    (void)column_sums(s.P1 + (int64_t)s.ckf[c] * m1, m1, nck, j + 1, -1, 0, hl, sred);
+  }
   const double h2sq =
       column_sums(s.P2 + (int64_t)s.ckf[c] * m1, m1, nck, j + 2, s.m, j + 1, h2l, sred);
   const double hn2 = h2l[j + 1].x - h2sq;
@@ -371,11 +405,9 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs_reorth(GState s, int j) {
   const cplx* vr0 = s.V + o;
   for (int r = threadIdx.x; r < len; r += GS_THREADS)
     w[r] = cscale(project_out(s, j, vr0 + r, w[r], h2l), inv);
-  if (blockIdx.x != s.ckf[c]) return;
-  (void)column_sums(s.P1 + (int64_t)s.ckf[c] * m1, m1, nck, j + 1, -1, 0, hl, sred);
+  if (!first_chunk) return;
   for (int i = threadIdx.x; i <= j; i += GS_THREADS) hl[i] = cadd(hl[i], h2l[i]);
-  __syncthreads();
-  column_step(s, c, j, hl, hn);
+  column_step(s, c, j, hl, hn, staged, pre);
 }
 
 // Chunked per-column sum of |src|^2: partials into P1 slot 0 (running columns

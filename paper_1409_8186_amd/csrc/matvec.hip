@@ -1076,3 +1076,17 @@ extern "C" int mudiff_apply_config(mudiff_t h, int R, int* kind, int* ct, int* r
   if (ms) *ms = tm;
   return MUDIFF_OK;
 }
+
+extern "C" int mudiff_set_apply_config(mudiff_t h, int R, int ct, int rp, int qs, int threads) {
+  if (!h) return fail(MUDIFF_ERR_INVALID, "NULL handle");
+  if (R < 1) return fail(MUDIFF_ERR_INVALID, "R < 1");
+  if (!use_mfma(h, R)) return fail(MUDIFF_ERR_INVALID, "this apply does not run on MFMA");
+  const MfmaChoice want{ct, rp, qs, threads};
+  for (const MfmaChoice& c : mfma_candidates(R))
+    if (c == want) {
+      h->mfma_choice[R] = want;
+      h->mfma_time_ms.erase(R);
+      return MUDIFF_OK;
+    }
+  return fail(MUDIFF_ERR_INVALID, "MFMA tile not among the candidates");
+}

@@ -359,6 +359,56 @@ def test_matvec_multi_rhs(P, R):
             assert rel(Y.cpu().numpy(), X @ M_.T) < 1e-12, (op, rel(Y.cpu().numpy(), X @ M_.T))
 
 
+def _mfma_candidates(R):
+    out = []
+    ctmax = max(1, min(4, (R + 7) // 8))
+    for waves in (4, 8):
+        for ct in (1, 2, 4):
+            if ct > ctmax and ct > 1:
+                continue
+            for qs in (0, 32):
+                out.append((ct, waves // ct, qs, 64 * waves))
+    return out
+
+
+@pytest.mark.parametrize("R", [8, 19])
+def test_matvec_every_mfma_tile(P, R):
+    """Every tile the autotuner may pick, forced in turn, on uneven instances
+    (non-uniform N_p from 5 to 26, so that rows need one to four 16-row tiles;
+    M up to 40, so that 32-disk segments split rows; a ragged RHS count): each
+    equals the dense oracle apply."""
+    cls = [synth.small_random(80 + i, M, 0.3, 1.0, 3.0 * math.sqrt(M), 0.1, 8.0, 6)
+           for i, M in enumerate((40, 7, 33))]
+    cls.append(synth.small_random(83, 12, 0.1, 1.5, 14.0, 0.1, 12.0, 8))  # n_p from 19 to 53
+    say("every MFMA tile R", R)
+    pr = P.from_clusters(cls)
+    rng = np.random.default_rng(90 + R)
+    Xs = [rng.normal(size=(R, c.n_tot)) + 1j * rng.normal(size=(R, c.n_tot)) for c in cls]
+    refs = [(_dense(c)[1] @ X.T).T for c, X in zip(cls, Xs)]
+    x = pr.pack(Xs)
+    for ct, rp, qs, th in _mfma_candidates(R):
+        pr.set_apply_config(R, ct, rp, qs, th)
+        cfg = pr.apply_config(R)
+        assert (cfg["kind"], cfg["ct"], cfg["rp"], cfg["qs"], cfg["threads"]) == ("mfma", ct, rp, qs, th)
+        y = pr.matvec(x, R=R, op=1)
+        for Y, ref in zip(pr.split(y, R), refs):
+            assert rel(Y.cpu().numpy(), ref) < 1e-12, (ct, rp, qs, th)
+
+
+def test_apply_config_kinds(P, tiny):
+    """The path each apply takes: one lane per pair for uniform N <= 12 and few
+    RHS, the generic kernel otherwise, MFMA (autotuned on first use) for R >= 8."""
+    one = synth.Cluster(np.array([[0.0, 0.0], [3.0, 0.5], [1.0, 4.0]]), np.array([0.5] * 3),
+                        np.array([12] * 3), 6.0)
+    assert P.from_cluster(one).apply_config(1)["kind"] == "lane"
+    pr = P.from_cluster(tiny)                       # N_p = 15
+    assert pr.apply_config(1)["kind"] == "generic"
+    x = torch.randn(8 * tiny.n_tot, dtype=torch.complex128, device="cuda")
+    pr.matvec(x, R=8, op=1)
+    cfg = pr.apply_config(8)
+    assert cfg["kind"] == "mfma" and cfg["tuned_ms"] > 0.0
+
+
 def test_gmres_multi_rhs_lockstep(P):
     """8 incidences x 2 instances: the MFMA apply inside lockstep GMRES; every
     column equals its LU solution."""

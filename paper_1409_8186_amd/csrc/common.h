@@ -166,6 +166,8 @@ struct mudiff_ctx {
   std::map<int, float> mfma_time_ms;      // timed apply of the choice (autotuned R only)
   std::map<int, size_t> mfma_bytes;       // apply scratch per R (largest candidate)
   MfmaSched mfma_sched;                   // current schedule (host copy + upload location)
+  bool mfma_tail = false;                 // straggler schedule (few columns still iterating)
+  std::vector<int32_t> mfma_tail_cols;    // columns of the straggler schedule
 };
 
 // ------------------------------------------------------------------ errors
@@ -230,6 +232,11 @@ int ensure_plan(mudiff_ctx* h, hipStream_t s);
 // (y is overwritten) when x and y are given.  Synchronises; not for use under
 // graph capture.
 int prepare_apply(mudiff_ctx* h, int R, const cplx* x, cplx* y, cplx* scratch, hipStream_t s);
+// Switch the MFMA schedule of R between the tuned form and the straggler form
+// (short column segments, only the tiles holding a column c with
+// cols[c] != 0, c = b * R + r); uploads into `scratch` and synchronises.
+int apply_set_tail(mudiff_ctx* h, int R, bool tail, cplx* scratch, hipStream_t s,
+                   const int32_t* cols);
 struct PlanHost;
 void make_plan(int B, const int64_t* idisk, const int32_t* N, PlanHost& P);
 size_t plan_sched_bytes(const PlanHost& P, int M);

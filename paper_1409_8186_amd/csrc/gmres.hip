@@ -39,6 +39,7 @@ struct GState {
   const cplx* f;            // [NT] preconditioned right-hand side
   cplx* x;                  // [NT] iterate (caller's rho)
   const int64_t* ck;        // [n_chunks][2]: (col | len << 32), begin
+  const int32_t* ckmap;     // chunks of the still-iterating columns, or NULL: all
   const int32_t* ckf;       // [C] first chunk of each column
   const int32_t* ckc;       // [C] chunks of each column
   cplx* P1;                 // [n_chunks][m+1] first-pass partials (slot m: ||w||^2)
@@ -67,12 +68,16 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-__device__ __forceinline__ void decode_chunk(const GState& s, int gidx, int* col, int* len,
-                                             int64_t* begin) {
+// Chunk of this workgroup (through the list of chunks of still-iterating
+// columns when one is set): returns the chunk index, which also indexes the
+// partial-sum buffers.
+__device__ __forceinline__ int decode_chunk(const GState& s, int* col, int* len, int64_t* begin) {
+  const int gidx = s.ckmap ? s.ckmap[blockIdx.x] : (int)blockIdx.x;
   const int64_t a = s.ck[2 * gidx];
   *col = (int)(a & 0xffffffff);
   *len = (int)(a >> 32);
   *begin = s.ck[2 * gidx + 1];
+  return gidx;
 }
 
 // Arnoldi bookkeeping of column c after step j (one thread): Hessenberg column
@@ -288,7 +293,7 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs_dots(GState s, int j, Pending
   __shared__ double sred[GS_WAVES];
   int c, len;
   int64_t o;
-  decode_chunk(s, blockIdx.x, &c, &len, &o);
+  const int gi = decode_chunk(s, &c, &len, &o);
   if (!s.inner[c]) return;
   const int m1 = s.m + 1;
   cplx* w = s.V + (int64_t)(j + 1) * s.NT + o;
@@ -314,7 +319,7 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs_dots(GState s, int j, Pending
     }
   }
   nn = block_sum(nn, sred);  // (its barrier also publishes wl)
-  cplx* part = s.P1 + (int64_t)blockIdx.x * m1;
+  cplx* part = s.P1 + (int64_t)gi * m1;
   chunk_dots(s, j, o, len, wl, part);
   if (threadIdx.x == 0) part[s.m] = cmk(nn, 0.0);
 }
@@ -330,11 +335,11 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs_update(GState s, int j) {
   __shared__ double sred[GS_WAVES];
   int c, len;
   int64_t o;
-  decode_chunk(s, blockIdx.x, &c, &len, &o);
+  const int gi = decode_chunk(s, &c, &len, &o);
   if (!s.inner[c]) return;
   const int m1 = s.m + 1;
   const int nck = s.ckc[c];
-  const bool first_chunk = blockIdx.x == s.ckf[c];
+  const bool first_chunk = gi == s.ckf[c];
   bool staged = false;
   ArnoldiPre pre{};
   if (first_chunk) {
@@ -367,7 +372,7 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs_update(GState s, int j) {
     nn += cabs2(v);
   }
   nn = block_sum(nn, sred);
-  cplx* part = s.P2 + (int64_t)blockIdx.x * m1;
+  cplx* part = s.P2 + (int64_t)gi * m1;
   chunk_dots(s, j, o, len, wl, part);
   if (threadIdx.x == 0) {
     part[s.m] = cmk(nn, 0.0);
@@ -384,11 +389,11 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs_reorth(GState s, int j) {
   __shared__ double sred[GS_WAVES];
   int c, len;
   int64_t o;
-  decode_chunk(s, blockIdx.x, &c, &len, &o);
+  const int gi = decode_chunk(s, &c, &len, &o);
   if (!s.inner[c] || !s.reorth[c]) return;
   const int m1 = s.m + 1;
   const int nck = s.ckc[c];
-  const bool first_chunk = blockIdx.x == s.ckf[c];
+  const bool first_chunk = gi == s.ckf[c];
   bool staged = false;
   ArnoldiPre pre{};
   if (first_chunk) {
@@ -418,7 +423,7 @@ __global__ __launch_bounds__(GS_THREADS) void k_resid(GState s, int mode, int on
   __shared__ double sred[GS_WAVES];
   int c, len;
   int64_t o;
-  decode_chunk(s, blockIdx.x, &c, &len, &o);
+  const int gi = decode_chunk(s, &c, &len, &o);
   if (only_run && !s.run[c]) return;
   double a = 0.0;
   for (int r = threadIdx.x; r < len; r += GS_THREADS) {
@@ -435,7 +440,7 @@ __global__ __launch_bounds__(GS_THREADS) void k_resid(GState s, int mode, int on
     a += cabs2(v);
   }
   a = block_sum(a, sred);
-  if (threadIdx.x == 0) s.P1[(int64_t)blockIdx.x * (s.m + 1)] = cmk(a, 0.0);
+  if (threadIdx.x == 0) s.P1[(int64_t)gi * (s.m + 1)] = cmk(a, 0.0);
 }
 
 // red[c] = sum of the k_resid partials of column c (one wave per column,
@@ -594,7 +599,7 @@ static int64_t max_col_rows(const mudiff_ctx* h) {
 
 namespace {
 struct GLayout {
-  size_t V, f, apply, ck, ckf, ckc, rowcol, P1, P2, H, g, cs, sn, y, normf, red, inv, status,
+  size_t V, f, apply, ck, ckmap, ckf, ckc, rowcol, P1, P2, H, g, cs, sn, y, normf, red, inv, status,
       inner, reorth, run, jdone, iters, ninner, total;
   int64_t n_chunks, NT;
 };
@@ -621,6 +626,7 @@ GLayout glayout(mudiff_ctx* h, int R, int m) {
   L.f = take(NT * 16);
   L.apply = take(apply_scratch_bytes(h, R));
   L.ck = take(nck * 16);
+  L.ckmap = take(nck * 4);
   L.ckf = take(C * 4);
   L.ckc = take(C * 4);
   L.rowcol = take(NT * 4);
@@ -675,10 +681,30 @@ struct GmresRun {
   int32_t* d_ckf;
   int32_t* d_ckc;
   int32_t* d_rowcol;
+  int32_t* d_ckmap;
   cplx* apply_part;
   int32_t* apply_cnt;
   hipStream_t st;
+  std::vector<int64_t> ck;      // host copy of the chunk table
+  std::vector<int32_t> ckmap;   // chunks of the running columns (straggler phase)
+  int n_compact = 0;            // running columns when the list was built (0: all chunks)
 };
+
+// Straggler phase (few running columns): the Gram-Schmidt kernels run over
+// the chunks of the running columns only, and the MFMA apply over the tiles
+// that hold one.  Built at a cycle boundary from the running set `run` of the
+// coming cycle (inner steps and the residual apply only touch those columns).
+static int compact_columns(GmresRun& G, const std::vector<int32_t>& run, int n_run) {
+  G.ckmap.clear();
+  for (int64_t k = 0; k < G.L.n_chunks; ++k)
+    if (run[(int)(G.ck[2 * k] & 0xffffffff)]) G.ckmap.push_back((int32_t)k);
+  if (!G.ckmap.empty()) {
+    HIP_TRY(hipMemcpyAsync(G.d_ckmap, G.ckmap.data(), G.ckmap.size() * 4, hipMemcpyHostToDevice, G.st));
+    HIP_TRY(hipStreamSynchronize(G.st));
+  }
+  G.n_compact = n_run;
+  return apply_set_tail(G.h, G.s.R, true, G.apply_part, G.st, run.data());
+}
 
 // One restart cycle (Arnoldi steps + solution update + true residual).
 static int enqueue_cycle(GmresRun& G, int check_every, bool host_checks) {
@@ -693,15 +719,23 @@ static int enqueue_cycle(GmresRun& G, int check_every, bool host_checks) {
                                   s.V + (int64_t)(j + 1) * s.NT, MUDIFF_OP_A, G.apply_part,
                                   G.apply_cnt, s.inner, G.st, &pending);
     if (rc != MUDIFF_OK) return rc;
-    const unsigned nb = (unsigned)G.L.n_chunks;
+    // Gram-Schmidt over all chunks, or the running columns' chunks only
+    GState sg = s;
+    unsigned nb = (unsigned)G.L.n_chunks;
+    if (G.n_compact > 0) {
+      sg.ckmap = G.d_ckmap;
+      nb = (unsigned)G.ckmap.size();
+    }
     PendingApply pa{G.h->dv, G.apply_part, G.h->plan.part_total, G.h->plan.d_nchunk,
                     G.h->plan.d_partoff};
-    if (pending)
-      hipLaunchKernelGGL(k_gs_dots<true>, dim3(nb), dim3(GS_THREADS), 0, G.st, s, j, pa);
-    else
-      hipLaunchKernelGGL(k_gs_dots<false>, dim3(nb), dim3(GS_THREADS), 0, G.st, s, j, pa);
-    hipLaunchKernelGGL(k_gs_update, dim3(nb), dim3(GS_THREADS), 0, G.st, s, j);
-    hipLaunchKernelGGL(k_gs_reorth, dim3(nb), dim3(GS_THREADS), 0, G.st, s, j);
+    if (nb > 0) {
+      if (pending)
+        hipLaunchKernelGGL(k_gs_dots<true>, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, j, pa);
+      else
+        hipLaunchKernelGGL(k_gs_dots<false>, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, j, pa);
+      hipLaunchKernelGGL(k_gs_update, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, j);
+      hipLaunchKernelGGL(k_gs_reorth, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, j);
+    }
     HIP_TRY(hipGetLastError());
     if (host_checks && check_every > 0 && (j + 1) % check_every == 0 && j + 1 < s.m) {
       int32_t n_in = 0;
@@ -756,6 +790,8 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
   s.f = (cplx*)(w + L.f);
   s.x = (cplx*)rho;
   s.ck = (int64_t*)(w + L.ck);
+  s.ckmap = nullptr;
+  G.d_ckmap = (int32_t*)(w + L.ckmap);
   s.P1 = (cplx*)(w + L.P1);
   s.P2 = (cplx*)(w + L.P2);
   s.H = (cplx*)(w + L.H);
@@ -784,10 +820,11 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
   // operator schedule (MFMA: tuned on V0 = 0 -> V1 on first use of R); uploads
   // happen here, outside any graph capture
   if ((rc = launch_fill_zero(s.V, (size_t)s.NT * 16, st)) != MUDIFF_OK) return rc;
+  if ((rc = apply_set_tail(h, R, false, G.apply_part, st, nullptr)) != MUDIFF_OK) return rc;
   if ((rc = prepare_apply(h, R, s.V, s.V + s.NT, G.apply_part, st)) != MUDIFF_OK) return rc;
 
   // chunk table (host) -> device
-  std::vector<int64_t> ck;
+  std::vector<int64_t>& ck = G.ck;
   std::vector<int32_t> ckf(s.C), ckc(s.C);
   ck.reserve(2 * L.n_chunks);
   int64_t idx = 0;
@@ -859,9 +896,12 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
   for (int64_t cyc = 0; cyc <= (int64_t)maxit; ++cyc) {
     HIP_TRY(hipMemcpyAsync(hstat.data(), s.run, s.C * 4, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    bool any = false;
-    for (int c = 0; c < s.C; ++c) any |= hstat[c] != 0;
-    if (!any) break;
+    int n_run = 0;
+    for (int c = 0; c < s.C; ++c) n_run += hstat[c] != 0;
+    if (n_run == 0) break;
+    if (!use_graph && s.C >= 32 && n_run * 32 <= s.C && (G.n_compact == 0 || n_run * 2 <= G.n_compact)) {
+      if ((result = compact_columns(G, hstat, n_run)) != MUDIFF_OK) break;
+    }
     if (use_graph) {
       if (!exec) {
         // capture on a private stream (the caller's may be the legacy default
@@ -902,5 +942,5 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
   if (result != MUDIFF_OK) return result;
   hipLaunchKernelGGL(k_finish, dim3(cb), dim3(64), 0, st, s, flag, relres, iters);
   HIP_TRY(hipGetLastError());
-  return MUDIFF_OK;
+  return apply_set_tail(h, R, false, G.apply_part, st, nullptr);  // back to the tuned schedule
 }

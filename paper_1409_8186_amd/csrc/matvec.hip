@@ -527,13 +527,17 @@ __global__ void k_apply_mfma_finish(DevView v, int R, const cplx* __restrict__ x
 
 // R at and above which the MFMA kernel applies the operator (N_p <= 31).
 #define MFMA_MIN_R 8
+// Column-disk segment length once few columns are still iterating: short
+// segments spread a large straggler instance over many workgroups.
+#define MFMA_TAIL_QS 16
 
 static bool use_mfma(const mudiff_ctx* h, int R) {
   return R >= MFMA_MIN_R && h->Nmax <= 31 && h->mfma_enabled;
 }
 
 // Host schedule of the MFMA apply for one tile choice.
-static void mfma_build(const mudiff_ctx* h, int R, const MfmaChoice& c, MfmaSched& S) {
+static void mfma_build(const mudiff_ctx* h, int R, const MfmaChoice& c, MfmaSched& S,
+                       const std::vector<int32_t>& cols = {}) {
   S.R = R;
   S.c = c;
   S.dev_base = nullptr;
@@ -566,7 +570,12 @@ static void mfma_build(const mudiff_ctx* h, int R, const MfmaChoice& c, MfmaSche
       S.gbase.push_back(pb);
       double rows = 0.0;
       for (int k = 0; k < rp; ++k) rows += 2 * h->N[p + k] + 1;
-      for (int t = 0; t < S.ntile; ++t)
+      for (int t = 0; t < S.ntile; ++t) {
+        if (!cols.empty()) {  // straggler schedule: tiles holding a running column only
+          bool any = false;
+          for (int r = t * RC; r < std::min(R, (t + 1) * RC); ++r) any |= cols[(size_t)b * R + r] != 0;
+          if (!any) continue;
+        }
         for (int s = 0; s < nseg; ++s) {
           const int64_t q0 = d0 + s * qs, q1 = std::min<int64_t>(d1, q0 + qs);
           double cols = 0.0;
@@ -581,6 +590,7 @@ static void mfma_build(const mudiff_ctx* h, int R, const MfmaChoice& c, MfmaSche
           e.r[5] = (int32_t)(pb + (int64_t)t * nseg + s);
           its.push_back(e);
         }
+      }
       pb += (int64_t)S.ntile * nseg;
     }
   }
@@ -702,11 +712,14 @@ static size_t mfma_scratch_bytes(mudiff_ctx* h, int R) {
   auto f = h->mfma_bytes.find(R);
   if (f != h->mfma_bytes.end()) return f->second;
   size_t mx = 0;
-  for (const MfmaChoice& c : mfma_candidates(R)) {
-    MfmaSched S;
-    mfma_build(h, R, c, S);
-    size_t off[7];
-    mx = std::max(mx, mfma_scratch_layout(h, S, off));
+  for (MfmaChoice c : mfma_candidates(R)) {
+    for (int qs : {c.QS, MFMA_TAIL_QS}) {  // also the short-segment form used for stragglers
+      c.QS = qs;
+      MfmaSched S;
+      mfma_build(h, R, c, S);
+      size_t off[7];
+      mx = std::max(mx, mfma_scratch_layout(h, S, off));
+    }
   }
   h->mfma_bytes[R] = mx;
   return mx;
@@ -762,9 +775,23 @@ static int mfma_prepare(mudiff_ctx* h, int R, const cplx* x, cplx* y, char* scra
     h->mfma_choice[R] = mfma_default(R);
     f = h->mfma_choice.find(R);
   }
-  if (h->mfma_sched.R != R || !(h->mfma_sched.c == f->second)) mfma_build(h, R, f->second, h->mfma_sched);
+  MfmaChoice c = f->second;
+  if (h->mfma_tail) c.QS = MFMA_TAIL_QS;
+  if (h->mfma_sched.R != R || !(h->mfma_sched.c == c))
+    mfma_build(h, R, c, h->mfma_sched, h->mfma_tail ? h->mfma_tail_cols : std::vector<int32_t>{});
   if (h->mfma_sched.dev_base != scratch) return mfma_upload(h, h->mfma_sched, scratch, s);
   return MUDIFF_OK;
+}
+
+int apply_set_tail(mudiff_ctx* h, int R, bool tail, cplx* scratch, hipStream_t s,
+                   const int32_t* cols) {
+  if (!use_mfma(h, R)) return MUDIFF_OK;
+  if (!tail && !h->mfma_tail) return MUDIFF_OK;
+  h->mfma_tail = tail;
+  if (tail && cols) h->mfma_tail_cols.assign(cols, cols + (size_t)h->B * R);
+  else h->mfma_tail_cols.clear();
+  h->mfma_sched.R = 0;  // rebuild
+  return mfma_prepare(h, R, nullptr, nullptr, (char*)scratch, s);
 }
 
 // ------------------------------------------------------------------ planning

@@ -264,6 +264,27 @@ def test_gmres_weak_coupling_second_pass(P):
     assert fl == 0 and abs(int(iters[0]) - it_ref) <= 2, (int(iters[0]), it_ref)
 
 
+@pytest.mark.parametrize("B,R", [(64, 1), (32, 8)])
+def test_gmres_straggler_phase(P, B, R):
+    """Many easy instances and one hard one (≈10 against ≈265 GMRES(10) steps):
+    once at most 1/32 of the columns still run, the Gram-Schmidt kernels run
+    over their chunks only and the MFMA apply (R = 8) over their tiles with
+    short column segments.  Every column must still equal LU."""
+    easy = [synth.small_random(300 + i, 4, 0.3, 0.5, 60.0, 5.0, 2.0, 3) for i in range(B - 1)]
+    hard = synth.small_random(201, 14, 0.6, 0.9, 9.0, 0.05, 1.5, 5)
+    cls = easy[:B // 2] + [hard] + easy[B // 2:]
+    betas = np.tile(synth.uniform_angles(R), (B, 1))
+    say("gmres straggler phase B", B, "R", R)
+    pr = P.from_clusters(cls)
+    rho, flag, relres, iters, _ = pr.gmres(betas=betas, restart=10, tol=1e-12, maxit=3000)
+    it = iters.cpu().numpy().reshape(B, R)
+    say("  iterations easy max", int(np.delete(it, B // 2, axis=0).max()), "hard", it[B // 2].tolist())
+    assert torch.all(flag == 0)
+    assert it[B // 2].min() > 20 * np.delete(it, B // 2, axis=0).max() // 2
+    for c, b, Y in zip(cls, betas, pr.split(rho, R)):
+        assert rel(Y.cpu().numpy(), _lu(c, b)) < 1e-10
+
+
 def test_gmres_batched_lockstep(P):
     """B = 3 uneven instances x R = 3 angles in one solve; every column equals LU."""
     cls = [_uneven(40 + i, M=4 + 3 * i) for i in range(3)]

@@ -329,8 +329,6 @@ __global__ void k_apply_finish(DevView v, int R, const cplx* __restrict__ x, cpl
 typedef double mf_d4 __attribute__((ext_vector_type(4)));
 
 #define MF_REC 6       // item record: p0, rp, tile, q0, q1, partial block
-#define MF_MAXZ 2048   // staged Z values per column disk: 4 ktmax (<= 64) x RC (<= 32)
-#define MF_MAXT 1016   // staged symbol values: RP (<= 8) x TL (<= 64 + 63)
 
 // K row tiles of one wave against one staged column disk: KT k-steps of 4,
 // two real MFMAs per tile and step (Re T, Im T against [Re Z | Im Z]).
@@ -350,13 +348,15 @@ __device__ __forceinline__ void mf_tiles(const cplx* trow, const cplx* zcol, int
   }
 }
 
-template <int MT, int THREADS>  // row tiles of 16: n_p <= 16 MT
+// MT row tiles of 16 (n_p <= 16 MT); ZK / TK staged input / symbol values per
+// thread, sized on the host for the batch (4 ktmax RC <= ZK THREADS and
+// RP TL <= TK THREADS), which keeps the register footprint of the staging to
+// what the batch needs.
+template <int MT, int THREADS, int ZK, int TK>
 __global__ __launch_bounds__(THREADS) void k_apply_mfma(
     DevView v, int R, const cplx* __restrict__ x, const int32_t* __restrict__ active,
     const int32_t* __restrict__ items, int n_items, int32_t* __restrict__ head,
     cplx* __restrict__ part, int64_t blk, int npad, int ktmax, int RP, int CT) {
-  constexpr int ZK = (MF_MAXZ + THREADS - 1) / THREADS;
-  constexpr int TK = (MF_MAXT + THREADS - 1) / THREADS;
   extern __shared__ cplx lds[];
   __shared__ int s_item;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -416,6 +416,7 @@ __global__ __launch_bounds__(THREADS) void k_apply_mfma(
       acc2[t] = mf_d4{0.0, 0.0, 0.0, 0.0};
     }
     cplx zr[ZK], tr[TK];
+    int32_t tof[TK];  // symbol offsets (the MFMA path requires T_all < 2^31)
     // gather the staged values of column disk q into registers
     auto gather = [&](int q) {
       const int Nq = v.N[q], nq = 2 * Nq + 1;
@@ -438,15 +439,26 @@ __global__ __launch_bounds__(THREADS) void k_apply_mfma(
           const int S = Npr + Nq;
           const int s = u - (16 * MT - 1) - Nq + Npr;
           if (s >= -S && s <= S) {
-            const int64_t g = pair_index(v.idisk, v.ipair, b, pr, q);
-            t = v.t[v.toff[g] + S + s];
+            t = v.t[tof[k] + S + s];
             if (pr > q && (s & 1)) t = cmk(-t.x, -t.y);
           }
         }
         tr[k] = t;
       }
     };
+    // symbol-row offsets of column disk q, loaded one disk ahead of gather(q)
+    // so that gathering the symbols is a single dependent load
+    auto load_toff = [&](int q) {
+#pragma unroll
+      for (int k = 0; k < TK; ++k) {
+        const int pr = p0 + trr[k];
+        tof[k] = (q < qe && trr[k] < rp && pr != q)
+                     ? (int32_t)v.toff[pair_index(v.idisk, v.ipair, b, pr, q)] : 0;
+      }
+    };
+    load_toff(qb);
     gather(qb);
+    load_toff(qb + 1);
     for (int q = qb; q < qe; ++q) {
       const int nq = 2 * v.N[q] + 1, KT = (nq + 3) >> 2;
       __syncthreads();  // previous column disk done with LDS
@@ -457,7 +469,10 @@ __global__ __launch_bounds__(THREADS) void k_apply_mfma(
       for (int k = 0; k < TK; ++k)
         if (trr[k] < RP) tl[trr[k] * TL + tru[k]] = tr[k];
       __syncthreads();
-      if (q + 1 < qe) gather(q + 1);  // in flight during the MFMAs
+      if (q + 1 < qe) {  // in flight during the MFMAs
+        gather(q + 1);
+        load_toff(q + 2);
+      }
       if (wave_active && q != p) {
         const cplx* trow = tl + row * TL;
         const cplx* zcol = zl + ctile * 8 + (j & 7);
@@ -532,7 +547,7 @@ __global__ void k_apply_mfma_finish(DevView v, int R, const cplx* __restrict__ x
 #define MFMA_TAIL_QS 16
 
 static bool use_mfma(const mudiff_ctx* h, int R) {
-  return R >= MFMA_MIN_R && h->Nmax <= 31 && h->mfma_enabled;
+  return R >= MFMA_MIN_R && h->Nmax <= 31 && h->mfma_enabled && h->T_all < ((int64_t)1 << 31);
 }
 
 // Host schedule of the MFMA apply for one tile choice.
@@ -657,6 +672,31 @@ static int mfma_upload(mudiff_ctx* h, MfmaSched& S, char* base, hipStream_t s) {
 }
 
 // Enqueue one MFMA apply with schedule S already uploaded at S.dev_base.
+typedef void (*mf_fn)(DevView, int, const cplx*, const int32_t*, const int32_t*, int, int32_t*,
+                      cplx*, int64_t, int, int, int, int);
+
+#define MF_TK3(MT, TH, ZK)                                 \
+  if (zk == ZK) {                                          \
+    if (tk == 1) return k_apply_mfma<MT, TH, ZK, 1>;       \
+    if (tk == 2) return k_apply_mfma<MT, TH, ZK, 2>;       \
+    if (TH == 256 && tk == 4) return k_apply_mfma<MT, TH, ZK, 4>; \
+  }
+#define MF_MT(MT)                                                                   \
+  if (mt == MT) {                                                                   \
+    if (th == 512) { MF_TK3(MT, 512, 1) MF_TK3(MT, 512, 2) MF_TK3(MT, 512, 4) }     \
+    if (th == 256) { MF_TK3(MT, 256, 1) MF_TK3(MT, 256, 2) MF_TK3(MT, 256, 4)       \
+                     MF_TK3(MT, 256, 8) }                                           \
+  }
+
+// Kernel variant for MT row tiles, workgroup size th and staging sizes zk, tk
+// (powers of two; at 512 threads zk <= 4, tk <= 2, at 256 zk <= 8, tk <= 4).
+static mf_fn mf_select(int mt, int th, int zk, int tk) {
+  MF_MT(1) MF_MT(2) MF_MT(3) MF_MT(4)
+  return nullptr;
+}
+#undef MF_MT
+#undef MF_TK3
+
 static int mfma_launch(mudiff_ctx* h, const MfmaSched& S, const cplx* x, cplx* y, int op,
                        const int32_t* active, hipStream_t s) {
   size_t off[7];
@@ -671,31 +711,21 @@ static int mfma_launch(mudiff_ctx* h, const MfmaSched& S, const cplx* x, cplx* y
   int rc = launch_fill_zero(head, 4, s);
   if (rc != MUDIFF_OK) return rc;
   if (S.n_items > 0) {
-    const int per_cu = S.c.threads == 256 ? 4 : 2;
-    const int grid = std::max(1, std::min(S.n_items, per_cu * h->n_cu));
     const int32_t* it = (const int32_t*)(base + off[1]);
-#define MF_LAUNCH(MTV, TH)                                                                      \
-  hipLaunchKernelGGL((k_apply_mfma<MTV, TH>), dim3(grid), dim3(TH), lds, s, h->dv, R_, x,      \
-                     active, it, S.n_items, head, part, S.blk, S.npad, kt, S.c.RP, S.c.CT)
-    const int R_ = S.R;
-    if (S.c.threads == 256) {
-      switch (mt) {
-        case 1: MF_LAUNCH(1, 256); break;
-        case 2: MF_LAUNCH(2, 256); break;
-        case 3: MF_LAUNCH(3, 256); break;
-        case 4: MF_LAUNCH(4, 256); break;
-        default: return fail(MUDIFF_ERR_INVALID, "N_p too large for the MFMA apply");
-      }
-    } else {
-      switch (mt) {
-        case 1: MF_LAUNCH(1, 512); break;
-        case 2: MF_LAUNCH(2, 512); break;
-        case 3: MF_LAUNCH(3, 512); break;
-        case 4: MF_LAUNCH(4, 512); break;
-        default: return fail(MUDIFF_ERR_INVALID, "N_p too large for the MFMA apply");
-      }
-    }
-#undef MF_LAUNCH
+const int TL = 4 * kt + 16 * mt - 1;
+    auto pow2 = [](int v) { int r = 1; while (r < v) r <<= 1; return r; };
+    const int zk = pow2((4 * kt * RC + S.c.threads - 1) / S.c.threads);
+    const int tk = pow2((S.c.RP * TL + S.c.threads - 1) / S.c.threads);
+    const mf_fn fn = mf_select(mt, S.c.threads, zk, tk);
+    if (!fn) return fail(MUDIFF_ERR_INVALID, "no MFMA apply variant for this tile");
+    // persistent grid: as many workgroups as are resident at once
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, S.c.threads, lds) !=
+            hipSuccess || per_cu < 1)
+      per_cu = 1;
+    const int grid = std::max(1, std::min(S.n_items, per_cu * h->n_cu));
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(S.c.threads), lds, s, h->dv, S.R, x, active, it,
+                       S.n_items, head, part, S.blk, S.npad, kt, S.c.RP, S.c.CT);
     HIP_TRY(hipGetLastError());
   }
   const int64_t total = (int64_t)S.R * h->N_all;

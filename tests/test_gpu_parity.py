@@ -201,6 +201,24 @@ def test_gmres_tiny_vs_lu(P, tiny, graph):
     assert rel(a, aref) < 1e-10
 
 
+def test_gmres_lane_path_graph_replay(P):
+    """Uniform N = 8 (one lane per pair, the chunk sums finished inside the
+    first Gram-Schmidt kernel): graph replay gives the eager result bit for
+    bit on repeated solves, and both equal LU."""
+    c = synth.Cluster(*synth.random_disks(np.random.default_rng(77), 40, 0.5, 0.5, 0.0, 25.0, 0.2),
+                      np.full(40, 8), 2.0 * math.pi)
+    say("gmres lane path graph replay")
+    pr = P.from_cluster(c)
+    rho, flag, _, iters, _ = pr.gmres(betas=[[0.4]], restart=20, tol=1e-12, maxit=3000)
+    assert int(flag[0]) == 0
+    assert rel(rho.cpu().numpy(), _lu(c, [0.4])[0]) < 1e-10
+    for rep in range(3):
+        rho_g, flag_g, _, iters_g, _ = pr.gmres(betas=[[0.4]], restart=20, tol=1e-12, maxit=3000,
+                                                graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(iters_g, iters) and torch.equal(rho_g, rho), rep
+
+
 def test_gmres_matches_oracle_gmres_iterations(P, tiny):
     """Same restart / tolerance: the iteration counts of the oracle's MGS GMRES
     and the device CGS2 GMRES agree to within a few (orthogonalisation
@@ -441,3 +459,12 @@ def test_gmres_multi_rhs_lockstep(P):
     assert torch.all(flag == 0), flag
     for b, (c, Rv) in enumerate(zip(cls, pr.split(rho, 8))):
         assert rel(Rv.cpu().numpy(), _lu(c, betas[b])) < 1e-10
+    # restart cycles replayed as HIP graphs (persistent MFMA queue, its counter
+    # reset and the finishing pass inside the graph): identical results, on
+    # repeated solves with host work in between
+    for rep in range(3):
+        rho_g, flag_g, relres_g, iters_g, _ = pr.gmres(betas=betas, restart=30, tol=1e-12,
+                                                       maxit=3000, graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(iters_g, iters) and torch.equal(flag_g, flag), rep
+        assert torch.equal(rho_g, rho), rep

@@ -226,26 +226,43 @@ __device__ double block_sum(double v, double* sred) {
   return t;
 }
 
-// w - sum_{i <= j} h_i V_i at row r of the chunk (sixteen loads in flight).
-__device__ __forceinline__ cplx project_out(const GState& s, int j, const cplx* vr, cplx v,
-                                            const cplx* h) {
+// The RPT rows tid + k * GS_THREADS (k < RPT) of a chunk of len <= RPT *
+// GS_THREADS rows: v[k] = w[r_k] - sum_{i <= j} h_i V_i[r_k], with 32 / RPT
+// basis vectors per round, so that 32 loads are in flight per thread.
+template <int RPT>
+__device__ __forceinline__ void project_rows(const GState& s, int j, const cplx* __restrict__ wc,
+                                             const cplx* __restrict__ vc, int len, const cplx* h,
+                                             cplx (&v)[RPT]) {
+  constexpr int U = 32 / RPT;
+  int r[RPT];
+  bool ok[RPT];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    r[k] = threadIdx.x + k * GS_THREADS;
+    ok[k] = r[k] < len;
+    v[k] = ok[k] ? wc[r[k]] : cmk(0.0, 0.0);
+  }
   int i = 0;
-  for (; i + 15 <= j; i += 16) {
-    cplx t[16];
+  for (; i + U - 1 <= j; i += U) {
+    cplx t[U][RPT];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) t[u] = vr[(int64_t)(i + u) * s.NT];
+    for (int u = 0; u < U; ++u)
 #pragma unroll
-    for (int u = 0; u < 16; ++u) v = csub(v, cmul(h[i + u], t[u]));
+      for (int k = 0; k < RPT; ++k)
+        t[u][k] = ok[k] ? vc[(int64_t)(i + u) * s.NT + r[k]] : cmk(0.0, 0.0);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const cplx hu = h[i + u];
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) v[k] = csub(v[k], cmul(hu, t[u][k]));
+    }
   }
-  for (; i + 3 <= j; i += 4) {
-    cplx t[4];
+  for (; i <= j; ++i) {
+    const cplx hi = h[i];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) t[u] = vr[(int64_t)(i + u) * s.NT];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) v = csub(v, cmul(h[i + u], t[u]));
+    for (int k = 0; k < RPT; ++k)
+      if (ok[k]) v[k] = csub(v[k], cmul(hi, vc[(int64_t)i * s.NT + r[k]]));
   }
-  for (; i <= j; ++i) v = csub(v, cmul(h[i], vr[(int64_t)i * s.NT]));
-  return v;
 }
 
 // Chunk 0 of column c, at the start of the kernel: the previous rotations go
@@ -329,6 +346,7 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs_dots(GState s, int j, Pending
 // with h_{j+1,j}^2 = ||w||^2 - ||h||^2, and chunk 0 does the Arnoldi step.
 // Otherwise w1 = w - V h is stored in place and its partials V^H w1, ||w1||^2
 // go to P2 for the second pass.
+template <int RPT>
 __global__ __launch_bounds__(GS_THREADS) void k_gs_update(GState s, int j) {
   __shared__ cplx hl[MUDIFF_MAX_RESTART + 1];
   __shared__ cplx wl[1024];
@@ -353,11 +371,16 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs_update(GState s, int j) {
   const bool second = !(hn2 > GS_REORTH_ETA * GS_REORTH_ETA * nw);
   cplx* w = s.V + (int64_t)(j + 1) * s.NT + o;
   const cplx* vr0 = s.V + o;
+  cplx v[RPT];
+  project_rows<RPT>(s, j, w, vr0, len, hl, v);
   if (!second) {
     const double hn = sqrt(hn2);
     const double inv = 1.0 / hn;
-    for (int r = threadIdx.x; r < len; r += GS_THREADS)
-      w[r] = cscale(project_out(s, j, vr0 + r, w[r], hl), inv);
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int r = threadIdx.x + k * GS_THREADS;
+      if (r < len) w[r] = cscale(v[k], inv);
+    }
     if (first_chunk) {
       if (threadIdx.x == 0) s.reorth[c] = 0;
       column_step(s, c, j, hl, hn, staged, pre);
@@ -365,11 +388,14 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs_update(GState s, int j) {
     return;
   }
   double nn = 0.0;
-  for (int r = threadIdx.x; r < len; r += GS_THREADS) {
-    const cplx v = project_out(s, j, vr0 + r, w[r], hl);
-    w[r] = v;
-    wl[r] = v;
-    nn += cabs2(v);
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int r = threadIdx.x + k * GS_THREADS;
+    if (r < len) {
+      w[r] = v[k];
+      wl[r] = v[k];
+      nn += cabs2(v[k]);
+    }
   }
   nn = block_sum(nn, sred);
   cplx* part = s.P2 + (int64_t)gi * m1;
@@ -383,6 +409,7 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs_update(GState s, int j) {
 // Second pass (columns flagged by k_gs_update): h2 = sum of the P2 partials,
 // V[j+1] = (w1 - V h2) / h_{j+1,j}, h_{j+1,j}^2 = ||w1||^2 - ||h2||^2; the
 // Hessenberg column is h + h2 (h re-added from P1).
+template <int RPT>
 __global__ __launch_bounds__(GS_THREADS) void k_gs_reorth(GState s, int j) {
   __shared__ cplx hl[MUDIFF_MAX_RESTART + 1];
   __shared__ cplx h2l[MUDIFF_MAX_RESTART + 1];
@@ -408,8 +435,13 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs_reorth(GState s, int j) {
   const double inv = 1.0 / hn;  // unused when hn == 0: the column stops
   cplx* w = s.V + (int64_t)(j + 1) * s.NT + o;
   const cplx* vr0 = s.V + o;
-  for (int r = threadIdx.x; r < len; r += GS_THREADS)
-    w[r] = cscale(project_out(s, j, vr0 + r, w[r], h2l), inv);
+  cplx v[RPT];
+  project_rows<RPT>(s, j, w, vr0, len, h2l, v);
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int r = threadIdx.x + k * GS_THREADS;
+    if (r < len) w[r] = cscale(v[k], inv);
+  }
   if (!first_chunk) return;
   for (int i = threadIdx.x; i <= j; i += GS_THREADS) hl[i] = cadd(hl[i], h2l[i]);
   column_step(s, c, j, hl, hn, staged, pre);
@@ -688,6 +720,7 @@ struct GmresRun {
   std::vector<int64_t> ck;      // host copy of the chunk table
   std::vector<int32_t> ckmap;   // chunks of the running columns (straggler phase)
   int n_compact = 0;            // running columns when the list was built (0: all chunks)
+  int rpt = 1;                  // chunk rows per Gram-Schmidt thread (1, 2 or 4)
 };
 
 // Straggler phase (few running columns): the Gram-Schmidt kernels run over
@@ -733,8 +766,20 @@ static int enqueue_cycle(GmresRun& G, int check_every, bool host_checks) {
         hipLaunchKernelGGL(k_gs_dots<true>, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, j, pa);
       else
         hipLaunchKernelGGL(k_gs_dots<false>, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, j, pa);
-      hipLaunchKernelGGL(k_gs_update, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, j);
-      hipLaunchKernelGGL(k_gs_reorth, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, j);
+      switch (G.rpt) {  // chunk rows per thread
+        case 1:
+          hipLaunchKernelGGL(k_gs_update<1>, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, j);
+          hipLaunchKernelGGL(k_gs_reorth<1>, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, j);
+          break;
+        case 2:
+          hipLaunchKernelGGL(k_gs_update<2>, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, j);
+          hipLaunchKernelGGL(k_gs_reorth<2>, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, j);
+          break;
+        default:
+          hipLaunchKernelGGL(k_gs_update<4>, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, j);
+          hipLaunchKernelGGL(k_gs_reorth<4>, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, j);
+          break;
+      }
     }
     HIP_TRY(hipGetLastError());
     if (host_checks && check_every > 0 && (j + 1) % check_every == 0 && j + 1 < s.m) {
@@ -829,6 +874,7 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
   ck.reserve(2 * L.n_chunks);
   int64_t idx = 0;
   const int64_t ch = chunk_rows(L.NT, max_col_rows(h));
+  G.rpt = ch <= GS_THREADS ? 1 : (ch <= 2 * GS_THREADS ? 2 : 4);
   for (int b = 0; b < h->B; ++b) {
     const int64_t Nb = h->imode[b + 1] - h->imode[b];
     for (int r = 0; r < R; ++r) {

@@ -80,7 +80,7 @@ enum {
 
 /* Largest accepted truncation order N_p and GMRES restart length. */
 #define MUDIFF_MAX_NP 200
-#define MUDIFF_MAX_RESTART 1024
+#define MUDIFF_MAX_RESTART 512
 
 /* ---------------------------------------------------------------- tables */
 

@@ -208,6 +208,7 @@ __device__ __forceinline__ cplx lane_chunk_sum(const DevView& v, const cplx* __r
   const cplx* pr = part + partoff[p] + m;
   cplx w = cmk(0.0, 0.0);
   const int nch = nchunk[p];
+#pragma unroll 8
   for (int k = 0; k < nch; ++k) w = cadd(w, pr[(int64_t)k * np]);
   return w;
 }

@@ -2,17 +2,20 @@
 // A x = f, A = D^{-1} L, f = -D^{-1} U, one Krylov space per column (instance,
 // right-hand side); all columns share each operator application.
 //
-// Orthogonalisation is classical Gram-Schmidt with selective
-// reorthogonalisation (the Daniel-Gragg-Kaufman-Stewart test): one pass
-// h = V^H w, and a second pass only when ||w - V h|| < ||w|| / sqrt(2)
-// (cancellation), which keeps the basis orthogonal to working precision.  A
-// looser threshold (0.1) skips the second pass on cycles of 50 steps without
-// changing convergence, but over a 170-step cycle of an ill-conditioned
-// low-frequency cluster the one-pass basis loses orthogonality and GMRES
-// stalls.  The
-// Hessenberg column, the Givens rotations and the residual estimate
-// |g_{j+1}| / ||f|| are updated on the device, so the host only synchronises to
-// test for the end of a cycle.
+// Orthogonalisation is classical Gram-Schmidt applied twice with the second
+// pass delayed by one step (DCGS2): step j applies the operator to the
+// candidate u = V[j] (orthogonalised once), and one reduction gives both the
+// reorthogonalisation coefficients of u, s = V^H u, and the projection of
+// w = A u, z = V^H w.  One sweep over the basis then finalises q_j = (u - V s)
+// / rho and forms the next candidate (w - V z - g_j q_j) / rho; the Hessenberg
+// column j-1 receives the correction s (from A q_{j-1} = V h + u), and A q_j
+// follows from A u by linearity.  So each step reads the basis twice (once for
+// the dots, once for the update) and has one reduction, against four reads and
+// two or three reductions for CGS2; the basis stays orthogonal to working
+// precision as with CGS2.  The Givens rotations and the residual estimate
+// |g_{j+1}| / ||f|| are updated on the device one step after the operator
+// application (so a converging column performs one extra application); the
+// host only synchronises to test for the end of a cycle.
 //
 // Reductions are per column and free of inter-workgroup synchronisation: the
 // rows of a column are cut into chunks, every chunk writes its partial sums,
@@ -27,7 +30,6 @@
 #define GS_THREADS 256
 #define GS_WAVES (GS_THREADS / 64)
 #define GS_BATCH 4
-#define GS_REORTH_ETA 0.70710678118654752  // 1 / sqrt(2)
 
 enum { ST_RUN = 0, ST_CONV = 1, ST_BREAK = 2, ST_MAXIT = 3 };
 
@@ -42,9 +44,11 @@ struct GState {
   const int32_t* ckmap;     // chunks of the still-iterating columns, or NULL: all
   const int32_t* ckf;       // [C] first chunk of each column
   const int32_t* ckc;       // [C] chunks of each column
-  cplx* P1;                 // [n_chunks][m+1] first-pass partials (slot m: ||w||^2)
-  cplx* P2;                 // [n_chunks][m+1] second-pass partials (slot m: ||w1||^2)
-  cplx* H;                  // [C][(m+1) m]
+  int sl;                   // partial-sum slots per chunk (2m + 2)
+  cplx* P1;                 // [n_chunks][sl] partial sums
+  cplx* H;                  // [C][m][m+1] Hessenberg columns after the Givens rotations
+  cplx* Hraw;               // [C][m][m+1] Hessenberg columns as formed
+  cplx* htent;              // [C][m+1] tentative column of the current step
   cplx* g;                  // [C][m+1]
   double* cs;               // [C][m]
   cplx* sn;                 // [C][m]
@@ -53,7 +57,6 @@ struct GState {
   double* red;              // [C] scalar reduction result
   int32_t* status;          // [C]
   int32_t* inner;           // [C] active in the current Arnoldi cycle
-  int32_t* reorth;          // [C] the current step takes a second pass
   double* inv;              // [C] 1 / ||V0|| at the start of a cycle
   int32_t* run;             // [C] running at the start of the current cycle
   int32_t* jdone;           // [C] Arnoldi steps done in the current cycle
@@ -146,154 +149,214 @@ __device__ void arnoldi_step(const GState& s, int c, int j, const cplx* hl, cons
   }
 }
 
-// Sums, in chunk order, slots 0..ns-1 of the partials of the nck chunks that
-// start at pbase (slot ns-1 read from slot `last` when last >= 0) into out[]
-// (LDS); returns, in every thread, sum |out[i]|^2 over i < nd.  Wave w takes
-// slots w, w + GS_WAVES, ...; its lanes stride over the chunks.
-__device__ double column_sums(const cplx* __restrict__ pbase, int m1, int nck, int ns, int last,
-                              int nd, cplx* out, double* sred) {
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  double sq = 0.0;
-  for (int i0 = wv; i0 < ns; i0 += GS_WAVES * GS_BATCH) {
-    cplx a[GS_BATCH];
-#pragma unroll
-    for (int u = 0; u < GS_BATCH; ++u) {
-      a[u] = cmk(0.0, 0.0);
-      const int i = i0 + u * GS_WAVES;
-      if (i < ns) {
-        const int sl = (i == ns - 1 && last >= 0) ? last : i;
-        for (int k = lane; k < nck; k += 64) a[u] = cadd(a[u], pbase[(int64_t)k * m1 + sl]);
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < GS_BATCH; ++u) {
-      a[u].x = wave_sum(a[u].x);
-      a[u].y = wave_sum(a[u].y);
-      const int i = i0 + u * GS_WAVES;
-      if (i < ns && lane == 0) out[i] = a[u];
-      if (i < nd) sq += cabs2(a[u]);
-    }
-  }
-  if (lane == 0) sred[wv] = sq;
-  __syncthreads();
-  double t = 0.0;
-  for (int k = 0; k < GS_WAVES; ++k) t += sred[k];
-  __syncthreads();  // sred reusable
-  return t;
-}
+// ------------------------------------------------------------------ delayed CGS2
+// Partial-sum slots of a chunk (stride s.sl = 2m + 2) at step j:
+//   [0, j)   V_i^H u        (reorthogonalisation of the candidate u = V[j])
+//   [j, 2j)  V_i^H w        (projection of w = A u)
+//   2j       u^H u,   2j+1  u^H w
 
-// Dots of the chunk's rows of wl against V_0..V_j into part[0..j] (one wave
-// per vector, GS_BATCH vectors in flight).
-__device__ void chunk_dots(const GState& s, int j, int64_t o, int len, const cplx* wl,
-                           cplx* __restrict__ part) {
+// Dots of the chunk's rows of ul and wl against V_0..V_{j-1}: part[i] = V_i^H u,
+// part[j + i] = V_i^H w (when has_w).  One wave per vector, GS_BATCH vectors
+// in flight, both products from one read of V_i.
+__device__ __forceinline__ void chunk_dots2(const GState& s, int j, int64_t o, int len, const cplx* ul,
+                            const cplx* wl, bool has_w, cplx* __restrict__ part) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int i0 = wv; i0 <= j; i0 += GS_WAVES * GS_BATCH) {
-    cplx a[GS_BATCH];
+  for (int i0 = wv; i0 < j; i0 += GS_WAVES * GS_BATCH) {
+    cplx au[GS_BATCH], aw[GS_BATCH];
     const cplx* vi[GS_BATCH];
 #pragma unroll
     for (int u = 0; u < GS_BATCH; ++u) {
-      a[u] = cmk(0.0, 0.0);
-      const int i = min(i0 + u * GS_WAVES, j);  // past j: a valid row, result unused
+      au[u] = cmk(0.0, 0.0);
+      aw[u] = cmk(0.0, 0.0);
+      const int i = min(i0 + u * GS_WAVES, j - 1);  // past j-1: a valid row, result unused
       vi[u] = s.V + (int64_t)i * s.NT + o;
     }
 #pragma unroll 4
     for (int r = lane; r < len; r += 64) {
-      const cplx wr = wl[r];
+      const cplx ur = ul[r];
+      const cplx wr = has_w ? wl[r] : cmk(0.0, 0.0);
 #pragma unroll
-      for (int u = 0; u < GS_BATCH; ++u) cmacc(a[u], vi[u][r], wr);
+      for (int u = 0; u < GS_BATCH; ++u) {
+        const cplx vv = vi[u][r];
+        cmacc(au[u], vv, ur);
+        cmacc(aw[u], vv, wr);
+      }
     }
 #pragma unroll
     for (int u = 0; u < GS_BATCH; ++u) {
-      a[u].x = wave_sum(a[u].x);
-      a[u].y = wave_sum(a[u].y);
+      au[u].x = wave_sum(au[u].x);
+      au[u].y = wave_sum(au[u].y);
+      aw[u].x = wave_sum(aw[u].x);
+      aw[u].y = wave_sum(aw[u].y);
     }
     if (lane == 0) {
 #pragma unroll
-      for (int u = 0; u < GS_BATCH; ++u)
-        if (i0 + u * GS_WAVES <= j) part[i0 + u * GS_WAVES] = a[u];
+      for (int u = 0; u < GS_BATCH; ++u) {
+        const int i = i0 + u * GS_WAVES;
+        if (i < j) {
+          part[i] = au[u];
+          if (has_w) part[j + i] = aw[u];
+        }
+      }
     }
   }
 }
 
-// Sum over the block of a per-thread value (every thread gets the total).
+// Sums over the block of NV per-thread values in one LDS round (every thread
+// gets the totals, added in wave order).  sred holds NV * GS_WAVES doubles.
+template <int NV>
+__device__ void block_sums(double (&v)[NV], double* sred) {
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    v[q] = wave_sum(v[q]);
+    if ((threadIdx.x & 63) == 0) sred[q * GS_WAVES + (threadIdx.x >> 6)] = v[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double t = 0.0;
+    for (int k = 0; k < GS_WAVES; ++k) t += sred[q * GS_WAVES + k];
+    v[q] = t;
+  }
+  __syncthreads();  // sred reusable
+}
+
 __device__ double block_sum(double v, double* sred) {
-  v = wave_sum(v);
-  if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double t = 0.0;
-  for (int k = 0; k < GS_WAVES; ++k) t += sred[k];
-  __syncthreads();
-  return t;
+  double a[1] = {v};
+  block_sums<1>(a, sred);
+  return a[0];
+}
+
+// Sums over the nck chunks of a column, in a fixed order, of slots 0..ns-1 of
+// their partials (at pbase, stride sl; slot ns-1 read from slot `last` when
+// last >= 0) into out[] (LDS); returns, in every thread, sum |out[i]|^2 over
+// i < nd.  Loads run along the slots (coalesced).  Up to 8 chunks: a thread
+// adds one slot over all chunks in chunk order.  More: wave g adds chunks g,
+// g + GS_WAVES, ... for 64 slots at a time and the wave sums are added in wave
+// order through tmp[GS_WAVES * 64].  Every workgroup of a column so derives
+// the same values.
+__device__ double column_sums(const cplx* __restrict__ pbase, int sl, int nck, int ns, int last,
+                              int nd, cplx* out, cplx* tmp, double* sred) {
+  const int tid = threadIdx.x;
+  double sq = 0.0;
+  if (nck <= 8) {
+    for (int i = tid; i < ns; i += GS_THREADS) {
+      const cplx* p = pbase + ((i == ns - 1 && last >= 0) ? last : i);
+      cplx t[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) t[k] = k < nck ? p[(int64_t)k * sl] : cmk(0.0, 0.0);
+      cplx a = t[0];
+#pragma unroll
+      for (int k = 1; k < 8; ++k)
+        if (k < nck) a = cadd(a, t[k]);
+      out[i] = a;
+      if (i < nd) sq += cabs2(a);
+    }
+  } else {
+    const int lane = tid & 63, g = tid >> 6;
+    for (int i0 = 0; i0 < ns; i0 += 64) {
+      const int i = i0 + lane;
+      cplx a = cmk(0.0, 0.0);
+      if (i < ns) {
+        const cplx* p = pbase + ((i == ns - 1 && last >= 0) ? last : i);
+        for (int k0 = g; k0 < nck; k0 += 8 * GS_WAVES) {
+          cplx t[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int k = k0 + u * GS_WAVES;
+            t[u] = k < nck ? p[(int64_t)k * sl] : cmk(0.0, 0.0);
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (k0 + u * GS_WAVES < nck) a = cadd(a, t[u]);
+        }
+      }
+      tmp[g * 64 + lane] = a;
+      __syncthreads();
+      if (g == 0 && i < ns) {
+        cplx v = tmp[lane];
+        for (int q = 1; q < GS_WAVES; ++q) v = cadd(v, tmp[q * 64 + lane]);
+        out[i] = v;
+        if (i < nd) sq += cabs2(v);
+      }
+      __syncthreads();
+    }
+  }
+  return block_sum(sq, sred);  // (its barrier also publishes out[])
 }
 
 // The RPT rows tid + k * GS_THREADS (k < RPT) of a chunk of len <= RPT *
-// GS_THREADS rows: v[k] = w[r_k] - sum_{i <= j} h_i V_i[r_k], with 32 / RPT
-// basis vectors per round, so that 32 loads are in flight per thread.
+// GS_THREADS rows: a[k] = u[r_k] - sum_{i < j} sc_i V_i[r_k] and
+// b[k] = w[r_k] - sum_{i < j} zc_i V_i[r_k], from one read of each V_i[r_k];
+// 16 / RPT basis vectors per round, so that 16 loads are in flight per thread.
 template <int RPT>
-__device__ __forceinline__ void project_rows(const GState& s, int j, const cplx* __restrict__ wc,
-                                             const cplx* __restrict__ vc, int len, const cplx* h,
-                                             cplx (&v)[RPT]) {
-  constexpr int U = 32 / RPT;
+__device__ __forceinline__ void project_rows2(const GState& s, int j, const cplx* __restrict__ uc,
+                                              const cplx* __restrict__ wc,
+                                              const cplx* __restrict__ vc, int len,
+                                              const cplx* sc, const cplx* zc, cplx (&a)[RPT],
+                                              cplx (&b)[RPT]) {
+  constexpr int U = 16 / RPT;
   int r[RPT];
   bool ok[RPT];
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
     r[k] = threadIdx.x + k * GS_THREADS;
     ok[k] = r[k] < len;
-    v[k] = ok[k] ? wc[r[k]] : cmk(0.0, 0.0);
+    a[k] = ok[k] ? uc[r[k]] : cmk(0.0, 0.0);
+    b[k] = ok[k] ? wc[r[k]] : cmk(0.0, 0.0);
   }
   int i = 0;
-  for (; i + U - 1 <= j; i += U) {
+  for (; i + U <= j; i += U) {
     cplx t[U][RPT];
 #pragma unroll
-    for (int u = 0; u < U; ++u)
+    for (int q = 0; q < U; ++q)
 #pragma unroll
       for (int k = 0; k < RPT; ++k)
-        t[u][k] = ok[k] ? vc[(int64_t)(i + u) * s.NT + r[k]] : cmk(0.0, 0.0);
+        t[q][k] = ok[k] ? vc[(int64_t)(i + q) * s.NT + r[k]] : cmk(0.0, 0.0);
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const cplx hu = h[i + u];
+    for (int q = 0; q < U; ++q) {
+      const cplx sq = sc[i + q], zq = zc[i + q];
 #pragma unroll
-      for (int k = 0; k < RPT; ++k) v[k] = csub(v[k], cmul(hu, t[u][k]));
+      for (int k = 0; k < RPT; ++k) {
+        a[k] = csub(a[k], cmul(sq, t[q][k]));
+        b[k] = csub(b[k], cmul(zq, t[q][k]));
+      }
     }
   }
-  for (; i <= j; ++i) {
-    const cplx hi = h[i];
+  if (i < j) {  // last, partial batch: rows past j-1 are loaded but not used
+    cplx t[U][RPT];
 #pragma unroll
-    for (int k = 0; k < RPT; ++k)
-      if (ok[k]) v[k] = csub(v[k], cmul(hi, vc[(int64_t)i * s.NT + r[k]]));
+    for (int q = 0; q < U; ++q) {
+      const int iq = min(i + q, j - 1);
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) t[q][k] = ok[k] ? vc[(int64_t)iq * s.NT + r[k]] : cmk(0.0, 0.0);
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      if (i + q >= j) break;
+      const cplx sq = sc[i + q], zq = zc[i + q];
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        a[k] = csub(a[k], cmul(sq, t[q][k]));
+        b[k] = csub(b[k], cmul(zq, t[q][k]));
+      }
+    }
   }
 }
 
-// Chunk 0 of column c, at the start of the kernel: the previous rotations go
-// to LDS behind the slots 0..j+1 that the column sums will fill (when they fit)
-// and thread 0 loads what the Arnoldi step reads from global memory.
-__device__ bool stage_rotations(const GState& s, int c, int j, cplx* hl) {
-  const bool fits = 2 * j + 2 + (j + 1) / 2 <= MUDIFF_MAX_RESTART + 1;
-  if (fits) {
-    const double* csg = s.cs + (int64_t)c * s.m;
-    const cplx* sng = s.sn + (int64_t)c * s.m;
-    for (int i = threadIdx.x; i < j; i += GS_THREADS) {
-      hl[j + 2 + i] = sng[i];
-      reinterpret_cast<double*>(hl + 2 * j + 2)[i] = csg[i];
-    }
+// The rotations 0..col-1 of column c into LDS: rot[0, col) = sn,
+// (double*)(rot + col)[0, col) = cs.
+__device__ void stage_rotations(const GState& s, int c, int col, cplx* rot) {
+  const double* csg = s.cs + (int64_t)c * s.m;
+  const cplx* sng = s.sn + (int64_t)c * s.m;
+  for (int i = threadIdx.x; i < col; i += GS_THREADS) {
+    rot[i] = sng[i];
+    reinterpret_cast<double*>(rot + col)[i] = csg[i];
   }
-  return fits;  // visible to thread 0 after the next barrier
-}
-
-// Chunk 0 of column c: the Arnoldi/Givens step on h = hl[0..j].
-__device__ void column_step(const GState& s, int c, int j, const cplx* hl, double hn, bool staged,
-                            const ArnoldiPre& pre) {
-  __syncthreads();  // hl and the staged rotations complete
-  if (threadIdx.x != 0) return;
-  const double* csl = staged ? reinterpret_cast<const double*>(hl + 2 * j + 2)
-                             : s.cs + (int64_t)c * s.m;
-  const cplx* snl = staged ? hl + j + 2 : s.sn + (int64_t)c * s.m;
-  arnoldi_step(s, c, j, hl, csl, snl, hn, pre);
 }
 
 // Chunk partial sums of an operator apply still to be added (one-lane-per-pair
-// path): w = A V[j] is completed row by row by the first Gram-Schmidt pass.
+// path): w = A V[j] is completed row by row by the dots kernel.
 struct PendingApply {
   DevView v;
   const cplx* part;
@@ -302,55 +365,79 @@ struct PendingApply {
   const int64_t* partoff;
 };
 
-// Pass 1 of step j on w = V[j+1]: partial h = V^H w and ||w||^2 into P1.  With
-// FIN, w is first formed from the apply's chunk partial sums and stored.
+// Step j, pass 1: the chunk's partial sums of V_i^H u, V_i^H w (i < j), u^H u
+// and u^H w, u = V[j] the candidate, w = V[j+1] = A u.  With FIN, w is first
+// formed from the apply's chunk partial sums and stored.  Without has_w (the
+// end of a cycle) only V_i^H u and u^H u.
 template <bool FIN>
-__global__ __launch_bounds__(GS_THREADS) void k_gs_dots(GState s, int j, PendingApply pa) {
+__global__ __launch_bounds__(GS_THREADS) void k_dg_dots(GState s, int j, PendingApply pa,
+                                                        int has_w) {
+  __shared__ cplx ul[1024];
   __shared__ cplx wl[1024];
-  __shared__ double sred[GS_WAVES];
+  __shared__ double sred[3 * GS_WAVES];
   int c, len;
   int64_t o;
   const int gi = decode_chunk(s, &c, &len, &o);
   if (!s.inner[c]) return;
-  const int m1 = s.m + 1;
+  const cplx* u = s.V + (int64_t)j * s.NT + o;
   cplx* w = s.V + (int64_t)(j + 1) * s.NT + o;
-  double nn = 0.0;
+  double uu = 0.0;
+  cplx uw = cmk(0.0, 0.0);
+  int64_t i0 = 0;
+  const cplx* pr = nullptr;
+  int b = 0;
   if (FIN) {
-    const int b = c / s.R, r = c - (c / s.R) * s.R;
-    const int64_t i0 = pa.v.imode[b] + (o - col_base(pa.v.imode, b, s.R, r));
-    const cplx* xj = s.V + (int64_t)j * s.NT + o;
-    const cplx* pr = pa.part + (int64_t)r * pa.part_total;
-    for (int rr = threadIdx.x; rr < len; rr += GS_THREADS) {
-      const int64_t i = i0 + rr;
-      const cplx v =
-          finalize(pa.v, MUDIFF_OP_A, i, xj[rr], lane_chunk_sum(pa.v, pr, pa.nchunk, pa.partoff, b, i));
-      w[rr] = v;
-      wl[rr] = v;
-      nn += cabs2(v);
-    }
-  } else {
-    for (int r = threadIdx.x; r < len; r += GS_THREADS) {
-      const cplx v = w[r];
-      wl[r] = v;
-      nn += cabs2(v);
+    b = c / s.R;
+    const int r = c - b * s.R;
+    i0 = pa.v.imode[b] + (o - col_base(pa.v.imode, b, s.R, r));
+    pr = pa.part + (int64_t)r * pa.part_total;
+  }
+  for (int rr = threadIdx.x; rr < len; rr += GS_THREADS) {
+    const cplx uv = u[rr];
+    ul[rr] = uv;
+    uu += cabs2(uv);
+    if (has_w) {
+      cplx wv;
+      if (FIN) {
+        wv = finalize(pa.v, MUDIFF_OP_A, i0 + rr, uv,
+                      lane_chunk_sum(pa.v, pr, pa.nchunk, pa.partoff, b, i0 + rr));
+        w[rr] = wv;
+      } else {
+        wv = w[rr];
+      }
+      wl[rr] = wv;
+      cmacc(uw, uv, wv);
     }
   }
-  nn = block_sum(nn, sred);  // (its barrier also publishes wl)
-  cplx* part = s.P1 + (int64_t)gi * m1;
-  chunk_dots(s, j, o, len, wl, part);
-  if (threadIdx.x == 0) part[s.m] = cmk(nn, 0.0);
+  double red3[3] = {uu, uw.x, uw.y};
+  block_sums<3>(red3, sred);  // (its barriers also publish ul, wl)
+  uu = red3[0];
+  uw = cmk(red3[1], red3[2]);
+  cplx* part = s.P1 + (int64_t)gi * s.sl;
+  chunk_dots2(s, j, o, len, ul, wl, has_w != 0, part);
+  if (threadIdx.x == 0) {
+    part[2 * j] = cmk(uu, 0.0);
+    part[2 * j + 1] = uw;
+  }
 }
 
-// Pass 2: every workgroup of column c adds the P1 partials (h, ||w||^2) and
-// takes the same decision.  Without cancellation, V[j+1] = (w - V h) / h_{j+1,j}
-// with h_{j+1,j}^2 = ||w||^2 - ||h||^2, and chunk 0 does the Arnoldi step.
-// Otherwise w1 = w - V h is stored in place and its partials V^H w1, ||w1||^2
-// go to P2 for the second pass.
+// Step j, pass 2.  Every workgroup of column c adds the partials of its column
+// (same order everywhere, so identical values): s = V^H u, z = V^H w, u^H u,
+// u^H w; rho = ||u - V s|| = sqrt(u^H u - ||s||^2) (s is small: u was
+// orthogonalised once already, so no cancellation).  Rows:
+//   V[j]   = q_j    = (u - V s) / rho                       (final)
+//   V[j+1] = u_next = (w - V z - g_j q_j) / rho,  g_j = (u^H w - s^H z) / rho,
+// the candidate of the next step (u_next = A q_j - [V q_j] h_j, the once
+// orthogonalised vector).  Chunk 0 finalises Hessenberg column j-1 (its
+// tentative entries plus s, subdiagonal rho), takes the Givens step, and forms
+// the tentative column j, h_j = ([z; g_j] - H s) / rho, H the unrotated
+// Hessenberg columns 0..j-1.
 template <int RPT>
-__global__ __launch_bounds__(GS_THREADS) void k_gs_update(GState s, int j) {
-  __shared__ cplx hl[MUDIFF_MAX_RESTART + 1];
-  __shared__ cplx wl[1024];
-  __shared__ double sred[GS_WAVES];
+__global__ __launch_bounds__(GS_THREADS) void k_dg_update(GState s, int j) {
+  __shared__ cplx cl[2 * MUDIFF_MAX_RESTART + 2];
+  __shared__ cplx aux[MUDIFF_MAX_RESTART + MUDIFF_MAX_RESTART + MUDIFF_MAX_RESTART / 2];
+  __shared__ cplx tmp[GS_WAVES * 64];
+  __shared__ double sred[2 * GS_WAVES];
   int c, len;
   int64_t o;
   const int gi = decode_chunk(s, &c, &len, &o);
@@ -358,93 +445,123 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs_update(GState s, int j) {
   const int m1 = s.m + 1;
   const int nck = s.ckc[c];
   const bool first_chunk = gi == s.ckf[c];
-  bool staged = false;
+  cplx* hcol = aux;                          // column j-1 of the Hessenberg matrix
+  cplx* rot = aux + MUDIFF_MAX_RESTART;      // rotations 0..j-2
   ArnoldiPre pre{};
-  if (first_chunk) {
-    staged = stage_rotations(s, c, j, hl);
-    if (threadIdx.x == 0) pre = arnoldi_preload(s, c, j);
+  if (first_chunk && j >= 1) {
+    stage_rotations(s, c, j - 1, rot);
+    if (threadIdx.x == 0) pre = arnoldi_preload(s, c, j - 1);
+    for (int i = threadIdx.x; i < j; i += GS_THREADS) hcol[i] = s.htent[(int64_t)c * m1 + i];
   }
-  const double hsq = column_sums(s.P1 + (int64_t)s.ckf[c] * m1, m1, nck, j + 2, s.m, j + 1, hl, sred);
-  const double nw = hl[j + 1].x;
-  const double hn2 = nw - hsq;
-  // ||w - V h||^2 <= eta^2 ||w||^2 (or not finite): second pass
-  const bool second = !(hn2 > GS_REORTH_ETA * GS_REORTH_ETA * nw);
+  const double ssq = column_sums(s.P1 + (int64_t)s.ckf[c] * s.sl, s.sl, nck, 2 * j + 2, -1, j, cl,
+                                 tmp, sred);
+  const double alpha = cl[2 * j].x;
+  const cplx beta = cl[2 * j + 1];
+  const double rho2 = alpha - ssq;
+  const double rho = sqrt(rho2 > 0.0 ? rho2 : 0.0);
+  const double inv = 1.0 / rho;  // rho == 0: breakdown, the column stops below
+  cplx sz = cmk(0.0, 0.0);       // s^H z
+  for (int i = threadIdx.x; i < j; i += GS_THREADS) cmacc(sz, cl[i], cl[j + i]);
+  {
+    double r2[2] = {sz.x, sz.y};
+    block_sums<2>(r2, sred);
+    sz = cmk(r2[0], r2[1]);
+  }
+  const cplx gj = cscale(csub(beta, sz), inv);
+  cplx* u = s.V + (int64_t)j * s.NT + o;
   cplx* w = s.V + (int64_t)(j + 1) * s.NT + o;
-  const cplx* vr0 = s.V + o;
-  cplx v[RPT];
-  project_rows<RPT>(s, j, w, vr0, len, hl, v);
-  if (!second) {
-    const double hn = sqrt(hn2);
-    const double inv = 1.0 / hn;
-#pragma unroll
-    for (int k = 0; k < RPT; ++k) {
-      const int r = threadIdx.x + k * GS_THREADS;
-      if (r < len) w[r] = cscale(v[k], inv);
-    }
-    if (first_chunk) {
-      if (threadIdx.x == 0) s.reorth[c] = 0;
-      column_step(s, c, j, hl, hn, staged, pre);
-    }
-    return;
-  }
-  double nn = 0.0;
+  cplx a[RPT], bb[RPT];
+  project_rows2<RPT>(s, j, u, w, s.V + o, len, cl, cl + j, a, bb);
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
     const int r = threadIdx.x + k * GS_THREADS;
     if (r < len) {
-      w[r] = v[k];
-      wl[r] = v[k];
-      nn += cabs2(v[k]);
+      const cplx q = cscale(a[k], inv);
+      u[r] = q;
+      w[r] = cscale(csub(bb[k], cmul(gj, q)), inv);
     }
   }
-  nn = block_sum(nn, sred);
-  cplx* part = s.P2 + (int64_t)gi * m1;
-  chunk_dots(s, j, o, len, wl, part);
-  if (threadIdx.x == 0) {
-    part[s.m] = cmk(nn, 0.0);
-    if (first_chunk) s.reorth[c] = 1;
+  if (!first_chunk) return;
+  cplx* Hr = s.Hraw + (int64_t)c * m1 * s.m;  // unrotated columns, [k][m+1]
+  if (j >= 1) {
+    for (int i = threadIdx.x; i < j; i += GS_THREADS) {
+      hcol[i] = cadd(hcol[i], cl[i]);
+      Hr[(int64_t)(j - 1) * m1 + i] = hcol[i];
+    }
+    if (threadIdx.x == 0) Hr[(int64_t)(j - 1) * m1 + j] = cmk(rho, 0.0);
+    __syncthreads();  // column j-1 and the staged rotations complete
+    if (threadIdx.x == 0)
+      arnoldi_step(s, c, j - 1, hcol, reinterpret_cast<const double*>(rot + (j - 1)), rot, rho,
+                   pre);
+  }
+  // tentative column j, entries h_i = (g_i - sum_k Hraw[k][i] s_k) / rho,
+  // g = [z; g_j], k from i-1 (Hessenberg) to j-1: waves 1.. while thread 0 takes
+  // the Givens step; eight lanes per entry split the sum over k and add their
+  // parts by shuffles.
+  const int w0 = j >= 1 ? 1 : 0;
+  const int wv = (int)threadIdx.x >> 6;
+  if (wv < w0) return;
+  const int lane = threadIdx.x & 63, kl = lane & 7;
+  const int per_pass = (GS_WAVES - w0) * 8;
+  for (int i0 = 0; i0 <= j; i0 += per_pass) {
+    const int i = i0 + (wv - w0) * 8 + (lane >> 3);
+    cplx hs = cmk(0.0, 0.0);
+    if (i <= j) {
+      for (int k = (i > 0 ? i - 1 : 0) + kl; k < j; k += 32) {
+        cplx t[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int kk = min(k + 8 * u, j - 1);
+          t[u] = Hr[(int64_t)kk * m1 + i];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (k + 8 * u < j) hs = cadd(hs, cmul(t[u], cl[k + 8 * u]));
+      }
+    }
+#pragma unroll
+    for (int o = 1; o < 8; o <<= 1) {
+      hs.x += __shfl_xor(hs.x, o, 64);
+      hs.y += __shfl_xor(hs.y, o, 64);
+    }
+    if (kl == 0 && i <= j) {
+      const cplx g = i < j ? cl[j + i] : gj;
+      s.htent[(int64_t)c * m1 + i] = cscale(csub(g, hs), inv);
+    }
   }
 }
 
-// Second pass (columns flagged by k_gs_update): h2 = sum of the P2 partials,
-// V[j+1] = (w1 - V h2) / h_{j+1,j}, h_{j+1,j}^2 = ||w1||^2 - ||h2||^2; the
-// Hessenberg column is h + h2 (h re-added from P1).
-template <int RPT>
-__global__ __launch_bounds__(GS_THREADS) void k_gs_reorth(GState s, int j) {
-  __shared__ cplx hl[MUDIFF_MAX_RESTART + 1];
-  __shared__ cplx h2l[MUDIFF_MAX_RESTART + 1];
+// End of a cycle (after m steps): column m-1 is finalised from the last
+// candidate u = V[m]: s = V^H u, rho = sqrt(u^H u - ||s||^2).  One workgroup
+// per column.
+__global__ __launch_bounds__(GS_THREADS) void k_dg_flush(GState s) {
+  __shared__ cplx cl[MUDIFF_MAX_RESTART + 1];
+  __shared__ cplx aux[MUDIFF_MAX_RESTART + MUDIFF_MAX_RESTART + MUDIFF_MAX_RESTART / 2];
+  __shared__ cplx tmp[GS_WAVES * 64];
   __shared__ double sred[GS_WAVES];
-  int c, len;
-  int64_t o;
-  const int gi = decode_chunk(s, &c, &len, &o);
-  if (!s.inner[c] || !s.reorth[c]) return;
+  const int c = blockIdx.x;
+  if (!s.inner[c]) return;
+  const int j = s.m;
   const int m1 = s.m + 1;
-  const int nck = s.ckc[c];
-  const bool first_chunk = gi == s.ckf[c];
-  bool staged = false;
+  cplx* hcol = aux;
+  cplx* rot = aux + MUDIFF_MAX_RESTART;
+  stage_rotations(s, c, j - 1, rot);
   ArnoldiPre pre{};
-  if (first_chunk) {
-    staged = stage_rotations(s, c, j, hl);
-    if (threadIdx.x == 0) pre = arnoldi_preload(s, c, j);
-    (void)column_sums(s.P1 + (int64_t)s.ckf[c] * m1, m1, nck, j + 1, -1, 0, hl, sred);
+  if (threadIdx.x == 0) pre = arnoldi_preload(s, c, j - 1);
+  for (int i = threadIdx.x; i < j; i += GS_THREADS) hcol[i] = s.htent[(int64_t)c * m1 + i];
+  const double ssq = column_sums(s.P1 + (int64_t)s.ckf[c] * s.sl, s.sl, s.ckc[c], j + 1, 2 * j, j,
+                                 cl, tmp, sred);
+  const double rho2 = cl[j].x - ssq;
+  const double rho = sqrt(rho2 > 0.0 ? rho2 : 0.0);
+  cplx* Hr = s.Hraw + (int64_t)c * m1 * s.m;
+  for (int i = threadIdx.x; i < j; i += GS_THREADS) {
+    hcol[i] = cadd(hcol[i], cl[i]);
+    Hr[(int64_t)(j - 1) * m1 + i] = hcol[i];
   }
-  const double h2sq =
-      column_sums(s.P2 + (int64_t)s.ckf[c] * m1, m1, nck, j + 2, s.m, j + 1, h2l, sred);
-  const double hn2 = h2l[j + 1].x - h2sq;
-  const double hn = sqrt(hn2 > 0.0 ? hn2 : 0.0);
-  const double inv = 1.0 / hn;  // unused when hn == 0: the column stops
-  cplx* w = s.V + (int64_t)(j + 1) * s.NT + o;
-  const cplx* vr0 = s.V + o;
-  cplx v[RPT];
-  project_rows<RPT>(s, j, w, vr0, len, h2l, v);
-#pragma unroll
-  for (int k = 0; k < RPT; ++k) {
-    const int r = threadIdx.x + k * GS_THREADS;
-    if (r < len) w[r] = cscale(v[k], inv);
-  }
-  if (!first_chunk) return;
-  for (int i = threadIdx.x; i <= j; i += GS_THREADS) hl[i] = cadd(hl[i], h2l[i]);
-  column_step(s, c, j, hl, hn, staged, pre);
+  if (threadIdx.x == 0) Hr[(int64_t)(j - 1) * m1 + j] = cmk(rho, 0.0);
+  __syncthreads();
+  if (threadIdx.x == 0)
+    arnoldi_step(s, c, j - 1, hcol, reinterpret_cast<const double*>(rot + (j - 1)), rot, rho, pre);
 }
 
 // Chunked per-column sum of |src|^2: partials into P1 slot 0 (running columns
@@ -472,7 +589,7 @@ __global__ __launch_bounds__(GS_THREADS) void k_resid(GState s, int mode, int on
     a += cabs2(v);
   }
   a = block_sum(a, sred);
-  if (threadIdx.x == 0) s.P1[(int64_t)gi * (s.m + 1)] = cmk(a, 0.0);
+  if (threadIdx.x == 0) s.P1[(int64_t)gi * s.sl] = cmk(a, 0.0);
 }
 
 // red[c] = sum of the k_resid partials of column c (one wave per column,
@@ -480,9 +597,8 @@ __global__ __launch_bounds__(GS_THREADS) void k_resid(GState s, int mode, int on
 __global__ __launch_bounds__(64) void k_col_sum(GState s, int only_run) {
   const int c = blockIdx.x, lane = threadIdx.x;
   if (only_run && !s.run[c]) return;
-  const int m1 = s.m + 1;
   double t = 0.0;
-  for (int k = lane; k < s.ckc[c]; k += 64) t += s.P1[(int64_t)(s.ckf[c] + k) * m1].x;
+  for (int k = lane; k < s.ckc[c]; k += 64) t += s.P1[(int64_t)(s.ckf[c] + k) * s.sl].x;
   t = wave_sum(t);
   if (lane == 0) s.red[c] = t;
 }
@@ -631,8 +747,8 @@ static int64_t max_col_rows(const mudiff_ctx* h) {
 
 namespace {
 struct GLayout {
-  size_t V, f, apply, ck, ckmap, ckf, ckc, rowcol, P1, P2, H, g, cs, sn, y, normf, red, inv, status,
-      inner, reorth, run, jdone, iters, ninner, total;
+  size_t V, f, apply, ck, ckmap, ckf, ckc, rowcol, P1, H, Hraw, htent, g, cs, sn, y, normf, red,
+      inv, status, inner, run, jdone, iters, ninner, total;
   int64_t n_chunks, NT;
 };
 
@@ -662,9 +778,10 @@ GLayout glayout(mudiff_ctx* h, int R, int m) {
   L.ckf = take(C * 4);
   L.ckc = take(C * 4);
   L.rowcol = take(NT * 4);
-  L.P1 = take(nck * (m + 1) * 16);
-  L.P2 = take(nck * (m + 1) * 16);
+  L.P1 = take(nck * (2 * m + 2) * 16);
   L.H = take(C * (m + 1) * m * 16);
+  L.Hraw = take(C * (m + 1) * m * 16);
+  L.htent = take(C * (m + 1) * 16);
   L.g = take(C * (m + 1) * 16);
   L.cs = take(C * m * 8);
   L.sn = take(C * m * 16);
@@ -674,7 +791,6 @@ GLayout glayout(mudiff_ctx* h, int R, int m) {
   L.inv = take(C * 8);
   L.status = take(C * 4);
   L.inner = take(C * 4);
-  L.reorth = take(C * 4);
   L.run = take(C * 4);
   L.jdone = take(C * 4);
   L.iters = take(C * 4);
@@ -763,22 +879,13 @@ static int enqueue_cycle(GmresRun& G, int check_every, bool host_checks) {
                     G.h->plan.d_partoff};
     if (nb > 0) {
       if (pending)
-        hipLaunchKernelGGL(k_gs_dots<true>, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, j, pa);
+        hipLaunchKernelGGL(k_dg_dots<true>, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, j, pa, 1);
       else
-        hipLaunchKernelGGL(k_gs_dots<false>, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, j, pa);
+        hipLaunchKernelGGL(k_dg_dots<false>, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, j, pa, 1);
       switch (G.rpt) {  // chunk rows per thread
-        case 1:
-          hipLaunchKernelGGL(k_gs_update<1>, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, j);
-          hipLaunchKernelGGL(k_gs_reorth<1>, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, j);
-          break;
-        case 2:
-          hipLaunchKernelGGL(k_gs_update<2>, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, j);
-          hipLaunchKernelGGL(k_gs_reorth<2>, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, j);
-          break;
-        default:
-          hipLaunchKernelGGL(k_gs_update<4>, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, j);
-          hipLaunchKernelGGL(k_gs_reorth<4>, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, j);
-          break;
+        case 1: hipLaunchKernelGGL(k_dg_update<1>, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, j); break;
+        case 2: hipLaunchKernelGGL(k_dg_update<2>, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, j); break;
+        default: hipLaunchKernelGGL(k_dg_update<4>, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, j); break;
       }
     }
     HIP_TRY(hipGetLastError());
@@ -788,6 +895,19 @@ static int enqueue_cycle(GmresRun& G, int check_every, bool host_checks) {
       HIP_TRY(hipStreamSynchronize(G.st));
       if (n_in <= 0) break;
     }
+  }
+  {  // columns that ran all m steps: Hessenberg column m-1 from the last candidate V[m]
+    GState sg = s;
+    unsigned nb = (unsigned)G.L.n_chunks;
+    if (G.n_compact > 0) {
+      sg.ckmap = G.d_ckmap;
+      nb = (unsigned)G.ckmap.size();
+    }
+    PendingApply pa{};
+    if (nb > 0)
+      hipLaunchKernelGGL(k_dg_dots<false>, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, s.m, pa, 0);
+    hipLaunchKernelGGL(k_dg_flush, dim3(s.C), dim3(GS_THREADS), 0, G.st, s);
+    HIP_TRY(hipGetLastError());
   }
   hipLaunchKernelGGL(k_cycle_solve, dim3(s.C), dim3(64), 0, G.st, s);
   hipLaunchKernelGGL(k_update_x, dim3(eb), dim3(256), 0, G.st, s, s.NT, G.d_rowcol);
@@ -837,9 +957,11 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
   s.ck = (int64_t*)(w + L.ck);
   s.ckmap = nullptr;
   G.d_ckmap = (int32_t*)(w + L.ckmap);
+  s.sl = 2 * restart + 2;
   s.P1 = (cplx*)(w + L.P1);
-  s.P2 = (cplx*)(w + L.P2);
   s.H = (cplx*)(w + L.H);
+  s.Hraw = (cplx*)(w + L.Hraw);
+  s.htent = (cplx*)(w + L.htent);
   s.g = (cplx*)(w + L.g);
   s.cs = (double*)(w + L.cs);
   s.sn = (cplx*)(w + L.sn);
@@ -849,7 +971,6 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
   s.inv = (double*)(w + L.inv);
   s.status = (int32_t*)(w + L.status);
   s.inner = (int32_t*)(w + L.inner);
-  s.reorth = (int32_t*)(w + L.reorth);
   s.run = (int32_t*)(w + L.run);
   s.jdone = (int32_t*)(w + L.jdone);
   s.iters = (int32_t*)(w + L.iters);

@@ -277,7 +277,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--graph", action="store_true", help="replay GMRES cycles as HIP graphs")
+    ap.add_argument("--graph", dest="graph", action="store_true", default=True,
+                    help="replay each GMRES restart cycle as a captured HIP graph (default)")
+    ap.add_argument("--no-graph", dest="graph", action="store_false",
+                    help="enqueue every GMRES kernel from the host")
     ap.add_argument("--kernel-only", type=int, default=0, metavar="REPS",
                     help="profiling mode: build the tables, run REPS operator applies, exit")
     ap.add_argument("--workload", default="one_rhs",

@@ -213,6 +213,74 @@ __device__ __forceinline__ cplx lane_chunk_sum(const DevView& v, const cplx* __r
   return w;
 }
 
+// ------------------------------------------------------------------ lane reductions
+// Reduce-scatter of NV doubles over the 64 lanes of a wave: lane l ends with
+// the sum over all lanes of value l >> (6 - log2 NV).  At each step the lanes
+// pair up and each keeps one half of the remaining values (the upper half
+// where the step's lane bit is set) plus its partner's copy of that half.
+// Steps 32 and 16 use the gfx950 lane swaps (v_permlane32/16_swap), which hand
+// every lane both of its addends at once; steps 8, 4, 2, 1 read the partner by
+// DPP (row mirror, half-row mirror, quad permutations: partners differ in the
+// step's bit, and the partner sets stay disjoint).  Steps past NV are plain
+// sums over the remaining lanes.  All VALU: no LDS traffic.
+template <int CTRL>
+__device__ __forceinline__ double dpp_read(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+template <int O>
+__device__ __forceinline__ double lane_partner(double v) {
+  if constexpr (O == 8) return dpp_read<0x140>(v);       // row_mirror: l <-> 15 - l
+  else if constexpr (O == 4) return dpp_read<0x141>(v);  // row_half_mirror: l <-> 7 - l
+  else if constexpr (O == 2) return dpp_read<0x4E>(v);   // quad_perm [2,3,0,1]
+  else return dpp_read<0xB1>(v);                          // quad_perm [1,0,3,2]
+}
+
+// a in the lower, b in the upper lane half (of 64 for O = 32, of each 32 for
+// O = 16): returns own + partner's copy of the half the lane keeps.
+template <int O>
+__device__ __forceinline__ double swap_add(double a, double b) {
+  if constexpr (O == 32) {
+    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(a), __double2loint(b), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(a), __double2hiint(b), false, false);
+    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+  } else {
+    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(a), __double2loint(b), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(a), __double2hiint(b), false, false);
+    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+  }
+}
+
+template <int O, int CNT>
+__device__ __forceinline__ void rs_dpp_step(double* val, int lane) {
+  if constexpr (CNT > 1) {
+    const bool upper = (lane & O) != 0;
+#pragma unroll
+    for (int k = 0; k < CNT / 2; ++k) {
+      const double send = upper ? val[k] : val[CNT / 2 + k];
+      const double keep = upper ? val[CNT / 2 + k] : val[k];
+      val[k] = keep + lane_partner<O>(send);
+    }
+  } else {
+    val[0] += lane_partner<O>(val[0]);
+  }
+}
+
+template <int NV>
+__device__ __forceinline__ void lane_reduce_scatter(double* val, int lane) {
+  static_assert(NV >= 8 && NV <= 64 && (NV & (NV - 1)) == 0, "NV: 8, 16, 32 or 64");
+#pragma unroll
+  for (int k = 0; k < NV / 2; ++k) val[k] = swap_add<32>(val[k], val[NV / 2 + k]);
+#pragma unroll
+  for (int k = 0; k < NV / 4; ++k) val[k] = swap_add<16>(val[k], val[NV / 4 + k]);
+  rs_dpp_step<8, NV / 4>(val, lane);
+  rs_dpp_step<4, (NV / 8 > 1 ? NV / 8 : 1)>(val, lane);
+  rs_dpp_step<2, (NV / 16 > 1 ? NV / 16 : 1)>(val, lane);
+  rs_dpp_step<1, (NV / 32 > 1 ? NV / 32 : 1)>(val, lane);
+}
+
 // ------------------------------------------------------------------ internal API
 // Operator apply on R columns. `part`/`counters` come from the caller's scratch
 // (mudiff_matvec_workspace_size); counters must be zero on entry and are left

@@ -182,21 +182,22 @@ __device__ __forceinline__ void chunk_dots2(const GState& s, int j, int64_t o, i
         cmacc(aw[u], vv, wr);
       }
     }
+    // the 4 GS_BATCH sums reduce-scattered: lane l holds value l >> 2
+    double val[4 * GS_BATCH];
 #pragma unroll
     for (int u = 0; u < GS_BATCH; ++u) {
-      au[u].x = wave_sum(au[u].x);
-      au[u].y = wave_sum(au[u].y);
-      aw[u].x = wave_sum(aw[u].x);
-      aw[u].y = wave_sum(aw[u].y);
+      val[4 * u] = au[u].x;
+      val[4 * u + 1] = au[u].y;
+      val[4 * u + 2] = aw[u].x;
+      val[4 * u + 3] = aw[u].y;
     }
-    if (lane == 0) {
-#pragma unroll
-      for (int u = 0; u < GS_BATCH; ++u) {
-        const int i = i0 + u * GS_WAVES;
-        if (i < j) {
-          part[i] = au[u];
-          if (has_w) part[j + i] = aw[u];
-        }
+    lane_reduce_scatter<4 * GS_BATCH>(val, lane);
+    if ((lane & 3) == 0) {
+      const int vi = lane >> 2, u = vi >> 2, comp = vi & 3;
+      const int i = i0 + u * GS_WAVES;
+      if (i < j && (comp < 2 || has_w)) {
+        double* dst = reinterpret_cast<double*>(part + (comp < 2 ? i : j + i));
+        dst[comp & 1] = val[0];
       }
     }
   }

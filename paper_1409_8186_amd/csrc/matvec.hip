@@ -253,23 +253,10 @@ __global__ __launch_bounds__(64) void k_apply_lane(
       for (int m = nu; m < n; ++m) cmac(acc[m], tm, z[m - nu]);
     }
   }
-  // reduce-scatter over the lanes: at offset o the lanes with bit o set keep
-  // the upper half of the remaining values, the others the lower half
   double val[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) val[k] = k < 2 * n ? ((k & 1) ? acc[k >> 1].y : acc[k >> 1].x) : 0.0;
-#pragma unroll
-  for (int cnt = NV, o = 32; cnt > 1; cnt >>= 1, o >>= 1) {
-    const bool upper = (lane & o) != 0;
-#pragma unroll
-    for (int k = 0; k < cnt / 2; ++k) {
-      const double send = upper ? val[k] : val[cnt / 2 + k];
-      const double keep = upper ? val[cnt / 2 + k] : val[k];
-      val[k] = keep + __shfl_xor(send, o, 64);
-    }
-  }
-#pragma unroll
-  for (int o = (1 << SH) >> 1; o > 0; o >>= 1) val[0] += __shfl_xor(val[0], o, 64);
+  lane_reduce_scatter<NV>(val, lane);
   const int vi = lane >> SH;
   if ((lane & ((1 << SH) - 1)) == 0 && vi < 2 * n) {
     double* pr = reinterpret_cast<double*>(part + (int64_t)r * part_total + partoff[p] + (int64_t)c * n);

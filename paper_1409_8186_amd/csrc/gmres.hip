@@ -233,9 +233,9 @@ __device__ double block_sum(double v, double* sred) {
 // last >= 0) into out[] (LDS); returns, in every thread, sum |out[i]|^2 over
 // i < nd.  Loads run along the slots (coalesced).  Up to 8 chunks: a thread
 // adds one slot over all chunks in chunk order.  More: wave g adds chunks g,
-// g + GS_WAVES, ... for 64 slots at a time and the wave sums are added in wave
-// order through tmp[GS_WAVES * 64].  Every workgroup of a column so derives
-// the same values.
+// g + GS_WAVES, ... (16 loads in flight) for 64 slots at a time, and the wave
+// sums are added in wave order through tmp[GS_WAVES * 64].  Every workgroup
+// of a column so derives the same values.
 __device__ double column_sums(const cplx* __restrict__ pbase, int sl, int nck, int ns, int last,
                               int nd, cplx* out, cplx* tmp, double* sred) {
   const int tid = threadIdx.x;
@@ -260,15 +260,15 @@ __device__ double column_sums(const cplx* __restrict__ pbase, int sl, int nck, i
       cplx a = cmk(0.0, 0.0);
       if (i < ns) {
         const cplx* p = pbase + ((i == ns - 1 && last >= 0) ? last : i);
-        for (int k0 = g; k0 < nck; k0 += 8 * GS_WAVES) {
-          cplx t[8];
+        for (int k0 = g; k0 < nck; k0 += 16 * GS_WAVES) {
+          cplx t[16];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
+          for (int u = 0; u < 16; ++u) {
             const int k = k0 + u * GS_WAVES;
             t[u] = k < nck ? p[(int64_t)k * sl] : cmk(0.0, 0.0);
           }
 #pragma unroll
-          for (int u = 0; u < 8; ++u)
+          for (int u = 0; u < 16; ++u)
             if (k0 + u * GS_WAVES < nck) a = cadd(a, t[u]);
         }
       }
@@ -497,31 +497,31 @@ __global__ __launch_bounds__(GS_THREADS) void k_dg_update(GState s, int j) {
   }
   // tentative column j, entries h_i = (g_i - sum_k Hraw[k][i] s_k) / rho,
   // g = [z; g_j], k from i-1 (Hessenberg) to j-1: waves 1.. while thread 0 takes
-  // the Givens step; eight lanes per entry split the sum over k and add their
-  // parts by shuffles.
+  // the Givens step; four lanes per entry split the sum over k (16 loads in
+  // flight each) and add their parts by shuffles.
   const int w0 = j >= 1 ? 1 : 0;
   const int wv = (int)threadIdx.x >> 6;
   if (wv < w0) return;
-  const int lane = threadIdx.x & 63, kl = lane & 7;
-  const int per_pass = (GS_WAVES - w0) * 8;
+  const int lane = threadIdx.x & 63, kl = lane & 3;
+  const int per_pass = (GS_WAVES - w0) * 16;
   for (int i0 = 0; i0 <= j; i0 += per_pass) {
-    const int i = i0 + (wv - w0) * 8 + (lane >> 3);
+    const int i = i0 + (wv - w0) * 16 + (lane >> 2);
     cplx hs = cmk(0.0, 0.0);
     if (i <= j) {
-      for (int k = (i > 0 ? i - 1 : 0) + kl; k < j; k += 32) {
-        cplx t[4];
+      for (int k = (i > 0 ? i - 1 : 0) + kl; k < j; k += 64) {
+        cplx t[16];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int kk = min(k + 8 * u, j - 1);
+        for (int u = 0; u < 16; ++u) {
+          const int kk = min(k + 4 * u, j - 1);
           t[u] = Hr[(int64_t)kk * m1 + i];
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (k + 8 * u < j) hs = cadd(hs, cmul(t[u], cl[k + 8 * u]));
+        for (int u = 0; u < 16; ++u)
+          if (k + 4 * u < j) hs = cadd(hs, cmul(t[u], cl[k + 4 * u]));
       }
     }
 #pragma unroll
-    for (int o = 1; o < 8; o <<= 1) {
+    for (int o = 1; o < 4; o <<= 1) {
       hs.x += __shfl_xor(hs.x, o, 64);
       hs.y += __shfl_xor(hs.y, o, 64);
     }

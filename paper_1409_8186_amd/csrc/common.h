@@ -89,6 +89,11 @@ struct DevView {
 
 #define LANE_CHUNK 64
 #define LANE_REC 4   // complex values per pair record
+// One-lane work item, int32 words: p, chunk, q_begin, q_end, instance b, its
+// first disk, then int64 at word 6: first unknown of b, unknowns of b, record
+// offset of (p, chunk) in lt, partial-sum offset of (p, chunk); word 14: 0.
+// All the kernel needs before its vector loads comes from this one record.
+#define LANE_ITEM_INTS 16
 #define LANE_NMAX 12
 
 // Column c = b * R + r of a packed [B][R][N_b] vector starts at
@@ -117,7 +122,8 @@ struct MatvecPlan {
   int n_items = 0;
   size_t lds_bytes = 0;
   int64_t part_total = 0;       // complex partials per right-hand side
-  int32_t* d_items = nullptr;   // [n_items][4] : p, chunk, q_begin, q_end
+  int32_t* d_items = nullptr;   // [n_items][4] : p, chunk, q_begin, q_end (generic);
+                                // [n_items][LANE_ITEM_INTS] on the one-lane path
   int32_t* d_nchunk = nullptr;  // [M_all]
   int64_t* d_partoff = nullptr; // [M_all]
 };
@@ -294,6 +300,11 @@ int apply_operator_split(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, c
                          int32_t* counters, const int32_t* active, hipStream_t s,
                          bool* pending);
 size_t apply_scratch_bytes(mudiff_ctx* h, int R);
+// Lane-record layout of the one-lane-per-pair apply: total size in complex
+// values (0 when N is not uniform or out of range), the common N, and per disk
+// the offset of its first chunk.
+int64_t lane_layout(int B, const int64_t* disk_off, const int32_t* n_modes, int* lane_N,
+                    std::vector<int64_t>* ltoff);
 int ensure_plan(mudiff_ctx* h, hipStream_t s);
 // Schedule for R applies made current (one-lane/generic plan, or the MFMA
 // schedule uploaded into `scratch`, the apply scratch later passed as `part`).

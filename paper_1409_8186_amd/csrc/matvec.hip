@@ -204,26 +204,27 @@ __global__ __launch_bounds__(APPLY_THREADS) void k_apply(
 template <int N>
 __global__ __launch_bounds__(64) void k_apply_lane(
     DevView v, int R, const cplx* __restrict__ x, cplx* __restrict__ part, int64_t part_total,
-    const int32_t* __restrict__ items, const int64_t* __restrict__ partoff,
-    const int32_t* __restrict__ active) {
+    const int32_t* __restrict__ items, const int32_t* __restrict__ active) {
   constexpr int n = 2 * N + 1, S = 2 * N;
   constexpr int NV = 2 * n <= 8 ? 8 : (2 * n <= 16 ? 16 : (2 * n <= 32 ? 32 : 64));
   constexpr int SH = NV == 8 ? 3 : (NV == 16 ? 2 : (NV == 32 ? 1 : 0));  // 6 - log2 NV
-  const int it = blockIdx.x, r = blockIdx.y;
-  const int p = items[4 * it], c = items[4 * it + 1], jb = items[4 * it + 2], je = items[4 * it + 3];
-  const int b = v.inst[p];
+  const int r = blockIdx.y;
+  const int32_t* itp = items + (int64_t)LANE_ITEM_INTS * blockIdx.x;
+  const int p = itp[0], jb = itp[2], je = itp[3], b = itp[4];
   if (active && active[b * R + r] == 0) return;
   const int lane = threadIdx.x;
-  const int64_t d0 = v.idisk[b];
-  const int64_t i0 = v.imode[b];
-  const int64_t cb = col_base(v.imode, b, R, r);
+  const int64_t d0 = itp[5];
+  const int64_t i0 = *reinterpret_cast<const int64_t*>(itp + 6);
+  const int64_t cb = (int64_t)R * i0 + (int64_t)r * *reinterpret_cast<const int64_t*>(itp + 8);
+  const int64_t recb = *reinterpret_cast<const int64_t*>(itp + 10);
+  const int64_t pb = *reinterpret_cast<const int64_t*>(itp + 12);
   const int j = jb + lane;
   cplx acc[n];
 #pragma unroll
   for (int m = 0; m < n; ++m) acc[m] = cmk(0.0, 0.0);
   if (j < je) {
     const int q = (int)(d0 + j + ((d0 + j) >= p ? 1 : 0));
-    const cplx* __restrict__ rec = v.lt + v.ltoff[p] + (int64_t)c * (LANE_CHUNK * LANE_REC) + lane;
+    const cplx* __restrict__ rec = v.lt + recb + lane;
     const int64_t iq = (int64_t)(q - d0) * n;  // uniform N: moff[q] = (q - d0) n
     const cplx h0 = rec[0];
     cplx H = rec[LANE_CHUNK];
@@ -259,7 +260,7 @@ __global__ __launch_bounds__(64) void k_apply_lane(
   lane_reduce_scatter<NV>(val, lane);
   const int vi = lane >> SH;
   if ((lane & ((1 << SH) - 1)) == 0 && vi < 2 * n) {
-    double* pr = reinterpret_cast<double*>(part + (int64_t)r * part_total + partoff[p] + (int64_t)c * n);
+    double* pr = reinterpret_cast<double*>(part + (int64_t)r * part_total + pb);
     pr[vi] = val[0];
   }
 }
@@ -815,7 +816,7 @@ int apply_set_tail(mudiff_ctx* h, int R, bool tail, cplx* scratch, hipStream_t s
 namespace {
 typedef void (*apply_fn)(DevView, int, const cplx*, cplx*, int, cplx*, int64_t, int32_t*,
                          const int32_t*, const int32_t*, const int64_t*, const int32_t*, int, int, int);
-typedef void (*lane_fn)(DevView, int, const cplx*, cplx*, int64_t, const int32_t*, const int64_t*,
+typedef void (*lane_fn)(DevView, int, const cplx*, cplx*, int64_t, const int32_t*,
                         const int32_t*);
 
 struct Variant {
@@ -858,6 +859,7 @@ const LaneVariant* find_lane(int n) {
 // layout, from the batch description alone (also used to size workspaces).
 struct PlanHost {
   int lane = 0;  // 1: one-lane-per-pair kernel (uniform N = nspec)
+  int item_ints = 4;
   int waves = 1;
   int bt = 4, nspec = -1, zs = 0, ts = 0, ppcap = 1;
   size_t lds = 0;
@@ -898,8 +900,17 @@ void make_plan(int B, const int64_t* idisk, const int32_t* N, PlanHost& P) {
     if (N[p] != N[0]) uniform = false;
   if (uniform && N[0] <= LANE_NMAX && find_lane(N[0])) {
     P.lane = 1;
+    P.item_ints = LANE_ITEM_INTS;
     P.nspec = N[0];
     const int np = 2 * N[0] + 1;
+    int lane_N = -1;
+    std::vector<int64_t> ltoff;
+    lane_layout(B, idisk, N, &lane_N, &ltoff);
+    auto push64 = [&](int64_t v) {
+      P.items.push_back((int32_t)(v & 0xffffffff));
+      P.items.push_back((int32_t)(v >> 32));
+    };
+    int64_t i0 = 0;  // first unknown of instance b
     for (int b = 0; b < B; ++b) {
       const int64_t d0 = idisk[b], Mb = idisk[b + 1] - d0;
       const int64_t n = (Mb - 1 + LANE_CHUNK - 1) / LANE_CHUNK;  // 0 for M = 1
@@ -913,8 +924,16 @@ void make_plan(int B, const int64_t* idisk, const int32_t* N, PlanHost& P) {
           P.items.push_back((int32_t)c);
           P.items.push_back((int32_t)jb);
           P.items.push_back((int32_t)je);
+          P.items.push_back(b);
+          P.items.push_back((int32_t)d0);
+          push64(i0);
+          push64(Mb * np);
+          push64(ltoff[p] + c * (int64_t)(LANE_CHUNK * LANE_REC));
+          push64(P.poff[p] + c * np);
+          push64(0);
         }
       }
+      i0 += Mb * np;
     }
     return;
   }
@@ -985,7 +1004,7 @@ int ensure_plan(mudiff_ctx* h, hipStream_t s) {
   P.ppcap = H.ppcap;
   P.part_total = H.part;
   P.lds_bytes = H.lds;
-  P.n_items = (int)(H.items.size() / 4);
+  P.n_items = (int)(H.items.size() / H.item_ints);
   P.waves = H.waves;
   P.ready = true;
   return MUDIFF_OK;
@@ -1022,7 +1041,7 @@ int apply_operator_split(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, c
     if (!lv) return fail(MUDIFF_ERR_INVALID, "no operator kernel variant");
     if (P.n_items > 0) {
       hipLaunchKernelGGL(lv->fn, dim3(P.n_items, R), dim3(64), 0, s, h->dv, R, x, part,
-                         P.part_total, P.d_items, P.d_partoff, active);
+                         P.part_total, P.d_items, active);
       HIP_TRY(hipGetLastError());
     }
     *pending = true;  // the chunk sums still have to be added and finalised
@@ -1046,7 +1065,7 @@ int apply_operator(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, cplx* p
     if (!lv) return fail(MUDIFF_ERR_INVALID, "no operator kernel variant");
     if (P.n_items > 0) {
       hipLaunchKernelGGL(lv->fn, dim3(P.n_items, R), dim3(64), 0, s, h->dv, R, x, part,
-                         P.part_total, P.d_items, P.d_partoff, active);
+                         P.part_total, P.d_items, active);
       HIP_TRY(hipGetLastError());
     }
     const int64_t total = (int64_t)R * h->N_all;

@@ -37,6 +37,16 @@ APPLY_SRC = [os.path.join(ROOT, "paper_1409_8186_amd", "csrc", f)
              for f in ("matvec.hip", "common.h", "tables.hip")]
 
 
+def measured_peaks(achieved, kind="fp64_fma"):
+    """The same rate against what this device reaches on a plain loop of the
+    dominant instruction (FP64 FMA or FP64 MFMA), and its copy bandwidth."""
+    from paper_1409_8186_amd import probe
+    peak = probe(kind)
+    return {"peak_measured": peak, "frac_of_measured": achieved / peak,
+            "peak_measured_kind": kind + " loop (mudiff_probe)",
+            "copy_GBps_measured": probe("copy", 1 << 30)}
+
+
 def apply_source_sha():
     """Digest of the sources that define the one-RHS apply kernels and their data."""
     h = hashlib.sha256()
@@ -164,10 +174,12 @@ def other_workload(args):
         return ev0.elapsed_time(ev1) / 1e3 / reps
 
     def mfma_roofline(flops, t, cfg):
-        return {"bound": "mfma", "achieved": flops / t / 1e12, "peak": 78.6, "unit": "TFLOP/s",
-                "frac": flops / t / 1e12 / 78.6, "traffic": None,
-                "kernel": "k_apply_mfma + k_apply_mfma_finish", "tile": cfg,
-                "algorithmic_flops_per_launch": flops}
+        r = {"bound": "mfma", "achieved": flops / t / 1e12, "peak": 78.6, "unit": "TFLOP/s",
+             "frac": flops / t / 1e12 / 78.6, "traffic": None,
+             "kernel": "k_apply_mfma + k_apply_mfma_finish", "tile": cfg,
+             "algorithmic_flops_per_launch": flops}
+        r.update(measured_peaks(flops / t / 1e12, "fp64_mfma"))
+        return r
 
     if args.workload == "multi_rhs":
         cl = synth.multi_rhs()
@@ -411,6 +423,7 @@ def main():
                      "algorithmic_flops_per_launch": flops,
                      "algorithmic_bytes_per_launch": algorithmic_bytes(cl.n_modes)},
     }
+    out["roofline"].update(measured_peaks(achieved))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cl, iters)
     print(json.dumps(out), flush=True)

@@ -228,6 +228,29 @@ int mudiff_grad(mudiff_t h, int R, const double* beta, int n_rec, const double* 
                 void* workspace, size_t ws_bytes,
                 double* loss, double* d_centers, double* d_radii, double* d_k, void* stream);
 
+/* ---------------------------------------------------------------- device probes */
+
+/* Achievable throughput of the current device, so that kernel rates can be
+ * reported against measured as well as published peaks.  Not part of the
+ * method (the paper has no counterpart).
+ *   kind       MUDIFF_PROBE_FP64_FMA   loop of independent FP64 fused multiply-adds
+ *                                      on the vector ALUs (8 workgroups per CU)
+ *              MUDIFF_PROBE_FP64_MFMA  loop of v_mfma_f64_16x16x4f64 on the matrix
+ *                                      cores (8 independent accumulators per wave)
+ *              MUDIFF_PROBE_COPY       device-to-device copy of `bytes` bytes
+ *                                      (rounded down to a multiple of 16)
+ *   bytes      COPY only (>= 16); ignored otherwise
+ *   workspace  device, 256-byte aligned, >= mudiff_probe_workspace_size(kind, bytes)
+ *              bytes (its contents are overwritten)
+ *   rate       [host] out: TFLOP/s (FMA, MFMA) or GB/s of read + write (COPY)
+ * One warm-up launch, then three launches timed with HIP events on `stream`;
+ * synchronises the stream.  Errors: MUDIFF_ERR_INVALID (kind, NULL pointer,
+ * alignment), MUDIFF_ERR_NOMEM (workspace too small), MUDIFF_ERR_DEVICE. */
+enum { MUDIFF_PROBE_FP64_FMA = 0, MUDIFF_PROBE_FP64_MFMA = 1, MUDIFF_PROBE_COPY = 2 };
+size_t mudiff_probe_workspace_size(int kind, size_t bytes);
+int mudiff_probe(int kind, size_t bytes, void* workspace, size_t ws_bytes, double* rate,
+                 void* stream);
+
 /* Thread-local message of the last failing call on this thread. */
 const char* mudiff_last_error(void);
 

@@ -17,6 +17,9 @@ def __getattr__(name):
     if name in ("Problem",):
         from .api import Problem
         return Problem
+    if name == "probe":
+        from .api import probe
+        return probe
     if name == "FarFieldMisfit":
         from .autograd import FarFieldMisfit
         return FarFieldMisfit

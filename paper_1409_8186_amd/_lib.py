@@ -37,12 +37,15 @@ SIGNATURES = {
     "mudiff_grad_workspace_size": (_sz, [_vp, _i32, _i32, _i32, _i32]),
     "mudiff_grad": (_i32, [_vp, _i32, _vp, _i32, _vp, _vp, _i32, _d, _i32, _i32, _vp, _sz,
                            _vp, _vp, _vp, _vp, _vp]),
+    "mudiff_probe_workspace_size": (_sz, [_i32, _sz]),
+    "mudiff_probe": (_i32, [_i32, _sz, _vp, _sz, ctypes.POINTER(_d), _vp]),
     "mudiff_last_error": (ctypes.c_char_p, []),
 }
 
 STATUS = {0: "OK", 1: "INVALID", 2: "OVERLAP", 3: "NOMEM", 4: "DEVICE", 5: "NOT_CONVERGED"}
 OP_L, OP_A = 0, 1
 X0, GRAPH = 1, 2
+PROBE_FP64_FMA, PROBE_FP64_MFMA, PROBE_COPY = 0, 1, 2
 
 
 class MudiffError(RuntimeError):

@@ -241,3 +241,17 @@ class Problem:
                                      maxit, flags, _p(ws), ws.numel(), _p(loss), _p(dc), _p(da),
                                      _p(dk), _stream()))
         return loss, dc.view(M, 2), da, dk
+
+
+def probe(kind: str, nbytes: int = 1 << 30, device: str = "cuda") -> float:
+    """Achievable device throughput: kind "fp64_fma" or "fp64_mfma" (TFLOP/s),
+    or "copy" (GB/s of read + write over an nbytes copy).  Synchronises."""
+    k = {"fp64_fma": L.PROBE_FP64_FMA, "fp64_mfma": L.PROBE_FP64_MFMA, "copy": L.PROBE_COPY}[kind]
+    lib = L.load()
+    n = lib.mudiff_probe_workspace_size(k, nbytes)
+    if n == 0:
+        raise L.MudiffError(1, "probe: no device or bad kind")
+    ws = torch.empty(int(n), dtype=torch.uint8, device=device)
+    rate = ctypes.c_double(0.0)
+    L.check(lib.mudiff_probe(k, nbytes, _p(ws), ws.numel(), ctypes.byref(rate), _stream()))
+    return rate.value

@@ -659,10 +659,20 @@ __global__ void k_scale_v0(GState s, int64_t nrows_total, const int32_t* __restr
 }
 
 // End of a cycle: y = R^{-1} g (upper-triangular Hessenberg after rotations).
-// One wavefront per column: back substitution with the column-oriented
-// update g_k -= R_{k,i} y_i spread over the lanes, g held in LDS.
+// One wavefront per column.  Up to 64 steps: the triangle is staged into LDS
+// in one sweep (16 columns of loads in flight), lane k keeps g_k and 1 / R_kk
+// in registers, and each step broadcasts g_i and 1 / R_ii from lane i and
+// updates g_k -= R_ki y_i in the lanes k < i, with no barrier.  Longer cycles:
+// column-oriented update with g in LDS.
+#define SOLVE_SMALL 64
+__device__ __forceinline__ double lane_bcast(double v, int l) {  // l wave-uniform
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
 __global__ __launch_bounds__(64) void k_cycle_solve(GState s) {
   __shared__ cplx gl[MUDIFF_MAX_RESTART + 1];
+  __shared__ cplx tri[SOLVE_SMALL * (SOLVE_SMALL + 1) / 2];
   const int c = blockIdx.x;
   const int lane = threadIdx.x;
   const int n = s.run[c] ? s.jdone[c] : 0;
@@ -670,6 +680,37 @@ __global__ __launch_bounds__(64) void k_cycle_solve(GState s) {
   const cplx* Hc = s.H + (int64_t)c * m1 * s.m;
   const cplx* gc = s.g + (int64_t)c * m1;
   cplx* yc = s.y + (int64_t)c * s.m;
+  if (n <= SOLVE_SMALL) {
+    // column i, rows 0..i, at tri[i (i + 1) / 2 + k]
+    for (int i0 = 0; i0 < n; i0 += 16) {
+      cplx t[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int i = min(i0 + u, n - 1);
+        t[u] = lane <= i ? Hc[(int64_t)i * m1 + lane] : cmk(0.0, 0.0);
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int i = i0 + u;
+        if (i < n && lane <= i) tri[i * (i + 1) / 2 + lane] = t[u];
+      }
+    }
+    cplx g = lane < n ? gc[lane] : cmk(0.0, 0.0);
+    __syncthreads();
+    cplx rinv = cmk(0.0, 0.0);  // 1 / R_kk, 0 for a zero pivot
+    if (lane < n) {
+      const cplx d = tri[lane * (lane + 1) / 2 + lane];
+      if (d.x != 0.0 || d.y != 0.0) rinv = cdiv(cmk(1.0, 0.0), d);
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      const cplx rik = lane < i ? tri[i * (i + 1) / 2 + lane] : cmk(0.0, 0.0);
+      const cplx gi = cmk(lane_bcast(g.x, i), lane_bcast(g.y, i));
+      const cplx yi = cmul(gi, cmk(lane_bcast(rinv.x, i), lane_bcast(rinv.y, i)));
+      if (lane == 0) yc[i] = yi;
+      if (lane < i) g = csub(g, cmul(rik, yi));
+    }
+    return;
+  }
   for (int k = lane; k < n; k += 64) gl[k] = gc[k];
   __syncthreads();
   for (int i = n - 1; i >= 0; --i) {

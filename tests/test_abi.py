@@ -103,3 +103,15 @@ def test_null_handle_rejected(lib):
     assert st == 1
     assert lib.mudiff_matvec_workspace_size(None, 1) == 0
     assert lib.mudiff_gmres_workspace_size(None, 1, 30, 0) == 0
+
+
+def test_probe_validation(lib):
+    rate = ctypes.c_double(-1.0)
+    buf = ctypes.create_string_buffer(512)
+    # unknown kind and NULL pointers are rejected before any device work
+    assert lib.mudiff_probe(7, 0, buf, 512, ctypes.byref(rate), None) == 1
+    assert lib.mudiff_probe(0, 0, None, 0, ctypes.byref(rate), None) == 1
+    assert lib.mudiff_probe(0, 0, buf, 512, None, None) == 1
+    assert lib.mudiff_probe(2, 8, buf, 512, ctypes.byref(rate), None) == 1   # copy < 16 bytes
+    assert rate.value == -1.0
+    assert lib.mudiff_probe_workspace_size(9, 0) == 0

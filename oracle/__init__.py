@@ -18,6 +18,8 @@ What it computes, each module citing the paper passage it writes out:
   solve      dense LU solve of L rho = -U, restarted GMRES(m)     (sec. 5)
   gradient   far-field misfit, its adjoint gradient w.r.t.
              centers, radii and k, and central differences        (derived from sec. 4-5)
+  dort       far-field mirror matrix F, time-reversal matrix      (sec. 7, Example III)
+             T = conj(F)^T F, its eigen-decomposition, Herglotz waves
 
 Everything is float64 / complex128, written as the plain definition: dense
 matrices, library LU and Bessel routines, no blocking, fusion or reordering.
@@ -27,4 +29,4 @@ identities of the truncated system, brute force).  The one output with no
 such pin is the GMRES iteration count (parity unpinned; the converged
 solution is pinned against LU).
 """
-from . import geometry, bessel, operator, rhs, farfield, solve, gradient  # noqa: F401
+from . import geometry, bessel, operator, rhs, farfield, solve, gradient, dort  # noqa: F401

@@ -183,6 +183,18 @@ def differentiation(seed: int = 5, n_cfg: int = 32, M: int = 100, R: int = 64,
     return out
 
 
+def dort_example(n_alpha: int = 512) -> Cluster:
+    """Three small sound-soft disks of the time-reversal example: centers
+    (0,20), (10,-10), (-10,-20), radii 0.02, 0.01, 0.005, k = 2 pi;
+    N_p = ceil(k a_p) + 3 = 4; mirror angles 2 pi j / n_alpha (incidences and,
+    shifted by pi, receivers)."""
+    centers = np.array([[0.0, 20.0], [10.0, -10.0], [-10.0, -20.0]])
+    radii = np.array([0.02, 0.01, 0.005])
+    k = 2.0 * math.pi
+    al = uniform_angles(n_alpha)
+    return Cluster(centers, radii, _ceil_rule(k, radii, 3), k, al, al + math.pi, "dort")
+
+
 def small_random(seed: int, M: int, r_lo: float, r_hi: float, box: float, gap: float,
                  k: float, extra: int, R: int = 1, n_theta: int = 64) -> Cluster:
     """Small seeded cluster for tests: N_p = ceil(k a_p) + extra."""

@@ -355,3 +355,85 @@ def test_gradient_translation_and_scaling():
     assert abs(np.sum(dc[:, 1]) - ty) < 1e-10 * (abs(ty) + np.max(np.abs(dc)))
     lhs = np.sum(base.centers * dc) + np.sum(base.radii * da) - base.k * dk
     assert abs(lhs - scale) < 1e-10 * (abs(scale) + np.max(np.abs(dc)))
+
+
+# ------------------------------------------- time reversal (sec. 7, Example III)
+def test_dort_single_disk_spectrum():
+    """One disk: F = D C D with D a unitary diagonal (the translation phases)
+    and C circulant in alpha_i - alpha_j, whose eigenvalues are N_alpha times
+    the Mie far-field coefficients -e^{-i pi/4} sqrt(2/(pi k)) J_m(ka)/H_m(ka)
+    (times (-1)^m from the receiver shift by pi).  So T = conj(F)^T F has the
+    2N+1 eigenvalues N_alpha^2 |c_m|^2 and is zero otherwise."""
+    from oracle import dort
+    center, a, k, N, n_alpha = (0.8, -0.3), 0.7, 5.0, 6, 32
+    F = dort.farfield_matrix(np.array([center]), np.array([a]), np.array([N]), k, n_alpha)
+    w, V = dort.eig_desc(dort.time_reversal(F))
+    m = np.arange(-N, N + 1)
+    c = -np.exp(-0.25j * np.pi) * np.sqrt(2.0 / (np.pi * k)) * sp.jv(m, k * a) / sp.hankel1(m, k * a)
+    ref = np.sort(n_alpha ** 2 * np.abs(c) ** 2)[::-1]
+    np.testing.assert_allclose(w[:2 * N + 1], ref, rtol=1e-11)
+    assert np.max(np.abs(w[2 * N + 1:])) < 1e-12 * w[0]
+    # unit eigenvectors
+    np.testing.assert_allclose(np.linalg.norm(V, axis=0), 1.0, rtol=1e-12)
+
+
+def test_dort_farfield_matrix_is_symmetric():
+    """With receivers at alpha_i + pi, reciprocity a(theta; beta) =
+    a(beta + pi; theta + pi) makes F complex symmetric (F = F^T) for any
+    configuration; receivers at alpha_i would not."""
+    from oracle import dort
+    cl = synth.small_random(21, 5, 0.3, 0.8, 6.0, 0.3, 4.0, 4)
+    F = dort.farfield_matrix(cl.centers, cl.radii, cl.n_modes, cl.k, 24)
+    assert rel(F, F.T) < 1e-12
+    al = dort.mirror_angles(24)
+    from oracle import gradient
+    F_same = gradient.forward(cl.centers, cl.radii, cl.n_modes, cl.k, al, al).T
+    assert rel(F_same, F_same.T) > 1e-3
+
+
+def test_dort_time_reversal_is_hermitian_psd():
+    from oracle import dort
+    cl = synth.small_random(22, 4, 0.3, 0.8, 6.0, 0.3, 4.0, 3)
+    F = dort.farfield_matrix(cl.centers, cl.radii, cl.n_modes, cl.k, 20)
+    T = dort.time_reversal(F)
+    assert rel(T, T.conj().T) < 1e-15
+    w, V = dort.eig_desc(T)
+    assert w[-1] > -1e-12 * w[0]
+    assert np.all(np.diff(w) <= 0)
+    assert rel(V @ np.diag(w) @ V.conj().T, T) < 1e-12
+    # the nonzero spectrum of T is that of F F^H (brute force: singular values of F)
+    s = np.linalg.svd(F, compute_uv=False)
+    np.testing.assert_allclose(w[:len(s)], s ** 2, rtol=1e-10, atol=1e-12 * w[0])
+
+
+@pytest.mark.parametrize("m", [0, 1, -3, 7])
+def test_herglotz_jacobi_anger(m):
+    """f_j = e^{-i m alpha_j}: u_I(x) -> int_0^{2pi} e^{i k r cos(alpha - phi)} e^{-i m alpha}
+    d alpha = 2 pi i^m J_m(k r) e^{-i m phi}; the trapezoid rule is exact to
+    rounding once N_alpha exceeds k r + |m| by a margin."""
+    from oracle import dort
+    k, n_alpha = 2 * math.pi, 128
+    rng = np.random.default_rng(5)
+    pts = rng.uniform(-4, 4, size=(20, 2))
+    f = np.exp(-1j * m * dort.mirror_angles(n_alpha))
+    u = dort.herglotz(n_alpha, f, k, pts)
+    r, phi = np.hypot(pts[:, 0], pts[:, 1]), np.arctan2(pts[:, 1], pts[:, 0])
+    ref = 2 * np.pi * (1j ** m) * sp.jv(m, k * r) * np.exp(-1j * m * phi)
+    assert np.max(np.abs(u - ref)) < 1e-12
+
+
+def test_dort_example_three_significant_eigenvalues_and_focusing():
+    """The paper's example: three small scatterers give three significant
+    eigenvalues of T, and the Herglotz wave of each of the three eigenvectors
+    focuses on one obstacle, from the most to the least reflecting (largest
+    to smallest radius).  512 mirror cells resolve the Herglotz waves out to
+    |x| ~ N_alpha / (2k) ~ 40, beyond the obstacles at distance 20-22."""
+    from oracle import dort
+    cl = synth.dort_example(512)
+    F = dort.farfield_matrix(cl.centers, cl.radii, cl.n_modes, cl.k, 512)
+    w, V = dort.eig_desc(dort.time_reversal(F))
+    assert w[2] > 100 * w[3]
+    for j in range(3):
+        u = np.abs(dort.herglotz(512, V[:, j], cl.k, cl.centers))
+        assert np.argmax(u) == j
+        assert u[j] > 2 * np.max(np.delete(u, j))

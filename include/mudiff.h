@@ -228,6 +228,47 @@ int mudiff_grad(mudiff_t h, int R, const double* beta, int n_rec, const double* 
                 void* workspace, size_t ws_bytes,
                 double* loss, double* d_centers, double* d_radii, double* d_k, void* stream);
 
+/* ---------------------------------------------------------------- time reversal */
+
+/* The far-field mirror of sec. 7 (Example III): N_alpha cells at the angles
+ * alpha_j send plane waves (incidence alpha_j) and record the far field in the
+ * opposite direction, so that F[i][j] = a(alpha_i + pi; alpha_j) (obtained with
+ * mudiff_gmres for R = N_alpha incidences and mudiff_farfield at the angles
+ * alpha_i + pi).  In these calls F is passed as X = F^T, X[j][i] = F[i][j]:
+ * complex128, row-major [n][m] (n incidences, m receivers), which is exactly
+ * mudiff_farfield's output for one instance. */
+
+/* T = conj(F)^T F, the time-reversal matrix: T[a][b] = sum_i conj(X[a][i]) X[b][i].
+ *   X  device complex128 [n][m];  T  device complex128 [n][n] (Hermitian, PSD)
+ * FP64 matrix-core kernel; enqueues on `stream`.  Errors: MUDIFF_ERR_INVALID. */
+int mudiff_tro(int n, int m, const void* X, void* T, void* stream);
+
+/* Eigen-decomposition of T = conj(F)^T F without forming T: one-sided Jacobi
+ * rotations orthogonalise the columns of F (rows of X), F V = [f_1 .. f_n] with
+ * f_j^H f_k = 0, so T V = V diag(|f_j|^2).
+ *   X          device complex128 [n][m], overwritten with (F V)^T
+ *   w          device double [n]: eigenvalues of T, decreasing
+ *   evec       device complex128 [n][n]: row j = unit eigenvector of w[j]
+ *              (component index second), unique up to a phase where w[j] is simple
+ *   max_sweeps >= 1; tol > 0: a column pair counts as orthogonal when
+ *              |f_p^H f_q| <= tol |f_p| |f_q| (or below 1e-28 |F|_F^2)
+ *   workspace  device, 256-byte aligned, >= mudiff_tro_eigh_workspace_size(n, m)
+ *   sweeps     [host] out: sweeps used, or -1 if max_sweeps ran out (the outputs
+ *              are then the last iterate)
+ * Synchronises `stream` once per sweep.  Errors: MUDIFF_ERR_INVALID,
+ * MUDIFF_ERR_NOMEM, MUDIFF_ERR_DEVICE. */
+size_t mudiff_tro_eigh_workspace_size(int n, int m);
+int mudiff_tro_eigh(int n, int m, void* X, double* w, void* evec, int max_sweeps, double tol,
+                    void* workspace, size_t ws_bytes, int32_t* sweeps, void* stream);
+
+/* Discrete Herglotz waves u_t(x) = sum_j h f_t[j] exp(i k (x_1 cos alpha_j + x_2 sin alpha_j))
+ * (sec. 7) for n_f parameter vectors at n_pts points.
+ *   alpha  device double [n_alpha];  f  device complex128 [n_f][n_alpha]
+ *   pts    device double [n_pts][2];  u  device complex128 [n_f][n_pts]
+ * Errors: MUDIFF_ERR_INVALID (sizes, k <= 0, NULL pointers). */
+int mudiff_herglotz(int n_alpha, const double* alpha, int n_f, const void* f, double k, double h,
+                    int n_pts, const double* pts, void* u, void* stream);
+
 /* ---------------------------------------------------------------- device probes */
 
 /* Achievable throughput of the current device, so that kernel rates can be

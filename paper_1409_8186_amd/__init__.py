@@ -17,9 +17,9 @@ def __getattr__(name):
     if name in ("Problem",):
         from .api import Problem
         return Problem
-    if name == "probe":
-        from .api import probe
-        return probe
+    if name in ("probe", "tro", "tro_eigh", "herglotz"):
+        from . import api
+        return getattr(api, name)
     if name == "FarFieldMisfit":
         from .autograd import FarFieldMisfit
         return FarFieldMisfit

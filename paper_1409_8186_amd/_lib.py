@@ -37,6 +37,11 @@ SIGNATURES = {
     "mudiff_grad_workspace_size": (_sz, [_vp, _i32, _i32, _i32, _i32]),
     "mudiff_grad": (_i32, [_vp, _i32, _vp, _i32, _vp, _vp, _i32, _d, _i32, _i32, _vp, _sz,
                            _vp, _vp, _vp, _vp, _vp]),
+    "mudiff_tro": (_i32, [_i32, _i32, _vp, _vp, _vp]),
+    "mudiff_tro_eigh_workspace_size": (_sz, [_i32, _i32]),
+    "mudiff_tro_eigh": (_i32, [_i32, _i32, _vp, _vp, _vp, _i32, _d, _vp, _sz,
+                               ctypes.POINTER(ctypes.c_int32), _vp]),
+    "mudiff_herglotz": (_i32, [_i32, _vp, _i32, _vp, _d, _d, _i32, _vp, _vp, _vp]),
     "mudiff_probe_workspace_size": (_sz, [_i32, _sz]),
     "mudiff_probe": (_i32, [_i32, _sz, _vp, _sz, ctypes.POINTER(_d), _vp]),
     "mudiff_last_error": (ctypes.c_char_p, []),

@@ -215,6 +215,21 @@ class Problem:
                                          _p(out), _stream()))
         return out.view(self.B * R, th.numel())
 
+    # ----------------------------------------------------------- time reversal
+    def mirror_farfield(self, n_alpha: int, restart: int = 50, tol: float = 1e-12,
+                        maxit: int = 20000, graph: bool = False):
+        """Far-field matrix of a mirror with n_alpha cells (sec. 7, Example III):
+        incidences alpha_j = 2 pi j / n_alpha, receivers at alpha_i + pi.  One
+        instance only.  Returns (X, flag, relres, iters) with X[j, i] = F[i, j] =
+        a(alpha_i + pi; alpha_j), shape [n_alpha, n_alpha]."""
+        if self.B != 1:
+            raise ValueError("mirror_farfield takes a handle with one instance")
+        al = 2.0 * np.pi * np.arange(n_alpha) / n_alpha
+        rho, flag, relres, iters, _ = self.gmres(betas=al[None, :], restart=restart, tol=tol,
+                                                 maxit=maxit, graph=graph)
+        X = self.farfield(rho, al + np.pi, R=n_alpha)
+        return X, flag, relres, iters
+
     # ----------------------------------------------------------- gradient
     def grad_workspace(self, R: int, n_rec: int, restart: int, flags: int = 0) -> torch.Tensor:
         n = self.lib.mudiff_grad_workspace_size(self.h, R, n_rec, restart, flags)
@@ -255,3 +270,45 @@ def probe(kind: str, nbytes: int = 1 << 30, device: str = "cuda") -> float:
     rate = ctypes.c_double(0.0)
     L.check(lib.mudiff_probe(k, nbytes, _p(ws), ws.numel(), ctypes.byref(rate), _stream()))
     return rate.value
+
+
+def tro(X: torch.Tensor) -> torch.Tensor:
+    """T = conj(F)^T F for X = F^T ([n, m] complex128 on the device): T[a, b] =
+    sum_i conj(X[a, i]) X[b, i]."""
+    X = X.contiguous()
+    n, m = X.shape
+    lib = L.load()
+    T = torch.empty(n, n, dtype=torch.complex128, device=X.device)
+    L.check(lib.mudiff_tro(n, m, _p(X), _p(T), _stream()))
+    return T
+
+
+def tro_eigh(X: torch.Tensor, tol: float = 1e-13, max_sweeps: int = 60):
+    """Eigenvalues (decreasing) and unit eigenvectors (rows) of T = conj(F)^T F
+    from X = F^T by one-sided Jacobi; X is not modified.  Returns (w, evec, sweeps)."""
+    Xw = X.contiguous().clone()
+    n, m = Xw.shape
+    lib = L.load()
+    w = torch.empty(n, dtype=torch.float64, device=Xw.device)
+    ev = torch.empty(n, n, dtype=torch.complex128, device=Xw.device)
+    ws = torch.empty(int(lib.mudiff_tro_eigh_workspace_size(n, m)), dtype=torch.uint8,
+                     device=Xw.device)
+    sweeps = ctypes.c_int32(0)
+    L.check(lib.mudiff_tro_eigh(n, m, _p(Xw), _p(w), _p(ev), max_sweeps, tol, _p(ws), ws.numel(),
+                                ctypes.byref(sweeps), _stream()))
+    return w, ev, sweeps.value
+
+
+def herglotz(alpha, f: torch.Tensor, k: float, points, h: float | None = None) -> torch.Tensor:
+    """u_t(x) = sum_j h f[t, j] exp(i k (x_1 cos alpha_j + x_2 sin alpha_j)) at
+    points [P, 2]; f [n_f, n_alpha] (or [n_alpha]); h defaults to 2 pi / n_alpha."""
+    dev = f.device
+    al = torch.as_tensor(alpha, dtype=torch.float64).to(dev).contiguous()
+    F = f.reshape(-1, al.numel()).to(torch.complex128).contiguous()
+    pts = torch.as_tensor(points, dtype=torch.float64).to(dev).reshape(-1, 2).contiguous()
+    h = 2.0 * np.pi / al.numel() if h is None else h
+    u = torch.empty(F.shape[0], pts.shape[0], dtype=torch.complex128, device=dev)
+    lib = L.load()
+    L.check(lib.mudiff_herglotz(al.numel(), _p(al), F.shape[0], _p(F), float(k), float(h),
+                                pts.shape[0], _p(pts), _p(u), _stream()))
+    return u

@@ -1,0 +1,289 @@
+// Time reversal with a far-field mirror (paper sec. 7, Example III): the
+// time-reversal matrix T = conj(F)^T F of the mirror's far-field matrix F, the
+// eigen-decomposition of T, and the Herglotz waves its eigenvectors define.
+//
+// Layout: X[j][i] = F[i][j] = a(theta_i; alpha_j), i.e. row j of X is the far
+// field of incidence j at the receivers (mudiff_farfield's output for one
+// instance with R = n incidences), so the columns of F are contiguous rows.
+#include "common.h"
+
+namespace {
+
+typedef double dort_d4 __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------ T = F^H F
+// T[a][b] = sum_i conj(X[a][i]) X[b][i]:
+//   Re T = Xr Xr^T + Xi Xi^T,   Im T = Xr Xi^T - Xi Xr^T,
+// four real 16x4-by-4x16 products per step of four receivers on the FP64
+// matrix cores (v_mfma_f64_16x16x4f64: lane l holds A[l%16][l/16],
+// B[l/16][l%16] and D[4v + l/16][l%16]).  One wave per 16x16 tile of T.
+__global__ __launch_bounds__(64) void k_tro(int n, int m, const cplx* __restrict__ X,
+                                            cplx* __restrict__ T) {
+  const int a0 = blockIdx.x * 16, b0 = blockIdx.y * 16;
+  const int lane = threadIdx.x, r = lane & 15, kk = lane >> 4;
+  const int ra = a0 + r, rb = b0 + r;
+  dort_d4 accr = {0.0, 0.0, 0.0, 0.0}, acci = {0.0, 0.0, 0.0, 0.0};
+  for (int i0 = 0; i0 < m; i0 += 4) {
+    const int i = i0 + kk;
+    const cplx xa = (ra < n && i < m) ? X[(int64_t)ra * m + i] : cmk(0.0, 0.0);
+    const cplx xb = (rb < n && i < m) ? X[(int64_t)rb * m + i] : cmk(0.0, 0.0);
+    accr = __builtin_amdgcn_mfma_f64_16x16x4f64(xa.x, xb.x, accr, 0, 0, 0);
+    accr = __builtin_amdgcn_mfma_f64_16x16x4f64(xa.y, xb.y, accr, 0, 0, 0);
+    acci = __builtin_amdgcn_mfma_f64_16x16x4f64(xa.x, xb.y, acci, 0, 0, 0);
+    acci = __builtin_amdgcn_mfma_f64_16x16x4f64(-xa.y, xb.x, acci, 0, 0, 0);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int a = a0 + 4 * v + kk, b = b0 + r;
+    if (a < n && b < n) T[(int64_t)a * n + b] = cmk(accr[v], acci[v]);
+  }
+}
+
+// ------------------------------------------------------------------ one-sided Jacobi
+// The eigenpairs of T = F^H F follow from orthogonalising the columns of F by
+// plane rotations (Hestenes): F J_1 J_2 ... = F V with orthogonal columns, so
+// V^H T V = diag(|F v_j|^2).  A sweep pairs every two columns once, in rounds
+// of n'/2 disjoint pairs (circle method over n' = n rounded up to even; the
+// pairs with the padding index are skipped), one workgroup per pair and one
+// launch per round: the pairs of a round touch disjoint columns, so no
+// synchronisation between workgroups is needed.
+constexpr int JAC_THREADS = 256;
+
+__device__ __forceinline__ void round_pair(int r, int k, int np, int* p, int* q) {
+  if (k == 0) {
+    *p = r;
+    *q = np - 1;
+  } else {
+    *p = (r + k) % (np - 1);
+    *q = (r - k + np - 1) % (np - 1);
+  }
+  if (*p > *q) {
+    const int t = *p;
+    *p = *q;
+    *q = t;
+  }
+}
+
+// Sum over the block of four per-thread values, in a fixed order.
+__device__ void block_sum4(double (&v)[4], double* sred) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[c] += __shfl_xor(v[c], o, 64);
+    if (lane == 0) sred[c * (JAC_THREADS / 64) + wv] = v[c];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    double t = 0.0;
+    for (int k = 0; k < JAC_THREADS / 64; ++k) t += sred[c * (JAC_THREADS / 64) + k];
+    v[c] = t;
+  }
+}
+
+// Rotation of columns p, q of F (rows p, q of X) and of V (rows p, q of Vt)
+// that zeroes gamma = f_p^H f_q: with zeta = (beta - alpha) / (2 |gamma|),
+// t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), cs = 1 / sqrt(1 + t^2),
+// s = t cs gamma / |gamma|:  [f_p, f_q] <- [f_p, f_q] [[cs, s], [-conj(s), cs]].
+// Pairs with |gamma| <= tol sqrt(alpha beta) or <= floor (noise level of F)
+// count as orthogonal.  n_rot counts the rotations of the sweep.
+__global__ __launch_bounds__(JAC_THREADS) void k_jacobi_round(int n, int m, int np, int r,
+                                                              cplx* __restrict__ X,
+                                                              cplx* __restrict__ Vt, double tol,
+                                                              const double* __restrict__ fro2,
+                                                              int32_t* __restrict__ n_rot) {
+  __shared__ double sred[4 * (JAC_THREADS / 64)];
+  int p, q;
+  round_pair(r, blockIdx.x, np, &p, &q);
+  if (q >= n) return;  // pair with the padding index
+  cplx* fp = X + (int64_t)p * m;
+  cplx* fq = X + (int64_t)q * m;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};  // alpha, beta, Re gamma, Im gamma
+  for (int i = threadIdx.x; i < m; i += JAC_THREADS) {
+    const cplx a = fp[i], b = fq[i];
+    v[0] += cabs2(a);
+    v[1] += cabs2(b);
+    v[2] = fma(a.x, b.x, fma(a.y, b.y, v[2]));
+    v[3] = fma(a.x, b.y, fma(-a.y, b.x, v[3]));
+  }
+  block_sum4(v, sred);
+  const double al = v[0], be = v[1];
+  const double g = sqrt(v[2] * v[2] + v[3] * v[3]);
+  const double floor_abs = 1e-28 * fro2[0];  // (~n eps ||F||)^2: noise columns
+  if (!(g > tol * sqrt(al * be)) || !(g > floor_abs)) return;
+  const double zeta = (be - al) / (2.0 * g);
+  const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double cs = 1.0 / sqrt(1.0 + t * t);
+  const cplx s = cmk(t * cs * v[2] / g, t * cs * v[3] / g);
+  const cplx sc = cconj(s);
+  for (int i = threadIdx.x; i < m; i += JAC_THREADS) {
+    const cplx a = fp[i], b = fq[i];
+    fp[i] = csub(cscale(a, cs), cmul(sc, b));
+    fq[i] = cadd(cmul(s, a), cscale(b, cs));
+  }
+  cplx* vp = Vt + (int64_t)p * n;
+  cplx* vq = Vt + (int64_t)q * n;
+  for (int i = threadIdx.x; i < n; i += JAC_THREADS) {
+    const cplx a = vp[i], b = vq[i];
+    vp[i] = csub(cscale(a, cs), cmul(sc, b));
+    vq[i] = cadd(cmul(s, a), cscale(b, cs));
+  }
+  if (threadIdx.x == 0) atomicAdd(n_rot, 1);
+}
+
+// Vt = I.
+__global__ void k_eye(int n, cplx* __restrict__ Vt) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (int64_t)n * n) return;
+  Vt[g] = cmk((g / n) == (g % n) ? 1.0 : 0.0, 0.0);
+}
+
+// Squared norm of every row of X (one workgroup per row); with `total`, the
+// squared Frobenius norm of X instead (one workgroup).
+__global__ __launch_bounds__(JAC_THREADS) void k_row_norms(int n, int m, const cplx* __restrict__ X,
+                                                           double* __restrict__ out, int total) {
+  __shared__ double sred[4 * (JAC_THREADS / 64)];
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  const int64_t len = total ? (int64_t)n * m : m;
+  const cplx* x = total ? X : X + (int64_t)blockIdx.x * m;
+  for (int64_t i = threadIdx.x; i < len; i += JAC_THREADS) v[0] += cabs2(x[i]);
+  block_sum4(v, sred);
+  if (threadIdx.x == 0) out[total ? 0 : blockIdx.x] = v[0];
+}
+
+// Eigenvalues in decreasing order (ties by index) and the matching rows of Vt:
+// one workgroup per eigenpair computes its rank and copies its row.
+__global__ __launch_bounds__(JAC_THREADS) void k_rank_sort(int n, const double* __restrict__ wr,
+                                                           const cplx* __restrict__ Vt,
+                                                           double* __restrict__ w,
+                                                           cplx* __restrict__ evec) {
+  __shared__ int cnt[JAC_THREADS / 64];
+  const int j = blockIdx.x;
+  const double wj = wr[j];
+  int c = 0;
+  for (int i = threadIdx.x; i < n; i += JAC_THREADS) c += (wr[i] > wj || (wr[i] == wj && i < j));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = c;
+  __syncthreads();
+  int rank = 0;
+  for (int k = 0; k < JAC_THREADS / 64; ++k) rank += cnt[k];
+  if (threadIdx.x == 0) w[rank] = wj;
+  for (int i = threadIdx.x; i < n; i += JAC_THREADS) evec[(int64_t)rank * n + i] = Vt[(int64_t)j * n + i];
+}
+
+// ------------------------------------------------------------------ Herglotz waves
+// u[t][x] = sum_j h f[t][j] exp(i k (x_1 cos alpha_j + x_2 sin alpha_j)), one
+// thread per point, up to HG_F parameter vectors per pass sharing each
+// exponential; (cos, sin) of the angles staged in LDS in blocks.
+constexpr int HG_THREADS = 256;
+constexpr int HG_F = 4;
+constexpr int HG_ANG = 512;
+
+__global__ __launch_bounds__(HG_THREADS) void k_herglotz(int n_alpha, const double* __restrict__ alpha,
+                                                         int n_f, const cplx* __restrict__ f, double k,
+                                                         double h, int n_pts,
+                                                         const double* __restrict__ pts,
+                                                         cplx* __restrict__ u) {
+  __shared__ double cs[HG_ANG], sn[HG_ANG];
+  const int P = blockIdx.x * HG_THREADS + threadIdx.x;
+  const int t0 = blockIdx.y * HG_F;
+  const int nf = min(HG_F, n_f - t0);
+  const double x1 = P < n_pts ? pts[2 * P] : 0.0, x2 = P < n_pts ? pts[2 * P + 1] : 0.0;
+  cplx acc[HG_F];
+#pragma unroll
+  for (int t = 0; t < HG_F; ++t) acc[t] = cmk(0.0, 0.0);
+  for (int j0 = 0; j0 < n_alpha; j0 += HG_ANG) {
+    const int nj = min(HG_ANG, n_alpha - j0);
+    __syncthreads();
+    for (int j = threadIdx.x; j < nj; j += HG_THREADS) sincos(alpha[j0 + j], &sn[j], &cs[j]);
+    __syncthreads();
+    for (int j = 0; j < nj; ++j) {
+      const cplx e = cexpi(k * (x1 * cs[j] + x2 * sn[j]));
+#pragma unroll
+      for (int t = 0; t < HG_F; ++t)
+        if (t < nf) cmac(acc[t], f[(int64_t)(t0 + t) * n_alpha + j0 + j], e);
+    }
+  }
+  if (P < n_pts) {
+#pragma unroll
+    for (int t = 0; t < HG_F; ++t)
+      if (t < nf) u[(int64_t)(t0 + t) * n_pts + P] = cscale(acc[t], h);
+  }
+}
+
+}  // namespace
+
+extern "C" int mudiff_tro(int n, int m, const void* X, void* T, void* stream) {
+  if (n < 1 || m < 1) return fail(MUDIFF_ERR_INVALID, "n, m must be >= 1");
+  if (!X || !T) return fail(MUDIFF_ERR_INVALID, "NULL argument");
+  const unsigned g = (unsigned)((n + 15) / 16);
+  hipLaunchKernelGGL(k_tro, dim3(g, g), dim3(64), 0, (hipStream_t)stream, n, m, (const cplx*)X,
+                     (cplx*)T);
+  HIP_TRY(hipGetLastError());
+  return MUDIFF_OK;
+}
+
+extern "C" size_t mudiff_tro_eigh_workspace_size(int n, int m) {
+  if (n < 1 || m < 1) return 0;
+  return align256((size_t)n * n * 16) + align256((size_t)n * 8) + 256 + 256;
+}
+
+extern "C" int mudiff_tro_eigh(int n, int m, void* X, double* w, void* evec, int max_sweeps,
+                               double tol, void* workspace, size_t ws_bytes, int32_t* sweeps,
+                               void* stream) {
+  if (n < 1 || m < 1) return fail(MUDIFF_ERR_INVALID, "n, m must be >= 1");
+  if (!X || !w || !evec || !workspace || !sweeps) return fail(MUDIFF_ERR_INVALID, "NULL argument");
+  if (max_sweeps < 1) return fail(MUDIFF_ERR_INVALID, "max_sweeps < 1");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(MUDIFF_ERR_INVALID, "tol must be > 0");
+  const size_t need = mudiff_tro_eigh_workspace_size(n, m);
+  if (ws_bytes < need) return fail(MUDIFF_ERR_NOMEM, "tro_eigh workspace needs " + std::to_string(need) + " bytes");
+  if (((uintptr_t)workspace) & 255) return fail(MUDIFF_ERR_INVALID, "workspace must be 256-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  char* wsp = (char*)workspace;
+  cplx* Vt = (cplx*)wsp;
+  double* wr = (double*)(wsp + align256((size_t)n * n * 16));
+  double* fro2 = (double*)(wsp + align256((size_t)n * n * 16) + align256((size_t)n * 8));
+  int32_t* n_rot = (int32_t*)((char*)fro2 + 256);
+  cplx* Xc = (cplx*)X;
+  const int np = n + (n & 1);
+  hipLaunchKernelGGL(k_eye, dim3((unsigned)(((int64_t)n * n + 255) / 256)), dim3(256), 0, s, n, Vt);
+  hipLaunchKernelGGL(k_row_norms, dim3(1), dim3(JAC_THREADS), 0, s, n, m, (const cplx*)Xc, fro2, 1);
+  HIP_TRY(hipGetLastError());
+  int used = -1;
+  for (int sweep = 1; sweep <= max_sweeps; ++sweep) {
+    int rc = launch_fill_zero(n_rot, 4, s);
+    if (rc != MUDIFF_OK) return rc;
+    for (int r = 0; r < np - 1; ++r)
+      hipLaunchKernelGGL(k_jacobi_round, dim3((unsigned)(np / 2)), dim3(JAC_THREADS), 0, s, n, m, np,
+                         r, Xc, Vt, tol, (const double*)fro2, n_rot);
+    HIP_TRY(hipGetLastError());
+    int32_t h_rot = 0;
+    HIP_TRY(hipMemcpyAsync(&h_rot, n_rot, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (h_rot == 0) {
+      used = sweep;
+      break;
+    }
+  }
+  hipLaunchKernelGGL(k_row_norms, dim3((unsigned)n), dim3(JAC_THREADS), 0, s, n, m, (const cplx*)Xc, wr, 0);
+  hipLaunchKernelGGL(k_rank_sort, dim3((unsigned)n), dim3(JAC_THREADS), 0, s, n, (const double*)wr,
+                     (const cplx*)Vt, w, (cplx*)evec);
+  HIP_TRY(hipGetLastError());
+  *sweeps = used;
+  return MUDIFF_OK;
+}
+
+extern "C" int mudiff_herglotz(int n_alpha, const double* alpha, int n_f, const void* f, double k,
+                               double h, int n_pts, const double* pts, void* u, void* stream) {
+  if (n_alpha < 1 || n_f < 1 || n_pts < 0) return fail(MUDIFF_ERR_INVALID, "bad sizes");
+  if (!(k > 0.0) || !std::isfinite(k) || !std::isfinite(h)) return fail(MUDIFF_ERR_INVALID, "k must be > 0, h finite");
+  if (!alpha || !f || (n_pts > 0 && (!pts || !u))) return fail(MUDIFF_ERR_INVALID, "NULL argument");
+  if (n_pts == 0) return MUDIFF_OK;
+  dim3 grid((unsigned)((n_pts + HG_THREADS - 1) / HG_THREADS), (unsigned)((n_f + HG_F - 1) / HG_F));
+  hipLaunchKernelGGL(k_herglotz, grid, dim3(HG_THREADS), 0, (hipStream_t)stream, n_alpha, alpha, n_f,
+                     (const cplx*)f, k, h, n_pts, pts, (cplx*)u);
+  HIP_TRY(hipGetLastError());
+  return MUDIFF_OK;
+}

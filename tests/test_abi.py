@@ -115,3 +115,21 @@ def test_probe_validation(lib):
     assert lib.mudiff_probe(2, 8, buf, 512, ctypes.byref(rate), None) == 1   # copy < 16 bytes
     assert rate.value == -1.0
     assert lib.mudiff_probe_workspace_size(9, 0) == 0
+
+
+def test_time_reversal_validation(lib):
+    buf = ctypes.create_string_buffer(4096)
+    sweeps = ctypes.c_int32(7)
+    assert lib.mudiff_tro(0, 4, buf, buf, None) == 1
+    assert lib.mudiff_tro(4, 4, None, buf, None) == 1
+    assert lib.mudiff_tro_eigh_workspace_size(0, 3) == 0
+    need = lib.mudiff_tro_eigh_workspace_size(8, 8)
+    assert need >= 8 * 8 * 16
+    assert lib.mudiff_tro_eigh(8, 8, buf, buf, buf, 0, 1e-13, buf, 4096, ctypes.byref(sweeps), None) == 1
+    assert lib.mudiff_tro_eigh(8, 8, buf, buf, buf, 10, 0.0, buf, 4096, ctypes.byref(sweeps), None) == 1
+    assert lib.mudiff_tro_eigh(8, 8, buf, buf, buf, 10, 1e-13, buf, need - 1, ctypes.byref(sweeps), None) == 3
+    assert lib.mudiff_tro_eigh(8, 8, buf, buf, buf, 10, 1e-13, buf, 4096, None, None) == 1
+    assert sweeps.value == 7
+    assert lib.mudiff_herglotz(0, buf, 1, buf, ctypes.c_double(1.0), ctypes.c_double(0.1), 4, buf, buf, None) == 1
+    assert lib.mudiff_herglotz(4, buf, 1, buf, ctypes.c_double(-1.0), ctypes.c_double(0.1), 4, buf, buf, None) == 1
+    assert lib.mudiff_herglotz(4, buf, 1, buf, ctypes.c_double(1.0), ctypes.c_double(0.1), 4, None, buf, None) == 1

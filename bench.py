@@ -90,6 +90,11 @@ def traffic_per_launch():
     return float(f.group(1)) + float(w.group(1))
 
 
+def _blas_threads():
+    from threadpoolctl import threadpool_info
+    return int(max([d.get("num_threads", 1) for d in threadpool_info()] + [1]))
+
+
 def cpu_baseline(cl, n_iter_gpu):
     """The oracle on the host: dense assembly of the preconditioned EFIE matrix,
     then oracle GMRES iterations (dense ZGEMV + modified Gram-Schmidt); the
@@ -236,6 +241,8 @@ def other_workload(args):
                                   "mean_s_per_instance": per_inst_single,
                                   "extrapolated_s_all": per_inst_single * len(insts),
                                   "batched_speedup": per_inst_single * len(insts) / t_s}}
+    if args.workload == "dort":
+        return dort_workload(base)
     pairs = synth.differentiation()
     bases = [b for b, _ in pairs]
     betas = np.stack([b.betas for b in bases])
@@ -283,6 +290,84 @@ def other_workload(args):
                               "batched_speedup": (len(bases) / t) / (4 / t1)}}
 
 
+def dort_workload(base):
+    """The time-reversal experiment of the paper's Example III (sound-soft): far-field
+    mirror matrix F (batched GMRES over the 512 incidences + far field at the 512
+    opposite directions), T = conj(F)^T F, its eigen-decomposition, and the
+    Herglotz waves of the three leading eigenvectors on a 201 x 201 grid."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1409_8186_amd import Problem, herglotz, tro, tro_eigh
+    n_alpha = 512
+    cl = synth.dort_example(n_alpha)
+    g = np.linspace(-30.0, 30.0, 201)
+    grid = np.stack(np.meshgrid(g, g, indexing="ij"), axis=-1).reshape(-1, 2)
+    grid_d = torch.tensor(grid, device="cuda")
+    al_d = torch.tensor(2.0 * np.pi * np.arange(n_alpha) / n_alpha, device="cuda")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def run():
+        t = {}
+        s0 = time.perf_counter()
+        P = Problem.from_cluster(cl)
+        X, flag, relres, iters = P.mirror_farfield(n_alpha, restart=30, tol=1e-12, maxit=2000)
+        torch.cuda.synchronize()
+        t["farfield_matrix_s"] = time.perf_counter() - s0
+        s1 = time.perf_counter()
+        T = tro(X)
+        torch.cuda.synchronize()
+        t["tro_s"] = time.perf_counter() - s1
+        s2 = time.perf_counter()
+        w, ev, sweeps = tro_eigh(X, tol=1e-13)
+        torch.cuda.synchronize()
+        t["eigh_s"] = time.perf_counter() - s2
+        s3 = time.perf_counter()
+        u = herglotz(al_d, ev[:3].contiguous(), cl.k, grid_d)
+        torch.cuda.synchronize()
+        t["herglotz_s"] = time.perf_counter() - s3
+        t["total_s"] = time.perf_counter() - s0
+        P.close()
+        return t, w, sweeps, int(flag.max()), int(iters.max()), u
+    run()
+    t, w, sweeps, fmax, itmax, u = run()
+    w = w.cpu().numpy()
+    # the Jacobi rounds: per launch, 256 column pairs each read and rewrite two
+    # columns of F (512 complex) and two rows of V (512 complex)
+    launches = sweeps * (n_alpha - 1)
+    bytes_round = (n_alpha // 2) * 2 * 2 * (n_alpha + n_alpha) * 16
+    # the oracle on the host: dense LU solve, T, LAPACK eigh, Herglotz sums
+    from oracle import dort as odort
+    c0 = time.perf_counter()
+    F = odort.farfield_matrix(cl.centers, cl.radii, cl.n_modes, cl.k, n_alpha)
+    wo, Vo = odort.eig_desc(odort.time_reversal(F))
+    for j in range(3):
+        odort.herglotz(n_alpha, Vo[:, j], cl.k, grid)
+    t_cpu = time.perf_counter() - c0
+    out = {**base, "metric": "time per DORT experiment", "value": t["total_s"], "unit": "s",
+           "higher_is_better": False, "ms_per_step": t["total_s"] * 1e3,
+           "config": {"workload": "dort: Example III sound-soft, 3 disks (0,20),(10,-10),(-10,-20), "
+                                  "a=0.02,0.01,0.005, k=2pi, N_p=4, 512 mirror cells, GMRES(30) "
+                                  "to 1e-12 for 512 incidences, T, one-sided Jacobi eigh (tol "
+                                  "1e-13), 3 Herglotz waves on a 201x201 grid over [-30,30]^2",
+                      "gmres_iters_max": itmax, "all_converged": fmax == 0,
+                      "jacobi_sweeps": sweeps,
+                      "eigenvalues_top4": [float(x) for x in w[:4]]},
+           "phases_s": t,
+           "roofline": {"bound": "hbm", "kernel": "k_jacobi_round (one-sided Jacobi round)",
+                        "achieved": bytes_round * launches / t["eigh_s"] / 1e9,
+                        "peak": 8000.0, "unit": "GB/s",
+                        "frac": bytes_round * launches / t["eigh_s"] / 1e9 / 8000.0,
+                        "traffic": None,
+                        "note": "includes launch gaps and the per-sweep host check; "
+                                "the 8 MB of F and V stay in the last-level cache"},
+           "cpu_baseline": {"value": t_cpu, "unit": "s", "cores": _blas_threads(),
+                            "kind": "oracle", "sample": "the whole experiment (LU solve, T, "
+                            "LAPACK eigh, 3 Herglotz waves)"}}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -296,7 +381,7 @@ def main():
     ap.add_argument("--kernel-only", type=int, default=0, metavar="REPS",
                     help="profiling mode: build the tables, run REPS operator applies, exit")
     ap.add_argument("--workload", default="one_rhs",
-                    choices=["one_rhs", "multi_rhs", "uneven", "differentiation"],
+                    choices=["one_rhs", "multi_rhs", "uneven", "differentiation", "dort"],
                     help="one_rhs (default bench line) or a documentation run of another workload")
     ap.add_argument("--solve", action="store_true",
                     help="with --workload multi_rhs: also time the GMRES(50) solve to 1e-8")

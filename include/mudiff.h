@@ -251,7 +251,8 @@ int mudiff_tro(int n, int m, const void* X, void* T, void* stream);
  *   evec       device complex128 [n][n]: row j = unit eigenvector of w[j]
  *              (component index second), unique up to a phase where w[j] is simple
  *   max_sweeps >= 1; tol > 0: a column pair counts as orthogonal when
- *              |f_p^H f_q| <= tol |f_p| |f_q| (or below 1e-28 |F|_F^2)
+ *              |f_p^H f_q| <= tol |f_p| |f_q|, or <= eps |F|_F^2 (the rounding
+ *              level of the entries of T; eps = 2^-52)
  *   workspace  device, 256-byte aligned, >= mudiff_tro_eigh_workspace_size(n, m)
  *   sweeps     [host] out: sweeps used, or -1 if max_sweeps ran out (the outputs
  *              are then the last iterate)

@@ -5,6 +5,8 @@
 // Layout: X[j][i] = F[i][j] = a(theta_i; alpha_j), i.e. row j of X is the far
 // field of incidence j at the receivers (mudiff_farfield's output for one
 // instance with R = n incidences), so the columns of F are contiguous rows.
+#include <algorithm>
+
 #include "common.h"
 
 namespace {
@@ -86,8 +88,12 @@ __device__ void block_sum4(double (&v)[4], double* sred) {
 // that zeroes gamma = f_p^H f_q: with zeta = (beta - alpha) / (2 |gamma|),
 // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), cs = 1 / sqrt(1 + t^2),
 // s = t cs gamma / |gamma|:  [f_p, f_q] <- [f_p, f_q] [[cs, s], [-conj(s), cs]].
-// Pairs with |gamma| <= tol sqrt(alpha beta) or <= floor (noise level of F)
-// count as orthogonal.  n_rot counts the rotations of the sweep.
+// A pair counts as orthogonal when |gamma| <= tol sqrt(alpha beta), or when
+// |gamma| <= eps |F|_F^2, below the rounding level of the entries of T.  The
+// four rows are loaded into registers at once (EPT elements per thread; EPT = 0:
+// rows longer than 8 * JAC_THREADS, streamed twice).  n_rot counts the
+// rotations of the sweep.
+template <int EPT>
 __global__ __launch_bounds__(JAC_THREADS) void k_jacobi_round(int n, int m, int np, int r,
                                                               cplx* __restrict__ X,
                                                               cplx* __restrict__ Vt, double tol,
@@ -99,35 +105,64 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi_round(int n, int m, int 
   if (q >= n) return;  // pair with the padding index
   cplx* fp = X + (int64_t)p * m;
   cplx* fq = X + (int64_t)q * m;
+  cplx* vp = Vt + (int64_t)p * n;
+  cplx* vq = Vt + (int64_t)q * n;
+  constexpr int E = EPT > 0 ? EPT : 1;
+  cplx ra[E], rb[E], va[E], vb[E];
   double v[4] = {0.0, 0.0, 0.0, 0.0};  // alpha, beta, Re gamma, Im gamma
-  for (int i = threadIdx.x; i < m; i += JAC_THREADS) {
-    const cplx a = fp[i], b = fq[i];
+  auto gram = [&](cplx a, cplx b) {
     v[0] += cabs2(a);
     v[1] += cabs2(b);
     v[2] = fma(a.x, b.x, fma(a.y, b.y, v[2]));
     v[3] = fma(a.x, b.y, fma(-a.y, b.x, v[3]));
+  };
+  if constexpr (EPT > 0) {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int i = threadIdx.x + e * JAC_THREADS;
+      ra[e] = i < m ? fp[i] : cmk(0.0, 0.0);
+      rb[e] = i < m ? fq[i] : cmk(0.0, 0.0);
+      va[e] = i < n ? vp[i] : cmk(0.0, 0.0);
+      vb[e] = i < n ? vq[i] : cmk(0.0, 0.0);
+    }
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) gram(ra[e], rb[e]);
+  } else {
+    for (int i = threadIdx.x; i < m; i += JAC_THREADS) gram(fp[i], fq[i]);
   }
   block_sum4(v, sred);
   const double al = v[0], be = v[1];
   const double g = sqrt(v[2] * v[2] + v[3] * v[3]);
-  const double floor_abs = 1e-28 * fro2[0];  // (~n eps ||F||)^2: noise columns
-  if (!(g > tol * sqrt(al * be)) || !(g > floor_abs)) return;
+  if (!(g > tol * sqrt(al * be)) || !(g > 2.220446049250313e-16 * fro2[0])) return;
   const double zeta = (be - al) / (2.0 * g);
   const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
   const double cs = 1.0 / sqrt(1.0 + t * t);
   const cplx s = cmk(t * cs * v[2] / g, t * cs * v[3] / g);
   const cplx sc = cconj(s);
-  for (int i = threadIdx.x; i < m; i += JAC_THREADS) {
-    const cplx a = fp[i], b = fq[i];
-    fp[i] = csub(cscale(a, cs), cmul(sc, b));
-    fq[i] = cadd(cmul(s, a), cscale(b, cs));
-  }
-  cplx* vp = Vt + (int64_t)p * n;
-  cplx* vq = Vt + (int64_t)q * n;
-  for (int i = threadIdx.x; i < n; i += JAC_THREADS) {
-    const cplx a = vp[i], b = vq[i];
-    vp[i] = csub(cscale(a, cs), cmul(sc, b));
-    vq[i] = cadd(cmul(s, a), cscale(b, cs));
+  if constexpr (EPT > 0) {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int i = threadIdx.x + e * JAC_THREADS;
+      if (i < m) {
+        fp[i] = csub(cscale(ra[e], cs), cmul(sc, rb[e]));
+        fq[i] = cadd(cmul(s, ra[e]), cscale(rb[e], cs));
+      }
+      if (i < n) {
+        vp[i] = csub(cscale(va[e], cs), cmul(sc, vb[e]));
+        vq[i] = cadd(cmul(s, va[e]), cscale(vb[e], cs));
+      }
+    }
+  } else {
+    for (int i = threadIdx.x; i < m; i += JAC_THREADS) {
+      const cplx a = fp[i], b = fq[i];
+      fp[i] = csub(cscale(a, cs), cmul(sc, b));
+      fq[i] = cadd(cmul(s, a), cscale(b, cs));
+    }
+    for (int i = threadIdx.x; i < n; i += JAC_THREADS) {
+      const cplx a = vp[i], b = vq[i];
+      vp[i] = csub(cscale(a, cs), cmul(sc, b));
+      vq[i] = cadd(cmul(s, a), cscale(b, cs));
+    }
   }
   if (threadIdx.x == 0) atomicAdd(n_rot, 1);
 }
@@ -139,17 +174,25 @@ __global__ void k_eye(int n, cplx* __restrict__ Vt) {
   Vt[g] = cmk((g / n) == (g % n) ? 1.0 : 0.0, 0.0);
 }
 
-// Squared norm of every row of X (one workgroup per row); with `total`, the
-// squared Frobenius norm of X instead (one workgroup).
-__global__ __launch_bounds__(JAC_THREADS) void k_row_norms(int n, int m, const cplx* __restrict__ X,
-                                                           double* __restrict__ out, int total) {
+// Squared norm of every row of X, one workgroup per row.
+__global__ __launch_bounds__(JAC_THREADS) void k_row_norms(int m, const cplx* __restrict__ X,
+                                                           double* __restrict__ out) {
   __shared__ double sred[4 * (JAC_THREADS / 64)];
   double v[4] = {0.0, 0.0, 0.0, 0.0};
-  const int64_t len = total ? (int64_t)n * m : m;
-  const cplx* x = total ? X : X + (int64_t)blockIdx.x * m;
-  for (int64_t i = threadIdx.x; i < len; i += JAC_THREADS) v[0] += cabs2(x[i]);
+  const cplx* x = X + (int64_t)blockIdx.x * m;
+  for (int i = threadIdx.x; i < m; i += JAC_THREADS) v[0] += cabs2(x[i]);
   block_sum4(v, sred);
-  if (threadIdx.x == 0) out[total ? 0 : blockIdx.x] = v[0];
+  if (threadIdx.x == 0) out[blockIdx.x] = v[0];
+}
+
+// out[0] = sum of in[0..n) (one workgroup, fixed order).
+__global__ __launch_bounds__(JAC_THREADS) void k_sum(int n, const double* __restrict__ in,
+                                                     double* __restrict__ out) {
+  __shared__ double sred[4 * (JAC_THREADS / 64)];
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < n; i += JAC_THREADS) v[0] += in[i];
+  block_sum4(v, sred);
+  if (threadIdx.x == 0) out[0] = v[0];
 }
 
 // Eigenvalues in decreasing order (ties by index) and the matching rows of Vt:
@@ -249,15 +292,27 @@ extern "C" int mudiff_tro_eigh(int n, int m, void* X, double* w, void* evec, int
   cplx* Xc = (cplx*)X;
   const int np = n + (n & 1);
   hipLaunchKernelGGL(k_eye, dim3((unsigned)(((int64_t)n * n + 255) / 256)), dim3(256), 0, s, n, Vt);
-  hipLaunchKernelGGL(k_row_norms, dim3(1), dim3(JAC_THREADS), 0, s, n, m, (const cplx*)Xc, fro2, 1);
+  hipLaunchKernelGGL(k_row_norms, dim3((unsigned)n), dim3(JAC_THREADS), 0, s, m, (const cplx*)Xc, wr);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(JAC_THREADS), 0, s, n, (const double*)wr, fro2);
   HIP_TRY(hipGetLastError());
   int used = -1;
   for (int sweep = 1; sweep <= max_sweeps; ++sweep) {
     int rc = launch_fill_zero(n_rot, 4, s);
     if (rc != MUDIFF_OK) return rc;
-    for (int r = 0; r < np - 1; ++r)
-      hipLaunchKernelGGL(k_jacobi_round, dim3((unsigned)(np / 2)), dim3(JAC_THREADS), 0, s, n, m, np,
-                         r, Xc, Vt, tol, (const double*)fro2, n_rot);
+    const int len = std::max(n, m);
+    for (int r = 0; r < np - 1; ++r) {
+      const dim3 g((unsigned)(np / 2)), b(JAC_THREADS);
+      if (len <= JAC_THREADS)
+        hipLaunchKernelGGL(k_jacobi_round<1>, g, b, 0, s, n, m, np, r, Xc, Vt, tol, (const double*)fro2, n_rot);
+      else if (len <= 2 * JAC_THREADS)
+        hipLaunchKernelGGL(k_jacobi_round<2>, g, b, 0, s, n, m, np, r, Xc, Vt, tol, (const double*)fro2, n_rot);
+      else if (len <= 4 * JAC_THREADS)
+        hipLaunchKernelGGL(k_jacobi_round<4>, g, b, 0, s, n, m, np, r, Xc, Vt, tol, (const double*)fro2, n_rot);
+      else if (len <= 8 * JAC_THREADS)
+        hipLaunchKernelGGL(k_jacobi_round<8>, g, b, 0, s, n, m, np, r, Xc, Vt, tol, (const double*)fro2, n_rot);
+      else
+        hipLaunchKernelGGL(k_jacobi_round<0>, g, b, 0, s, n, m, np, r, Xc, Vt, tol, (const double*)fro2, n_rot);
+    }
     HIP_TRY(hipGetLastError());
     int32_t h_rot = 0;
     HIP_TRY(hipMemcpyAsync(&h_rot, n_rot, 4, hipMemcpyDeviceToHost, s));
@@ -267,7 +322,7 @@ extern "C" int mudiff_tro_eigh(int n, int m, void* X, double* w, void* evec, int
       break;
     }
   }
-  hipLaunchKernelGGL(k_row_norms, dim3((unsigned)n), dim3(JAC_THREADS), 0, s, n, m, (const cplx*)Xc, wr, 0);
+  hipLaunchKernelGGL(k_row_norms, dim3((unsigned)n), dim3(JAC_THREADS), 0, s, m, (const cplx*)Xc, wr);
   hipLaunchKernelGGL(k_rank_sort, dim3((unsigned)n), dim3(JAC_THREADS), 0, s, n, (const double*)wr,
                      (const cplx*)Vt, w, (cplx*)evec);
   HIP_TRY(hipGetLastError());

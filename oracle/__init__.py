@@ -18,6 +18,10 @@ What it computes, each module citing the paper passage it writes out:
   solve      dense LU solve of L rho = -U, restarted GMRES(m)     (sec. 5)
   gradient   far-field misfit, its adjoint gradient w.r.t.
              centers, radii and k, and central differences        (derived from sec. 4-5)
+  operators  the operators M, N, D and identity, combinations,    (sec. 3 formulations,
+             normal-derivative plane-wave coefficients, the        sec. 4.2 block formulas,
+             double-layer far field; EFIE, MFIE, CFIE, BWIE,        Prop. 4, sec. 4.4)
+             sound-hard single- and double-layer equations
   dort       far-field mirror matrix F, time-reversal matrix      (sec. 7, Example III)
              T = conj(F)^T F, its eigen-decomposition, Herglotz waves
 
@@ -29,4 +33,4 @@ identities of the truncated system, brute force).  The one output with no
 such pin is the GMRES iteration count (parity unpinned; the converged
 solution is pinned against LU).
 """
-from . import geometry, bessel, operator, rhs, farfield, solve, gradient, dort  # noqa: F401
+from . import geometry, bessel, operator, rhs, farfield, solve, gradient, dort, operators  # noqa: F401

@@ -437,3 +437,138 @@ def test_dort_example_three_significant_eigenvalues_and_focusing():
         u = np.abs(dort.herglotz(512, V[:, j], cl.k, cl.centers))
         assert np.argmax(u) == j
         assert u[j] > 2 * np.max(np.delete(u, j))
+
+
+# ------------------------------- operators M, N, D and the other formulations
+def _green_derivs(k, x, y, nx, ny):
+    """G = (i/4) H_0(k r) and its normal derivatives for x on one circle, y on
+    another: d_{n_y} G, d_{n_x} G, d_{n_x} d_{n_y} G (d = x - y, r = |d|)."""
+    dx = x[0][:, None] - y[0][None, :]
+    dy = x[1][:, None] - y[1][None, :]
+    r = np.hypot(dx, dy)
+    H0, H1 = sp.hankel1(0, k * r), sp.hankel1(1, k * r)
+    dny = dx * ny[0][None, :] + dy * ny[1][None, :]          # d . n_y
+    dnx = dx * nx[0][:, None] + dy * nx[1][:, None]          # d . n_x
+    nn = nx[0][:, None] * ny[0][None, :] + nx[1][:, None] * ny[1][None, :]
+    dG_ny = 0.25j * k * H1 / r * dny
+    dG_nx = -0.25j * k * H1 / r * dnx
+    ddG = 0.25j * k * (dny * dnx / r * (k * H0 / r - 2.0 * H1 / r ** 2) + H1 / r * nn)
+    return dG_ny, dG_nx, ddG
+
+
+def test_mnd_offdiag_blocks_vs_quadrature():
+    """X^{pq}_{mn} = <X Phi^q_n, Phi^p_m> with the kernels of sec. 3:
+    M: -d_{n_y} G, N: d_{n_x} G, D: -d_{n_x} d_{n_y} G, by the trapezoid rule on
+    both circles (smooth periodic integrand for disjoint disks)."""
+    from oracle import operators as ops
+    centers = np.array([[0.3, -0.2], [1.9, 1.1], [-1.4, 1.6]])
+    radii = np.array([0.5, 0.7, 0.4])
+    n_modes = np.array([4, 6, 3])
+    k = 3.1
+    mats = {n: ops.operator_matrix(n, centers, radii, n_modes, k) for n in "MND"}
+    off, _ = geometry.mode_offsets(n_modes)
+    Q = 96
+    for p, q in [(0, 1), (1, 0), (2, 1), (0, 2)]:
+        xp, yp, tp = _circle(centers[p], radii[p], Q)
+        xq, yq, tq = _circle(centers[q], radii[q], Q)
+        dG_ny, dG_nx, ddG = _green_derivs(k, (xp, yp), (xq, yq), (np.cos(tp), np.sin(tp)),
+                                          (np.cos(tq), np.sin(tq)))
+        kern = {"M": -dG_ny, "N": dG_nx, "D": -ddG}
+        w = (2.0 * np.pi * radii[q] / Q) * (2.0 * np.pi * radii[p] / Q)
+        for mi, m in enumerate(range(-n_modes[p], n_modes[p] + 1)):
+            phim = np.exp(1j * m * tp) / np.sqrt(2 * np.pi * radii[p])
+            for ni, n in enumerate(range(-n_modes[q], n_modes[q] + 1)):
+                phin = np.exp(1j * n * tq) / np.sqrt(2 * np.pi * radii[q])
+                for name, K in kern.items():
+                    val = np.sum(np.conj(phim)[:, None] * K * phin[None, :]) * w
+                    got = mats[name][off[p] + mi, off[q] + ni]
+                    assert abs(got - val) <= 1e-10 * max(1.0, abs(val)), (name, p, q, m, n, got, val)
+
+
+def test_planewave_dn_vs_quadrature():
+    """dU^p_m = <d_n u_inc, Phi^p_m> on Gamma_p (Prop. 4 from its definition)."""
+    from oracle import operators as ops
+    centers = np.array([[0.3, -0.2], [2.5, 1.0]])
+    radii = np.array([0.5, 1.2])
+    n_modes = np.array([5, 9])
+    k, beta = 4.2, 0.77
+    dU = ops.planewave_dn(centers, radii, n_modes, k, [beta])[0]
+    off, _ = geometry.mode_offsets(n_modes)
+    Q = 128
+    for p in range(2):
+        x, y, t = _circle(centers[p], radii[p], Q)
+        dn = 1j * k * (np.cos(beta) * np.cos(t) + np.sin(beta) * np.sin(t)) * np.exp(
+            1j * k * (np.cos(beta) * x + np.sin(beta) * y))
+        for mi, m in enumerate(range(-n_modes[p], n_modes[p] + 1)):
+            phim = np.exp(1j * m * t) / np.sqrt(2 * np.pi * radii[p])
+            val = np.sum(dn * np.conj(phim)) * 2 * np.pi * radii[p] / Q
+            assert abs(dU[off[p] + mi] - val) < 1e-12
+
+
+def test_double_layer_farfield_is_the_potentials_limit():
+    """a_M(theta) = lim r^{1/2} e^{-ikr} (M Phi)(r theta_hat) for the volume
+    double-layer potential M lambda(x) = -int d_{n_y} G(x, y) lambda(y) dGamma,
+    integrated by the trapezoid rule at r = 1e6 (error O(1/r))."""
+    from oracle import operators as ops
+    centers = np.array([[0.6, -0.3], [-1.0, 0.8]])
+    radii = np.array([0.45, 0.7])
+    n_modes = np.array([4, 5])
+    k = 3.3
+    th = np.array([0.2, 1.7, 3.9])
+    A = ops.farfield_rows_dl(centers, radii, n_modes, k, th)
+    off, _ = geometry.mode_offsets(n_modes)
+    R, Q = 1e6, 256
+    for j, t in enumerate(th):
+        x = (np.array([R * np.cos(t)]), np.array([R * np.sin(t)]))
+        for p in range(2):
+            xq, yq, tq = _circle(centers[p], radii[p], Q)
+            dG_ny, _, _ = _green_derivs(k, x, (xq, yq), (np.array([0.0]), np.array([0.0])),
+                                        (np.cos(tq), np.sin(tq)))
+            for mi, m in enumerate(range(-n_modes[p], n_modes[p] + 1)):
+                phin = np.exp(1j * m * tq) / np.sqrt(2 * np.pi * radii[p])
+                pot = -np.sum(dG_ny[0] * phin) * 2 * np.pi * radii[p] / Q
+                lim = pot * np.sqrt(R) * np.exp(-1j * k * R)
+                assert abs(lim - A[j, off[p] + mi]) < 1e-4 * max(abs(A[j, off[p] + mi]), 1e-3)
+
+
+def _mie_general(center, a, k, beta, thetas, N, hard):
+    m = np.arange(-N, N + 1)
+    ratio = (sp.jvp(m, k * a) / sp.h1vp(m, k * a)) if hard else (sp.jv(m, k * a) / sp.hankel1(m, k * a))
+    O = np.asarray(center)
+    ph = np.exp(1j * k * ((np.cos(beta) - np.cos(thetas)) * O[0] + (np.sin(beta) - np.sin(thetas)) * O[1]))
+    s = np.sum(ratio[None, :] * np.exp(1j * m[None, :] * (thetas[:, None] - beta)), axis=1)
+    return -np.exp(-0.25j * np.pi) * np.sqrt(2.0 / (np.pi * k)) * ph * s
+
+
+FORMS = [("efie", {}, False), ("mfie", {}, False), ("cfie", {"alpha": 0.5, "eta": 3j}, False),
+         ("bwie", {"eta": 3j}, False), ("neumann_sl", {}, True), ("neumann_dl", {}, True)]
+
+
+@pytest.mark.parametrize("name,kw,hard", FORMS)
+def test_formulations_single_disk_mie(name, kw, hard):
+    """Every formulation reproduces the textbook single-disk far field:
+    -sqrt(2/(pi k)) e^{-i pi/4} sum_m c_m e^{i m (theta - beta)}, c_m = J_m/H_m
+    (sound-soft) or J'_m/H'_m (sound-hard)."""
+    from oracle import operators as ops
+    c, a, k, N, beta = (0.7, -0.4), 0.9, 4.0, 14, 0.6
+    th = synth.uniform_angles(40)
+    _, af = ops.solve_farfield(name, np.array([c]), np.array([a]), np.array([N]), k, [beta], th, **kw)
+    ref = _mie_general(c, a, k, beta, th, N, hard)
+    assert rel(af[0], ref) < 1e-13
+
+
+def test_formulations_agree_on_a_cluster():
+    """Four disks: EFIE, MFIE, CFIE and BWIE give one sound-soft far field, the
+    single- and double-layer equations one sound-hard far field, and the two
+    differ."""
+    from oracle import operators as ops
+    cl = synth.small_random(31, 4, 0.4, 0.8, 6.0, 0.4, 3.0, 12)
+    th = synth.uniform_angles(48)
+    far = {}
+    for name, kw, _ in FORMS:
+        kw = {k: (v * cl.k / 3.0 if k == "eta" else v) for k, v in kw.items()}
+        far[name] = ops.solve_farfield(name, cl.centers, cl.radii, cl.n_modes, cl.k, [0.3], th, **kw)[1][0]
+    for name in ("mfie", "cfie", "bwie"):
+        assert rel(far[name], far["efie"]) < 1e-12, name
+    assert rel(far["neumann_dl"], far["neumann_sl"]) < 1e-12
+    assert rel(far["neumann_sl"], far["efie"]) > 1e-2

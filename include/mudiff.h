@@ -170,6 +170,40 @@ int mudiff_set_apply_config(mudiff_t h, int R, int ct, int rp, int qs, int threa
  *              right-hand side f = -D^{-1} U (precond = 1). */
 int mudiff_rhs(mudiff_t h, int R, const double* beta, void* out, int precond, void* stream);
 
+/* ---------------------------------------------------------------- operators */
+
+/* Replaces the handle's operator, right-hand side and far field by a linear
+ * combination of the identity and the four boundary integral operators
+ * (sec. 3 formulations, sec. 4.2 block formulas, Prop. 4, sec. 4.4):
+ *   op    = w_I I + w_L L + w_M M + w_N N + w_D D
+ *   b     = w_U U + w_dU dU      (U = d J, dU = k d J' of the plane wave, Prop. 4)
+ *   a(th) = f_L a_L + f_M a_M    (a_M: double-layer far field, the sign of the
+ *                                 double-layer potential's large-r form)
+ * after which mudiff_matvec applies op (MUDIFF_OP_L) or D^{-1} op with D the
+ * diagonal blocks of op (MUDIFF_OP_A), mudiff_rhs returns b (or D^{-1} b),
+ * mudiff_gmres solves op rho = b (from incidence angles) or op rho = -rhs (from
+ * a given rhs, as for the single layer), and mudiff_farfield uses (f_L, f_M).
+ * Examples: MFIE  op (1/2) I + N, b = -dU;  CFIE (alpha eta) L + (1-alpha)(I/2 + N),
+ * b = -alpha eta U - (1-alpha) dU;  Brakhage-Werner (1/2) I - eta L - M,
+ * b = -U, a = -(eta a_L + a_M);  sound-hard single layer -(1/2) I + N,
+ * b = -dU;  sound-hard double layer D, b = -dU, a = a_M.
+ *   op_w       [host] 5 complex (re, im pairs): w_I, w_L, w_M, w_N, w_D, or NULL
+ *              to return to the built-in single layer (EFIE)
+ *   rhs_w      [host] 2 complex: w_U, w_dU;  ff_w  [host] 2 complex: f_L, f_M
+ *   workspace  device, 256-byte aligned, >= mudiff_operator_workspace_size(h);
+ *              holds the per-unknown factor tables and must outlive their use
+ * The operators with nonzero weight among L, M, N, D must share their row
+ * factor (L and M: J; N and D: J') or their column factor (L and N: J; M and D:
+ * J'), so that the off-diagonal blocks stay one diagonal-Toeplitz-diagonal
+ * product; otherwise MUDIFF_ERR_INVALID.  The D diagonal is
+ * -(i pi k^2 a / 2) J'_m H'_m (the normal derivative of the double-layer
+ * potential of a mode; the printed + sign contradicts the off-diagonal D
+ * blocks).  mudiff_grad requires the single layer (MUDIFF_ERR_INVALID otherwise).
+ * Enqueues the table kernel on `stream`. */
+size_t mudiff_operator_workspace_size(mudiff_t h);
+int mudiff_set_operator(mudiff_t h, const double* op_w, const double* rhs_w, const double* ff_w,
+                        void* workspace, size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------- solver */
 
 size_t mudiff_gmres_workspace_size(mudiff_t h, int R, int restart, int flags);

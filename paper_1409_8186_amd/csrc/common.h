@@ -85,6 +85,17 @@ struct DevView {
   int lane_N;
   cplx* lt;
   const int64_t* ltoff;       // [M_all]
+  // Operator set by mudiff_set_operator, or NULL for the built-in single layer
+  // (EFIE).  Per unknown: the column factor of the off-diagonal blocks, row
+  // factor / diagonal, row factor, diagonal, right-hand-side factor (raw and
+  // divided by the diagonal) and the far-field factor.
+  const cplx* op_col = nullptr;
+  const cplx* op_rowA = nullptr;
+  const cplx* op_row = nullptr;
+  const cplx* op_diag = nullptr;
+  const cplx* op_rhs = nullptr;
+  const cplx* op_rhsp = nullptr;
+  const cplx* op_ff = nullptr;
 };
 
 #define LANE_CHUNK 64
@@ -196,10 +207,21 @@ static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 //   MUDIFF_OP_L: L^{pp}_{mm} x + (i pi / 2) sqrt(a_p) J_m w
 #define OP_RAW_W 7
 __device__ __forceinline__ cplx finalize(const DevView& v, int op, int64_t i, cplx xv, cplx w) {
+  if (v.op_rowA) {  // operator set by mudiff_set_operator
+    if (op == MUDIFF_OP_A) return cadd(xv, cmul(v.op_rowA[i], w));
+    if (op == OP_RAW_W) return w;
+    return cadd(cmul(v.op_diag[i], xv), cmul(v.op_row[i], w));
+  }
   if (op == MUDIFF_OP_A) return cadd(xv, cmul(v.invSH[i], w));
   if (op == OP_RAW_W) return w;
   const double f = 0.5 * 3.14159265358979323846 * v.sJ[i];  // (i pi / 2) s_m w
   return cadd(cmul(v.Ldiag[i], xv), cmk(-f * w.y, f * w.x));
+}
+
+// Input x_n scaled by the column factor of unknown i: sqrt(a_q) J_n(k a_q)
+// for the single layer, the set operator's factor otherwise.
+__device__ __forceinline__ cplx col_scale(const DevView& v, int64_t i, cplx x) {
+  return v.op_col ? cmul(x, v.op_col[i]) : cscale(x, v.sJ[i]);
 }
 
 // Sum, in chunk order, of the one-lane-per-pair partial sums of unknown i

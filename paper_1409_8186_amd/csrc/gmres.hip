@@ -766,7 +766,7 @@ __global__ void k_precond_rhs(DevView v, int R, const cplx* __restrict__ src, cp
   const int64_t Nb = v.imode[lo + 1] - v.imode[lo];
   const int64_t rem = g - (int64_t)R * v.imode[lo];
   const int64_t i = v.imode[lo] + rem % Nb;
-  f[g] = cscale(cdiv(src[g], v.Ldiag[i]), scale);
+  f[g] = cscale(cdiv(src[g], v.op_diag ? v.op_diag[i] : v.Ldiag[i]), scale);
 }
 
 // ------------------------------------------------------------------ host driver

@@ -105,7 +105,7 @@ __global__ __launch_bounds__(APPLY_THREADS) void k_apply(
         const int nq = 2 * (NSPEC >= 0 ? NSPEC : v.N[q]) + 1;
         if (n < nq) {
           const int64_t iq = v.moff[q] + n;
-          z = cscale(xc[iq], v.sJ[i0 + iq]);
+          z = col_scale(v, i0 + iq, xc[iq]);
         }
       }
       zl[e] = z;
@@ -201,7 +201,7 @@ __global__ __launch_bounds__(APPLY_THREADS) void k_apply(
 // launch (rows of unequal cost or rows fewer than the compute units would
 // leave whole workgroups idle), and the two launches need no counters or
 // memory fences.
-template <int N>
+template <int N, bool OPC>
 __global__ __launch_bounds__(64) void k_apply_lane(
     DevView v, int R, const cplx* __restrict__ x, cplx* __restrict__ part, int64_t part_total,
     const int32_t* __restrict__ items, const int32_t* __restrict__ active) {
@@ -232,7 +232,8 @@ __global__ __launch_bounds__(64) void k_apply_lane(
     const double r2 = rec[3 * LANE_CHUNK].x;
     cplx z[n];
 #pragma unroll
-    for (int k = 0; k < n; ++k) z[k] = cscale(x[cb + iq + k], v.sJ[i0 + iq + k]);
+    for (int k = 0; k < n; ++k)
+      z[k] = OPC ? cmul(x[cb + iq + k], v.op_col[i0 + iq + k]) : cscale(x[cb + iq + k], v.sJ[i0 + iq + k]);
 #pragma unroll
     for (int m = 0; m < n; ++m) cmac(acc[m], h0, z[m]);
     cplx Hm = h0;
@@ -414,7 +415,7 @@ __global__ __launch_bounds__(THREADS) void k_apply_mfma(
         const int c = zc[k], n = zn[k];
         cplx z = cmk(0.0, 0.0);
         if (c < RC && n < nq && c0 + c < R)
-          z = cscale(x[col_base(v.imode, b, R, c0 + c) + mq + n], v.sJ[i0 + mq + n]);
+          z = col_scale(v, i0 + mq + n, x[col_base(v.imode, b, R, c0 + c) + mq + n]);
         zr[k] = z;
       }
 #pragma unroll
@@ -838,14 +839,24 @@ const Variant* find_variant(int bt, int nspec) {
 
 struct LaneVariant {
   int n;
-  lane_fn fn;
+  lane_fn fn;     // single-layer column factors (real)
+  lane_fn fn_op;  // column factors of an operator set by mudiff_set_operator
 };
 
 // one-lane-per-pair kernels (uniform N)
 const LaneVariant kLane[] = {
-    {1, k_apply_lane<1>},   {2, k_apply_lane<2>},   {3, k_apply_lane<3>},   {4, k_apply_lane<4>},
-    {5, k_apply_lane<5>},   {6, k_apply_lane<6>},   {7, k_apply_lane<7>},   {8, k_apply_lane<8>},
-    {9, k_apply_lane<9>},   {10, k_apply_lane<10>}, {11, k_apply_lane<11>}, {12, k_apply_lane<12>},
+    {1, k_apply_lane<1, false>, k_apply_lane<1, true>},
+    {2, k_apply_lane<2, false>, k_apply_lane<2, true>},
+    {3, k_apply_lane<3, false>, k_apply_lane<3, true>},
+    {4, k_apply_lane<4, false>, k_apply_lane<4, true>},
+    {5, k_apply_lane<5, false>, k_apply_lane<5, true>},
+    {6, k_apply_lane<6, false>, k_apply_lane<6, true>},
+    {7, k_apply_lane<7, false>, k_apply_lane<7, true>},
+    {8, k_apply_lane<8, false>, k_apply_lane<8, true>},
+    {9, k_apply_lane<9, false>, k_apply_lane<9, true>},
+    {10, k_apply_lane<10, false>, k_apply_lane<10, true>},
+    {11, k_apply_lane<11, false>, k_apply_lane<11, true>},
+    {12, k_apply_lane<12, false>, k_apply_lane<12, true>},
 };
 
 const LaneVariant* find_lane(int n) {
@@ -1040,8 +1051,8 @@ int apply_operator_split(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, c
     const LaneVariant* lv = find_lane(P.spec_N);
     if (!lv) return fail(MUDIFF_ERR_INVALID, "no operator kernel variant");
     if (P.n_items > 0) {
-      hipLaunchKernelGGL(lv->fn, dim3(P.n_items, R), dim3(64), 0, s, h->dv, R, x, part,
-                         P.part_total, P.d_items, active);
+      hipLaunchKernelGGL(h->dv.op_col ? lv->fn_op : lv->fn, dim3(P.n_items, R), dim3(64), 0, s,
+                         h->dv, R, x, part, P.part_total, P.d_items, active);
       HIP_TRY(hipGetLastError());
     }
     *pending = true;  // the chunk sums still have to be added and finalised
@@ -1064,8 +1075,8 @@ int apply_operator(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, cplx* p
     const LaneVariant* lv = find_lane(P.spec_N);
     if (!lv) return fail(MUDIFF_ERR_INVALID, "no operator kernel variant");
     if (P.n_items > 0) {
-      hipLaunchKernelGGL(lv->fn, dim3(P.n_items, R), dim3(64), 0, s, h->dv, R, x, part,
-                         P.part_total, P.d_items, active);
+      hipLaunchKernelGGL(h->dv.op_col ? lv->fn_op : lv->fn, dim3(P.n_items, R), dim3(64), 0, s,
+                         h->dv, R, x, part, P.part_total, P.d_items, active);
       HIP_TRY(hipGetLastError());
     }
     const int64_t total = (int64_t)R * h->N_all;

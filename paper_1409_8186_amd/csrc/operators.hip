@@ -1,0 +1,168 @@
+// Boundary integral operators beyond the single layer (paper sec. 3
+// formulations, sec. 4.2 block formulas, Prop. 4, sec. 4.4 far fields).
+//
+// The four operators share the separation matrix S of the single layer:
+// for p != q,  X^{pq} = c_X sqrt(a_p a_q) R_X^p (S^{pq})^T C_X^q  with
+//   L: c =  i pi / 2,      R = J,  C = J
+//   M: c = -i k pi / 2,    R = J,  C = J'
+//   N: c =  i k pi / 2,    R = J', C = J
+//   D: c = -i k^2 pi / 2,  R = J', C = J'
+// (J, J' diagonal matrices of J_m(k a), J'_m(k a)), and on the diagonal
+//   L: (i pi a / 2) J H,  M: 1/2 - (i pi k a / 2) J' H,  N: -1/2 + (i pi k a / 2) J' H,
+//   D: -(i pi k^2 a / 2) J' H'
+// (the sign of the D diagonal is the one of the normal derivative of the
+// double-layer potential of a mode, which also gives the off-diagonal D blocks).
+// A combination w_I I + w_L L + w_M M + w_N N + w_D D whose operators with
+// nonzero weight share their row factor (L, M; or N, D) or their column
+// factor (L, N; or M, D) has off-diagonal blocks sqrt(a_p a_q) r^p S^T c^q
+// with one row and one column factor vector: it runs on the single-layer
+// kernels with the factor tables built here.  Right-hand side
+// w_U U + w_dU dU (U = d J, dU = k d J', Prop. 4) and far field
+// f_L a_L + f_M a_M with (a_M)^p_m = -k (J'_m / J_m) (a_L)^p_m (the sign of the
+// double-layer potential's large-r form).
+#include "common.h"
+
+namespace {
+
+#define OPS_PI 3.14159265358979323846
+
+struct OpWeights {
+  cplx w[5];   // I, L, M, N, D
+  cplx rU, rdU;
+  cplx fL, fM;
+  int shared;  // 0: shared row factor, 1: shared column factor
+  int kind;    // the shared factor: 0 = J, 1 = J'
+};
+
+// J_m, J'_m, H_m, H'_m of unknown i from the disk tables (orders 0..N+1;
+// J_{-m} = (-1)^m J_m, same for H and the derivatives).
+__device__ void mode_values(const DevView& v, int p, int m, double* J, double* Jd, cplx* H, cplx* Hd) {
+  const int am = m < 0 ? -m : m;
+  const double sg = (m < 0 && (am & 1)) ? -1.0 : 1.0;
+  const double* Jt = v.Jd + v.dtab[p];
+  const cplx* Ht = v.Hd + v.dtab[p];
+  // J_{|m|-1} with J_{-1} = -J_1
+  const double Jm1 = am > 0 ? Jt[am - 1] : -Jt[1];
+  const cplx Hm1 = am > 0 ? Ht[am - 1] : cscale(Ht[1], -1.0);
+  *J = sg * Jt[am];
+  *H = cscale(Ht[am], sg);
+  // d/dx of the reflected function: (-1)^m (J_{|m|-1} - J_{|m|+1}) / 2
+  *Jd = sg * 0.5 * (Jm1 - Jt[am + 1]);
+  *Hd = cscale(csub(Hm1, Ht[am + 1]), 0.5 * sg);
+}
+
+__global__ void k_op_tables(DevView v, OpWeights o, cplx* __restrict__ col, cplx* __restrict__ rowA,
+                            cplx* __restrict__ row, cplx* __restrict__ diag, cplx* __restrict__ rhs,
+                            cplx* __restrict__ rhsp, cplx* __restrict__ ff) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= v.N_all) return;
+  const int p = v.udisk[i];
+  const int b = v.inst[p];
+  const int m = (int)(i - v.imode[b] - v.moff[p]) - v.N[p];
+  double J, Jd;
+  cplx H, Hd;
+  mode_values(v, p, m, &J, &Jd, &H, &Hd);
+  const double k = v.kd[p], a = v.a[p], sa = sqrt(a);
+  const cplx I1 = cmk(0.0, 1.0);
+  // diagonal block value
+  const cplx iJH = cmul(I1, cscale(H, J)), iJdH = cmul(I1, cscale(H, Jd)), iJdHd = cmul(I1, cscale(Hd, Jd));
+  cplx d = o.w[0];
+  d = cadd(d, cmul(o.w[1], cscale(iJH, 0.5 * OPS_PI * a)));
+  d = cadd(d, cmul(o.w[2], csub(cmk(0.5, 0.0), cscale(iJdH, 0.5 * OPS_PI * k * a))));
+  d = cadd(d, cmul(o.w[3], cadd(cmk(-0.5, 0.0), cscale(iJdH, 0.5 * OPS_PI * k * a))));
+  d = cadd(d, cmul(o.w[4], cscale(iJdHd, -0.5 * OPS_PI * k * k * a)));
+  // off-diagonal factors: scalars c_X, row and column Bessel factors
+  const cplx cX[4] = {cmk(0.0, 0.5 * OPS_PI), cmk(0.0, -0.5 * k * OPS_PI), cmk(0.0, 0.5 * k * OPS_PI),
+                      cmk(0.0, -0.5 * k * k * OPS_PI)};
+  const int rK[4] = {0, 0, 1, 1}, cK[4] = {0, 1, 0, 1};  // 0: J, 1: J'
+  cplx r = cmk(0.0, 0.0), c = cmk(0.0, 0.0);
+  if (o.shared == 0) {
+    r = cmk(sa * (o.kind ? Jd : J), 0.0);
+    for (int x = 0; x < 4; ++x)
+      c = cadd(c, cmul(cmul(o.w[x + 1], cX[x]), cmk(sa * (cK[x] ? Jd : J), 0.0)));
+  } else {
+    c = cmk(sa * (o.kind ? Jd : J), 0.0);
+    for (int x = 0; x < 4; ++x)
+      r = cadd(r, cmul(cmul(o.w[x + 1], cX[x]), cmk(sa * (rK[x] ? Jd : J), 0.0)));
+  }
+  col[i] = c;
+  row[i] = r;
+  diag[i] = d;
+  rowA[i] = cdiv(r, d);
+  const double s2pa = sqrt(2.0 * OPS_PI * a);
+  const cplx bq = cscale(cadd(cscale(o.rU, J), cscale(o.rdU, k * Jd)), s2pa);
+  rhs[i] = bq;
+  rhsp[i] = cdiv(bq, d);
+  ff[i] = cadd(cscale(o.fL, sa * J), cscale(o.fM, -k * sa * Jd));
+}
+
+constexpr int OP_TABLES = 7;
+
+cplx read_c(const double* w, int k) { return cmk(w[2 * k], w[2 * k + 1]); }
+
+}  // namespace
+
+extern "C" size_t mudiff_operator_workspace_size(mudiff_t h) {
+  if (!h) return 0;
+  return (size_t)OP_TABLES * align256((size_t)h->N_all * 16);
+}
+
+extern "C" int mudiff_set_operator(mudiff_t h, const double* op_w, const double* rhs_w,
+                                   const double* ff_w, void* workspace, size_t ws_bytes,
+                                   void* stream) {
+  if (!h) return fail(MUDIFF_ERR_INVALID, "NULL handle");
+  DevView& v = h->dv;
+  if (!op_w) {  // back to the built-in single layer
+    v.op_col = v.op_rowA = v.op_row = v.op_diag = v.op_rhs = v.op_rhsp = v.op_ff = nullptr;
+    return MUDIFF_OK;
+  }
+  if (!rhs_w || !ff_w || !workspace) return fail(MUDIFF_ERR_INVALID, "NULL argument");
+  for (int k = 0; k < 10; ++k)
+    if (!std::isfinite(op_w[k])) return fail(MUDIFF_ERR_INVALID, "non-finite operator weight");
+  for (int k = 0; k < 4; ++k)
+    if (!std::isfinite(rhs_w[k]) || !std::isfinite(ff_w[k])) return fail(MUDIFF_ERR_INVALID, "non-finite weight");
+  const size_t need = mudiff_operator_workspace_size(h);
+  if (ws_bytes < need) return fail(MUDIFF_ERR_NOMEM, "operator workspace needs " + std::to_string(need) + " bytes");
+  if (((uintptr_t)workspace) & 255) return fail(MUDIFF_ERR_INVALID, "workspace must be 256-byte aligned");
+  OpWeights o{};
+  for (int k = 0; k < 5; ++k) o.w[k] = read_c(op_w, k);
+  o.rU = read_c(rhs_w, 0);
+  o.rdU = read_c(rhs_w, 1);
+  o.fL = read_c(ff_w, 0);
+  o.fM = read_c(ff_w, 1);
+  // which operators act off the diagonal; their row kinds (L, M: J; N, D: J')
+  // and column kinds (L, N: J; M, D: J')
+  const int rK[4] = {0, 0, 1, 1}, cK[4] = {0, 1, 0, 1};
+  int rmask = 0, cmask = 0;
+  for (int x = 0; x < 4; ++x)
+    if (o.w[x + 1].x != 0.0 || o.w[x + 1].y != 0.0) {
+      rmask |= 1 << rK[x];
+      cmask |= 1 << cK[x];
+    }
+  if (rmask == 3 && cmask == 3)
+    return fail(MUDIFF_ERR_INVALID,
+                "the operators with nonzero weight share neither their row factor (L, M or N, D) "
+                "nor their column factor (L, N or M, D): not one diagonal-Toeplitz-diagonal product");
+  if (rmask != 3) {
+    o.shared = 0;
+    o.kind = rmask == 2 ? 1 : 0;
+  } else {
+    o.shared = 1;
+    o.kind = cmask == 2 ? 1 : 0;
+  }
+  const size_t stride = align256((size_t)h->N_all * 16);
+  char* w = (char*)workspace;
+  cplx* t[OP_TABLES];
+  for (int k = 0; k < OP_TABLES; ++k) t[k] = (cplx*)(w + k * stride);
+  hipLaunchKernelGGL(k_op_tables, dim3((unsigned)((h->N_all + 255) / 256)), dim3(256), 0,
+                     (hipStream_t)stream, v, o, t[0], t[1], t[2], t[3], t[4], t[5], t[6]);
+  HIP_TRY(hipGetLastError());
+  v.op_col = t[0];
+  v.op_rowA = t[1];
+  v.op_row = t[2];
+  v.op_diag = t[3];
+  v.op_rhs = t[4];
+  v.op_rhsp = t[5];
+  v.op_ff = t[6];
+  return MUDIFF_OK;
+}

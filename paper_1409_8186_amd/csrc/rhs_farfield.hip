@@ -38,6 +38,10 @@ __global__ void k_rhs(DevView v, int R, const double* __restrict__ beta, cplx* _
   const cplx e2 = cexpi(m * (0.5 * PI_D - be));
   const cplx e = cmul(e1, e2);
   const double s2pi = sqrt(2.0 * PI_D);
+  if (v.op_rhs) {  // operator set by mudiff_set_operator: w_U U + w_dU dU (over its diagonal)
+    out[g] = cmul(e, precond ? v.op_rhsp[i] : v.op_rhs[i]);
+    return;
+  }
   if (precond) {
     const cplx w = cmul(e, v.invSH[i]);
     const double c = 2.0 / PI_D * s2pi;
@@ -91,7 +95,7 @@ __global__ __launch_bounds__(FF_TH* FF_DG) void k_farfield(DevView v, int R,
     cplx e = cexpi(-Np * (th - 0.5 * PI_D));
     cplx sm = cmk(0.0, 0.0);
     for (int mm = 0; mm <= 2 * Np; ++mm) {
-      cmac(sm, e, cscale(rc[o + mm], v.sJ[i0 + mm]));
+      cmac(sm, e, v.op_ff ? cmul(rc[o + mm], v.op_ff[i0 + mm]) : cscale(rc[o + mm], v.sJ[i0 + mm]));
       e = cmul(e, ephi);
     }
     const cplx ep = cexpi(-kk * (ct * v.cx[p] + st * v.cy[p]));

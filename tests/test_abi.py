@@ -133,3 +133,9 @@ def test_time_reversal_validation(lib):
     assert lib.mudiff_herglotz(0, buf, 1, buf, ctypes.c_double(1.0), ctypes.c_double(0.1), 4, buf, buf, None) == 1
     assert lib.mudiff_herglotz(4, buf, 1, buf, ctypes.c_double(-1.0), ctypes.c_double(0.1), 4, buf, buf, None) == 1
     assert lib.mudiff_herglotz(4, buf, 1, buf, ctypes.c_double(1.0), ctypes.c_double(0.1), 4, None, buf, None) == 1
+
+
+def test_set_operator_validation(lib):
+    w = (ctypes.c_double * 10)()
+    assert lib.mudiff_set_operator(None, w, w, w, None, 0, None) == 1
+    assert lib.mudiff_operator_workspace_size(None) == 0

@@ -243,6 +243,8 @@ def other_workload(args):
                                   "batched_speedup": per_inst_single * len(insts) / t_s}}
     if args.workload == "dort":
         return dort_workload(base)
+    if args.workload == "formulations":
+        return formulations_workload(base)
     pairs = synth.differentiation()
     bases = [b for b, _ in pairs]
     betas = np.stack([b.betas for b in bases])
@@ -368,6 +370,70 @@ def dort_workload(base):
     return out
 
 
+def formulations_workload(base):
+    """The one-RHS geometry (M=400, N_p=12, k=2 pi, beta=pi/4) solved by every
+    formulation (GMRES(50) to 1e-8, single-scattering preconditioner): time,
+    iterations, agreement of the far fields (sound-soft forms against the
+    EFIE, sound-hard forms against each other), and the one-RHS apply with the
+    operator tables."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1409_8186_amd import Problem
+    cl = synth.one_rhs()
+    th = torch.tensor(cl.thetas, device="cuda")
+    beta = [[math.pi / 4]]
+    P = Problem.from_cluster(cl)
+    res, far = {}, {}
+    for name in Problem.FORMULATIONS:
+        if name == "efie":
+            P.set_operator(None)
+        else:
+            P.set_operator(name)
+        P.gmres(betas=beta, restart=50, tol=1e-8, maxit=20000, graph=True)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rho, flag, relres, iters, _ = P.gmres(betas=beta, restart=50, tol=1e-8, maxit=20000,
+                                              graph=True)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        far[name] = P.farfield(rho, th).cpu().numpy()[0]
+        x = torch.randn(cl.n_tot, dtype=torch.complex128, device="cuda")
+        y = P.empty(1)
+        P.matvec(x, op=1, out=y)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            P.matvec(x, op=1, out=y)
+        e1.record()
+        e1.synchronize()
+        res[name] = {"solve_s": t, "iters": int(iters[0]), "flag": int(flag[0]),
+                     "relres": float(relres[0]), "apply_us": e0.elapsed_time(e1) / 20 * 1e3}
+    P.set_operator(None)
+
+    def dev(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    for name in ("mfie", "cfie", "bwie"):
+        res[name]["farfield_rel_diff_vs_efie"] = dev(far[name], far["efie"])
+    res["neumann_dl"]["farfield_rel_diff_vs_neumann_sl"] = dev(far["neumann_dl"], far["neumann_sl"])
+    flops = algorithmic_flops(cl.n_modes, 1)
+    t_app = res["cfie"]["apply_us"] * 1e-6
+    return {**base, "metric": "time-to-1e-8 GMRES solve per formulation", "value": res["cfie"]["solve_s"],
+            "unit": "s (CFIE)", "higher_is_better": False, "ms_per_step": res["cfie"]["solve_s"] * 1e3,
+            "config": {"workload": "formulations: one_rhs geometry (M=400, a=0.5, N_p=12, k=2pi, "
+                                   "beta=pi/4), GMRES(50) to 1e-8 with graph replay; CFIE alpha=1/2, "
+                                   "eta=ik; BWIE eta=ik",
+                       "n_unknowns": cl.n_tot},
+            "formulations": res,
+            "roofline": {"bound": "alu", "kernel": "operator apply with operator tables, one RHS: "
+                                                   "k_apply_lane<12, true> + k_apply_finish (CFIE)",
+                         "achieved": flops / t_app / 1e12, "peak": PEAK_FP64_VECTOR_TFLOPS,
+                         "unit": "TFLOP/s", "frac": flops / t_app / 1e12 / PEAK_FP64_VECTOR_TFLOPS,
+                         "traffic": None}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -381,7 +447,8 @@ def main():
     ap.add_argument("--kernel-only", type=int, default=0, metavar="REPS",
                     help="profiling mode: build the tables, run REPS operator applies, exit")
     ap.add_argument("--workload", default="one_rhs",
-                    choices=["one_rhs", "multi_rhs", "uneven", "differentiation", "dort"],
+                    choices=["one_rhs", "multi_rhs", "uneven", "differentiation", "dort",
+                             "formulations"],
                     help="one_rhs (default bench line) or a documentation run of another workload")
     ap.add_argument("--solve", action="store_true",
                     help="with --workload multi_rhs: also time the GMRES(50) solve to 1e-8")

@@ -572,3 +572,93 @@ def test_formulations_agree_on_a_cluster():
         assert rel(far[name], far["efie"]) < 1e-12, name
     assert rel(far["neumann_dl"], far["neumann_sl"]) < 1e-12
     assert rel(far["neumann_sl"], far["efie"]) > 1e-2
+
+
+# -------------------------------------------------------------------- near field
+def test_layer_potentials_vs_quadrature():
+    """L rho(x) = int_Gamma G(x, y) rho(y) dGamma and M lam(x) = -int d_{n_y} G lam
+    by the trapezoid rule, at points at least half a radius from every circle."""
+    from oracle import nearfield
+    centers = np.array([[0.3, -0.2], [2.4, 1.1], [-1.5, 1.7]])
+    radii = np.array([0.5, 0.7, 0.4])
+    n_modes = np.array([6, 8, 5])
+    k = 2.7
+    rng = np.random.default_rng(3)
+    n = int(np.sum(2 * n_modes + 1))
+    dens = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    pts = np.array([[1.4, -1.3], [0.9, 0.9], [-1.9, 0.2], [3.6, 2.6], [0.2, 2.9]])
+    uL = nearfield.potential(centers, radii, n_modes, k, dens, pts, 1.0, 0.0)
+    uM = nearfield.potential(centers, radii, n_modes, k, dens, pts, 0.0, 1.0)
+    off, _ = geometry.mode_offsets(n_modes)
+    Q = 256
+    refL = np.zeros(len(pts), complex)
+    refM = np.zeros(len(pts), complex)
+    for p in range(3):
+        xq, yq, tq = _circle(centers[p], radii[p], Q)
+        m = np.arange(-n_modes[p], n_modes[p] + 1)
+        rho = np.exp(1j * np.outer(tq, m)) @ dens[off[p]:off[p + 1]] / np.sqrt(2 * np.pi * radii[p])
+        w = 2 * np.pi * radii[p] / Q
+        G = 0.25j * sp.hankel1(0, k * np.hypot(pts[:, 0:1] - xq[None, :], pts[:, 1:2] - yq[None, :]))
+        refL += G @ rho * w
+        dG_ny, _, _ = _green_derivs(k, (pts[:, 0], pts[:, 1]), (xq, yq),
+                                    (np.zeros(len(pts)), np.zeros(len(pts))), (np.cos(tq), np.sin(tq)))
+        refM += -(dG_ny @ rho) * w
+    assert rel(uL, refL) < 1e-12
+    assert rel(uM, refM) < 1e-12
+
+
+def test_total_field_single_disk_mie():
+    """Sound-soft disk at O: u_t = sum_m i^m [J_m(k r) - J_m(k a) H_m(k r) / H_m(k a)]
+    e^{i m (theta - beta)} e^{i k beta_hat . O} (polar coordinates about O)."""
+    from oracle import nearfield
+    O, a, k, N, beta = np.array([0.4, -0.3]), 0.8, 3.5, 16, 0.9
+    L = operator.efie_matrix(O[None, :], [a], [N], k)
+    U = rhs.planewave(O[None, :], [a], [N], k, [beta])
+    rho = solve.efie_solve_lu(L, U)[0]
+    rng = np.random.default_rng(4)
+    rr = rng.uniform(1.05 * a, 4.0, 30)
+    tt = rng.uniform(0, 2 * np.pi, 30)
+    pts = np.stack([O[0] + rr * np.cos(tt), O[1] + rr * np.sin(tt)], 1)
+    ut = nearfield.total_field(O[None, :], [a], [N], k, rho[None, :], pts, [beta])[0]
+    m = np.arange(-40, 41)
+    ref = np.exp(1j * k * (np.cos(beta) * O[0] + np.sin(beta) * O[1])) * np.sum(
+        (1j ** m)[None, :] * (sp.jv(m[None, :], k * rr[:, None])
+                              - sp.jv(m, k * a)[None, :] * sp.hankel1(m[None, :], k * rr[:, None])
+                              / sp.hankel1(m, k * a)[None, :])
+        * np.exp(1j * m[None, :] * (tt[:, None] - beta)), axis=1)
+    # the truncation at N = 16 leaves ~1e-12 at these radii (k a = 2.8)
+    assert np.max(np.abs(ut - ref)) < 1e-10
+
+
+def test_total_field_vanishes_on_the_boundaries(tiny):
+    """Four disks: u_t on every circle shrinks with N (truncation-limited)."""
+    from oracle import nearfield
+    worst = []
+    for N in (10, 16):
+        cl = tiny
+        n_modes = np.full(4, N)
+        L = operator.efie_matrix(cl.centers, cl.radii, n_modes, cl.k)
+        U = rhs.planewave(cl.centers, cl.radii, n_modes, cl.k, [0.0])
+        rho = solve.efie_solve_lu(L, U)[0]
+        pts = np.concatenate([np.stack(_circle(cl.centers[p], cl.radii[p] * (1 + 1e-12), 48)[:2], 1)
+                              for p in range(4)])
+        ut = nearfield.total_field(cl.centers, cl.radii, n_modes, cl.k, rho[None, :], pts, [0.0])[0]
+        worst.append(np.max(np.abs(ut)))
+    assert worst[1] < 1e-5 and worst[1] < worst[0] / 10, worst
+
+
+def test_near_field_tends_to_the_far_field():
+    """sqrt(r) e^{-i k r} u(r theta_hat) -> a(theta) (sec. 4.4), single and double layer."""
+    from oracle import nearfield, operators as ops
+    cl = synth.small_random(61, 3, 0.3, 0.7, 4.0, 0.3, 3.0, 5)
+    rng = np.random.default_rng(6)
+    dens = rng.standard_normal(cl.n_tot) + 1j * rng.standard_normal(cl.n_tot)
+    th = np.array([0.3, 2.0, 4.4])
+    R = 1e7
+    pts = np.stack([R * np.cos(th), R * np.sin(th)], 1)
+    for fL, fM in ((1.0, 0.0), (0.0, 1.0)):
+        u = nearfield.potential(cl.centers, cl.radii, cl.n_modes, cl.k, dens, pts, fL, fM)
+        lim = u * np.sqrt(R) * np.exp(-1j * cl.k * R)
+        G = fL * farfield.farfield_rows(cl.centers, cl.radii, cl.n_modes, cl.k, th) + \
+            fM * ops.farfield_rows_dl(cl.centers, cl.radii, cl.n_modes, cl.k, th)
+        assert rel(lim, G @ dens) < 1e-5

@@ -241,6 +241,22 @@ int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* rhs, void* r
 int mudiff_farfield(mudiff_t h, int R, const void* rho, int n_theta, const double* theta,
                     void* a_out, void* stream);
 
+/* ---------------------------------------------------------------- near field */
+
+/* Field at points of the propagation domain (sec. 4.4, Graf's addition theorem):
+ *   u(x) = sum_p sum_m (i sqrt(pi/8)) F^p_m rho^p_m H_m(k r_p) e^{i m theta_p},
+ * (r_p, theta_p) the polar coordinates of x - O_p, F^p_m = sqrt(a_p) J_m(k a_p)
+ * (single-layer potential) or, after mudiff_set_operator, f_L sqrt(a) J_m -
+ * f_M k sqrt(a) J'_m (its far-field weights: single- plus double-layer potential).
+ *   rho    device complex128 [B][R][N_b] densities
+ *   pts    device double [n_pts][2], shared by all instances
+ *   beta   device [B][R] incidence angles: the total field u_inc + u; or NULL:
+ *          the scattered field u
+ *   out    device complex128 [B][R][n_pts]; 0 at points inside a disk
+ * Errors: MUDIFF_ERR_INVALID. */
+int mudiff_nearfield(mudiff_t h, int R, const void* rho, int n_pts, const double* pts,
+                     const double* beta, void* out, void* stream);
+
 /* ---------------------------------------------------------------- gradient */
 
 size_t mudiff_grad_workspace_size(mudiff_t h, int R, int n_rec, int restart, int flags);

@@ -34,6 +34,7 @@ SIGNATURES = {
     "mudiff_gmres": (_i32, [_vp, _i32, _vp, _vp, _vp, _i32, _d, _i32, _i32, _vp, _sz,
                             _vp, _vp, _vp, _vp, _vp]),
     "mudiff_farfield": (_i32, [_vp, _i32, _vp, _i32, _vp, _vp, _vp]),
+    "mudiff_nearfield": (_i32, [_vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp]),
     "mudiff_grad_workspace_size": (_sz, [_vp, _i32, _i32, _i32, _i32]),
     "mudiff_grad": (_i32, [_vp, _i32, _vp, _i32, _vp, _vp, _i32, _d, _i32, _i32, _vp, _sz,
                            _vp, _vp, _vp, _vp, _vp]),

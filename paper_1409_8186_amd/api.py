@@ -215,6 +215,17 @@ class Problem:
                                          _p(out), _stream()))
         return out.view(self.B * R, th.numel())
 
+    # ----------------------------------------------------------- near field
+    def nearfield(self, rho: torch.Tensor, points, R: int = 1, betas=None) -> torch.Tensor:
+        """Scattered field (or, with betas [B, R], the total field) at points
+        [P, 2]; 0 inside disks.  Returns [B*R, P]."""
+        pts = self._f64(points).reshape(-1, 2).contiguous()
+        bt = None if betas is None else self._f64(betas).reshape(self.B, R).contiguous()
+        out = torch.empty(self.B * R * pts.shape[0], dtype=torch.complex128, device=self.device)
+        L.check(self.lib.mudiff_nearfield(self.h, R, _p(rho.contiguous()), pts.shape[0], _p(pts),
+                                          _p(bt), _p(out), _stream()))
+        return out.view(self.B * R, pts.shape[0])
+
     # ----------------------------------------------------------- operators
     FORMULATIONS = ("efie", "mfie", "cfie", "bwie", "neumann_sl", "neumann_dl")
 

@@ -245,6 +245,8 @@ def other_workload(args):
         return dort_workload(base)
     if args.workload == "formulations":
         return formulations_workload(base)
+    if args.workload == "nearfield":
+        return nearfield_workload(base)
     pairs = synth.differentiation()
     bases = [b for b, _ in pairs]
     betas = np.stack([b.betas for b in bases])
@@ -434,6 +436,59 @@ def formulations_workload(base):
                          "traffic": None}}
 
 
+def nearfield_workload(base):
+    """Total field of the one-RHS solve on a 1000 x 1000 grid over [-5, 65]^2
+    (1e6 points x 400 disks), after GMRES(50) to 1e-8."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1409_8186_amd import Problem
+    cl = synth.one_rhs()
+    P = Problem.from_cluster(cl)
+    rho, flag, _, _, _ = P.gmres(betas=[[math.pi / 4]], restart=50, tol=1e-8, maxit=20000, graph=True)
+    g = np.linspace(-5.0, 65.0, 1000)
+    pts = torch.tensor(np.stack(np.meshgrid(g, g, indexing="ij"), -1).reshape(-1, 2), device="cuda")
+    P.nearfield(rho, pts, betas=[[math.pi / 4]])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    reps = 3
+    for _ in range(reps):
+        u = P.nearfield(rho, pts, betas=[[math.pi / 4]])
+    e1.record()
+    e1.synchronize()
+    t = e0.elapsed_time(e1) / reps / 1e3
+    n_pairs = pts.shape[0] * cl.M
+    # per (point, disk): the mode sum, 2N+1 complex MACs, the H_m and phase
+    # recurrences (N complex updates each); H_0, H_1 not counted
+    N = int(cl.n_modes[0])
+    flops_pair = 8 * (2 * N + 1) + 2 * 8 * N
+    # the oracle on a sample of 2000 points
+    from oracle import nearfield as onf
+    sample = pts[:2000].cpu().numpy()
+    c0 = time.perf_counter()
+    onf.total_field(cl.centers, cl.radii, cl.n_modes, cl.k, rho.cpu().numpy()[None, :], sample,
+                    [math.pi / 4])
+    t_cpu = (time.perf_counter() - c0) * pts.shape[0] / len(sample)
+    return {**base, "metric": "near-field points x disks per second", "value": n_pairs / t,
+            "unit": "point-disk evaluations/s", "ms_per_step": t * 1e3,
+            "config": {"workload": "nearfield: one_rhs geometry (M=400, N_p=12, k=2pi), total field "
+                                   "on a 1000x1000 grid over [-5,65]^2 after GMRES(50) to 1e-8",
+                       "points": int(pts.shape[0]), "disks": cl.M,
+                       "max_abs_total_field": float(u.abs().max())},
+           "roofline": {"bound": "alu", "kernel": "k_nearfield",
+                        "achieved": n_pairs * flops_pair / t / 1e12, "peak": PEAK_FP64_VECTOR_TFLOPS,
+                        "unit": "TFLOP/s",
+                        "frac": n_pairs * flops_pair / t / 1e12 / PEAK_FP64_VECTOR_TFLOPS,
+                        "traffic": None,
+                        "note": "counts the mode sums and recurrences only; the H_0, H_1 "
+                                "evaluation per (point, disk) is not counted"},
+           "cpu_baseline": {"value": n_pairs / t_cpu, "unit": "point-disk evaluations/s",
+                            "cores": _blas_threads(), "kind": "oracle",
+                            "sample": "oracle total field on 2000 of the grid points, extrapolated"}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -448,7 +503,7 @@ def main():
                     help="profiling mode: build the tables, run REPS operator applies, exit")
     ap.add_argument("--workload", default="one_rhs",
                     choices=["one_rhs", "multi_rhs", "uneven", "differentiation", "dort",
-                             "formulations"],
+                             "formulations", "nearfield"],
                     help="one_rhs (default bench line) or a documentation run of another workload")
     ap.add_argument("--solve", action="store_true",
                     help="with --workload multi_rhs: also time the GMRES(50) solve to 1e-8")

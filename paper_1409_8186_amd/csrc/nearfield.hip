@@ -19,10 +19,53 @@ namespace {
 constexpr int NF_THREADS = 256;
 constexpr int NF_RC = 4;
 
+// Hankel's large-argument expansion of H_0, H_1 (DLMF 10.17.5) with a fixed
+// number of terms by range: the k-th term is prod_{j<=k} (4 nu^2 - (2j-1)^2) /
+// (8 j x) times the first, below 3e-17 at x = 25 for k = 18, at x = 50 for
+// k = 12 and at x = 100 for k = 9 (nu = 0, 1).  Same phase handling as the
+// table code: e^{ix} from sincos of the exact argument.
+template <int K>
+__device__ __forceinline__ void hankel01_series(double x, cplx* s0, cplx* s1) {
+  const double ix = 1.0 / (8.0 * x);
+  cplx t0 = cmk(1.0, 0.0), t1 = cmk(1.0, 0.0);
+  cplx a0 = t0, a1 = t1;
+#pragma unroll
+  for (int kk = 1; kk <= K; ++kk) {
+    const double q = (2.0 * kk - 1.0) * (2.0 * kk - 1.0);
+    const double f0 = -q * ix / kk, f1 = (4.0 - q) * ix / kk;
+    t0 = cmk(-t0.y * f0, t0.x * f0);  // * i * f
+    t1 = cmk(-t1.y * f1, t1.x * f1);
+    a0 = cadd(a0, t0);
+    a1 = cadd(a1, t1);
+  }
+  *s0 = a0;
+  *s1 = a1;
+}
+
+__device__ __forceinline__ void hankel01_near(double x, cplx* H0, cplx* H1) {
+  if (x < BESSEL_X_ASY) {
+    hankel01(x, H0, H1);
+    return;
+  }
+  cplx s0, s1;
+  if (x >= 100.0) hankel01_series<10>(x, &s0, &s1);
+  else if (x >= 50.0) hankel01_series<13>(x, &s0, &s1);
+  else hankel01_series<19>(x, &s0, &s1);
+  const double r2 = 0.70710678118654752440;
+  double sn, cs;
+  sincos(x, &sn, &cs);
+  const double amp = sqrt(0.63661977236758134308 / x);  // sqrt(2 / (pi x))
+  const cplx e = cmk(amp * cs, amp * sn);
+  *H0 = cmul(cmul(e, cmk(r2, -r2)), s0);   // e^{-i pi/4}
+  *H1 = cmul(cmul(e, cmk(-r2, -r2)), s1);  // e^{-3 i pi/4}
+}
+
 __global__ __launch_bounds__(NF_THREADS) void k_nearfield(DevView v, int R, const cplx* __restrict__ rho,
                                                           int n_pts, const double* __restrict__ pts,
                                                           const double* __restrict__ beta,
                                                           cplx* __restrict__ out) {
+  // coefficients (i sqrt(pi/8)) F rho of the current disk: [2 N_p + 1][NF_RC]
+  __shared__ cplx cf[(2 * MUDIFF_MAX_NP + 1) * NF_RC];
   const int P = blockIdx.x * NF_THREADS + threadIdx.x;
   const int nchunk = (R + NF_RC - 1) / NF_RC;
   const int b = blockIdx.y / nchunk;
@@ -36,11 +79,23 @@ __global__ __launch_bounds__(NF_THREADS) void k_nearfield(DevView v, int R, cons
   for (int c = 0; c < NF_RC; ++c) acc[c] = cmk(0.0, 0.0);
   bool inside = false;
   for (int64_t p = v.idisk[b]; p < v.idisk[b + 1]; ++p) {
+    const int Np = v.N[p];
+    const int n = 2 * Np + 1;
+    const int64_t i0 = v.imode[b] + v.moff[p];  // unknown of mode -N_p
+    __syncthreads();  // the previous disk's coefficients are no longer read
+    for (int e = threadIdx.x; e < n * NF_RC; e += NF_THREADS) {
+      const int mi = e / NF_RC, c = e - mi * NF_RC;
+      cplx t = cmk(0.0, 0.0);
+      if (c < nr) {
+        const cplx F = v.op_ff ? v.op_ff[i0 + mi] : cmk(v.sJ[i0 + mi], 0.0);
+        t = cmul(F, rho[col_base(v.imode, b, R, r0 + c) + v.moff[p] + mi]);
+      }
+      cf[e] = cmk(-cst * t.y, cst * t.x);
+    }
+    __syncthreads();
     const double dx = x1 - v.cx[p], dy = x2 - v.cy[p];
     const double r2 = dx * dx + dy * dy;
     const double ap = v.a[p];
-    const int Np = v.N[p];
-    const int64_t i0 = v.imode[b] + v.moff[p] + Np;  // unknown of mode 0
     if (r2 < ap * ap) {
       inside = true;
       continue;
@@ -48,19 +103,12 @@ __global__ __launch_bounds__(NF_THREADS) void k_nearfield(DevView v, int R, cons
     const double r = sqrt(r2);
     const double xx = k * r;
     cplx H0, H1;
-    hankel01(xx, &H0, &H1);
+    hankel01_near(xx, &H0, &H1);
     const cplx e1 = cmk(dx / r, dy / r);  // e^{i theta_p}
-    // coefficient (i sqrt(pi/8)) F rho of mode m, column c
-    auto coef = [&](int m, int c) {
-      const int64_t i = i0 + m;
-      const cplx F = v.op_ff ? v.op_ff[i] : cmk(v.sJ[i], 0.0);
-      const cplx rv = rho[col_base(v.imode, b, R, r0 + c) + v.moff[p] + Np + m];
-      const cplx t = cmul(F, rv);
-      return cmk(-cst * t.y, cst * t.x);
-    };
+    const cplx* c0 = cf + Np * NF_RC;     // mode 0
 #pragma unroll
     for (int c = 0; c < NF_RC; ++c)
-      if (c < nr) cmac(acc[c], coef(0, c), H0);
+      if (c < nr) cmac(acc[c], c0[c], H0);
     cplx Hm1 = H0, Hm = H1, em = e1;
     for (int m = 1; m <= Np; ++m) {
       if (m >= 2) {
@@ -75,8 +123,8 @@ __global__ __launch_bounds__(NF_THREADS) void k_nearfield(DevView v, int R, cons
 #pragma unroll
       for (int c = 0; c < NF_RC; ++c)
         if (c < nr) {
-          cmac(acc[c], coef(m, c), tp);
-          cmac(acc[c], coef(-m, c), tm);
+          cmac(acc[c], c0[m * NF_RC + c], tp);
+          cmac(acc[c], c0[-m * NF_RC + c], tm);
         }
     }
   }

@@ -662,3 +662,72 @@ def test_near_field_tends_to_the_far_field():
         G = fL * farfield.farfield_rows(cl.centers, cl.radii, cl.n_modes, cl.k, th) + \
             fM * ops.farfield_rows_dl(cl.centers, cl.radii, cl.n_modes, cl.k, th)
         assert rel(lim, G @ dens) < 1e-5
+
+
+# -------------------------------------------------------------- penetrable disks
+def _transmission_mie(center, a, k, ki, mu, beta, thetas, N):
+    """Penetrable disk: matching J_m(k a) + c_m H_m(k a) = b_m J_m(ki a) and
+    k (J'_m(k a) + c_m H'_m(k a)) = mu ki b_m J'_m(ki a) per mode gives
+    c_m = (mu ki J'_m(ki a) J_m(k a) - k J_m(ki a) J'_m(k a))
+          / (k J_m(ki a) H'_m(k a) - mu ki J'_m(ki a) H_m(k a)),
+    far field sqrt(2/(pi k)) e^{-i pi/4} sum_m c_m e^{i m (theta - beta)}."""
+    m = np.arange(-N, N + 1)
+    Ji, Jid = sp.jv(m, ki * a), sp.jvp(m, ki * a)
+    J, Jd, H, Hd = sp.jv(m, k * a), sp.jvp(m, k * a), sp.hankel1(m, k * a), sp.h1vp(m, k * a)
+    c = (mu * ki * Jid * J - k * Ji * Jd) / (k * Ji * Hd - mu * ki * Jid * H)
+    O = np.asarray(center)
+    ph = np.exp(1j * k * ((np.cos(beta) - np.cos(thetas)) * O[0] + (np.sin(beta) - np.sin(thetas)) * O[1]))
+    return np.exp(-0.25j * np.pi) * np.sqrt(2.0 / (np.pi * k)) * ph * np.sum(
+        c[None, :] * np.exp(1j * m[None, :] * (thetas[:, None] - beta)), axis=1)
+
+
+@pytest.mark.parametrize("ki,mu", [(2.0 * 4.0, 1.0), (0.6 * 4.0, 1.0), (1.5 * 4.0, 2.5)])
+def test_penetrable_single_disk_mie(ki, mu):
+    from oracle import penetrable as pen
+    c, a, k, N, beta = (0.4, -0.6), 0.8, 4.0, 18, 0.7
+    th = synth.uniform_angles(36)
+    rp, _ = pen.solve(np.array([c]), np.array([a]), np.array([N]), k, [ki], [beta], mu=[mu])
+    af = pen.farfield(np.array([c]), np.array([a]), np.array([N]), k, rp, th)[0]
+    assert rel(af, _transmission_mie(c, a, k, ki, mu, beta, th, N)) < 1e-12
+
+
+def test_penetrable_matched_medium_does_not_scatter():
+    """k- = k+ and mu = 1: no scattered field (the truncated system reproduces it exactly)."""
+    from oracle import penetrable as pen
+    cl = synth.small_random(81, 4, 0.3, 0.8, 6.0, 0.3, 3.0, 6)
+    rp, rm = pen.solve(cl.centers, cl.radii, cl.n_modes, cl.k, np.full(4, cl.k), [0.5])
+    a = pen.farfield(cl.centers, cl.radii, cl.n_modes, cl.k, rp, synth.uniform_angles(24))
+    assert np.max(np.abs(a)) < 1e-12
+    assert np.max(np.abs(rp)) < 1e-12 * np.max(np.abs(rm))
+
+
+def test_penetrable_transmission_conditions_on_the_boundaries():
+    """Three disks with different interior wavenumbers and mu: on every circle
+    the exterior total field equals the interior field, and its radial
+    derivative equals mu times the interior one (second-order one-sided
+    differences on each side), to a truncation-limited level that shrinks
+    with N."""
+    from oracle import nearfield, penetrable as pen
+    centers = np.array([[0.0, 0.0], [2.2, 0.4], [0.6, 2.1]])
+    radii = np.array([0.6, 0.5, 0.45])
+    k, beta = 3.0, 0.3
+    ki, mu = np.array([5.0, 2.0, 4.0]), np.array([1.0, 1.5, 0.8])
+    t = np.linspace(0, 2 * np.pi, 40, endpoint=False)
+    dirs = np.stack([np.cos(t), np.sin(t)], 1)
+    h = 2e-4
+    worst = []
+    for N in (8, 14):
+        n_modes = np.full(3, N)
+        rp, rm = pen.solve(centers, radii, n_modes, k, ki, [beta], mu=mu)
+        err = 0.0
+        for p in range(3):
+            a = radii[p]
+            out = [nearfield.total_field(centers, radii, n_modes, k, rp, centers[p] + (a * (1 + 1e-13) + j * h) * dirs,
+                                         [beta])[0] for j in range(3)]
+            inn = [pen.interior_field(centers, radii, n_modes, ki, rm[0], p, centers[p] + (a * (1 - 1e-13) - j * h) * dirs)
+                   for j in range(3)]
+            du_o = (-3 * out[0] + 4 * out[1] - out[2]) / (2 * h)
+            du_i = (3 * inn[0] - 4 * inn[1] + inn[2]) / (2 * h)
+            err = max(err, np.max(np.abs(out[0] - inn[0])), np.max(np.abs(du_o - mu[p] * du_i)) / k)
+        worst.append(err)
+    assert worst[1] < 1e-5 and worst[1] < worst[0] / 10, worst

@@ -204,6 +204,28 @@ size_t mudiff_operator_workspace_size(mudiff_t h);
 int mudiff_set_operator(mudiff_t h, const double* op_w, const double* rhs_w, const double* ff_w,
                         void* workspace, size_t ws_bytes, void* stream);
 
+/* Penetrable disks (sec. 7, Example II): replaces the handle's operator,
+ * right-hand side and far field by those of the transmission problem with
+ * interior wavenumber k-_p and contrast mu_p in disk p (u+ - u- = -u_inc,
+ * d_n u+ - mu d_n u- = -d_n u_inc; u+ = L+ rho+ with the exterior wavenumber,
+ * u- = L- rho- with k-_p).  The interior operators act within one disk, so
+ * rho- is eliminated mode by mode; the equation solved is, per mode (any
+ * scaling of its two weights),
+ *   [J_m(k- a) (N+ - I/2) - mu k- J'_m(k- a) L+] rho+ = -J_m(k- a) dU + mu k- J'_m(k- a) U,
+ * and mudiff_farfield / mudiff_nearfield return the exterior scattered field
+ * a_L rho+ / L+ rho+.  The second row's interior block is -mu (I/2 + N-): the
+ * sign that the jump relations give, with which a matched medium (k- = k,
+ * mu = 1) scatters nothing; the printed + sign does not.  The interior density
+ * of mode m is rho-_m = (L+ rho+ + U)_m / ((i pi a / 2) J_m(k- a) H_m(k- a)).
+ *   k_int      [host] double [M_all] interior wavenumbers, > 0
+ *   mu         [host] double [M_all] contrasts, > 0, or NULL for all 1
+ *   workspace  as for mudiff_set_operator (same size), must outlive its use
+ * Undone by mudiff_set_operator(h, NULL, ...).  MUDIFF_ERR_INVALID on a
+ * wavenumber or contrast that is not finite and positive.  Enqueues two table
+ * kernels on `stream` and waits for them. */
+int mudiff_set_penetrable(mudiff_t h, const double* k_int, const double* mu, void* workspace,
+                          size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------- solver */
 
 size_t mudiff_gmres_workspace_size(mudiff_t h, int R, int restart, int flags);

@@ -279,6 +279,20 @@ class Problem:
                                              _p(ws), ws.numel(), _stream()))
         self._op_ws = ws  # the handle points into it
 
+    def set_penetrable(self, k_int, mu=None) -> None:
+        """Penetrable disks (sec. 7, Example II): interior wavenumber k_int and
+        contrast mu (scalars or one per disk over all instances).  gmres then
+        returns the exterior density rho+, farfield/nearfield the scattered field;
+        set_operator(None) returns to sound-soft disks."""
+        ki = np.broadcast_to(np.asarray(k_int, dtype=np.float64), (len(self.radii),)).copy()
+        mu_a = None if mu is None else np.broadcast_to(np.asarray(mu, dtype=np.float64), (len(self.radii),)).copy()
+        n = self.lib.mudiff_operator_workspace_size(self.h)
+        ws = torch.empty(int(n), dtype=torch.uint8, device=self.device)
+        L.check(self.lib.mudiff_set_penetrable(self.h, ki.ctypes.data,
+                                               None if mu_a is None else mu_a.ctypes.data,
+                                               _p(ws), ws.numel(), _stream()))
+        self._op_ws = ws
+
     # ----------------------------------------------------------- time reversal
     def mirror_farfield(self, n_alpha: int, restart: int = 50, tol: float = 1e-12,
                         maxit: int = 20000, graph: bool = False):

@@ -20,6 +20,7 @@
 // w_U U + w_dU dU (U = d J, dU = k d J', Prop. 4) and far field
 // f_L a_L + f_M a_M with (a_M)^p_m = -k (J'_m / J_m) (a_L)^p_m (the sign of the
 // double-layer potential's large-r form).
+#include "bessel.h"
 #include "common.h"
 
 namespace {
@@ -96,15 +97,121 @@ __global__ void k_op_tables(DevView v, OpWeights o, cplx* __restrict__ col, cplx
   ff[i] = cadd(cscale(o.fL, sa * J), cscale(o.fM, -k * sa * Jd));
 }
 
+// Penetrable disks (sec. 7, Example II): the transmission system
+//   [ L+           -L-            ] [rho+]   [ -U  ]
+//   [ -I/2 + N+    -mu (I/2 + N-) ] [rho-] = [ -dU ]
+// with the interior self blocks L- = (i pi a/2) J H and I/2 + N- =
+// (i pi k- a/2) J' H at k-_p a_p (diagonal in m; the sign of the (2,2) block is
+// the one the jump relations give).  Eliminating rho- mode by mode and
+// multiplying by J_m(k- a) (which keeps every mode solvable, also where J_m(k- a)
+// vanishes):
+//   [J- (N+ - I/2) - mu k- J'- L+] rho+ = -J- dU + mu k- J'- U,
+// one combination of N+ and L+ (shared column factor J) with per-mode row
+// weights s1 = J_m(k- a), s2 = -mu k- J'_m(k- a) (any per-mode scaling of the
+// two is the same equation).  The single-scattering preconditioner divides the
+// row weights out again.  J_m(k- a), m = 0..N+1,
+// comes from Miller's algorithm per disk.
+__global__ void k_interior_j(DevView v, const double* __restrict__ k_int, double* __restrict__ Jint) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= v.M_all) return;
+  double S0, S1;
+  bessel_j_miller(k_int[p] * v.a[p], v.N[p] + 1, Jint + v.dtab[p], 1, &S0, &S1);
+}
+
+__global__ void k_pen_tables(DevView v, const double* __restrict__ k_int, const double* __restrict__ mu,
+                             const double* __restrict__ Jint, cplx* __restrict__ col,
+                             cplx* __restrict__ rowA, cplx* __restrict__ row, cplx* __restrict__ diag,
+                             cplx* __restrict__ rhs, cplx* __restrict__ rhsp, cplx* __restrict__ ff) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= v.N_all) return;
+  const int p = v.udisk[i];
+  const int b = v.inst[p];
+  const int m = (int)(i - v.imode[b] - v.moff[p]) - v.N[p];
+  double J, Jd;
+  cplx H, Hd;
+  mode_values(v, p, m, &J, &Jd, &H, &Hd);
+  // interior J_m, J'_m at k- a (reflection to negative orders as for the exterior)
+  const int am = m < 0 ? -m : m;
+  const double sg = (m < 0 && (am & 1)) ? -1.0 : 1.0;
+  const double* Jt = Jint + v.dtab[p];
+  const double Ji = sg * Jt[am];
+  const double Jid = sg * 0.5 * ((am > 0 ? Jt[am - 1] : -Jt[1]) - Jt[am + 1]);
+  const double k = v.kd[p], a = v.a[p], sa = sqrt(a), ki = k_int[p];
+  // row weights, normalised so that |s1| + |s2| = 1 (J_m and J'_m of one
+  // argument never vanish together; without it the rows of high orders at small
+  // k- a would be tiny)
+  double s1 = Ji, s2 = -(mu ? mu[p] : 1.0) * ki * Jid;
+  const double nrm = 1.0 / (fabs(s1) + fabs(s2));
+  s1 *= nrm;
+  s2 *= nrm;
+  const cplx I1 = cmk(0.0, 1.0);
+  // row factor: s1 (i k pi / 2) sqrt(a) J'_m + s2 (i pi / 2) sqrt(a) J_m
+  const cplx r = cmul(I1, cmk(0.5 * OPS_PI * sa * (s1 * k * Jd + s2 * J), 0.0));
+  // diagonal: s1 (N+_mm - 1/2) + s2 L+_mm,  N+_mm = -1/2 + (i pi k a / 2) J' H
+  const cplx iJdH = cmul(I1, cscale(H, Jd)), iJH = cmul(I1, cscale(H, J));
+  const cplx d = cadd(cscale(cadd(cmk(-1.0, 0.0), cscale(iJdH, 0.5 * OPS_PI * k * a)), s1),
+                      cscale(iJH, 0.5 * OPS_PI * a * s2));
+  col[i] = cmk(sa * J, 0.0);
+  row[i] = r;
+  diag[i] = d;
+  rowA[i] = cdiv(r, d);
+  const cplx bq = cmk(sqrt(2.0 * OPS_PI * a) * (-s1 * k * Jd - s2 * J), 0.0);
+  rhs[i] = bq;
+  rhsp[i] = cdiv(bq, d);
+  ff[i] = cmk(sa * J, 0.0);
+}
+
 constexpr int OP_TABLES = 7;
 
 cplx read_c(const double* w, int k) { return cmk(w[2 * k], w[2 * k + 1]); }
+
+// Operator workspace: 7 complex tables per unknown, then (penetrable disks)
+// the interior J table and the per-disk k-, mu.
+size_t op_tables_bytes(const mudiff_ctx* h) { return (size_t)OP_TABLES * align256((size_t)h->N_all * 16); }
 
 }  // namespace
 
 extern "C" size_t mudiff_operator_workspace_size(mudiff_t h) {
   if (!h) return 0;
-  return (size_t)OP_TABLES * align256((size_t)h->N_all * 16);
+  return op_tables_bytes(h) + align256((size_t)h->D_all * 8) + 2 * align256((size_t)h->M_all * 8);
+}
+
+extern "C" int mudiff_set_penetrable(mudiff_t h, const double* k_int, const double* mu,
+                                     void* workspace, size_t ws_bytes, void* stream) {
+  if (!h || !k_int || !workspace) return fail(MUDIFF_ERR_INVALID, "NULL argument");
+  for (int p = 0; p < h->M_all; ++p) {
+    if (!(k_int[p] > 0.0) || !std::isfinite(k_int[p])) return fail(MUDIFF_ERR_INVALID, "interior wavenumbers must be > 0");
+    if (mu && (!(mu[p] > 0.0) || !std::isfinite(mu[p]))) return fail(MUDIFF_ERR_INVALID, "mu must be > 0");
+  }
+  const size_t need = mudiff_operator_workspace_size(h);
+  if (ws_bytes < need) return fail(MUDIFF_ERR_NOMEM, "operator workspace needs " + std::to_string(need) + " bytes");
+  if (((uintptr_t)workspace) & 255) return fail(MUDIFF_ERR_INVALID, "workspace must be 256-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  DevView& v = h->dv;
+  const size_t stride = align256((size_t)h->N_all * 16);
+  char* w = (char*)workspace;
+  cplx* t[OP_TABLES];
+  for (int k = 0; k < OP_TABLES; ++k) t[k] = (cplx*)(w + k * stride);
+  double* Jint = (double*)(w + op_tables_bytes(h));
+  double* dk = (double*)((char*)Jint + align256((size_t)h->D_all * 8));
+  double* dmu = (double*)((char*)dk + align256((size_t)h->M_all * 8));
+  HIP_TRY(hipMemcpyAsync(dk, k_int, (size_t)h->M_all * 8, hipMemcpyHostToDevice, s));
+  if (mu) HIP_TRY(hipMemcpyAsync(dmu, mu, (size_t)h->M_all * 8, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_interior_j, dim3((unsigned)((h->M_all + 63) / 64)), dim3(64), 0, s, v,
+                     (const double*)dk, Jint);
+  hipLaunchKernelGGL(k_pen_tables, dim3((unsigned)((h->N_all + 255) / 256)), dim3(256), 0, s, v,
+                     (const double*)dk, mu ? (const double*)dmu : nullptr, (const double*)Jint, t[0],
+                     t[1], t[2], t[3], t[4], t[5], t[6]);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));  // the host arrays are read by the copies above
+  v.op_col = t[0];
+  v.op_rowA = t[1];
+  v.op_row = t[2];
+  v.op_diag = t[3];
+  v.op_rhs = t[4];
+  v.op_rhsp = t[5];
+  v.op_ff = t[6];
+  return MUDIFF_OK;
 }
 
 extern "C" int mudiff_set_operator(mudiff_t h, const double* op_w, const double* rhs_w,

@@ -139,3 +139,5 @@ def test_set_operator_validation(lib):
     w = (ctypes.c_double * 10)()
     assert lib.mudiff_set_operator(None, w, w, w, None, 0, None) == 1
     assert lib.mudiff_operator_workspace_size(None) == 0
+    k = (ctypes.c_double * 4)(1.0, 1.0, 1.0, 1.0)
+    assert lib.mudiff_set_penetrable(None, k, None, w, 4096, None) == 1

@@ -1,0 +1,177 @@
+"""GPU parity of the penetrable-disk transmission problem (sec. 7, Example II)
+against the CPU oracle, through the C ABI via the binding.
+
+The GPU solves the reduced one-unknown equation (rho- eliminated mode by mode);
+the oracle solves the 2 x 2 block system, so the comparison of rho+ and of the
+far field also checks the reduction.  Tolerances: applies 1e-12 (norm-wise);
+solves at tol 1e-13: densities and far fields 1e-10; closed forms 1e-10;
+properties at full size (optical theorem) 1e-9.
+"""
+import numpy as np
+import pytest
+import torch
+from scipy import special as sp
+
+import synth
+from oracle import nearfield, operators as ops, penetrable as pen, rhs as orhs
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_1409_8186_amd import Problem
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return Problem
+
+
+CLUSTERS = {
+    # uniform N <= 12: one-lane kernel for R = 1, MFMA for R >= 8
+    "uniform": lambda: synth.Cluster(*synth.random_disks(np.random.default_rng(91), 9, 0.3, 0.7, 0.0, 7.0, 0.3),
+                                     np.full(9, 8, np.int32), 3.5),
+    # uneven N: generic kernel for R = 1
+    "uneven": lambda: synth.small_random(92, 7, 0.3, 0.9, 7.0, 0.3, 4.0, 4),
+}
+
+
+def _media(M, k, seed):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(0.5, 2.5, M) * k, rng.uniform(0.6, 2.0, M)
+
+
+def _reduced(cl, ki, mu):
+    """(N+ - I/2) - diag(mu (I/2 + N-) / L-) L+: the second block row after
+    eliminating rho- with the first (any per-row scaling gives the same D^-1 op)."""
+    Lp = ops.operator_matrix("L", cl.centers, cl.radii, cl.n_modes, cl.k)
+    Np = ops.operator_matrix("N", cl.centers, cl.radii, cl.n_modes, cl.k)
+    Lm, Nm = pen.interior_diagonals(cl.radii, cl.n_modes, ki)
+    disk = np.repeat(np.arange(len(cl.radii)), 2 * np.asarray(cl.n_modes) + 1)
+    return Np - 0.5 * np.eye(len(Lm)) - (mu[disk] * Nm / Lm)[:, None] * Lp
+
+
+@pytest.mark.parametrize("cname", ["uniform", "uneven"])
+@pytest.mark.parametrize("R", [1, 9])
+def test_penetrable_apply_matches_oracle(P, cname, R):
+    from paper_1409_8186_amd import _lib as L
+    cl = CLUSTERS[cname]()
+    ki, mu = _media(len(cl.radii), cl.k, 1)
+    red = _reduced(cl, ki, mu)
+    A = red / np.diag(red)[:, None]
+    rng = np.random.default_rng(R)
+    x = rng.standard_normal((R, red.shape[0])) + 1j * rng.standard_normal((R, red.shape[0]))
+    pr = P.from_cluster(cl)
+    pr.set_penetrable(ki, mu)
+    y = pr.matvec(torch.tensor(x.reshape(-1), device="cuda"), R=R, op=L.OP_A).cpu().numpy().reshape(R, -1)
+    say(cname, R, "D^-1 op x rel", rel(y, x @ A.T))
+    assert rel(y, x @ A.T) < 1e-12
+
+
+def test_penetrable_solve_and_farfield_match_oracle(P):
+    """Two instances (different k), per-disk k- and mu, three incidences."""
+    c1 = synth.small_random(93, 6, 0.3, 0.8, 6.0, 0.3, 3.0, 5)
+    c2 = synth.small_random(94, 5, 0.3, 0.9, 6.0, 0.3, 4.5, 5)
+    k1, m1 = _media(6, c1.k, 2)
+    k2, m2 = _media(5, c2.k, 3)
+    betas = np.array([[0.3, 1.9, 4.4], [2.0, 0.1, 5.5]])
+    th = synth.uniform_angles(48)
+    pr = P.from_clusters([c1, c2])
+    pr.set_penetrable(np.concatenate([k1, k2]), np.concatenate([m1, m2]))
+    rho, flag, relres, iters, _ = pr.gmres(betas=betas, restart=30, tol=1e-13, maxit=2000)
+    assert np.all(flag.cpu().numpy() == 0), relres
+    parts = pr.split(rho, R=3)
+    af = pr.farfield(rho, th, R=3).cpu().numpy().reshape(2, 3, -1)
+    for b, (cl, ki, mu) in enumerate([(c1, k1, m1), (c2, k2, m2)]):
+        rp, _ = pen.solve(cl.centers, cl.radii, cl.n_modes, cl.k, ki, betas[b], mu=mu)
+        say("instance", b, "rho+ rel", rel(parts[b].cpu().numpy(), rp))
+        assert rel(parts[b].cpu().numpy(), rp) < 1e-10
+        ref = pen.farfield(cl.centers, cl.radii, cl.n_modes, cl.k, rp, th)
+        assert rel(af[b], ref) < 1e-10
+    # near field of the first instance against the oracle total field of rho+
+    pr1 = P.from_cluster(c1)
+    pr1.set_penetrable(k1, m1)
+    rho1, flag1, _, _, _ = pr1.gmres(betas=betas[:1], restart=30, tol=1e-13, maxit=2000)
+    rp, _ = pen.solve(c1.centers, c1.radii, c1.n_modes, c1.k, k1, betas[0], mu=m1)
+    g = np.linspace(-2.0, 8.0, 30)
+    pts = np.stack(np.meshgrid(g, g, indexing="ij"), -1).reshape(-1, 2)
+    ut = pr1.nearfield(rho1, pts, R=3, betas=betas[:1]).cpu().numpy()
+    ref = nearfield.total_field(c1.centers, c1.radii, c1.n_modes, c1.k, rp, pts, betas[0])
+    assert rel(ut, ref) < 1e-10
+
+
+@pytest.mark.parametrize("ki,mu", [(8.0, 1.0), (2.4, 1.0), (6.0, 2.5)])
+def test_penetrable_single_disk_transmission_mie(P, ki, mu):
+    """One disk: matching the field and mu times its normal derivative across
+    the circle mode by mode gives c_m = (mu k- J'(k- a) J(k a) - k J(k- a) J'(k a))
+    / (k J(k- a) H'(k a) - mu k- J'(k- a) H(k a)) for the scattered field."""
+    O, a, k, N, beta = np.array([0.4, -0.6]), 0.8, 4.0, 18, 0.7
+    cl = synth.Cluster(O[None, :], np.array([a]), np.array([N], np.int32), k)
+    pr = P.from_cluster(cl)
+    pr.set_penetrable([ki], [mu])
+    rho, flag, _, _, _ = pr.gmres(betas=[[beta]], restart=40, tol=1e-14, maxit=400)
+    th = synth.uniform_angles(36)
+    af = pr.farfield(rho, th).cpu().numpy()[0]
+    m = np.arange(-N, N + 1)
+    Ji, Jid = sp.jv(m, ki * a), sp.jvp(m, ki * a)
+    J, Jd, H, Hd = sp.jv(m, k * a), sp.jvp(m, k * a), sp.hankel1(m, k * a), sp.h1vp(m, k * a)
+    c = (mu * ki * Jid * J - k * Ji * Jd) / (k * Ji * Hd - mu * ki * Jid * H)
+    ph = np.exp(1j * k * ((np.cos(beta) - np.cos(th)) * O[0] + (np.sin(beta) - np.sin(th)) * O[1]))
+    ref = np.exp(-0.25j * np.pi) * np.sqrt(2.0 / (np.pi * k)) * ph * np.sum(
+        c[None, :] * np.exp(1j * m[None, :] * (th[:, None] - beta)), axis=1)
+    assert rel(af, ref) < 1e-10
+
+
+def test_penetrable_matched_medium_has_no_right_hand_side(P):
+    """k- = k and mu = 1: the reduced right-hand side -J dU + k J' U vanishes mode
+    by mode (no scattered field), to rounding of the two Bessel tables."""
+    cl = synth.small_random(95, 6, 0.3, 0.8, 6.0, 0.3, 3.0, 6)
+    betas = [0.5, 2.0]
+    pr = P.from_cluster(cl)
+    pr.set_penetrable(cl.k)
+    b = pr.rhs([betas]).cpu().numpy().reshape(2, -1)
+    U = orhs.planewave(cl.centers, cl.radii, cl.n_modes, cl.k, betas)
+    dU = ops.planewave_dn(cl.centers, cl.radii, cl.n_modes, cl.k, betas)
+    assert np.all(np.abs(b) <= 1e-13 * np.maximum(np.abs(U), np.abs(dU)) + 1e-300)
+
+
+def test_penetrable_reset_and_gradient_guard(P):
+    from paper_1409_8186_amd import _lib as L
+    cl = CLUSTERS["uneven"]()
+    pr = P.from_cluster(cl)
+    r0, _, _, _, _ = pr.gmres(betas=[[0.8]], tol=1e-12)
+    pr.set_penetrable(1.7 * cl.k, 1.3)
+    with pytest.raises(L.MudiffError):
+        pr.grad([[0.8]], [0.1, 0.2], torch.zeros(2, dtype=torch.complex128, device="cuda"))
+    pr.set_operator(None)
+    r1, _, _, _, _ = pr.gmres(betas=[[0.8]], tol=1e-12)
+    assert torch.allclose(r0, r1, rtol=0, atol=1e-13 * float(r0.abs().max()))
+
+
+def test_penetrable_full_size_optical_theorem(P):
+    """The one-RHS geometry (M = 400, N_p = 12, k = 2 pi) with k- = 1.5 k and mu
+    in [0.6, 2]: solve to 1e-12, then energy conservation
+    int |a|^2 = -sqrt(8 pi / k) Re(e^{i pi/4} a(beta; beta)), which the truncated
+    system keeps exactly for real k- and mu (4096 far-field angles integrate |a|^2
+    exactly here)."""
+    cl = synth.one_rhs()
+    beta = np.pi / 4
+    mu = np.random.default_rng(6).uniform(0.6, 2.0, len(cl.radii))
+    pr = P.from_cluster(cl)
+    pr.set_penetrable(1.5 * cl.k, mu)
+    rho, flag, relres, iters, _ = pr.gmres(betas=[[beta]], restart=50, tol=1e-12, maxit=20000, graph=True)
+    say("iterations", int(iters[0]), "relres", float(relres[0]))
+    assert int(flag[0]) == 0
+    nt = 4096
+    a = pr.farfield(rho, synth.uniform_angles(nt)).cpu().numpy()[0]
+    a0 = pr.farfield(rho, [beta]).cpu().numpy()[0, 0]
+    lhs = np.sum(np.abs(a) ** 2) * 2 * np.pi / nt
+    rhs_ = -np.sqrt(8 * np.pi / cl.k) * np.real(np.exp(0.25j * np.pi) * a0)
+    say("optical theorem", lhs, rhs_)
+    assert abs(lhs - rhs_) < 1e-9 * abs(rhs_)

@@ -731,3 +731,23 @@ def test_penetrable_transmission_conditions_on_the_boundaries():
             err = max(err, np.max(np.abs(out[0] - inn[0])), np.max(np.abs(du_o - mu[p] * du_i)) / k)
         worst.append(err)
     assert worst[1] < 1e-5 and worst[1] < worst[0] / 10, worst
+
+
+def test_penetrable_optical_theorem():
+    """Real k- and mu: no energy is absorbed inside, and the truncated system
+    keeps int |a|^2 = -sqrt(8 pi / k) Re(e^{i pi/4} a(beta; beta)) exactly.  A
+    phase error in an interior block (a lost i, a conjugated Hankel function)
+    breaks it; a real rescaling of mu does not (the matched-medium and Mie pins
+    cover those)."""
+    from oracle import penetrable as pen
+    cl = synth.small_random(13, 8, 0.2, 0.9, 7.0, 0.2, 3.7, 5)
+    ki = np.linspace(0.6, 2.2, 8) * cl.k
+    mu = np.linspace(0.7, 2.0, 8)
+    beta, nt = 0.9, 512
+    th = synth.uniform_angles(nt)
+    rp, _ = pen.solve(cl.centers, cl.radii, cl.n_modes, cl.k, ki, [beta], mu=mu)
+    a = pen.farfield(cl.centers, cl.radii, cl.n_modes, cl.k, rp, th)[0]
+    a0 = pen.farfield(cl.centers, cl.radii, cl.n_modes, cl.k, rp, [beta])[0, 0]
+    lhs = np.sum(np.abs(a) ** 2) * 2 * np.pi / nt
+    rhs_ = -np.sqrt(8 * np.pi / cl.k) * np.real(np.exp(0.25j * np.pi) * a0)
+    assert abs(lhs - rhs_) < 1e-12 * abs(rhs_)

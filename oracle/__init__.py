@@ -24,6 +24,8 @@ What it computes, each module citing the paper passage it writes out:
              sound-hard single- and double-layer equations
   penetrable transmission problem of penetrable disks: the 2x2       (sec. 7, Example II)
              block system, far field, interior fields
+  pointsource trace coefficients of a point source's incident wave  (Prop. 5)
+             and the incident field (i/4) H_0(k |x - s|)
   nearfield  single- and double-layer potentials at points        (sec. 4.4, Graf's theorem)
              and the total field
   dort       far-field mirror matrix F, time-reversal matrix      (sec. 7, Example III)
@@ -37,4 +39,4 @@ identities of the truncated system, brute force).  The one output with no
 such pin is the GMRES iteration count (parity unpinned; the converged
 solution is pinned against LU).
 """
-from . import geometry, bessel, operator, rhs, farfield, solve, gradient, dort, operators, nearfield, penetrable  # noqa: F401
+from . import geometry, bessel, operator, rhs, farfield, solve, gradient, dort, operators, nearfield, penetrable, pointsource  # noqa: F401

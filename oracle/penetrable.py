@@ -62,9 +62,16 @@ def system(centers, radii, n_modes, k, k_int, mu=None):
 
 def solve(centers, radii, n_modes, k, k_int, betas, mu=None):
     """(rho+ [R, N_tot], rho- [R, N_tot]) for plane waves of incidence betas."""
-    A = system(centers, radii, n_modes, k, k_int, mu)
     U = planewave(centers, radii, n_modes, k, betas)
     dU = planewave_dn(centers, radii, n_modes, k, betas)
+    return solve_coefficients(centers, radii, n_modes, k, k_int, U, dU, mu)
+
+
+def solve_coefficients(centers, radii, n_modes, k, k_int, U, dU, mu=None):
+    """(rho+, rho-) for given trace coefficients U, dU [R, N_tot] of the
+    incident wave (plane wave, Prop. 4; point source, Prop. 5)."""
+    A = system(centers, radii, n_modes, k, k_int, mu)
+    U, dU = np.atleast_2d(U), np.atleast_2d(dU)
     x = np.linalg.solve(A, np.concatenate([-U, -dU], axis=1).T).T
     n = U.shape[1]
     return x[:, :n], x[:, n:]

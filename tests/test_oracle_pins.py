@@ -751,3 +751,83 @@ def test_penetrable_optical_theorem():
     lhs = np.sum(np.abs(a) ** 2) * 2 * np.pi / nt
     rhs_ = -np.sqrt(8 * np.pi / cl.k) * np.real(np.exp(0.25j * np.pi) * a0)
     assert abs(lhs - rhs_) < 1e-12 * abs(rhs_)
+
+
+# -------------------------------------------------------------- point source
+def _circle_coefficients(fun, O, a, N, nq=512):
+    """<f, Phi_m> = int_0^{2 pi} f(O + a e^{it}) e^{-imt} a dt / sqrt(2 pi a) by the
+    trapezoid rule (spectrally accurate for a smooth periodic integrand)."""
+    t = 2 * np.pi * np.arange(nq) / nq
+    x = np.asarray(O)[None, :] + a * np.stack([np.cos(t), np.sin(t)], 1)
+    f = fun(x, t)
+    m = np.arange(-N, N + 1)
+    return (f[None, :] * np.exp(-1j * m[:, None] * t[None, :])).sum(1) * (2 * np.pi / nq) * a / np.sqrt(2 * np.pi * a)
+
+
+def test_point_source_coefficients_by_quadrature():
+    """Prop. 5 against quadrature of G(x, s) = (i/4) H_0(k|x - s|) and of its
+    normal derivative -(i/4) k H_1(k|x - s|) (x - s).n / |x - s| over each circle."""
+    from oracle import pointsource as ps
+    from oracle.geometry import mode_offsets
+    cl = synth.small_random(101, 4, 0.3, 0.9, 6.0, 0.3, 3.3, 7)
+    src = np.array([[-1.5, 2.0], [7.5, -0.5]])
+    U = ps.point_source(cl.centers, cl.radii, cl.n_modes, cl.k, src)
+    dU = ps.point_source_dn(cl.centers, cl.radii, cl.n_modes, cl.k, src)
+    off, _ = mode_offsets(cl.n_modes)
+    for r, s in enumerate(src):
+        for p in range(len(cl.radii)):
+            O, a, N = cl.centers[p], cl.radii[p], int(cl.n_modes[p])
+
+            def g(x, t):
+                return 0.25j * sp.hankel1(0, cl.k * np.hypot(*(x - s).T))
+
+            def dg(x, t):
+                d = x - s
+                rr = np.hypot(*d.T)
+                nrm = np.stack([np.cos(t), np.sin(t)], 1)
+                return -0.25j * cl.k * sp.hankel1(1, cl.k * rr) * np.sum(d * nrm, 1) / rr
+            assert rel(U[r, off[p]:off[p + 1]], _circle_coefficients(g, O, a, N)) < 1e-12
+            assert rel(dU[r, off[p]:off[p + 1]], _circle_coefficients(dg, O, a, N)) < 1e-12
+
+
+def test_point_source_single_disk_closed_form():
+    """Sound-soft disk, source s: u = -(i/4) sum_m J_m(ka)/H_m(ka) H_m(k r_s)
+    H_m(k r) e^{i m (theta - theta_s)} outside (Graf's theorem plus u + G = 0 on
+    the circle), against the EFIE solve and its near field."""
+    from oracle import nearfield, pointsource as ps
+    O, a, k, N = np.array([0.3, -0.2]), 0.7, 2.7, 22
+    s = np.array([1.9, 1.1])
+    U = ps.point_source(O[None, :], [a], [N], k, s[None, :])
+    L = operator.efie_matrix(O[None, :], np.array([a]), np.array([N]), k)
+    rho = np.linalg.solve(L, -U[0])
+    rng = np.random.default_rng(7)
+    rr = rng.uniform(1.05 * a, 3.0, 40)
+    tt = rng.uniform(0, 2 * np.pi, 40)
+    pts = O[None, :] + rr[:, None] * np.stack([np.cos(tt), np.sin(tt)], 1)
+    u = nearfield.potential(O[None, :], [a], [N], k, rho, pts)
+    rs, ts = np.hypot(*(s - O)), np.arctan2(*(s - O)[::-1])
+    m = np.arange(-40, 41)
+    ref = -0.25j * np.sum((sp.jv(m, k * a) / sp.hankel1(m, k * a) * sp.hankel1(m, k * rs))[None, :]
+                          * sp.hankel1(m[None, :], k * rr[:, None]) * np.exp(1j * m[None, :] * (tt[:, None] - ts)), 1)
+    assert rel(u, ref) < 1e-12
+
+
+def test_point_source_reciprocity():
+    """The scattered field is symmetric in source and receiver:
+    u^s(x; s) = u^s(s; x), for sound-soft (EFIE) and penetrable disks."""
+    from oracle import nearfield, penetrable as pen, pointsource as ps
+    cl = synth.small_random(102, 5, 0.3, 0.8, 6.0, 0.3, 3.1, 8)
+    s1, s2 = np.array([-1.0, 1.5]), np.array([7.0, 4.0])
+    src = np.stack([s1, s2])
+    U = ps.point_source(cl.centers, cl.radii, cl.n_modes, cl.k, src)
+    L = operator.efie_matrix(cl.centers, cl.radii, cl.n_modes, cl.k)
+    rho = np.linalg.solve(L, -U.T).T
+    u12 = nearfield.potential(cl.centers, cl.radii, cl.n_modes, cl.k, rho[0], s2[None, :])[0]
+    u21 = nearfield.potential(cl.centers, cl.radii, cl.n_modes, cl.k, rho[1], s1[None, :])[0]
+    assert abs(u12 - u21) < 1e-12 * abs(u12)
+    ki, mu = np.linspace(0.6, 2.0, 5) * cl.k, np.linspace(0.8, 1.6, 5)
+    dU = ps.point_source_dn(cl.centers, cl.radii, cl.n_modes, cl.k, src)
+    rp, _ = pen.solve_coefficients(cl.centers, cl.radii, cl.n_modes, cl.k, ki, U, dU, mu)
+    v12 = nearfield.potential(cl.centers, cl.radii, cl.n_modes, cl.k, rp[0], s2[None, :])[0]
+    v21 = nearfield.potential(cl.centers, cl.radii, cl.n_modes, cl.k, rp[1], s1[None, :])[0]
+    assert abs(v12 - v21) < 1e-11 * abs(v12)

@@ -75,7 +75,8 @@ enum {
 /* mudiff_gmres flags */
 enum {
   MUDIFF_X0 = 1,        /* rho holds the initial guess on entry (else x0 = 0)          */
-  MUDIFF_GRAPH = 2      /* replay each restart cycle as one captured HIP graph          */
+  MUDIFF_GRAPH = 2,     /* replay each restart cycle as one captured HIP graph          */
+  MUDIFF_POINT_SOURCE = 4 /* beta holds point-source positions [B][R][2] (Prop. 5)   */
 };
 
 /* Largest accepted truncation order N_p and GMRES restart length. */
@@ -170,6 +171,19 @@ int mudiff_set_apply_config(mudiff_t h, int R, int ct, int rp, int qs, int threa
  *              right-hand side f = -D^{-1} U (precond = 1). */
 int mudiff_rhs(mudiff_t h, int R, const double* beta, void* out, int precond, void* stream);
 
+/* Point-source right-hand side (Prop. 5): the incident wave is the Green's
+ * function G(x, s) = (i/4) H_0(k |x - s|) of a source s outside every disk, with
+ *   U^p_m = (i/4) sqrt(2 pi a_p) J_m(k a_p) H_m(k r_p) e^{-i m theta_p},
+ * (r_p, theta_p) the polar coordinates of s - O_p (the printed
+ * (i pi a/2) J H conj(Phi~(s)) with Phi~ = e^{i m theta} / sqrt(2 pi a)).
+ *   src        device double [B][R][2] source positions
+ *   out        as for mudiff_rhs (also after mudiff_set_operator /
+ *              mudiff_set_penetrable: their right-hand side from this U, dU)
+ * A source inside or on disk p (r_p <= a_p, where the expansion does not hold)
+ * gives NaN coefficients for that disk; mudiff_gmres then ends the column with
+ * flag 2. */
+int mudiff_rhs_point(mudiff_t h, int R, const double* src, void* out, int precond, void* stream);
+
 /* ---------------------------------------------------------------- operators */
 
 /* Replaces the handle's operator, right-hand side and far field by a linear
@@ -233,7 +247,9 @@ size_t mudiff_gmres_workspace_size(mudiff_t h, int R, int restart, int flags);
 /* Restarted GMRES(restart) on A x = f, A = D^{-1} L, f = -D^{-1} U (sec. 5),
  * one independent Krylov space per (instance, right-hand side) column, all
  * columns sharing every operator application (lockstep batching).
- *   beta       device [B][R] incidence angles, or NULL to use `rhs`
+ *   beta       device [B][R] incidence angles, or with MUDIFF_POINT_SOURCE
+ *              [B][R][2] point-source positions (mudiff_rhs_point), or NULL to
+ *              use `rhs`
  *   rhs        device complex128 [B][R][N_b]: the right-hand side U of
  *              L rho = -U (used when beta == NULL)
  *   rho        device complex128 [B][R][N_b] output density; with MUDIFF_X0
@@ -274,10 +290,12 @@ int mudiff_farfield(mudiff_t h, int R, const void* rho, int n_theta, const doubl
  *   pts    device double [n_pts][2], shared by all instances
  *   beta   device [B][R] incidence angles: the total field u_inc + u; or NULL:
  *          the scattered field u
+ *   flags  0, or MUDIFF_POINT_SOURCE: beta holds [B][R][2] source positions and
+ *          u_inc = (i/4) H_0(k |x - s|) (infinite at x = s)
  *   out    device complex128 [B][R][n_pts]; 0 at points inside a disk
- * Errors: MUDIFF_ERR_INVALID. */
+ * Errors: MUDIFF_ERR_INVALID (also for other flags). */
 int mudiff_nearfield(mudiff_t h, int R, const void* rho, int n_pts, const double* pts,
-                     const double* beta, void* out, void* stream);
+                     const double* beta, int flags, void* out, void* stream);
 
 /* ---------------------------------------------------------------- gradient */
 

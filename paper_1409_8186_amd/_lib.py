@@ -30,11 +30,12 @@ SIGNATURES = {
     "mudiff_matvec_workspace_size": (_sz, [_vp, _i32]),
     "mudiff_matvec": (_i32, [_vp, _i32, _vp, _vp, _i32, _vp, _sz, _vp]),
     "mudiff_rhs": (_i32, [_vp, _i32, _vp, _vp, _i32, _vp]),
+    "mudiff_rhs_point": (_i32, [_vp, _i32, _vp, _vp, _i32, _vp]),
     "mudiff_gmres_workspace_size": (_sz, [_vp, _i32, _i32, _i32]),
     "mudiff_gmres": (_i32, [_vp, _i32, _vp, _vp, _vp, _i32, _d, _i32, _i32, _vp, _sz,
                             _vp, _vp, _vp, _vp, _vp]),
     "mudiff_farfield": (_i32, [_vp, _i32, _vp, _i32, _vp, _vp, _vp]),
-    "mudiff_nearfield": (_i32, [_vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp]),
+    "mudiff_nearfield": (_i32, [_vp, _i32, _vp, _i32, _vp, _vp, _i32, _vp, _vp]),
     "mudiff_grad_workspace_size": (_sz, [_vp, _i32, _i32, _i32, _i32]),
     "mudiff_grad": (_i32, [_vp, _i32, _vp, _i32, _vp, _vp, _i32, _d, _i32, _i32, _vp, _sz,
                            _vp, _vp, _vp, _vp, _vp]),
@@ -53,7 +54,7 @@ SIGNATURES = {
 
 STATUS = {0: "OK", 1: "INVALID", 2: "OVERLAP", 3: "NOMEM", 4: "DEVICE", 5: "NOT_CONVERGED"}
 OP_L, OP_A = 0, 1
-X0, GRAPH = 1, 2
+X0, GRAPH, POINT_SOURCE = 1, 2, 4
 PROBE_FP64_FMA, PROBE_FP64_MFMA, PROBE_COPY = 0, 1, 2
 
 

@@ -160,13 +160,23 @@ class Problem:
         """Fix the MFMA tile of the R-column apply (no autotuning for this R)."""
         L.check(self.lib.mudiff_set_apply_config(self.h, R, ct, rp, qs, threads))
 
-    def rhs(self, betas, precond: bool = False) -> torch.Tensor:
-        """betas: [B, R] incidence angles."""
+    def rhs(self, betas=None, precond: bool = False, sources=None) -> torch.Tensor:
+        """betas: [B, R] incidence angles, or sources: [B, R, 2] point-source
+        positions (Prop. 5)."""
+        if sources is not None:
+            src = self._sources(sources)
+            R = src.shape[1]
+            out = self.empty(R)
+            L.check(self.lib.mudiff_rhs_point(self.h, R, _p(src), _p(out), int(precond), _stream()))
+            return out
         b = self._f64(betas).reshape(self.B, -1)
         R = b.shape[1]
         out = self.empty(R)
         L.check(self.lib.mudiff_rhs(self.h, R, _p(b), _p(out), int(precond), _stream()))
         return out
+
+    def _sources(self, sources) -> torch.Tensor:
+        return self._f64(sources).reshape(self.B, -1, 2).contiguous()
 
     # ----------------------------------------------------------- solver
     def gmres_workspace(self, R: int, restart: int, flags: int = 0) -> torch.Tensor:
@@ -177,11 +187,17 @@ class Problem:
 
     def gmres(self, betas=None, rhs=None, R: int | None = None, restart: int = 50,
               tol: float = 1e-8, maxit: int = 20000, x0=None, graph: bool = False,
-              want_resvec: bool = False, workspace=None):
-        """Solves L rho = -U.  Returns (rho, flag, relres, iters, resvec)."""
+              want_resvec: bool = False, workspace=None, sources=None):
+        """Solves L rho = -U for plane waves (betas [B, R]), point sources
+        (sources [B, R, 2]) or a given U (rhs).  Returns (rho, flag, relres,
+        iters, resvec)."""
         flags = 0
         bt = None
-        if betas is not None:
+        if sources is not None:
+            bt = self._sources(sources)
+            R = bt.shape[1]
+            flags |= L.POINT_SOURCE
+        elif betas is not None:
             bt = self._f64(betas).reshape(self.B, -1)
             R = bt.shape[1]
         else:
@@ -216,14 +232,19 @@ class Problem:
         return out.view(self.B * R, th.numel())
 
     # ----------------------------------------------------------- near field
-    def nearfield(self, rho: torch.Tensor, points, R: int = 1, betas=None) -> torch.Tensor:
-        """Scattered field (or, with betas [B, R], the total field) at points
-        [P, 2]; 0 inside disks.  Returns [B*R, P]."""
+    def nearfield(self, rho: torch.Tensor, points, R: int = 1, betas=None, sources=None) -> torch.Tensor:
+        """Scattered field (or, with betas [B, R] or point sources [B, R, 2], the
+        total field) at points [P, 2]; 0 inside disks.  Returns [B*R, P]."""
         pts = self._f64(points).reshape(-1, 2).contiguous()
-        bt = None if betas is None else self._f64(betas).reshape(self.B, R).contiguous()
+        flags = 0
+        if sources is not None:
+            bt = self._f64(sources).reshape(self.B, R, 2).contiguous()
+            flags = L.POINT_SOURCE
+        else:
+            bt = None if betas is None else self._f64(betas).reshape(self.B, R).contiguous()
         out = torch.empty(self.B * R * pts.shape[0], dtype=torch.complex128, device=self.device)
         L.check(self.lib.mudiff_nearfield(self.h, R, _p(rho.contiguous()), pts.shape[0], _p(pts),
-                                          _p(bt), _p(out), _stream()))
+                                          _p(bt), flags, _p(out), _stream()))
         return out.view(self.B * R, pts.shape[0])
 
     # ----------------------------------------------------------- operators

@@ -343,5 +343,6 @@ struct PlanHost;
 void make_plan(int B, const int64_t* idisk, const int32_t* N, PlanHost& P);
 size_t plan_sched_bytes(const PlanHost& P, int M);
 
-int launch_rhs(mudiff_ctx* h, int R, const double* beta, cplx* out, int precond, hipStream_t s);
+int launch_rhs(mudiff_ctx* h, int R, const double* beta, cplx* out, int precond, int point,
+               hipStream_t s);
 int launch_fill_zero(void* p, size_t bytes, hipStream_t s);

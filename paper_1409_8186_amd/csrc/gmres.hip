@@ -1065,7 +1065,8 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
   if ((rc = launch_fill_zero(s.n_inner, 4, st)) != MUDIFF_OK) return rc;
   // right-hand side f
   if (beta) {
-    if ((rc = launch_rhs(h, R, beta, (cplx*)s.f, 1, st)) != MUDIFF_OK) return rc;
+    if ((rc = launch_rhs(h, R, beta, (cplx*)s.f, 1, (flags & MUDIFF_POINT_SOURCE) ? 1 : 0, st)) != MUDIFF_OK)
+      return rc;
   } else {
     hipLaunchKernelGGL(k_precond_rhs, dim3(eb), dim3(256), 0, st, h->dv, R, (const cplx*)rhs,
                        (cplx*)s.f, -1.0);

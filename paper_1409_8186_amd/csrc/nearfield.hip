@@ -4,7 +4,8 @@
 // F^p_m = sqrt(a_p) J_m(k a_p) for the single-layer potential; for an operator
 // set by mudiff_set_operator, F = f_L sqrt(a) J_m - f_M k sqrt(a) J'_m (its
 // far-field weights: single- plus double-layer potential).  The total field
-// adds the incident plane wave.  Points inside a disk get 0.
+// adds the incident wave: the plane wave e^{i k beta_hat . x}, or for a point
+// source s (Prop. 5) G(x, s) = (i/4) H_0(k |x - s|).  Points inside a disk get 0.
 //
 // One thread per point, every thread walking the same disks (so the disk data
 // and the coefficients are wave-uniform loads); per (point, disk): H_0, H_1 of
@@ -63,7 +64,7 @@ __device__ __forceinline__ void hankel01_near(double x, cplx* H0, cplx* H1) {
 __global__ __launch_bounds__(NF_THREADS) void k_nearfield(DevView v, int R, const cplx* __restrict__ rho,
                                                           int n_pts, const double* __restrict__ pts,
                                                           const double* __restrict__ beta,
-                                                          cplx* __restrict__ out) {
+                                                          int point, cplx* __restrict__ out) {
   // coefficients (i sqrt(pi/8)) F rho of the current disk: [2 N_p + 1][NF_RC]
   __shared__ cplx cf[(2 * MUDIFF_MAX_NP + 1) * NF_RC];
   const int P = blockIdx.x * NF_THREADS + threadIdx.x;
@@ -134,7 +135,12 @@ __global__ __launch_bounds__(NF_THREADS) void k_nearfield(DevView v, int R, cons
     if (c >= nr) continue;
     const int col = b * R + r0 + c;
     cplx u = acc[c];
-    if (beta) {
+    if (beta && point) {
+      const double dx = x1 - beta[2 * col], dy = x2 - beta[2 * col + 1];
+      cplx H0, H1;
+      hankel01_near(k * sqrt(dx * dx + dy * dy), &H0, &H1);
+      u = cadd(u, cmk(-0.25 * H0.y, 0.25 * H0.x));
+    } else if (beta) {
       double sb, cb;
       sincos(beta[col], &sb, &cb);
       u = cadd(u, cexpi(k * (cb * x1 + sb * x2)));
@@ -146,14 +152,16 @@ __global__ __launch_bounds__(NF_THREADS) void k_nearfield(DevView v, int R, cons
 }  // namespace
 
 extern "C" int mudiff_nearfield(mudiff_t h, int R, const void* rho, int n_pts, const double* pts,
-                                const double* beta, void* out, void* stream) {
+                                const double* beta, int flags, void* out, void* stream) {
   if (!h || !rho || !pts || !out) return fail(MUDIFF_ERR_INVALID, "NULL argument");
+  if (flags & ~MUDIFF_POINT_SOURCE) return fail(MUDIFF_ERR_INVALID, "unknown flags");
   if (R < 1 || n_pts < 1) return fail(MUDIFF_ERR_INVALID, "R < 1 or n_pts < 1");
   const int nchunk = (R + NF_RC - 1) / NF_RC;
   if ((int64_t)h->B * nchunk > 65535) return fail(MUDIFF_ERR_INVALID, "too many instance x RHS columns");
   dim3 grid((unsigned)((n_pts + NF_THREADS - 1) / NF_THREADS), (unsigned)(h->B * nchunk));
   hipLaunchKernelGGL(k_nearfield, grid, dim3(NF_THREADS), 0, (hipStream_t)stream, h->dv, R,
-                     (const cplx*)rho, n_pts, pts, beta, (cplx*)out);
+                     (const cplx*)rho, n_pts, pts, beta, (flags & MUDIFF_POINT_SOURCE) ? 1 : 0,
+                     (cplx*)out);
   HIP_TRY(hipGetLastError());
   return MUDIFF_OK;
 }

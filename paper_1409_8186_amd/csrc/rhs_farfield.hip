@@ -6,13 +6,41 @@
 //   a(theta) = sum_p sum_m g^p_m(theta) rho^p_m,
 //   g^p_m(theta) = (e^{i pi/4} / (2 sqrt k)) e^{-i k theta_hat . O_p}
 //                  sqrt(a_p) J_m(k a_p) e^{i m (theta - pi/2)}
+//
+// Point source s (Prop. 5): the same with the incident factor
+//   e = (i/4) H_m(k r_p) e^{-i m theta_p}  (r_p, theta_p: polar coordinates of s - O_p)
+// in place of e^{i k beta_hat . O_p} e^{i m (pi/2 - beta)}, so that
+// U = sqrt(2 pi a) J_m e as for the plane wave.
+#include "bessel.h"
 #include "common.h"
 
 #define PI_D 3.14159265358979323846
 
-// one thread per unknown of every (instance, rhs) column
+// (i/4) H_m(k r) e^{-i m theta} of the source at src relative to disk p; NaN if
+// the source is not outside the disk (the expansion needs r > a).
+__device__ cplx point_factor(const DevView& v, int p, int m, const double* src) {
+  const double dx = src[0] - v.cx[p], dy = src[1] - v.cy[p];
+  const double r = sqrt(dx * dx + dy * dy);
+  if (!(r > v.a[p])) return cmk(__builtin_nan(""), __builtin_nan(""));
+  const double x = v.kd[p] * r;
+  cplx Hm1, Hm;
+  hankel01(x, &Hm1, &Hm);  // H_0, H_1
+  const int am = m < 0 ? -m : m;
+  if (am == 0) Hm = Hm1;
+  for (int n = 1; n < am; ++n) {  // upward recurrence (stable: Y_n grows)
+    const cplx Hn = csub(cscale(Hm, 2.0 * n / x), Hm1);
+    Hm1 = Hm;
+    Hm = Hn;
+  }
+  if (m < 0 && (am & 1)) Hm = cscale(Hm, -1.0);  // H_{-m} = (-1)^m H_m
+  const cplx t = cmul(Hm, cexpi(-m * atan2(dy, dx)));
+  return cmk(-0.25 * t.y, 0.25 * t.x);
+}
+
+// one thread per unknown of every (instance, rhs) column; `point`: beta holds
+// source positions [B][R][2]
 __global__ void k_rhs(DevView v, int R, const double* __restrict__ beta, cplx* __restrict__ out,
-                      int precond) {
+                      int precond, int point) {
   const int64_t total = (int64_t)R * v.N_all;
   int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= total) return;
@@ -30,13 +58,18 @@ __global__ void k_rhs(DevView v, int R, const double* __restrict__ beta, cplx* _
   const int64_t i = v.imode[b] + il;
   const int p = v.udisk[i];
   const int m = (int)(il - v.moff[p]) - v.N[p];
-  const double be = beta[b * R + r];
-  const double kk = v.kd[p];
-  double sb, cb;
-  sincos(be, &sb, &cb);
-  const cplx e1 = cexpi(kk * (cb * v.cx[p] + sb * v.cy[p]));
-  const cplx e2 = cexpi(m * (0.5 * PI_D - be));
-  const cplx e = cmul(e1, e2);
+  cplx e;
+  if (point) {
+    e = point_factor(v, p, m, beta + 2 * ((int64_t)b * R + r));
+  } else {
+    const double be = beta[b * R + r];
+    const double kk = v.kd[p];
+    double sb, cb;
+    sincos(be, &sb, &cb);
+    const cplx e1 = cexpi(kk * (cb * v.cx[p] + sb * v.cy[p]));
+    const cplx e2 = cexpi(m * (0.5 * PI_D - be));
+    e = cmul(e1, e2);
+  }
   const double s2pi = sqrt(2.0 * PI_D);
   if (v.op_rhs) {  // operator set by mudiff_set_operator: w_U U + w_dU dU (over its diagonal)
     out[g] = cmul(e, precond ? v.op_rhsp[i] : v.op_rhs[i]);
@@ -51,10 +84,11 @@ __global__ void k_rhs(DevView v, int R, const double* __restrict__ beta, cplx* _
   }
 }
 
-int launch_rhs(mudiff_ctx* h, int R, const double* beta, cplx* out, int precond, hipStream_t s) {
+int launch_rhs(mudiff_ctx* h, int R, const double* beta, cplx* out, int precond, int point,
+               hipStream_t s) {
   const int64_t total = (int64_t)R * h->N_all;
   hipLaunchKernelGGL(k_rhs, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, h->dv, R, beta,
-                     out, precond);
+                     out, precond, point);
   HIP_TRY(hipGetLastError());
   return MUDIFF_OK;
 }
@@ -63,7 +97,14 @@ extern "C" int mudiff_rhs(mudiff_t h, int R, const double* beta, void* out, int 
                           void* stream) {
   if (!h || !beta || !out) return fail(MUDIFF_ERR_INVALID, "NULL argument");
   if (R < 1) return fail(MUDIFF_ERR_INVALID, "R < 1");
-  return launch_rhs(h, R, beta, (cplx*)out, precond ? 1 : 0, (hipStream_t)stream);
+  return launch_rhs(h, R, beta, (cplx*)out, precond ? 1 : 0, 0, (hipStream_t)stream);
+}
+
+extern "C" int mudiff_rhs_point(mudiff_t h, int R, const double* src, void* out, int precond,
+                                void* stream) {
+  if (!h || !src || !out) return fail(MUDIFF_ERR_INVALID, "NULL argument");
+  if (R < 1) return fail(MUDIFF_ERR_INVALID, "R < 1");
+  return launch_rhs(h, R, src, (cplx*)out, precond ? 1 : 0, 1, (hipStream_t)stream);
 }
 
 // Far field.  Workgroup = (column, tile of FF_TH angles); its FF_DG thread

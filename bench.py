@@ -247,6 +247,8 @@ def other_workload(args):
         return formulations_workload(base)
     if args.workload == "nearfield":
         return nearfield_workload(base)
+    if args.workload == "penetrable":
+        return penetrable_workload(base)
     pairs = synth.differentiation()
     bases = [b for b, _ in pairs]
     betas = np.stack([b.betas for b in bases])
@@ -489,6 +491,85 @@ def nearfield_workload(base):
                             "sample": "oracle total field on 2000 of the grid points, extrapolated"}}
 
 
+def penetrable_workload(base):
+    """Penetrable lattice (400 unit disks, k+ = 1, k- = 2, point source at the
+    origin): one step = tables + penetrable tables, GMRES(50) to 1e-8 with the
+    point-source right-hand side, far field at 720 angles, total field on a
+    400 x 400 grid over [-33, 33]^2."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1409_8186_amd import Problem
+    cl = synth.penetrable_example()
+    k_int = 2.0
+    src = [[[0.0, 0.0]]]
+    th = torch.tensor(cl.thetas, device="cuda")
+    g = np.linspace(-33.0, 33.0, 400)
+    pts = torch.tensor(np.stack(np.meshgrid(g, g, indexing="ij"), -1).reshape(-1, 2), device="cuda")
+    info = {}
+
+    def step():
+        P = Problem.from_cluster(cl)
+        P.set_penetrable(k_int)
+        rho, flag, relres, iters, _ = P.gmres(sources=src, restart=50, tol=1e-8, maxit=20000, graph=True)
+        a = P.farfield(rho, th)
+        u = P.nearfield(rho, pts, sources=src)
+        info.update(P=P, rho=rho, flag=flag, relres=relres, iters=iters, a=a, u=u)
+
+    step()
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        step()
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / reps
+    P = info["P"]
+    x = torch.randn(cl.n_tot, dtype=torch.complex128, device="cuda")
+    y = P.empty(1)
+    P.matvec(x, op=1, out=y)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        P.matvec(x, op=1, out=y)
+    e1.record()
+    e1.synchronize()
+    t_app = e0.elapsed_time(e1) / 20 / 1e3
+    flops = algorithmic_flops(cl.n_modes, 1)
+    a = info["a"].cpu().numpy()[0]
+    rcs = 10 * np.log10(2 * np.pi * np.abs(a) ** 2)
+    out = {**base, "metric": "penetrable point-source step time", "value": t, "unit": "s",
+           "higher_is_better": False, "ms_per_step": t * 1e3, "steps": reps,
+           "config": {"workload": "penetrable: 400 unit disks on a 21x21 lattice of spacing 3 minus "
+                                  "the middle row and column, k+=1, k-=2, mu=1, N_p=8, point source "
+                                  "at the origin; GMRES(50) to 1e-8 with graph replay, far field at "
+                                  "720 angles, total field on 400x400 points",
+                      "n_unknowns": cl.n_tot},
+           "iterations": int(info["iters"][0]), "flag": int(info["flag"][0]),
+           "relres": float(info["relres"][0]), "rcs_db_min_max": [float(rcs.min()), float(rcs.max())],
+           "max_abs_total_field": float(info["u"].abs().max()),
+           "apply_us": t_app * 1e6,
+           "roofline": {"bound": "alu", "kernel": "operator apply with the penetrable tables, one RHS: "
+                                                  "k_apply_lane<8, true> + k_apply_finish",
+                        "achieved": flops / t_app / 1e12, "peak": PEAK_FP64_VECTOR_TFLOPS,
+                        "unit": "TFLOP/s", "frac": flops / t_app / 1e12 / PEAK_FP64_VECTOR_TFLOPS,
+                        "traffic": None}}
+    # the oracle's dense 2x2 block solve on a 14 x 14 sub-lattice (196 disks)
+    from oracle import penetrable as opn, pointsource as ops_
+    sub = synth.penetrable_example(half=7)
+    c0 = time.perf_counter()
+    U = ops_.point_source(sub.centers, sub.radii, sub.n_modes, sub.k, [[0.0, 0.0]])
+    dU = ops_.point_source_dn(sub.centers, sub.radii, sub.n_modes, sub.k, [[0.0, 0.0]])
+    opn.solve_coefficients(sub.centers, sub.radii, sub.n_modes, sub.k, np.full(sub.M, k_int), U, dU)
+    t_cpu = time.perf_counter() - c0
+    out["cpu_baseline"] = {"value": t_cpu, "unit": "s per solve", "cores": _blas_threads(), "kind": "oracle",
+                           "sample": f"dense block-system solve of a 196-disk sub-lattice "
+                                     f"({2 * sub.n_tot} unknowns), not the 400-disk step"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -503,7 +584,7 @@ def main():
                     help="profiling mode: build the tables, run REPS operator applies, exit")
     ap.add_argument("--workload", default="one_rhs",
                     choices=["one_rhs", "multi_rhs", "uneven", "differentiation", "dort",
-                             "formulations", "nearfield"],
+                             "formulations", "nearfield", "penetrable"],
                     help="one_rhs (default bench line) or a documentation run of another workload")
     ap.add_argument("--solve", action="store_true",
                     help="with --workload multi_rhs: also time the GMRES(50) solve to 1e-8")

@@ -195,6 +195,21 @@ def dort_example(n_alpha: int = 512) -> Cluster:
     return Cluster(centers, radii, _ceil_rule(k, radii, 3), k, al, al + math.pi, "dort")
 
 
+def penetrable_example(spacing: float = 3.0, half: int = 10) -> Cluster:
+    """Penetrable lattice: unit disks on a (2 half + 1)^2 square lattice of the
+    given spacing centered on the origin, with the row and the column through
+    the origin removed (400 disks for half = 10); k+ = 1 (k- = 2 is the
+    workload's interior wavenumber); N_p = 8; one point source at the origin;
+    720 far-field angles."""
+    g = spacing * np.arange(-half, half + 1)
+    g = g[g != 0.0]
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    centers = np.stack([X.ravel(), Y.ravel()], 1)
+    M = centers.shape[0]
+    return Cluster(centers, np.ones(M), np.full(M, 8, np.int32), 1.0, np.zeros(1),
+                   uniform_angles(720), "penetrable")
+
+
 def small_random(seed: int, M: int, r_lo: float, r_hi: float, box: float, gap: float,
                  k: float, extra: int, R: int = 1, n_theta: int = 64) -> Cluster:
     """Small seeded cluster for tests: N_p = ceil(k a_p) + extra."""

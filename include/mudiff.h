@@ -227,6 +227,7 @@ int mudiff_set_operator(mudiff_t h, const double* op_w, const double* rhs_w, con
  * scaling of its two weights),
  *   [J_m(k- a) (N+ - I/2) - mu k- J'_m(k- a) L+] rho+ = -J_m(k- a) dU + mu k- J'_m(k- a) U,
  * and mudiff_farfield / mudiff_nearfield return the exterior scattered field
+ * (mudiff_interior_field the field inside the disks)
  * a_L rho+ / L+ rho+.  The second row's interior block is -mu (I/2 + N-): the
  * sign that the jump relations give, with which a matched medium (k- = k,
  * mu = 1) scatters nothing; the printed + sign does not.  The interior density
@@ -239,6 +240,26 @@ int mudiff_set_operator(mudiff_t h, const double* op_w, const double* rhs_w, con
  * kernels on `stream` and waits for them. */
 int mudiff_set_penetrable(mudiff_t h, const double* k_int, const double* mu, void* workspace,
                           size_t ws_bytes, void* stream);
+
+/* Interior field of penetrable disks (sec. 7, Example II): at points inside
+ * disk p, u-(x) = sum_m c_m J_m(k-_p r) e^{i m theta}, (r, theta) the polar
+ * coordinates of x - O_p, with c_m = (U + L+ rho+)_m / (sqrt(2 pi a_p) J_m(k-_p a_p))
+ * from the transmission condition u- = u+ + u_inc on the circle (the same field
+ * as L- rho- with rho- from the first block row).  Points outside every disk
+ * are left untouched, so that after mudiff_nearfield with the total field
+ * `out` holds the total field everywhere.
+ *   rho        device complex128 [B][R][N_b] exterior densities (mudiff_gmres
+ *              after mudiff_set_penetrable)
+ *   inc, flags the incidence of rho: [B][R] angles (flags 0) or [B][R][2] point
+ *              sources (MUDIFF_POINT_SOURCE)
+ *   pts, out   device double [n_pts][2]; device complex128 [B][R][n_pts]
+ *   workspace  device, 256-byte aligned, >= mudiff_interior_workspace_size(h, R)
+ * MUDIFF_ERR_INVALID when the handle has no penetrable disks set.  Where
+ * J_m(k- a) = 0 for a kept order (k- an interior Dirichlet eigenvalue) the
+ * field of that disk is not finite. */
+size_t mudiff_interior_workspace_size(mudiff_t h, int R);
+int mudiff_interior_field(mudiff_t h, int R, const void* rho, const double* inc, int flags, int n_pts,
+                          const double* pts, void* out, void* workspace, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------- solver */
 

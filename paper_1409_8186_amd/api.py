@@ -314,6 +314,27 @@ class Problem:
                                                _p(ws), ws.numel(), _stream()))
         self._op_ws = ws
 
+    def interior_field(self, rho: torch.Tensor, points, R: int = 1, betas=None, sources=None,
+                       out=None) -> torch.Tensor:
+        """Field inside penetrable disks (after set_penetrable and a solve for
+        rho+ with these betas [B, R] or sources [B, R, 2]) at points [P, 2],
+        written into out [B*R, P] (a fresh zero tensor if None) at the points
+        inside a disk; other points keep their values."""
+        pts = self._f64(points).reshape(-1, 2).contiguous()
+        if sources is not None:
+            inc, flags = self._f64(sources).reshape(self.B, R, 2).contiguous(), L.POINT_SOURCE
+        else:
+            inc, flags = self._f64(betas).reshape(self.B, R).contiguous(), 0
+        if out is None:
+            out = torch.zeros(self.B * R, pts.shape[0], dtype=torch.complex128, device=self.device)
+        assert out.is_contiguous() and out.numel() == self.B * R * pts.shape[0]
+        n = self.lib.mudiff_interior_workspace_size(self.h, R)
+        ws = torch.empty(int(n), dtype=torch.uint8, device=self.device)
+        L.check(self.lib.mudiff_interior_field(self.h, R, _p(rho.contiguous()), _p(inc), flags,
+                                               pts.shape[0], _p(pts), _p(out), _p(ws), ws.numel(),
+                                               _stream()))
+        return out
+
     # ----------------------------------------------------------- time reversal
     def mirror_farfield(self, n_alpha: int, restart: int = 50, tol: float = 1e-12,
                         maxit: int = 20000, graph: bool = False):

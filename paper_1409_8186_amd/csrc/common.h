@@ -185,6 +185,10 @@ struct mudiff_ctx {
   MfmaSched mfma_sched;                   // current schedule (host copy + upload location)
   bool mfma_tail = false;                 // straggler schedule (few columns still iterating)
   std::vector<int32_t> mfma_tail_cols;    // columns of the straggler schedule
+  // penetrable disks (set by mudiff_set_penetrable, in its workspace): interior
+  // wavenumbers [M_all] and J_n(k- a), n = 0..N_p+1, at dtab offsets
+  const double* pen_k = nullptr;
+  const double* pen_J = nullptr;
 };
 
 // ------------------------------------------------------------------ errors

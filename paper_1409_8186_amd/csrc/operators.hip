@@ -211,6 +211,114 @@ extern "C" int mudiff_set_penetrable(mudiff_t h, const double* k_int, const doub
   v.op_rhs = t[4];
   v.op_rhsp = t[5];
   v.op_ff = t[6];
+  h->pen_k = dk;
+  h->pen_J = Jint;
+  return MUDIFF_OK;
+}
+
+namespace {
+
+// c_i = (U + L rho+)_i / (sqrt(2 pi a) J_|m|(k- a)): the interior field's
+// coefficients from the Dirichlet trace of the exterior total field (written
+// over U).
+__global__ void k_interior_coef(DevView v, int R, const double* __restrict__ Jint,
+                                cplx* __restrict__ U, const cplx* __restrict__ Lr) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (int64_t)R * v.N_all) return;
+  int lo = 0, hi = v.B;  // instance of g: R * imode[b] <= g
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if ((int64_t)R * v.imode[mid] <= g) lo = mid; else hi = mid;
+  }
+  const int b = lo;
+  const int64_t Nb = v.imode[b + 1] - v.imode[b];
+  const int64_t rem = g - (int64_t)R * v.imode[b];
+  const int64_t il = rem - (rem / Nb) * Nb;
+  const int p = v.udisk[v.imode[b] + il];
+  const int m = (int)(il - v.moff[p]) - v.N[p];
+  const double Ja = Jint[v.dtab[p] + (m < 0 ? -m : m)];
+  U[g] = cscale(cadd(U[g], Lr[g]), 1.0 / (sqrt(2.0 * OPS_PI * v.a[p]) * Ja));
+}
+
+// Points inside a disk: u-(x) = sum_m c_m J_|m|(k- r) e^{i m theta} (polar
+// coordinates about the disk's center); other points are left as they are.
+__global__ __launch_bounds__(256) void k_interior_field(DevView v, int R, const double* __restrict__ k_int,
+                                                        const cplx* __restrict__ c, int n_pts,
+                                                        const double* __restrict__ pts,
+                                                        cplx* __restrict__ out) {
+  const int P = blockIdx.x * 256 + threadIdx.x;
+  if (P >= n_pts) return;
+  const int col = blockIdx.y;
+  const int b = col / R, r = col - b * R;
+  const double x1 = pts[2 * P], x2 = pts[2 * P + 1];
+  int64_t pin = -1;
+  for (int64_t p = v.idisk[b]; p < v.idisk[b + 1]; ++p) {
+    const double dx = x1 - v.cx[p], dy = x2 - v.cy[p];
+    if (dx * dx + dy * dy < v.a[p] * v.a[p]) pin = p;
+  }
+  if (pin < 0) return;
+  const int p = (int)pin;
+  const int Np = v.N[p];
+  const double dx = x1 - v.cx[p], dy = x2 - v.cy[p];
+  const double rr = sqrt(dx * dx + dy * dy);
+  const cplx* cp = c + col_base(v.imode, b, R, r) + v.moff[p] + Np;  // mode 0
+  cplx u;
+  if (rr == 0.0) {
+    u = cp[0];  // J_0(0) = 1, J_m(0) = 0
+  } else {
+    double Jr[MUDIFF_MAX_NP + 1], S0, S1;
+    bessel_j_miller(k_int[p] * rr, Np, Jr, 1, &S0, &S1);
+    const cplx e1 = cmk(dx / rr, dy / rr);
+    u = cscale(cp[0], Jr[0]);
+    cplx em = cmk(1.0, 0.0);
+    for (int m = 1; m <= Np; ++m) {
+      em = cmul(em, e1);
+      cmac(u, cscale(cp[m], Jr[m]), em);
+      cmac(u, cscale(cp[-m], Jr[m]), cconj(em));
+    }
+  }
+  out[(int64_t)col * n_pts + P] = u;
+}
+
+}  // namespace
+
+extern "C" size_t mudiff_interior_workspace_size(mudiff_t h, int R) {
+  if (!h || R < 1) return 0;
+  return mudiff_matvec_workspace_size(h, R) + 2 * align256((size_t)R * h->N_all * 16);
+}
+
+extern "C" int mudiff_interior_field(mudiff_t h, int R, const void* rho, const double* inc, int flags,
+                                     int n_pts, const double* pts, void* out, void* workspace,
+                                     size_t ws_bytes, void* stream) {
+  if (!h || !rho || !inc || !pts || !out || !workspace) return fail(MUDIFF_ERR_INVALID, "NULL argument");
+  if (!h->pen_J) return fail(MUDIFF_ERR_INVALID, "no penetrable disks set on this handle");
+  if (R < 1 || n_pts < 1) return fail(MUDIFF_ERR_INVALID, "R < 1 or n_pts < 1");
+  if (flags & ~MUDIFF_POINT_SOURCE) return fail(MUDIFF_ERR_INVALID, "unknown flags");
+  if ((int64_t)h->B * R > 65535) return fail(MUDIFF_ERR_INVALID, "too many instance x RHS columns");
+  const size_t need = mudiff_interior_workspace_size(h, R);
+  if (ws_bytes < need) return fail(MUDIFF_ERR_NOMEM, "interior workspace needs " + std::to_string(need) + " bytes");
+  if (((uintptr_t)workspace) & 255) return fail(MUDIFF_ERR_INVALID, "workspace must be 256-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t mv = mudiff_matvec_workspace_size(h, R);
+  char* w = (char*)workspace;
+  cplx* U = (cplx*)(w + mv);
+  cplx* Lr = (cplx*)(w + mv + align256((size_t)R * h->N_all * 16));
+  // U and L+ rho+ with the single-layer tables: the operator pointers are
+  // cleared for these two launches (kernel arguments are taken at launch)
+  DevView& v = h->dv;
+  const DevView saved = v;
+  v.op_col = v.op_rowA = v.op_row = v.op_diag = v.op_rhs = v.op_rhsp = v.op_ff = nullptr;
+  int rc = launch_fill_zero(w, mv, s);
+  if (rc == MUDIFF_OK) rc = launch_rhs(h, R, inc, U, 0, (flags & MUDIFF_POINT_SOURCE) ? 1 : 0, s);
+  if (rc == MUDIFF_OK) rc = mudiff_matvec(h, R, rho, Lr, MUDIFF_OP_L, w, mv, stream);
+  v = saved;
+  if (rc != MUDIFF_OK) return rc;
+  const int64_t tot = (int64_t)R * h->N_all;
+  hipLaunchKernelGGL(k_interior_coef, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, v, R,
+                     h->pen_J, U, (const cplx*)Lr);
+  hipLaunchKernelGGL(k_interior_field, dim3((unsigned)((n_pts + 255) / 256), (unsigned)(h->B * R)), dim3(256),
+                     0, s, v, R, h->pen_k, (const cplx*)U, n_pts, pts, (cplx*)out);
+  HIP_TRY(hipGetLastError());
   return MUDIFF_OK;
 }
 
@@ -221,6 +329,7 @@ extern "C" int mudiff_set_operator(mudiff_t h, const double* op_w, const double*
   DevView& v = h->dv;
   if (!op_w) {  // back to the built-in single layer
     v.op_col = v.op_rowA = v.op_row = v.op_diag = v.op_rhs = v.op_rhsp = v.op_ff = nullptr;
+    h->pen_k = h->pen_J = nullptr;
     return MUDIFF_OK;
   }
   if (!rhs_w || !ff_w || !workspace) return fail(MUDIFF_ERR_INVALID, "NULL argument");
@@ -271,5 +380,6 @@ extern "C" int mudiff_set_operator(mudiff_t h, const double* op_w, const double*
   v.op_rhs = t[4];
   v.op_rhsp = t[5];
   v.op_ff = t[6];
+  h->pen_k = h->pen_J = nullptr;
   return MUDIFF_OK;
 }

@@ -175,3 +175,53 @@ def test_penetrable_full_size_optical_theorem(P):
     rhs_ = -np.sqrt(8 * np.pi / cl.k) * np.real(np.exp(0.25j * np.pi) * a0)
     say("optical theorem", lhs, rhs_)
     assert abs(lhs - rhs_) < 1e-9 * abs(rhs_)
+
+
+def _inside_points(cl, n, rng):
+    p = rng.integers(0, len(cl.radii), n)
+    rr = cl.radii[p] * np.sqrt(rng.uniform(0, 1, n))
+    t = rng.uniform(0, 2 * np.pi, n)
+    return cl.centers[p] + rr[:, None] * np.stack([np.cos(t), np.sin(t)], 1), p
+
+
+@pytest.mark.parametrize("kind", ["plane", "point"])
+def test_penetrable_interior_field_matches_oracle(P, kind):
+    """Interior field (from the Dirichlet trace U + L+ rho+) against the oracle's
+    L- rho- with rho- from its block solve; points outside the disks keep the
+    near field's total field.  (Continuity across the circles is truncation-
+    limited, 1e-6..5e-4 here; the oracle pins it with its convergence in N.)"""
+    from oracle import pointsource as ps
+    cl = synth.small_random(96, 5, 0.3, 0.8, 6.0, 0.3, 3.2, 6)
+    ki, mu = _media(5, cl.k, 4)
+    rng = np.random.default_rng(11)
+    pin, which = _inside_points(cl, 300, rng)
+    g = np.linspace(-1.0, 7.0, 20)
+    pout = np.stack(np.meshgrid(g, g, indexing="ij"), -1).reshape(-1, 2)
+    pts = np.concatenate([pin, pout])
+    pr = P.from_cluster(cl)
+    pr.set_penetrable(ki, mu)
+    if kind == "plane":
+        inc = dict(betas=[[0.6, 2.5]])
+        rp, rm = pen.solve(cl.centers, cl.radii, cl.n_modes, cl.k, ki, [0.6, 2.5], mu=mu)
+    else:
+        src = np.array([[-1.5, 2.0], [8.0, 1.0]])
+        inc = dict(sources=[src])
+        U = ps.point_source(cl.centers, cl.radii, cl.n_modes, cl.k, src)
+        dU = ps.point_source_dn(cl.centers, cl.radii, cl.n_modes, cl.k, src)
+        rp, rm = pen.solve_coefficients(cl.centers, cl.radii, cl.n_modes, cl.k, ki, U, dU, mu)
+    rho, flag, _, _, _ = pr.gmres(restart=30, tol=1e-13, maxit=2000, **inc)
+    assert np.all(flag.cpu().numpy() == 0)
+    tot = pr.nearfield(rho, pts, R=2, **inc)
+    ext = tot.clone()
+    u = pr.interior_field(rho, pts, R=2, out=tot, **inc).cpu().numpy()
+    n_in = len(pin)
+    ref = np.stack([np.concatenate([pen.interior_field(cl.centers, cl.radii, cl.n_modes, ki, rm[r], p, x[None, :])
+                                    for x, p in zip(pin, which)]) for r in range(2)])
+    say(kind, "interior rel", rel(u[:, :n_in], ref))
+    assert rel(u[:, :n_in], ref) < 1e-10
+    outside = np.ones(len(pts), bool)
+    for c, a in zip(cl.centers, cl.radii):
+        outside &= np.hypot(*(pts - c).T) >= a
+    assert outside[n_in:].sum() > 300
+    keep = torch.tensor(outside, device="cuda")
+    assert torch.equal(tot[:, keep], ext[:, keep])

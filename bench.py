@@ -706,7 +706,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
                      "traffic": traffic,
-                     "kernel": "operator apply, one RHS: k_apply_lane<12> + k_apply_finish",
+                     "kernel": "operator apply, one RHS: k_apply_lane<12, false> + k_apply_finish",
                      "source_sha256_16": apply_source_sha(),
                      "algorithmic_flops_per_launch": flops,
                      "algorithmic_bytes_per_launch": algorithmic_bytes(cl.n_modes)},

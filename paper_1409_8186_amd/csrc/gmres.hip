@@ -155,20 +155,21 @@ __device__ void arnoldi_step(const GState& s, int c, int j, const cplx* hl, cons
 //   [j, 2j)  V_i^H w        (projection of w = A u)
 //   2j       u^H u,   2j+1  u^H w
 
-// Dots of the chunk's rows of ul and wl against V_0..V_{j-1}: part[i] = V_i^H u,
+// Dots of the chunk's rows of ul and wl against V_ib..V_{ie-1}: part[i] = V_i^H u,
 // part[j + i] = V_i^H w (when has_w).  One wave per vector, GS_BATCH vectors
 // in flight, both products from one read of V_i.
-__device__ __forceinline__ void chunk_dots2(const GState& s, int j, int64_t o, int len, const cplx* ul,
-                            const cplx* wl, bool has_w, cplx* __restrict__ part) {
+__device__ __forceinline__ void chunk_dots2(const GState& s, int j, int ib, int ie, int64_t o, int len,
+                                            const cplx* ul, const cplx* wl, bool has_w,
+                                            cplx* __restrict__ part) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int i0 = wv; i0 < j; i0 += GS_WAVES * GS_BATCH) {
+  for (int i0 = ib + wv; i0 < ie; i0 += GS_WAVES * GS_BATCH) {
     cplx au[GS_BATCH], aw[GS_BATCH];
     const cplx* vi[GS_BATCH];
 #pragma unroll
     for (int u = 0; u < GS_BATCH; ++u) {
       au[u] = cmk(0.0, 0.0);
       aw[u] = cmk(0.0, 0.0);
-      const int i = min(i0 + u * GS_WAVES, j - 1);  // past j-1: a valid row, result unused
+      const int i = min(i0 + u * GS_WAVES, ie - 1);  // past ie-1: a valid row, result unused
       vi[u] = s.V + (int64_t)i * s.NT + o;
     }
 #pragma unroll 4
@@ -195,7 +196,7 @@ __device__ __forceinline__ void chunk_dots2(const GState& s, int j, int64_t o, i
     if ((lane & 3) == 0) {
       const int vi = lane >> 2, u = vi >> 2, comp = vi & 3;
       const int i = i0 + u * GS_WAVES;
-      if (i < j && (comp < 2 || has_w)) {
+      if (i < ie && (comp < 2 || has_w)) {
         double* dst = reinterpret_cast<double*>(part + (comp < 2 ? i : j + i));
         dst[comp & 1] = val[0];
       }
@@ -286,65 +287,6 @@ __device__ double column_sums(const cplx* __restrict__ pbase, int sl, int nck, i
   return block_sum(sq, sred);  // (its barrier also publishes out[])
 }
 
-// The RPT rows tid + k * GS_THREADS (k < RPT) of a chunk of len <= RPT *
-// GS_THREADS rows: a[k] = u[r_k] - sum_{i < j} sc_i V_i[r_k] and
-// b[k] = w[r_k] - sum_{i < j} zc_i V_i[r_k], from one read of each V_i[r_k];
-// 16 / RPT basis vectors per round, so that 16 loads are in flight per thread.
-template <int RPT>
-__device__ __forceinline__ void project_rows2(const GState& s, int j, const cplx* __restrict__ uc,
-                                              const cplx* __restrict__ wc,
-                                              const cplx* __restrict__ vc, int len,
-                                              const cplx* sc, const cplx* zc, cplx (&a)[RPT],
-                                              cplx (&b)[RPT]) {
-  constexpr int U = 16 / RPT;
-  int r[RPT];
-  bool ok[RPT];
-#pragma unroll
-  for (int k = 0; k < RPT; ++k) {
-    r[k] = threadIdx.x + k * GS_THREADS;
-    ok[k] = r[k] < len;
-    a[k] = ok[k] ? uc[r[k]] : cmk(0.0, 0.0);
-    b[k] = ok[k] ? wc[r[k]] : cmk(0.0, 0.0);
-  }
-  int i = 0;
-  for (; i + U <= j; i += U) {
-    cplx t[U][RPT];
-#pragma unroll
-    for (int q = 0; q < U; ++q)
-#pragma unroll
-      for (int k = 0; k < RPT; ++k)
-        t[q][k] = ok[k] ? vc[(int64_t)(i + q) * s.NT + r[k]] : cmk(0.0, 0.0);
-#pragma unroll
-    for (int q = 0; q < U; ++q) {
-      const cplx sq = sc[i + q], zq = zc[i + q];
-#pragma unroll
-      for (int k = 0; k < RPT; ++k) {
-        a[k] = csub(a[k], cmul(sq, t[q][k]));
-        b[k] = csub(b[k], cmul(zq, t[q][k]));
-      }
-    }
-  }
-  if (i < j) {  // last, partial batch: rows past j-1 are loaded but not used
-    cplx t[U][RPT];
-#pragma unroll
-    for (int q = 0; q < U; ++q) {
-      const int iq = min(i + q, j - 1);
-#pragma unroll
-      for (int k = 0; k < RPT; ++k) t[q][k] = ok[k] ? vc[(int64_t)iq * s.NT + r[k]] : cmk(0.0, 0.0);
-    }
-#pragma unroll
-    for (int q = 0; q < U; ++q) {
-      if (i + q >= j) break;
-      const cplx sq = sc[i + q], zq = zc[i + q];
-#pragma unroll
-      for (int k = 0; k < RPT; ++k) {
-        a[k] = csub(a[k], cmul(sq, t[q][k]));
-        b[k] = csub(b[k], cmul(zq, t[q][k]));
-      }
-    }
-  }
-}
-
 // The rotations 0..col-1 of column c into LDS: rot[0, col) = sn,
 // (double*)(rot + col)[0, col) = cs.
 __device__ void stage_rotations(const GState& s, int c, int col, cplx* rot) {
@@ -367,9 +309,11 @@ struct PendingApply {
 };
 
 // Step j, pass 1: the chunk's partial sums of V_i^H u, V_i^H w (i < j), u^H u
-// and u^H w, u = V[j] the candidate, w = V[j+1] = A u.  With FIN, w is first
-// formed from the apply's chunk partial sums and stored.  Without has_w (the
-// end of a cycle) only V_i^H u and u^H u.
+// and u^H w, u = V[j] the candidate, w = V[j+1] = A u.  grid.y splits the
+// basis into groups of GS_WAVES * GS_BATCH vectors, one workgroup each (every
+// group forms u, w; group 0 writes the u^H u, u^H w slots).  With FIN, w is
+// first formed from the apply's chunk partial sums and stored (by group 0).
+// Without has_w (the end of a cycle) only V_i^H u and u^H u.
 template <bool FIN>
 __global__ __launch_bounds__(GS_THREADS) void k_dg_dots(GState s, int j, PendingApply pa,
                                                         int has_w) {
@@ -402,7 +346,7 @@ __global__ __launch_bounds__(GS_THREADS) void k_dg_dots(GState s, int j, Pending
       if (FIN) {
         wv = finalize(pa.v, MUDIFF_OP_A, i0 + rr, uv,
                       lane_chunk_sum(pa.v, pr, pa.nchunk, pa.partoff, b, i0 + rr));
-        w[rr] = wv;
+        if (blockIdx.y == 0) w[rr] = wv;
       } else {
         wv = w[rr];
       }
@@ -415,8 +359,9 @@ __global__ __launch_bounds__(GS_THREADS) void k_dg_dots(GState s, int j, Pending
   uu = red3[0];
   uw = cmk(red3[1], red3[2]);
   cplx* part = s.P1 + (int64_t)gi * s.sl;
-  chunk_dots2(s, j, o, len, ul, wl, has_w != 0, part);
-  if (threadIdx.x == 0) {
+  const int ib = (int)blockIdx.y * GS_WAVES * GS_BATCH;
+  chunk_dots2(s, j, ib, min(j, ib + GS_WAVES * GS_BATCH), o, len, ul, wl, has_w != 0, part);
+  if (threadIdx.x == 0 && blockIdx.y == 0) {
     part[2 * j] = cmk(uu, 0.0);
     part[2 * j + 1] = uw;
   }
@@ -429,23 +374,31 @@ __global__ __launch_bounds__(GS_THREADS) void k_dg_dots(GState s, int j, Pending
 //   V[j]   = q_j    = (u - V s) / rho                       (final)
 //   V[j+1] = u_next = (w - V z - g_j q_j) / rho,  g_j = (u^H w - s^H z) / rho,
 // the candidate of the next step (u_next = A q_j - [V q_j] h_j, the once
-// orthogonalised vector).  Chunk 0 finalises Hessenberg column j-1 (its
-// tentative entries plus s, subdiagonal rho), takes the Givens step, and forms
-// the tentative column j, h_j = ([z; g_j] - H s) / rho, H the unrotated
-// Hessenberg columns 0..j-1.
-template <int RPT>
+// orthogonalised vector).  A workgroup takes 64 rows of a chunk (grid.y runs
+// over the chunk's 64-row blocks): wave g sums the basis vectors g, g + 4, ...
+// of each row (the first round of them loaded before the column sums), and
+// the four wave sums are added through LDS.  Block 0 of chunk 0 finalises
+// Hessenberg column j-1 (its tentative entries plus s, subdiagonal rho), takes
+// the Givens step, and forms the tentative column j, h_j = ([z; g_j] - H s) / rho,
+// H the unrotated Hessenberg columns 0..j-1.
+// basis vectors per wave and round of the row sweep of k_dg_update
+constexpr int UB = 16;
+
 __global__ __launch_bounds__(GS_THREADS) void k_dg_update(GState s, int j) {
   __shared__ cplx cl[2 * MUDIFF_MAX_RESTART + 2];
   __shared__ cplx aux[MUDIFF_MAX_RESTART + MUDIFF_MAX_RESTART + MUDIFF_MAX_RESTART / 2];
   __shared__ cplx tmp[GS_WAVES * 64];
+  __shared__ cplx pab[2][GS_WAVES][64];
   __shared__ double sred[2 * GS_WAVES];
   int c, len;
   int64_t o;
   const int gi = decode_chunk(s, &c, &len, &o);
   if (!s.inner[c]) return;
+  const int rb = (int)blockIdx.y * 64;  // this workgroup's rows of the chunk
+  if (rb >= len) return;
   const int m1 = s.m + 1;
   const int nck = s.ckc[c];
-  const bool first_chunk = gi == s.ckf[c];
+  const bool first_chunk = gi == s.ckf[c] && blockIdx.y == 0;
   cplx* hcol = aux;                          // column j-1 of the Hessenberg matrix
   cplx* rot = aux + MUDIFF_MAX_RESTART;      // rotations 0..j-2
   ArnoldiPre pre{};
@@ -453,6 +406,24 @@ __global__ __launch_bounds__(GS_THREADS) void k_dg_update(GState s, int j) {
     stage_rotations(s, c, j - 1, rot);
     if (threadIdx.x == 0) pre = arnoldi_preload(s, c, j - 1);
     for (int i = threadIdx.x; i < j; i += GS_THREADS) hcol[i] = s.htent[(int64_t)c * m1 + i];
+  }
+  const int lane = threadIdx.x & 63, wq = threadIdx.x >> 6;
+  const int r = rb + lane;
+  const bool ok = r < len;
+  cplx* u = s.V + (int64_t)j * s.NT + o;
+  cplx* w = s.V + (int64_t)(j + 1) * s.NT + o;
+  cplx ur = cmk(0.0, 0.0), wr = cmk(0.0, 0.0);
+  if (wq == 0 && ok) {
+    ur = u[r];
+    wr = w[r];
+  }
+  // the first round of basis rows, loaded before the column sums
+  const cplx* vb = s.V + o + r;
+  cplx t0[UB];
+#pragma unroll
+  for (int q = 0; q < UB; ++q) {
+    const int i = min(wq + q * GS_WAVES, j - 1);
+    t0[q] = (ok && j > 0) ? vb[(int64_t)i * s.NT] : cmk(0.0, 0.0);
   }
   const double ssq = column_sums(s.P1 + (int64_t)s.ckf[c] * s.sl, s.sl, nck, 2 * j + 2, -1, j, cl,
                                  tmp, sred);
@@ -469,18 +440,45 @@ __global__ __launch_bounds__(GS_THREADS) void k_dg_update(GState s, int j) {
     sz = cmk(r2[0], r2[1]);
   }
   const cplx gj = cscale(csub(beta, sz), inv);
-  cplx* u = s.V + (int64_t)j * s.NT + o;
-  cplx* w = s.V + (int64_t)(j + 1) * s.NT + o;
-  cplx a[RPT], bb[RPT];
-  project_rows2<RPT>(s, j, u, w, s.V + o, len, cl, cl + j, a, bb);
+  // wave wq: basis vectors wq, wq + GS_WAVES, ... of row r
+  cplx pa = cmk(0.0, 0.0), pb = cmk(0.0, 0.0);
 #pragma unroll
-  for (int k = 0; k < RPT; ++k) {
-    const int r = threadIdx.x + k * GS_THREADS;
-    if (r < len) {
-      const cplx q = cscale(a[k], inv);
-      u[r] = q;
-      w[r] = cscale(csub(bb[k], cmul(gj, q)), inv);
+  for (int q = 0; q < UB; ++q) {
+    const int i = wq + q * GS_WAVES;
+    if (i < j) {
+      pa = csub(pa, cmul(cl[i], t0[q]));
+      pb = csub(pb, cmul(cl[j + i], t0[q]));
     }
+  }
+  for (int i0 = wq + UB * GS_WAVES; i0 < j; i0 += UB * GS_WAVES) {
+    cplx t[UB];
+#pragma unroll
+    for (int q = 0; q < UB; ++q) {
+      const int i = min(i0 + q * GS_WAVES, j - 1);
+      t[q] = ok ? vb[(int64_t)i * s.NT] : cmk(0.0, 0.0);
+    }
+#pragma unroll
+    for (int q = 0; q < UB; ++q) {
+      const int i = i0 + q * GS_WAVES;
+      if (i < j) {
+        pa = csub(pa, cmul(cl[i], t[q]));
+        pb = csub(pb, cmul(cl[j + i], t[q]));
+      }
+    }
+  }
+  pab[0][wq][lane] = pa;
+  pab[1][wq][lane] = pb;
+  __syncthreads();
+  if (wq == 0 && ok) {
+    cplx a = ur, bb = wr;
+#pragma unroll
+    for (int q = 0; q < GS_WAVES; ++q) {
+      a = cadd(a, pab[0][q][lane]);
+      bb = cadd(bb, pab[1][q][lane]);
+    }
+    const cplx qv = cscale(a, inv);
+    u[r] = qv;
+    w[r] = cscale(csub(bb, cmul(gj, qv)), inv);
   }
   if (!first_chunk) return;
   cplx* Hr = s.Hraw + (int64_t)c * m1 * s.m;  // unrotated columns, [k][m+1]
@@ -502,7 +500,7 @@ __global__ __launch_bounds__(GS_THREADS) void k_dg_update(GState s, int j) {
   const int w0 = j >= 1 ? 1 : 0;
   const int wv = (int)threadIdx.x >> 6;
   if (wv < w0) return;
-  const int lane = threadIdx.x & 63, kl = lane & 3;
+  const int kl = lane & 3;
   const int per_pass = (GS_WAVES - w0) * 16;
   for (int i0 = 0; i0 <= j; i0 += per_pass) {
     const int i = i0 + (wv - w0) * 16 + (lane >> 2);
@@ -878,7 +876,7 @@ struct GmresRun {
   std::vector<int64_t> ck;      // host copy of the chunk table
   std::vector<int32_t> ckmap;   // chunks of the running columns (straggler phase)
   int n_compact = 0;            // running columns when the list was built (0: all chunks)
-  int rpt = 1;                  // chunk rows per Gram-Schmidt thread (1, 2 or 4)
+  int64_t ch = 256;             // rows per Gram-Schmidt chunk
 };
 
 // Straggler phase (few running columns): the Gram-Schmidt kernels run over
@@ -920,15 +918,12 @@ static int enqueue_cycle(GmresRun& G, int check_every, bool host_checks) {
     PendingApply pa{G.h->dv, G.apply_part, G.h->plan.part_total, G.h->plan.d_nchunk,
                     G.h->plan.d_partoff};
     if (nb > 0) {
+      const unsigned vg = (unsigned)std::max(1, (j + GS_WAVES * GS_BATCH - 1) / (GS_WAVES * GS_BATCH));
       if (pending)
-        hipLaunchKernelGGL(k_dg_dots<true>, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, j, pa, 1);
+        hipLaunchKernelGGL(k_dg_dots<true>, dim3(nb, vg), dim3(GS_THREADS), 0, G.st, sg, j, pa, 1);
       else
-        hipLaunchKernelGGL(k_dg_dots<false>, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, j, pa, 1);
-      switch (G.rpt) {  // chunk rows per thread
-        case 1: hipLaunchKernelGGL(k_dg_update<1>, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, j); break;
-        case 2: hipLaunchKernelGGL(k_dg_update<2>, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, j); break;
-        default: hipLaunchKernelGGL(k_dg_update<4>, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, j); break;
-      }
+        hipLaunchKernelGGL(k_dg_dots<false>, dim3(nb, vg), dim3(GS_THREADS), 0, G.st, sg, j, pa, 1);
+      hipLaunchKernelGGL(k_dg_update, dim3(nb, (unsigned)(G.ch / 64)), dim3(GS_THREADS), 0, G.st, sg, j);
     }
     HIP_TRY(hipGetLastError());
     if (host_checks && check_every > 0 && (j + 1) % check_every == 0 && j + 1 < s.m) {
@@ -947,7 +942,8 @@ static int enqueue_cycle(GmresRun& G, int check_every, bool host_checks) {
     }
     PendingApply pa{};
     if (nb > 0)
-      hipLaunchKernelGGL(k_dg_dots<false>, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, s.m, pa, 0);
+      hipLaunchKernelGGL(k_dg_dots<false>, dim3(nb, (unsigned)((s.m + GS_WAVES * GS_BATCH - 1) / (GS_WAVES * GS_BATCH))),
+                         dim3(GS_THREADS), 0, G.st, sg, s.m, pa, 0);
     hipLaunchKernelGGL(k_dg_flush, dim3(s.C), dim3(GS_THREADS), 0, G.st, s);
     HIP_TRY(hipGetLastError());
   }
@@ -1037,7 +1033,7 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
   ck.reserve(2 * L.n_chunks);
   int64_t idx = 0;
   const int64_t ch = chunk_rows(L.NT, max_col_rows(h));
-  G.rpt = ch <= GS_THREADS ? 1 : (ch <= 2 * GS_THREADS ? 2 : 4);
+  G.ch = ch;
   for (int b = 0; b < h->B; ++b) {
     const int64_t Nb = h->imode[b + 1] - h->imode[b];
     for (int r = 0; r < R; ++r) {

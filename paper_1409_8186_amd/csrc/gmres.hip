@@ -30,6 +30,9 @@
 #define GS_THREADS 256
 #define GS_WAVES (GS_THREADS / 64)
 #define GS_BATCH 4
+// Gram-Schmidt launches with at most this many chunks split the basis (dots)
+// and the rows (update) over more workgroups
+#define GS_SPREAD_CHUNKS 64
 
 enum { ST_RUN = 0, ST_CONV = 1, ST_BREAK = 2, ST_MAXIT = 3 };
 
@@ -287,6 +290,65 @@ __device__ double column_sums(const cplx* __restrict__ pbase, int sl, int nck, i
   return block_sum(sq, sred);  // (its barrier also publishes out[])
 }
 
+// The RPT rows tid + k * GS_THREADS (k < RPT) of a chunk of len <= RPT *
+// GS_THREADS rows: a[k] = u[r_k] - sum_{i < j} sc_i V_i[r_k] and
+// b[k] = w[r_k] - sum_{i < j} zc_i V_i[r_k], from one read of each V_i[r_k];
+// 16 / RPT basis vectors per round, so that 16 loads are in flight per thread.
+template <int RPT>
+__device__ __forceinline__ void project_rows2(const GState& s, int j, const cplx* __restrict__ uc,
+                                              const cplx* __restrict__ wc,
+                                              const cplx* __restrict__ vc, int len,
+                                              const cplx* sc, const cplx* zc, cplx (&a)[RPT],
+                                              cplx (&b)[RPT]) {
+  constexpr int U = 16 / RPT;
+  int r[RPT];
+  bool ok[RPT];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    r[k] = threadIdx.x + k * GS_THREADS;
+    ok[k] = r[k] < len;
+    a[k] = ok[k] ? uc[r[k]] : cmk(0.0, 0.0);
+    b[k] = ok[k] ? wc[r[k]] : cmk(0.0, 0.0);
+  }
+  int i = 0;
+  for (; i + U <= j; i += U) {
+    cplx t[U][RPT];
+#pragma unroll
+    for (int q = 0; q < U; ++q)
+#pragma unroll
+      for (int k = 0; k < RPT; ++k)
+        t[q][k] = ok[k] ? vc[(int64_t)(i + q) * s.NT + r[k]] : cmk(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const cplx sq = sc[i + q], zq = zc[i + q];
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        a[k] = csub(a[k], cmul(sq, t[q][k]));
+        b[k] = csub(b[k], cmul(zq, t[q][k]));
+      }
+    }
+  }
+  if (i < j) {  // last, partial batch: rows past j-1 are loaded but not used
+    cplx t[U][RPT];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int iq = min(i + q, j - 1);
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) t[q][k] = ok[k] ? vc[(int64_t)iq * s.NT + r[k]] : cmk(0.0, 0.0);
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      if (i + q >= j) break;
+      const cplx sq = sc[i + q], zq = zc[i + q];
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        a[k] = csub(a[k], cmul(sq, t[q][k]));
+        b[k] = csub(b[k], cmul(zq, t[q][k]));
+      }
+    }
+  }
+}
+
 // The rotations 0..col-1 of column c into LDS: rot[0, col) = sn,
 // (double*)(rot + col)[0, col) = cs.
 __device__ void stage_rotations(const GState& s, int c, int col, cplx* rot) {
@@ -311,7 +373,7 @@ struct PendingApply {
 // Step j, pass 1: the chunk's partial sums of V_i^H u, V_i^H w (i < j), u^H u
 // and u^H w, u = V[j] the candidate, w = V[j+1] = A u.  grid.y splits the
 // basis into groups of GS_WAVES * GS_BATCH vectors, one workgroup each (every
-// group forms u, w; group 0 writes the u^H u, u^H w slots).  With FIN, w is
+// group forms u, w; group 0 writes the u^H u, u^H w slots), or is 1: all j.  With FIN, w is
 // first formed from the apply's chunk partial sums and stored (by group 0).
 // Without has_w (the end of a cycle) only V_i^H u and u^H u.
 template <bool FIN>
@@ -359,8 +421,10 @@ __global__ __launch_bounds__(GS_THREADS) void k_dg_dots(GState s, int j, Pending
   uu = red3[0];
   uw = cmk(red3[1], red3[2]);
   cplx* part = s.P1 + (int64_t)gi * s.sl;
-  const int ib = (int)blockIdx.y * GS_WAVES * GS_BATCH;
-  chunk_dots2(s, j, ib, min(j, ib + GS_WAVES * GS_BATCH), o, len, ul, wl, has_w != 0, part);
+  // basis vectors [ib, ib + per) of this workgroup: all of them when grid.y is 1
+  const int per = gridDim.y == 1 ? j : GS_WAVES * GS_BATCH;
+  const int ib = (int)blockIdx.y * per;
+  chunk_dots2(s, j, ib, min(j, ib + per), o, len, ul, wl, has_w != 0, part);
   if (threadIdx.x == 0 && blockIdx.y == 0) {
     part[2 * j] = cmk(uu, 0.0);
     part[2 * j + 1] = uw;
@@ -374,16 +438,19 @@ __global__ __launch_bounds__(GS_THREADS) void k_dg_dots(GState s, int j, Pending
 //   V[j]   = q_j    = (u - V s) / rho                       (final)
 //   V[j+1] = u_next = (w - V z - g_j q_j) / rho,  g_j = (u^H w - s^H z) / rho,
 // the candidate of the next step (u_next = A q_j - [V q_j] h_j, the once
-// orthogonalised vector).  A workgroup takes 64 rows of a chunk (grid.y runs
-// over the chunk's 64-row blocks): wave g sums the basis vectors g, g + 4, ...
-// of each row (the first round of them loaded before the column sums), and
-// the four wave sums are added through LDS.  Block 0 of chunk 0 finalises
+// orthogonalised vector).  RPT = 0 (few chunks, latency-bound): a workgroup
+// takes 64 rows of a chunk (grid.y runs over the chunk's 64-row blocks), wave
+// g sums the basis vectors g, g + 4, ... of each row (the first round of them
+// loaded before the column sums) and the four wave sums are added through LDS.
+// RPT = 1, 2, 4 (many chunks, bandwidth-bound): one workgroup per chunk, RPT
+// rows per thread, each reading the whole basis.  Block 0 of chunk 0 finalises
 // Hessenberg column j-1 (its tentative entries plus s, subdiagonal rho), takes
 // the Givens step, and forms the tentative column j, h_j = ([z; g_j] - H s) / rho,
 // H the unrotated Hessenberg columns 0..j-1.
 // basis vectors per wave and round of the row sweep of k_dg_update
 constexpr int UB = 16;
 
+template <int RPT>
 __global__ __launch_bounds__(GS_THREADS) void k_dg_update(GState s, int j) {
   __shared__ cplx cl[2 * MUDIFF_MAX_RESTART + 2];
   __shared__ cplx aux[MUDIFF_MAX_RESTART + MUDIFF_MAX_RESTART + MUDIFF_MAX_RESTART / 2];
@@ -394,7 +461,7 @@ __global__ __launch_bounds__(GS_THREADS) void k_dg_update(GState s, int j) {
   int64_t o;
   const int gi = decode_chunk(s, &c, &len, &o);
   if (!s.inner[c]) return;
-  const int rb = (int)blockIdx.y * 64;  // this workgroup's rows of the chunk
+  const int rb = RPT == 0 ? (int)blockIdx.y * 64 : 0;  // this workgroup's rows of the chunk
   if (rb >= len) return;
   const int m1 = s.m + 1;
   const int nck = s.ckc[c];
@@ -413,17 +480,19 @@ __global__ __launch_bounds__(GS_THREADS) void k_dg_update(GState s, int j) {
   cplx* u = s.V + (int64_t)j * s.NT + o;
   cplx* w = s.V + (int64_t)(j + 1) * s.NT + o;
   cplx ur = cmk(0.0, 0.0), wr = cmk(0.0, 0.0);
-  if (wq == 0 && ok) {
-    ur = u[r];
-    wr = w[r];
-  }
-  // the first round of basis rows, loaded before the column sums
   const cplx* vb = s.V + o + r;
   cplx t0[UB];
+  if constexpr (RPT == 0) {
+    if (wq == 0 && ok) {
+      ur = u[r];
+      wr = w[r];
+    }
+    // the first round of basis rows, loaded before the column sums
 #pragma unroll
-  for (int q = 0; q < UB; ++q) {
-    const int i = min(wq + q * GS_WAVES, j - 1);
-    t0[q] = (ok && j > 0) ? vb[(int64_t)i * s.NT] : cmk(0.0, 0.0);
+    for (int q = 0; q < UB; ++q) {
+      const int i = min(wq + q * GS_WAVES, j - 1);
+      t0[q] = (ok && j > 0) ? vb[(int64_t)i * s.NT] : cmk(0.0, 0.0);
+    }
   }
   const double ssq = column_sums(s.P1 + (int64_t)s.ckf[c] * s.sl, s.sl, nck, 2 * j + 2, -1, j, cl,
                                  tmp, sred);
@@ -440,45 +509,59 @@ __global__ __launch_bounds__(GS_THREADS) void k_dg_update(GState s, int j) {
     sz = cmk(r2[0], r2[1]);
   }
   const cplx gj = cscale(csub(beta, sz), inv);
-  // wave wq: basis vectors wq, wq + GS_WAVES, ... of row r
-  cplx pa = cmk(0.0, 0.0), pb = cmk(0.0, 0.0);
-#pragma unroll
-  for (int q = 0; q < UB; ++q) {
-    const int i = wq + q * GS_WAVES;
-    if (i < j) {
-      pa = csub(pa, cmul(cl[i], t0[q]));
-      pb = csub(pb, cmul(cl[j + i], t0[q]));
-    }
-  }
-  for (int i0 = wq + UB * GS_WAVES; i0 < j; i0 += UB * GS_WAVES) {
-    cplx t[UB];
-#pragma unroll
+  if constexpr (RPT == 0) {
+    // wave wq: basis vectors wq, wq + GS_WAVES, ... of row r
+    cplx pa = cmk(0.0, 0.0), pb = cmk(0.0, 0.0);
+  #pragma unroll
     for (int q = 0; q < UB; ++q) {
-      const int i = min(i0 + q * GS_WAVES, j - 1);
-      t[q] = ok ? vb[(int64_t)i * s.NT] : cmk(0.0, 0.0);
-    }
-#pragma unroll
-    for (int q = 0; q < UB; ++q) {
-      const int i = i0 + q * GS_WAVES;
+      const int i = wq + q * GS_WAVES;
       if (i < j) {
-        pa = csub(pa, cmul(cl[i], t[q]));
-        pb = csub(pb, cmul(cl[j + i], t[q]));
+        pa = csub(pa, cmul(cl[i], t0[q]));
+        pb = csub(pb, cmul(cl[j + i], t0[q]));
       }
     }
-  }
-  pab[0][wq][lane] = pa;
-  pab[1][wq][lane] = pb;
-  __syncthreads();
-  if (wq == 0 && ok) {
-    cplx a = ur, bb = wr;
-#pragma unroll
-    for (int q = 0; q < GS_WAVES; ++q) {
-      a = cadd(a, pab[0][q][lane]);
-      bb = cadd(bb, pab[1][q][lane]);
+    for (int i0 = wq + UB * GS_WAVES; i0 < j; i0 += UB * GS_WAVES) {
+      cplx t[UB];
+  #pragma unroll
+      for (int q = 0; q < UB; ++q) {
+        const int i = min(i0 + q * GS_WAVES, j - 1);
+        t[q] = ok ? vb[(int64_t)i * s.NT] : cmk(0.0, 0.0);
+      }
+  #pragma unroll
+      for (int q = 0; q < UB; ++q) {
+        const int i = i0 + q * GS_WAVES;
+        if (i < j) {
+          pa = csub(pa, cmul(cl[i], t[q]));
+          pb = csub(pb, cmul(cl[j + i], t[q]));
+        }
+      }
     }
-    const cplx qv = cscale(a, inv);
-    u[r] = qv;
-    w[r] = cscale(csub(bb, cmul(gj, qv)), inv);
+    pab[0][wq][lane] = pa;
+    pab[1][wq][lane] = pb;
+    __syncthreads();
+    if (wq == 0 && ok) {
+      cplx a = ur, bb = wr;
+  #pragma unroll
+      for (int q = 0; q < GS_WAVES; ++q) {
+        a = cadd(a, pab[0][q][lane]);
+        bb = cadd(bb, pab[1][q][lane]);
+      }
+      const cplx qv = cscale(a, inv);
+      u[r] = qv;
+      w[r] = cscale(csub(bb, cmul(gj, qv)), inv);
+    }
+  } else {
+    cplx a[RPT], bb[RPT];
+    project_rows2<RPT>(s, j, u, w, s.V + o, len, cl, cl + j, a, bb);
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int rr = threadIdx.x + k * GS_THREADS;
+      if (rr < len) {
+        const cplx qv = cscale(a[k], inv);
+        u[rr] = qv;
+        w[rr] = cscale(csub(bb[k], cmul(gj, qv)), inv);
+      }
+    }
   }
   if (!first_chunk) return;
   cplx* Hr = s.Hraw + (int64_t)c * m1 * s.m;  // unrotated columns, [k][m+1]
@@ -918,12 +1001,22 @@ static int enqueue_cycle(GmresRun& G, int check_every, bool host_checks) {
     PendingApply pa{G.h->dv, G.apply_part, G.h->plan.part_total, G.h->plan.d_nchunk,
                     G.h->plan.d_partoff};
     if (nb > 0) {
-      const unsigned vg = (unsigned)std::max(1, (j + GS_WAVES * GS_BATCH - 1) / (GS_WAVES * GS_BATCH));
+      // few chunks (latency-bound): the basis split over workgroups; many
+      // chunks (bandwidth-bound): one workgroup per chunk
+      const bool spread = nb <= GS_SPREAD_CHUNKS;
+      const unsigned vg = spread ? (unsigned)std::max(1, (j + GS_WAVES * GS_BATCH - 1) / (GS_WAVES * GS_BATCH)) : 1u;
       if (pending)
         hipLaunchKernelGGL(k_dg_dots<true>, dim3(nb, vg), dim3(GS_THREADS), 0, G.st, sg, j, pa, 1);
       else
         hipLaunchKernelGGL(k_dg_dots<false>, dim3(nb, vg), dim3(GS_THREADS), 0, G.st, sg, j, pa, 1);
-      hipLaunchKernelGGL(k_dg_update, dim3(nb, (unsigned)(G.ch / 64)), dim3(GS_THREADS), 0, G.st, sg, j);
+      if (spread)
+        hipLaunchKernelGGL(k_dg_update<0>, dim3(nb, (unsigned)(G.ch / 64)), dim3(GS_THREADS), 0, G.st, sg, j);
+      else if (G.ch <= GS_THREADS)
+        hipLaunchKernelGGL(k_dg_update<1>, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, j);
+      else if (G.ch <= 2 * GS_THREADS)
+        hipLaunchKernelGGL(k_dg_update<2>, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, j);
+      else
+        hipLaunchKernelGGL(k_dg_update<4>, dim3(nb), dim3(GS_THREADS), 0, G.st, sg, j);
     }
     HIP_TRY(hipGetLastError());
     if (host_checks && check_every > 0 && (j + 1) % check_every == 0 && j + 1 < s.m) {
@@ -942,7 +1035,8 @@ static int enqueue_cycle(GmresRun& G, int check_every, bool host_checks) {
     }
     PendingApply pa{};
     if (nb > 0)
-      hipLaunchKernelGGL(k_dg_dots<false>, dim3(nb, (unsigned)((s.m + GS_WAVES * GS_BATCH - 1) / (GS_WAVES * GS_BATCH))),
+      hipLaunchKernelGGL(k_dg_dots<false>,
+                         dim3(nb, nb <= GS_SPREAD_CHUNKS ? (unsigned)((s.m + GS_WAVES * GS_BATCH - 1) / (GS_WAVES * GS_BATCH)) : 1u),
                          dim3(GS_THREADS), 0, G.st, sg, s.m, pa, 0);
     hipLaunchKernelGGL(k_dg_flush, dim3(s.C), dim3(GS_THREADS), 0, G.st, s);
     HIP_TRY(hipGetLastError());

@@ -108,9 +108,12 @@ extern "C" int mudiff_rhs_point(mudiff_t h, int R, const double* src, void* out,
 }
 
 // Far field.  Workgroup = (column, tile of FF_TH angles); its FF_DG thread
-// groups split the disks of the instance, then reduce in LDS.
-#define FF_TH 64
-#define FF_DG 4
+// groups split the disks of the instance (thread t: angle t % FF_TH of the
+// tile, disks g, g + FF_DG, ... with g = t / FF_TH), then the group sums are
+// added in LDS in a fixed order.  Small tiles and many groups keep a
+// one-column call (720 angles x 400 disks) spread over the chip.
+#define FF_TH 16
+#define FF_DG 64
 __global__ __launch_bounds__(FF_TH* FF_DG) void k_farfield(DevView v, int R,
                                                            const cplx* __restrict__ rho,
                                                            int n_theta,
@@ -144,9 +147,22 @@ __global__ __launch_bounds__(FF_TH* FF_DG) void k_farfield(DevView v, int R,
   }
   red[dg][tj] = acc;
   __syncthreads();
+  // groups 0..FF_DG-1 added in order: first eight partial runs of FF_DG / 8
+  // groups, then the eight runs
+  constexpr int RUN = FF_DG / 8;
+  const bool summer = threadIdx.x < 8 * FF_TH;
+  const int run = threadIdx.x / FF_TH;
+  cplx sacc = cmk(0.0, 0.0);
+  if (summer) {
+    sacc = red[run * RUN][tj];
+    for (int k = 1; k < RUN; ++k) sacc = cadd(sacc, red[run * RUN + k][tj]);
+  }
+  __syncthreads();  // every run read before any is overwritten
+  if (summer) red[run][tj] = sacc;
+  __syncthreads();
   if (dg == 0 && j < n_theta) {
     cplx s = red[0][tj];
-    for (int k = 1; k < FF_DG; ++k) s = cadd(s, red[k][tj]);
+    for (int k = 1; k < 8; ++k) s = cadd(s, red[k][tj]);
     // e^{i pi/4} / (2 sqrt k)
     const double c = 0.70710678118654752440 / (2.0 * sqrt(kk));
     a_out[(int64_t)col * n_theta + j] = cmul(cmk(c, c), s);
@@ -157,6 +173,7 @@ extern "C" int mudiff_farfield(mudiff_t h, int R, const void* rho, int n_theta, 
                                void* a_out, void* stream) {
   if (!h || !rho || !theta || !a_out) return fail(MUDIFF_ERR_INVALID, "NULL argument");
   if (R < 1 || n_theta < 1) return fail(MUDIFF_ERR_INVALID, "R < 1 or n_theta < 1");
+  if ((int64_t)h->B * R > 65535) return fail(MUDIFF_ERR_INVALID, "too many instance x RHS columns");
   dim3 grid((n_theta + FF_TH - 1) / FF_TH, h->B * R);
   hipLaunchKernelGGL(k_farfield, grid, dim3(FF_TH * FF_DG), 0, (hipStream_t)stream, h->dv, R,
                      (const cplx*)rho, n_theta, theta, (cplx*)a_out);

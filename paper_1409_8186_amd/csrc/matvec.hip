@@ -319,14 +319,24 @@ typedef double mf_d4 __attribute__((ext_vector_type(4)));
 
 #define MF_REC 6       // item record: p0, rp, tile, q0, q1, partial block
 
+// Column of element (n, c) of the staged input panel [4 ktmax][RC] in LDS:
+// c XOR a function of the row n, so that a staging store (consecutive rows, one
+// column) spreads over 16 bank groups and an MFMA B read (rows n..n+3, eight
+// columns) puts even and odd rows in different halves of the banks.
+__device__ __forceinline__ int mf_zcol(int n, int c, int RC) {
+  const int f = ((n & 1) << 3) | ((n >> 1) & 7);
+  return c ^ (f & (RC >= 16 ? 15 : RC - 1));
+}
+
 // K row tiles of one wave against one staged column disk: KT k-steps of 4,
-// two real MFMAs per tile and step (Re T, Im T against [Re Z | Im Z]).
+// two real MFMAs per tile and step (Re T, Im T against [Re Z | Im Z]); zl is
+// the staged panel and zc this lane's panel column.
 template <int K, int MT>
-__device__ __forceinline__ void mf_tiles(const cplx* trow, const cplx* zcol, int RC, int j, int kq,
-                                         int KT, mf_d4* acc1, mf_d4* acc2) {
+__device__ __forceinline__ void mf_tiles(const cplx* trow, const cplx* zl, int zc, int RC, int j,
+                                         int kq, int KT, mf_d4* acc1, mf_d4* acc2) {
   for (int kk = 0; kk < KT; ++kk) {
     const int n = 4 * kk + kq;
-    const cplx zz = zcol[n * RC];
+    const cplx zz = zl[n * RC + mf_zcol(n, zc, RC)];
     const double bv = j < 8 ? zz.x : zz.y;
 #pragma unroll
     for (int mt = 0; mt < K; ++mt) {
@@ -453,7 +463,7 @@ __global__ __launch_bounds__(THREADS) void k_apply_mfma(
       __syncthreads();  // previous column disk done with LDS
 #pragma unroll
       for (int k = 0; k < ZK; ++k)
-        if (zc[k] < RC) zl[zn[k] * RC + zc[k]] = zr[k];
+        if (zc[k] < RC) zl[zn[k] * RC + mf_zcol(zn[k], zc[k], RC)] = zr[k];
 #pragma unroll
       for (int k = 0; k < TK; ++k)
         if (trr[k] < RP) tl[trr[k] * TL + tru[k]] = tr[k];
@@ -464,14 +474,14 @@ __global__ __launch_bounds__(THREADS) void k_apply_mfma(
       }
       if (wave_active && q != p) {
         const cplx* trow = tl + row * TL;
-        const cplx* zcol = zl + ctile * 8 + (j & 7);
+        const int zcl = ctile * 8 + (j & 7);
         // only the row tiles of this row disk (wave-uniform count)
-        if (mtp >= MT) mf_tiles<MT, MT>(trow, zcol, RC, j, kq, KT, acc1, acc2);
+        if (mtp >= MT) mf_tiles<MT, MT>(trow, zl, zcl, RC, j, kq, KT, acc1, acc2);
         else if constexpr (MT >= 2) {
-          if (mtp == MT - 1) mf_tiles<MT - 1, MT>(trow, zcol, RC, j, kq, KT, acc1, acc2);
+          if (mtp == MT - 1) mf_tiles<MT - 1, MT>(trow, zl, zcl, RC, j, kq, KT, acc1, acc2);
           else if constexpr (MT >= 3) {
-            if (mtp == MT - 2) mf_tiles<MT - 2, MT>(trow, zcol, RC, j, kq, KT, acc1, acc2);
-            else if constexpr (MT >= 4) mf_tiles<MT - 3, MT>(trow, zcol, RC, j, kq, KT, acc1, acc2);
+            if (mtp == MT - 2) mf_tiles<MT - 2, MT>(trow, zl, zcl, RC, j, kq, KT, acc1, acc2);
+            else if constexpr (MT >= 4) mf_tiles<MT - 3, MT>(trow, zl, zcl, RC, j, kq, KT, acc1, acc2);
           }
         }
       }

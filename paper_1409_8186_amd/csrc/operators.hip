@@ -140,7 +140,13 @@ __global__ void k_pen_tables(DevView v, const double* __restrict__ k_int, const 
   // row weights, normalised so that |s1| + |s2| = 1 (J_m and J'_m of one
   // argument never vanish together; without it the rows of high orders at small
   // k- a would be tiny)
-  double s1 = Ji, s2 = -(mu ? mu[p] : 1.0) * ki * Jid;
+  const double mup = mu ? mu[p] : 1.0;
+  double s1 = Ji, s2 = -mup * ki * Jid;
+  if (!(fabs(s1) + fabs(s2) > 0.0)) {
+    // both underflowed (high order, small k- a): J'_m / J_m -> |m| / (k- a)
+    s1 = 1.0;
+    s2 = -mup * (double)am / a;
+  }
   const double nrm = 1.0 / (fabs(s1) + fabs(s2));
   s1 *= nrm;
   s2 *= nrm;
@@ -237,7 +243,10 @@ __global__ void k_interior_coef(DevView v, int R, const double* __restrict__ Jin
   const int p = v.udisk[v.imode[b] + il];
   const int m = (int)(il - v.moff[p]) - v.N[p];
   const double Ja = Jint[v.dtab[p] + (m < 0 ? -m : m)];
-  U[g] = cscale(cadd(U[g], Lr[g]), 1.0 / (sqrt(2.0 * OPS_PI * v.a[p]) * Ja));
+  // J_m(k- a) underflowed (high order, small k- a): the mode's interior field,
+  // |J_m(k- r) / J_m(k- a)| <= 1 times its trace coefficient, is below rounding
+  U[g] = Ja == 0.0 ? cmk(0.0, 0.0)
+                   : cscale(cadd(U[g], Lr[g]), 1.0 / (sqrt(2.0 * OPS_PI * v.a[p]) * Ja));
 }
 
 // Points inside a disk: u-(x) = sum_m c_m J_|m|(k- r) e^{i m theta} (polar

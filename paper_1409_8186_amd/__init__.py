@@ -6,11 +6,17 @@ include/mudiff.h, with a thin Python binding.
     P = Problem.from_cluster(cluster)             # tables on the device
     rho, flag, relres, iters, _ = P.gmres(betas=[[0.0]], tol=1e-8)
     a = P.farfield(rho, thetas)
+    u = P.nearfield(rho, points, betas=[[0.0]])   # total field at points
+
+Other formulations (P.set_operator("cfie"), ...), penetrable disks
+(P.set_penetrable(k_int, mu), P.interior_field), point sources (sources=
+instead of betas), the time-reversal operator (tro, tro_eigh, herglotz) and
+the misfit gradient (P.grad, FarFieldMisfit) use the same handle.
 
 Importing the package does not load the library; ``Problem`` loads it and
 raises if it was not built (``python -m paper_1409_8186_amd.build``).
 """
-from ._lib import GRAPH, OP_A, OP_L, X0, MudiffError  # noqa: F401
+from ._lib import GRAPH, OP_A, OP_L, POINT_SOURCE, X0, MudiffError  # noqa: F401
 
 
 def __getattr__(name):

@@ -10,8 +10,9 @@ include/mudiff.h, with a thin Python binding.
 
 Other formulations (P.set_operator("cfie"), ...), penetrable disks
 (P.set_penetrable(k_int, mu), P.interior_field), point sources (sources=
-instead of betas), the time-reversal operator (tro, tro_eigh, herglotz) and
-the misfit gradient (P.grad, FarFieldMisfit) use the same handle.
+instead of betas) and the misfit gradient (P.grad, FarFieldMisfit) use the
+same handle; the time-reversal operator is built from P.mirror_farfield with
+the module functions tro, tro_eigh and herglotz.
 
 Importing the package does not load the library; ``Problem`` loads it and
 raises if it was not built (``python -m paper_1409_8186_amd.build``).

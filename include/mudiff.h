@@ -138,6 +138,9 @@ size_t mudiff_matvec_workspace_size(mudiff_t h, int R);
  *              it ready for the next one (its counters return to zero), so
  *              one buffer serves any number of calls on one stream.  Calls
  *              that overlap in time (several streams) need separate buffers.
+ *              No state is kept in it between calls beyond those zeros: for
+ *              R >= 8 (FP64 MFMA) each call uploads the tile schedule into it
+ *              again (one host synchronisation of the stream).
  * Off-diagonal blocks are applied as Toeplitz products in the mode
  * difference n - m (the diagonal.Toeplitz.diagonal structure of sec. 5). */
 int mudiff_matvec(mudiff_t h, int R, const void* x, void* y, int op,

@@ -326,6 +326,12 @@ int apply_operator_split(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, c
                          int32_t* counters, const int32_t* active, hipStream_t s,
                          bool* pending);
 size_t apply_scratch_bytes(mudiff_ctx* h, int R);
+// Forget where the MFMA schedule was last uploaded: the next apply uploads it
+// into its scratch again.  Every entry point that takes an apply scratch from
+// the caller calls this first, so a buffer whose memory was used for anything
+// else between calls (or a new buffer at a recycled address) never runs on a
+// stale schedule.
+void apply_forget_upload(mudiff_ctx* h);
 // Lane-record layout of the one-lane-per-pair apply: total size in complex
 // values (0 when N is not uniform or out of range), the common N, and per disk
 // the offset of its first chunk.

@@ -1067,6 +1067,7 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
   if (maxit < 1) return fail(MUDIFF_ERR_INVALID, "maxit < 1");
   GLayout L = glayout(h, R, restart);
   if (!workspace) return fail(MUDIFF_ERR_INVALID, "workspace is NULL");
+  apply_forget_upload(h);
   if (ws_bytes < L.total) return fail(MUDIFF_ERR_NOMEM, "gmres workspace needs " + std::to_string(L.total) + " bytes");
   if (((uintptr_t)workspace) & 255) return fail(MUDIFF_ERR_INVALID, "workspace must be 256-byte aligned");
   hipStream_t st = (hipStream_t)stream;

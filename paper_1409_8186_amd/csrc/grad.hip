@@ -490,6 +490,7 @@ extern "C" int mudiff_grad(mudiff_t h, int R, const double* beta, int n_rec, con
   if (!(tol > 0.0) || maxit < 1) return fail(MUDIFF_ERR_INVALID, "tol <= 0 or maxit < 1");
   if (h->dv.op_col) return fail(MUDIFF_ERR_INVALID, "the gradient is for the single-layer EFIE; reset the operator first");
   if (flags & MUDIFF_POINT_SOURCE) return fail(MUDIFF_ERR_INVALID, "the gradient is for plane-wave incidence");
+  apply_forget_upload(h);
   const int gflags = flags & MUDIFF_GRAPH;
   GradLayout L = grad_layout(h, R, n_rec, restart, gflags);
   if (!workspace) return fail(MUDIFF_ERR_INVALID, "workspace is NULL");

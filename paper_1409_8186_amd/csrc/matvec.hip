@@ -1044,6 +1044,8 @@ size_t apply_scratch_bytes(mudiff_ctx* h, int R) {
   return align256((size_t)R * h->plan_part * 16) + counters;
 }
 
+void apply_forget_upload(mudiff_ctx* h) { h->mfma_sched.dev_base = nullptr; }
+
 int prepare_apply(mudiff_ctx* h, int R, const cplx* x, cplx* y, cplx* scratch, hipStream_t s) {
   if (use_mfma(h, R)) return mfma_prepare(h, R, x, y, (char*)scratch, s);
   return ensure_plan(h, s);
@@ -1119,6 +1121,7 @@ extern "C" int mudiff_matvec(mudiff_t h, int R, const void* x, void* y, int op, 
   size_t need = apply_scratch_bytes(h, R);
   if (!workspace) return fail(MUDIFF_ERR_INVALID, "workspace is NULL");
   if (ws_bytes < need) return fail(MUDIFF_ERR_NOMEM, "matvec workspace needs " + std::to_string(need) + " bytes");
+  apply_forget_upload(h);
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)workspace;
   if (use_mfma(h, R)) {

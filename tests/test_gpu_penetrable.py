@@ -225,3 +225,22 @@ def test_penetrable_interior_field_matches_oracle(P, kind):
     assert outside[n_in:].sum() > 300
     keep = torch.tensor(outside, device="cuda")
     assert torch.equal(tot[:, keep], ext[:, keep])
+
+
+def test_penetrable_interior_field_many_incidences(P):
+    """Nine incidences (the trace L+ rho+ on the FP64-MFMA apply), twice in a row
+    with fresh workspaces, against the oracle."""
+    cl = synth.Cluster(*synth.random_disks(np.random.default_rng(97), 6, 0.3, 0.7, 0.0, 6.0, 0.3),
+                       np.full(6, 8, np.int32), 3.0)
+    ki, mu = _media(6, cl.k, 5)
+    betas = 2 * np.pi * np.arange(9) / 9
+    rp, rm = pen.solve(cl.centers, cl.radii, cl.n_modes, cl.k, ki, betas, mu=mu)
+    pin, which = _inside_points(cl, 60, np.random.default_rng(12))
+    ref = np.stack([np.concatenate([pen.interior_field(cl.centers, cl.radii, cl.n_modes, ki, rm[r], p, x[None, :])
+                                    for x, p in zip(pin, which)]) for r in range(9)])
+    pr = P.from_cluster(cl)
+    pr.set_penetrable(ki, mu)
+    rho = pr.pack([rp])
+    for _ in range(2):
+        u = pr.interior_field(rho, pin, R=9, betas=[betas]).cpu().numpy()
+        assert rel(u, ref) < 1e-11

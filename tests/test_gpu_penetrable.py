@@ -244,3 +244,28 @@ def test_penetrable_interior_field_many_incidences(P):
     for _ in range(2):
         u = pr.interior_field(rho, pin, R=9, betas=[betas]).cpu().numpy()
         assert rel(u, ref) < 1e-11
+
+
+def test_penetrable_time_reversal_matrix(P):
+    """The mirror far-field matrix of three penetrable disks (the geometry of the
+    time-reversal example, with k- = 2 k): F[i, j] = a(alpha_i + pi; alpha_j)
+    against the oracle's block solve, F complex symmetric (reciprocity), and the
+    eigenvalues of T = conj(F)^T F against LAPACK."""
+    from paper_1409_8186_amd import tro, tro_eigh
+    cl = synth.dort_example(64)
+    ki = np.full(3, 2 * cl.k)
+    n_alpha = 64
+    al = 2 * np.pi * np.arange(n_alpha) / n_alpha
+    rp, _ = pen.solve(cl.centers, cl.radii, cl.n_modes, cl.k, ki, al)
+    Fo = pen.farfield(cl.centers, cl.radii, cl.n_modes, cl.k, rp, al + np.pi).T   # [receiver, incidence]
+    pr = P.from_cluster(cl)
+    pr.set_penetrable(ki)
+    X, flag, relres, iters = pr.mirror_farfield(n_alpha, restart=30, tol=1e-13, maxit=500)
+    assert np.all(flag.cpu().numpy() == 0)
+    F = X.cpu().numpy().T
+    assert rel(F, Fo) < 1e-10
+    assert rel(F, F.T) < 1e-10
+    w, ev, sweeps = tro_eigh(X)
+    wo = np.sort(np.linalg.eigvalsh(Fo.conj().T @ Fo))[::-1]
+    assert np.max(np.abs(w.cpu().numpy() - wo)) < 1e-10 * wo[0]
+    say("penetrable T: leading eigenvalues", w.cpu().numpy()[:4])

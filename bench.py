@@ -424,6 +424,12 @@ def formulations_workload(base):
     res["neumann_dl"]["farfield_rel_diff_vs_neumann_sl"] = dev(far["neumann_dl"], far["neumann_sl"])
     flops = algorithmic_flops(cl.n_modes, 1)
     t_app = res["cfie"]["apply_us"] * 1e-6
+    # the oracle: dense CFIE assembly, LU solve and far field on the first 200 disks
+    from oracle import operators as oops
+    c0 = time.perf_counter()
+    oops.solve_farfield("cfie", cl.centers[:200], cl.radii[:200], cl.n_modes[:200], cl.k,
+                        [math.pi / 4], cl.thetas, alpha=0.5, eta=1j * cl.k)
+    t_cpu = time.perf_counter() - c0
     return {**base, "metric": "time-to-1e-8 GMRES solve per formulation", "value": res["cfie"]["solve_s"],
             "unit": "s (CFIE)", "higher_is_better": False, "ms_per_step": res["cfie"]["solve_s"] * 1e3,
             "config": {"workload": "formulations: one_rhs geometry (M=400, a=0.5, N_p=12, k=2pi, "
@@ -435,7 +441,11 @@ def formulations_workload(base):
                                                    "k_apply_lane<12, true> + k_apply_finish (CFIE)",
                          "achieved": flops / t_app / 1e12, "peak": PEAK_FP64_VECTOR_TFLOPS,
                          "unit": "TFLOP/s", "frac": flops / t_app / 1e12 / PEAK_FP64_VECTOR_TFLOPS,
-                         "traffic": None}}
+                         "traffic": None},
+            "cpu_baseline": {"value": t_cpu, "unit": "s per solve", "cores": _blas_threads(),
+                             "kind": "oracle",
+                             "sample": "dense CFIE assembly + LU solve + far field of the first 200 "
+                                       "disks (5,000 unknowns), not the 400-disk solve"}}
 
 
 def nearfield_workload(base):

@@ -414,35 +414,48 @@ __global__ __launch_bounds__(THREADS) void k_apply_mfma(
       acc1[t] = mf_d4{0.0, 0.0, 0.0, 0.0};
       acc2[t] = mf_d4{0.0, 0.0, 0.0, 0.0};
     }
-    cplx zr[ZK], tr[TK];
+    // Gathered values of the next column disk, loaded while the current one is
+    // on the matrix cores: nothing in the gather consumes a load (the input
+    // scale and the symbol sign are applied when staging), so the gather does
+    // not hold up the MFMAs behind it.  N and the mode offset of the disks are
+    // read one disk ahead of their gather, N of the item's row disks once.
+    cplx zr[ZK], zs[ZK], tr[TK];
+    double tsg[TK];
     int32_t tof[TK];  // symbol offsets (the MFMA path requires T_all < 2^31)
-    // gather the staged values of column disk q into registers
-    auto gather = [&](int q) {
-      const int Nq = v.N[q], nq = 2 * Nq + 1;
-      const int64_t mq = v.moff[q];
+    int npr[TK];
+#pragma unroll
+    for (int k = 0; k < TK; ++k) npr[k] = trr[k] < rp ? v.N[p0 + trr[k]] : 0;
+    auto gather = [&](int q, int Nq, int64_t mq) {
+      const int nq = 2 * Nq + 1;
 #pragma unroll
       for (int k = 0; k < ZK; ++k) {
         const int c = zc[k], n = zn[k];
-        cplx z = cmk(0.0, 0.0);
-        if (c < RC && n < nq && c0 + c < R)
-          z = col_scale(v, i0 + mq + n, x[col_base(v.imode, b, R, c0 + c) + mq + n]);
+        cplx z = cmk(0.0, 0.0), sc = cmk(0.0, 0.0);
+        if (c < RC && n < nq && c0 + c < R) {
+          const int64_t iu = i0 + mq + n;
+          z = x[col_base(v.imode, b, R, c0 + c) + mq + n];
+          sc = v.op_col ? v.op_col[iu] : cmk(v.sJ[iu], 0.0);
+        }
         zr[k] = z;
+        zs[k] = sc;
       }
 #pragma unroll
       for (int k = 0; k < TK; ++k) {
         const int rr = trr[k], u = tru[k];
         cplx t = cmk(0.0, 0.0);
+        double sg = 1.0;
         const int pr = p0 + rr;
         if (rr < rp && pr != q) {
-          const int Npr = v.N[pr];
+          const int Npr = npr[k];
           const int S = Npr + Nq;
           const int s = u - (16 * MT - 1) - Nq + Npr;
           if (s >= -S && s <= S) {
             t = v.t[tof[k] + S + s];
-            if (pr > q && (s & 1)) t = cmk(-t.x, -t.y);
+            if (pr > q && (s & 1)) sg = -1.0;
           }
         }
         tr[k] = t;
+        tsg[k] = sg;
       }
     };
     // symbol-row offsets of column disk q, loaded one disk ahead of gather(q)
@@ -455,21 +468,38 @@ __global__ __launch_bounds__(THREADS) void k_apply_mfma(
                      ? (int32_t)v.toff[pair_index(v.idisk, v.ipair, b, pr, q)] : 0;
       }
     };
-    load_toff(qb);
-    gather(qb);
-    load_toff(qb + 1);
+    // N and mode offset of disks q (0), q + 1 (1) and q + 2 (2)
+    int Nq0 = 0, Nq1 = 0, Nq2 = 0;
+    int64_t mq0 = 0, mq1 = 0, mq2 = 0;
+    if (qb < qe) {
+      Nq0 = v.N[qb];
+      mq0 = v.moff[qb];
+    }
+    if (qb + 1 < qe) {
+      Nq1 = v.N[qb + 1];
+      mq1 = v.moff[qb + 1];
+    }
+    if (qb < qe) {
+      load_toff(qb);
+      gather(qb, Nq0, mq0);
+      load_toff(qb + 1);
+    }
     for (int q = qb; q < qe; ++q) {
-      const int nq = 2 * v.N[q] + 1, KT = (nq + 3) >> 2;
+      const int nq = 2 * Nq0 + 1, KT = (nq + 3) >> 2;
       __syncthreads();  // previous column disk done with LDS
 #pragma unroll
       for (int k = 0; k < ZK; ++k)
-        if (zc[k] < RC) zl[zn[k] * RC + mf_zcol(zn[k], zc[k], RC)] = zr[k];
+        if (zc[k] < RC) zl[zn[k] * RC + mf_zcol(zn[k], zc[k], RC)] = cmul(zr[k], zs[k]);
 #pragma unroll
       for (int k = 0; k < TK; ++k)
-        if (trr[k] < RP) tl[trr[k] * TL + tru[k]] = tr[k];
+        if (trr[k] < RP) tl[trr[k] * TL + tru[k]] = cscale(tr[k], tsg[k]);
       __syncthreads();
+      if (q + 2 < qe) {  // used by the next iteration's gather
+        Nq2 = v.N[q + 2];
+        mq2 = v.moff[q + 2];
+      }
       if (q + 1 < qe) {  // in flight during the MFMAs
-        gather(q + 1);
+        gather(q + 1, Nq1, mq1);
         load_toff(q + 2);
       }
       if (wave_active && q != p) {
@@ -485,6 +515,10 @@ __global__ __launch_bounds__(THREADS) void k_apply_mfma(
           }
         }
       }
+      Nq0 = Nq1;
+      mq0 = mq1;
+      Nq1 = Nq2;
+      mq1 = mq2;
     }
     if (!wave_active) continue;
     // partial block [RP][npad][RC]: row r of the item, mode row m, RHS column

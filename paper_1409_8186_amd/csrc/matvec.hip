@@ -416,10 +416,11 @@ __global__ __launch_bounds__(THREADS) void k_apply_mfma(
     }
     // Gathered values of the next column disk, loaded while the current one is
     // on the matrix cores: nothing in the gather consumes a load (the input
-    // scale and the symbol sign are applied when staging), so the gather does
-    // not hold up the MFMAs behind it.  N and the mode offset of the disks are
-    // read one disk ahead of their gather, N of the item's row disks once.
-    cplx zr[ZK], zs[ZK], tr[TK];
+    // arrives scaled by its column factor, the symbol sign is applied when
+    // staging), so the gather does not hold up the MFMAs behind it.  N and the
+    // mode offset of the disks are read one disk ahead of their gather, N of
+    // the item's row disks once.
+    cplx zr[ZK], tr[TK];
     double tsg[TK];
     int32_t tof[TK];  // symbol offsets (the MFMA path requires T_all < 2^31)
     int npr[TK];
@@ -430,14 +431,9 @@ __global__ __launch_bounds__(THREADS) void k_apply_mfma(
 #pragma unroll
       for (int k = 0; k < ZK; ++k) {
         const int c = zc[k], n = zn[k];
-        cplx z = cmk(0.0, 0.0), sc = cmk(0.0, 0.0);
-        if (c < RC && n < nq && c0 + c < R) {
-          const int64_t iu = i0 + mq + n;
-          z = x[col_base(v.imode, b, R, c0 + c) + mq + n];
-          sc = v.op_col ? v.op_col[iu] : cmk(v.sJ[iu], 0.0);
-        }
+        cplx z = cmk(0.0, 0.0);
+        if (c < RC && n < nq && c0 + c < R) z = x[col_base(v.imode, b, R, c0 + c) + mq + n];
         zr[k] = z;
-        zs[k] = sc;
       }
 #pragma unroll
       for (int k = 0; k < TK; ++k) {
@@ -489,7 +485,7 @@ __global__ __launch_bounds__(THREADS) void k_apply_mfma(
       __syncthreads();  // previous column disk done with LDS
 #pragma unroll
       for (int k = 0; k < ZK; ++k)
-        if (zc[k] < RC) zl[zn[k] * RC + mf_zcol(zn[k], zc[k], RC)] = cmul(zr[k], zs[k]);
+        if (zc[k] < RC) zl[zn[k] * RC + mf_zcol(zn[k], zc[k], RC)] = zr[k];
 #pragma unroll
       for (int k = 0; k < TK; ++k)
         if (trr[k] < RP) tl[trr[k] * TL + tru[k]] = cscale(tr[k], tsg[k]);
@@ -536,6 +532,27 @@ __global__ __launch_bounds__(THREADS) void k_apply_mfma(
       }
     }
   }
+}
+
+// z = x scaled by the column factor of its unknown (sqrt(a) J_n, or the
+// operator's column table), once per apply: the MFMA gathers then load one
+// value per panel element.
+__global__ void k_apply_mfma_scale(DevView v, int R, const cplx* __restrict__ x, cplx* __restrict__ z,
+                                   const int32_t* __restrict__ active) {
+  const int64_t total = (int64_t)R * v.N_all;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  int lo = 0, hi = v.B;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if ((int64_t)R * v.imode[mid] <= g) lo = mid; else hi = mid;
+  }
+  const int64_t Nb = v.imode[lo + 1] - v.imode[lo];
+  const int64_t rem = g - (int64_t)R * v.imode[lo];
+  const int r = (int)(rem / Nb);
+  if (active && active[lo * R + r] == 0) return;  // columns that no longer iterate
+  const int64_t i = v.imode[lo] + (rem - (int64_t)r * Nb);
+  z[g] = col_scale(v, i, x[g]);
 }
 
 // y = finalize(sum over the segments of the MFMA partial blocks), one thread
@@ -666,6 +683,7 @@ static size_t mfma_scratch_layout(const mudiff_ctx* h, const MfmaSched& S, size_
   off[4] = take(S.gnseg.size() * 4);
   off[5] = take(S.gbase.size() * 8);
   off[6] = take((size_t)S.n_pb * S.blk * 16);
+  off[7] = take((size_t)S.R * h->N_all * 16);  // the input with its column scale applied
   return o;
 }
 
@@ -692,7 +710,7 @@ static MfmaChoice mfma_default(int R) {
 // Upload schedule S into the apply scratch at `base` (synchronises; not for
 // use under graph capture).
 static int mfma_upload(mudiff_ctx* h, MfmaSched& S, char* base, hipStream_t s) {
-  size_t off[7];
+  size_t off[8];
   mfma_scratch_layout(h, S, off);
   HIP_TRY(hipMemcpyAsync(base + off[1], S.items.data(), S.items.size() * 4, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(base + off[2], S.dgrp.data(), (size_t)h->M_all * 4, hipMemcpyHostToDevice, s));
@@ -732,7 +750,7 @@ static mf_fn mf_select(int mt, int th, int zk, int tk) {
 
 static int mfma_launch(mudiff_ctx* h, const MfmaSched& S, const cplx* x, cplx* y, int op,
                        const int32_t* active, hipStream_t s) {
-  size_t off[7];
+  size_t off[8];
   mfma_scratch_layout(h, S, off);
   char* base = (char*)S.dev_base;
   int32_t* head = (int32_t*)(base + off[0]);
@@ -743,6 +761,11 @@ static int mfma_launch(mudiff_ctx* h, const MfmaSched& S, const cplx* x, cplx* y
   const size_t lds = ((size_t)4 * kt * RC + (size_t)S.c.RP * (4 * kt + 16 * mt - 1)) * 16;
   int rc = launch_fill_zero(head, 4, s);
   if (rc != MUDIFF_OK) return rc;
+  cplx* z = (cplx*)(base + off[7]);
+  const int64_t nz = (int64_t)S.R * h->N_all;
+  hipLaunchKernelGGL(k_apply_mfma_scale, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, s, h->dv,
+                     S.R, x, z, active);
+  HIP_TRY(hipGetLastError());
   if (S.n_items > 0) {
     const int32_t* it = (const int32_t*)(base + off[1]);
 const int TL = 4 * kt + 16 * mt - 1;
@@ -757,7 +780,7 @@ const int TL = 4 * kt + 16 * mt - 1;
             hipSuccess || per_cu < 1)
       per_cu = 1;
     const int grid = std::max(1, std::min(S.n_items, per_cu * h->n_cu));
-    hipLaunchKernelGGL(fn, dim3(grid), dim3(S.c.threads), lds, s, h->dv, S.R, x, active, it,
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(S.c.threads), lds, s, h->dv, S.R, (const cplx*)z, active, it,
                        S.n_items, head, part, S.blk, S.npad, kt, S.c.RP, S.c.CT);
     HIP_TRY(hipGetLastError());
   }
@@ -780,7 +803,7 @@ static size_t mfma_scratch_bytes(mudiff_ctx* h, int R) {
       c.QS = qs;
       MfmaSched S;
       mfma_build(h, R, c, S);
-      size_t off[7];
+      size_t off[8];
       mx = std::max(mx, mfma_scratch_layout(h, S, off));
     }
   }

@@ -157,7 +157,7 @@ struct MfmaSched {
   MfmaChoice c{};
   int ntile = 0, n_items = 0, npad = 0;
   int64_t blk = 0, n_pb = 0;
-  std::vector<int32_t> items, dgrp, gp0, gnseg;
+  std::vector<int32_t> items, dgrp, grow, gnseg, drow;  // grow: RP row disks per group (-1: none)
   std::vector<int64_t> gbase;
   void* dev_base = nullptr;  // apply scratch the device copy lives in
 };

@@ -302,7 +302,9 @@ __global__ void k_apply_finish(DevView v, int R, const cplx* __restrict__ x, cpl
 // Lane layout (checked on the device): lane l holds A[l % 16][l / 16],
 // B[l / 16][l % 16] and D[4 v + l / 16][l % 16], v < 4.
 //
-// Work item: row disks p0..p0+rp-1 (rp <= RP) of one instance, a tile of 8 CT
+// Work item: a group of rp <= RP row disks of one instance (disks of equal row
+// tile count grouped together, so that the waves of a workgroup issue equal
+// numbers of MFMAs between barriers), a tile of 8 CT
 // right-hand sides and a segment [q0, q1) of its column disks.  Wave w of the
 // workgroup computes row w / CT and right-hand-side sub-tile w % CT.  Per
 // column disk q the input panel Z^q = sqrt(a_q) J_n(k a_q) x^q_n and the symbol
@@ -317,7 +319,7 @@ __global__ void k_apply_finish(DevView v, int R, const cplx* __restrict__ x, cpl
 // and R by timing the candidates on the real data (mfma_autotune).
 typedef double mf_d4 __attribute__((ext_vector_type(4)));
 
-#define MF_REC 6       // item record: p0, rp, tile, q0, q1, partial block
+#define MF_REC 6       // item record: row group, rp, tile, q0, q1, partial block
 
 // Column of element (n, c) of the staged input panel [4 ktmax][RC] in LDS:
 // c XOR a function of the row n, so that a staging store (consecutive rows, one
@@ -355,7 +357,8 @@ template <int MT, int THREADS, int ZK, int TK>
 __global__ __launch_bounds__(THREADS) void k_apply_mfma(
     DevView v, int R, const cplx* __restrict__ x, const int32_t* __restrict__ active,
     const int32_t* __restrict__ items, int n_items, int32_t* __restrict__ head,
-    cplx* __restrict__ part, int64_t blk, int npad, int ktmax, int RP, int CT) {
+    cplx* __restrict__ part, int64_t blk, int npad, int ktmax, int RP, int CT,
+    const int32_t* __restrict__ grow) {
   extern __shared__ cplx lds[];
   __shared__ int s_item;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -388,17 +391,18 @@ __global__ __launch_bounds__(THREADS) void k_apply_mfma(
     const int it = s_item;
     if (it >= n_items) break;
     const int32_t* rec = items + (int64_t)MF_REC * it;
-    const int p0 = rec[0], rp = rec[1], tile = rec[2], qb = rec[3], qe = rec[4];
+    const int rp = rec[1], tile = rec[2], qb = rec[3], qe = rec[4];
+    const int32_t* grp = grow + (int64_t)rec[0] * RP;  // the item's row disks
     const int64_t pb = rec[5];
     const int c0 = tile * RC;
-    const int b = v.inst[p0];
+    const int b = v.inst[grp[0]];
     bool any = false;  // converged columns: the whole tile may be skipped
     for (int r = c0; r < min(R, c0 + RC); ++r)
       if (!active || active[b * R + r]) any = true;
     if (!any) continue;
     const int64_t i0 = v.imode[b];
-    const int p = p0 + row;
     const bool row_ok = row < rp;
+    const int p = row_ok ? grp[row] : -1;
     const int mtp = row_ok ? (2 * v.N[p] + 1 + 15) >> 4 : 0;  // row tiles of this row disk
     bool wave_active = row_ok;
     if (wave_active) {
@@ -423,9 +427,12 @@ __global__ __launch_bounds__(THREADS) void k_apply_mfma(
     cplx zr[ZK], tr[TK];
     double tsg[TK];
     int32_t tof[TK];  // symbol offsets (the MFMA path requires T_all < 2^31)
-    int npr[TK];
+    int npr[TK], prw[TK];  // N and index of this thread's symbol-row disks
 #pragma unroll
-    for (int k = 0; k < TK; ++k) npr[k] = trr[k] < rp ? v.N[p0 + trr[k]] : 0;
+    for (int k = 0; k < TK; ++k) {
+      prw[k] = trr[k] < rp ? grp[trr[k]] : -1;
+      npr[k] = prw[k] >= 0 ? v.N[prw[k]] : 0;
+    }
     auto gather = [&](int q, int Nq, int64_t mq) {
       const int nq = 2 * Nq + 1;
 #pragma unroll
@@ -440,7 +447,7 @@ __global__ __launch_bounds__(THREADS) void k_apply_mfma(
         const int rr = trr[k], u = tru[k];
         cplx t = cmk(0.0, 0.0);
         double sg = 1.0;
-        const int pr = p0 + rr;
+        const int pr = prw[k];
         if (rr < rp && pr != q) {
           const int Npr = npr[k];
           const int S = Npr + Nq;
@@ -459,7 +466,7 @@ __global__ __launch_bounds__(THREADS) void k_apply_mfma(
     auto load_toff = [&](int q) {
 #pragma unroll
       for (int k = 0; k < TK; ++k) {
-        const int pr = p0 + trr[k];
+        const int pr = prw[k];
         tof[k] = (q < qe && trr[k] < rp && pr != q)
                      ? (int32_t)v.toff[pair_index(v.idisk, v.ipair, b, pr, q)] : 0;
       }
@@ -560,7 +567,7 @@ __global__ void k_apply_mfma_scale(DevView v, int R, const cplx* __restrict__ x,
 __global__ void k_apply_mfma_finish(DevView v, int R, const cplx* __restrict__ x,
                                     cplx* __restrict__ y, int op, const cplx* __restrict__ part,
                                     int64_t blk, int npad, int RC, const int32_t* __restrict__ dgrp,
-                                    const int32_t* __restrict__ gp0,
+                                    const int32_t* __restrict__ drow,
                                     const int32_t* __restrict__ gnseg,
                                     const int64_t* __restrict__ gbase,
                                     const int32_t* __restrict__ active) {
@@ -584,7 +591,7 @@ __global__ void k_apply_mfma_finish(DevView v, int R, const cplx* __restrict__ x
   const int t = r / RC, rc = r - (r / RC) * RC;
   const int ns = gnseg[gr];
   const cplx* pr = part + (gbase[gr] + (int64_t)t * ns) * blk +
-                   ((int64_t)(p - gp0[gr]) * npad + m) * RC + rc;
+                   ((int64_t)drow[p] * npad + m) * RC + rc;
   cplx w = cmk(0.0, 0.0);
   for (int s = 0; s < ns; ++s) w = cadd(w, pr[(int64_t)s * blk]);
   y[g] = finalize(v, op, i, x[g], w);
@@ -612,10 +619,11 @@ static void mfma_build(const mudiff_ctx* h, int R, const MfmaChoice& c, MfmaSche
   S.npad = 16 * mt;
   S.blk = (int64_t)c.RP * S.npad * RC;
   S.items.clear();
-  S.gp0.clear();
+  S.grow.clear();
   S.gnseg.clear();
   S.gbase.clear();
   S.dgrp.assign(h->M_all, 0);
+  S.drow.assign(h->M_all, 0);
   struct It {
     double cost;
     int32_t r[MF_REC];
@@ -626,15 +634,27 @@ static void mfma_build(const mudiff_ctx* h, int R, const MfmaChoice& c, MfmaSche
     const int64_t d0 = h->idisk[b], d1 = h->idisk[b + 1], Mb = d1 - d0;
     const int64_t qs = c.QS > 0 ? c.QS : Mb;
     const int nseg = (int)((Mb + qs - 1) / qs);
-    for (int64_t p = d0; p < d1; p += c.RP) {
-      const int rp = (int)std::min<int64_t>(c.RP, d1 - p);
-      const int gi = (int)S.gp0.size();
-      for (int k = 0; k < rp; ++k) S.dgrp[p + k] = gi;
-      S.gp0.push_back((int32_t)p);
+    // row disks ordered by their number of 16-row tiles (stable), in groups of RP
+    std::vector<int32_t> ord((size_t)Mb);
+    for (int64_t k = 0; k < Mb; ++k) ord[(size_t)k] = (int32_t)(d0 + k);
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t u, int32_t w) {
+      return (2 * h->N[u] + 16) / 16 > (2 * h->N[w] + 16) / 16;
+    });
+    for (int64_t o = 0; o < Mb; o += c.RP) {
+      const int rp = (int)std::min<int64_t>(c.RP, Mb - o);
+      const int gi = (int)S.gnseg.size();
+      for (int k = 0; k < c.RP; ++k) {
+        const int32_t pk = k < rp ? ord[(size_t)(o + k)] : -1;
+        S.grow.push_back(pk);
+        if (pk >= 0) {
+          S.dgrp[pk] = gi;
+          S.drow[pk] = k;
+        }
+      }
       S.gnseg.push_back(nseg);
       S.gbase.push_back(pb);
       double rows = 0.0;
-      for (int k = 0; k < rp; ++k) rows += 2 * h->N[p + k] + 1;
+      for (int k = 0; k < rp; ++k) rows += 2 * h->N[ord[(size_t)(o + k)]] + 1;
       for (int t = 0; t < S.ntile; ++t) {
         if (!cols.empty()) {  // straggler schedule: tiles holding a running column only
           bool any = false;
@@ -647,7 +667,7 @@ static void mfma_build(const mudiff_ctx* h, int R, const MfmaChoice& c, MfmaSche
           for (int64_t q = q0; q < q1; ++q) cols += 2 * h->N[q] + 1;
           It e;
           e.cost = rows * cols + 64.0 * (double)(q1 - q0);  // MACs + per-disk staging
-          e.r[0] = (int32_t)p;
+          e.r[0] = gi;
           e.r[1] = rp;
           e.r[2] = t;
           e.r[3] = (int32_t)q0;
@@ -668,7 +688,7 @@ static void mfma_build(const mudiff_ctx* h, int R, const MfmaChoice& c, MfmaSche
 }
 
 // Byte layout of the MFMA schedule inside the apply scratch:
-// [head][items][dgrp][gp0][gnseg][gbase][partial blocks]
+// [head][items][dgrp][grow][gnseg][gbase][partial blocks][scaled input][drow]
 static size_t mfma_scratch_layout(const mudiff_ctx* h, const MfmaSched& S, size_t* off) {
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -679,11 +699,12 @@ static size_t mfma_scratch_layout(const mudiff_ctx* h, const MfmaSched& S, size_
   off[0] = take(4);
   off[1] = take(S.items.size() * 4);
   off[2] = take((size_t)h->M_all * 4);
-  off[3] = take(S.gp0.size() * 4);
+  off[3] = take(S.grow.size() * 4);
   off[4] = take(S.gnseg.size() * 4);
   off[5] = take(S.gbase.size() * 8);
   off[6] = take((size_t)S.n_pb * S.blk * 16);
   off[7] = take((size_t)S.R * h->N_all * 16);  // the input with its column scale applied
+  off[8] = take((size_t)h->M_all * 4);
   return o;
 }
 
@@ -710,11 +731,12 @@ static MfmaChoice mfma_default(int R) {
 // Upload schedule S into the apply scratch at `base` (synchronises; not for
 // use under graph capture).
 static int mfma_upload(mudiff_ctx* h, MfmaSched& S, char* base, hipStream_t s) {
-  size_t off[8];
+  size_t off[9];
   mfma_scratch_layout(h, S, off);
   HIP_TRY(hipMemcpyAsync(base + off[1], S.items.data(), S.items.size() * 4, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(base + off[2], S.dgrp.data(), (size_t)h->M_all * 4, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(base + off[3], S.gp0.data(), S.gp0.size() * 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(base + off[3], S.grow.data(), S.grow.size() * 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(base + off[8], S.drow.data(), (size_t)h->M_all * 4, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(base + off[4], S.gnseg.data(), S.gnseg.size() * 4, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(base + off[5], S.gbase.data(), S.gbase.size() * 8, hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -724,7 +746,7 @@ static int mfma_upload(mudiff_ctx* h, MfmaSched& S, char* base, hipStream_t s) {
 
 // Enqueue one MFMA apply with schedule S already uploaded at S.dev_base.
 typedef void (*mf_fn)(DevView, int, const cplx*, const int32_t*, const int32_t*, int, int32_t*,
-                      cplx*, int64_t, int, int, int, int);
+                      cplx*, int64_t, int, int, int, int, const int32_t*);
 
 #define MF_TK3(MT, TH, ZK)                                 \
   if (zk == ZK) {                                          \
@@ -750,7 +772,7 @@ static mf_fn mf_select(int mt, int th, int zk, int tk) {
 
 static int mfma_launch(mudiff_ctx* h, const MfmaSched& S, const cplx* x, cplx* y, int op,
                        const int32_t* active, hipStream_t s) {
-  size_t off[8];
+  size_t off[9];
   mfma_scratch_layout(h, S, off);
   char* base = (char*)S.dev_base;
   int32_t* head = (int32_t*)(base + off[0]);
@@ -781,13 +803,14 @@ const int TL = 4 * kt + 16 * mt - 1;
       per_cu = 1;
     const int grid = std::max(1, std::min(S.n_items, per_cu * h->n_cu));
     hipLaunchKernelGGL(fn, dim3(grid), dim3(S.c.threads), lds, s, h->dv, S.R, (const cplx*)z, active, it,
-                       S.n_items, head, part, S.blk, S.npad, kt, S.c.RP, S.c.CT);
+                       S.n_items, head, part, S.blk, S.npad, kt, S.c.RP, S.c.CT,
+                       (const int32_t*)(base + off[3]));
     HIP_TRY(hipGetLastError());
   }
   const int64_t total = (int64_t)S.R * h->N_all;
   hipLaunchKernelGGL(k_apply_mfma_finish, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
                      h->dv, S.R, x, y, op, (const cplx*)part, S.blk, S.npad, RC,
-                     (const int32_t*)(base + off[2]), (const int32_t*)(base + off[3]),
+                     (const int32_t*)(base + off[2]), (const int32_t*)(base + off[8]),
                      (const int32_t*)(base + off[4]), (const int64_t*)(base + off[5]), active);
   HIP_TRY(hipGetLastError());
   return MUDIFF_OK;
@@ -803,7 +826,7 @@ static size_t mfma_scratch_bytes(mudiff_ctx* h, int R) {
       c.QS = qs;
       MfmaSched S;
       mfma_build(h, R, c, S);
-      size_t off[8];
+      size_t off[9];
       mx = std::max(mx, mfma_scratch_layout(h, S, off));
     }
   }

@@ -304,13 +304,14 @@ __global__ void k_apply_finish(DevView v, int R, const cplx* __restrict__ x, cpl
 //
 // Work item: a group of rp <= RP row disks of one instance (disks of equal row
 // tile count grouped together, so that the waves of a workgroup issue equal
-// numbers of MFMAs between barriers), a tile of 8 CT
-// right-hand sides and a segment [q0, q1) of its column disks.  Wave w of the
-// workgroup computes row w / CT and right-hand-side sub-tile w % CT.  Per
-// column disk q the input panel Z^q = sqrt(a_q) J_n(k a_q) x^q_n and the symbol
-// rows of the item's row disks are staged in LDS once for all waves; the next
-// disk's values are gathered into registers while the current one is on the
-// matrix cores.  The workgroups are persistent: each takes items from a queue
+// numbers of MFMAs between barriers), a tile of 8 CT right-hand sides and a
+// segment [q0, q1) of its column disks.  Wave w of the workgroup computes row
+// w / CT and right-hand-side sub-tile w % CT.  The input panel
+// Z^q = sqrt(a_q) J_n(k a_q) x^q_n is formed once per apply for all columns
+// (k_apply_mfma_scale); per column disk q its panel and the symbol rows of the
+// item's row disks are staged in LDS once for all waves, and the next disk's
+// values are gathered into registers while the current one is on the matrix
+// cores.  The workgroups are persistent: each takes items from a queue
 // (one atomic counter, items sorted by decreasing cost), so instances of very
 // different sizes share one launch and the launch ends evenly.  Each item's
 // sums go to its own partial block; k_apply_mfma_finish adds the segments of

@@ -24,16 +24,18 @@ constexpr int NF_RC = 4;
 // number of terms by range: the k-th term is prod_{j<=k} (4 nu^2 - (2j-1)^2) /
 // (8 j x) times the first, below 3e-17 at x = 25 for k = 18, at x = 50 for
 // k = 12 and at x = 100 for k = 9 (nu = 0, 1).  Same phase handling as the
-// table code: e^{ix} from sincos of the exact argument.
+// table code: e^{ix} from sincos of the exact argument.  ix = 1 / x; the
+// per-term factors (4 nu^2 - (2j-1)^2) / (8 j) are compile-time constants, so
+// a term costs multiplications only.
 template <int K>
-__device__ __forceinline__ void hankel01_series(double x, cplx* s0, cplx* s1) {
-  const double ix = 1.0 / (8.0 * x);
+__device__ __forceinline__ void hankel01_series(double ixx, cplx* s0, cplx* s1) {
   cplx t0 = cmk(1.0, 0.0), t1 = cmk(1.0, 0.0);
   cplx a0 = t0, a1 = t1;
 #pragma unroll
   for (int kk = 1; kk <= K; ++kk) {
     const double q = (2.0 * kk - 1.0) * (2.0 * kk - 1.0);
-    const double f0 = -q * ix / kk, f1 = (4.0 - q) * ix / kk;
+    constexpr double e8 = 0.125;
+    const double f0 = (-q * e8 / kk) * ixx, f1 = ((4.0 - q) * e8 / kk) * ixx;
     t0 = cmk(-t0.y * f0, t0.x * f0);  // * i * f
     t1 = cmk(-t1.y * f1, t1.x * f1);
     a0 = cadd(a0, t0);
@@ -49,13 +51,14 @@ __device__ __forceinline__ void hankel01_near(double x, cplx* H0, cplx* H1) {
     return;
   }
   cplx s0, s1;
-  if (x >= 100.0) hankel01_series<10>(x, &s0, &s1);
-  else if (x >= 50.0) hankel01_series<13>(x, &s0, &s1);
-  else hankel01_series<19>(x, &s0, &s1);
+  const double ixx = 1.0 / x;
+  if (x >= 100.0) hankel01_series<10>(ixx, &s0, &s1);
+  else if (x >= 50.0) hankel01_series<13>(ixx, &s0, &s1);
+  else hankel01_series<19>(ixx, &s0, &s1);
   const double r2 = 0.70710678118654752440;
   double sn, cs;
   sincos(x, &sn, &cs);
-  const double amp = sqrt(0.63661977236758134308 / x);  // sqrt(2 / (pi x))
+  const double amp = sqrt(0.63661977236758134308 * ixx);  // sqrt(2 / (pi x))
   const cplx e = cmk(amp * cs, amp * sn);
   *H0 = cmul(cmul(e, cmk(r2, -r2)), s0);   // e^{-i pi/4}
   *H1 = cmul(cmul(e, cmk(-r2, -r2)), s1);  // e^{-3 i pi/4}
@@ -102,10 +105,12 @@ __global__ __launch_bounds__(NF_THREADS) void k_nearfield(DevView v, int R, cons
       continue;
     }
     const double r = sqrt(r2);
+    const double ir = 1.0 / r;
     const double xx = k * r;
+    const double tox = 2.0 / xx;  // the recurrence factor 2 (m - 1) / x is (m - 1) tox
     cplx H0, H1;
     hankel01_near(xx, &H0, &H1);
-    const cplx e1 = cmk(dx / r, dy / r);  // e^{i theta_p}
+    const cplx e1 = cmk(dx * ir, dy * ir);  // e^{i theta_p}
     const cplx* c0 = cf + Np * NF_RC;     // mode 0
 #pragma unroll
     for (int c = 0; c < NF_RC; ++c)
@@ -113,7 +118,7 @@ __global__ __launch_bounds__(NF_THREADS) void k_nearfield(DevView v, int R, cons
     cplx Hm1 = H0, Hm = H1, em = e1;
     for (int m = 1; m <= Np; ++m) {
       if (m >= 2) {
-        const cplx Hn = csub(cscale(Hm, 2.0 * (m - 1) / xx), Hm1);
+        const cplx Hn = csub(cscale(Hm, (m - 1) * tox), Hm1);
         Hm1 = Hm;
         Hm = Hn;
         em = cmul(em, e1);

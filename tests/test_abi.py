@@ -143,3 +143,4 @@ def test_set_operator_validation(lib):
     assert lib.mudiff_set_penetrable(None, k, None, w, 4096, None) == 1
     assert lib.mudiff_interior_field(None, 1, w, w, 0, 1, w, w, w, 4096, None) == 1
     assert lib.mudiff_interior_workspace_size(None, 1) == 0
+    assert lib.mudiff_rhs_point(None, 1, w, w, 0, None) == 1

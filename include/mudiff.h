@@ -69,14 +69,16 @@ typedef enum {
 /* matvec operators */
 enum {
   MUDIFF_OP_L = 0,      /* y = L x                 (sec. 4.2, truncated as in sec. 5)        */
-  MUDIFF_OP_A = 1       /* y = D^{-1} L x = x + K x, D = diag(L^{pp}) (sec. 5 preconditioner) */
+  MUDIFF_OP_A = 1,      /* y = D^{-1} L x = x + K x, D = diag(L^{pp}) (sec. 5 preconditioner) */
+  MUDIFF_OP_LT = 2      /* y = L^T x (plain transpose) = P L P x, P: m -> -m in every disk   */
 };
 
 /* mudiff_gmres flags */
 enum {
   MUDIFF_X0 = 1,        /* rho holds the initial guess on entry (else x0 = 0)          */
   MUDIFF_GRAPH = 2,     /* replay each restart cycle as one captured HIP graph          */
-  MUDIFF_POINT_SOURCE = 4 /* beta holds point-source positions [B][R][2] (Prop. 5)   */
+  MUDIFF_POINT_SOURCE = 4, /* beta holds point-source positions [B][R][2] (Prop. 5)  */
+  MUDIFF_NO_PRECOND = 8  /* GMRES on L rho = -U itself (no single-scattering preconditioner) */
 };
 
 /* Largest accepted truncation order N_p and GMRES restart length. */
@@ -132,7 +134,8 @@ size_t mudiff_matvec_workspace_size(mudiff_t h, int R);
 
 /* y = op(x) for R right-hand sides per instance (sec. 4.2 / sec. 5).
  *   x, y       device complex128 [B][R][N_b], distinct buffers
- *   op         MUDIFF_OP_L or MUDIFF_OP_A
+ *   op         MUDIFF_OP_L, MUDIFF_OP_A or MUDIFF_OP_LT (the single layer only:
+ *              MUDIFF_ERR_INVALID after mudiff_set_operator / mudiff_set_penetrable)
  *   workspace  device scratch of mudiff_matvec_workspace_size(h, R) bytes; it
  *              must be zero-filled before its first use and every call leaves
  *              it ready for the next one (its counters return to zero), so
@@ -268,7 +271,8 @@ int mudiff_interior_field(mudiff_t h, int R, const void* rho, const double* inc,
 
 size_t mudiff_gmres_workspace_size(mudiff_t h, int R, int restart, int flags);
 
-/* Restarted GMRES(restart) on A x = f, A = D^{-1} L, f = -D^{-1} U (sec. 5),
+/* Restarted GMRES(restart) on A x = f, A = D^{-1} L, f = -D^{-1} U (sec. 5), or with
+ * MUDIFF_NO_PRECOND on L x = -U itself (after mudiff_set_operator: op x = b),
  * one independent Krylov space per (instance, right-hand side) column, all
  * columns sharing every operator application (lockstep batching).
  *   beta       device [B][R] incidence angles, or with MUDIFF_POINT_SOURCE
@@ -282,7 +286,8 @@ size_t mudiff_gmres_workspace_size(mudiff_t h, int R, int restart, int flags);
  *              iterations (operator applications in the Arnoldi process)
  *   flag       device int32 [B][R]: 0 converged (relres <= tol), 1 maxit
  *              reached, 2 breakdown without convergence or a non-finite value
- *   relres     device double [B][R]: true ||f - A x|| / ||f|| at exit
+ *   relres     device double [B][R]: true ||f - A x|| / ||f|| at exit (A = L, f = -U
+ *              with MUDIFF_NO_PRECOND)
  *   iters      device int32 [B][R]: inner iterations performed
  *   resvec     device double [B][R][maxit+1] Arnoldi residual estimates
  *              |g_{j+1}| / ||f|| (entry 0 = initial), or NULL

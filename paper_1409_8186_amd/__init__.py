@@ -17,7 +17,7 @@ the module functions tro, tro_eigh and herglotz.
 Importing the package does not load the library; ``Problem`` loads it and
 raises if it was not built (``python -m paper_1409_8186_amd.build``).
 """
-from ._lib import GRAPH, OP_A, OP_L, POINT_SOURCE, X0, MudiffError  # noqa: F401
+from ._lib import GRAPH, NO_PRECOND, OP_A, OP_L, OP_LT, POINT_SOURCE, X0, MudiffError  # noqa: F401
 
 
 def __getattr__(name):

@@ -55,8 +55,8 @@ SIGNATURES = {
 }
 
 STATUS = {0: "OK", 1: "INVALID", 2: "OVERLAP", 3: "NOMEM", 4: "DEVICE", 5: "NOT_CONVERGED"}
-OP_L, OP_A = 0, 1
-X0, GRAPH, POINT_SOURCE = 1, 2, 4
+OP_L, OP_A, OP_LT = 0, 1, 2
+X0, GRAPH, POINT_SOURCE, NO_PRECOND = 1, 2, 4, 8
 PROBE_FP64_FMA, PROBE_FP64_MFMA, PROBE_COPY = 0, 1, 2
 
 

@@ -187,11 +187,12 @@ class Problem:
 
     def gmres(self, betas=None, rhs=None, R: int | None = None, restart: int = 50,
               tol: float = 1e-8, maxit: int = 20000, x0=None, graph: bool = False,
-              want_resvec: bool = False, workspace=None, sources=None):
+              want_resvec: bool = False, workspace=None, sources=None, precond: bool = True):
         """Solves L rho = -U for plane waves (betas [B, R]), point sources
-        (sources [B, R, 2]) or a given U (rhs).  Returns (rho, flag, relres,
+        (sources [B, R, 2]) or a given U (rhs), with the single-scattering
+        preconditioner unless precond=False.  Returns (rho, flag, relres,
         iters, resvec)."""
-        flags = 0
+        flags = 0 if precond else L.NO_PRECOND
         bt = None
         if sources is not None:
             bt = self._sources(sources)

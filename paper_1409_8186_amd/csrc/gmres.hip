@@ -38,6 +38,7 @@ enum { ST_RUN = 0, ST_CONV = 1, ST_BREAK = 2, ST_MAXIT = 3 };
 
 struct GState {
   int C, R, m, maxit;
+  int op;                   // MUDIFF_OP_A (preconditioned) or MUDIFF_OP_L
   double tol;
   int64_t NT;               // complex entries of one multivector
   cplx* V;                  // [(m+1)][NT]
@@ -406,7 +407,7 @@ __global__ __launch_bounds__(GS_THREADS) void k_dg_dots(GState s, int j, Pending
     if (has_w) {
       cplx wv;
       if (FIN) {
-        wv = finalize(pa.v, MUDIFF_OP_A, i0 + rr, uv,
+        wv = finalize(pa.v, s.op, i0 + rr, uv,
                       lane_chunk_sum(pa.v, pr, pa.nchunk, pa.partoff, b, i0 + rr));
         if (blockIdx.y == 0) w[rr] = wv;
       } else {
@@ -833,9 +834,10 @@ __global__ void k_zero_c(cplx* p, int64_t n) {
   if (g < n) p[g] = cmk(0.0, 0.0);
 }
 
-// f = scale * src / Ldiag  (general right-hand side: f = -D^{-1} U)
+// f = scale * src / Ldiag  (general right-hand side: f = -D^{-1} U), or
+// without the preconditioner (div = 0) f = scale * src
 __global__ void k_precond_rhs(DevView v, int R, const cplx* __restrict__ src, cplx* __restrict__ f,
-                              double scale) {
+                              double scale, int div) {
   const int64_t total = (int64_t)R * v.N_all;
   int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= total) return;
@@ -847,7 +849,7 @@ __global__ void k_precond_rhs(DevView v, int R, const cplx* __restrict__ src, cp
   const int64_t Nb = v.imode[lo + 1] - v.imode[lo];
   const int64_t rem = g - (int64_t)R * v.imode[lo];
   const int64_t i = v.imode[lo] + rem % Nb;
-  f[g] = cscale(cdiv(src[g], v.op_diag ? v.op_diag[i] : v.Ldiag[i]), scale);
+  f[g] = div ? cscale(cdiv(src[g], v.op_diag ? v.op_diag[i] : v.Ldiag[i]), scale) : cscale(src[g], scale);
 }
 
 // ------------------------------------------------------------------ host driver
@@ -988,7 +990,7 @@ static int enqueue_cycle(GmresRun& G, int check_every, bool host_checks) {
   for (int j = 0; j < s.m; ++j) {
     bool pending = false;
     int rc = apply_operator_split(G.h, s.R, s.V + (int64_t)j * s.NT,
-                                  s.V + (int64_t)(j + 1) * s.NT, MUDIFF_OP_A, G.apply_part,
+                                  s.V + (int64_t)(j + 1) * s.NT, s.op, G.apply_part,
                                   G.apply_cnt, s.inner, G.st, &pending);
     if (rc != MUDIFF_OK) return rc;
     // Gram-Schmidt over all chunks, or the running columns' chunks only
@@ -1044,7 +1046,7 @@ static int enqueue_cycle(GmresRun& G, int check_every, bool host_checks) {
   hipLaunchKernelGGL(k_cycle_solve, dim3(s.C), dim3(64), 0, G.st, s);
   hipLaunchKernelGGL(k_update_x, dim3(eb), dim3(256), 0, G.st, s, s.NT, G.d_rowcol);
   HIP_TRY(hipGetLastError());
-  int rc = apply_operator(G.h, s.R, s.x, s.V, MUDIFF_OP_A, G.apply_part, G.apply_cnt, s.run, G.st);
+  int rc = apply_operator(G.h, s.R, s.x, s.V, s.op, G.apply_part, G.apply_cnt, s.run, G.st);
   if (rc != MUDIFF_OK) return rc;
   hipLaunchKernelGGL(k_resid, dim3((unsigned)G.L.n_chunks), dim3(GS_THREADS), 0, G.st, s, 2, 1,
                      (const cplx*)nullptr);
@@ -1081,6 +1083,7 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
   s.C = h->B * R;
   s.R = R;
   s.m = restart;
+  s.op = (flags & MUDIFF_NO_PRECOND) ? MUDIFF_OP_L : MUDIFF_OP_A;
   s.maxit = maxit;
   s.tol = tol;
   s.NT = L.NT;
@@ -1156,11 +1159,12 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
   if ((rc = launch_fill_zero(s.n_inner, 4, st)) != MUDIFF_OK) return rc;
   // right-hand side f
   if (beta) {
-    if ((rc = launch_rhs(h, R, beta, (cplx*)s.f, 1, (flags & MUDIFF_POINT_SOURCE) ? 1 : 0, st)) != MUDIFF_OK)
+    if ((rc = launch_rhs(h, R, beta, (cplx*)s.f, s.op == MUDIFF_OP_A ? 1 : 2,
+                         (flags & MUDIFF_POINT_SOURCE) ? 1 : 0, st)) != MUDIFF_OK)
       return rc;
   } else {
     hipLaunchKernelGGL(k_precond_rhs, dim3(eb), dim3(256), 0, st, h->dv, R, (const cplx*)rhs,
-                       (cplx*)s.f, -1.0);
+                       (cplx*)s.f, -1.0, s.op == MUDIFF_OP_A ? 1 : 0);
     HIP_TRY(hipGetLastError());
   }
   if (resvec) {
@@ -1173,7 +1177,7 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
   HIP_TRY(hipGetLastError());
   // initial residual V0 = f - A x0 (or f with x0 = 0)
   if (flags & MUDIFF_X0) {
-    rc = apply_operator(h, R, s.x, s.V, MUDIFF_OP_A, G.apply_part, G.apply_cnt, s.run, st);
+    rc = apply_operator(h, R, s.x, s.V, s.op, G.apply_part, G.apply_cnt, s.run, st);
     if (rc != MUDIFF_OK) return rc;
     hipLaunchKernelGGL(k_resid, dim3((unsigned)L.n_chunks), dim3(GS_THREADS), 0, st, s, 2, 1,
                        (const cplx*)nullptr);

@@ -1188,9 +1188,38 @@ int apply_operator(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, cplx* p
   return MUDIFF_OK;
 }
 
+namespace {
+// Mode flip P (x^p_m -> x^p_{-m} in every disk) of R columns: out = P in, or
+// in place when out == in (one thread per pair m > 0 then).  L^T = P L P.
+__global__ void k_flip_modes(DevView v, int R, const cplx* in, cplx* out) {
+  const int64_t total = (int64_t)R * v.N_all;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  int lo = 0, hi = v.B;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if ((int64_t)R * v.imode[mid] <= g) lo = mid; else hi = mid;
+  }
+  const int64_t Nb = v.imode[lo + 1] - v.imode[lo];
+  const int64_t rem = g - (int64_t)R * v.imode[lo];
+  const int64_t il = rem - (rem / Nb) * Nb;
+  const int p = v.udisk[v.imode[lo] + il];
+  const int64_t m = il - v.moff[p] - v.N[p];
+  const int64_t g2 = g - 2 * m;  // mode -m of the same disk and column
+  if (in != out) {
+    out[g] = in[g2];
+  } else if (m > 0) {
+    const cplx a = out[g];
+    out[g] = out[g2];
+    out[g2] = a;
+  }
+}
+}  // namespace
+
 extern "C" size_t mudiff_matvec_workspace_size(mudiff_t h, int R) {
   if (!h || R < 1) return 0;
-  return apply_scratch_bytes(h, R);
+  // apply scratch, then room for the flipped input of MUDIFF_OP_LT
+  return apply_scratch_bytes(h, R) + align256((size_t)R * h->N_all * 16);
 }
 
 extern "C" int mudiff_matvec(mudiff_t h, int R, const void* x, void* y, int op, void* workspace,
@@ -1198,21 +1227,41 @@ extern "C" int mudiff_matvec(mudiff_t h, int R, const void* x, void* y, int op, 
   if (!h || !x || !y) return fail(MUDIFF_ERR_INVALID, "NULL argument");
   if (R < 1) return fail(MUDIFF_ERR_INVALID, "R < 1");
   if (x == y) return fail(MUDIFF_ERR_INVALID, "x and y must be distinct buffers");
-  if (op != MUDIFF_OP_L && op != MUDIFF_OP_A) return fail(MUDIFF_ERR_INVALID, "unknown op");
-  size_t need = apply_scratch_bytes(h, R);
+  if (op != MUDIFF_OP_L && op != MUDIFF_OP_A && op != MUDIFF_OP_LT)
+    return fail(MUDIFF_ERR_INVALID, "unknown op");
+  if (op == MUDIFF_OP_LT && h->dv.op_col)
+    return fail(MUDIFF_ERR_INVALID, "MUDIFF_OP_LT applies the single layer only (reset the operator first)");
+  const size_t need = apply_scratch_bytes(h, R);
+  const size_t need_all = mudiff_matvec_workspace_size(h, R);
   if (!workspace) return fail(MUDIFF_ERR_INVALID, "workspace is NULL");
-  if (ws_bytes < need) return fail(MUDIFF_ERR_NOMEM, "matvec workspace needs " + std::to_string(need) + " bytes");
+  if (ws_bytes < (op == MUDIFF_OP_LT ? need_all : need))
+    return fail(MUDIFF_ERR_NOMEM, "matvec workspace needs " + std::to_string(need_all) + " bytes");
   apply_forget_upload(h);
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)workspace;
-  if (use_mfma(h, R)) {
-    int st = mfma_prepare(h, R, (const cplx*)x, (cplx*)y, w, s);  // autotunes on first use of R
-    if (st != MUDIFF_OK) return st;
-    return mfma_launch(h, h->mfma_sched, (const cplx*)x, (cplx*)y, op, nullptr, s);
+  const cplx* xin = (const cplx*)x;
+  const int64_t tot = (int64_t)R * h->N_all;
+  const unsigned fb = (unsigned)((tot + 255) / 256);
+  if (op == MUDIFF_OP_LT) {  // L^T x = P L (P x)
+    cplx* xf = (cplx*)(w + need);
+    hipLaunchKernelGGL(k_flip_modes, dim3(fb), dim3(256), 0, s, h->dv, R, xin, xf);
+    HIP_TRY(hipGetLastError());
+    xin = xf;
   }
-  size_t part_bytes = need - align256((size_t)R * h->M_all * 4);
-  int32_t* counters = (int32_t*)(w + part_bytes);  // zero on first use, left zero
-  return apply_operator(h, R, (const cplx*)x, (cplx*)y, op, (cplx*)w, counters, nullptr, s);
+  const int aop = op == MUDIFF_OP_LT ? MUDIFF_OP_L : op;
+  int rc;
+  if (use_mfma(h, R)) {
+    rc = mfma_prepare(h, R, xin, (cplx*)y, w, s);  // autotunes on first use of R
+    if (rc == MUDIFF_OK) rc = mfma_launch(h, h->mfma_sched, xin, (cplx*)y, aop, nullptr, s);
+  } else {
+    size_t part_bytes = need - align256((size_t)R * h->M_all * 4);
+    int32_t* counters = (int32_t*)(w + part_bytes);  // zero on first use, left zero
+    rc = apply_operator(h, R, xin, (cplx*)y, aop, (cplx*)w, counters, nullptr, s);
+  }
+  if (rc != MUDIFF_OK || op != MUDIFF_OP_LT) return rc;
+  hipLaunchKernelGGL(k_flip_modes, dim3(fb), dim3(256), 0, s, h->dv, R, (const cplx*)y, (cplx*)y);
+  HIP_TRY(hipGetLastError());
+  return MUDIFF_OK;
 }
 
 extern "C" int mudiff_apply_config(mudiff_t h, int R, int* kind, int* ct, int* rp, int* qs,

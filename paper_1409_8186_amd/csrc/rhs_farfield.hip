@@ -38,7 +38,8 @@ __device__ cplx point_factor(const DevView& v, int p, int m, const double* src) 
 }
 
 // one thread per unknown of every (instance, rhs) column; `point`: beta holds
-// source positions [B][R][2]
+// source positions [B][R][2]; precond 0: U (or an operator's b), 1: the
+// preconditioned b, 2: b (-U for the single layer)
 __global__ void k_rhs(DevView v, int R, const double* __restrict__ beta, cplx* __restrict__ out,
                       int precond, int point) {
   const int64_t total = (int64_t)R * v.N_all;
@@ -72,7 +73,11 @@ __global__ void k_rhs(DevView v, int R, const double* __restrict__ beta, cplx* _
   }
   const double s2pi = sqrt(2.0 * PI_D);
   if (v.op_rhs) {  // operator set by mudiff_set_operator: w_U U + w_dU dU (over its diagonal)
-    out[g] = cmul(e, precond ? v.op_rhsp[i] : v.op_rhs[i]);
+    out[g] = cmul(e, precond == 1 ? v.op_rhsp[i] : v.op_rhs[i]);
+    return;
+  }
+  if (precond == 2) {  // the unpreconditioned system's right-hand side -U
+    out[g] = cscale(e, -s2pi * v.sJ[i]);
     return;
   }
   if (precond) {

@@ -145,3 +145,24 @@ def test_point_source_penetrable_graph_replay_matches_eager(P):
         r_g, f_g, _, it_g, _ = pr.gmres(sources=[s], restart=20, tol=1e-12, maxit=400, graph=True)
         assert np.all(f_e.cpu().numpy() == 0)
         assert torch.equal(it_e, it_g) and torch.equal(r_e, r_g)
+
+
+def test_mixed_reciprocity_on_the_gpu(P):
+    """GPU only: the far field at theta of the point-source solve equals
+    e^{i pi/4} / sqrt(8 pi k) times the plane-wave (direction -theta) scattered
+    field at the source, for sound-soft and penetrable disks."""
+    cl = synth.Cluster(*synth.random_disks(np.random.default_rng(132), 12, 0.3, 0.7, 0.0, 8.0, 0.3),
+                       np.full(12, 10, np.int32), 3.0)
+    src = np.array([[-1.0, 4.0], [9.5, 2.0], [4.0, 10.0]])
+    th = np.array([0.2, 2.1, 3.9, 5.5])
+    gam = np.exp(0.25j * np.pi) / np.sqrt(8 * np.pi * cl.k)
+    pr = P.from_cluster(cl)
+    for pen_on in (False, True):
+        if pen_on:
+            pr.set_penetrable(1.7 * cl.k, 1.4)
+        r_ps, f1, _, _, _ = pr.gmres(sources=[src], restart=40, tol=1e-13, maxit=3000)
+        a_ps = pr.farfield(r_ps, th, R=3).cpu().numpy()                       # [source, theta]
+        r_pw, f2, _, _, _ = pr.gmres(betas=[th + np.pi], restart=40, tol=1e-13, maxit=3000)
+        u_pw = pr.nearfield(r_pw, src, R=4).cpu().numpy()                      # [theta, source]
+        assert np.all(f1.cpu().numpy() == 0) and np.all(f2.cpu().numpy() == 0)
+        assert rel(a_ps, gam * u_pw.T) < 1e-10

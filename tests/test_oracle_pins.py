@@ -831,3 +831,32 @@ def test_point_source_reciprocity():
     v12 = nearfield.potential(cl.centers, cl.radii, cl.n_modes, cl.k, rp[0], s2[None, :])[0]
     v21 = nearfield.potential(cl.centers, cl.radii, cl.n_modes, cl.k, rp[1], s1[None, :])[0]
     assert abs(v12 - v21) < 1e-11 * abs(v12)
+
+
+def test_mixed_reciprocity_point_source_and_plane_wave():
+    """The far field in direction theta of the wave scattered from a point
+    source at s equals e^{i pi/4} / sqrt(8 pi k) (the far-field factor of
+    G(., s) = (i/4) H_0) times the scattered field at s of the plane wave
+    travelling in direction -theta: ties Prop. 5 to Prop. 4, the near field and
+    the far field of sec. 4.4 (sound-soft and penetrable)."""
+    from oracle import farfield, nearfield, penetrable as pen, pointsource as ps
+    cl = synth.small_random(131, 5, 0.3, 0.8, 6.0, 0.3, 3.3, 8)
+    src = np.array([[-1.5, 2.0], [8.0, 1.0]])
+    th = np.array([0.3, 1.7, 4.0])
+    gam = np.exp(0.25j * np.pi) / np.sqrt(8 * np.pi * cl.k)
+    L = operator.efie_matrix(cl.centers, cl.radii, cl.n_modes, cl.k)
+    G = farfield.farfield_rows(cl.centers, cl.radii, cl.n_modes, cl.k, th)
+    U = ps.point_source(cl.centers, cl.radii, cl.n_modes, cl.k, src)
+    a_ps = np.linalg.solve(L, -U.T).T @ G.T                                  # [source, theta]
+    Up = rhs.planewave(cl.centers, cl.radii, cl.n_modes, cl.k, th + np.pi)
+    rp = np.linalg.solve(L, -Up.T).T
+    u_pw = np.stack([nearfield.potential(cl.centers, cl.radii, cl.n_modes, cl.k, rp[j], src)
+                     for j in range(len(th))], 1)
+    assert rel(a_ps, gam * u_pw) < 1e-12
+    ki, mu = np.linspace(0.6, 2.0, 5) * cl.k, np.linspace(0.8, 1.6, 5)
+    dU = ps.point_source_dn(cl.centers, cl.radii, cl.n_modes, cl.k, src)
+    rps, _ = pen.solve_coefficients(cl.centers, cl.radii, cl.n_modes, cl.k, ki, U, dU, mu)
+    rpw, _ = pen.solve(cl.centers, cl.radii, cl.n_modes, cl.k, ki, th + np.pi, mu=mu)
+    v_pw = np.stack([nearfield.potential(cl.centers, cl.radii, cl.n_modes, cl.k, rpw[j], src)
+                     for j in range(len(th))], 1)
+    assert rel(rps @ G.T, gam * v_pw) < 1e-11

@@ -116,9 +116,9 @@ extern "C" int mudiff_rhs_point(mudiff_t h, int R, const double* src, void* out,
 // groups split the disks of the instance (thread t: angle t % FF_TH of the
 // tile, disks g, g + FF_DG, ... with g = t / FF_TH), then the group sums are
 // added in LDS in a fixed order.  Small tiles and many groups keep a
-// one-column call (720 angles x 400 disks) spread over the chip.
-#define FF_TH 16
-#define FF_DG 64
+// one-column call (720 angles x 400 disks) spread over the chip; instances of
+// few disks take wide tiles and few groups (16 x 64 or 64 x 16 threads).
+template <int FF_TH, int FF_DG>
 __global__ __launch_bounds__(FF_TH* FF_DG) void k_farfield(DevView v, int R,
                                                            const cplx* __restrict__ rho,
                                                            int n_theta,
@@ -179,9 +179,17 @@ extern "C" int mudiff_farfield(mudiff_t h, int R, const void* rho, int n_theta, 
   if (!h || !rho || !theta || !a_out) return fail(MUDIFF_ERR_INVALID, "NULL argument");
   if (R < 1 || n_theta < 1) return fail(MUDIFF_ERR_INVALID, "R < 1 or n_theta < 1");
   if ((int64_t)h->B * R > 65535) return fail(MUDIFF_ERR_INVALID, "too many instance x RHS columns");
-  dim3 grid((n_theta + FF_TH - 1) / FF_TH, h->B * R);
-  hipLaunchKernelGGL(k_farfield, grid, dim3(FF_TH * FF_DG), 0, (hipStream_t)stream, h->dv, R,
-                     (const cplx*)rho, n_theta, theta, (cplx*)a_out);
+  int64_t mmax = 0;  // disks of the largest instance
+  for (int b = 0; b < h->B; ++b) mmax = std::max<int64_t>(mmax, h->idisk[b + 1] - h->idisk[b]);
+  if (mmax >= 64) {
+    dim3 grid((n_theta + 15) / 16, h->B * R);
+    hipLaunchKernelGGL((k_farfield<16, 64>), grid, dim3(1024), 0, (hipStream_t)stream, h->dv, R,
+                       (const cplx*)rho, n_theta, theta, (cplx*)a_out);
+  } else {
+    dim3 grid((n_theta + 63) / 64, h->B * R);
+    hipLaunchKernelGGL((k_farfield<64, 16>), grid, dim3(1024), 0, (hipStream_t)stream, h->dv, R,
+                       (const cplx*)rho, n_theta, theta, (cplx*)a_out);
+  }
   HIP_TRY(hipGetLastError());
   return MUDIFF_OK;
 }

@@ -92,7 +92,8 @@ __device__ void block_sum4(double (&v)[4], double* sred) {
 // |gamma| <= eps |F|_F^2, below the rounding level of the entries of T.  The
 // four rows are loaded into registers at once (EPT elements per thread; EPT = 0:
 // rows longer than 8 * JAC_THREADS, streamed twice).  n_rot counts the
-// rotations of the sweep.
+// rotations of the sweep.  These rounds serve rows longer than 1024 entries;
+// shorter ones take the block rounds below.
 template <int EPT>
 __global__ __launch_bounds__(JAC_THREADS) void k_jacobi_round(int n, int m, int np, int r,
                                                               cplx* __restrict__ X,
@@ -165,6 +166,160 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi_round(int n, int m, int 
     }
   }
   if (threadIdx.x == 0) atomicAdd(n_rot, 1);
+}
+
+// Block rounds, for rows of X and Vt of at most EPT * NT entries (NT threads
+// per workgroup).  The columns are grouped in nb = ceil(n / 4) blocks of JB = 4,
+// block P holding columns P, P + nb, P + 2 nb, P + 3 nb (neighbouring columns of
+// a far-field matrix are nearly parallel; spread over different blocks they
+// take fewer sweeps), and a round pairs the blocks (circle method over nb
+// rounded up to even, nb').  The workgroup of blocks (P, Q) rotates the 16
+// pairs (p_i, q_j) in four steps of the four disjoint pairs
+// (p_i, q_{(i+s) mod 4}); in the first round of a sweep it first rotates the 6
+// pairs inside each of its two blocks, in three steps.  Every pair of columns
+// is rotated once per sweep, as in the rounds above, in nb' - 1 launches
+// instead of n' - 1.  The 8 columns of F and of V stay in registers for the
+// round; the 16 sums of a step (alpha, beta, gamma of each pair) share one block
+// reduction: a reduce-scatter across the wave (lane swaps and DPP) leaves sum c
+// on lanes 4c..4c+3, then the waves' partial sums are added from LDS in a fixed
+// order by lane k (mod 4) for pair k, which also computes that pair's rotation,
+// handed to the wave by readlane: one copy of the rotation arithmetic per step.
+// Slots past column n - 1 and those of the padding block read as zero and are
+// never rotated or stored.  Blocks of 8 (63 launches a sweep at n = 512) were
+// slower: they put the sweep's arithmetic on half as many compute units.
+
+// The value of x on lane l, for the whole wave.
+__device__ __forceinline__ double wave_bcast(double x, int l) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __hiloint2double(hi, lo);
+}
+
+constexpr int JB = 4;
+
+template <int EPT, int NT>
+__global__ __launch_bounds__(NT) void k_jacobi_block_round(int n, int m, int nbp, int r,
+                                                            cplx* __restrict__ X,
+                                                            cplx* __restrict__ Vt, double tol,
+                                                            const double* __restrict__ fro2,
+                                                            int32_t* __restrict__ n_rot) {
+  constexpr int NW = NT / 64, NS = 4 * JB, LPV = 64 / NS;
+  __shared__ double sred[2][NS][NW + 1];  // padded: the lanes of different pairs hit different banks
+  int P, Q;
+  round_pair(r, blockIdx.x, nbp, &P, &Q);
+  const int nb = (n + JB - 1) / JB;
+  if (Q >= nb && r > 0) return;  // the padding block: nothing inside a block left to do
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const double eps_f = 2.220446049250313e-16 * fro2[0];
+  int col[2 * JB];  // column of each slot, -1 for none
+  cplx f[2 * JB][EPT], v[2 * JB][EPT];
+#pragma unroll
+  for (int j = 0; j < 2 * JB; ++j) {
+    const int B = j < JB ? P : Q;
+    const int c = B + nb * (j & (JB - 1));
+    col[j] = (B < nb && c < n) ? c : -1;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int i = threadIdx.x + e * NT;
+      f[j][e] = (col[j] >= 0 && i < m) ? X[(int64_t)c * m + i] : cmk(0.0, 0.0);
+      v[j][e] = (col[j] >= 0 && i < n) ? Vt[(int64_t)c * n + i] : cmk(0.0, 0.0);
+    }
+  }
+  int buf = 0, cnt = 0;
+  unsigned touched = 0u;
+  // One step: the JB disjoint pairs (a[k], b[k]).
+  auto step = [&](const int (&a)[JB], const int (&b)[JB]) {
+    double s[NS];
+#pragma unroll
+    for (int k = 0; k < JB; ++k) {
+      double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const cplx x = f[a[k]][e], y = f[b[k]][e];
+        al += cabs2(x);
+        be += cabs2(y);
+        gr = fma(x.x, y.x, fma(x.y, y.y, gr));
+        gi = fma(x.x, y.y, fma(-x.y, y.x, gi));
+      }
+      s[4 * k] = al;
+      s[4 * k + 1] = be;
+      s[4 * k + 2] = gr;
+      s[4 * k + 3] = gi;
+    }
+    lane_reduce_scatter<NS>(s, lane);  // lanes LPV c .. LPV c + LPV - 1: the wave's sum c
+    if ((lane & (LPV - 1)) == 0) sred[buf][lane / LPV][wv] = s[0];
+    __syncthreads();
+    double q4[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      double u = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) u += sred[buf][4 * (lane & (JB - 1)) + c][w];
+      q4[c] = u;
+    }
+    buf ^= 1;
+    // the rotation of the rounds above, with the same correctly rounded square
+    // roots and quotients (an rsqrt form of it, a few ulp less orthogonal, took
+    // 11 sweeps instead of 8 on a 512-cell far-field matrix)
+    double cs = 1.0, snr = 0.0, sni = 0.0;
+    const double g = sqrt(q4[2] * q4[2] + q4[3] * q4[3]);
+    const bool rot = (g > tol * sqrt(q4[0] * q4[1])) && (g > eps_f);
+    if (rot) {
+      const double zeta = (q4[1] - q4[0]) / (2.0 * g);
+      const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+      cs = 1.0 / sqrt(1.0 + tt * tt);
+      snr = tt * cs * q4[2] / g;
+      sni = tt * cs * q4[3] / g;
+    }
+#pragma unroll
+    for (int k = 0; k < JB; ++k) {
+      if (!__builtin_amdgcn_readlane((int)rot, k)) continue;
+      const double c = wave_bcast(cs, k);
+      const cplx sn = cmk(wave_bcast(snr, k), wave_bcast(sni, k));
+      const cplx sc = cconj(sn);
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const cplx x = f[a[k]][e], y = f[b[k]][e];
+        f[a[k]][e] = csub(cscale(x, c), cmul(sc, y));
+        f[b[k]][e] = cadd(cmul(sn, x), cscale(y, c));
+        const cplx p = v[a[k]][e], q = v[b[k]][e];
+        v[a[k]][e] = csub(cscale(p, c), cmul(sc, q));
+        v[b[k]][e] = cadd(cmul(sn, p), cscale(q, c));
+      }
+      ++cnt;
+      touched |= (1u << a[k]) | (1u << b[k]);
+    }
+  };
+  if (r == 0) {
+    // inside the blocks: (0,1)(2,3), (0,2)(1,3), (0,3)(1,2) in P and in Q (this
+    // order took 8 sweeps on a 512-cell far-field matrix, the circle order 11)
+    step({0, 2, 4, 6}, {1, 3, 5, 7});
+    step({0, 1, 4, 5}, {2, 3, 6, 7});
+    step({0, 1, 4, 5}, {3, 2, 7, 6});
+  }
+#pragma unroll
+  for (int t = 0; t < JB; ++t) {
+    int a[JB], b[JB];
+#pragma unroll
+    for (int k = 0; k < JB; ++k) {
+      a[k] = k;
+      b[k] = JB + (k + t) % JB;
+    }
+    step(a, b);
+  }
+#pragma unroll
+  for (int j = 0; j < 2 * JB; ++j) {
+    const int c = col[j];
+    if (!((touched >> j) & 1u) || c < 0) continue;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int i = threadIdx.x + e * NT;
+      if (i < m) X[(int64_t)c * m + i] = f[j][e];
+      if (i < n) Vt[(int64_t)c * n + i] = v[j][e];
+    }
+  }
+  if (threadIdx.x == 0 && cnt > 0) atomicAdd(n_rot, cnt);
 }
 
 // Vt = I.
@@ -300,15 +455,20 @@ extern "C" int mudiff_tro_eigh(int n, int m, void* X, double* w, void* evec, int
     int rc = launch_fill_zero(n_rot, 4, s);
     if (rc != MUDIFF_OK) return rc;
     const int len = std::max(n, m);
-    for (int r = 0; r < np - 1; ++r) {
+    // rows of at most 1024 entries: blocks of 4 columns
+    const int nb = (n + 3) / 4, nbp = nb + (nb & 1);
+    for (int r = 0; len <= 1024 && r < nbp - 1; ++r) {
+      const dim3 g((unsigned)(nbp / 2));
+      if (len <= 256)
+        hipLaunchKernelGGL((k_jacobi_block_round<1, 256>), g, dim3(256), 0, s, n, m, nbp, r, Xc, Vt, tol, (const double*)fro2, n_rot);
+      else if (len <= 512)
+        hipLaunchKernelGGL((k_jacobi_block_round<2, 256>), g, dim3(256), 0, s, n, m, nbp, r, Xc, Vt, tol, (const double*)fro2, n_rot);
+      else
+        hipLaunchKernelGGL((k_jacobi_block_round<2, 512>), g, dim3(512), 0, s, n, m, nbp, r, Xc, Vt, tol, (const double*)fro2, n_rot);
+    }
+    for (int r = 0; len > 1024 && r < np - 1; ++r) {
       const dim3 g((unsigned)(np / 2)), b(JAC_THREADS);
-      if (len <= JAC_THREADS)
-        hipLaunchKernelGGL(k_jacobi_round<1>, g, b, 0, s, n, m, np, r, Xc, Vt, tol, (const double*)fro2, n_rot);
-      else if (len <= 2 * JAC_THREADS)
-        hipLaunchKernelGGL(k_jacobi_round<2>, g, b, 0, s, n, m, np, r, Xc, Vt, tol, (const double*)fro2, n_rot);
-      else if (len <= 4 * JAC_THREADS)
-        hipLaunchKernelGGL(k_jacobi_round<4>, g, b, 0, s, n, m, np, r, Xc, Vt, tol, (const double*)fro2, n_rot);
-      else if (len <= 8 * JAC_THREADS)
+      if (len <= 8 * JAC_THREADS)
         hipLaunchKernelGGL(k_jacobi_round<8>, g, b, 0, s, n, m, np, r, Xc, Vt, tol, (const double*)fro2, n_rot);
       else
         hipLaunchKernelGGL(k_jacobi_round<0>, g, b, 0, s, n, m, np, r, Xc, Vt, tol, (const double*)fro2, n_rot);

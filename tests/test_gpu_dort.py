@@ -98,6 +98,27 @@ def test_tro_eigh_single_disk_closed_form(P):
     assert np.max(np.abs(w[2 * N + 1:])) < 1e-11 * w[0]
 
 
+@pytest.mark.parametrize("n,m", [(1, 7), (18, 40), (257, 120), (300, 700), (600, 300), (40, 1500),
+                                 (24, 2100)])
+def test_tro_eigh_random_matrix(P, n, m):
+    """Eigenpairs of T = conj(X) X^T for a seeded complex Gaussian X against the
+    oracle's dense eigen-decomposition.  Rows of at most 1024 entries take
+    blocks of 4 columns, one (n = 1, 18), two (n = 257) or two per 512 threads
+    (n = 300, 600) entries per thread, with a partial last block and the padding
+    block for n = 18 and 257; longer rows take one column pair per workgroup,
+    held in registers (m = 1500) or streamed (m = 2100)."""
+    from paper_1409_8186_amd import tro_eigh
+    rng = np.random.default_rng(1000 + n)
+    Xh = rng.standard_normal((n, m)) + 1j * rng.standard_normal((n, m))
+    say("tro_eigh random: n", n, "m", m)
+    w, ev, sweeps = tro_eigh(torch.tensor(Xh, device="cuda"))
+    say("  jacobi sweeps", sweeps)
+    assert 1 <= sweeps <= 30
+    T_ref = dort.time_reversal(Xh.T)
+    w_ref, V_ref = dort.eig_desc(T_ref)
+    _check_eig(w.cpu().numpy(), ev.cpu().numpy(), w_ref, V_ref, T_ref)
+
+
 @pytest.mark.parametrize("m", [0, 2, -5])
 def test_herglotz_matches_oracle_and_jacobi_anger(P, m):
     from scipy import special as sp

@@ -837,9 +837,12 @@ static size_t mfma_scratch_bytes(mudiff_ctx* h, int R) {
 
 // Pick the tile choice for R by timing every candidate on x -> y (outputs
 // are overwritten; the inputs only need to be finite), then leave the chosen
-// schedule uploaded at `scratch`.
+// schedule uploaded at `scratch`.  Segmented candidates are skipped when no
+// instance has more disks than a segment: their schedule is the unsegmented one.
 static int mfma_autotune(mudiff_ctx* h, int R, const cplx* x, cplx* y, char* scratch,
                          hipStream_t s) {
+  int64_t mmax = 0;
+  for (int b = 0; b < h->B; ++b) mmax = std::max(mmax, h->idisk[b + 1] - h->idisk[b]);
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
@@ -847,6 +850,7 @@ static int mfma_autotune(mudiff_ctx* h, int R, const cplx* x, cplx* y, char* scr
   MfmaChoice bc = mfma_default(R);
   int rc = MUDIFF_OK;
   for (const MfmaChoice& c : mfma_candidates(R)) {
+    if (c.QS > 0 && mmax <= c.QS) continue;
     MfmaSched S;
     mfma_build(h, R, c, S);
     if ((rc = mfma_upload(h, S, scratch, s)) != MUDIFF_OK) break;

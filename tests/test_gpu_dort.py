@@ -99,14 +99,15 @@ def test_tro_eigh_single_disk_closed_form(P):
 
 
 @pytest.mark.parametrize("n,m", [(1, 7), (18, 40), (257, 120), (300, 700), (600, 300), (40, 1500),
-                                 (24, 2100)])
+                                 (24, 2100), (40, 5)])
 def test_tro_eigh_random_matrix(P, n, m):
     """Eigenpairs of T = conj(X) X^T for a seeded complex Gaussian X against the
     oracle's dense eigen-decomposition.  Rows of at most 1024 entries take
     blocks of 4 columns, one (n = 1, 18), two (n = 257) or two per 512 threads
     (n = 300, 600) entries per thread, with a partial last block and the padding
     block for n = 18 and 257; longer rows take one column pair per workgroup,
-    held in registers (m = 1500) or streamed (m = 2100)."""
+    held in registers (m = 1500) or streamed (m = 2100).  n = 40, m = 5: rank 5,
+    35 eigenvalues at the rounding level (the eps |F|^2 stopping rule)."""
     from paper_1409_8186_amd import tro_eigh
     rng = np.random.default_rng(1000 + n)
     Xh = rng.standard_normal((n, m)) + 1j * rng.standard_normal((n, m))
@@ -117,6 +118,15 @@ def test_tro_eigh_random_matrix(P, n, m):
     T_ref = dort.time_reversal(Xh.T)
     w_ref, V_ref = dort.eig_desc(T_ref)
     _check_eig(w.cpu().numpy(), ev.cpu().numpy(), w_ref, V_ref, T_ref)
+
+
+def test_tro_eigh_zero_matrix(P):
+    """F = 0: no pair is rotated, one sweep, all eigenvalues 0 and V = I."""
+    from paper_1409_8186_amd import tro_eigh
+    w, ev, sweeps = tro_eigh(torch.zeros((9, 4), dtype=torch.complex128, device="cuda"))
+    assert sweeps == 1
+    assert np.array_equal(w.cpu().numpy(), np.zeros(9))
+    assert np.array_equal(ev.cpu().numpy(), np.eye(9))
 
 
 @pytest.mark.parametrize("m", [0, 2, -5])

@@ -455,8 +455,8 @@ extern "C" int mudiff_tro_eigh(int n, int m, void* X, double* w, void* evec, int
     int rc = launch_fill_zero(n_rot, 4, s);
     if (rc != MUDIFF_OK) return rc;
     const int len = std::max(n, m);
-    // rows of at most 1024 entries: blocks of 4 columns
-    const int nb = (n + 3) / 4, nbp = nb + (nb & 1);
+    // rows of at most 1024 entries: blocks of JB columns
+    const int nb = (n + JB - 1) / JB, nbp = nb + (nb & 1);
     for (int r = 0; len <= 1024 && r < nbp - 1; ++r) {
       const dim3 g((unsigned)(nbp / 2));
       if (len <= 256)

@@ -45,13 +45,13 @@ __device__ __forceinline__ void hankel01_series(double ixx, cplx* s0, cplx* s1) 
   *s1 = a1;
 }
 
-__device__ __forceinline__ void hankel01_near(double x, cplx* H0, cplx* H1) {
+// H_0(x), H_1(x) given x and ixx = 1 / x.
+__device__ __forceinline__ void hankel01_near(double x, double ixx, cplx* H0, cplx* H1) {
   if (x < BESSEL_X_ASY) {
     hankel01(x, H0, H1);
     return;
   }
   cplx s0, s1;
-  const double ixx = 1.0 / x;
   if (x >= 100.0) hankel01_series<10>(ixx, &s0, &s1);
   else if (x >= 50.0) hankel01_series<13>(ixx, &s0, &s1);
   else hankel01_series<19>(ixx, &s0, &s1);
@@ -62,6 +62,10 @@ __device__ __forceinline__ void hankel01_near(double x, cplx* H0, cplx* H1) {
   const cplx e = cmk(amp * cs, amp * sn);
   *H0 = cmul(cmul(e, cmk(r2, -r2)), s0);   // e^{-i pi/4}
   *H1 = cmul(cmul(e, cmk(-r2, -r2)), s1);  // e^{-3 i pi/4}
+}
+
+__device__ __forceinline__ void hankel01_near(double x, cplx* H0, cplx* H1) {
+  hankel01_near(x, 1.0 / x, H0, H1);
 }
 
 __global__ __launch_bounds__(NF_THREADS) void k_nearfield(DevView v, int R, const cplx* __restrict__ rho,
@@ -77,6 +81,7 @@ __global__ __launch_bounds__(NF_THREADS) void k_nearfield(DevView v, int R, cons
   const int nr = min(NF_RC, R - r0);
   const double x1 = P < n_pts ? pts[2 * P] : 0.0, x2 = P < n_pts ? pts[2 * P + 1] : 0.0;
   const double k = v.kd[v.idisk[b]];
+  const double ik = 1.0 / k;
   const double cst = 0.62665706865775012560;  // sqrt(pi / 8): (i pi a / 2) / sqrt(2 pi a) = i sqrt(pi/8) sqrt(a)
   cplx acc[NF_RC];
 #pragma unroll
@@ -104,12 +109,13 @@ __global__ __launch_bounds__(NF_THREADS) void k_nearfield(DevView v, int R, cons
       inside = true;
       continue;
     }
-    const double r = sqrt(r2);
-    const double ir = 1.0 / r;
+    const double r = sqrt(r2);   // correctly rounded: the phase of e^{i k r} rests on it
+    const double ir = rsqrt(r2);  // 1 / r, and 1 / (k r) below, with no division
     const double xx = k * r;
-    const double tox = 2.0 / xx;  // the recurrence factor 2 (m - 1) / x is (m - 1) tox
+    const double ixx = ik * ir;
+    const double tox = 2.0 * ixx;  // the recurrence factor 2 (m - 1) / x is (m - 1) tox
     cplx H0, H1;
-    hankel01_near(xx, &H0, &H1);
+    hankel01_near(xx, ixx, &H0, &H1);
     const cplx e1 = cmk(dx * ir, dy * ir);  // e^{i theta_p}
     const cplx* c0 = cf + Np * NF_RC;     // mode 0
 #pragma unroll
@@ -123,14 +129,15 @@ __global__ __launch_bounds__(NF_THREADS) void k_nearfield(DevView v, int R, cons
         Hm = Hn;
         em = cmul(em, e1);
       }
-      const cplx tp = cmul(Hm, em);                       // H_m e^{i m theta}
-      cplx tm = cmul(Hm, cconj(em));                      // H_{-m} e^{-i m theta} = (-1)^m H_m e^{-i m theta}
-      if (m & 1) tm = cmk(-tm.x, -tm.y);
+      // H_{-m} e^{-i m theta} = (-1)^m H_m e^{-i m theta}: both modes take
+      // (c_m e^{i m theta} + (-1)^m c_{-m} e^{-i m theta}) H_m
+      const cplx emc = (m & 1) ? cmk(-em.x, em.y) : cconj(em);
 #pragma unroll
       for (int c = 0; c < NF_RC; ++c)
         if (c < nr) {
-          cmac(acc[c], c0[m * NF_RC + c], tp);
-          cmac(acc[c], c0[-m * NF_RC + c], tm);
+          cplx t = cmul(c0[m * NF_RC + c], em);
+          cmac(t, c0[-m * NF_RC + c], emc);
+          cmac(acc[c], t, Hm);
         }
     }
   }

@@ -198,38 +198,111 @@ __device__ __forceinline__ double wave_bcast(double x, int l) {
 
 constexpr int JB = 4;
 
+// Rotation records: rec[parity of the round][workgroup][step][pair] = (cs,
+// Re s, Im s, 1 if rotated else 0), at most 7 steps a round.
+constexpr int JSTEPS = 7;
+
+__device__ __forceinline__ double* jac_rec(double* rec, int rr, int nwg, int wg, int st, int k) {
+  return rec + 4 * ((((int64_t)(rr & 1) * nwg + wg) * JSTEPS + st) * JB + k);
+}
+
+// The steps of round rr in order, each as its four pairs (a[k], b[k]) of slots.
+template <typename StepFn>
+__device__ __forceinline__ void jac_steps(int rr, StepFn&& step) {
+  if (rr == 0) {
+    // inside the blocks: (0,1)(2,3), (0,2)(1,3), (0,3)(1,2) in P and in Q (this
+    // order took 8 sweeps on a 512-cell far-field matrix, the circle order 11)
+    step(0, {0, 2, 4, 6}, {1, 3, 5, 7});
+    step(1, {0, 1, 4, 5}, {2, 3, 6, 7});
+    step(2, {0, 1, 4, 5}, {3, 2, 7, 6});
+  }
+  const int s0 = rr == 0 ? 3 : 0;
+  step(s0, {0, 1, 2, 3}, {4, 5, 6, 7});
+  step(s0 + 1, {0, 1, 2, 3}, {5, 6, 7, 4});
+  step(s0 + 2, {0, 1, 2, 3}, {6, 7, 4, 5});
+  step(s0 + 3, {0, 1, 2, 3}, {7, 4, 5, 6});
+}
+
+// One launch: workgroups [0, nf) take round r on the columns of F and record
+// each rotation; workgroups [nf, nf + nv) apply the rotations recorded in round
+// rv = r - 1 (the previous launch) to the columns of V, on other compute units
+// and off the path of F's reductions.  r = -1: V only (the last round of a
+// sweep); rv = -1: F only (the first).
 template <int EPT, int NT>
-__global__ __launch_bounds__(NT) void k_jacobi_block_round(int n, int m, int nbp, int r,
+__global__ __launch_bounds__(NT) void k_jacobi_block_round(int n, int m, int nbp, int r, int rv,
                                                             cplx* __restrict__ X,
                                                             cplx* __restrict__ Vt, double tol,
                                                             const double* __restrict__ fro2,
+                                                            double* __restrict__ rec,
                                                             int32_t* __restrict__ n_rot) {
   constexpr int NW = NT / 64, NS = 4 * JB, LPV = 64 / NS;
   __shared__ double sred[2][NS][NW + 1];  // padded: the lanes of different pairs hit different banks
+  const int nwg = nbp / 2, nf = r >= 0 ? nwg : 0;
+  const bool frole = (int)blockIdx.x < nf;
+  const int rr = frole ? r : rv, wg = frole ? (int)blockIdx.x : (int)blockIdx.x - nf;
   int P, Q;
-  round_pair(r, blockIdx.x, nbp, &P, &Q);
+  round_pair(rr, wg, nbp, &P, &Q);
   const int nb = (n + JB - 1) / JB;
-  if (Q >= nb && r > 0) return;  // the padding block: nothing inside a block left to do
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const double eps_f = 2.220446049250313e-16 * fro2[0];
+  if (Q >= nb && rr > 0) return;  // the padding block: nothing inside a block left to do
   int col[2 * JB];  // column of each slot, -1 for none
-  cplx f[2 * JB][EPT], v[2 * JB][EPT];
 #pragma unroll
   for (int j = 0; j < 2 * JB; ++j) {
     const int B = j < JB ? P : Q;
     const int c = B + nb * (j & (JB - 1));
     col[j] = (B < nb && c < n) ? c : -1;
+  }
+  unsigned touched = 0u;
+  if (!frole) {
+    // V: replay the round's rotations on the rows of Vt
+    cplx v[2 * JB][EPT];
+#pragma unroll
+    for (int j = 0; j < 2 * JB; ++j)
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const int i = threadIdx.x + e * NT;
+        v[j][e] = (col[j] >= 0 && i < n) ? Vt[(int64_t)col[j] * n + i] : cmk(0.0, 0.0);
+      }
+    jac_steps(rr, [&](int st, const int (&a)[JB], const int (&b)[JB]) {
+#pragma unroll
+      for (int k = 0; k < JB; ++k) {
+        const double* q = jac_rec(rec, rr, nwg, wg, st, k);
+        if (q[3] == 0.0) continue;
+        const double c = q[0];
+        const cplx sn = cmk(q[1], q[2]);
+        const cplx sc = cconj(sn);
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+          const cplx x = v[a[k]][e], y = v[b[k]][e];
+          v[a[k]][e] = csub(cscale(x, c), cmul(sc, y));
+          v[b[k]][e] = cadd(cmul(sn, x), cscale(y, c));
+        }
+        touched |= (1u << a[k]) | (1u << b[k]);
+      }
+    });
+#pragma unroll
+    for (int j = 0; j < 2 * JB; ++j) {
+      if (!((touched >> j) & 1u) || col[j] < 0) continue;
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const int i = threadIdx.x + e * NT;
+        if (i < n) Vt[(int64_t)col[j] * n + i] = v[j][e];
+      }
+    }
+    return;
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const double eps_f = 2.220446049250313e-16 * fro2[0];
+  cplx f[2 * JB][EPT];
+#pragma unroll
+  for (int j = 0; j < 2 * JB; ++j)
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
       const int i = threadIdx.x + e * NT;
-      f[j][e] = (col[j] >= 0 && i < m) ? X[(int64_t)c * m + i] : cmk(0.0, 0.0);
-      v[j][e] = (col[j] >= 0 && i < n) ? Vt[(int64_t)c * n + i] : cmk(0.0, 0.0);
+      f[j][e] = (col[j] >= 0 && i < m) ? X[(int64_t)col[j] * m + i] : cmk(0.0, 0.0);
     }
-  }
   int buf = 0, cnt = 0;
-  unsigned touched = 0u;
   // One step: the JB disjoint pairs (a[k], b[k]).
-  auto step = [&](const int (&a)[JB], const int (&b)[JB]) {
+  jac_steps(rr, [&](int st, const int (&a)[JB], const int (&b)[JB]) {
     double s[NS];
 #pragma unroll
     for (int k = 0; k < JB; ++k) {
@@ -272,6 +345,13 @@ __global__ __launch_bounds__(NT) void k_jacobi_block_round(int n, int m, int nbp
       snr = tt * cs * q4[2] / g;
       sni = tt * cs * q4[3] / g;
     }
+    if (threadIdx.x < JB) {  // the record for V (vector stores, lanes 0..3)
+      double* q = jac_rec(rec, rr, nwg, wg, st, threadIdx.x);
+      q[0] = cs;
+      q[1] = snr;
+      q[2] = sni;
+      q[3] = rot ? 1.0 : 0.0;
+    }
 #pragma unroll
     for (int k = 0; k < JB; ++k) {
       if (!__builtin_amdgcn_readlane((int)rot, k)) continue;
@@ -283,40 +363,18 @@ __global__ __launch_bounds__(NT) void k_jacobi_block_round(int n, int m, int nbp
         const cplx x = f[a[k]][e], y = f[b[k]][e];
         f[a[k]][e] = csub(cscale(x, c), cmul(sc, y));
         f[b[k]][e] = cadd(cmul(sn, x), cscale(y, c));
-        const cplx p = v[a[k]][e], q = v[b[k]][e];
-        v[a[k]][e] = csub(cscale(p, c), cmul(sc, q));
-        v[b[k]][e] = cadd(cmul(sn, p), cscale(q, c));
       }
       ++cnt;
       touched |= (1u << a[k]) | (1u << b[k]);
     }
-  };
-  if (r == 0) {
-    // inside the blocks: (0,1)(2,3), (0,2)(1,3), (0,3)(1,2) in P and in Q (this
-    // order took 8 sweeps on a 512-cell far-field matrix, the circle order 11)
-    step({0, 2, 4, 6}, {1, 3, 5, 7});
-    step({0, 1, 4, 5}, {2, 3, 6, 7});
-    step({0, 1, 4, 5}, {3, 2, 7, 6});
-  }
-#pragma unroll
-  for (int t = 0; t < JB; ++t) {
-    int a[JB], b[JB];
-#pragma unroll
-    for (int k = 0; k < JB; ++k) {
-      a[k] = k;
-      b[k] = JB + (k + t) % JB;
-    }
-    step(a, b);
-  }
+  });
 #pragma unroll
   for (int j = 0; j < 2 * JB; ++j) {
-    const int c = col[j];
-    if (!((touched >> j) & 1u) || c < 0) continue;
+    if (!((touched >> j) & 1u) || col[j] < 0) continue;
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
       const int i = threadIdx.x + e * NT;
-      if (i < m) X[(int64_t)c * m + i] = f[j][e];
-      if (i < n) Vt[(int64_t)c * n + i] = v[j][e];
+      if (i < m) X[(int64_t)col[j] * m + i] = f[j][e];
     }
   }
   if (threadIdx.x == 0 && cnt > 0) atomicAdd(n_rot, cnt);
@@ -423,9 +481,15 @@ extern "C" int mudiff_tro(int n, int m, const void* X, void* T, void* stream) {
   return MUDIFF_OK;
 }
 
+// Rotation records of the block rounds: two rounds of nb'/2 workgroups.
+static size_t jac_rec_bytes(int n) {
+  const int nb = (n + JB - 1) / JB, nbp = nb + (nb & 1);
+  return align256((size_t)2 * (nbp / 2) * JSTEPS * JB * 4 * sizeof(double));
+}
+
 extern "C" size_t mudiff_tro_eigh_workspace_size(int n, int m) {
   if (n < 1 || m < 1) return 0;
-  return align256((size_t)n * n * 16) + align256((size_t)n * 8) + 256 + 256;
+  return align256((size_t)n * n * 16) + align256((size_t)n * 8) + 256 + 256 + jac_rec_bytes(n);
 }
 
 extern "C" int mudiff_tro_eigh(int n, int m, void* X, double* w, void* evec, int max_sweeps,
@@ -444,6 +508,7 @@ extern "C" int mudiff_tro_eigh(int n, int m, void* X, double* w, void* evec, int
   double* wr = (double*)(wsp + align256((size_t)n * n * 16));
   double* fro2 = (double*)(wsp + align256((size_t)n * n * 16) + align256((size_t)n * 8));
   int32_t* n_rot = (int32_t*)((char*)fro2 + 256);
+  double* rec = (double*)((char*)n_rot + 256);
   cplx* Xc = (cplx*)X;
   const int np = n + (n & 1);
   hipLaunchKernelGGL(k_eye, dim3((unsigned)(((int64_t)n * n + 255) / 256)), dim3(256), 0, s, n, Vt);
@@ -455,16 +520,18 @@ extern "C" int mudiff_tro_eigh(int n, int m, void* X, double* w, void* evec, int
     int rc = launch_fill_zero(n_rot, 4, s);
     if (rc != MUDIFF_OK) return rc;
     const int len = std::max(n, m);
-    // rows of at most 1024 entries: blocks of JB columns
-    const int nb = (n + JB - 1) / JB, nbp = nb + (nb & 1);
-    for (int r = 0; len <= 1024 && r < nbp - 1; ++r) {
-      const dim3 g((unsigned)(nbp / 2));
+    // rows of at most 1024 entries: blocks of JB columns; launch r takes round r
+    // on F and round r - 1 on V, a last launch round nb' - 2 on V
+    const int nb = (n + JB - 1) / JB, nbp = nb + (nb & 1), nwg = nbp / 2;
+    for (int r = 0; len <= 1024 && r <= nbp - 1; ++r) {
+      const int rf = r < nbp - 1 ? r : -1, rv = r - 1;
+      const dim3 g((unsigned)((rf >= 0 ? nwg : 0) + (rv >= 0 ? nwg : 0)));
       if (len <= 256)
-        hipLaunchKernelGGL((k_jacobi_block_round<1, 256>), g, dim3(256), 0, s, n, m, nbp, r, Xc, Vt, tol, (const double*)fro2, n_rot);
+        hipLaunchKernelGGL((k_jacobi_block_round<1, 256>), g, dim3(256), 0, s, n, m, nbp, rf, rv, Xc, Vt, tol, (const double*)fro2, rec, n_rot);
       else if (len <= 512)
-        hipLaunchKernelGGL((k_jacobi_block_round<2, 256>), g, dim3(256), 0, s, n, m, nbp, r, Xc, Vt, tol, (const double*)fro2, n_rot);
+        hipLaunchKernelGGL((k_jacobi_block_round<2, 256>), g, dim3(256), 0, s, n, m, nbp, rf, rv, Xc, Vt, tol, (const double*)fro2, rec, n_rot);
       else
-        hipLaunchKernelGGL((k_jacobi_block_round<2, 512>), g, dim3(512), 0, s, n, m, nbp, r, Xc, Vt, tol, (const double*)fro2, n_rot);
+        hipLaunchKernelGGL((k_jacobi_block_round<2, 512>), g, dim3(512), 0, s, n, m, nbp, rf, rv, Xc, Vt, tol, (const double*)fro2, rec, n_rot);
     }
     for (int r = 0; len > 1024 && r < np - 1; ++r) {
       const dim3 g((unsigned)(np / 2)), b(JAC_THREADS);

@@ -177,9 +177,9 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi_round(int n, int m, int 
 // pairs (p_i, q_j) in four steps of the four disjoint pairs
 // (p_i, q_{(i+s) mod 4}); in the first round of a sweep it first rotates the 6
 // pairs inside each of its two blocks, in three steps.  Every pair of columns
-// is rotated once per sweep, as in the rounds above, in nb' - 1 launches
-// instead of n' - 1.  The 8 columns of F and of V stay in registers for the
-// round; the 16 sums of a step (alpha, beta, gamma of each pair) share one block
+// is rotated once per sweep, as in the rounds above, in nb' launches instead of
+// n' - 1 (V follows one launch behind F, see the kernel).  The 8 columns of F
+// stay in registers for the round; the 16 sums of a step (alpha, beta, gamma of each pair) share one block
 // reduction: a reduce-scatter across the wave (lane swaps and DPP) leaves sum c
 // on lanes 4c..4c+3, then the waves' partial sums are added from LDS in a fixed
 // order by lane k (mod 4) for pair k, which also computes that pair's rotation,

@@ -26,16 +26,6 @@ def pair_geometry(centers) -> tuple[np.ndarray, np.ndarray]:
     return np.hypot(dx, dy), np.arctan2(dy, dx)
 
 
-def check_disjoint(centers, radii) -> None:
-    """The scatterers are disjoint (sec. 2); raise ValueError otherwise."""
-    b, _ = pair_geometry(centers)
-    r = np.asarray(radii, dtype=np.float64)
-    gap = b - r[:, None] - r[None, :]
-    np.fill_diagonal(gap, np.inf)
-    if np.any(gap <= 0.0):
-        raise ValueError("disks overlap or touch")
-
-
 def mode_index(n_modes) -> tuple[np.ndarray, np.ndarray]:
     """For every unknown i: its disk p(i) and mode m(i)."""
     disk = np.concatenate([np.full(2 * N + 1, p) for p, N in enumerate(n_modes)])

@@ -860,3 +860,76 @@ def test_mixed_reciprocity_point_source_and_plane_wave():
     v_pw = np.stack([nearfield.potential(cl.centers, cl.radii, cl.n_modes, cl.k, rpw[j], src)
                      for j in range(len(th))], 1)
     assert rel(rps @ G.T, gam * v_pw) < 1e-11
+
+
+def test_point_source_incident_field_by_graf():
+    """The incident field (i/4) H_0(k |x - s|) of a point source (Prop. 5)
+    against Graf's addition theorem about a center O with |x - O| < |s - O|:
+    (i/4) sum_m J_m(k rho) H_m(k r_s) e^{i m (phi - theta_s)}, evaluated at
+    scattered points and through its Fourier coefficients on a circle; and the
+    Prop. 5 coefficients as the <u_inc, Phi^p_m> quadrature of this field."""
+    from oracle import pointsource as ps
+    k = 3.7
+    O = np.array([0.4, -0.3])
+    s = np.array([2.9, 1.6])
+    rs, ts = np.hypot(*(s - O)), math.atan2(*(s - O)[::-1])
+    rng = np.random.default_rng(11)
+    rho = rng.uniform(0.05, 0.6 * rs, 30)
+    phi = rng.uniform(0.0, 2 * np.pi, 30)
+    pts = O[None, :] + rho[:, None] * np.stack([np.cos(phi), np.sin(phi)], 1)
+    m = np.arange(-90, 91)
+    ref = 0.25j * np.sum(sp.jv(m[None, :], k * rho[:, None]) * sp.hankel1(m, k * rs)[None, :]
+                         * np.exp(1j * m[None, :] * (phi[:, None] - ts)), 1)
+    u = ps.incident(k, s[None, :], pts)[0]
+    assert rel(u, ref) < 1e-12
+    # Fourier coefficients on the circle |x - O| = a
+    a, N = 0.9, 14
+    c = _circle_coefficients(lambda x, t: ps.incident(k, s[None, :], x)[0], O, a, N)
+    mm = np.arange(-N, N + 1)
+    want = 0.25j * sp.jv(mm, k * a) * sp.hankel1(mm, k * rs) * np.exp(-1j * mm * ts) * np.sqrt(2 * np.pi * a)
+    assert rel(c, want) < 1e-12
+    # Prop. 5 coefficients of a cluster are the projections of this field
+    cl = synth.small_random(103, 3, 0.3, 0.8, 5.0, 0.3, 2.6, 6)
+    src = np.array([[-1.2, 1.4]])
+    U = ps.point_source(cl.centers, cl.radii, cl.n_modes, cl.k, src)
+    off, _ = geometry.mode_offsets(cl.n_modes)
+    for p in range(cl.M):
+        cp = _circle_coefficients(lambda x, t: ps.incident(cl.k, src, x)[0], cl.centers[p],
+                                  cl.radii[p], int(cl.n_modes[p]))
+        assert rel(U[0, off[p]:off[p + 1]], cp) < 1e-12
+
+
+def test_point_source_incident_field_is_the_outgoing_green_function():
+    """(i/4) H_0(k |x - s|) is the outgoing fundamental solution of
+    -(Laplace + k^2): the Helmholtz residual vanishes away from s (fourth-order
+    finite differences), the flux of its gradient through a small circle about
+    s is -1 (a unit source), its imaginary part tends to 1/4 at s, and it
+    satisfies the radiation condition r^{1/2} (d_r u - i k u) -> 0."""
+    from oracle import pointsource as ps
+    k = 2.3
+    s = np.array([[0.7, -0.4]])
+    u = lambda x: ps.incident(k, s, np.atleast_2d(x))[0]
+    h = 1e-2
+    for x0 in ([1.9, 0.3], [-2.0, 1.1], [0.9, 2.5]):
+        x0 = np.array(x0)
+        lap = 0.0
+        for e in (np.array([1.0, 0.0]), np.array([0.0, 1.0])):
+            f = u(np.stack([x0 - 2 * h * e, x0 - h * e, x0, x0 + h * e, x0 + 2 * h * e]))
+            lap = lap + (-f[0] + 16 * f[1] - 30 * f[2] + 16 * f[3] - f[4]) / (12 * h * h)
+        res = lap + k * k * u(x0)[0]
+        assert abs(res) < 1e-6 * abs(k * k * u(x0)[0])
+    # flux through |x - s| = eps by the trapezoid rule on d_r u (central differences)
+    eps, d = 1e-3, 1e-6
+    t = 2 * np.pi * np.arange(64) / 64
+    e = np.stack([np.cos(t), np.sin(t)], 1)
+    dr = (u(s + (eps + d) * e) - u(s + (eps - d) * e)) / (2 * d)
+    flux = np.sum(dr) * (2 * np.pi / 64) * eps
+    assert abs(flux - (-1.0)) < 1e-4
+    assert abs(u(s + 1e-7 * e[:1])[0].imag - 0.25) < 1e-6
+    # radiation condition: r^{1/2} |d_r u - i k u| decays like r^{-1}
+    vals = []
+    for r in (50.0, 200.0, 800.0):
+        x = s + r * e[3:4]
+        drr = (u(x + 1e-4 * e[3:4]) - u(x - 1e-4 * e[3:4]))[0] / 2e-4
+        vals.append(np.sqrt(r) * abs(drr - 1j * k * u(x)[0]))
+    assert vals[1] < 0.3 * vals[0] and vals[2] < 0.3 * vals[1]

@@ -81,16 +81,22 @@ enum {
   MUDIFF_NO_PRECOND = 8  /* GMRES on L rho = -U itself (no single-scattering preconditioner) */
 };
 
+/* mudiff_tables flags */
+enum {
+  MUDIFF_TABLES_CIRCULANT = 1  /* also build the circulant-embedded form of the
+                                  well-separated blocks (see mudiff_tables) */
+};
+
 /* Largest accepted truncation order N_p and GMRES restart length. */
 #define MUDIFF_MAX_NP 200
 #define MUDIFF_MAX_RESTART 512
 
 /* ---------------------------------------------------------------- tables */
 
-/* Bytes of device workspace mudiff_tables needs for this batch (pure host
- * computation, no device call).  Returns 0 for invalid arguments. */
+/* Bytes of device workspace mudiff_tables needs for this batch and flags
+ * (pure host computation, no device call).  Returns 0 for invalid arguments. */
 size_t mudiff_tables_workspace_size(int B, const int64_t* disk_off /*[host] B+1*/,
-                                    const int32_t* n_modes /*[host] M_tot*/);
+                                    const int32_t* n_modes /*[host] M_tot*/, int flags);
 
 /* Geometry, Bessel/Hankel tables and the operator schedule (sec. 4.1-4.2).
  *   B          number of instances, >= 1
@@ -101,15 +107,49 @@ size_t mudiff_tables_workspace_size(int B, const int64_t* disk_off /*[host] B+1*
  *   k          [host] [B] wavenumbers > 0
  *   workspace  device buffer of at least mudiff_tables_workspace_size bytes;
  *              it holds the tables for the lifetime of the handle
+ *   flags      0 or MUDIFF_TABLES_CIRCULANT
  *   out        receives the handle (host object; free with mudiff_destroy)
  * Computes on the device: per disk J_m(k a_p), H_m(k a_p) (m = 0..N_p+1,
  * Miller's downward recurrence for J, Neumann series / Hankel's expansion and
  * upward recurrence for Y) and per unordered pair p<q the separation symbols
- * t^{pq}_s, |s| <= N_p + N_q.  Errors: INVALID, OVERLAP (b_pq <= a_p + a_q),
- * NOMEM, DEVICE. */
+ * t^{pq}_s, |s| <= N_p + N_q.
+ * With MUDIFF_TABLES_CIRCULANT (the Toeplitz products through FFTs of sec. 5):
+ * every instance b with M_b >= 2 gets an embedding length L_b = 2 (N' + N'') + 1,
+ * N' >= N'' its two largest orders (L_b >= n_p + n_q - 1 for every pair, so
+ * the circulant of length L_b holds each Toeplitz block exactly), and for every
+ * frequency f < L_b the matrix
+ *   T_f[p][q] = (1/L_b) sum_{|s| <= N_p+N_q} t^{pq}_s w^{f (s + N_q - N_p)},
+ *   w = e^{2 pi i / L_b},
+ * over the ordered pairs that are well separated, k b_pq >= N_p + N_q (zero on
+ * the diagonal and for close pairs: there the symbols grow by orders of
+ * magnitude and a transform would spread their rounding over every mode).
+ * Then for a well-separated pair the Toeplitz product is
+ *   sum_n t^{pq}_{n-m} z_n = sum_f w^{f j} T_f[p][q] Z_f,  Z_f = sum_k w^{-f k} z_k,
+ * with k = n + N_q, j = m + N_p.  This costs sum_b L_b M_b^2 complex values of
+ * workspace (about 1.3 GB for 1,000 disks at N_p <= 20); multi-right-hand-side
+ * applies (R >= 8, N_p <= 31) may then run those pairs as one dense complex
+ * product per frequency on the matrix cores and the close pairs directly
+ * (chosen per R by timing: mudiff_apply_config, mudiff_set_circulant).  The
+ * flag requires N_p <= 31.
+ * Errors: INVALID, OVERLAP (b_pq <= a_p + a_q), NOMEM, DEVICE. */
 int mudiff_tables(int B, const int64_t* disk_off, const double* centers, const double* radii,
                   const int32_t* n_modes, const double* k, void* workspace, size_t ws_bytes,
-                  void* stream, mudiff_t* out);
+                  int flags, void* stream, mudiff_t* out);
+
+/* Classification of the ordered disk pairs of a handle built with
+ * MUDIFF_TABLES_CIRCULANT (host outputs, any may be NULL): well-separated
+ * pairs (k b_pq >= N_p + N_q, circulant form), close pairs (direct form) and
+ * the largest embedding length.  Zeros for a handle built without the flag. */
+int mudiff_circulant_info(mudiff_t h, int64_t* far_pairs, int64_t* near_pairs, int* L_max);
+
+/* Form of the R-column apply on a handle built with MUDIFF_TABLES_CIRCULANT:
+ * mode -1 (default) times the direct and the circulant forms on the first
+ * apply with this R and keeps the faster, 0 keeps every pair in the direct
+ * form, 1 uses the circulant form.  The circulant form covers the instances
+ * whose well-separated pairs hold at least half of the direct form's work;
+ * the others stay direct.  Takes effect at the next call with this R.
+ * Errors: MUDIFF_ERR_INVALID (mode, no circulant tables). */
+int mudiff_set_circulant(mudiff_t h, int R, int mode);
 
 /* Releases the host handle (not the caller's device memory). */
 int mudiff_destroy(mudiff_t h);
@@ -152,7 +192,9 @@ int mudiff_matvec(mudiff_t h, int R, const void* x, void* y, int op,
 /* Kernel configuration of the R-column operator apply, as chosen on this
  * handle (host outputs; any pointer may be NULL):
  *   kind       0 one lane per pair (uniform N_p <= 12, R < 8), 1 FP64-MFMA
- *              work queue (R >= 8, N_p <= 31), 2 generic LDS-staged kernel
+ *              work queue (R >= 8, N_p <= 31), 2 generic LDS-staged kernel,
+ *              3 circulant form on the FP64 matrix cores for the well-separated
+ *              pairs and the MFMA work queue for the close ones
  *   ct, rp     MFMA tile: 8*ct right-hand sides x rp row disks per work item
  *   qs         MFMA column-disk segment length (0: whole instance)
  *   threads    MFMA workgroup size

@@ -19,8 +19,10 @@ _sz = ctypes.c_size_t
 _d = ctypes.c_double
 
 SIGNATURES = {
-    "mudiff_tables_workspace_size": (_sz, [_i32, _vp, _vp]),
-    "mudiff_tables": (_i32, [_i32, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp, ctypes.POINTER(_vp)]),
+    "mudiff_tables_workspace_size": (_sz, [_i32, _vp, _vp, _i32]),
+    "mudiff_tables": (_i32, [_i32, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _i32, _vp, ctypes.POINTER(_vp)]),
+    "mudiff_circulant_info": (_i32, [_vp, _i64p, _i64p, ctypes.POINTER(_i32)]),
+    "mudiff_set_circulant": (_i32, [_vp, _i32, _i32]),
     "mudiff_destroy": (_i32, [_vp]),
     "mudiff_sizes": (_i32, [_vp, _i64p]),
     "mudiff_disk_tables": (_i32, [_vp, _vp, _vp, _vp]),
@@ -57,6 +59,7 @@ SIGNATURES = {
 STATUS = {0: "OK", 1: "INVALID", 2: "OVERLAP", 3: "NOMEM", 4: "DEVICE", 5: "NOT_CONVERGED"}
 OP_L, OP_A, OP_LT = 0, 1, 2
 X0, GRAPH, POINT_SOURCE, NO_PRECOND = 1, 2, 4, 8
+TABLES_CIRCULANT = 1
 PROBE_FP64_FMA, PROBE_FP64_MFMA, PROBE_COPY = 0, 1, 2
 
 

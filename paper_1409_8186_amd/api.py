@@ -35,9 +35,11 @@ class Problem:
     """B independent disk clusters sharing one set of device tables.
 
     ``instances``: sequence of (centers [M,2], radii [M], n_modes [M], k).
+    ``circulant``: also build the circulant-embedded form of the well-separated
+    blocks (MUDIFF_TABLES_CIRCULANT), used by multi-right-hand-side applies.
     """
 
-    def __init__(self, instances: Sequence, device: str = "cuda"):
+    def __init__(self, instances: Sequence, device: str = "cuda", circulant: bool = False):
         self.lib = L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("libmudiff needs a HIP device")
@@ -56,8 +58,9 @@ class Problem:
         self.n_modes = np.ascontiguousarray(np.concatenate(ns))
         self.k = _host(ks, np.float64)
         self.disk_off = _host(offs, np.int64)
+        self.flags = L.TABLES_CIRCULANT if circulant else 0
         ws = self.lib.mudiff_tables_workspace_size(self.B, self.disk_off.ctypes.data,
-                                                   self.n_modes.ctypes.data)
+                                                   self.n_modes.ctypes.data, self.flags)
         if ws == 0:
             raise L.MudiffError(1, "invalid sizes (disk_off / n_modes)")
         self.ws = torch.empty(int(ws), dtype=torch.uint8, device=self.device)
@@ -65,8 +68,8 @@ class Problem:
         h = ctypes.c_void_p()
         L.check(self.lib.mudiff_tables(self.B, self.disk_off.ctypes.data, self.centers.ctypes.data,
                                        self.radii.ctypes.data, self.n_modes.ctypes.data,
-                                       self.k.ctypes.data, _p(self.ws), int(ws), _stream(),
-                                       ctypes.byref(h)))
+                                       self.k.ctypes.data, _p(self.ws), int(ws), self.flags,
+                                       _stream(), ctypes.byref(h)))
         self.h = h
         n = np.zeros(self.B, np.int64)
         L.check(self.lib.mudiff_sizes(h, n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
@@ -75,12 +78,12 @@ class Problem:
         self._mv_ws = {}
 
     @classmethod
-    def from_cluster(cls, cl, device="cuda"):
-        return cls([(cl.centers, cl.radii, cl.n_modes, cl.k)], device)
+    def from_cluster(cls, cl, device="cuda", circulant=False):
+        return cls([(cl.centers, cl.radii, cl.n_modes, cl.k)], device, circulant)
 
     @classmethod
-    def from_clusters(cls, cls_list, device="cuda"):
-        return cls([(c.centers, c.radii, c.n_modes, c.k) for c in cls_list], device)
+    def from_clusters(cls, cls_list, device="cuda", circulant=False):
+        return cls([(c.centers, c.radii, c.n_modes, c.k) for c in cls_list], device, circulant)
 
     def close(self):
         if getattr(self, "h", None):
@@ -153,12 +156,24 @@ class Problem:
         L.check(self.lib.mudiff_apply_config(self.h, R, *[ctypes.byref(v) for v in vals],
                                               ctypes.byref(ms)))
         kind, ct, rp, qs, th = (v.value for v in vals)
-        return {"kind": ["lane", "mfma", "generic"][kind], "ct": ct, "rp": rp, "qs": qs,
-                "threads": th, "tuned_ms": ms.value}
+        return {"kind": ["lane", "mfma", "generic", "circulant"][kind], "ct": ct, "rp": rp,
+                "qs": qs, "threads": th, "tuned_ms": ms.value}
 
     def set_apply_config(self, R: int, ct: int, rp: int, qs: int, threads: int) -> None:
         """Fix the MFMA tile of the R-column apply (no autotuning for this R)."""
         L.check(self.lib.mudiff_set_apply_config(self.h, R, ct, rp, qs, threads))
+
+    def circulant_info(self) -> dict:
+        """Ordered pairs in the circulant (well-separated) and direct (close)
+        forms, and the largest embedding length."""
+        far, near, lm = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int(0)
+        L.check(self.lib.mudiff_circulant_info(self.h, ctypes.byref(far), ctypes.byref(near),
+                                               ctypes.byref(lm)))
+        return {"far_pairs": far.value, "near_pairs": near.value, "L_max": lm.value}
+
+    def set_circulant(self, R: int, mode: int) -> None:
+        """Form of the R-column apply: -1 timed, 0 direct only, 1 circulant."""
+        L.check(self.lib.mudiff_set_circulant(self.h, R, mode))
 
     def rhs(self, betas=None, precond: bool = False, sources=None) -> torch.Tensor:
         """betas: [B, R] incidence angles, or sources: [B, R, 2] point-source

@@ -1,0 +1,319 @@
+// Circulant-embedded form of the well-separated off-diagonal blocks (paper
+// sec. 5: the block-Toeplitz matrix-vector products are done with FFTs).
+//
+// A block (p, q) acts as w_m = sum_n t^{pq}_{n-m} z_n (m = -N_p..N_p,
+// n = -N_q..N_q).  Embedded in a circulant of length L >= n_p + n_q - 1 it is
+// diagonalised by the discrete Fourier transform.  With one length L_b for
+// every pair of an instance and indices k = n + N_q, j = m + N_p:
+//   Z_f = sum_k w^{-f k} z_k,   w = e^{2 pi i / L_b},
+//   T_f[p][q] = (1/L_b) sum_s t^{pq}_s w^{f (s + N_q - N_p)},
+//   w^p_j = sum_f w^{f j} sum_q T_f[p][q] Z^q_f.
+// The middle step is, for each frequency f, one dense complex product of the
+// M_b x M_b matrix T_f with the M_b x R panel of transformed inputs: it runs
+// on the FP64 matrix cores (k_circ_gemm), the transforms of the inputs and
+// outputs are small dense sums (k_circ_fwd, and the finishing pass of the
+// apply).  T_f is zero on the diagonal and for close pairs (k b_pq < N_p + N_q):
+// their symbols grow by orders of magnitude with the order, and a transform
+// would spread that rounding over every mode, so they stay in the direct form.
+#include "common.h"
+
+// Twiddles w^j = e^{2 pi i j / L_b}, j < L_b, of every instance.
+__global__ void k_circ_twiddles(DevView v, cplx* tw) {
+  const int b = blockIdx.y;
+  const int Lb = v.cL[b];
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= Lb) return;
+  double s, c;
+  sincospi(2.0 * (double)j / (double)Lb, &s, &c);
+  tw[v.cWo[b] + j] = cmk(c, s);
+}
+
+// T_f[p][q] for one row disk p and 16 column disks, every f: the symbol rows
+// (sign of the reverse pair applied, zero for close pairs and p = q) are
+// staged in LDS, thread (q, f-lane) sums its row against the twiddles.
+#define CS_Q 16
+__global__ __launch_bounds__(256) void k_circ_symbols(DevView v, const uint8_t* __restrict__ nearf,
+                                                      cplx* __restrict__ cT, int ts) {
+  extern __shared__ cplx lds[];
+  cplx* rows = lds;                   // [CS_Q][ts]
+  cplx* tw = lds + CS_Q * ts;         // [L_b]
+  const int p = blockIdx.x, tid = threadIdx.x;
+  const int b = v.inst[p];
+  const int Lb = v.cL[b];
+  if (Lb == 0) return;
+  const int64_t d0 = v.idisk[b], Mb = v.idisk[b + 1] - d0;
+  const int64_t q0 = (int64_t)blockIdx.y * CS_Q;
+  if (q0 >= Mb) return;
+  const int Np = v.N[p];
+  for (int e = tid; e < CS_Q * ts; e += 256) {
+    const int kq = e / ts, u = e - (e / ts) * ts;
+    const int64_t ql = q0 + kq;
+    cplx val = cmk(0.0, 0.0);
+    if (ql < Mb) {
+      const int q = (int)(d0 + ql);
+      if (q != p) {
+        const int64_t g = pair_index(v.idisk, v.ipair, b, p, q);
+        const int S = Np + v.N[q];
+        if (!nearf[g] && u <= 2 * S) {
+          val = v.t[v.toff[g] + u];                                   // s = u - S
+          if (p > q && ((u - S) & 1)) val = cmk(-val.x, -val.y);       // t^{pq}_s = (-1)^s t^{qp}_s
+        }
+      }
+    }
+    rows[e] = val;
+  }
+  for (int e = tid; e < Lb; e += 256) tw[e] = v.ctw[v.cWo[b] + e];
+  __syncthreads();
+  const int kq = tid & (CS_Q - 1);
+  const int64_t ql = q0 + kq;
+  if (ql >= Mb) return;
+  const int q = (int)(d0 + ql);
+  const int S = Np + v.N[q];
+  const int sh = v.N[q] - Np;
+  const double inv = 1.0 / (double)Lb;
+  cplx* out = cT + v.cTo[b] + (int64_t)(p - d0) * Mb + ql;
+  const cplx* row = rows + kq * ts;
+  for (int f = tid / CS_Q; f < Lb; f += 256 / CS_Q) {
+    cplx acc = cmk(0.0, 0.0);
+    int idx = (int)(((int64_t)f * (sh - S)) % Lb);  // f (s + N_q - N_p) mod L_b at s = -S
+    if (idx < 0) idx += Lb;
+    for (int u = 0; u <= 2 * S; ++u) {
+      cmac(acc, row[u], tw[idx]);
+      idx += f;
+      if (idx >= Lb) idx -= Lb;
+    }
+    out[(int64_t)f * Mb * Mb] = cscale(acc, inv);
+  }
+}
+
+// Transformed inputs Z_f[q][r] = sum_k w^{-f k} z^q_k for one column disk q and
+// 32 right-hand sides: the panel z (already scaled by its column factor) is
+// staged in LDS as [k][r], thread (f-lane, r) runs over the frequencies.
+#define CF_R 32
+__global__ __launch_bounds__(256) void k_circ_fwd(DevView v, int R, const cplx* __restrict__ z,
+                                                  cplx* __restrict__ zh,
+                                                  const int32_t* __restrict__ con,
+                                                  const int32_t* __restrict__ active) {
+  __shared__ cplx zs[64 * CF_R];
+  __shared__ cplx tw[128];
+  const int q = blockIdx.x, tid = threadIdx.x;
+  const int b = v.inst[q];
+  if (!con[b]) return;
+  const int r0 = blockIdx.y * CF_R;
+  if (r0 >= R) return;
+  if (active) {
+    bool any = false;
+    for (int r = r0; r < min(R, r0 + CF_R); ++r) any |= active[b * R + r] != 0;
+    if (!any) return;
+  }
+  const int Lb = v.cL[b];
+  const int nq = 2 * v.N[q] + 1;
+  const int64_t d0 = v.idisk[b], Mb = v.idisk[b + 1] - d0;
+  const int64_t mq = v.moff[q];
+  for (int e = tid; e < CF_R * nq; e += 256) {
+    const int r = e / nq, k = e - (e / nq) * nq;
+    cplx val = cmk(0.0, 0.0);
+    if (r0 + r < R) val = z[col_base(v.imode, b, R, r0 + r) + mq + k];
+    zs[k * CF_R + r] = val;
+  }
+  for (int e = tid; e < Lb; e += 256) tw[e] = v.ctw[v.cWo[b] + e];
+  __syncthreads();
+  const int r = tid & (CF_R - 1);
+  if (r0 + r >= R) return;
+  cplx* out = zh + (int64_t)R * v.cZo[b] + (q - d0) * R + r0 + r;
+  for (int f = tid / CF_R; f < Lb; f += 256 / CF_R) {
+    cplx acc = cmk(0.0, 0.0);
+    int idx = 0;
+    for (int k = 0; k < nq; ++k) {
+      cmacc(acc, tw[idx], zs[k * CF_R + r]);  // conj(w^{f k}) z_k
+      idx += f;
+      if (idx >= Lb) idx -= Lb;
+    }
+    out[(int64_t)f * Mb * R] = acc;
+  }
+}
+
+// W_f = T_f Z_f for every frequency of the instances using the form: a dense
+// complex product per (instance, frequency) on v_mfma_f64_16x16x4f64.  Work
+// item: (instance, frequency, row tile, column tile).  Workgroup: 4 waves as
+// WR x WC, each wave WM x WN tiles of 16 rows x 8 complex columns; a complex
+// product is two real MFMAs against [Re Z | Im Z] (lane l holds A[l % 16][l / 16],
+// B[l / 16][l % 16], D[4 v + l / 16][l % 16]).  K steps of 16 column disks are
+// staged in LDS, the next one loaded into registers while the current one is
+// on the matrix cores.  Consecutive items (the tiles of one frequency) are
+// placed on one XCD, whose L2 then serves the rows of T_f and the panel Z_f to
+// all of them.
+typedef double cg_d4 __attribute__((ext_vector_type(4)));
+
+template <int WR, int WC, int WM, int WN>
+__global__ __launch_bounds__(256) void k_circ_gemm(DevView v, int R, const cplx* __restrict__ zh,
+                                                   cplx* __restrict__ wh,
+                                                   const int32_t* __restrict__ items, int n_items,
+                                                   const int32_t* __restrict__ active) {
+  constexpr int BM = WR * 16 * WM, BN = WC * 8 * WN, BK = 16;
+  constexpr int AS = BK + 1, BS = BN + 1;  // LDS row strides (complex)
+  constexpr int NA = BM * BK / 256, NB = (BK * BN + 255) / 256;
+  __shared__ cplx As[BM * AS];
+  __shared__ cplx Bs[BK * BS];
+  const int i = blockIdx.x;
+  const int xc = i & 7, slot = i >> 3;
+  const int it = xc * (n_items >> 3) + min(xc, n_items & 7) + slot;
+  const int32_t* rec = items + 4 * (int64_t)it;
+  const int b = rec[0], f = rec[1];
+  const int64_t row0 = (int64_t)rec[2] * BM;
+  const int col0 = rec[3] * BN;
+  if (active) {
+    bool any = false;
+    for (int c = col0; c < min(R, col0 + BN); ++c) any |= active[b * R + c] != 0;
+    if (!any) return;
+  }
+  const int64_t Mb = v.idisk[b + 1] - v.idisk[b];
+  const cplx* __restrict__ A = v.cT + v.cTo[b] + (int64_t)f * Mb * Mb;
+  const int64_t zo = (int64_t)R * v.cZo[b] + (int64_t)f * Mb * R;
+  const cplx* __restrict__ Bm = zh + zo;
+  cplx* __restrict__ C = wh + zo;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int j = lane & 15, kq = lane >> 4;
+  const int wr = wave / WC, wc = wave - (wave / WC) * WC;
+  cplx ra[NA], rb[NB];
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int e = tid + u * 256;
+      const int r = e / BK, c = e - (e / BK) * BK;
+      const int64_t gr = row0 + r, gc = k0 + c;
+      ra[u] = (gr < Mb && gc < Mb) ? A[gr * Mb + gc] : cmk(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int e = tid + u * 256;
+      const int r = e / BN, c = e - (e / BN) * BN;
+      const int64_t gr = k0 + r;
+      const int gc = col0 + c;
+      rb[u] = (e < BK * BN && gr < Mb && gc < R) ? Bm[gr * R + gc] : cmk(0.0, 0.0);
+    }
+  };
+  cg_d4 acc1[WM][WN], acc2[WM][WN];
+#pragma unroll
+  for (int mt = 0; mt < WM; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < WN; ++nt) {
+      acc1[mt][nt] = cg_d4{0.0, 0.0, 0.0, 0.0};
+      acc2[mt][nt] = cg_d4{0.0, 0.0, 0.0, 0.0};
+    }
+  const int64_t nk = (Mb + BK - 1) / BK;
+  load(0);
+  for (int64_t kc = 0; kc < nk; ++kc) {
+    __syncthreads();  // previous step done with LDS
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int e = tid + u * 256;
+      As[(e / BK) * AS + (e % BK)] = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int e = tid + u * 256;
+      if (e < BK * BN) Bs[(e / BN) * BS + (e % BN)] = rb[u];
+    }
+    __syncthreads();
+    if (kc + 1 < nk) load((kc + 1) * BK);  // in flight during the MFMAs
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      cplx a[WM];
+      double bv[WN];
+#pragma unroll
+      for (int mt = 0; mt < WM; ++mt) a[mt] = As[(wr * 16 * WM + 16 * mt + j) * AS + 4 * kk + kq];
+#pragma unroll
+      for (int nt = 0; nt < WN; ++nt) {
+        const cplx zz = Bs[(4 * kk + kq) * BS + wc * 8 * WN + 8 * nt + (j & 7)];
+        bv[nt] = j < 8 ? zz.x : zz.y;
+      }
+#pragma unroll
+      for (int mt = 0; mt < WM; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < WN; ++nt) {
+          acc1[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mt].x, bv[nt], acc1[mt][nt], 0, 0, 0);
+          acc2[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mt].y, bv[nt], acc2[mt][nt], 0, 0, 0);
+        }
+    }
+  }
+#pragma unroll
+  for (int mt = 0; mt < WM; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < WN; ++nt)
+#pragma unroll
+      for (int vv = 0; vv < 4; ++vv) {
+        const double a1 = acc1[mt][nt][vv], a2 = acc2[mt][nt][vv];
+        const double other = __shfl_xor(a2, 8, 64);
+        const double val = j < 8 ? a1 - other : a1 + other;  // Re W (j < 8), Im W (j >= 8)
+        const double im = __shfl_xor(val, 8, 64);
+        const int64_t row = row0 + wr * 16 * WM + 16 * mt + 4 * vv + kq;
+        const int col = col0 + wc * 8 * WN + 8 * nt + (j & 7);
+        if (j < 8 && row < Mb && col < R) C[row * R + col] = cmk(val, im);
+      }
+}
+
+// Product tile of each variant (rows, complex columns), chosen by R.
+struct CircVariant {
+  int bm, bn;
+  void (*fn)(DevView, int, const cplx*, cplx*, const int32_t*, int, const int32_t*);
+};
+static const CircVariant kCircVar[] = {
+    {64, 64, k_circ_gemm<2, 2, 2, 4>},   // R >= 48
+    {64, 32, k_circ_gemm<2, 2, 2, 2>},   // 24 <= R < 48
+    {128, 16, k_circ_gemm<4, 1, 2, 2>},  // 12 <= R < 24
+    {128, 8, k_circ_gemm<4, 1, 2, 1>},   // R < 12
+};
+
+int circ_variant(int R) { return R >= 48 ? 0 : (R >= 24 ? 1 : (R >= 12 ? 2 : 3)); }
+void circ_tile(int var, int* bm, int* bn) {
+  *bm = kCircVar[var].bm;
+  *bn = kCircVar[var].bn;
+}
+
+// Enqueue the transforms of the inputs and the per-frequency products.
+// z: inputs scaled by their column factors [B][R][N_b]; zh, wh: [sum_b L_b M_b][R].
+int circ_launch(mudiff_ctx* h, int R, const cplx* z, cplx* zh, cplx* wh, const int32_t* citems,
+                int n_citems, int var, const int32_t* con, const int32_t* active, hipStream_t s) {
+  hipLaunchKernelGGL(k_circ_fwd, dim3((unsigned)h->M_all, (unsigned)((R + CF_R - 1) / CF_R)), dim3(256), 0,
+                     s, h->dv, R, z, zh, con, active);
+  HIP_TRY(hipGetLastError());
+  if (n_citems > 0) {
+    hipLaunchKernelGGL(kCircVar[var].fn, dim3((unsigned)n_citems), dim3(256), 0, s, h->dv, R,
+                       (const cplx*)zh, wh, citems, n_citems, active);
+    HIP_TRY(hipGetLastError());
+  }
+  return MUDIFF_OK;
+}
+
+// Twiddles and transformed symbols of a handle built with the circulant flag
+// (enqueued on s after the pair tables).
+int circ_build(mudiff_ctx* h, hipStream_t s) {
+  int Lmax = 0;
+  int64_t Mmax = 0;
+  for (int b = 0; b < h->B; ++b) {
+    Lmax = std::max(Lmax, h->cL[b]);
+    Mmax = std::max(Mmax, h->idisk[b + 1] - h->idisk[b]);
+  }
+  if (Lmax == 0) return MUDIFF_OK;
+  cplx* tw = const_cast<cplx*>(h->dv.ctw);
+  hipLaunchKernelGGL(k_circ_twiddles, dim3((unsigned)((Lmax + 255) / 256), (unsigned)h->B), dim3(256), 0, s,
+                     h->dv, tw);
+  HIP_TRY(hipGetLastError());
+  const int ts = 4 * h->Nmax + 1;  // longest symbol row
+  const size_t lds = ((size_t)CS_Q * ts + Lmax) * 16;
+  hipLaunchKernelGGL(k_circ_symbols, dim3((unsigned)h->M_all, (unsigned)((Mmax + CS_Q - 1) / CS_Q)),
+                     dim3(256), lds, s, h->dv, h->circ_near_dev, const_cast<cplx*>(h->dv.cT), ts);
+  HIP_TRY(hipGetLastError());
+  return MUDIFF_OK;
+}
+
+extern "C" int mudiff_circulant_info(mudiff_t h, int64_t* far_pairs, int64_t* near_pairs, int* L_max) {
+  if (!h) return fail(MUDIFF_ERR_INVALID, "NULL handle");
+  int lm = 0;
+  for (int32_t l : h->cL) lm = std::max(lm, (int)l);
+  if (far_pairs) *far_pairs = h->circ ? h->n_far : 0;
+  if (near_pairs) *near_pairs = h->circ ? h->n_near : 0;
+  if (L_max) *L_max = lm;
+  return MUDIFF_OK;
+}

@@ -96,6 +96,17 @@ struct DevView {
   const cplx* op_rhs = nullptr;
   const cplx* op_rhsp = nullptr;
   const cplx* op_ff = nullptr;
+  // Circulant-embedded form of the well-separated blocks (MUDIFF_TABLES_CIRCULANT,
+  // sec. 5 Toeplitz products through discrete Fourier transforms), per instance b:
+  // embedding length L_b (0: none), offset of its transformed symbol matrices
+  // [L_b][M_b][M_b] in cT, of its transformed panels ([L_b][M_b][R], times R)
+  // and of its twiddles w^j = e^{2 pi i j / L_b}, j < L_b, in ctw.
+  const int32_t* cL = nullptr;
+  const int64_t* cTo = nullptr;
+  const int64_t* cZo = nullptr;
+  const int64_t* cWo = nullptr;
+  const cplx* cT = nullptr;
+  const cplx* ctw = nullptr;
 };
 
 #define LANE_CHUNK 64
@@ -142,10 +153,14 @@ struct MatvecPlan {
 // MFMA apply tile choice: CT sub-tiles of 8 right-hand sides, RP row disks per
 // work item (RP * CT waves), column-disk segment length QS (0: whole
 // instance), workgroup size.
+// circ: well-separated pairs of the instances marked in the schedule go
+// through the circulant-embedded form, their close pairs through the MFMA
+// items (column lists).
 struct MfmaChoice {
   int CT = 1, RP = 4, QS = 0, threads = 256;
+  bool circ = false;
   bool operator==(const MfmaChoice& o) const {
-    return CT == o.CT && RP == o.RP && QS == o.QS && threads == o.threads;
+    return CT == o.CT && RP == o.RP && QS == o.QS && threads == o.threads && circ == o.circ;
   }
 };
 
@@ -159,6 +174,11 @@ struct MfmaSched {
   int64_t blk = 0, n_pb = 0;
   std::vector<int32_t> items, dgrp, grow, gnseg, drow;  // grow: RP row disks per group (-1: none)
   std::vector<int64_t> gbase;
+  // circulant form: column lists of the close-pair items ((q << 8) | mask of
+  // the group rows close to q), per-frequency product items (instance,
+  // frequency, row tile, column tile) and the instances that use the form
+  std::vector<int32_t> qlist, citems, con;
+  int n_citems = 0, cvar = 0;
   void* dev_base = nullptr;  // apply scratch the device copy lives in
 };
 
@@ -185,6 +205,19 @@ struct mudiff_ctx {
   MfmaSched mfma_sched;                   // current schedule (host copy + upload location)
   bool mfma_tail = false;                 // straggler schedule (few columns still iterating)
   std::vector<int32_t> mfma_tail_cols;    // columns of the straggler schedule
+  // circulant-embedded form (MUDIFF_TABLES_CIRCULANT): host copies of the
+  // embedding lengths and of the close-pair lists (CSR over the disks)
+  bool circ = false;
+  std::map<int, int> circ_modes;          // per R: -1 timed, 0 off, 1 on (mudiff_set_circulant)
+  std::vector<int32_t> cL;                // [B]
+  std::vector<int64_t> cZo;               // [B]
+  int64_t cZ_all = 0;                     // sum_b L_b M_b
+  std::vector<int64_t> near_off;          // [M_all + 1]
+  std::vector<int32_t> near;              // close column disks of each row disk
+  std::vector<uint8_t> circ_on;           // [B] instance worth the circulant form
+  std::vector<uint8_t> circ_nearflag;     // [P_all] 1: close unordered pair (host copy)
+  const uint8_t* circ_near_dev = nullptr; // the same on the device
+  int64_t n_far = 0, n_near = 0;          // ordered pairs of each kind
   // penetrable disks (set by mudiff_set_penetrable, in its workspace): interior
   // wavenumbers [M_all] and J_n(k- a), n = 0..N_p+1, at dtab offsets
   const double* pen_k = nullptr;

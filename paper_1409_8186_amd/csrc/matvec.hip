@@ -320,7 +320,7 @@ __global__ void k_apply_finish(DevView v, int R, const cplx* __restrict__ x, cpl
 // and R by timing the candidates on the real data (mfma_autotune).
 typedef double mf_d4 __attribute__((ext_vector_type(4)));
 
-#define MF_REC 6       // item record: row group, rp, tile, q0, q1, partial block
+#define MF_REC 7       // item record: row group, rp, tile, q0, q1, partial block, list flag
 
 // Column of element (n, c) of the staged input panel [4 ktmax][RC] in LDS:
 // c XOR a function of the row n, so that a staging store (consecutive rows, one
@@ -354,12 +354,15 @@ __device__ __forceinline__ void mf_tiles(const cplx* trow, const cplx* zl, int z
 // thread, sized on the host for the batch (4 ktmax RC <= ZK THREADS and
 // RP TL <= TK THREADS), which keeps the register footprint of the staging to
 // what the batch needs.
+// An item with its list flag set takes its column disks from qlist[q0..q1):
+// entry (q << 8) | mask, mask bit r set when row r of the item's group is a
+// close pair with q (the circulant form covers the other pairs).
 template <int MT, int THREADS, int ZK, int TK>
 __global__ __launch_bounds__(THREADS) void k_apply_mfma(
     DevView v, int R, const cplx* __restrict__ x, const int32_t* __restrict__ active,
     const int32_t* __restrict__ items, int n_items, int32_t* __restrict__ head,
     cplx* __restrict__ part, int64_t blk, int npad, int ktmax, int RP, int CT,
-    const int32_t* __restrict__ grow) {
+    const int32_t* __restrict__ grow, const int32_t* __restrict__ qlist) {
   extern __shared__ cplx lds[];
   __shared__ int s_item;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -393,6 +396,10 @@ __global__ __launch_bounds__(THREADS) void k_apply_mfma(
     if (it >= n_items) break;
     const int32_t* rec = items + (int64_t)MF_REC * it;
     const int rp = rec[1], tile = rec[2], qb = rec[3], qe = rec[4];
+    const int32_t* __restrict__ ql = rec[6] ? qlist : nullptr;
+    // column disk and row mask of list position i (qb <= i < qe)
+    auto qat = [&](int i) { return ql ? (ql[i] >> 8) : i; };
+    auto mat = [&](int i) { return ql ? (ql[i] & 0xff) : 0xff; };
     const int32_t* grp = grow + (int64_t)rec[0] * RP;  // the item's row disks
     const int64_t pb = rec[5];
     const int c0 = tile * RC;
@@ -434,7 +441,7 @@ __global__ __launch_bounds__(THREADS) void k_apply_mfma(
       prw[k] = trr[k] < rp ? grp[trr[k]] : -1;
       npr[k] = prw[k] >= 0 ? v.N[prw[k]] : 0;
     }
-    auto gather = [&](int q, int Nq, int64_t mq) {
+    auto gather = [&](int q, int qmask, int Nq, int64_t mq) {
       const int nq = 2 * Nq + 1;
 #pragma unroll
       for (int k = 0; k < ZK; ++k) {
@@ -449,7 +456,7 @@ __global__ __launch_bounds__(THREADS) void k_apply_mfma(
         cplx t = cmk(0.0, 0.0);
         double sg = 1.0;
         const int pr = prw[k];
-        if (rr < rp && pr != q) {
+        if (rr < rp && pr != q && ((qmask >> rr) & 1)) {
           const int Npr = npr[k];
           const int S = Npr + Nq;
           const int s = u - (16 * MT - 1) - Nq + Npr;
@@ -464,31 +471,38 @@ __global__ __launch_bounds__(THREADS) void k_apply_mfma(
     };
     // symbol-row offsets of column disk q, loaded one disk ahead of gather(q)
     // so that gathering the symbols is a single dependent load
-    auto load_toff = [&](int q) {
+    auto load_toff = [&](int q, int qmask) {
 #pragma unroll
       for (int k = 0; k < TK; ++k) {
         const int pr = prw[k];
-        tof[k] = (q < qe && trr[k] < rp && pr != q)
+        tof[k] = (q >= 0 && trr[k] < rp && pr != q && ((qmask >> trr[k]) & 1))
                      ? (int32_t)v.toff[pair_index(v.idisk, v.ipair, b, pr, q)] : 0;
       }
     };
-    // N and mode offset of disks q (0), q + 1 (1) and q + 2 (2)
+    // disk, row mask, N and mode offset of list positions i (0), i + 1 (1)
+    // and i + 2 (2)
+    int qd0 = -1, qd1 = -1, qd2 = -1, qm0 = 0, qm1 = 0, qm2 = 0;
     int Nq0 = 0, Nq1 = 0, Nq2 = 0;
     int64_t mq0 = 0, mq1 = 0, mq2 = 0;
     if (qb < qe) {
-      Nq0 = v.N[qb];
-      mq0 = v.moff[qb];
+      qd0 = qat(qb);
+      qm0 = mat(qb);
+      Nq0 = v.N[qd0];
+      mq0 = v.moff[qd0];
     }
     if (qb + 1 < qe) {
-      Nq1 = v.N[qb + 1];
-      mq1 = v.moff[qb + 1];
+      qd1 = qat(qb + 1);
+      qm1 = mat(qb + 1);
+      Nq1 = v.N[qd1];
+      mq1 = v.moff[qd1];
     }
     if (qb < qe) {
-      load_toff(qb);
-      gather(qb, Nq0, mq0);
-      load_toff(qb + 1);
+      load_toff(qd0, qm0);
+      gather(qd0, qm0, Nq0, mq0);
+      load_toff(qd1, qm1);
     }
-    for (int q = qb; q < qe; ++q) {
+    for (int qi = qb; qi < qe; ++qi) {
+      const int q = qd0;
       const int nq = 2 * Nq0 + 1, KT = (nq + 3) >> 2;
       __syncthreads();  // previous column disk done with LDS
 #pragma unroll
@@ -498,15 +512,19 @@ __global__ __launch_bounds__(THREADS) void k_apply_mfma(
       for (int k = 0; k < TK; ++k)
         if (trr[k] < RP) tl[trr[k] * TL + tru[k]] = cscale(tr[k], tsg[k]);
       __syncthreads();
-      if (q + 2 < qe) {  // used by the next iteration's gather
-        Nq2 = v.N[q + 2];
-        mq2 = v.moff[q + 2];
+      qd2 = -1;
+      qm2 = 0;
+      if (qi + 2 < qe) {  // used by the next iteration's gather
+        qd2 = qat(qi + 2);
+        qm2 = mat(qi + 2);
+        Nq2 = v.N[qd2];
+        mq2 = v.moff[qd2];
       }
-      if (q + 1 < qe) {  // in flight during the MFMAs
-        gather(q + 1, Nq1, mq1);
-        load_toff(q + 2);
+      if (qi + 1 < qe) {  // in flight during the MFMAs
+        gather(qd1, qm1, Nq1, mq1);
+        load_toff(qd2, qm2);
       }
-      if (wave_active && q != p) {
+      if (wave_active && q != p && ((qm0 >> row) & 1)) {
         const cplx* trow = tl + row * TL;
         const int zcl = ctile * 8 + (j & 7);
         // only the row tiles of this row disk (wave-uniform count)
@@ -519,8 +537,12 @@ __global__ __launch_bounds__(THREADS) void k_apply_mfma(
           }
         }
       }
+      qd0 = qd1;
+      qm0 = qm1;
       Nq0 = Nq1;
       mq0 = mq1;
+      qd1 = qd2;
+      qm1 = qm2;
       Nq1 = Nq2;
       mq1 = mq2;
     }
@@ -571,7 +593,9 @@ __global__ void k_apply_mfma_finish(DevView v, int R, const cplx* __restrict__ x
                                     const int32_t* __restrict__ drow,
                                     const int32_t* __restrict__ gnseg,
                                     const int64_t* __restrict__ gbase,
-                                    const int32_t* __restrict__ active) {
+                                    const int32_t* __restrict__ active,
+                                    const cplx* __restrict__ wh,
+                                    const int32_t* __restrict__ con) {
   const int64_t total = (int64_t)R * v.N_all;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= total) return;
@@ -595,6 +619,21 @@ __global__ void k_apply_mfma_finish(DevView v, int R, const cplx* __restrict__ x
                    ((int64_t)drow[p] * npad + m) * RC + rc;
   cplx w = cmk(0.0, 0.0);
   for (int s = 0; s < ns; ++s) w = cadd(w, pr[(int64_t)s * blk]);
+  if (wh && con[b]) {  // well-separated pairs: w_j += sum_f w^{f j} W_f[p][r]
+    const int Lb = v.cL[b];
+    const int64_t d0 = v.idisk[b], Mb = v.idisk[b + 1] - d0;
+    const cplx* __restrict__ wf = wh + (int64_t)R * v.cZo[b] + (p - d0) * R + r;
+    const cplx* __restrict__ tw = v.ctw + v.cWo[b];
+    const int jm = (int)m;
+    int idx = 0;
+    cplx acc = cmk(0.0, 0.0);
+    for (int f = 0; f < Lb; ++f) {
+      cmac(acc, tw[idx], wf[(int64_t)f * Mb * R]);
+      idx += jm;
+      if (idx >= Lb) idx -= Lb;
+    }
+    w = cadd(w, acc);
+  }
   y[g] = finalize(v, op, i, x[g], w);
 }
 
@@ -608,7 +647,14 @@ static bool use_mfma(const mudiff_ctx* h, int R) {
   return R >= MFMA_MIN_R && h->Nmax <= 31 && h->mfma_enabled && h->T_all < ((int64_t)1 << 31);
 }
 
-// Host schedule of the MFMA apply for one tile choice.
+int circ_variant(int R);
+void circ_tile(int var, int* bm, int* bn);
+int circ_launch(mudiff_ctx* h, int R, const cplx* z, cplx* zh, cplx* wh, const int32_t* citems,
+                int n_citems, int var, const int32_t* con, const int32_t* active, hipStream_t s);
+
+// Host schedule of the MFMA apply for one tile choice.  With c.circ, the
+// instances marked circ_on keep only their close pairs in the MFMA items
+// (column lists) and get per-frequency product items instead.
 static void mfma_build(const mudiff_ctx* h, int R, const MfmaChoice& c, MfmaSched& S,
                        const std::vector<int32_t>& cols = {}) {
   S.R = R;
@@ -623,18 +669,31 @@ static void mfma_build(const mudiff_ctx* h, int R, const MfmaChoice& c, MfmaSche
   S.grow.clear();
   S.gnseg.clear();
   S.gbase.clear();
+  S.qlist.clear();
+  S.citems.clear();
+  S.con.assign(h->B, 0);
   S.dgrp.assign(h->M_all, 0);
   S.drow.assign(h->M_all, 0);
+  S.cvar = circ_variant(R);
+  int cbm = 0, cbn = 0;
+  circ_tile(S.cvar, &cbm, &cbn);
   struct It {
     double cost;
     int32_t r[MF_REC];
   };
   std::vector<It> its;
+  auto tile_runs = [&](int b, int r0, int r1) {  // straggler schedule: a running column in [r0, r1)
+    if (cols.empty()) return true;
+    for (int r = r0; r < std::min(R, r1); ++r)
+      if (cols[(size_t)b * R + r] != 0) return true;
+    return false;
+  };
   int64_t pb = 0;
   for (int b = 0; b < h->B; ++b) {
     const int64_t d0 = h->idisk[b], d1 = h->idisk[b + 1], Mb = d1 - d0;
+    const bool circ = c.circ && h->circ && h->circ_on[b];
+    S.con[b] = circ ? 1 : 0;
     const int64_t qs = c.QS > 0 ? c.QS : Mb;
-    const int nseg = (int)((Mb + qs - 1) / qs);
     // row disks ordered by their number of 16-row tiles (stable), in groups of RP
     std::vector<int32_t> ord((size_t)Mb);
     for (int64_t k = 0; k < Mb; ++k) ord[(size_t)k] = (int32_t)(d0 + k);
@@ -652,32 +711,61 @@ static void mfma_build(const mudiff_ctx* h, int R, const MfmaChoice& c, MfmaSche
           S.drow[pk] = k;
         }
       }
-      S.gnseg.push_back(nseg);
-      S.gbase.push_back(pb);
       double rows = 0.0;
       for (int k = 0; k < rp; ++k) rows += 2 * h->N[ord[(size_t)(o + k)]] + 1;
-      for (int t = 0; t < S.ntile; ++t) {
-        if (!cols.empty()) {  // straggler schedule: tiles holding a running column only
-          bool any = false;
-          for (int r = t * RC; r < std::min(R, (t + 1) * RC); ++r) any |= cols[(size_t)b * R + r] != 0;
-          if (!any) continue;
+      // column disks of the group: a contiguous range, or the list of the
+      // close pairs of its rows (with the mask of the rows close to each)
+      int64_t ncol = Mb, lbase = 0;
+      std::vector<double> lw;  // column widths of the list entries
+      if (circ) {
+        std::map<int32_t, int> mask;
+        for (int k = 0; k < rp; ++k) {
+          const int32_t pk = ord[(size_t)(o + k)];
+          for (int64_t e = h->near_off[pk]; e < h->near_off[pk + 1]; ++e) mask[h->near[(size_t)e]] |= 1 << k;
         }
-        for (int s = 0; s < nseg; ++s) {
-          const int64_t q0 = d0 + s * qs, q1 = std::min<int64_t>(d1, q0 + qs);
-          double cols = 0.0;
-          for (int64_t q = q0; q < q1; ++q) cols += 2 * h->N[q] + 1;
+        lbase = (int64_t)S.qlist.size();
+        for (const auto& kv : mask) {
+          S.qlist.push_back((kv.first << 8) | kv.second);
+          lw.push_back(2.0 * h->N[kv.first] + 1);
+        }
+        ncol = (int64_t)mask.size();
+      }
+      const int64_t qsg = circ ? (c.QS > 0 ? c.QS : std::max<int64_t>(ncol, 1)) : qs;
+      const int nseg = (int)((ncol + qsg - 1) / qsg);
+      S.gnseg.push_back(nseg);
+      S.gbase.push_back(pb);
+      for (int t = 0; t < S.ntile; ++t) {
+        if (!tile_runs(b, t * RC, (t + 1) * RC)) continue;
+        for (int sg = 0; sg < nseg; ++sg) {
+          const int64_t i0 = sg * qsg, i1 = std::min<int64_t>(ncol, i0 + qsg);
+          double cw = 0.0;
+          for (int64_t i = i0; i < i1; ++i) cw += circ ? lw[(size_t)i] : 2.0 * h->N[d0 + i] + 1;
           It e;
-          e.cost = rows * cols + 64.0 * (double)(q1 - q0);  // MACs + per-disk staging
+          e.cost = rows * cw + 64.0 * (double)(i1 - i0);  // MACs + per-disk staging
           e.r[0] = gi;
           e.r[1] = rp;
           e.r[2] = t;
-          e.r[3] = (int32_t)q0;
-          e.r[4] = (int32_t)q1;
-          e.r[5] = (int32_t)(pb + (int64_t)t * nseg + s);
+          e.r[3] = (int32_t)((circ ? lbase : d0) + i0);
+          e.r[4] = (int32_t)((circ ? lbase : d0) + i1);
+          e.r[5] = (int32_t)(pb + (int64_t)t * nseg + sg);
+          e.r[6] = circ ? 1 : 0;
           its.push_back(e);
         }
       }
       pb += (int64_t)S.ntile * nseg;
+    }
+    if (circ) {  // per-frequency products: (instance, frequency, row tile, column tile)
+      const int Lb = h->cL[b];
+      const int nrt = (int)((Mb + cbm - 1) / cbm), nct = (R + cbn - 1) / cbn;
+      for (int f = 0; f < Lb; ++f)
+        for (int rt = 0; rt < nrt; ++rt)
+          for (int ct = 0; ct < nct; ++ct) {
+            if (!tile_runs(b, ct * cbn, (ct + 1) * cbn)) continue;
+            S.citems.push_back(b);
+            S.citems.push_back(f);
+            S.citems.push_back(rt);
+            S.citems.push_back(ct);
+          }
     }
   }
   S.n_pb = pb;
@@ -686,10 +774,13 @@ static void mfma_build(const mudiff_ctx* h, int R, const MfmaChoice& c, MfmaSche
   for (size_t k = 0; k < its.size(); ++k)
     for (int f = 0; f < MF_REC; ++f) S.items[k * MF_REC + f] = its[k].r[f];
   S.n_items = (int)its.size();
+  S.n_citems = (int)(S.citems.size() / 4);
 }
 
 // Byte layout of the MFMA schedule inside the apply scratch:
 // [head][items][dgrp][grow][gnseg][gbase][partial blocks][scaled input][drow]
+// [qlist][product items][con][transformed inputs][transformed outputs]
+#define MF_NOFF 14
 static size_t mfma_scratch_layout(const mudiff_ctx* h, const MfmaSched& S, size_t* off) {
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -706,6 +797,12 @@ static size_t mfma_scratch_layout(const mudiff_ctx* h, const MfmaSched& S, size_
   off[6] = take((size_t)S.n_pb * S.blk * 16);
   off[7] = take((size_t)S.R * h->N_all * 16);  // the input with its column scale applied
   off[8] = take((size_t)h->M_all * 4);
+  off[9] = take(S.qlist.size() * 4);
+  off[10] = take(S.citems.size() * 4);
+  off[11] = take((size_t)h->B * 4);
+  const size_t zw = S.c.circ ? (size_t)S.R * h->cZ_all * 16 : 0;
+  off[12] = take(zw);
+  off[13] = take(zw);
   return o;
 }
 
@@ -718,22 +815,38 @@ static std::vector<MfmaChoice> mfma_candidates(int R) {
       if (ct > ctmax && ct > 1) continue;
       const int rp = waves / ct;
       if (rp < 1 || rp > 8) continue;
-      for (int qs : {0, 32}) out.push_back(MfmaChoice{ct, rp, qs, 64 * waves});
+      for (int qs : {0, 32}) out.push_back(MfmaChoice{ct, rp, qs, 64 * waves, false});
     }
   return out;
+}
+
+// The circulant form is a candidate when the tables hold it and some
+// instance is worth it (and the caller has not switched it off for R).
+static bool circ_usable(const mudiff_ctx* h, int R) {
+  if (!h->circ || h->M_all >= (1 << 23)) return false;  // column lists hold q << 8
+  auto f = h->circ_modes.find(R);
+  if (f != h->circ_modes.end() && f->second == 0) return false;
+  for (uint8_t c : h->circ_on)
+    if (c) return true;
+  return false;
 }
 
 static MfmaChoice mfma_default(int R) {
   const int ct0 = std::min(4, (R + 7) / 8);
   const int ct = ct0 == 3 ? 4 : ct0;
-  return MfmaChoice{ct, 4 / ct, 0, 256};
+  return MfmaChoice{ct, 4 / ct, 0, 256, false};
 }
 
 // Upload schedule S into the apply scratch at `base` (synchronises; not for
 // use under graph capture).
 static int mfma_upload(mudiff_ctx* h, MfmaSched& S, char* base, hipStream_t s) {
-  size_t off[9];
+  size_t off[MF_NOFF];
   mfma_scratch_layout(h, S, off);
+  if (!S.qlist.empty())
+    HIP_TRY(hipMemcpyAsync(base + off[9], S.qlist.data(), S.qlist.size() * 4, hipMemcpyHostToDevice, s));
+  if (!S.citems.empty())
+    HIP_TRY(hipMemcpyAsync(base + off[10], S.citems.data(), S.citems.size() * 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(base + off[11], S.con.data(), (size_t)h->B * 4, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(base + off[1], S.items.data(), S.items.size() * 4, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(base + off[2], S.dgrp.data(), (size_t)h->M_all * 4, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(base + off[3], S.grow.data(), S.grow.size() * 4, hipMemcpyHostToDevice, s));
@@ -747,7 +860,7 @@ static int mfma_upload(mudiff_ctx* h, MfmaSched& S, char* base, hipStream_t s) {
 
 // Enqueue one MFMA apply with schedule S already uploaded at S.dev_base.
 typedef void (*mf_fn)(DevView, int, const cplx*, const int32_t*, const int32_t*, int, int32_t*,
-                      cplx*, int64_t, int, int, int, int, const int32_t*);
+                      cplx*, int64_t, int, int, int, int, const int32_t*, const int32_t*);
 
 #define MF_TK3(MT, TH, ZK)                                 \
   if (zk == ZK) {                                          \
@@ -773,7 +886,7 @@ static mf_fn mf_select(int mt, int th, int zk, int tk) {
 
 static int mfma_launch(mudiff_ctx* h, const MfmaSched& S, const cplx* x, cplx* y, int op,
                        const int32_t* active, hipStream_t s) {
-  size_t off[9];
+  size_t off[MF_NOFF];
   mfma_scratch_layout(h, S, off);
   char* base = (char*)S.dev_base;
   int32_t* head = (int32_t*)(base + off[0]);
@@ -789,6 +902,15 @@ static int mfma_launch(mudiff_ctx* h, const MfmaSched& S, const cplx* x, cplx* y
   hipLaunchKernelGGL(k_apply_mfma_scale, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, s, h->dv,
                      S.R, x, z, active);
   HIP_TRY(hipGetLastError());
+  cplx* wh = nullptr;
+  const int32_t* con = (const int32_t*)(base + off[11]);
+  if (S.c.circ) {  // well-separated pairs of the marked instances
+    cplx* zh = (cplx*)(base + off[12]);
+    wh = (cplx*)(base + off[13]);
+    rc = circ_launch(h, S.R, z, zh, wh, (const int32_t*)(base + off[10]), S.n_citems, S.cvar, con,
+                     active, s);
+    if (rc != MUDIFF_OK) return rc;
+  }
   if (S.n_items > 0) {
     const int32_t* it = (const int32_t*)(base + off[1]);
 const int TL = 4 * kt + 16 * mt - 1;
@@ -805,14 +927,15 @@ const int TL = 4 * kt + 16 * mt - 1;
     const int grid = std::max(1, std::min(S.n_items, per_cu * h->n_cu));
     hipLaunchKernelGGL(fn, dim3(grid), dim3(S.c.threads), lds, s, h->dv, S.R, (const cplx*)z, active, it,
                        S.n_items, head, part, S.blk, S.npad, kt, S.c.RP, S.c.CT,
-                       (const int32_t*)(base + off[3]));
+                       (const int32_t*)(base + off[3]), (const int32_t*)(base + off[9]));
     HIP_TRY(hipGetLastError());
   }
   const int64_t total = (int64_t)S.R * h->N_all;
   hipLaunchKernelGGL(k_apply_mfma_finish, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
                      h->dv, S.R, x, y, op, (const cplx*)part, S.blk, S.npad, RC,
                      (const int32_t*)(base + off[2]), (const int32_t*)(base + off[8]),
-                     (const int32_t*)(base + off[4]), (const int64_t*)(base + off[5]), active);
+                     (const int32_t*)(base + off[4]), (const int64_t*)(base + off[5]), active,
+                     (const cplx*)wh, con);
   HIP_TRY(hipGetLastError());
   return MUDIFF_OK;
 }
@@ -823,13 +946,15 @@ static size_t mfma_scratch_bytes(mudiff_ctx* h, int R) {
   if (f != h->mfma_bytes.end()) return f->second;
   size_t mx = 0;
   for (MfmaChoice c : mfma_candidates(R)) {
-    for (int qs : {c.QS, MFMA_TAIL_QS}) {  // also the short-segment form used for stragglers
-      c.QS = qs;
-      MfmaSched S;
-      mfma_build(h, R, c, S);
-      size_t off[9];
-      mx = std::max(mx, mfma_scratch_layout(h, S, off));
-    }
+    for (int circ = 0; circ < (h->circ ? 2 : 1); ++circ)
+      for (int qs : {c.QS, MFMA_TAIL_QS}) {  // also the short-segment form used for stragglers
+        c.QS = qs;
+        c.circ = circ != 0;
+        MfmaSched S;
+        mfma_build(h, R, c, S);
+        size_t off[MF_NOFF];
+        mx = std::max(mx, mfma_scratch_layout(h, S, off));
+      }
   }
   h->mfma_bytes[R] = mx;
   return mx;
@@ -849,7 +974,18 @@ static int mfma_autotune(mudiff_ctx* h, int R, const cplx* x, cplx* y, char* scr
   float best = 0.0f;
   MfmaChoice bc = mfma_default(R);
   int rc = MUDIFF_OK;
-  for (const MfmaChoice& c : mfma_candidates(R)) {
+  std::vector<MfmaChoice> cands;
+  auto fc = h->circ_modes.find(R);
+  const int cmode = fc != h->circ_modes.end() ? fc->second : -1;
+  const bool cu = circ_usable(h, R);
+  for (MfmaChoice c : mfma_candidates(R)) {
+    if (cmode != 1 || !cu) cands.push_back(c);
+    if (cu) {
+      c.circ = true;
+      cands.push_back(c);
+    }
+  }
+  for (const MfmaChoice& c : cands) {
     if (c.QS > 0 && mmax <= c.QS) continue;
     MfmaSched S;
     mfma_build(h, R, c, S);
@@ -886,7 +1022,9 @@ static int mfma_prepare(mudiff_ctx* h, int R, const cplx* x, cplx* y, char* scra
   auto f = h->mfma_choice.find(R);
   if (f == h->mfma_choice.end()) {
     if (x && y && h->mfma_tune) return mfma_autotune(h, R, x, y, scratch, s);
-    h->mfma_choice[R] = mfma_default(R);
+    MfmaChoice d = mfma_default(R);
+    d.circ = circ_usable(h, R);
+    h->mfma_choice[R] = d;
     f = h->mfma_choice.find(R);
   }
   MfmaChoice c = f->second;
@@ -1277,7 +1415,9 @@ extern "C" int mudiff_apply_config(mudiff_t h, int R, int* kind, int* ct, int* r
   if (use_mfma(h, R)) {
     k = 1;
     auto f = h->mfma_choice.find(R);
-    const MfmaChoice ch = f != h->mfma_choice.end() ? f->second : mfma_default(R);
+    MfmaChoice ch = f != h->mfma_choice.end() ? f->second : mfma_default(R);
+    if (f == h->mfma_choice.end()) ch.circ = circ_usable(h, R);
+    if (ch.circ) k = 3;
     c = ch.CT;
     r = ch.RP;
     q = ch.QS;
@@ -1302,12 +1442,33 @@ extern "C" int mudiff_set_apply_config(mudiff_t h, int R, int ct, int rp, int qs
   if (!h) return fail(MUDIFF_ERR_INVALID, "NULL handle");
   if (R < 1) return fail(MUDIFF_ERR_INVALID, "R < 1");
   if (!use_mfma(h, R)) return fail(MUDIFF_ERR_INVALID, "this apply does not run on MFMA");
-  const MfmaChoice want{ct, rp, qs, threads};
+  MfmaChoice want{ct, rp, qs, threads, false};
   for (const MfmaChoice& c : mfma_candidates(R))
     if (c == want) {
+      auto f = h->circ_modes.find(R);
+      want.circ = circ_usable(h, R) && (f == h->circ_modes.end() || f->second != 0);
       h->mfma_choice[R] = want;
       h->mfma_time_ms.erase(R);
       return MUDIFF_OK;
     }
   return fail(MUDIFF_ERR_INVALID, "MFMA tile not among the candidates");
+}
+
+extern "C" int mudiff_set_circulant(mudiff_t h, int R, int mode) {
+  if (!h) return fail(MUDIFF_ERR_INVALID, "NULL handle");
+  if (R < 1) return fail(MUDIFF_ERR_INVALID, "R < 1");
+  if (mode < -1 || mode > 1) return fail(MUDIFF_ERR_INVALID, "mode must be -1, 0 or 1");
+  if (!h->circ) return fail(MUDIFF_ERR_INVALID, "the handle was built without MUDIFF_TABLES_CIRCULANT");
+  h->circ_modes[R] = mode;
+  auto f = h->mfma_choice.find(R);
+  if (f != h->mfma_choice.end()) {
+    if (h->mfma_time_ms.count(R)) {  // timed choice: time again with the new mode
+      h->mfma_choice.erase(f);
+      h->mfma_time_ms.erase(R);
+    } else {  // fixed tile: keep it, switch the form
+      f->second.circ = mode != 0 && circ_usable(h, R);
+    }
+  }
+  if (h->mfma_sched.R == R) h->mfma_sched.R = 0;  // rebuild at the next apply
+  return MUDIFF_OK;
 }

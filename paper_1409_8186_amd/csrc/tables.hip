@@ -205,16 +205,36 @@ int64_t lane_layout(int B, const int64_t* disk_off, const int32_t* n_modes, int*
   return o;
 }
 
+// Embedding length of the circulant form of instance [d0, d1): 2 (N' + N'') + 1
+// with N' >= N'' its two largest orders (0 for fewer than two disks).
+int64_t circ_len(const int32_t* n_modes, int64_t d0, int64_t d1) {
+  if (d1 - d0 < 2) return 0;
+  int a = -1, c = -1;
+  for (int64_t p = d0; p < d1; ++p) {
+    const int n = n_modes[p];
+    if (n > a) {
+      c = a;
+      a = n;
+    } else if (n > c) {
+      c = n;
+    }
+  }
+  return 2 * (int64_t)(a + c) + 1;
+}
+
 namespace {
 struct Layout {
   size_t off_cx, off_cy, off_a, off_kd, off_N, off_inst, off_moff, off_dtab, off_idisk, off_imode,
       off_ipair, off_toff, off_t, off_Jd, off_Hd, off_sJ, off_invSH, off_Ldiag, off_udisk, off_sched,
       off_lt, off_ltoff;
+  // circulant form (MUDIFF_TABLES_CIRCULANT)
+  size_t off_cL = 0, off_cTo = 0, off_cZo = 0, off_cWo = 0, off_ctw = 0, off_cnear = 0, off_cT = 0;
+  int64_t c_tw = 0, c_T = 0;  // twiddles, transformed symbols (complex values)
   size_t sched_bytes, total;
 };
 
 Layout make_layout(int B, const int64_t* disk_off, const int32_t* n_modes, int64_t N_all,
-                   int64_t P_all, int64_t T_all, int64_t D_all) {
+                   int64_t P_all, int64_t T_all, int64_t D_all, int flags) {
   Layout L{};
   const int64_t M = disk_off[B];
   size_t o = 0;
@@ -248,6 +268,21 @@ Layout make_layout(int B, const int64_t* disk_off, const int32_t* n_modes, int64
   const int64_t lt = lane_layout(B, disk_off, n_modes, &lane_N, nullptr);
   L.off_lt = take(lt * 16);
   L.off_ltoff = take(M * 8);
+  if (flags & MUDIFF_TABLES_CIRCULANT) {
+    for (int b = 0; b < B; ++b) {
+      const int64_t Lb = circ_len(n_modes, disk_off[b], disk_off[b + 1]);
+      const int64_t Mb = disk_off[b + 1] - disk_off[b];
+      L.c_tw += Lb;
+      L.c_T += Lb * Mb * Mb;
+    }
+    L.off_cL = take((size_t)B * 4);
+    L.off_cTo = take((size_t)B * 8);
+    L.off_cZo = take((size_t)B * 8);
+    L.off_cWo = take((size_t)B * 8);
+    L.off_ctw = take((size_t)L.c_tw * 16);
+    L.off_cnear = take((size_t)P_all);
+    L.off_cT = take((size_t)L.c_T * 16);
+  }
 
   L.total = o;
   return L;
@@ -276,17 +311,22 @@ bool sizes_of(int B, const int64_t* disk_off, const int32_t* n_modes, int64_t* N
 
 // ------------------------------------------------------------------ C ABI
 extern "C" size_t mudiff_tables_workspace_size(int B, const int64_t* disk_off,
-                                               const int32_t* n_modes) {
+                                               const int32_t* n_modes, int flags) {
   int64_t N_all, P_all, T_all, D_all;
+  if (flags & ~MUDIFF_TABLES_CIRCULANT) return 0;
   if (!sizes_of(B, disk_off, n_modes, &N_all, &P_all, &T_all, &D_all)) return 0;
-  return make_layout(B, disk_off, n_modes, N_all, P_all, T_all, D_all).total;
+  return make_layout(B, disk_off, n_modes, N_all, P_all, T_all, D_all, flags).total;
 }
+
+int circ_build(mudiff_ctx* h, hipStream_t s);
 
 extern "C" int mudiff_tables(int B, const int64_t* disk_off, const double* centers,
                              const double* radii, const int32_t* n_modes, const double* k,
-                             void* workspace, size_t ws_bytes, void* stream, mudiff_t* out) {
+                             void* workspace, size_t ws_bytes, int flags, void* stream,
+                             mudiff_t* out) {
   if (!out) return fail(MUDIFF_ERR_INVALID, "out is NULL");
   *out = nullptr;
+  if (flags & ~MUDIFF_TABLES_CIRCULANT) return fail(MUDIFF_ERR_INVALID, "unknown flags");
   if (B < 1 || !disk_off || !centers || !radii || !n_modes || !k)
     return fail(MUDIFF_ERR_INVALID, "B < 1 or a NULL pointer");
   if (disk_off[0] != 0) return fail(MUDIFF_ERR_INVALID, "disk_off[0] != 0");
@@ -306,6 +346,9 @@ extern "C" int mudiff_tables(int B, const int64_t* disk_off, const double* cente
   for (int b = 0; b < B; ++b)
     if (!(k[b] > 0.0) || !std::isfinite(k[b]))
       return fail(MUDIFF_ERR_INVALID, "k must be finite and > 0");
+  if (flags & MUDIFF_TABLES_CIRCULANT)
+    for (int64_t p = 0; p < M; ++p)
+      if (n_modes[p] > 31) return fail(MUDIFF_ERR_INVALID, "the circulant form needs N_p <= 31");
   // disjointness (sec. 2): b_pq > a_p + a_q inside every instance
   for (int b = 0; b < B; ++b)
     for (int64_t p = disk_off[b]; p < disk_off[b + 1]; ++p)
@@ -318,7 +361,7 @@ extern "C" int mudiff_tables(int B, const int64_t* disk_off, const double* cente
   int64_t N_all, P_all, T_all, D_all;
   if (!sizes_of(B, disk_off, n_modes, &N_all, &P_all, &T_all, &D_all))
     return fail(MUDIFF_ERR_INVALID, "bad sizes");
-  Layout L = make_layout(B, disk_off, n_modes, N_all, P_all, T_all, D_all);
+  Layout L = make_layout(B, disk_off, n_modes, N_all, P_all, T_all, D_all, flags);
   if (!workspace) return fail(MUDIFF_ERR_INVALID, "workspace is NULL");
   if (ws_bytes < L.total)
     return fail(MUDIFF_ERR_NOMEM, "tables workspace needs " + std::to_string(L.total) + " bytes");
@@ -405,6 +448,66 @@ extern "C" int mudiff_tables(int B, const int64_t* disk_off, const double* cente
   }
   h->sched_base = base + L.off_sched;
   h->sched_bytes = L.sched_bytes;
+  std::vector<int64_t> cTo, cWo;
+  if (flags & MUDIFF_TABLES_CIRCULANT) {
+    h->circ = true;
+    h->cL.assign(B, 0);
+    h->cZo.assign(B, 0);
+    cTo.assign(B, 0);
+    cWo.assign(B, 0);
+    int64_t to_ = 0, zo = 0, wo = 0;
+    for (int b = 0; b < B; ++b) {
+      const int64_t Lb = circ_len(n_modes, disk_off[b], disk_off[b + 1]);
+      const int64_t Mb = disk_off[b + 1] - disk_off[b];
+      h->cL[b] = (int32_t)Lb;
+      cTo[b] = to_;
+      h->cZo[b] = zo;
+      cWo[b] = wo;
+      to_ += Lb * Mb * Mb;
+      zo += Lb * Mb;
+      wo += Lb;
+    }
+    h->cZ_all = zo;
+    v.cL = (const int32_t*)(base + L.off_cL);
+    v.cTo = (const int64_t*)(base + L.off_cTo);
+    v.cZo = (const int64_t*)(base + L.off_cZo);
+    v.cWo = (const int64_t*)(base + L.off_cWo);
+    v.ctw = (const cplx*)(base + L.off_ctw);
+    v.cT = (const cplx*)(base + L.off_cT);
+    // close pairs (k b_pq < N_p + N_q): direct form; the rest go through the
+    // circulant form.  Decided here, once, on the host.
+    h->near_off.assign(M + 1, 0);
+    h->circ_nearflag.assign(P_all, 0);
+    std::vector<std::vector<int32_t>> nl((size_t)M);
+    int64_t g = 0;
+    h->circ_on.assign(B, 0);
+    for (int b = 0; b < B; ++b) {
+      double far_w = 0.0, all_w = 0.0;
+      for (int64_t p = disk_off[b]; p < disk_off[b + 1]; ++p)
+        for (int64_t q = p + 1; q < disk_off[b + 1]; ++q, ++g) {
+          const double d = std::hypot(centers[2 * p] - centers[2 * q], centers[2 * p + 1] - centers[2 * q + 1]);
+          const bool nr = k[b] * d < (double)(n_modes[p] + n_modes[q]);
+          const double w = 2.0 * (2.0 * n_modes[p] + 1) * (2.0 * n_modes[q] + 1);
+          all_w += w;
+          if (nr) {
+            h->circ_nearflag[g] = 1;
+            nl[p].push_back((int32_t)q);
+            nl[q].push_back((int32_t)p);
+            h->n_near += 2;
+          } else {
+            far_w += w;
+            h->n_far += 2;
+          }
+        }
+      h->circ_on[b] = (h->cL[b] > 0 && far_w >= 0.5 * all_w) ? 1 : 0;
+    }
+    for (int64_t p = 0; p < M; ++p) {
+      std::sort(nl[p].begin(), nl[p].end());
+      h->near_off[p + 1] = h->near_off[p] + (int64_t)nl[p].size();
+    }
+    h->near.reserve((size_t)h->near_off[M]);
+    for (int64_t p = 0; p < M; ++p) h->near.insert(h->near.end(), nl[p].begin(), nl[p].end());
+  }
 
   hipStream_t s = (hipStream_t)stream;
   auto up = [&](const void* dst, const void* src, size_t bytes) {
@@ -428,6 +531,13 @@ extern "C" int mudiff_tables(int B, const int64_t* disk_off, const double* cente
   chk(up(v.ipair, h->ipair.data(), (B + 1) * 8), "upload ipair");
   chk(up(v.toff, h->toff.data(), (P_all + 1) * 8), "upload toff");
   chk(up(v.ltoff, h->ltoff.data(), M * 8), "upload ltoff");
+  if (h->circ) {
+    chk(up(v.cL, h->cL.data(), (size_t)B * 4), "upload cL");
+    chk(up(v.cTo, cTo.data(), (size_t)B * 8), "upload cTo");
+    chk(up(v.cZo, h->cZo.data(), (size_t)B * 8), "upload cZo");
+    chk(up(v.cWo, cWo.data(), (size_t)B * 8), "upload cWo");
+    if (P_all > 0) chk(up(base + L.off_cnear, h->circ_nearflag.data(), (size_t)P_all), "upload near flags");
+  }
   // the uploads read pageable host memory that this function owns only
   // until it returns: finish them before the kernels are enqueued
   chk(hipStreamSynchronize(s), "upload sync");
@@ -442,6 +552,11 @@ extern "C" int mudiff_tables(int B, const int64_t* disk_off, const double* cente
   if (P_all > 0) {
     hipLaunchKernelGGL(k_pair_tables, dim3((unsigned)((P_all + 63) / 64)), dim3(64), 0, s, v, P_all);
     chk(hipGetLastError(), "k_pair_tables");
+  }
+  if (st == MUDIFF_OK && h->circ) {
+    h->circ_near_dev = (const uint8_t*)(base + L.off_cnear);
+    const int rc = circ_build(h, s);
+    if (rc != MUDIFF_OK) st = rc;
   }
   if (st != MUDIFF_OK) {
     delete h;

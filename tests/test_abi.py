@@ -43,10 +43,10 @@ def test_every_declared_symbol_is_exported(lib):
     assert sorted(_lib.SIGNATURES) == names
 
 
-def _sizes(lib, disk_off, n_modes):
+def _sizes(lib, disk_off, n_modes, flags=0):
     d = np.ascontiguousarray(disk_off, np.int64)
     n = np.ascontiguousarray(n_modes, np.int32)
-    return lib.mudiff_tables_workspace_size(len(d) - 1, d.ctypes.data, n.ctypes.data)
+    return lib.mudiff_tables_workspace_size(len(d) - 1, d.ctypes.data, n.ctypes.data, flags)
 
 
 def test_workspace_size_queries(lib):
@@ -59,9 +59,15 @@ def test_workspace_size_queries(lib):
     # monotone in the number of modes
     assert _sizes(lib, [0, 4], [12] * 4) > _sizes(lib, [0, 4], [8] * 4)
     assert _sizes(lib, [0, 4], [30] * 4) > _sizes(lib, [0, 4], [20] * 4)
+    # the circulant form adds sum_b L_b M_b^2 complex values, L_b = 2 (N' + N'') + 1
+    base = _sizes(lib, [0, 40], [10] * 40)
+    circ = _sizes(lib, [0, 40], [10] * 40, flags=1)
+    assert circ - base >= 41 * 40 * 40 * 16
+    assert circ - base < 41 * 40 * 40 * 16 + 41 * 16 + 40 * 39 // 2 + 8 * 256
+    assert _sizes(lib, [0, 4], [3] * 4, flags=2) == 0         # unknown flag
 
 
-def _tables(lib, centers, radii, n_modes, k, ws_bytes=1 << 40, ws_ptr=256):
+def _tables(lib, centers, radii, n_modes, k, ws_bytes=1 << 40, ws_ptr=256, flags=0):
     c = np.ascontiguousarray(centers, np.float64)
     r = np.ascontiguousarray(radii, np.float64)
     n = np.ascontiguousarray(n_modes, np.int32)
@@ -69,7 +75,8 @@ def _tables(lib, centers, radii, n_modes, k, ws_bytes=1 << 40, ws_ptr=256):
     d = np.ascontiguousarray([0, len(r)], np.int64)
     h = ctypes.c_void_p()
     st = lib.mudiff_tables(1, d.ctypes.data, c.ctypes.data, r.ctypes.data, n.ctypes.data,
-                           kk.ctypes.data, ctypes.c_void_p(ws_ptr), ws_bytes, None, ctypes.byref(h))
+                           kk.ctypes.data, ctypes.c_void_p(ws_ptr), ws_bytes, flags, None,
+                           ctypes.byref(h))
     return st, lib.mudiff_last_error().decode()
 
 
@@ -144,3 +151,17 @@ def test_set_operator_validation(lib):
     assert lib.mudiff_interior_field(None, 1, w, w, 0, 1, w, w, w, 4096, None) == 1
     assert lib.mudiff_interior_workspace_size(None, 1) == 0
     assert lib.mudiff_rhs_point(None, 1, w, w, 0, None) == 1
+
+
+def test_circulant_validation(lib):
+    """The circulant flag: unknown flags and orders beyond the form's limit are
+    rejected on the host; the pair classification and mode calls reject a
+    NULL handle and bad modes."""
+    c = [[0, 0], [3, 0], [0, 3]]
+    st, msg = _tables(lib, c, [1, 1, 1], [4, 4, 4], 2.0, flags=4)
+    assert st == 1 and "flag" in msg
+    st, msg = _tables(lib, c, [1, 1, 1], [4, 32, 4], 2.0, flags=1)
+    assert st == 1 and "31" in msg                              # beyond the MFMA tile range
+    far, near = ctypes.c_int64(-1), ctypes.c_int64(-1)
+    assert lib.mudiff_circulant_info(None, ctypes.byref(far), ctypes.byref(near), None) == 1
+    assert lib.mudiff_set_circulant(None, 8, 1) == 1

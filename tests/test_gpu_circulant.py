@@ -1,0 +1,175 @@
+"""GPU parity of the circulant-embedded form of the well-separated blocks
+(MUDIFF_TABLES_CIRCULANT; the FFT Toeplitz products of the paper's sec. 5)
+against the dense CPU oracle, element by element, on seeded clusters whose
+pairs straddle the gate k b_pq = N_p + N_q (close pairs stay in the direct
+form).  The bar is the operator apply's: 1e-12 relative per column; solves at
+tol 1e-12 against LU: 1e-10.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import geometry, operator, rhs, solve
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_1409_8186_amd import Problem
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return Problem
+
+
+def _dense(cl):
+    L = operator.efie_matrix(cl.centers, cl.radii, cl.n_modes, cl.k)
+    D = operator.efie_diagonal(cl.radii, cl.n_modes, cl.k)
+    return L, operator.preconditioned(L, D)
+
+
+def _near_pairs(cl):
+    """Ordered pairs below the gate, counted from the geometry alone."""
+    b, _ = geometry.pair_geometry(cl.centers)
+    S = cl.n_modes[:, None] + cl.n_modes[None, :]
+    near = cl.k * b < S
+    np.fill_diagonal(near, False)
+    return int(near.sum())
+
+
+def _mixed(seed, M=30):
+    """Radii 0.3..1, k = 6, N_p = ceil(k a_p) + 4 (7..10): about one pair in
+    ten below the gate."""
+    return synth.small_random(seed, M, 0.3, 1.0, 3.6 * math.sqrt(M), 0.1, 6.0, 4)
+
+
+def _batch():
+    """A mixed instance, a dense low-frequency one (mostly close pairs: it stays
+    in the direct form), another mixed one with other orders, and one disk."""
+    one = synth.Cluster(np.array([[0.5, -0.2]]), np.array([0.7]), np.array([6]), 6.0)
+    low = synth.small_random(505, 10, 0.5, 0.9, 6.0, 0.1, 1.0, 6)
+    return [_mixed(501), low, synth.small_random(502, 18, 0.2, 0.8, 16.0, 0.1, 9.0, 3), one]
+
+
+def test_circulant_classification(P):
+    cls = _batch()
+    pr = P.from_clusters(cls, circulant=True)
+    info = pr.circulant_info()
+    near = sum(_near_pairs(c) for c in cls)
+    total = sum(c.M * (c.M - 1) for c in cls)
+    say("circulant info", info, "near (host count)", near, "of", total)
+    assert info["near_pairs"] == near and info["far_pairs"] == total - near
+    assert 0 < near < total
+    Ns = [np.sort(c.n_modes)[::-1] for c in cls if c.M > 1]
+    assert info["L_max"] == max(2 * (int(n[0]) + int(n[1])) + 1 for n in Ns)
+    assert P.from_clusters(cls).circulant_info() == {"far_pairs": 0, "near_pairs": 0, "L_max": 0}
+
+
+@pytest.mark.parametrize("R", [8, 13, 32, 40, 64])
+def test_circulant_matvec(P, R):
+    """Every product tile of the per-frequency step (R picks it: 8, 16, 32 or
+    64 columns) with ragged column counts, on instances in and out of the form,
+    for A = D^-1 L, L and L^T."""
+    cls = _batch()
+    say("circulant matvec R", R)
+    pr = P.from_clusters(cls, circulant=True)
+    pr.set_circulant(R, 1)
+    rng = np.random.default_rng(700 + R)
+    Xs = [rng.normal(size=(R, c.n_tot)) + 1j * rng.normal(size=(R, c.n_tot)) for c in cls]
+    x = pr.pack(Xs)
+    for op in (1, 0, 2):
+        y = pr.matvec(x, R=R, op=op)
+        assert pr.apply_config(R)["kind"] == "circulant"
+        for c, X, Y in zip(cls, Xs, pr.split(y, R)):
+            L, A = _dense(c)
+            Mx = {1: A, 0: L, 2: L.T}[op]
+            e = rel(Y.cpu().numpy(), X @ Mx.T)
+            assert e < 1e-12, (op, c.M, e)
+    # the direct form on the same handle agrees
+    pr.set_circulant(R, 0)
+    y = pr.matvec(x, R=R, op=1)
+    assert pr.apply_config(R)["kind"] == "mfma"
+    for c, X, Y in zip(cls, Xs, pr.split(y, R)):
+        assert rel(Y.cpu().numpy(), X @ _dense(c)[1].T) < 1e-12
+
+
+def test_circulant_close_pair_lists_every_tile(P):
+    """Denser clusters (13-50% of the pairs close, up to 43 close neighbours per
+    group of 8 rows, so that 32-entry segments split the lists; the 9-disk one
+    falls below half far work and stays direct) under every MFMA tile the
+    autotuner may pick, with the circulant form on."""
+    cls = [synth.small_random(510 + i, M, 0.4, 1.0, 2.2 * math.sqrt(M), 0.1, 7.0, 9)
+           for i, M in enumerate((60, 9, 45))]
+    R = 19
+    pr = P.from_clusters(cls, circulant=True)
+    info = pr.circulant_info()
+    say("close-pair lists: info", info)
+    rng = np.random.default_rng(77)
+    Xs = [rng.normal(size=(R, c.n_tot)) + 1j * rng.normal(size=(R, c.n_tot)) for c in cls]
+    refs = [X @ _dense(c)[1].T for c, X in zip(cls, Xs)]
+    x = pr.pack(Xs)
+    pr.set_circulant(R, 1)
+    ctmax = max(1, min(4, (R + 7) // 8))
+    for waves in (4, 8):
+        for ct in (1, 2, 4):
+            if ct > ctmax and ct > 1:
+                continue
+            for qs in (0, 32):
+                pr.set_apply_config(R, ct, waves // ct, qs, 64 * waves)
+                assert pr.apply_config(R)["kind"] == "circulant"
+                y = pr.matvec(x, R=R, op=1)
+                for Y, ref in zip(pr.split(y, R), refs):
+                    assert rel(Y.cpu().numpy(), ref) < 1e-12, (ct, waves, qs)
+
+
+def _lu(cl, betas):
+    L = operator.efie_matrix(cl.centers, cl.radii, cl.n_modes, cl.k)
+    U = rhs.planewave(cl.centers, cl.radii, cl.n_modes, cl.k, betas)
+    return solve.efie_solve_lu(L, U)
+
+
+def test_circulant_gmres_graph_and_stragglers(P):
+    """Lockstep GMRES on the circulant form: every column equals LU, graph
+    replays are bit-identical to the eager solve, and a batch with one hard
+    instance runs its straggler phase (short close-pair segments, product
+    tiles of the running columns only) to the same LU solutions."""
+    cls = [_mixed(520), _mixed(521, M=22)]
+    R = 8
+    betas = np.stack([synth.uniform_angles(R), synth.uniform_angles(R) + 0.2])
+    pr = P.from_clusters(cls, circulant=True)
+    pr.set_circulant(R, 1)
+    rho, flag, relres, iters, _ = pr.gmres(betas=betas, restart=30, tol=1e-12, maxit=3000)
+    say("circulant gmres iterations", iters.cpu().numpy().tolist())
+    assert pr.apply_config(R)["kind"] == "circulant"
+    assert torch.all(flag == 0), flag
+    for b, (c, Y) in enumerate(zip(cls, pr.split(rho, R))):
+        assert rel(Y.cpu().numpy(), _lu(c, betas[b])) < 1e-10
+    for rep in range(3):
+        rho_g, flag_g, _, iters_g, _ = pr.gmres(betas=betas, restart=30, tol=1e-12, maxit=3000,
+                                                graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(iters_g, iters) and torch.equal(flag_g, flag) and torch.equal(rho_g, rho), rep
+    B = 32
+    easy = [synth.small_random(300 + i, 4, 0.3, 0.5, 60.0, 5.0, 2.0, 3) for i in range(B - 1)]
+    hard = _mixed(530, M=26)
+    allc = easy[:B // 2] + [hard] + easy[B // 2:]
+    bet = np.tile(synth.uniform_angles(R), (B, 1))
+    pr2 = P.from_clusters(allc, circulant=True)
+    pr2.set_circulant(R, 1)
+    rho, flag, _, iters, _ = pr2.gmres(betas=bet, restart=10, tol=1e-12, maxit=5000)
+    it = iters.cpu().numpy().reshape(B, R)
+    say("  straggler: easy max", int(np.delete(it, B // 2, axis=0).max()), "hard", it[B // 2].tolist())
+    assert torch.all(flag == 0)
+    assert it[B // 2].min() > 4 * np.delete(it, B // 2, axis=0).max()
+    for c, b, Y in zip(allc, bet, pr2.split(rho, R)):
+        assert rel(Y.cpu().numpy(), _lu(c, b)) < 1e-10

@@ -1,20 +1,24 @@
 """Benchmark of the multiple-scattering hot path on one MI355X.
 
-Workload (one RHS): M = 400 disks of radius 0.5 placed by seeded rejection in
-[0,60]^2 with edge gap 0.2, k = 2 pi, N_p = 12 (10,000 complex128 unknowns),
-incidence pi/4, GMRES(50) to a 1e-8 relative residual, far field at 720 angles.
+Default line (the batched multi-right-hand-side workload, the largest that the
+headline metric is quoted on): M = 1000 disks, radii U[0.3, 1] placed by seeded
+rejection in [0,150]^2 with edge gap 0.1, k = 10, N_p = ceil(k a_p) + 10
+(34,932 complex128 unknowns), 256 incidence angles.
 
-One step = the whole hot path on that input: geometry and Bessel/Hankel tables
-on the device, plane-wave right-hand side, preconditioned restarted GMRES to
-1e-8 (operator applies + Gram-Schmidt), far field.  Inputs are host arrays of
-a few KB (centers, radii); everything else is produced and kept in HBM.
+One step = one operator apply A = D^-1 L on all 256 columns (the metric's
+complex unknown.RHS matvecs), inputs resident in HBM: input scale, forward
+transforms and per-frequency FP64-MFMA products of the well-separated pairs
+(circulant-embedded form), the close pairs on the MFMA work queue, output pass.
+value = N_tot * R / (mean step time).  Also printed: the phase times of the
+timed applies (HIP events on the launch stream), the roofline of the dominant
+kernel (the per-frequency products), time-to-1e-8 of the whole 256-column
+solve (tables + right-hand sides + lockstep GMRES(50)), the direct form's
+apply time, the one-RHS workload's step (tables + GMRES(50) to 1e-8 + far
+field), and the CPU oracle timed on a bounded sample.
 
-Printed (one JSON line): value = complex unknown.RHS operator applications per
-second over the whole step (N_tot * R * applies / step time), plus the
-time-to-1e-8, the operator-apply rate alone, the roofline of the dominant
-kernel (the operator apply) and the CPU oracle timed on a bounded sample.
-
-    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline] [--no-solve]
+    python bench.py --workload one_rhs | uneven | differentiation | dort | formulations |
+                               nearfield | penetrable      (documentation runs)
 """
 from __future__ import annotations
 
@@ -31,10 +35,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_VECTOR_TFLOPS = 78.6
+PEAK_FP64_MFMA_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_apply_one_rhs_traffic.txt")
 APPLY_SRC = [os.path.join(ROOT, "paper_1409_8186_amd", "csrc", f)
              for f in ("matvec.hip", "common.h", "tables.hip")]
+CIRC_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_circ_gemm_multi_rhs_traffic.txt")
+CIRC_SRC = [os.path.join(ROOT, "paper_1409_8186_amd", "csrc", f)
+            for f in ("circulant.hip", "common.h")]
 
 
 def measured_peaks(achieved, kind="fp64_fma"):
@@ -47,10 +55,11 @@ def measured_peaks(achieved, kind="fp64_fma"):
             "copy_GBps_measured": probe("copy", 1 << 30)}
 
 
-def apply_source_sha():
-    """Digest of the sources that define the one-RHS apply kernels and their data."""
+def apply_source_sha(files=None):
+    """Digest of the sources that define a kernel and its data (default: the
+    one-RHS apply)."""
     h = hashlib.sha256()
-    for f in APPLY_SRC:
+    for f in files or APPLY_SRC:
         h.update(open(f, "rb").read())
     return h.hexdigest()[:16]
 
@@ -75,19 +84,34 @@ def algorithmic_bytes(n_modes, R=1):
     return 16.0 * pair + ntot * (8 + 16) + 2 * 16.0 * R * ntot
 
 
-def traffic_per_launch():
-    """HBM bytes per apply launch from the committed rocprofv3 counter summary,
-    or None if absent or taken on a different revision of the kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+def traffic_per_launch(path=TRAFFIC_FILE, files=None):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, or None
+    if absent or taken on a different revision of the kernel source."""
+    if not os.path.exists(path):
         return None
-    txt = open(TRAFFIC_FILE).read()
-    sha = apply_source_sha()
+    txt = open(path).read()
+    sha = apply_source_sha(files)
     m = re.search(r"source_sha256_16:\s*([0-9a-f]+)", txt)
     f = re.search(r"fetch_bytes_per_launch:\s*([0-9.eE+]+)", txt)
     w = re.search(r"write_bytes_per_launch:\s*([0-9.eE+]+)", txt)
     if not (m and f and w) or m.group(1) != sha:
         return None
     return float(f.group(1)) + float(w.group(1))
+
+
+def circ_traffic_per_launch(tile):
+    """HBM bytes per launch of the per-frequency product variant `tile`
+    (rows, cols, kstep, buffers) from the committed counter summary, or None if
+    absent, not measured for that variant, or taken on another source revision."""
+    if not os.path.exists(CIRC_TRAFFIC_FILE):
+        return None
+    txt = open(CIRC_TRAFFIC_FILE).read()
+    m = re.search(r"source_sha256_16[^:]*:\s*([0-9a-f]+)", txt)
+    if not m or m.group(1) != apply_source_sha(CIRC_SRC):
+        return None
+    pat = r"variant %dx%d K%d buffers %d .*bytes_per_launch (\d+)" % tuple(tile)
+    v = re.search(pat, txt)
+    return float(v.group(1)) if v else None
 
 
 def _blas_threads():
@@ -186,25 +210,6 @@ def other_workload(args):
         r.update(measured_peaks(flops / t / 1e12, "fp64_mfma"))
         return r
 
-    if args.workload == "multi_rhs":
-        cl = synth.multi_rhs()
-        R = len(cl.betas)
-        P = Problem.from_cluster(cl)
-        t = time_apply(P, R, cl.n_tot, reps=3)
-        flops = algorithmic_flops(cl.n_modes, R)
-        out = {**base, "metric": "complex unknown·RHS matvecs/s", "value": cl.n_tot * R / t,
-               "unit": "complex unknown·RHS matvecs/s", "ms_per_step": t * 1e3,
-               "config": {"workload": "multi_rhs: M=1000, a~U[0.3,1], [0,150]^2, k=10, "
-                                      "N_p=ceil(10a)+10, R=256, one operator apply per step",
-                          "n_unknowns": cl.n_tot, "R": R},
-               "roofline": mfma_roofline(flops, t, P.apply_config(R))}
-        if args.solve:
-            rho, flag, its, t_s = _segmented_gmres(P, cl.betas[None, :], 50, 1e-8, "multi_rhs",
-                                                   seg_cycles=10)
-            out["time_to_1e8_s"] = t_s
-            out["gmres_iters_max"] = int(its.max())
-            out["all_converged"] = bool((flag == 0).all())
-        return out
     if args.workload == "uneven":
         insts = synth.uneven_instances()
         R = 8
@@ -582,24 +587,255 @@ def penetrable_workload(base):
     return out
 
 
+def cpu_baseline_multi(cl, R, t_budget=10.0):
+    """The oracle on the host for the 256-column apply: dense rows of L (oracle
+    row blocks of whole disks) times the 256 input columns (ZGEMM), on the first
+    disks until about t_budget seconds of assembly; the apply time is
+    extrapolated to all disks by the share of unknowns covered."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import operator
+    rng = np.random.default_rng(3)
+    X = rng.normal(size=(R, cl.n_tot)) + 1j * rng.normal(size=(R, cl.n_tot))
+    blocks, t_asm, rows = [], 0.0, 0
+    for p in range(cl.M):
+        t0 = time.perf_counter()
+        blocks.append(operator.efie_row_block(cl.centers, cl.radii, cl.n_modes, cl.k, p))
+        t_asm += time.perf_counter() - t0
+        rows += blocks[-1].shape[0]
+        if t_asm >= t_budget:
+            break
+    Lrows = np.concatenate(blocks)
+    del blocks
+    ts = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        Lrows @ X.T
+        ts.append(time.perf_counter() - t0)
+    t_mm = sorted(ts)[1]
+    scale = cl.n_tot / rows
+    t_apply = t_mm * scale
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    return {"value": cl.n_tot * R / t_apply, "unit": "complex unknown·RHS matvecs/s",
+            "cores": int(threads), "kind": "oracle",
+            "sample": (f"oracle dense rows of the first {p + 1} disks ({rows} of "
+                       f"{cl.n_tot} unknowns; assembly {t_asm:.1f} s) times the {R} columns "
+                       f"(ZGEMM, median of 3: {t_mm:.3f} s), extrapolated by unknowns to the "
+                       f"whole apply: {t_apply:.2f} s; dense assembly of the whole operator "
+                       f"extrapolated: {t_asm * scale:.0f} s"),
+            "apply_s_extrapolated": t_apply, "assembly_s_extrapolated": t_asm * scale}
+
+
+def one_rhs_step(args, n_steps, n_warm, with_cpu):
+    """The one-RHS workload: tables + GMRES(50) to 1e-8 + far field per step."""
+    import torch
+
+    import synth
+    from paper_1409_8186_amd import Problem
+    cl = synth.one_rhs()
+    beta = [[math.pi / 4]]
+    th = torch.tensor(cl.thetas, device="cuda")
+    info = {}
+
+    def step():
+        P = Problem.from_cluster(cl)                          # geometry + tables
+        rho, flag, relres, iters, _ = P.gmres(betas=beta, restart=50, tol=1e-8, maxit=20000,
+                                              graph=args.graph)
+        a = P.farfield(rho, th)                              # far field, 720 angles
+        info["P"], info["iters"], info["flag"], info["relres"], info["a"] = P, iters, flag, relres, a
+        return P
+
+    for _ in range(n_warm):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n_steps):
+        step()
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t0) / n_steps
+    iters = int(info["iters"][0])
+    flag = int(info["flag"][0])
+    assert flag == 0, f"GMRES did not converge (flag {flag})"
+    n_app = iters + math.ceil(iters / 50)           # Arnoldi applies + one residual per cycle
+    P = info["P"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P.gmres(betas=beta, restart=50, tol=1e-8, maxit=20000, graph=args.graph)
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t0
+    x = torch.randn(cl.n_tot, dtype=torch.complex128, device="cuda")
+    y = P.empty(1)
+    for _ in range(5):
+        P.matvec(x, op=1, out=y)
+    n_rep = 200
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(n_rep):
+        P.matvec(x, op=1, out=y)
+    ev1.record()
+    ev1.synchronize()
+    t_apply = ev0.elapsed_time(ev1) / 1e3 / n_rep      # lane kernel + output pass
+    P.profile_begin(n_rep)
+    for _ in range(n_rep):
+        P.matvec(x, op=1, out=y)
+    ph = P.profile_end()
+    t_lane = ph["mfma_or_lane"] / 1e3 / ph["applies"]
+    flops = algorithmic_flops(cl.n_modes)
+    achieved = flops / t_lane / 1e12
+    out = {"metric": "complex unknown·RHS matvecs/s", "value": cl.n_tot * n_app / t_step,
+           "unit": "complex unknown·RHS matvecs/s", "steps": n_steps, "warmup": n_warm,
+           "ms_per_step": t_step * 1e3,
+           "config": {"workload": "one_rhs: M=400 disks a=0.5 in [0,60]^2 gap 0.2, k=2pi, N_p=12 "
+                                  "(10,000 unknowns), beta=pi/4, GMRES(50) to 1e-8, far field 720 "
+                                  "angles; one step = tables + solve + far field",
+                      "n_unknowns": cl.n_tot, "R": 1, "gmres_iters": iters,
+                      "operator_applies_per_step": n_app, "graph": bool(args.graph)},
+           "time_to_1e8_ms": t_solve * 1e3, "apply_us": t_apply * 1e6,
+           "apply_rate": cl.n_tot / t_apply,
+           "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
+                        "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
+                        "traffic": traffic_per_launch(),
+                        "kernel": "k_apply_lane<12, false> (one lane per ordered pair)",
+                        "kernel_us": t_lane * 1e6,
+                        "source_sha256_16": apply_source_sha(),
+                        "algorithmic_flops_per_launch": flops,
+                        "algorithmic_bytes_per_launch": algorithmic_bytes(cl.n_modes)}}
+    if with_cpu:
+        out["roofline"].update(measured_peaks(achieved))
+        out["cpu_baseline"] = cpu_baseline(cl, iters)
+    return out
+
+
+def headline(args):
+    """The default line: the 256-column apply of the multi-RHS workload."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1409_8186_amd import Problem
+    cl = synth.multi_rhs()
+    R = len(cl.betas)
+    t0 = time.perf_counter()
+    P = Problem.from_cluster(cl, circulant=True)
+    torch.cuda.synchronize()
+    t_tables = time.perf_counter() - t0
+    x = torch.randn(R * cl.n_tot, dtype=torch.complex128, device="cuda")
+    y = P.empty(R)
+    P.matvec(x, R=R, op=1, out=y)           # first apply of this R times the candidate forms
+    for _ in range(args.warmup):
+        P.matvec(x, R=R, op=1, out=y)
+    torch.cuda.synchronize()
+    P.profile_begin(args.steps)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        P.matvec(x, R=R, op=1, out=y)
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t0) / args.steps
+    ph = P.profile_end()
+    n = ph.pop("applies")
+    phases_ms = {k: v / n for k, v in ph.items()}
+    cfg = P.apply_config(R)
+    info = P.circulant_info()
+    tile = P.circulant_tile(R)
+    circ = cfg["kind"] == "circulant"
+    if circ:
+        kern_s = phases_ms["frequency_products"] / 1e3
+        flops = 8.0 * R * info["L_max"] * info["far_pairs"]
+        kname = (f"k_circ_gemm (per-frequency products T_f Z_f, tile {tile[0]}x{tile[1]} "
+                 f"K{tile[2]}, {tile[3]} LDS buffers)")
+        traffic = circ_traffic_per_launch(tile)
+        sha = apply_source_sha(CIRC_SRC)
+    else:
+        kern_s = phases_ms["mfma_or_lane"] / 1e3
+        flops = algorithmic_flops(cl.n_modes, R)
+        kname = "k_apply_mfma (direct Toeplitz tiles on the MFMA work queue)"
+        traffic, sha = None, apply_source_sha()
+    achieved = flops / kern_s / 1e12
+    out = {"metric": "complex unknown·RHS matvecs/s", "value": cl.n_tot * R / t_step,
+           "unit": "complex unknown·RHS matvecs/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": t_step * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "complex128 (f64)",
+           "data": "synthetic (seeded disk cluster)",
+           "config": {"workload": "multi_rhs: M=1000 disks, a~U[0.3,1] in [0,150]^2 gap 0.1, k=10, "
+                                  "N_p=ceil(10a)+10 (34,932 unknowns), 256 incidences; one step = "
+                                  "one operator apply A = D^-1 L on all 256 columns",
+                      "n_unknowns": cl.n_tot, "R": R, "apply": cfg,
+                      "pairs": info, "product_tile": list(tile)},
+           "phases_ms": phases_ms, "tables_s": t_tables,
+           "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_MFMA_TFLOPS,
+                        "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_MFMA_TFLOPS,
+                        "traffic": traffic, "kernel": kname, "kernel_ms": kern_s * 1e3,
+                        "algorithmic_flops_per_launch": flops,
+                        "flops_note": ("8 R L per well-separated ordered pair (the products of "
+                                       "the circulant form; the zero entries of T_f for the "
+                                       "diagonal and the close pairs are not counted)" if circ
+                                       else "8 R n_p n_q per ordered pair"),
+                        "source_sha256_16": sha}}
+    out["roofline"].update(measured_peaks(achieved, "fp64_mfma"))
+    # the same apply in the direct form (every pair as Toeplitz tiles on MFMA)
+    P.set_circulant(R, 0)
+    P.matvec(x, R=R, op=1, out=y)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        P.matvec(x, R=R, op=1, out=y)
+    e1.record()
+    e1.synchronize()
+    out["direct_form_apply_ms"] = e0.elapsed_time(e1) / 3
+    P.set_circulant(R, -1)
+    print(f"[bench] apply {t_step * 1e3:.3f} ms; direct form {out['direct_form_apply_ms']:.1f} ms",
+          file=sys.stderr, flush=True)
+    if args.solve:
+        # time-to-1e-8: tables, right-hand sides and the lockstep solve of all 256 columns
+        P.close()
+        del P
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P = Problem.from_cluster(cl, circulant=True)
+        rho, flag, relres, iters, _ = P.gmres(betas=cl.betas[None, :], restart=50, tol=1e-8,
+                                              maxit=20000)
+        torch.cuda.synchronize()
+        out["time_to_1e8_s"] = time.perf_counter() - t0
+        out["solve"] = {"what": "tables + plane-wave right-hand sides + lockstep GMRES(50), x0 = 0, "
+                                "all 256 columns to 1e-8 (the first apply times the forms)",
+                        "gmres_iters_max": int(iters.max()), "gmres_iters_min": int(iters.min()),
+                        "all_converged": bool((flag == 0).all()),
+                        "relres_max": float(relres.max()),
+                        "apply_form": P.apply_config(R)["kind"]}
+        print(f"[bench] 256-column solve {out['time_to_1e8_s']:.1f} s", file=sys.stderr, flush=True)
+        P.close()
+        del P, rho
+        torch.cuda.empty_cache()
+    one = one_rhs_step(args, 3, 1, False)
+    out["one_rhs"] = {k: one[k] for k in ("value", "ms_per_step", "time_to_1e8_ms", "apply_us",
+                                          "apply_rate", "roofline")}
+    out["one_rhs"]["config"] = one["config"]
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_multi(cl, R)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", dest="graph", action="store_true", default=True,
                     help="replay each GMRES restart cycle as a captured HIP graph (default)")
     ap.add_argument("--no-graph", dest="graph", action="store_false",
                     help="enqueue every GMRES kernel from the host")
+    ap.add_argument("--no-solve", dest="solve", action="store_false", default=True,
+                    help="skip the 256-column time-to-1e-8 solve of the default line")
     ap.add_argument("--kernel-only", type=int, default=0, metavar="REPS",
-                    help="profiling mode: build the tables, run REPS operator applies, exit")
-    ap.add_argument("--workload", default="one_rhs",
-                    choices=["one_rhs", "multi_rhs", "uneven", "differentiation", "dort",
+                    help="profiling mode: build the tables, run REPS operator applies of the "
+                         "selected workload (multi_rhs: 256 columns; one_rhs: one), exit")
+    ap.add_argument("--workload", default="multi_rhs",
+                    choices=["multi_rhs", "one_rhs", "uneven", "differentiation", "dort",
                              "formulations", "nearfield", "penetrable"],
-                    help="one_rhs (default bench line) or a documentation run of another workload")
-    ap.add_argument("--solve", action="store_true",
-                    help="with --workload multi_rhs: also time the GMRES(50) solve to 1e-8")
+                    help="multi_rhs (default bench line) or a documentation run of another workload")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="profiling mode: one device-to-device copy of BYTES (counter calibration)")
     args = ap.parse_args()
@@ -608,7 +844,6 @@ def main():
               "(see the sharding notes in DESIGN.md); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import synth
@@ -628,105 +863,32 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": src.numel() * 8, "launches": 3}), flush=True)
         return
-    if args.workload != "one_rhs":
-        print(json.dumps(other_workload(args)), flush=True)
-        return
-    cl = synth.one_rhs()
     if args.kernel_only:
-        P = Problem.from_cluster(cl)
-        x = torch.randn(cl.n_tot, dtype=torch.complex128, device="cuda")
-        y = P.empty(1)
+        if args.workload == "one_rhs":
+            cl, R, P = synth.one_rhs(), 1, None
+            P = Problem.from_cluster(cl)
+        else:
+            cl = synth.multi_rhs()
+            R = len(cl.betas)
+            P = Problem.from_cluster(cl, circulant=True)
+        x = torch.randn(R * cl.n_tot, dtype=torch.complex128, device="cuda")
+        y = P.empty(R)
+        P.matvec(x, R=R, op=1, out=y)
         for _ in range(args.kernel_only):
-            P.matvec(x, op=1, out=y)
+            P.matvec(x, R=R, op=1, out=y)
         torch.cuda.synchronize()
-        print(json.dumps({"applies": args.kernel_only}), flush=True)
+        print(json.dumps({"applies": args.kernel_only, "apply": P.apply_config(R)}), flush=True)
         return
-    beta = [[math.pi / 4]]
-    th = torch.tensor(cl.thetas, device="cuda")
-
-    info = {}
-
-    def step():
-        P = Problem.from_cluster(cl)                          # geometry + tables
-        rho, flag, relres, iters, _ = P.gmres(betas=beta, restart=50, tol=1e-8, maxit=20000,
-                                              graph=args.graph)
-        a = P.farfield(rho, th)                              # far field, 720 angles
-        info["P"], info["iters"], info["flag"], info["relres"], info["a"] = P, iters, flag, relres, a
-        return P
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t_step = (time.perf_counter() - t0) / args.steps
-
-    iters = int(info["iters"][0])
-    flag = int(info["flag"][0])
-    assert flag == 0, f"GMRES did not converge (flag {flag})"
-    n_app = iters + math.ceil(iters / 50)           # Arnoldi applies + one residual per cycle
-    value = cl.n_tot * n_app / t_step
-
-    # time-to-1e-8 alone (tables prebuilt)
-    P = info["P"]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    P.gmres(betas=beta, restart=50, tol=1e-8, maxit=20000, graph=args.graph)
-    torch.cuda.synchronize()
-    t_solve = time.perf_counter() - t0
-
-    # dominant kernel: the operator apply, timed with events on the launch stream
-    x = torch.randn(cl.n_tot, dtype=torch.complex128, device="cuda")
-    y = P.empty(1)
-    for _ in range(5):
-        P.matvec(x, op=1, out=y)
-    n_rep = 200
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(n_rep):
-        P.matvec(x, op=1, out=y)
-    ev1.record()
-    ev1.synchronize()
-    t_apply = ev0.elapsed_time(ev1) / 1e3 / n_rep
-    flops = algorithmic_flops(cl.n_modes)
-    achieved = flops / t_apply / 1e12
-    traffic = traffic_per_launch()
-
-    out = {
-        "metric": "complex unknown·RHS matvecs/s",
-        "value": value,
-        "unit": "complex unknown·RHS matvecs/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": t_step * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "complex128 (f64)",
-        "data": "synthetic (seeded disk cluster)",
-        "config": {"workload": "one_rhs: M=400 disks a=0.5 in [0,60]^2 gap 0.2, k=2pi, N_p=12 "
-                               "(10,000 unknowns), beta=pi/4, GMRES(50) to 1e-8, far field 720 angles",
-                   "n_unknowns": cl.n_tot, "R": 1, "gmres_iters": iters,
-                   "operator_applies_per_step": n_app, "graph": bool(args.graph)},
-        "time_to_1e8_ms": t_solve * 1e3,
-        "apply_us": t_apply * 1e6,
-        "apply_rate": cl.n_tot / t_apply,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
-                     "traffic": traffic,
-                     "kernel": "operator apply, one RHS: k_apply_lane<12, false> + k_apply_finish",
-                     "source_sha256_16": apply_source_sha(),
-                     "algorithmic_flops_per_launch": flops,
-                     "algorithmic_bytes_per_launch": algorithmic_bytes(cl.n_modes)},
-    }
-    out["roofline"].update(measured_peaks(achieved))
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cl, iters)
-    print(json.dumps(out), flush=True)
+    if args.workload == "multi_rhs":
+        print(json.dumps(headline(args)), flush=True)
+        return
+    if args.workload == "one_rhs":
+        out = one_rhs_step(args, args.steps, args.warmup, not args.no_cpu_baseline)
+        out.update({"n_gpus": 1, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                    "dtype": "complex128 (f64)", "data": "synthetic (seeded disk cluster)"})
+        print(json.dumps(out), flush=True)
+        return
+    print(json.dumps(other_workload(args)), flush=True)
 
 
 if __name__ == "__main__":

@@ -151,6 +151,20 @@ int mudiff_circulant_info(mudiff_t h, int64_t* far_pairs, int64_t* near_pairs, i
  * Errors: MUDIFF_ERR_INVALID (mode, no circulant tables). */
 int mudiff_set_circulant(mudiff_t h, int R, int mode);
 
+/* Tile of the per-frequency products of the R-column apply when it uses the
+ * circulant form (host outputs, any may be NULL; zeros otherwise): rows and
+ * complex columns of a workgroup's output tile, K step (column disks staged
+ * per step) and LDS buffers (2: double-buffered).  The candidates for R are
+ * timed with the rest of the apply on first use. */
+int mudiff_circulant_tile(mudiff_t h, int R, int* rows, int* cols, int* kstep, int* buffers);
+
+/* Fixes that tile (one of the candidates for R: R >= 48: 64x64 K16 with 1 or
+ * 2 buffers, 64x32 K16 or K32, 128x32 K16; 24 <= R < 48: 64x32 K16 or K32,
+ * 128x32 K16; 12 <= R < 24: 128x16, 128x8; R < 12: 128x8, 64x8, all K16
+ * double-buffered) and switches the circulant form on for R.
+ * MUDIFF_ERR_INVALID for other tiles or when the form is not available. */
+int mudiff_set_circulant_tile(mudiff_t h, int R, int rows, int cols, int kstep, int buffers);
+
 /* Releases the host handle (not the caller's device memory). */
 int mudiff_destroy(mudiff_t h);
 
@@ -453,6 +467,24 @@ enum { MUDIFF_PROBE_FP64_FMA = 0, MUDIFF_PROBE_FP64_MFMA = 1, MUDIFF_PROBE_COPY 
 size_t mudiff_probe_workspace_size(int kind, size_t bytes);
 int mudiff_probe(int kind, size_t bytes, void* workspace, size_t ws_bytes, double* rate,
                  void* stream);
+
+/* Phase timing of the operator apply (a measurement aid; the paper has no
+ * counterpart).  Between mudiff_profile_begin and mudiff_profile_end, the first
+ * max_applies complete operator applies on this handle that are not being
+ * captured into a graph (those of mudiff_matvec, the multi-right-hand-side
+ * ones inside the solvers, and the residual applies of a restart cycle) record
+ * HIP events on their stream between their phases:
+ *   0 input scaled by its column factors (multi-right-hand-side applies),
+ *   1 forward transforms and 2 per-frequency products (circulant form),
+ *   3 the MFMA work queue, or the one-lane / generic kernel,
+ *   4 output pass (partial sums, inverse transforms, epilogue).
+ * Recording adds no synchronisation.  mudiff_profile_end synchronises on the
+ * last event and returns the number of profiled applies and the summed
+ * milliseconds of each phase (phases an apply does not have count 0), then
+ * releases the events.  Errors: MUDIFF_ERR_INVALID, MUDIFF_ERR_DEVICE. */
+#define MUDIFF_N_PHASES 5
+int mudiff_profile_begin(mudiff_t h, int max_applies);
+int mudiff_profile_end(mudiff_t h, int* n_applies, double* ms /*[host] MUDIFF_N_PHASES*/);
 
 /* Thread-local message of the last failing call on this thread. */
 const char* mudiff_last_error(void);

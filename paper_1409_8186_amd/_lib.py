@@ -23,6 +23,8 @@ SIGNATURES = {
     "mudiff_tables": (_i32, [_i32, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _i32, _vp, ctypes.POINTER(_vp)]),
     "mudiff_circulant_info": (_i32, [_vp, _i64p, _i64p, ctypes.POINTER(_i32)]),
     "mudiff_set_circulant": (_i32, [_vp, _i32, _i32]),
+    "mudiff_circulant_tile": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp]),
+    "mudiff_set_circulant_tile": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32]),
     "mudiff_destroy": (_i32, [_vp]),
     "mudiff_sizes": (_i32, [_vp, _i64p]),
     "mudiff_disk_tables": (_i32, [_vp, _vp, _vp, _vp]),
@@ -53,6 +55,8 @@ SIGNATURES = {
     "mudiff_herglotz": (_i32, [_i32, _vp, _i32, _vp, _d, _d, _i32, _vp, _vp, _vp]),
     "mudiff_probe_workspace_size": (_sz, [_i32, _sz]),
     "mudiff_probe": (_i32, [_i32, _sz, _vp, _sz, ctypes.POINTER(_d), _vp]),
+    "mudiff_profile_begin": (_i32, [_vp, _i32]),
+    "mudiff_profile_end": (_i32, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_d)]),
     "mudiff_last_error": (ctypes.c_char_p, []),
 }
 
@@ -60,6 +64,8 @@ STATUS = {0: "OK", 1: "INVALID", 2: "OVERLAP", 3: "NOMEM", 4: "DEVICE", 5: "NOT_
 OP_L, OP_A, OP_LT = 0, 1, 2
 X0, GRAPH, POINT_SOURCE, NO_PRECOND = 1, 2, 4, 8
 TABLES_CIRCULANT = 1
+N_PHASES = 5
+PHASES = ("scale", "forward_transform", "frequency_products", "mfma_or_lane", "output_pass")
 PROBE_FP64_FMA, PROBE_FP64_MFMA, PROBE_COPY = 0, 1, 2
 
 

@@ -175,6 +175,40 @@ class Problem:
         """Form of the R-column apply: -1 timed, 0 direct only, 1 circulant."""
         L.check(self.lib.mudiff_set_circulant(self.h, R, mode))
 
+    CIRCULANT_TILES = {48: [(64, 64, 16, 1), (64, 64, 16, 2), (64, 32, 16, 2), (64, 32, 32, 2),
+                            (128, 32, 16, 2)],
+                       24: [(64, 32, 16, 2), (64, 32, 32, 2), (128, 32, 16, 2)],
+                       12: [(128, 16, 16, 2), (128, 8, 16, 2)],
+                       1: [(128, 8, 16, 2), (64, 8, 16, 2)]}
+
+    @classmethod
+    def circulant_tiles(cls, R: int) -> list:
+        """Per-frequency product tiles (rows, cols, kstep, buffers) timed for R."""
+        for lo in (48, 24, 12, 1):
+            if R >= lo:
+                return cls.CIRCULANT_TILES[lo]
+
+    def profile_begin(self, max_applies: int) -> None:
+        """Record HIP events between the phases of the next max_applies applies."""
+        L.check(self.lib.mudiff_profile_begin(self.h, max_applies))
+
+    def profile_end(self) -> dict:
+        """{"applies": n, phase: summed ms} of the applies profiled since profile_begin."""
+        n = ctypes.c_int(0)
+        ms = (ctypes.c_double * L.N_PHASES)()
+        L.check(self.lib.mudiff_profile_end(self.h, ctypes.byref(n), ms))
+        out = {"applies": n.value}
+        out.update({name: ms[k] for k, name in enumerate(L.PHASES)})
+        return out
+
+    def circulant_tile(self, R: int) -> tuple:
+        v = [ctypes.c_int(0) for _ in range(4)]
+        L.check(self.lib.mudiff_circulant_tile(self.h, R, *[ctypes.byref(x) for x in v]))
+        return tuple(x.value for x in v)
+
+    def set_circulant_tile(self, R: int, rows: int, cols: int, kstep: int, buffers: int) -> None:
+        L.check(self.lib.mudiff_set_circulant_tile(self.h, R, rows, cols, kstep, buffers))
+
     def rhs(self, betas=None, precond: bool = False, sources=None) -> torch.Tensor:
         """betas: [B, R] incidence angles, or sources: [B, R, 2] point-source
         positions (Prop. 5)."""

@@ -138,23 +138,25 @@ __global__ __launch_bounds__(256) void k_circ_fwd(DevView v, int R, const cplx* 
 // item: (instance, frequency, row tile, column tile).  Workgroup: 4 waves as
 // WR x WC, each wave WM x WN tiles of 16 rows x 8 complex columns; a complex
 // product is two real MFMAs against [Re Z | Im Z] (lane l holds A[l % 16][l / 16],
-// B[l / 16][l % 16], D[4 v + l / 16][l % 16]).  K steps of 16 column disks are
+// B[l / 16][l % 16], D[4 v + l / 16][l % 16]).  K steps of BK column disks are
 // staged in LDS, the next one loaded into registers while the current one is
-// on the matrix cores.  Consecutive items (the tiles of one frequency) are
-// placed on one XCD, whose L2 then serves the rows of T_f and the panel Z_f to
-// all of them.
+// on the matrix cores; with DB the step goes to a second LDS buffer, so that
+// one barrier per step separates the buffers.  Consecutive items (the tiles of
+// one frequency) are placed on one XCD, whose L2 then serves the rows of T_f
+// and the panel Z_f to all of them.
 typedef double cg_d4 __attribute__((ext_vector_type(4)));
 
-template <int WR, int WC, int WM, int WN>
+template <int WR, int WC, int WM, int WN, int BK, bool DB>
 __global__ __launch_bounds__(256) void k_circ_gemm(DevView v, int R, const cplx* __restrict__ zh,
                                                    cplx* __restrict__ wh,
                                                    const int32_t* __restrict__ items, int n_items,
                                                    const int32_t* __restrict__ active) {
-  constexpr int BM = WR * 16 * WM, BN = WC * 8 * WN, BK = 16;
+  constexpr int BM = WR * 16 * WM, BN = WC * 8 * WN;
   constexpr int AS = BK + 1, BS = BN + 1;  // LDS row strides (complex)
   constexpr int NA = BM * BK / 256, NB = (BK * BN + 255) / 256;
-  __shared__ cplx As[BM * AS];
-  __shared__ cplx Bs[BK * BS];
+  constexpr int ASZ = BM * AS, BSZ = BK * BS;
+  __shared__ cplx As[(DB ? 2 : 1) * ASZ];
+  __shared__ cplx Bs[(DB ? 2 : 1) * BSZ];
   const int i = blockIdx.x;
   const int xc = i & 7, slot = i >> 3;
   const int it = xc * (n_items >> 3) + min(xc, n_items & 7) + slot;
@@ -193,6 +195,20 @@ __global__ __launch_bounds__(256) void k_circ_gemm(DevView v, int R, const cplx*
       rb[u] = (e < BK * BN && gr < Mb && gc < R) ? Bm[gr * R + gc] : cmk(0.0, 0.0);
     }
   };
+  auto store = [&](int buf) {
+    cplx* as = As + buf * ASZ;
+    cplx* bs = Bs + buf * BSZ;
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int e = tid + u * 256;
+      as[(e / BK) * AS + (e % BK)] = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int e = tid + u * 256;
+      if (e < BK * BN) bs[(e / BN) * BS + (e % BN)] = rb[u];
+    }
+  };
   cg_d4 acc1[WM][WN], acc2[WM][WN];
 #pragma unroll
   for (int mt = 0; mt < WM; ++mt)
@@ -201,31 +217,18 @@ __global__ __launch_bounds__(256) void k_circ_gemm(DevView v, int R, const cplx*
       acc1[mt][nt] = cg_d4{0.0, 0.0, 0.0, 0.0};
       acc2[mt][nt] = cg_d4{0.0, 0.0, 0.0, 0.0};
     }
-  const int64_t nk = (Mb + BK - 1) / BK;
-  load(0);
-  for (int64_t kc = 0; kc < nk; ++kc) {
-    __syncthreads();  // previous step done with LDS
-#pragma unroll
-    for (int u = 0; u < NA; ++u) {
-      const int e = tid + u * 256;
-      As[(e / BK) * AS + (e % BK)] = ra[u];
-    }
-#pragma unroll
-    for (int u = 0; u < NB; ++u) {
-      const int e = tid + u * 256;
-      if (e < BK * BN) Bs[(e / BN) * BS + (e % BN)] = rb[u];
-    }
-    __syncthreads();
-    if (kc + 1 < nk) load((kc + 1) * BK);  // in flight during the MFMAs
+  auto compute = [&](int buf) {
+    const cplx* as = As + buf * ASZ;
+    const cplx* bs = Bs + buf * BSZ;
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
       cplx a[WM];
       double bv[WN];
 #pragma unroll
-      for (int mt = 0; mt < WM; ++mt) a[mt] = As[(wr * 16 * WM + 16 * mt + j) * AS + 4 * kk + kq];
+      for (int mt = 0; mt < WM; ++mt) a[mt] = as[(wr * 16 * WM + 16 * mt + j) * AS + 4 * kk + kq];
 #pragma unroll
       for (int nt = 0; nt < WN; ++nt) {
-        const cplx zz = Bs[(4 * kk + kq) * BS + wc * 8 * WN + 8 * nt + (j & 7)];
+        const cplx zz = bs[(4 * kk + kq) * BS + wc * 8 * WN + 8 * nt + (j & 7)];
         bv[nt] = j < 8 ? zz.x : zz.y;
       }
 #pragma unroll
@@ -235,6 +238,27 @@ __global__ __launch_bounds__(256) void k_circ_gemm(DevView v, int R, const cplx*
           acc1[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mt].x, bv[nt], acc1[mt][nt], 0, 0, 0);
           acc2[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mt].y, bv[nt], acc2[mt][nt], 0, 0, 0);
         }
+    }
+  };
+  const int64_t nk = (Mb + BK - 1) / BK;
+  load(0);
+  if constexpr (DB) {
+    store(0);
+    __syncthreads();
+    for (int64_t kc = 0; kc < nk; ++kc) {
+      const int cur = (int)(kc & 1);
+      if (kc + 1 < nk) load((kc + 1) * BK);  // in flight during the MFMAs
+      compute(cur);
+      if (kc + 1 < nk) store(cur ^ 1);       // its readers passed the last barrier
+      __syncthreads();
+    }
+  } else {
+    for (int64_t kc = 0; kc < nk; ++kc) {
+      __syncthreads();  // previous step done with LDS
+      store(0);
+      __syncthreads();
+      if (kc + 1 < nk) load((kc + 1) * BK);  // in flight during the MFMAs
+      compute(0);
     }
   }
 #pragma unroll
@@ -253,22 +277,98 @@ __global__ __launch_bounds__(256) void k_circ_gemm(DevView v, int R, const cplx*
       }
 }
 
-// Product tile of each variant (rows, complex columns), chosen by R.
+// Output pass of an apply with the circulant form, one workgroup per (row disk,
+// 32 right-hand sides): the close-pair partial sums of the MFMA items, plus,
+// for an instance in the form, the inverse transform
+// w_j += sum_f w^{f j} W_f[p][r] from the transformed outputs staged in LDS
+// (each row of 32 right-hand sides read once, coalesced); then the epilogue.
+#define CI_R 32
+__global__ __launch_bounds__(256) void k_circ_finish(
+    DevView v, int R, const cplx* __restrict__ x, cplx* __restrict__ y, int op,
+    const cplx* __restrict__ part, int64_t blk, int npad, int RC, const int32_t* __restrict__ dgrp,
+    const int32_t* __restrict__ drow, const int32_t* __restrict__ gnseg,
+    const int64_t* __restrict__ gbase, const int32_t* __restrict__ active,
+    const cplx* __restrict__ wh, const int32_t* __restrict__ con) {
+  extern __shared__ cplx lds[];
+  const int p = blockIdx.x, tid = threadIdx.x;
+  const int b = v.inst[p];
+  const int r0 = blockIdx.y * CI_R;
+  if (r0 >= R) return;
+  const int np = 2 * v.N[p] + 1;
+  const int64_t d0 = v.idisk[b], Mb = v.idisk[b + 1] - d0;
+  const bool circ = con[b] != 0;
+  const int Lb = circ ? v.cL[b] : 0;
+  cplx* ws = lds;               // [L_b][CI_R]
+  cplx* tw = lds + Lb * CI_R;   // [L_b]
+  if (circ) {
+    const cplx* src = wh + (int64_t)R * v.cZo[b] + (p - d0) * R + r0;
+    for (int e = tid; e < Lb * CI_R; e += 256) {
+      const int f = e / CI_R, rr = e - (e / CI_R) * CI_R;
+      ws[e] = r0 + rr < R ? src[(int64_t)f * Mb * R + rr] : cmk(0.0, 0.0);
+    }
+    for (int e = tid; e < Lb; e += 256) tw[e] = v.ctw[v.cWo[b] + e];
+    __syncthreads();
+  }
+  const int gr = dgrp[p];
+  const int ns = gnseg[gr];
+  const int64_t ip = v.imode[b] + v.moff[p];
+  for (int e = tid; e < CI_R * np; e += 256) {
+    const int rr = e / np, m = e - (e / np) * np;
+    const int r = r0 + rr;
+    if (r >= R || (active && active[b * R + r] == 0)) continue;
+    const int t = r / RC, rc = r - (r / RC) * RC;
+    const cplx* pr = part + (gbase[gr] + (int64_t)t * ns) * blk + ((int64_t)drow[p] * npad + m) * RC + rc;
+    cplx w = cmk(0.0, 0.0);
+    for (int sg = 0; sg < ns; ++sg) w = cadd(w, pr[(int64_t)sg * blk]);
+    if (circ) {
+      cplx acc = cmk(0.0, 0.0);
+      int idx = 0;
+      for (int f = 0; f < Lb; ++f) {
+        cmac(acc, tw[idx], ws[f * CI_R + rr]);
+        idx += m;
+        if (idx >= Lb) idx -= Lb;
+      }
+      w = cadd(w, acc);
+    }
+    const int64_t g = col_base(v.imode, b, R, r) + v.moff[p] + m;
+    y[g] = finalize(v, op, ip + m, x[g], w);
+  }
+}
+
+// Product variants: tile (rows, complex columns), K step, LDS buffers.
 struct CircVariant {
-  int bm, bn;
+  int bm, bn, bk, db;
   void (*fn)(DevView, int, const cplx*, cplx*, const int32_t*, int, const int32_t*);
 };
 static const CircVariant kCircVar[] = {
-    {64, 64, k_circ_gemm<2, 2, 2, 4>},   // R >= 48
-    {64, 32, k_circ_gemm<2, 2, 2, 2>},   // 24 <= R < 48
-    {128, 16, k_circ_gemm<4, 1, 2, 2>},  // 12 <= R < 24
-    {128, 8, k_circ_gemm<4, 1, 2, 1>},   // R < 12
+    {64, 64, 16, 0, k_circ_gemm<2, 2, 2, 4, 16, false>},
+    {64, 64, 16, 1, k_circ_gemm<2, 2, 2, 4, 16, true>},
+    {64, 32, 16, 1, k_circ_gemm<2, 2, 2, 2, 16, true>},
+    {64, 32, 32, 1, k_circ_gemm<2, 2, 2, 2, 32, true>},
+    {128, 32, 16, 1, k_circ_gemm<2, 2, 4, 2, 16, true>},
+    {128, 16, 16, 1, k_circ_gemm<4, 1, 2, 2, 16, true>},
+    {128, 8, 16, 1, k_circ_gemm<4, 1, 2, 1, 16, true>},
+    {64, 8, 16, 1, k_circ_gemm<4, 1, 1, 1, 16, true>},
 };
+#define N_CIRC_VAR ((int)(sizeof(kCircVar) / sizeof(kCircVar[0])))
 
-int circ_variant(int R) { return R >= 48 ? 0 : (R >= 24 ? 1 : (R >= 12 ? 2 : 3)); }
+// Default product variant for R columns, and the variants worth timing.
+int circ_variant(int R) { return R >= 48 ? 1 : (R >= 24 ? 2 : (R >= 12 ? 5 : 6)); }
+std::vector<int> circ_variants(int R) {
+  if (R >= 48) return {0, 1, 2, 3, 4};
+  if (R >= 24) return {2, 3, 4};
+  if (R >= 12) return {5, 6};
+  return {6, 7};
+}
 void circ_tile(int var, int* bm, int* bn) {
   *bm = kCircVar[var].bm;
   *bn = kCircVar[var].bn;
+}
+void circ_var_dims(int var, int* bm, int* bn, int* bk, int* db) {
+  *bm = kCircVar[var].bm;
+  *bn = kCircVar[var].bn;
+  *bk = kCircVar[var].bk;
+  *db = kCircVar[var].db ? 2 : 1;
 }
 
 // Enqueue the transforms of the inputs and the per-frequency products.
@@ -278,11 +378,30 @@ int circ_launch(mudiff_ctx* h, int R, const cplx* z, cplx* zh, cplx* wh, const i
   hipLaunchKernelGGL(k_circ_fwd, dim3((unsigned)h->M_all, (unsigned)((R + CF_R - 1) / CF_R)), dim3(256), 0,
                      s, h->dv, R, z, zh, con, active);
   HIP_TRY(hipGetLastError());
+  prof_mark(h, s, 2);
   if (n_citems > 0) {
     hipLaunchKernelGGL(kCircVar[var].fn, dim3((unsigned)n_citems), dim3(256), 0, s, h->dv, R,
                        (const cplx*)zh, wh, citems, n_citems, active);
     HIP_TRY(hipGetLastError());
   }
+  prof_mark(h, s, 3);
+  return MUDIFF_OK;
+}
+
+int circ_finish(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, const cplx* part, int64_t blk,
+                int npad, int RC, const int32_t* dgrp, const int32_t* drow, const int32_t* gnseg,
+                const int64_t* gbase, const int32_t* active, const cplx* wh, const int32_t* con,
+                hipStream_t s) {
+  int Lmax = 0;
+  for (int32_t l : h->cL) Lmax = std::max(Lmax, (int)l);
+  const size_t lds = (size_t)Lmax * (CI_R + 1) * 16;
+  if (lds > 65536)
+    HIP_TRY(hipFuncSetAttribute((const void*)k_circ_finish, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds));
+  hipLaunchKernelGGL(k_circ_finish, dim3((unsigned)h->M_all, (unsigned)((R + CI_R - 1) / CI_R)), dim3(256),
+                     lds, s, h->dv, R, x, y, op, part, blk, npad, RC, dgrp, drow, gnseg, gbase, active,
+                     wh, con);
+  HIP_TRY(hipGetLastError());
   return MUDIFF_OK;
 }
 

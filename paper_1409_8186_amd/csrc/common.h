@@ -156,11 +156,14 @@ struct MatvecPlan {
 // circ: well-separated pairs of the instances marked in the schedule go
 // through the circulant-embedded form, their close pairs through the MFMA
 // items (column lists).
+// cvar: variant of the per-frequency product (-1: the default for R).
 struct MfmaChoice {
   int CT = 1, RP = 4, QS = 0, threads = 256;
   bool circ = false;
+  int cvar = -1;
   bool operator==(const MfmaChoice& o) const {
-    return CT == o.CT && RP == o.RP && QS == o.QS && threads == o.threads && circ == o.circ;
+    return CT == o.CT && RP == o.RP && QS == o.QS && threads == o.threads && circ == o.circ &&
+           cvar == o.cvar;
   }
 };
 
@@ -218,6 +221,10 @@ struct mudiff_ctx {
   std::vector<uint8_t> circ_nearflag;     // [P_all] 1: close unordered pair (host copy)
   const uint8_t* circ_near_dev = nullptr; // the same on the device
   int64_t n_far = 0, n_near = 0;          // ordered pairs of each kind
+  // phase timing (mudiff_profile_begin/end): MUDIFF_N_PHASES + 1 events per
+  // profiled apply, the slot of the apply in flight (-1: none)
+  std::vector<hipEvent_t> prof_ev;
+  int prof_max = 0, prof_n = 0, prof_cur = -1;
   // penetrable disks (set by mudiff_set_penetrable, in its workspace): interior
   // wavenumbers [M_all] and J_n(k- a), n = 0..N_p+1, at dtab offsets
   const double* pen_k = nullptr;
@@ -389,3 +396,9 @@ size_t plan_sched_bytes(const PlanHost& P, int M);
 int launch_rhs(mudiff_ctx* h, int R, const double* beta, cplx* out, int precond, int point,
                hipStream_t s);
 int launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+
+// Phase marks of a profiled apply: prof_open picks the apply's event slot
+// (none when profiling is off, full, or the stream is being captured) and
+// records mark 0; prof_mark(k) records mark k (1..MUDIFF_N_PHASES) after phase k-1.
+void prof_open(mudiff_ctx* h, hipStream_t s);
+void prof_mark(mudiff_ctx* h, hipStream_t s, int k);

@@ -648,7 +648,13 @@ static bool use_mfma(const mudiff_ctx* h, int R) {
 }
 
 int circ_variant(int R);
+std::vector<int> circ_variants(int R);
 void circ_tile(int var, int* bm, int* bn);
+void circ_var_dims(int var, int* bm, int* bn, int* bk, int* db);
+int circ_finish(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, const cplx* part, int64_t blk,
+                int npad, int RC, const int32_t* dgrp, const int32_t* drow, const int32_t* gnseg,
+                const int64_t* gbase, const int32_t* active, const cplx* wh, const int32_t* con,
+                hipStream_t s);
 int circ_launch(mudiff_ctx* h, int R, const cplx* z, cplx* zh, cplx* wh, const int32_t* citems,
                 int n_citems, int var, const int32_t* con, const int32_t* active, hipStream_t s);
 
@@ -674,7 +680,7 @@ static void mfma_build(const mudiff_ctx* h, int R, const MfmaChoice& c, MfmaSche
   S.con.assign(h->B, 0);
   S.dgrp.assign(h->M_all, 0);
   S.drow.assign(h->M_all, 0);
-  S.cvar = circ_variant(R);
+  S.cvar = c.cvar >= 0 ? c.cvar : circ_variant(R);
   int cbm = 0, cbn = 0;
   circ_tile(S.cvar, &cbm, &cbn);
   struct It {
@@ -895,6 +901,7 @@ static int mfma_launch(mudiff_ctx* h, const MfmaSched& S, const cplx* x, cplx* y
   const int kt = (2 * h->Nmax + 1 + 3) / 4;
   const int RC = 8 * S.c.CT;
   const size_t lds = ((size_t)4 * kt * RC + (size_t)S.c.RP * (4 * kt + 16 * mt - 1)) * 16;
+  prof_open(h, s);
   int rc = launch_fill_zero(head, 4, s);
   if (rc != MUDIFF_OK) return rc;
   cplx* z = (cplx*)(base + off[7]);
@@ -902,6 +909,7 @@ static int mfma_launch(mudiff_ctx* h, const MfmaSched& S, const cplx* x, cplx* y
   hipLaunchKernelGGL(k_apply_mfma_scale, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, s, h->dv,
                      S.R, x, z, active);
   HIP_TRY(hipGetLastError());
+  prof_mark(h, s, 1);
   cplx* wh = nullptr;
   const int32_t* con = (const int32_t*)(base + off[11]);
   if (S.c.circ) {  // well-separated pairs of the marked instances
@@ -910,6 +918,9 @@ static int mfma_launch(mudiff_ctx* h, const MfmaSched& S, const cplx* x, cplx* y
     rc = circ_launch(h, S.R, z, zh, wh, (const int32_t*)(base + off[10]), S.n_citems, S.cvar, con,
                      active, s);
     if (rc != MUDIFF_OK) return rc;
+  } else {
+    prof_mark(h, s, 2);
+    prof_mark(h, s, 3);
   }
   if (S.n_items > 0) {
     const int32_t* it = (const int32_t*)(base + off[1]);
@@ -930,6 +941,15 @@ const int TL = 4 * kt + 16 * mt - 1;
                        (const int32_t*)(base + off[3]), (const int32_t*)(base + off[9]));
     HIP_TRY(hipGetLastError());
   }
+  prof_mark(h, s, 4);
+  if (S.c.circ) {
+    rc = circ_finish(h, S.R, x, y, op, (const cplx*)part, S.blk, S.npad, RC,
+                     (const int32_t*)(base + off[2]), (const int32_t*)(base + off[8]),
+                     (const int32_t*)(base + off[4]), (const int64_t*)(base + off[5]), active,
+                     (const cplx*)wh, con, s);
+    prof_mark(h, s, 5);
+    return rc;
+  }
   const int64_t total = (int64_t)S.R * h->N_all;
   hipLaunchKernelGGL(k_apply_mfma_finish, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
                      h->dv, S.R, x, y, op, (const cplx*)part, S.blk, S.npad, RC,
@@ -937,6 +957,7 @@ const int TL = 4 * kt + 16 * mt - 1;
                      (const int32_t*)(base + off[4]), (const int64_t*)(base + off[5]), active,
                      (const cplx*)wh, con);
   HIP_TRY(hipGetLastError());
+  prof_mark(h, s, 5);
   return MUDIFF_OK;
 }
 
@@ -950,10 +971,14 @@ static size_t mfma_scratch_bytes(mudiff_ctx* h, int R) {
       for (int qs : {c.QS, MFMA_TAIL_QS}) {  // also the short-segment form used for stragglers
         c.QS = qs;
         c.circ = circ != 0;
-        MfmaSched S;
-        mfma_build(h, R, c, S);
-        size_t off[MF_NOFF];
-        mx = std::max(mx, mfma_scratch_layout(h, S, off));
+        std::vector<int> vars = circ ? circ_variants(R) : std::vector<int>{-1};
+        for (int cv : vars) {
+          c.cvar = cv;
+          MfmaSched S;
+          mfma_build(h, R, c, S);
+          size_t off[MF_NOFF];
+          mx = std::max(mx, mfma_scratch_layout(h, S, off));
+        }
       }
   }
   h->mfma_bytes[R] = mx;
@@ -978,32 +1003,55 @@ static int mfma_autotune(mudiff_ctx* h, int R, const cplx* x, cplx* y, char* scr
   auto fc = h->circ_modes.find(R);
   const int cmode = fc != h->circ_modes.end() ? fc->second : -1;
   const bool cu = circ_usable(h, R);
-  for (MfmaChoice c : mfma_candidates(R)) {
-    if (cmode != 1 || !cu) cands.push_back(c);
-    if (cu) {
+  if (cu)  // the circulant form first: it usually sets the bar the direct tiles then fail
+    for (MfmaChoice c : mfma_candidates(R)) {
       c.circ = true;
       cands.push_back(c);
     }
-  }
-  for (const MfmaChoice& c : cands) {
-    if (c.QS > 0 && mmax <= c.QS) continue;
+  if (cmode != 1 || !cu)
+    for (const MfmaChoice& c : mfma_candidates(R)) cands.push_back(c);
+  // one warm-up and two timed applies of candidate c; keeps the fastest
+  auto time_one = [&](const MfmaChoice& c) {
     MfmaSched S;
     mfma_build(h, R, c, S);
-    if ((rc = mfma_upload(h, S, scratch, s)) != MUDIFF_OK) break;
-    if ((rc = mfma_launch(h, S, x, y, MUDIFF_OP_A, nullptr, s)) != MUDIFF_OK) break;  // warm-up
+    if ((rc = mfma_upload(h, S, scratch, s)) != MUDIFF_OK) return;
+    (void)hipEventRecord(e0, s);
+    if ((rc = mfma_launch(h, S, x, y, MUDIFF_OP_A, nullptr, s)) != MUDIFF_OK) return;  // warm-up
+    (void)hipEventRecord(e1, s);
+    if (best > 0.0f) {  // a warm-up already twice as slow as the best pair of applies: no contender
+      float w = 0.0f;
+      if (hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&w, e0, e1) == hipSuccess &&
+          w > best)
+        return;
+    }
     (void)hipEventRecord(e0, s);
     for (int k = 0; k < 2 && rc == MUDIFF_OK; ++k) rc = mfma_launch(h, S, x, y, MUDIFF_OP_A, nullptr, s);
     (void)hipEventRecord(e1, s);
-    if (rc != MUDIFF_OK) break;
+    if (rc != MUDIFF_OK) return;
     if (hipEventSynchronize(e1) != hipSuccess) {
       rc = fail(MUDIFF_ERR_DEVICE, "autotune: event synchronisation failed");
-      break;
+      return;
     }
     float ms = 0.0f;
     (void)hipEventElapsedTime(&ms, e0, e1);
     if (best == 0.0f || ms < best) {
       best = ms;
       bc = c;
+    }
+  };
+  for (const MfmaChoice& c : cands) {
+    if (c.QS > 0 && mmax <= c.QS) continue;
+    time_one(c);
+    if (rc != MUDIFF_OK) break;
+  }
+  if (rc == MUDIFF_OK && bc.circ) {  // then the per-frequency product variants on that tile
+    const MfmaChoice base = bc;
+    for (int cv : circ_variants(R)) {
+      if (cv == circ_variant(R)) continue;
+      MfmaChoice c = base;
+      c.cvar = cv;
+      time_one(c);
+      if (rc != MUDIFF_OK) break;
     }
   }
   (void)hipEventDestroy(e0);
@@ -1306,6 +1354,10 @@ int apply_operator(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, cplx* p
   int st = ensure_plan(h, s);
   if (st != MUDIFF_OK) return st;
   const MatvecPlan& P = h->plan;
+  prof_open(h, s);
+  prof_mark(h, s, 1);
+  prof_mark(h, s, 2);
+  prof_mark(h, s, 3);
   if (P.lane) {
     const LaneVariant* lv = find_lane(P.spec_N);
     if (!lv) return fail(MUDIFF_ERR_INVALID, "no operator kernel variant");
@@ -1314,11 +1366,13 @@ int apply_operator(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, cplx* p
                          h->dv, R, x, part, P.part_total, P.d_items, active);
       HIP_TRY(hipGetLastError());
     }
+    prof_mark(h, s, 4);
     const int64_t total = (int64_t)R * h->N_all;
     hipLaunchKernelGGL(k_apply_finish, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
                        h->dv, R, x, y, op, (const cplx*)part, P.part_total, P.d_nchunk,
                        P.d_partoff, active);
     HIP_TRY(hipGetLastError());
+    prof_mark(h, s, 5);
     return MUDIFF_OK;
   }
   const Variant* var = find_variant(P.Bt, P.spec_N);
@@ -1327,6 +1381,8 @@ int apply_operator(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, cplx* p
                      y, op, part, P.part_total, counters, P.d_items, P.d_nchunk, P.d_partoff, active,
                      P.zs, P.ts, P.ppcap);
   HIP_TRY(hipGetLastError());
+  prof_mark(h, s, 4);
+  prof_mark(h, s, 5);
   return MUDIFF_OK;
 }
 
@@ -1470,5 +1526,107 @@ extern "C" int mudiff_set_circulant(mudiff_t h, int R, int mode) {
     }
   }
   if (h->mfma_sched.R == R) h->mfma_sched.R = 0;  // rebuild at the next apply
+  return MUDIFF_OK;
+}
+
+extern "C" int mudiff_circulant_tile(mudiff_t h, int R, int* rows, int* cols, int* kstep,
+                                     int* buffers) {
+  if (!h) return fail(MUDIFF_ERR_INVALID, "NULL handle");
+  if (R < 1) return fail(MUDIFF_ERR_INVALID, "R < 1");
+  int bm = 0, bn = 0, bk = 0, db = 0;
+  if (use_mfma(h, R)) {
+    auto f = h->mfma_choice.find(R);
+    MfmaChoice ch = f != h->mfma_choice.end() ? f->second : mfma_default(R);
+    if (f == h->mfma_choice.end()) ch.circ = circ_usable(h, R);
+    if (ch.circ) circ_var_dims(ch.cvar >= 0 ? ch.cvar : circ_variant(R), &bm, &bn, &bk, &db);
+  }
+  if (rows) *rows = bm;
+  if (cols) *cols = bn;
+  if (kstep) *kstep = bk;
+  if (buffers) *buffers = db;
+  return MUDIFF_OK;
+}
+
+extern "C" int mudiff_set_circulant_tile(mudiff_t h, int R, int rows, int cols, int kstep,
+                                         int buffers) {
+  if (!h) return fail(MUDIFF_ERR_INVALID, "NULL handle");
+  if (R < 1) return fail(MUDIFF_ERR_INVALID, "R < 1");
+  if (!use_mfma(h, R) || !circ_usable(h, R))
+    return fail(MUDIFF_ERR_INVALID, "this apply does not use the circulant form");
+  for (int v : circ_variants(R)) {
+    int bm, bn, bk, db;
+    circ_var_dims(v, &bm, &bn, &bk, &db);
+    if (bm == rows && bn == cols && bk == kstep && db == buffers) {
+      auto f = h->mfma_choice.find(R);
+      MfmaChoice ch = f != h->mfma_choice.end() ? f->second : mfma_default(R);
+      ch.circ = true;
+      ch.cvar = v;
+      h->mfma_choice[R] = ch;
+      h->mfma_time_ms.erase(R);
+      h->circ_modes[R] = 1;
+      if (h->mfma_sched.R == R) h->mfma_sched.R = 0;
+      return MUDIFF_OK;
+    }
+  }
+  return fail(MUDIFF_ERR_INVALID, "product tile not among the candidates for this R");
+}
+
+// ------------------------------------------------------------------ phase timing
+void prof_open(mudiff_ctx* h, hipStream_t s) {
+  h->prof_cur = -1;
+  if (h->prof_n >= h->prof_max) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+  h->prof_cur = h->prof_n++;
+  (void)hipEventRecord(h->prof_ev[(size_t)h->prof_cur * (MUDIFF_N_PHASES + 1)], s);
+}
+
+void prof_mark(mudiff_ctx* h, hipStream_t s, int k) {
+  if (h->prof_cur < 0) return;
+  (void)hipEventRecord(h->prof_ev[(size_t)h->prof_cur * (MUDIFF_N_PHASES + 1) + k], s);
+  if (k == MUDIFF_N_PHASES) h->prof_cur = -1;
+}
+
+static void prof_release(mudiff_ctx* h) {
+  for (hipEvent_t e : h->prof_ev) (void)hipEventDestroy(e);
+  h->prof_ev.clear();
+  h->prof_max = h->prof_n = 0;
+  h->prof_cur = -1;
+}
+
+extern "C" int mudiff_profile_begin(mudiff_t h, int max_applies) {
+  if (!h) return fail(MUDIFF_ERR_INVALID, "NULL handle");
+  if (max_applies < 1 || max_applies > 100000) return fail(MUDIFF_ERR_INVALID, "max_applies out of range");
+  prof_release(h);
+  h->prof_ev.resize((size_t)max_applies * (MUDIFF_N_PHASES + 1));
+  for (size_t k = 0; k < h->prof_ev.size(); ++k) {
+    if (hipEventCreate(&h->prof_ev[k]) != hipSuccess) {
+      h->prof_ev.resize(k);
+      prof_release(h);
+      return fail(MUDIFF_ERR_DEVICE, "hipEventCreate failed");
+    }
+  }
+  h->prof_max = max_applies;
+  return MUDIFF_OK;
+}
+
+extern "C" int mudiff_profile_end(mudiff_t h, int* n_applies, double* ms) {
+  if (!h || !n_applies || !ms) return fail(MUDIFF_ERR_INVALID, "NULL argument");
+  for (int k = 0; k < MUDIFF_N_PHASES; ++k) ms[k] = 0.0;
+  *n_applies = h->prof_n;
+  if (h->prof_n > 0) {
+    const hipEvent_t last = h->prof_ev[(size_t)(h->prof_n - 1) * (MUDIFF_N_PHASES + 1) + MUDIFF_N_PHASES];
+    if (hipEventSynchronize(last) != hipSuccess) {
+      prof_release(h);
+      return fail(MUDIFF_ERR_DEVICE, "profile: event synchronisation failed");
+    }
+    for (int a = 0; a < h->prof_n; ++a)
+      for (int k = 0; k < MUDIFF_N_PHASES; ++k) {
+        float t = 0.0f;
+        const size_t b = (size_t)a * (MUDIFF_N_PHASES + 1);
+        if (hipEventElapsedTime(&t, h->prof_ev[b + k], h->prof_ev[b + k + 1]) == hipSuccess) ms[k] += t;
+      }
+  }
+  prof_release(h);
   return MUDIFF_OK;
 }

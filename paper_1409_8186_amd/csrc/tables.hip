@@ -567,6 +567,8 @@ extern "C" int mudiff_tables(int B, const int64_t* disk_off, const double* cente
 }
 
 extern "C" int mudiff_destroy(mudiff_t h) {
+  if (h)
+    for (hipEvent_t e : h->prof_ev) (void)hipEventDestroy(e);
   delete h;
   return MUDIFF_OK;
 }

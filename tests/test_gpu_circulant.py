@@ -95,6 +95,13 @@ def test_circulant_matvec(P, R):
             Mx = {1: A, 0: L, 2: L.T}[op]
             e = rel(Y.cpu().numpy(), X @ Mx.T)
             assert e < 1e-12, (op, c.M, e)
+    # every per-frequency product tile the autotuner may pick for R
+    for tile in pr.circulant_tiles(R):
+        pr.set_circulant_tile(R, *tile)
+        y = pr.matvec(x, R=R, op=1)
+        assert pr.circulant_tile(R) == tile
+        for c, X, Y in zip(cls, Xs, pr.split(y, R)):
+            assert rel(Y.cpu().numpy(), X @ _dense(c)[1].T) < 1e-12, tile
     # the direct form on the same handle agrees
     pr.set_circulant(R, 0)
     y = pr.matvec(x, R=R, op=1)

@@ -203,6 +203,23 @@ size_t mudiff_matvec_workspace_size(mudiff_t h, int R);
 int mudiff_matvec(mudiff_t h, int R, const void* x, void* y, int op,
                   void* workspace, size_t ws_bytes, void* stream);
 
+/* No-allocation variant of mudiff_matvec, for callers that cannot allocate
+ * or hand over device memory between calls (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the apply scratch is
+ * a static device array of MUDIFF_NOALLOC_SCRATCH_MB MiB inside the library,
+ * one copy per device, held until the process ends; the call itself allocates
+ * nothing and does not synchronise.  Same operands and results as
+ * mudiff_matvec (x, y, op, stream); it covers the one-lane and generic kernels
+ * (R < 8, or a batch with N_p > 31).  Every call on a device shares that
+ * device's array and leaves its contents behind (it clears what must start at
+ * zero itself): calls that overlap in time on one device (several streams or
+ * threads) race.  Errors: MUDIFF_ERR_INVALID (as mudiff_matvec, or R >= 8 with
+ * N_p <= 31: use mudiff_matvec), MUDIFF_ERR_NOMEM (the apply needs more scratch
+ * than the array holds: about 16 R sum_p (2N_p+1) ceil((M-1)/64) bytes on the
+ * one-lane path), MUDIFF_ERR_DEVICE. */
+#define MUDIFF_NOALLOC_SCRATCH_MB 64
+int mudiff_matvec_noalloc(mudiff_t h, int R, const void* x, void* y, int op, void* stream);
+
 /* Kernel configuration of the R-column operator apply, as chosen on this
  * handle (host outputs; any pointer may be NULL):
  *   kind       0 one lane per pair (uniform N_p <= 12, R < 8), 1 FP64-MFMA

@@ -33,6 +33,7 @@ SIGNATURES = {
     "mudiff_set_apply_config": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32]),
     "mudiff_matvec_workspace_size": (_sz, [_vp, _i32]),
     "mudiff_matvec": (_i32, [_vp, _i32, _vp, _vp, _i32, _vp, _sz, _vp]),
+    "mudiff_matvec_noalloc": (_i32, [_vp, _i32, _vp, _vp, _i32, _vp]),
     "mudiff_rhs": (_i32, [_vp, _i32, _vp, _vp, _i32, _vp]),
     "mudiff_rhs_point": (_i32, [_vp, _i32, _vp, _vp, _i32, _vp]),
     "mudiff_gmres_workspace_size": (_sz, [_vp, _i32, _i32, _i32]),

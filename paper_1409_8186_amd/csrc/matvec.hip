@@ -15,6 +15,8 @@
 // adds them in chunk order, so the result does not depend on scheduling.
 #include "common.h"
 
+#include <mutex>
+
 
 #define APPLY_THREADS 256
 #define APPLY_NPASS 2
@@ -1628,5 +1630,79 @@ extern "C" int mudiff_profile_end(mudiff_t h, int* n_applies, double* ms) {
       }
   }
   prof_release(h);
+  return MUDIFF_OK;
+}
+
+// ------------------------------------------------------------------ no-allocation apply
+// Apply scratch of mudiff_matvec_noalloc: a file-scope device array, one copy
+// per device, held until the process ends.  Host code never hands the array's
+// name to a kernel (on the host it is only a stand-in for the symbol): its
+// device address comes from hipGetSymbolAddress, once per device.
+#define NOALLOC_SCRATCH_BYTES ((size_t)MUDIFF_NOALLOC_SCRATCH_MB << 20)
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static std::map<int, char*> g_scratch_ptr;  // device -> address of its copy of scratch
+
+static int scratch_address(char** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto f = g_scratch_ptr.find(dev);
+  if (f != g_scratch_ptr.end()) {
+    *out = f->second;
+    return MUDIFF_OK;
+  }
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(MUDIFF_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch_ptr[dev] = (char*)ptr;
+  *out = (char*)ptr;
+  return MUDIFF_OK;
+}
+
+extern "C" int mudiff_matvec_noalloc(mudiff_t h, int R, const void* x, void* y, int op,
+                                     void* stream) {
+  if (!h || !x || !y) return fail(MUDIFF_ERR_INVALID, "NULL argument");
+  if (R < 1) return fail(MUDIFF_ERR_INVALID, "R < 1");
+  if (x == y) return fail(MUDIFF_ERR_INVALID, "x and y must be distinct buffers");
+  if (op != MUDIFF_OP_L && op != MUDIFF_OP_A && op != MUDIFF_OP_LT)
+    return fail(MUDIFF_ERR_INVALID, "unknown op");
+  if (op == MUDIFF_OP_LT && h->dv.op_col)
+    return fail(MUDIFF_ERR_INVALID, "MUDIFF_OP_LT applies the single layer only (reset the operator first)");
+  if (use_mfma(h, R))
+    return fail(MUDIFF_ERR_INVALID, "the no-allocation apply covers the one-lane and generic kernels "
+                                    "(R < 8, or N_p > 31); use mudiff_matvec");
+  if (!h->plan.ready) return fail(MUDIFF_ERR_INVALID, "no operator plan for this handle");
+  const size_t need = apply_scratch_bytes(h, R);
+  const size_t flip = op == MUDIFF_OP_LT ? align256((size_t)R * h->N_all * 16) : 0;
+  if (need + flip > NOALLOC_SCRATCH_BYTES)
+    return fail(MUDIFF_ERR_NOMEM, "the no-allocation apply needs " + std::to_string(need + flip) +
+                                      " bytes of scratch, more than its " +
+                                      std::to_string(NOALLOC_SCRATCH_BYTES));
+  char* w = nullptr;
+  int rc = scratch_address(&w);
+  if (rc != MUDIFF_OK) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t part_bytes = need - align256((size_t)R * h->M_all * 4);
+  int32_t* counters = (int32_t*)(w + part_bytes);
+  // the generic kernel's counters start at zero (a fill kernel: no memset node
+  // if the caller captures this call)
+  if ((rc = launch_fill_zero(counters, (size_t)R * h->M_all * 4, s)) != MUDIFF_OK) return rc;
+  const cplx* xin = (const cplx*)x;
+  const int64_t tot = (int64_t)R * h->N_all;
+  const unsigned fb = (unsigned)((tot + 255) / 256);
+  if (op == MUDIFF_OP_LT) {  // L^T x = P L (P x)
+    cplx* xf = (cplx*)(w + need);
+    hipLaunchKernelGGL(k_flip_modes, dim3(fb), dim3(256), 0, s, h->dv, R, xin, xf);
+    HIP_TRY(hipGetLastError());
+    xin = xf;
+  }
+  rc = apply_operator(h, R, xin, (cplx*)y, op == MUDIFF_OP_LT ? MUDIFF_OP_L : op, (cplx*)w, counters,
+                      nullptr, s);
+  if (rc != MUDIFF_OK || op != MUDIFF_OP_LT) return rc;
+  hipLaunchKernelGGL(k_flip_modes, dim3(fb), dim3(256), 0, s, h->dv, R, (const cplx*)y, (cplx*)y);
+  HIP_TRY(hipGetLastError());
   return MUDIFF_OK;
 }

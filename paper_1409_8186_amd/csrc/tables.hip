@@ -545,6 +545,10 @@ extern "C" int mudiff_tables(int B, const int64_t* disk_off, const double* cente
     delete h;
     return st;
   }
+  // operator plan of the one-lane / generic kernels, uploaded now so that no
+  // later apply has to synchronise for it (a plan that does not fit the
+  // generic kernel stays unbuilt: such batches apply on the matrix cores)
+  if (ensure_plan(h, s) == MUDIFF_ERR_DEVICE) st = MUDIFF_ERR_DEVICE;
   hipLaunchKernelGGL(k_disk_tables, dim3((unsigned)((M + 63) / 64)), dim3(64), 0, s, v);
   chk(hipGetLastError(), "k_disk_tables");
   hipLaunchKernelGGL(k_unknown_tables, dim3((unsigned)((N_all + 255) / 256)), dim3(256), 0, s, v);

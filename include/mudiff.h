@@ -197,7 +197,9 @@ size_t mudiff_matvec_workspace_size(mudiff_t h, int R);
  *              that overlap in time (several streams) need separate buffers.
  *              No state is kept in it between calls beyond those zeros: for
  *              R >= 8 (FP64 MFMA) each call uploads the tile schedule into it
- *              again (one host synchronisation of the stream).
+ *              again, asynchronously, from host memory the handle keeps.  The
+ *              call enqueues and returns; only the first call with a new R
+ *              synchronises (it times the candidate tiles and forms).
  * Off-diagonal blocks are applied as Toeplitz products in the mode
  * difference n - m (the diagonal.Toeplitz.diagonal structure of sec. 5). */
 int mudiff_matvec(mudiff_t h, int R, const void* x, void* y, int op,
@@ -296,6 +298,32 @@ int mudiff_rhs_point(mudiff_t h, int R, const double* src, void* out, int precon
 size_t mudiff_operator_workspace_size(mudiff_t h);
 int mudiff_set_operator(mudiff_t h, const double* op_w, const double* rhs_w, const double* ff_w,
                         void* workspace, size_t ws_bytes, void* stream);
+
+/* Named formulations of sec. 3 (with the right-hand sides of Prop. 4 and the
+ * far fields of sec. 4.4), set through mudiff_set_operator:
+ *   MUDIFF_FORM_EFIE         L rho = -U (the built-in single layer; the
+ *                            workspace is not used)
+ *   MUDIFF_FORM_MFIE         (I/2 + N) rho = -dU,                  a = a_L rho
+ *   MUDIFF_FORM_CFIE         (alpha eta L + (1 - alpha)(I/2 + N)) rho
+ *                              = -alpha eta U - (1 - alpha) dU,     a = a_L rho
+ *   MUDIFF_FORM_BWIE         Brakhage-Werner, u = -(eta L + M) psi:
+ *                            (I/2 - eta L - M) psi = -U,           a = -(eta a_L + a_M) psi
+ *   MUDIFF_FORM_SOUND_HARD_SINGLE  sound-hard boundary, u = L rho:
+ *                            (-I/2 + N) rho = -dU,                 a = a_L rho
+ *   MUDIFF_FORM_SOUND_HARD_DOUBLE  sound-hard boundary, u = M lambda:
+ *                            D lambda = -dU,                       a = a_M lambda
+ *   alpha      CFIE mixing weight (other kinds ignore it)
+ *   eta        coupling constant eta_re + i eta_im of CFIE and Brakhage-Werner,
+ *              nonzero there (i k is the usual choice)
+ *   workspace  as for mudiff_set_operator
+ * Errors: MUDIFF_ERR_INVALID (kind, non-finite alpha or eta, eta = 0 where it
+ * is used), and those of mudiff_set_operator. */
+enum {
+  MUDIFF_FORM_EFIE = 0, MUDIFF_FORM_MFIE = 1, MUDIFF_FORM_CFIE = 2, MUDIFF_FORM_BWIE = 3,
+  MUDIFF_FORM_SOUND_HARD_SINGLE = 4, MUDIFF_FORM_SOUND_HARD_DOUBLE = 5
+};
+int mudiff_set_formulation(mudiff_t h, int kind, double alpha, double eta_re, double eta_im,
+                           void* workspace, size_t ws_bytes, void* stream);
 
 /* Penetrable disks (sec. 7, Example II): replaces the handle's operator,
  * right-hand side and far field by those of the transmission problem with

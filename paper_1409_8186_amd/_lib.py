@@ -46,6 +46,7 @@ SIGNATURES = {
                            _vp, _vp, _vp, _vp, _vp]),
     "mudiff_operator_workspace_size": (_sz, [_vp]),
     "mudiff_set_operator": (_i32, [_vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "mudiff_set_formulation": (_i32, [_vp, _i32, _d, _d, _d, _vp, _sz, _vp]),
     "mudiff_set_penetrable": (_i32, [_vp, _vp, _vp, _vp, _sz, _vp]),
     "mudiff_interior_workspace_size": (_sz, [_vp, _i32]),
     "mudiff_interior_field": (_i32, [_vp, _i32, _vp, _vp, _i32, _i32, _vp, _vp, _vp, _sz, _vp]),

@@ -300,40 +300,27 @@ class Problem:
     # ----------------------------------------------------------- operators
     FORMULATIONS = ("efie", "mfie", "cfie", "bwie", "neumann_sl", "neumann_dl")
 
-    @staticmethod
-    def formulation_weights(name: str, alpha: float = 0.5, eta: complex | None = None):
-        """(operator weights {I, L, M, N, D}, right-hand side {U, dU}, far field
-        {L, M}) of a named formulation (sec. 3): EFIE, MFIE, CFIE(alpha, eta),
-        Brakhage-Werner(eta) for a sound-soft boundary; single- or double-layer
-        equation for a sound-hard one."""
-        if name == "efie":
-            return {"L": 1.0}, {"U": -1.0}, {"L": 1.0}
-        if name == "mfie":
-            return {"I": 0.5, "N": 1.0}, {"dU": -1.0}, {"L": 1.0}
-        if name == "cfie":
-            return ({"L": alpha * eta, "I": 0.5 * (1 - alpha), "N": 1 - alpha},
-                    {"U": -alpha * eta, "dU": -(1 - alpha)}, {"L": 1.0})
-        if name == "bwie":
-            return {"I": 0.5, "L": -eta, "M": -1.0}, {"U": -1.0}, {"L": -eta, "M": -1.0}
-        if name == "neumann_sl":
-            return {"I": -0.5, "N": 1.0}, {"dU": -1.0}, {"L": 1.0}
-        if name == "neumann_dl":
-            return {"D": 1.0}, {"dU": -1.0}, {"M": 1.0}
-        raise ValueError(name)
-
     def set_operator(self, name: str | None = None, ops=None, rhs=None, far=None,
                      alpha: float = 0.5, eta: complex | None = None) -> None:
         """Solve, apply and evaluate far fields with another formulation: a name
-        of FORMULATIONS (eta defaults to i k of the first instance), or explicit
-        weight dicts; None returns to the built-in single layer."""
+        of FORMULATIONS (mudiff_set_formulation; eta defaults to i k of the first
+        instance), or explicit weight dicts over I, L, M, N, D / U, dU / L, M
+        (mudiff_set_operator); None returns to the built-in single layer."""
+        n = self.lib.mudiff_operator_workspace_size(self.h)
         if name is None and ops is None:
             L.check(self.lib.mudiff_set_operator(self.h, None, None, None, None, 0, _stream()))
             self._op_ws = None
             return
+        ws = torch.empty(int(n), dtype=torch.uint8, device=self.device)
         if name is not None:
             if eta is None:
                 eta = 1j * float(self.k[0])
-            ops, rhs, far = self.formulation_weights(name, alpha, eta)
+            eta = complex(eta)
+            kind = self.FORMULATIONS.index(name)
+            L.check(self.lib.mudiff_set_formulation(self.h, kind, float(alpha), eta.real, eta.imag,
+                                                    _p(ws), ws.numel(), _stream()))
+            self._op_ws = ws if name != "efie" else None
+            return
 
         def cvec(d, keys):
             out = np.zeros(2 * len(keys), dtype=np.float64)
@@ -344,8 +331,6 @@ class Problem:
         w = cvec(ops, "ILMND")
         rw = cvec(rhs or {}, ("U", "dU"))
         fw = cvec(far or {"L": 1.0}, ("L", "M"))
-        n = self.lib.mudiff_operator_workspace_size(self.h)
-        ws = torch.empty(int(n), dtype=torch.uint8, device=self.device)
         L.check(self.lib.mudiff_set_operator(self.h, w.ctypes.data, rw.ctypes.data, fw.ctypes.data,
                                              _p(ws), ws.numel(), _stream()))
         self._op_ws = ws  # the handle points into it

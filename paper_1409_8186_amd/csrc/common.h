@@ -206,6 +206,8 @@ struct mudiff_ctx {
   std::map<int, float> mfma_time_ms;      // timed apply of the choice (autotuned R only)
   std::map<int, size_t> mfma_bytes;       // apply scratch per R (largest candidate)
   MfmaSched mfma_sched;                   // current schedule (host copy + upload location)
+  hipEvent_t sched_ev = nullptr;          // recorded after the last schedule upload
+  bool sched_pending = false;             // its copies may still read the host vectors
   bool mfma_tail = false;                 // straggler schedule (few columns still iterating)
   std::vector<int32_t> mfma_tail_cols;    // columns of the straggler schedule
   // circulant-embedded form (MUDIFF_TABLES_CIRCULANT): host copies of the
@@ -372,6 +374,9 @@ size_t apply_scratch_bytes(mudiff_ctx* h, int R);
 // else between calls (or a new buffer at a recycled address) never runs on a
 // stale schedule.
 void apply_forget_upload(mudiff_ctx* h);
+// Wait until the last schedule upload has read its host vectors (before they
+// are rebuilt or released).
+void sched_wait(mudiff_ctx* h);
 // Lane-record layout of the one-lane-per-pair apply: total size in complex
 // values (0 when N is not uniform or out of range), the common N, and per disk
 // the offset of its first chunk.

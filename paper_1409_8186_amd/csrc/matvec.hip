@@ -845,8 +845,17 @@ static MfmaChoice mfma_default(int R) {
   return MfmaChoice{ct, 4 / ct, 0, 256, false};
 }
 
-// Upload schedule S into the apply scratch at `base` (synchronises; not for
-// use under graph capture).
+void sched_wait(mudiff_ctx* h) {
+  if (h->sched_pending) {
+    (void)hipEventSynchronize(h->sched_ev);
+    h->sched_pending = false;
+  }
+}
+
+// Upload schedule S into the apply scratch at `base`, asynchronously: the
+// host vectors of S stay untouched until sched_wait (S = the handle's
+// schedule) or a synchronisation of the stream (a local S).  Not for use under
+// graph capture.
 static int mfma_upload(mudiff_ctx* h, MfmaSched& S, char* base, hipStream_t s) {
   size_t off[MF_NOFF];
   mfma_scratch_layout(h, S, off);
@@ -861,7 +870,9 @@ static int mfma_upload(mudiff_ctx* h, MfmaSched& S, char* base, hipStream_t s) {
   HIP_TRY(hipMemcpyAsync(base + off[8], S.drow.data(), (size_t)h->M_all * 4, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(base + off[4], S.gnseg.data(), S.gnseg.size() * 4, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(base + off[5], S.gbase.data(), S.gbase.size() * 8, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipStreamSynchronize(s));
+  if (!h->sched_ev) HIP_TRY(hipEventCreateWithFlags(&h->sched_ev, hipEventDisableTiming));
+  HIP_TRY(hipEventRecord(h->sched_ev, s));
+  h->sched_pending = true;
   S.dev_base = base;
   return MUDIFF_OK;
 }
@@ -1016,6 +1027,10 @@ static int mfma_autotune(mudiff_ctx* h, int R, const cplx* x, cplx* y, char* scr
   auto time_one = [&](const MfmaChoice& c) {
     MfmaSched S;
     mfma_build(h, R, c, S);
+    struct Drain {  // the local schedule's copies finish before it is released
+      hipStream_t st;
+      ~Drain() { (void)hipStreamSynchronize(st); }
+    } drain{s};
     if ((rc = mfma_upload(h, S, scratch, s)) != MUDIFF_OK) return;
     (void)hipEventRecord(e0, s);
     if ((rc = mfma_launch(h, S, x, y, MUDIFF_OP_A, nullptr, s)) != MUDIFF_OK) return;  // warm-up
@@ -1061,6 +1076,7 @@ static int mfma_autotune(mudiff_ctx* h, int R, const cplx* x, cplx* y, char* scr
   if (rc != MUDIFF_OK) return rc;
   h->mfma_choice[R] = bc;
   h->mfma_time_ms[R] = best / 2.0f;
+  sched_wait(h);
   mfma_build(h, R, bc, h->mfma_sched);
   return mfma_upload(h, h->mfma_sched, scratch, s);
 }
@@ -1079,8 +1095,10 @@ static int mfma_prepare(mudiff_ctx* h, int R, const cplx* x, cplx* y, char* scra
   }
   MfmaChoice c = f->second;
   if (h->mfma_tail) c.QS = MFMA_TAIL_QS;
-  if (h->mfma_sched.R != R || !(h->mfma_sched.c == c))
+  if (h->mfma_sched.R != R || !(h->mfma_sched.c == c)) {
+    sched_wait(h);
     mfma_build(h, R, c, h->mfma_sched, h->mfma_tail ? h->mfma_tail_cols : std::vector<int32_t>{});
+  }
   if (h->mfma_sched.dev_base != scratch) return mfma_upload(h, h->mfma_sched, scratch, s);
   return MUDIFF_OK;
 }

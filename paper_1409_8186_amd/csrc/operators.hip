@@ -392,3 +392,62 @@ extern "C" int mudiff_set_operator(mudiff_t h, const double* op_w, const double*
   h->pen_k = h->pen_J = nullptr;
   return MUDIFF_OK;
 }
+
+// Named formulations (sec. 3): the operator, right-hand side and far-field
+// weights of each, then mudiff_set_operator.  Weight order as there: operator
+// I, L, M, N, D; right-hand side U, dU; far field a_L, a_M (re, im pairs).
+extern "C" int mudiff_set_formulation(mudiff_t h, int kind, double alpha, double eta_re,
+                                      double eta_im, void* workspace, size_t ws_bytes,
+                                      void* stream) {
+  if (!h) return fail(MUDIFF_ERR_INVALID, "NULL handle");
+  if (!std::isfinite(alpha) || !std::isfinite(eta_re) || !std::isfinite(eta_im))
+    return fail(MUDIFF_ERR_INVALID, "alpha and eta must be finite");
+  double op[10] = {0}, rw[4] = {0}, fw[4] = {0};
+  auto set = [](double* a, int k, double re, double im) {
+    a[2 * k] = re;
+    a[2 * k + 1] = im;
+  };
+  enum { I_ = 0, L_ = 1, M_ = 2, N_ = 3, D_ = 4 };
+  switch (kind) {
+    case MUDIFF_FORM_EFIE:  // L rho = -U, the built-in single layer
+      return mudiff_set_operator(h, nullptr, nullptr, nullptr, nullptr, 0, stream);
+    case MUDIFF_FORM_MFIE:  // (I/2 + N) rho = -dU
+      set(op, I_, 0.5, 0.0);
+      set(op, N_, 1.0, 0.0);
+      set(rw, 1, -1.0, 0.0);
+      set(fw, 0, 1.0, 0.0);
+      break;
+    case MUDIFF_FORM_CFIE:  // (alpha eta L + (1 - alpha)(I/2 + N)) rho = -alpha eta U - (1 - alpha) dU
+      if (eta_re == 0.0 && eta_im == 0.0) return fail(MUDIFF_ERR_INVALID, "CFIE needs eta != 0");
+      set(op, L_, alpha * eta_re, alpha * eta_im);
+      set(op, I_, 0.5 * (1.0 - alpha), 0.0);
+      set(op, N_, 1.0 - alpha, 0.0);
+      set(rw, 0, -alpha * eta_re, -alpha * eta_im);
+      set(rw, 1, -(1.0 - alpha), 0.0);
+      set(fw, 0, 1.0, 0.0);
+      break;
+    case MUDIFF_FORM_BWIE:  // (I/2 - eta L - M) psi = -U, u = -(eta L + M) psi
+      if (eta_re == 0.0 && eta_im == 0.0) return fail(MUDIFF_ERR_INVALID, "Brakhage-Werner needs eta != 0");
+      set(op, I_, 0.5, 0.0);
+      set(op, L_, -eta_re, -eta_im);
+      set(op, M_, -1.0, 0.0);
+      set(rw, 0, -1.0, 0.0);
+      set(fw, 0, -eta_re, -eta_im);
+      set(fw, 1, -1.0, 0.0);
+      break;
+    case MUDIFF_FORM_SOUND_HARD_SINGLE:  // (-I/2 + N) rho = -dU, u = L rho
+      set(op, I_, -0.5, 0.0);
+      set(op, N_, 1.0, 0.0);
+      set(rw, 1, -1.0, 0.0);
+      set(fw, 0, 1.0, 0.0);
+      break;
+    case MUDIFF_FORM_SOUND_HARD_DOUBLE:  // D lambda = -dU, u = M lambda
+      set(op, D_, 1.0, 0.0);
+      set(rw, 1, -1.0, 0.0);
+      set(fw, 1, 1.0, 0.0);
+      break;
+    default:
+      return fail(MUDIFF_ERR_INVALID, "unknown formulation");
+  }
+  return mudiff_set_operator(h, op, rw, fw, workspace, ws_bytes, stream);
+}

@@ -571,8 +571,11 @@ extern "C" int mudiff_tables(int B, const int64_t* disk_off, const double* cente
 }
 
 extern "C" int mudiff_destroy(mudiff_t h) {
-  if (h)
+  if (h) {
+    sched_wait(h);  // no schedule upload still reads the handle's host vectors
+    if (h->sched_ev) (void)hipEventDestroy(h->sched_ev);
     for (hipEvent_t e : h->prof_ev) (void)hipEventDestroy(e);
+  }
   delete h;
   return MUDIFF_OK;
 }

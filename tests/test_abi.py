@@ -151,6 +151,7 @@ def test_set_operator_validation(lib):
     assert lib.mudiff_interior_field(None, 1, w, w, 0, 1, w, w, w, 4096, None) == 1
     assert lib.mudiff_interior_workspace_size(None, 1) == 0
     assert lib.mudiff_rhs_point(None, 1, w, w, 0, None) == 1
+    assert lib.mudiff_set_formulation(None, 1, 0.5, 0.0, 1.0, w, 4096, None) == 1
 
 
 def test_circulant_validation(lib):

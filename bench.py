@@ -109,7 +109,7 @@ def circ_traffic_per_launch(tile):
     m = re.search(r"source_sha256_16[^:]*:\s*([0-9a-f]+)", txt)
     if not m or m.group(1) != apply_source_sha(CIRC_SRC):
         return None
-    pat = r"variant %dx%d K%d buffers %d .*bytes_per_launch (\d+)" % tuple(tile)
+    pat = r"variant %dx%d K%d stages %d threads %d .*bytes_per_launch (\d+)" % tuple(tile)
     v = re.search(pat, txt)
     return float(v.group(1)) if v else None
 
@@ -743,7 +743,7 @@ def headline(args):
         kern_s = phases_ms["frequency_products"] / 1e3
         flops = 8.0 * R * info["L_max"] * info["far_pairs"]
         kname = (f"k_circ_gemm (per-frequency products T_f Z_f, tile {tile[0]}x{tile[1]} "
-                 f"K{tile[2]}, {tile[3]} LDS buffers)")
+                 f"K{tile[2]}, staging depth {tile[3]}, {tile[4]} threads)")
         traffic = circ_traffic_per_launch(tile)
         sha = apply_source_sha(CIRC_SRC)
     else:

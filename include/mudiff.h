@@ -154,16 +154,19 @@ int mudiff_set_circulant(mudiff_t h, int R, int mode);
 /* Tile of the per-frequency products of the R-column apply when it uses the
  * circulant form (host outputs, any may be NULL; zeros otherwise): rows and
  * complex columns of a workgroup's output tile, K step (column disks staged
- * per step) and LDS buffers (2: double-buffered).  The candidates for R are
- * timed with the rest of the apply on first use. */
-int mudiff_circulant_tile(mudiff_t h, int R, int* rows, int* cols, int* kstep, int* buffers);
+ * per step), staging depth (1: one LDS buffer; 2: two LDS buffers; 3: two LDS
+ * buffers and two register sets, loads two steps ahead) and workgroup size.
+ * The candidates for R are timed with the rest of the apply on first use. */
+int mudiff_circulant_tile(mudiff_t h, int R, int* rows, int* cols, int* kstep, int* stages,
+                          int* threads);
 
-/* Fixes that tile (one of the candidates for R: R >= 48: 64x64 K16 with 1 or
- * 2 buffers, 64x32 K16 or K32, 128x32 K16; 24 <= R < 48: 64x32 K16 or K32,
- * 128x32 K16; 12 <= R < 24: 128x16, 128x8; R < 12: 128x8, 64x8, all K16
- * double-buffered) and switches the circulant form on for R.
+/* Fixes that tile (one of the candidates for R, as listed by
+ * Problem.circulant_tiles in the Python binding: for R >= 48, 64x64 K16 with
+ * stages 1 or 2, 64x32 K16 with stages 2 or 3, 64x32 K32, 128x32 K16 on 256 or
+ * 512 threads; fewer for smaller R) and switches the circulant form on for R.
  * MUDIFF_ERR_INVALID for other tiles or when the form is not available. */
-int mudiff_set_circulant_tile(mudiff_t h, int R, int rows, int cols, int kstep, int buffers);
+int mudiff_set_circulant_tile(mudiff_t h, int R, int rows, int cols, int kstep, int stages,
+                              int threads);
 
 /* Releases the host handle (not the caller's device memory). */
 int mudiff_destroy(mudiff_t h);

@@ -175,15 +175,18 @@ class Problem:
         """Form of the R-column apply: -1 timed, 0 direct only, 1 circulant."""
         L.check(self.lib.mudiff_set_circulant(self.h, R, mode))
 
-    CIRCULANT_TILES = {48: [(64, 64, 16, 1), (64, 64, 16, 2), (64, 32, 16, 2), (64, 32, 32, 2),
-                            (128, 32, 16, 2)],
-                       24: [(64, 32, 16, 2), (64, 32, 32, 2), (128, 32, 16, 2)],
-                       12: [(128, 16, 16, 2), (128, 8, 16, 2)],
-                       1: [(128, 8, 16, 2), (64, 8, 16, 2)]}
+    # per-frequency product tiles (rows, cols, kstep, stages, threads) timed for R
+    CIRCULANT_TILES = {48: [(64, 64, 16, 1, 256), (64, 64, 16, 2, 256), (64, 32, 16, 2, 256),
+                            (64, 32, 32, 2, 256), (128, 32, 16, 2, 256), (64, 32, 16, 3, 256),
+                            (128, 32, 16, 2, 512), (128, 32, 16, 3, 512)],
+                       24: [(64, 32, 16, 2, 256), (64, 32, 32, 2, 256), (128, 32, 16, 2, 256),
+                            (64, 32, 16, 3, 256), (128, 32, 16, 2, 512), (128, 32, 16, 3, 512)],
+                       12: [(128, 16, 16, 2, 256), (128, 8, 16, 2, 256), (128, 16, 16, 3, 256)],
+                       1: [(128, 8, 16, 2, 256), (64, 8, 16, 2, 256)]}
 
     @classmethod
     def circulant_tiles(cls, R: int) -> list:
-        """Per-frequency product tiles (rows, cols, kstep, buffers) timed for R."""
+        """Per-frequency product tiles (rows, cols, kstep, stages, threads) timed for R."""
         for lo in (48, 24, 12, 1):
             if R >= lo:
                 return cls.CIRCULANT_TILES[lo]
@@ -202,12 +205,13 @@ class Problem:
         return out
 
     def circulant_tile(self, R: int) -> tuple:
-        v = [ctypes.c_int(0) for _ in range(4)]
+        v = [ctypes.c_int(0) for _ in range(5)]
         L.check(self.lib.mudiff_circulant_tile(self.h, R, *[ctypes.byref(x) for x in v]))
         return tuple(x.value for x in v)
 
-    def set_circulant_tile(self, R: int, rows: int, cols: int, kstep: int, buffers: int) -> None:
-        L.check(self.lib.mudiff_set_circulant_tile(self.h, R, rows, cols, kstep, buffers))
+    def set_circulant_tile(self, R: int, rows: int, cols: int, kstep: int, stages: int,
+                           threads: int) -> None:
+        L.check(self.lib.mudiff_set_circulant_tile(self.h, R, rows, cols, kstep, stages, threads))
 
     def rhs(self, betas=None, precond: bool = False, sources=None) -> torch.Tensor:
         """betas: [B, R] incidence angles, or sources: [B, R, 2] point-source

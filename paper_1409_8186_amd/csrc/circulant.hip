@@ -146,15 +146,19 @@ __global__ __launch_bounds__(256) void k_circ_fwd(DevView v, int R, const cplx* 
 // and the panel Z_f to all of them.
 typedef double cg_d4 __attribute__((ext_vector_type(4)));
 
-template <int WR, int WC, int WM, int WN, int BK, bool DB>
-__global__ __launch_bounds__(256) void k_circ_gemm(DevView v, int R, const cplx* __restrict__ zh,
+// PF2: two register sets for the staged K steps, so that step kc + 2 is
+// loaded while step kc is on the matrix cores (two steps of latency hiding).
+template <int WR, int WC, int WM, int WN, int BK, bool DB, bool PF2>
+__global__ __launch_bounds__(WR * WC * 64) void k_circ_gemm(DevView v, int R, const cplx* __restrict__ zh,
                                                    cplx* __restrict__ wh,
                                                    const int32_t* __restrict__ items, int n_items,
                                                    const int32_t* __restrict__ active) {
+  constexpr int NT = WR * WC * 64;
   constexpr int BM = WR * 16 * WM, BN = WC * 8 * WN;
   constexpr int AS = BK + 1, BS = BN + 1;  // LDS row strides (complex)
-  constexpr int NA = BM * BK / 256, NB = (BK * BN + 255) / 256;
+  constexpr int NA = BM * BK / NT, NB = (BK * BN + NT - 1) / NT;
   constexpr int ASZ = BM * AS, BSZ = BK * BS;
+  static_assert(!PF2 || DB, "two register sets need two LDS buffers");
   __shared__ cplx As[(DB ? 2 : 1) * ASZ];
   __shared__ cplx Bs[(DB ? 2 : 1) * BSZ];
   const int i = blockIdx.x;
@@ -177,36 +181,36 @@ __global__ __launch_bounds__(256) void k_circ_gemm(DevView v, int R, const cplx*
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int j = lane & 15, kq = lane >> 4;
   const int wr = wave / WC, wc = wave - (wave / WC) * WC;
-  cplx ra[NA], rb[NB];
-  auto load = [&](int64_t k0) {
+  cplx ra[2][NA], rb[2][NB];
+  auto load = [&](int64_t k0, cplx (&xa)[NA], cplx (&xb)[NB]) {
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
-      const int e = tid + u * 256;
+      const int e = tid + u * NT;
       const int r = e / BK, c = e - (e / BK) * BK;
       const int64_t gr = row0 + r, gc = k0 + c;
-      ra[u] = (gr < Mb && gc < Mb) ? A[gr * Mb + gc] : cmk(0.0, 0.0);
+      xa[u] = (gr < Mb && gc < Mb) ? A[gr * Mb + gc] : cmk(0.0, 0.0);
     }
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
-      const int e = tid + u * 256;
+      const int e = tid + u * NT;
       const int r = e / BN, c = e - (e / BN) * BN;
       const int64_t gr = k0 + r;
       const int gc = col0 + c;
-      rb[u] = (e < BK * BN && gr < Mb && gc < R) ? Bm[gr * R + gc] : cmk(0.0, 0.0);
+      xb[u] = (e < BK * BN && gr < Mb && gc < R) ? Bm[gr * R + gc] : cmk(0.0, 0.0);
     }
   };
-  auto store = [&](int buf) {
+  auto store = [&](int buf, const cplx (&xa)[NA], const cplx (&xb)[NB]) {
     cplx* as = As + buf * ASZ;
     cplx* bs = Bs + buf * BSZ;
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
-      const int e = tid + u * 256;
-      as[(e / BK) * AS + (e % BK)] = ra[u];
+      const int e = tid + u * NT;
+      as[(e / BK) * AS + (e % BK)] = xa[u];
     }
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
-      const int e = tid + u * 256;
-      if (e < BK * BN) bs[(e / BN) * BS + (e % BN)] = rb[u];
+      const int e = tid + u * NT;
+      if (e < BK * BN) bs[(e / BN) * BS + (e % BN)] = xb[u];
     }
   };
   cg_d4 acc1[WM][WN], acc2[WM][WN];
@@ -241,23 +245,43 @@ __global__ __launch_bounds__(256) void k_circ_gemm(DevView v, int R, const cplx*
     }
   };
   const int64_t nk = (Mb + BK - 1) / BK;
-  load(0);
-  if constexpr (DB) {
-    store(0);
+  if constexpr (PF2) {
+    // register set s holds the steps kc with kc % 2 == s
+    load(0, ra[0], rb[0]);
+    if (nk > 1) load(BK, ra[1], rb[1]);
+    store(0, ra[0], rb[0]);
+    __syncthreads();
+    for (int64_t kc = 0; kc < nk; kc += 2) {
+      // even step kc: buffer 0; set 0 is free for step kc + 2
+      if (kc + 2 < nk) load((kc + 2) * BK, ra[0], rb[0]);
+      compute(0);
+      if (kc + 1 < nk) store(1, ra[1], rb[1]);
+      __syncthreads();
+      if (kc + 1 >= nk) break;
+      // odd step kc + 1: buffer 1; set 1 is free for step kc + 3
+      if (kc + 3 < nk) load((kc + 3) * BK, ra[1], rb[1]);
+      compute(1);
+      if (kc + 2 < nk) store(0, ra[0], rb[0]);
+      __syncthreads();
+    }
+  } else if constexpr (DB) {
+    load(0, ra[0], rb[0]);
+    store(0, ra[0], rb[0]);
     __syncthreads();
     for (int64_t kc = 0; kc < nk; ++kc) {
       const int cur = (int)(kc & 1);
-      if (kc + 1 < nk) load((kc + 1) * BK);  // in flight during the MFMAs
+      if (kc + 1 < nk) load((kc + 1) * BK, ra[0], rb[0]);  // in flight during the MFMAs
       compute(cur);
-      if (kc + 1 < nk) store(cur ^ 1);       // its readers passed the last barrier
+      if (kc + 1 < nk) store(cur ^ 1, ra[0], rb[0]);       // its readers passed the last barrier
       __syncthreads();
     }
   } else {
+    load(0, ra[0], rb[0]);
     for (int64_t kc = 0; kc < nk; ++kc) {
       __syncthreads();  // previous step done with LDS
-      store(0);
+      store(0, ra[0], rb[0]);
       __syncthreads();
-      if (kc + 1 < nk) load((kc + 1) * BK);  // in flight during the MFMAs
+      if (kc + 1 < nk) load((kc + 1) * BK, ra[0], rb[0]);  // in flight during the MFMAs
       compute(0);
     }
   }
@@ -335,40 +359,46 @@ __global__ __launch_bounds__(256) void k_circ_finish(
   }
 }
 
-// Product variants: tile (rows, complex columns), K step, LDS buffers.
+// Product variants: tile (rows, complex columns), K step, LDS buffers
+// (3: two buffers and two register sets), workgroup size.
 struct CircVariant {
-  int bm, bn, bk, db;
+  int bm, bn, bk, db, nt;
   void (*fn)(DevView, int, const cplx*, cplx*, const int32_t*, int, const int32_t*);
 };
 static const CircVariant kCircVar[] = {
-    {64, 64, 16, 0, k_circ_gemm<2, 2, 2, 4, 16, false>},
-    {64, 64, 16, 1, k_circ_gemm<2, 2, 2, 4, 16, true>},
-    {64, 32, 16, 1, k_circ_gemm<2, 2, 2, 2, 16, true>},
-    {64, 32, 32, 1, k_circ_gemm<2, 2, 2, 2, 32, true>},
-    {128, 32, 16, 1, k_circ_gemm<2, 2, 4, 2, 16, true>},
-    {128, 16, 16, 1, k_circ_gemm<4, 1, 2, 2, 16, true>},
-    {128, 8, 16, 1, k_circ_gemm<4, 1, 2, 1, 16, true>},
-    {64, 8, 16, 1, k_circ_gemm<4, 1, 1, 1, 16, true>},
+    {64, 64, 16, 1, 256, k_circ_gemm<2, 2, 2, 4, 16, false, false>},
+    {64, 64, 16, 2, 256, k_circ_gemm<2, 2, 2, 4, 16, true, false>},
+    {64, 32, 16, 2, 256, k_circ_gemm<2, 2, 2, 2, 16, true, false>},
+    {64, 32, 32, 2, 256, k_circ_gemm<2, 2, 2, 2, 32, true, false>},
+    {128, 32, 16, 2, 256, k_circ_gemm<2, 2, 4, 2, 16, true, false>},
+    {128, 16, 16, 2, 256, k_circ_gemm<4, 1, 2, 2, 16, true, false>},
+    {128, 8, 16, 2, 256, k_circ_gemm<4, 1, 2, 1, 16, true, false>},
+    {64, 8, 16, 2, 256, k_circ_gemm<4, 1, 1, 1, 16, true, false>},
+    {64, 32, 16, 3, 256, k_circ_gemm<2, 2, 2, 2, 16, true, true>},
+    {128, 32, 16, 2, 512, k_circ_gemm<4, 2, 2, 2, 16, true, false>},
+    {128, 32, 16, 3, 512, k_circ_gemm<4, 2, 2, 2, 16, true, true>},
+    {128, 16, 16, 3, 256, k_circ_gemm<4, 1, 2, 2, 16, true, true>},
 };
 #define N_CIRC_VAR ((int)(sizeof(kCircVar) / sizeof(kCircVar[0])))
 
 // Default product variant for R columns, and the variants worth timing.
-int circ_variant(int R) { return R >= 48 ? 1 : (R >= 24 ? 2 : (R >= 12 ? 5 : 6)); }
+int circ_variant(int R) { return R >= 48 ? 2 : (R >= 24 ? 2 : (R >= 12 ? 5 : 6)); }
 std::vector<int> circ_variants(int R) {
-  if (R >= 48) return {0, 1, 2, 3, 4};
-  if (R >= 24) return {2, 3, 4};
-  if (R >= 12) return {5, 6};
+  if (R >= 48) return {0, 1, 2, 3, 4, 8, 9, 10};
+  if (R >= 24) return {2, 3, 4, 8, 9, 10};
+  if (R >= 12) return {5, 6, 11};
   return {6, 7};
 }
 void circ_tile(int var, int* bm, int* bn) {
   *bm = kCircVar[var].bm;
   *bn = kCircVar[var].bn;
 }
-void circ_var_dims(int var, int* bm, int* bn, int* bk, int* db) {
+void circ_var_dims(int var, int* bm, int* bn, int* bk, int* db, int* nt) {
   *bm = kCircVar[var].bm;
   *bn = kCircVar[var].bn;
   *bk = kCircVar[var].bk;
-  *db = kCircVar[var].db ? 2 : 1;
+  *db = kCircVar[var].db;
+  *nt = kCircVar[var].nt;
 }
 
 // Enqueue the transforms of the inputs and the per-frequency products.
@@ -380,7 +410,7 @@ int circ_launch(mudiff_ctx* h, int R, const cplx* z, cplx* zh, cplx* wh, const i
   HIP_TRY(hipGetLastError());
   prof_mark(h, s, 2);
   if (n_citems > 0) {
-    hipLaunchKernelGGL(kCircVar[var].fn, dim3((unsigned)n_citems), dim3(256), 0, s, h->dv, R,
+    hipLaunchKernelGGL(kCircVar[var].fn, dim3((unsigned)n_citems), dim3(kCircVar[var].nt), 0, s, h->dv, R,
                        (const cplx*)zh, wh, citems, n_citems, active);
     HIP_TRY(hipGetLastError());
   }

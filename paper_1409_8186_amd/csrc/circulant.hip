@@ -11,8 +11,8 @@
 // The middle step is, for each frequency f, one dense complex product of the
 // M_b x M_b matrix T_f with the M_b x R panel of transformed inputs: it runs
 // on the FP64 matrix cores (k_circ_gemm), the transforms of the inputs and
-// outputs are small dense sums (k_circ_fwd, and the finishing pass of the
-// apply).  T_f is zero on the diagonal and for close pairs (k b_pq < N_p + N_q):
+// outputs are small dense sums (k_circ_fwd on the vector units, and the
+// output pass k_circ_finish_mfma on the matrix cores).  T_f is zero on the diagonal and for close pairs (k b_pq < N_p + N_q):
 // their symbols grow by orders of magnitude with the order, and a transform
 // would spread that rounding over every mode, so they stay in the direct form.
 #include "common.h"
@@ -301,59 +301,118 @@ __global__ __launch_bounds__(WR * WC * 64) void k_circ_gemm(DevView v, int R, co
       }
 }
 
-// Output pass of an apply with the circulant form, one workgroup per (row disk,
-// 32 right-hand sides): the close-pair partial sums of the MFMA items, plus,
-// for an instance in the form, the inverse transform
-// w_j += sum_f w^{f j} W_f[p][r] from the transformed outputs staged in LDS
-// (each row of 32 right-hand sides read once, coalesced); then the epilogue.
-#define CI_R 32
-__global__ __launch_bounds__(256) void k_circ_finish(
+// The inverse transform as a small dense product on the matrix cores (the
+// same complex-as-two-real-MFMAs scheme as k_circ_gemm, lane l holding
+// A[l % 16][l / 16], B[l / 16][l % 16], D[4 v + l / 16][l % 16]): per row disk p,
+//   w^p [n_p x R] = G [n_p x L] W^p [L x R],  G[j][f] = w^{f j};
+// the panel W^p is staged in LDS as [f][32 columns], each wave computing one
+// tile of 8 right-hand sides over all rows.  (The forward transform, n_q <= 63
+// terms per frequency, runs faster on the vector units: k_circ_fwd.)
+typedef double ct_d4 __attribute__((ext_vector_type(4)));
+#define CT_R 32       // right-hand sides per workgroup
+
+template <int TF>
+__device__ __forceinline__ void ct_product(const cplx* __restrict__ tw, int Lb, int nrow, int nk,
+                                           bool conj_tw, const cplx* __restrict__ panel, int c,
+                                           int j, int kq, ct_d4 (&acc1)[TF], ct_d4 (&acc2)[TF]) {
+  // acc += A[row][k] panel[k][c], A[row][k] = w^{+-row k}, rows < nrow, k < nk.
+  // Lane (j, kq) holds A[16 t + j][k] for its k = k0 + kq in registers and
+  // advances it by the factor w^{+-4 (16 t + j)} per K step (both read exactly
+  // from the twiddle table; four steps of rounding per 16 columns of k).
+  cplx a[TF], st[TF];
+#pragma unroll
+  for (int t = 0; t < TF; ++t) {
+    const int row = 16 * t + j;
+    a[t] = cmk(0.0, 0.0);
+    st[t] = cmk(0.0, 0.0);
+    if (row < nrow) {
+      a[t] = tw[(row * kq) % Lb];
+      st[t] = tw[(4 * row) % Lb];
+      if (conj_tw) {
+        a[t].y = -a[t].y;
+        st[t].y = -st[t].y;
+      }
+    }
+  }
+  for (int k0 = 0; k0 < nk; k0 += 4) {
+    const int k = k0 + kq;
+    const bool in = k < nk;
+    const cplx zz = in ? panel[k * CT_R + c] : cmk(0.0, 0.0);
+    const double bv = j < 8 ? zz.x : zz.y;
+#pragma unroll
+    for (int t = 0; t < TF; ++t) {
+      acc1[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(in ? a[t].x : 0.0, bv, acc1[t], 0, 0, 0);
+      acc2[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(in ? a[t].y : 0.0, bv, acc2[t], 0, 0, 0);
+      a[t] = cmul(a[t], st[t]);
+    }
+  }
+}
+
+// Output pass with the inverse transforms on the matrix cores: one workgroup
+// per (row disk p, 32 right-hand sides).  For an instance in the form, the
+// rows f of W^p are staged in LDS, wave w forms w^p_j for right-hand sides
+// 8w..8w+7 and leaves them in LDS; then, coalesced over the modes, the
+// close-pair partial sums are added and the epilogue applied.
+template <int TM>
+__global__ __launch_bounds__(256) void k_circ_finish_mfma(
     DevView v, int R, const cplx* __restrict__ x, cplx* __restrict__ y, int op,
     const cplx* __restrict__ part, int64_t blk, int npad, int RC, const int32_t* __restrict__ dgrp,
     const int32_t* __restrict__ drow, const int32_t* __restrict__ gnseg,
     const int64_t* __restrict__ gbase, const int32_t* __restrict__ active,
     const cplx* __restrict__ wh, const int32_t* __restrict__ con) {
   extern __shared__ cplx lds[];
-  const int p = blockIdx.x, tid = threadIdx.x;
+  cplx* tw = lds;                          // [L_b]
+  cplx* ws = lds + 128;                    // W^p rows [f][r], then the results [r][j]
+  const int p = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int j = lane & 15, kq = lane >> 4;
   const int b = v.inst[p];
-  const int r0 = blockIdx.y * CI_R;
+  const int r0 = blockIdx.y * CT_R;
   if (r0 >= R) return;
   const int np = 2 * v.N[p] + 1;
   const int64_t d0 = v.idisk[b], Mb = v.idisk[b + 1] - d0;
   const bool circ = con[b] != 0;
-  const int Lb = circ ? v.cL[b] : 0;
-  cplx* ws = lds;               // [L_b][CI_R]
-  cplx* tw = lds + Lb * CI_R;   // [L_b]
+  const int ldw = np + 1;
   if (circ) {
+    const int Lb = v.cL[b];
     const cplx* src = wh + (int64_t)R * v.cZo[b] + (p - d0) * R + r0;
-    for (int e = tid; e < Lb * CI_R; e += 256) {
-      const int f = e / CI_R, rr = e - (e / CI_R) * CI_R;
+    for (int e = tid; e < Lb * CT_R; e += 256) {
+      const int f = e / CT_R, rr = e - (e / CT_R) * CT_R;
       ws[e] = r0 + rr < R ? src[(int64_t)f * Mb * R + rr] : cmk(0.0, 0.0);
     }
     for (int e = tid; e < Lb; e += 256) tw[e] = v.ctw[v.cWo[b] + e];
+    __syncthreads();
+    ct_d4 acc1[TM], acc2[TM];
+#pragma unroll
+    for (int t = 0; t < TM; ++t) {
+      acc1[t] = ct_d4{0.0, 0.0, 0.0, 0.0};
+      acc2[t] = ct_d4{0.0, 0.0, 0.0, 0.0};
+    }
+    ct_product<TM>(tw, Lb, np, Lb, false, ws, 8 * wave + (j & 7), j, kq, acc1, acc2);
+    __syncthreads();  // every wave is done reading W^p: reuse ws for the results
+#pragma unroll
+    for (int t = 0; t < TM; ++t)
+#pragma unroll
+      for (int vv = 0; vv < 4; ++vv) {
+        const double a1 = acc1[t][vv], a2 = acc2[t][vv];
+        const double other = __shfl_xor(a2, 8, 64);
+        const double val = j < 8 ? a1 - other : a1 + other;
+        const double im = __shfl_xor(val, 8, 64);
+        const int m = 16 * t + 4 * vv + kq;
+        if (j < 8 && m < np) ws[(8 * wave + (j & 7)) * ldw + m] = cmk(val, im);
+      }
     __syncthreads();
   }
   const int gr = dgrp[p];
   const int ns = gnseg[gr];
   const int64_t ip = v.imode[b] + v.moff[p];
-  for (int e = tid; e < CI_R * np; e += 256) {
+  for (int e = tid; e < CT_R * np; e += 256) {
     const int rr = e / np, m = e - (e / np) * np;
     const int r = r0 + rr;
     if (r >= R || (active && active[b * R + r] == 0)) continue;
     const int t = r / RC, rc = r - (r / RC) * RC;
     const cplx* pr = part + (gbase[gr] + (int64_t)t * ns) * blk + ((int64_t)drow[p] * npad + m) * RC + rc;
-    cplx w = cmk(0.0, 0.0);
+    cplx w = circ ? ws[rr * ldw + m] : cmk(0.0, 0.0);
     for (int sg = 0; sg < ns; ++sg) w = cadd(w, pr[(int64_t)sg * blk]);
-    if (circ) {
-      cplx acc = cmk(0.0, 0.0);
-      int idx = 0;
-      for (int f = 0; f < Lb; ++f) {
-        cmac(acc, tw[idx], ws[f * CI_R + rr]);
-        idx += m;
-        if (idx >= Lb) idx -= Lb;
-      }
-      w = cadd(w, acc);
-    }
     const int64_t g = col_base(v.imode, b, R, r) + v.moff[p] + m;
     y[g] = finalize(v, op, ip + m, x[g], w);
   }
@@ -424,13 +483,16 @@ int circ_finish(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, const cplx
                 hipStream_t s) {
   int Lmax = 0;
   for (int32_t l : h->cL) Lmax = std::max(Lmax, (int)l);
-  const size_t lds = (size_t)Lmax * (CI_R + 1) * 16;
-  if (lds > 65536)
-    HIP_TRY(hipFuncSetAttribute((const void*)k_circ_finish, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)lds));
-  hipLaunchKernelGGL(k_circ_finish, dim3((unsigned)h->M_all, (unsigned)((R + CI_R - 1) / CI_R)), dim3(256),
-                     lds, s, h->dv, R, x, y, op, part, blk, npad, RC, dgrp, drow, gnseg, gbase, active,
-                     wh, con);
+  const int tm = (2 * h->Nmax + 1 + 15) / 16;  // row tiles: n_p <= 63 (N_p <= 31), L_b <= 125
+  typedef void (*fn_t)(DevView, int, const cplx*, cplx*, int, const cplx*, int64_t, int, int,
+                       const int32_t*, const int32_t*, const int32_t*, const int64_t*, const int32_t*,
+                       const cplx*, const int32_t*);
+  static const fn_t fin[5] = {nullptr, k_circ_finish_mfma<1>, k_circ_finish_mfma<2>, k_circ_finish_mfma<3>,
+                              k_circ_finish_mfma<4>};
+  if (tm < 1 || tm > 4 || Lmax > 128) return fail(MUDIFF_ERR_INVALID, "circulant form: orders out of range");
+  const size_t lds = (128 + (size_t)CT_R * std::max(Lmax, 2 * h->Nmax + 2)) * 16;
+  hipLaunchKernelGGL(fin[tm], dim3((unsigned)h->M_all, (unsigned)((R + CT_R - 1) / CT_R)), dim3(256), lds, s,
+                     h->dv, R, x, y, op, part, blk, npad, RC, dgrp, drow, gnseg, gbase, active, wh, con);
   HIP_TRY(hipGetLastError());
   return MUDIFF_OK;
 }

@@ -176,10 +176,45 @@ def _segmented_gmres(P, betas, restart, tol, label, seg_cycles=1, max_segments=2
     return rho, flag, its, time.perf_counter() - t0
 
 
+def circ_split(insts, R):
+    """Work of one batched apply in the form the library runs it: for the
+    instances in the circulant form (far-pair work >= half of the direct form's,
+    the library's rule), the per-frequency products, 8 R L_b per well-separated
+    ordered pair (L_b = 2 (N' + N'') + 1), and their minimal bytes (the
+    matrices T_f, 16 L_b M_b^2, and the transformed panels in and out,
+    2 x 16 R L_b M_b); and the direct form's 8 R n_p n_q for all other pairs.
+    Returns (product flops, product bytes, direct flops, instances in form)."""
+    import numpy as np
+    prod = direct = pbytes = 0.0
+    n_in = 0
+    for c in insts:
+        N = np.asarray(c.n_modes, dtype=np.int64)
+        n = 2 * N + 1
+        d = np.hypot(c.centers[:, None, 0] - c.centers[None, :, 0],
+                     c.centers[:, None, 1] - c.centers[None, :, 1])
+        near = c.k * d < (N[:, None] + N[None, :])
+        np.fill_diagonal(near, False)
+        w = np.outer(n, n).astype(float)
+        np.fill_diagonal(w, 0.0)
+        far = ~near
+        np.fill_diagonal(far, False)
+        Ns = np.sort(N)[::-1]
+        L = 2 * int(Ns[0] + Ns[1]) + 1 if len(N) > 1 else 0
+        if L > 0 and (w * far).sum() >= 0.5 * w.sum():
+            n_in += 1
+            prod += 8.0 * R * L * far.sum()
+            pbytes += 16.0 * L * len(N) ** 2 + 2 * 16.0 * R * L * len(N)
+            direct += 8.0 * R * (w * near).sum()
+        else:
+            direct += 8.0 * R * w.sum()
+    return prod, pbytes, direct, n_in
+
+
 def other_workload(args):
     """Documentation runs of the batched and differentiation workloads: the
-    batched apply rate against the FP64 MFMA roofline, the batched solve or
-    gradient, and the same work done one instance at a time on a sample."""
+    batched apply (phases timed by HIP events) against the FP64 MFMA roofline,
+    the batched solve or gradient, the same work one instance at a time on a
+    sample, and the oracle on a bounded sample."""
     import numpy as np
     import torch
 
@@ -189,35 +224,52 @@ def other_workload(args):
             "scaling": "weak", "vs_baseline": None, "dtype": "complex128 (f64)",
             "data": "synthetic (seeded disk clusters)"}
 
-    def time_apply(P, R, n, reps=5):
+    def apply_roofline(P, R, insts, reps=5):
+        n = sum(c.n_tot for c in insts)
         x = torch.randn(R * n, dtype=torch.complex128, device="cuda")
         y = P.empty(R)
-        P.matvec(x, R=R, op=1, out=y)       # first call of this R autotunes the tile
+        P.matvec(x, R=R, op=1, out=y)       # first call of this R times the forms and tiles
         torch.cuda.synchronize()
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record()
+        P.profile_begin(reps)
+        t0 = time.perf_counter()
         for _ in range(reps):
             P.matvec(x, R=R, op=1, out=y)
-        ev1.record()
-        ev1.synchronize()
-        return ev0.elapsed_time(ev1) / 1e3 / reps
-
-    def mfma_roofline(flops, t, cfg):
-        r = {"bound": "mfma", "achieved": flops / t / 1e12, "peak": 78.6, "unit": "TFLOP/s",
-             "frac": flops / t / 1e12 / 78.6, "traffic": None,
-             "kernel": "k_apply_mfma + k_apply_mfma_finish", "tile": cfg,
-             "algorithmic_flops_per_launch": flops}
-        r.update(measured_peaks(flops / t / 1e12, "fp64_mfma"))
-        return r
+        torch.cuda.synchronize()
+        t_app = (time.perf_counter() - t0) / reps
+        ph = P.profile_end()
+        k = ph.pop("applies")
+        ph = {key: v / k for key, v in ph.items()}
+        cfg = P.apply_config(R)
+        prod, pbytes, direct, n_in = circ_split(insts, R)
+        if cfg["kind"] == "circulant":
+            flops, kt = prod, ph["frequency_products"] / 1e3
+            kname = "k_circ_gemm (per-frequency products), tile %s" % (P.circulant_tile(R),)
+        else:
+            flops, kt = sum(algorithmic_flops(c.n_modes, R) for c in insts), ph["mfma_or_lane"] / 1e3
+            pbytes = 0.0
+            kname = "k_apply_mfma (direct Toeplitz tiles)"
+        # the bound is whichever of the minimal HBM traffic and the FP64 MFMA work
+        # takes longer at peak (few right-hand sides: the matrices T_f dominate)
+        if pbytes / (PEAK_HBM_GBS * 1e9) > flops / (PEAK_FP64_MFMA_TFLOPS * 1e12):
+            r = {"bound": "hbm", "achieved": pbytes / kt / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                 "frac": pbytes / kt / 1e9 / PEAK_HBM_GBS, "algorithmic_bytes_per_launch": pbytes,
+                 "flops_TFLOPs": flops / kt / 1e12}
+        else:
+            r = {"bound": "mfma", "achieved": flops / kt / 1e12, "peak": PEAK_FP64_MFMA_TFLOPS,
+                 "unit": "TFLOP/s", "frac": flops / kt / 1e12 / PEAK_FP64_MFMA_TFLOPS}
+            r.update(measured_peaks(flops / kt / 1e12, "fp64_mfma"))
+        r.update({"traffic": None, "kernel": kname, "kernel_ms": kt * 1e3, "apply": cfg,
+                  "algorithmic_flops_per_launch": flops, "instances_in_circulant_form": n_in,
+                  "direct_flops_of_close_pairs": direct})
+        return t_app, ph, r
 
     if args.workload == "uneven":
         insts = synth.uneven_instances()
         R = 8
         betas = np.stack([c.betas for c in insts])
-        P = Problem.from_clusters(insts)
+        P = Problem.from_clusters(insts, circulant=True)
         n = sum(c.n_tot for c in insts)
-        t_app = time_apply(P, R, n, reps=3)
-        flops = sum(algorithmic_flops(c.n_modes, R) for c in insts)
+        t_app, ph, roof = apply_roofline(P, R, insts, reps=5)
         rho, flag, its, t_s = _segmented_gmres(P, betas, 300, 1e-8, "uneven batched")
         it = its.numpy().reshape(len(insts), R)
         # the same solves one instance at a time, on a seeded sample
@@ -225,7 +277,7 @@ def other_workload(args):
         sample = sorted(rng.choice(len(insts), 16, replace=False).tolist())
         t1 = 0.0
         for b in sample:
-            Pb = Problem.from_cluster(insts[b])
+            Pb = Problem.from_cluster(insts[b], circulant=True)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             Pb.gmres(betas=betas[b:b + 1], restart=300, tol=1e-8, maxit=20000)
@@ -233,6 +285,14 @@ def other_workload(args):
             t1 += time.perf_counter() - t0
             Pb.close()
         per_inst_single = t1 / len(sample)
+        # the oracle: dense assembly + LU solve of the 8 incidences, same sample
+        from oracle import operator as oop, rhs as orhs, solve as osol
+        c0 = time.perf_counter()
+        for b in sample:
+            c = insts[b]
+            L = oop.efie_matrix(c.centers, c.radii, c.n_modes, c.k)
+            osol.efie_solve_lu(L, orhs.planewave(c.centers, c.radii, c.n_modes, c.k, c.betas))
+        t_cpu = (time.perf_counter() - c0) / len(sample) * len(insts)
         return {**base, "metric": "time-to-1e-8 GMRES solve (all instances)", "value": t_s,
                 "unit": "s", "higher_is_better": False, "ms_per_step": t_s * 1e3,
                 "config": {"workload": "uneven: 512 seeded instances, M~U{10..200}, k~U[1,20], "
@@ -240,12 +300,17 @@ def other_workload(args):
                                        "in each launch", "unknowns_x_rhs": n * R,
                            "iters_min": int(it.min()), "iters_max": int(it.max()),
                            "all_converged": bool((flag == 0).all())},
-                "apply_ms": t_app * 1e3,
-                "roofline": mfma_roofline(flops, t_app, P.apply_config(R)),
+                "apply_ms": t_app * 1e3, "apply_rate": n * R / t_app, "phases_ms": ph,
+                "roofline": roof,
                 "one_at_a_time": {"sample_instances": len(sample),
                                   "mean_s_per_instance": per_inst_single,
                                   "extrapolated_s_all": per_inst_single * len(insts),
-                                  "batched_speedup": per_inst_single * len(insts) / t_s}}
+                                  "batched_speedup": per_inst_single * len(insts) / t_s},
+                "cpu_baseline": {"value": t_cpu, "unit": "s (all instances)", "cores": _blas_threads(),
+                                 "kind": "oracle",
+                                 "sample": f"oracle dense assembly + LU solve (8 incidences) of the "
+                                           f"same {len(sample)} seeded instances, extrapolated by "
+                                           f"count to all {len(insts)}"}}
     if args.workload == "dort":
         return dort_workload(base)
     if args.workload == "formulations":
@@ -266,7 +331,7 @@ def other_workload(args):
     PT.close()
 
     def step(idx):
-        P = Problem.from_clusters([bases[i] for i in idx])
+        P = Problem.from_clusters([bases[i] for i in idx], circulant=True)
         out = P.grad(betas[idx], th, target[idx].reshape(-1), restart=50, tol=1e-8, maxit=20000)
         P.close()
         return out
@@ -284,10 +349,15 @@ def other_workload(args):
         step([i])
         torch.cuda.synchronize()
         t1 += time.perf_counter() - s0
-    P = Problem.from_clusters(bases)
-    n = sum(c.n_tot for c in bases)
-    t_app = time_apply(P, betas.shape[1], n, reps=3)
-    flops = sum(algorithmic_flops(c.n_modes, betas.shape[1]) for c in bases)
+    P = Problem.from_clusters(bases, circulant=True)
+    t_app, ph, roof = apply_roofline(P, betas.shape[1], bases, reps=5)
+    # the oracle adjoint gradient of one configuration (dense LU, 64 forward and
+    # 64 adjoint solves, chain rule over every factor)
+    from oracle import gradient as ograd
+    c0 = time.perf_counter()
+    ograd.misfit_grad(bases[0].centers, bases[0].radii, bases[0].n_modes, bases[0].k, bases[0].betas,
+                      th, target[0].cpu().numpy().reshape(len(bases[0].betas), -1))
+    t_cpu = time.perf_counter() - c0
     return {**base, "metric": "adjoint grads/s", "value": len(bases) / t, "unit": "gradients/s",
             "ms_per_step": t * 1e3,
             "config": {"workload": "differentiation: 32 configs, M=100, a~U[0.4,0.8], [0,40]^2, "
@@ -295,10 +365,14 @@ def other_workload(args):
                                    "adjoint GMRES(50) to 1e-8, gradient w.r.t. 200 center "
                                    "coordinates, 100 radii and k per config",
                        "configs_per_step": len(bases)},
-            "apply_ms": t_app * 1e3,
-            "roofline": mfma_roofline(flops, t_app, P.apply_config(betas.shape[1])),
+            "apply_ms": t_app * 1e3, "phases_ms": ph,
+            "roofline": roof,
             "one_at_a_time": {"sample_configs": 4, "grads_per_s": 4 / t1,
-                              "batched_speedup": (len(bases) / t) / (4 / t1)}}
+                              "batched_speedup": (len(bases) / t) / (4 / t1)},
+            "cpu_baseline": {"value": 1.0 / t_cpu, "unit": "gradients/s", "cores": _blas_threads(),
+                             "kind": "oracle",
+                             "sample": "oracle adjoint gradient of the first configuration "
+                                       f"(dense LU, 64 forward + 64 adjoint solves): {t_cpu:.1f} s"}}
 
 
 def dort_workload(base):

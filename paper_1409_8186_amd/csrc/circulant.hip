@@ -99,33 +99,36 @@ __global__ __launch_bounds__(256) void k_circ_fwd(DevView v, int R, const cplx* 
   const int q = blockIdx.x, tid = threadIdx.x;
   const int b = v.inst[q];
   if (!con[b]) return;
-  const int r0 = blockIdx.y * CF_R;
+  // columns per workgroup: 32, or 16 / 8 for fewer right-hand sides (the
+  // frequencies then spread over more threads)
+  const int cw = R >= CF_R ? CF_R : (R > 8 ? 16 : 8);
+  const int r0 = blockIdx.y * cw;
   if (r0 >= R) return;
   if (active) {
     bool any = false;
-    for (int r = r0; r < min(R, r0 + CF_R); ++r) any |= active[b * R + r] != 0;
+    for (int r = r0; r < min(R, r0 + cw); ++r) any |= active[b * R + r] != 0;
     if (!any) return;
   }
   const int Lb = v.cL[b];
   const int nq = 2 * v.N[q] + 1;
   const int64_t d0 = v.idisk[b], Mb = v.idisk[b + 1] - d0;
   const int64_t mq = v.moff[q];
-  for (int e = tid; e < CF_R * nq; e += 256) {
+  for (int e = tid; e < cw * nq; e += 256) {
     const int r = e / nq, k = e - (e / nq) * nq;
     cplx val = cmk(0.0, 0.0);
     if (r0 + r < R) val = z[col_base(v.imode, b, R, r0 + r) + mq + k];
-    zs[k * CF_R + r] = val;
+    zs[k * cw + r] = val;
   }
   for (int e = tid; e < Lb; e += 256) tw[e] = v.ctw[v.cWo[b] + e];
   __syncthreads();
-  const int r = tid & (CF_R - 1);
+  const int r = tid % cw;
   if (r0 + r >= R) return;
   cplx* out = zh + (int64_t)R * v.cZo[b] + (q - d0) * R + r0 + r;
-  for (int f = tid / CF_R; f < Lb; f += 256 / CF_R) {
+  for (int f = tid / cw; f < Lb; f += 256 / cw) {
     cplx acc = cmk(0.0, 0.0);
     int idx = 0;
     for (int k = 0; k < nq; ++k) {
-      cmacc(acc, tw[idx], zs[k * CF_R + r]);  // conj(w^{f k}) z_k
+      cmacc(acc, tw[idx], zs[k * cw + r]);  // conj(w^{f k}) z_k
       idx += f;
       if (idx >= Lb) idx -= Lb;
     }
@@ -313,25 +316,21 @@ typedef double ct_d4 __attribute__((ext_vector_type(4)));
 
 template <int TF>
 __device__ __forceinline__ void ct_product(const cplx* __restrict__ tw, int Lb, int nrow, int nk,
-                                           bool conj_tw, const cplx* __restrict__ panel, int c,
-                                           int j, int kq, ct_d4 (&acc1)[TF], ct_d4 (&acc2)[TF]) {
-  // acc += A[row][k] panel[k][c], A[row][k] = w^{+-row k}, rows < nrow, k < nk.
-  // Lane (j, kq) holds A[16 t + j][k] for its k = k0 + kq in registers and
-  // advances it by the factor w^{+-4 (16 t + j)} per K step (both read exactly
-  // from the twiddle table; four steps of rounding per 16 columns of k).
+                                           const cplx* __restrict__ panel, int c, int j, int kq,
+                                           int t0, int ts, ct_d4 (&acc1)[TF], ct_d4 (&acc2)[TF]) {
+  // acc[t] += A[row][k] panel[k][c] for the row tile 16 (t0 + ts t), A[row][k] = w^{row k},
+  // rows < nrow, k < nk.  Lane (j, kq) holds A[row][k] for its k = k0 + kq in
+  // registers and advances it by the factor w^{4 row} per K step (both read
+  // exactly from the twiddle table; a few steps of rounding per entry).
   cplx a[TF], st[TF];
 #pragma unroll
   for (int t = 0; t < TF; ++t) {
-    const int row = 16 * t + j;
+    const int row = 16 * (t0 + ts * t) + j;
     a[t] = cmk(0.0, 0.0);
     st[t] = cmk(0.0, 0.0);
     if (row < nrow) {
       a[t] = tw[(row * kq) % Lb];
       st[t] = tw[(4 * row) % Lb];
-      if (conj_tw) {
-        a[t].y = -a[t].y;
-        st[t].y = -st[t].y;
-      }
     }
   }
   for (int k0 = 0; k0 < nk; k0 += 4) {
@@ -341,6 +340,7 @@ __device__ __forceinline__ void ct_product(const cplx* __restrict__ tw, int Lb, 
     const double bv = j < 8 ? zz.x : zz.y;
 #pragma unroll
     for (int t = 0; t < TF; ++t) {
+      if (16 * (t0 + ts * t) >= nrow) continue;  // wave-uniform
       acc1[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(in ? a[t].x : 0.0, bv, acc1[t], 0, 0, 0);
       acc2[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(in ? a[t].y : 0.0, bv, acc2[t], 0, 0, 0);
       a[t] = cmul(a[t], st[t]);
@@ -349,25 +349,33 @@ __device__ __forceinline__ void ct_product(const cplx* __restrict__ tw, int Lb, 
 }
 
 // Output pass with the inverse transforms on the matrix cores: one workgroup
-// per (row disk p, 32 right-hand sides).  For an instance in the form, the
-// rows f of W^p are staged in LDS, wave w forms w^p_j for right-hand sides
-// 8w..8w+7 and leaves them in LDS; then, coalesced over the modes, the
-// close-pair partial sums are added and the epilogue applied.
+// per (row disk p, 8 nct right-hand sides, nct = 4 / wpc column tiles).  For an
+// instance in the form, the rows f of W^p are staged in LDS, and the wpc waves
+// of column tile w / wpc form w^p_j for its 8 right-hand sides, row tiles
+// w % wpc, w % wpc + wpc, ..., leaving them in LDS; then, coalesced over the
+// modes, the close-pair partial sums are added and the epilogue applied.
+// Workgroups whose right-hand sides have all stopped iterating do nothing.
 template <int TM>
 __global__ __launch_bounds__(256) void k_circ_finish_mfma(
     DevView v, int R, const cplx* __restrict__ x, cplx* __restrict__ y, int op,
     const cplx* __restrict__ part, int64_t blk, int npad, int RC, const int32_t* __restrict__ dgrp,
     const int32_t* __restrict__ drow, const int32_t* __restrict__ gnseg,
     const int64_t* __restrict__ gbase, const int32_t* __restrict__ active,
-    const cplx* __restrict__ wh, const int32_t* __restrict__ con) {
+    const cplx* __restrict__ wh, const int32_t* __restrict__ con, int wpc) {
   extern __shared__ cplx lds[];
   cplx* tw = lds;                          // [L_b]
   cplx* ws = lds + 128;                    // W^p rows [f][r], then the results [r][j]
   const int p = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int j = lane & 15, kq = lane >> 4;
   const int b = v.inst[p];
-  const int r0 = blockIdx.y * CT_R;
+  const int ncol = 8 * (4 / wpc);          // right-hand sides of this workgroup
+  const int r0 = blockIdx.y * ncol;
   if (r0 >= R) return;
+  if (active) {
+    bool any = false;
+    for (int r = r0; r < min(R, r0 + ncol); ++r) any |= active[b * R + r] != 0;
+    if (!any) return;
+  }
   const int np = 2 * v.N[p] + 1;
   const int64_t d0 = v.idisk[b], Mb = v.idisk[b + 1] - d0;
   const bool circ = con[b] != 0;
@@ -377,7 +385,7 @@ __global__ __launch_bounds__(256) void k_circ_finish_mfma(
     const cplx* src = wh + (int64_t)R * v.cZo[b] + (p - d0) * R + r0;
     for (int e = tid; e < Lb * CT_R; e += 256) {
       const int f = e / CT_R, rr = e - (e / CT_R) * CT_R;
-      ws[e] = r0 + rr < R ? src[(int64_t)f * Mb * R + rr] : cmk(0.0, 0.0);
+      ws[e] = rr < ncol && r0 + rr < R ? src[(int64_t)f * Mb * R + rr] : cmk(0.0, 0.0);
     }
     for (int e = tid; e < Lb; e += 256) tw[e] = v.ctw[v.cWo[b] + e];
     __syncthreads();
@@ -387,7 +395,8 @@ __global__ __launch_bounds__(256) void k_circ_finish_mfma(
       acc1[t] = ct_d4{0.0, 0.0, 0.0, 0.0};
       acc2[t] = ct_d4{0.0, 0.0, 0.0, 0.0};
     }
-    ct_product<TM>(tw, Lb, np, Lb, false, ws, 8 * wave + (j & 7), j, kq, acc1, acc2);
+    const int ct = wave / wpc, t0 = wave - (wave / wpc) * wpc;
+    ct_product<TM>(tw, Lb, np, Lb, ws, 8 * ct + (j & 7), j, kq, t0, wpc, acc1, acc2);
     __syncthreads();  // every wave is done reading W^p: reuse ws for the results
 #pragma unroll
     for (int t = 0; t < TM; ++t)
@@ -397,15 +406,15 @@ __global__ __launch_bounds__(256) void k_circ_finish_mfma(
         const double other = __shfl_xor(a2, 8, 64);
         const double val = j < 8 ? a1 - other : a1 + other;
         const double im = __shfl_xor(val, 8, 64);
-        const int m = 16 * t + 4 * vv + kq;
-        if (j < 8 && m < np) ws[(8 * wave + (j & 7)) * ldw + m] = cmk(val, im);
+        const int m = 16 * (t0 + wpc * t) + 4 * vv + kq;
+        if (j < 8 && m < np) ws[(8 * ct + (j & 7)) * ldw + m] = cmk(val, im);
       }
     __syncthreads();
   }
   const int gr = dgrp[p];
   const int ns = gnseg[gr];
   const int64_t ip = v.imode[b] + v.moff[p];
-  for (int e = tid; e < CT_R * np; e += 256) {
+  for (int e = tid; e < ncol * np; e += 256) {
     const int rr = e / np, m = e - (e / np) * np;
     const int r = r0 + rr;
     if (r >= R || (active && active[b * R + r] == 0)) continue;
@@ -464,7 +473,8 @@ void circ_var_dims(int var, int* bm, int* bn, int* bk, int* db, int* nt) {
 // z: inputs scaled by their column factors [B][R][N_b]; zh, wh: [sum_b L_b M_b][R].
 int circ_launch(mudiff_ctx* h, int R, const cplx* z, cplx* zh, cplx* wh, const int32_t* citems,
                 int n_citems, int var, const int32_t* con, const int32_t* active, hipStream_t s) {
-  hipLaunchKernelGGL(k_circ_fwd, dim3((unsigned)h->M_all, (unsigned)((R + CF_R - 1) / CF_R)), dim3(256), 0,
+  const int cw = R >= CF_R ? CF_R : (R > 8 ? 16 : 8);
+  hipLaunchKernelGGL(k_circ_fwd, dim3((unsigned)h->M_all, (unsigned)((R + cw - 1) / cw)), dim3(256), 0,
                      s, h->dv, R, z, zh, con, active);
   HIP_TRY(hipGetLastError());
   prof_mark(h, s, 2);
@@ -484,15 +494,19 @@ int circ_finish(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, const cplx
   int Lmax = 0;
   for (int32_t l : h->cL) Lmax = std::max(Lmax, (int)l);
   const int tm = (2 * h->Nmax + 1 + 15) / 16;  // row tiles: n_p <= 63 (N_p <= 31), L_b <= 125
+  // waves per 8-column tile: few right-hand sides spread the row tiles instead
+  const int wpc = R >= 32 ? 1 : (R > 8 ? 2 : 4);
+  const int tmw = (tm + wpc - 1) / wpc;
   typedef void (*fn_t)(DevView, int, const cplx*, cplx*, int, const cplx*, int64_t, int, int,
                        const int32_t*, const int32_t*, const int32_t*, const int64_t*, const int32_t*,
-                       const cplx*, const int32_t*);
+                       const cplx*, const int32_t*, int);
   static const fn_t fin[5] = {nullptr, k_circ_finish_mfma<1>, k_circ_finish_mfma<2>, k_circ_finish_mfma<3>,
                               k_circ_finish_mfma<4>};
   if (tm < 1 || tm > 4 || Lmax > 128) return fail(MUDIFF_ERR_INVALID, "circulant form: orders out of range");
   const size_t lds = (128 + (size_t)CT_R * std::max(Lmax, 2 * h->Nmax + 2)) * 16;
-  hipLaunchKernelGGL(fin[tm], dim3((unsigned)h->M_all, (unsigned)((R + CT_R - 1) / CT_R)), dim3(256), lds, s,
-                     h->dv, R, x, y, op, part, blk, npad, RC, dgrp, drow, gnseg, gbase, active, wh, con);
+  const int ncol = 8 * (4 / wpc);
+  hipLaunchKernelGGL(fin[tmw], dim3((unsigned)h->M_all, (unsigned)((R + ncol - 1) / ncol)), dim3(256), lds, s,
+                     h->dv, R, x, y, op, part, blk, npad, RC, dgrp, drow, gnseg, gbase, active, wh, con, wpc);
   HIP_TRY(hipGetLastError());
   return MUDIFF_OK;
 }

@@ -702,11 +702,35 @@ static void mfma_build(const mudiff_ctx* h, int R, const MfmaChoice& c, MfmaSche
     const bool circ = c.circ && h->circ && h->circ_on[b];
     S.con[b] = circ ? 1 : 0;
     const int64_t qs = c.QS > 0 ? c.QS : Mb;
-    // row disks ordered by their number of 16-row tiles (stable), in groups of RP
+    // row disks ordered by their number of 16-row tiles (stable), in groups of
+    // RP; for the column lists of the circulant form, by a Z-order (Morton)
+    // code of their centers within each tile class, so that a group's rows are
+    // neighbours and share most of their close column disks
     std::vector<int32_t> ord((size_t)Mb);
     for (int64_t k = 0; k < Mb; ++k) ord[(size_t)k] = (int32_t)(d0 + k);
+    std::vector<uint32_t> zc;
+    if (circ) {
+      double x0 = h->cx[d0], x1 = x0, y0 = h->cy[d0], y1 = y0;
+      for (int64_t q = d0; q < d1; ++q) {
+        x0 = std::min(x0, h->cx[q]);
+        x1 = std::max(x1, h->cx[q]);
+        y0 = std::min(y0, h->cy[q]);
+        y1 = std::max(y1, h->cy[q]);
+      }
+      const double sc = 65535.0 / std::max(std::max(x1 - x0, y1 - y0), 1e-300);
+      zc.resize((size_t)Mb);
+      for (int64_t k = 0; k < Mb; ++k) {
+        const uint32_t ix = (uint32_t)((h->cx[d0 + k] - x0) * sc), iy = (uint32_t)((h->cy[d0 + k] - y0) * sc);
+        uint32_t z = 0;
+        for (int bit = 0; bit < 16; ++bit)
+          z |= (((ix >> bit) & 1u) << (2 * bit)) | (((iy >> bit) & 1u) << (2 * bit + 1));
+        zc[(size_t)k] = z;
+      }
+    }
     std::stable_sort(ord.begin(), ord.end(), [&](int32_t u, int32_t w) {
-      return (2 * h->N[u] + 16) / 16 > (2 * h->N[w] + 16) / 16;
+      const int tu = (2 * h->N[u] + 16) / 16, tw = (2 * h->N[w] + 16) / 16;
+      if (tu != tw) return tu > tw;
+      return circ && zc[(size_t)(u - d0)] < zc[(size_t)(w - d0)];
     });
     for (int64_t o = 0; o < Mb; o += c.RP) {
       const int rp = (int)std::min<int64_t>(c.RP, Mb - o);

@@ -131,7 +131,7 @@ def test_uneven_instances_full_size_gmres(P):
     residual equals the oracle's ||A x - f|| / ||f|| of the returned iterate.
     The sampled instances (the largest, the smallest, the three slowest and
     two seeded ones) are then re-solved together at tol 1e-13 and compared
-    with oracle LU at the spec bar, 1e-10."""
+    with oracle LU at the parity bar, 1e-10."""
     insts = synth.uneven_instances()
     R = 8
     say("uneven: instances", len(insts), "unknowns", sum(c.n_tot for c in insts))

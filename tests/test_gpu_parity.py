@@ -6,7 +6,7 @@ Tolerances (relative, norm-wise per column unless stated):
     to ~1e-13 relative to |H|; arguments up to ~2e3 move the phase by x*eps);
   * operator apply: 1e-12 (a sum of N_tot products of O(1) terms in FP64);
   * right-hand side, far field of a given density: 1e-13;
-  * solutions / far fields of solves at tol 1e-12: 1e-10 (the spec bar).
+  * solutions / far fields of solves at tol 1e-12: 1e-10 (the parity bar for solutions).
 """
 import math
 

@@ -78,8 +78,13 @@ enum {
   MUDIFF_X0 = 1,        /* rho holds the initial guess on entry (else x0 = 0)          */
   MUDIFF_GRAPH = 2,     /* replay each restart cycle as one captured HIP graph          */
   MUDIFF_POINT_SOURCE = 4, /* beta holds point-source positions [B][R][2] (Prop. 5)  */
-  MUDIFF_NO_PRECOND = 8  /* GMRES on L rho = -U itself (no single-scattering preconditioner) */
+  MUDIFF_NO_PRECOND = 8, /* GMRES on L rho = -U itself (no single-scattering preconditioner) */
+  MUDIFF_BLOCK = 16      /* block GMRES: blocks of consecutive columns of an instance share one
+                            block Krylov space (block size: MUDIFF_BLOCK_SIZE, default 8) */
 };
+/* Block size s of a MUDIFF_BLOCK solve, or'ed into the flags: 1 <= s <= 16 and
+ * restart * s <= 2048 (a block never exceeds the instance's R columns). */
+#define MUDIFF_BLOCK_SIZE(s) (((s) & 0xff) << 8)
 
 /* mudiff_tables flags */
 enum {
@@ -94,7 +99,8 @@ enum {
 /* ---------------------------------------------------------------- tables */
 
 /* Bytes of device workspace mudiff_tables needs for this batch and flags
- * (pure host computation, no device call).  Returns 0 for invalid arguments. */
+ * (pure host computation, no device call).  Returns 0 for invalid arguments,
+ * including MUDIFF_TABLES_CIRCULANT with an order N_p > 31. */
 size_t mudiff_tables_workspace_size(int B, const int64_t* disk_off /*[host] B+1*/,
                                     const int32_t* n_modes /*[host] M_tot*/, int flags);
 
@@ -168,7 +174,7 @@ int mudiff_circulant_tile(mudiff_t h, int R, int* rows, int* cols, int* kstep, i
 int mudiff_set_circulant_tile(mudiff_t h, int R, int rows, int cols, int kstep, int stages,
                               int threads);
 
-/* Releases the host handle (not the caller's device memory). */
+/* Releases the host handle (not the caller's device memory); NULL is a no-op. */
 int mudiff_destroy(mudiff_t h);
 
 /* Unknowns per instance: n_tot[b] = N_b (host array of B entries). */
@@ -396,7 +402,22 @@ size_t mudiff_gmres_workspace_size(mudiff_t h, int R, int restart, int flags);
  *   resvec     device double [B][R][maxit+1] Arnoldi residual estimates
  *              |g_{j+1}| / ||f|| (entry 0 = initial), or NULL
  * Non-convergence is not an error: the call returns MUDIFF_OK with flag != 0.
- * Columns that converge stop iterating (their Krylov work is skipped). */
+ * Columns that converge stop iterating (their Krylov work is skipped).
+ * With MUDIFF_BLOCK the columns r = k s .. k s + s - 1 of each instance form
+ * block k (the last one may be narrower) and share one block Krylov space
+ * (block Arnoldi; the paper's solver is single-vector GMRES, sec. 5): each step
+ * applies the operator to the block's s basis vectors in one batched apply,
+ * orthogonalises against the block basis (classical Gram-Schmidt twice), and
+ * factors the new block by Cholesky QR twice, dropping directions whose pivot
+ * falls below 1e-14 of the column's squared norm.  The least-squares problem
+ * is triangularised by Householder reflectors as it grows, giving each column's
+ * residual estimate after every step; a block stops when all its columns meet
+ * tol (or at maxit), and at a restart the columns whose true residual meets
+ * tol leave the block.  iters counts block steps, resvec the estimates.  The
+ * restart cycle is one block step sequence of up to `restart` steps (block
+ * Krylov dimension restart * s).  The straggler compaction of the lockstep
+ * solver is not used.  Errors: MUDIFF_ERR_INVALID for a block size out of
+ * range or unknown flags. */
 int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* rhs, void* rho,
                  int restart, double tol, int maxit, int flags,
                  void* workspace, size_t ws_bytes,

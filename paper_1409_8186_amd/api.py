@@ -240,12 +240,16 @@ class Problem:
 
     def gmres(self, betas=None, rhs=None, R: int | None = None, restart: int = 50,
               tol: float = 1e-8, maxit: int = 20000, x0=None, graph: bool = False,
-              want_resvec: bool = False, workspace=None, sources=None, precond: bool = True):
+              want_resvec: bool = False, workspace=None, sources=None, precond: bool = True,
+              block: int = 0):
         """Solves L rho = -U for plane waves (betas [B, R]), point sources
         (sources [B, R, 2]) or a given U (rhs), with the single-scattering
-        preconditioner unless precond=False.  Returns (rho, flag, relres,
+        preconditioner unless precond=False; block > 0 runs block GMRES with
+        blocks of that many consecutive columns.  Returns (rho, flag, relres,
         iters, resvec)."""
         flags = 0 if precond else L.NO_PRECOND
+        if block:
+            flags |= L.BLOCK | L.block_size(block)
         bt = None
         if sources is not None:
             bt = self._sources(sources)

@@ -852,6 +852,536 @@ __global__ void k_precond_rhs(DevView v, int R, const cplx* __restrict__ src, cp
   f[g] = div ? cscale(cdiv(src[g], v.op_diag ? v.op_diag[i] : v.Ldiag[i]), scale) : cscale(src[g], scale);
 }
 
+// ------------------------------------------------------------------ block GMRES
+// With MUDIFF_BLOCK the R columns of an instance are split into blocks of sb
+// consecutive columns, and the columns of a block share one block Krylov space
+// (block Arnoldi): step j applies the operator to the sb basis vectors of
+// block V_j at once, orthogonalises the result W against V_0..V_j by classical
+// Gram-Schmidt applied twice, and factors W = V_{j+1} H_{j+1,j} by Cholesky QR
+// applied twice (a Cholesky pivot below 1e-14 of its column's squared norm drops
+// that direction: its basis vector is zero from then on).  The block
+// Hessenberg matrix is reduced to triangular form by one Householder reflector
+// of length sb + 1 per column as it grows, and the same reflectors applied to
+// the right-hand sides E_1 B (B from the QR of the block's residual) give every
+// column's residual estimate after every step.  A block stops when all its
+// columns are below the tolerance (or at the end of the cycle, or at maxit);
+// at a restart the columns whose true residual meets the tolerance leave the
+// block (their vectors are zero in the next cycle).  The basis blocks are the
+// same packed multivectors [B][R][N_b] as the lockstep basis: V_j of every
+// block of every instance is one multivector, so each step is one batched
+// operator apply.  Reductions over rows go through per-chunk partial sums
+// added in chunk order, as in the lockstep kernels.
+#define BG_SMAX 16      // largest block
+#define BG_TILE 64      // rows per LDS tile
+#define BG_CHUNK 1024   // rows per reduction chunk
+#define BG_MAXDIM 2048  // largest restart * block size (the back substitution stages it in LDS)
+
+struct BState {
+  GState s;
+  const int64_t* imode;  // [B + 1] first unknown of every instance
+  int sb;                // columns per block
+  int nbpi;              // blocks per instance
+  int NB;                // blocks
+  const int32_t* bck;    // [n_chunks][2] block, first row of every reduction chunk
+  const int32_t* bckoff; // [NB + 1] first chunk of every block
+  const int32_t* btile;  // [NB + 1] first 64-row tile of every block
+  cplx* P;               // [n_chunks][m + 1][sb * sb] partial sums
+  cplx* T;               // [NB][sb][(m + 1) sb] Gram-Schmidt coefficients, column-major
+  cplx* Hb;              // [NB][m sb][(m + 1) sb] block Hessenberg (triangularised in place)
+  cplx* Gb;              // [NB][sb][(m + 1) sb] right-hand sides of the least-squares problem
+  cplx* Rq;              // [NB][sb][sb] factor of the first Cholesky QR pass
+  cplx* Ri;              // [NB][sb][sb] inverse of the current Cholesky QR factor
+  cplx* hv;              // [NB][m sb][sb + 1] Householder vectors (first entry 1)
+  cplx* htau;            // [NB][m sb] Householder coefficients
+  cplx* Y;               // [NB][sb][(m + 1) sb] solution of the least-squares problem
+  int32_t* bin;          // [NB] block iterating in the current cycle
+  int32_t* brun;         // [NB] block has a running column in the current cycle
+  int32_t* bsteps;       // [NB] steps done in the current cycle
+  int32_t* bact;         // [C] column takes part in the next operator apply
+};
+
+__device__ __forceinline__ int bg_ld(const BState& bs) { return (bs.s.m + 1) * bs.sb; }
+
+// Block of a reduction chunk / of a 64-row tile (binary search in the prefix).
+__device__ __forceinline__ int bg_find(const int32_t* pre, int n, int g) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= g) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Column cl of block kb: global column index (or -1 past R) and its first entry.
+__device__ __forceinline__ int bg_col(const BState& bs, int kb, int cl, int64_t* base) {
+  const int b = kb / bs.nbpi, r = (kb % bs.nbpi) * bs.sb + cl;
+  if (cl >= bs.sb || r >= bs.s.R) return -1;
+  *base = col_base(bs.imode, b, bs.s.R, r);
+  return b * bs.s.R + r;
+}
+
+// P[chunk][i][a sb + c] = sum over the chunk's rows of conj(V_i[row][a]) W[row][c]
+// for i < gridDim.y (V_i = Vb + i vstride), blocks with gate[kb] set; columns
+// that are not running count as zero.  Thread (a, c) of each row phase adds
+// every rsplit-th row of each LDS tile; the phases are added in order.
+__global__ __launch_bounds__(256) void k_bdots(BState bs, const cplx* __restrict__ Vb,
+                                               int64_t vstride, const cplx* __restrict__ W,
+                                               const int32_t* __restrict__ gate) {
+  __shared__ cplx vt[BG_TILE * BG_SMAX];
+  __shared__ cplx wt[BG_TILE * BG_SMAX];
+  __shared__ cplx red[256];
+  const int g = blockIdx.x, i = blockIdx.y, t = threadIdx.x;
+  const int kb = bs.bck[2 * g], row0 = bs.bck[2 * g + 1];
+  if (!gate[kb]) return;
+  const int sb = bs.sb, np = sb * sb;
+  const int rsplit = max(1, 256 / np);
+  const int pr = t % np, rs = t / np;
+  const int a = pr / sb, c = pr % sb;
+  const int b = kb / bs.nbpi;
+  const int64_t Nb = bs.imode[b + 1] - bs.imode[b];
+  const int rows = (int)min((int64_t)BG_CHUNK, Nb - row0);
+  const cplx* Vi = Vb + (int64_t)i * vstride;
+  cplx acc = cmk(0.0, 0.0);
+  for (int t0 = 0; t0 < rows; t0 += BG_TILE) {
+    const int tl = min(BG_TILE, rows - t0);
+    __syncthreads();
+    for (int e = t; e < BG_TILE * sb; e += 256) {
+      const int col = e / BG_TILE, rr = e - col * BG_TILE;
+      cplx v = cmk(0.0, 0.0), w = cmk(0.0, 0.0);
+      int64_t base;
+      const int cc = bg_col(bs, kb, col, &base);
+      if (cc >= 0 && rr < tl && bs.s.run[cc]) {
+        const int64_t off = base + row0 + t0 + rr;
+        v = Vi[off];
+        w = W[off];
+      }
+      vt[rr * sb + col] = v;
+      wt[rr * sb + col] = w;
+    }
+    __syncthreads();
+    if (rs < rsplit)
+      for (int rr = rs; rr < tl; rr += rsplit) cmacc(acc, vt[rr * sb + a], wt[rr * sb + c]);
+  }
+  red[t] = acc;
+  __syncthreads();
+  if (t < np) {
+    cplx sum = red[t];
+    for (int q = 1; q < rsplit; ++q) sum = cadd(sum, red[q * np + t]);
+    bs.P[((int64_t)g * (bs.s.m + 1) + i) * np + t] = sum;
+  }
+}
+
+// Gram-Schmidt coefficients of step j from the chunk partials (chunk order):
+// T[kb] rows i sb + a, column c; the Hessenberg block column j receives them
+// (pass 0) or adds them (pass 1).
+__global__ __launch_bounds__(256) void k_bsum(BState bs, int j, int pass) {
+  const int kb = blockIdx.x, i = blockIdx.y, t = threadIdx.x;
+  if (!bs.bin[kb]) return;
+  const int sb = bs.sb, np = sb * sb, ld = bg_ld(bs);
+  if (t >= np) return;
+  const int a = t / sb, c = t % sb;
+  cplx sum = cmk(0.0, 0.0);
+  for (int g = bs.bckoff[kb]; g < bs.bckoff[kb + 1]; ++g)
+    sum = cadd(sum, bs.P[((int64_t)g * (bs.s.m + 1) + i) * np + t]);
+  bs.T[(int64_t)kb * ld * sb + (int64_t)c * ld + i * sb + a] = sum;
+  cplx* h = bs.Hb + (int64_t)kb * ld * (bs.s.m * sb) + (int64_t)(j * sb + c) * ld + i * sb + a;
+  *h = pass ? cadd(*h, sum) : sum;
+}
+
+// W[row][c] += sign * sum_{i < n_i} sum_a V_i[row][a] coef[kb][c][i sb + a] over
+// the rows of every block with gate[kb] set (n_i = nsteps[kb] * ... when given,
+// else ni), running columns only.  One 64-row tile per workgroup; thread
+// (row, column group) keeps up to 4 columns; the basis tile and the sb x sb
+// coefficients of each i are staged in LDS.
+__global__ __launch_bounds__(256) void k_bupdate(BState bs, const cplx* __restrict__ Vb,
+                                                 int64_t vstride, cplx* __restrict__ W,
+                                                 const cplx* __restrict__ coef, int ni,
+                                                 const int32_t* __restrict__ nsteps,
+                                                 const int32_t* __restrict__ gate, double sign) {
+  __shared__ cplx vt[BG_TILE * BG_SMAX];
+  __shared__ cplx cs[BG_SMAX * BG_SMAX];
+  const int t = threadIdx.x;
+  const int kb = bg_find(bs.btile, bs.NB, blockIdx.x);
+  if (!gate[kb]) return;
+  const int sb = bs.sb, ld = bg_ld(bs);
+  const int b = kb / bs.nbpi;
+  const int64_t Nb = bs.imode[b + 1] - bs.imode[b];
+  const int row0 = (blockIdx.x - bs.btile[kb]) * BG_TILE;
+  const int tl = (int)min((int64_t)BG_TILE, Nb - row0);
+  const int n_i = nsteps ? nsteps[kb] : ni;
+  const int rr = t & 63, cg = t >> 6;
+  cplx acc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = cmk(0.0, 0.0);
+  const cplx* ck = coef + (int64_t)kb * ld * sb;
+  for (int i = 0; i < n_i; ++i) {
+    __syncthreads();
+    for (int e = t; e < sb * sb; e += 256) {
+      const int a = e / sb, c = e - a * sb;
+      cs[e] = ck[(int64_t)c * ld + i * sb + a];
+    }
+    const cplx* Vi = Vb + (int64_t)i * vstride;
+    for (int e = t; e < BG_TILE * sb; e += 256) {
+      const int col = e / BG_TILE, r = e - col * BG_TILE;
+      cplx v = cmk(0.0, 0.0);
+      int64_t base;
+      const int cc = bg_col(bs, kb, col, &base);
+      if (cc >= 0 && r < tl && bs.s.run[cc]) v = Vi[base + row0 + r];
+      vt[r * sb + col] = v;
+    }
+    __syncthreads();
+    for (int a = 0; a < sb; ++a) {
+      const cplx v = vt[rr * sb + a];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = cg + 4 * q;
+        if (c < sb) cmac(acc[q], v, cs[a * sb + c]);
+      }
+    }
+  }
+  if (rr >= tl) return;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int c = cg + 4 * q;
+    int64_t base;
+    const int cc = bg_col(bs, kb, c, &base);
+    if (cc < 0 || !bs.s.run[cc]) continue;
+    const int64_t off = base + row0 + rr;
+    W[off] = cadd(W[off], cscale(acc[q], sign));
+  }
+}
+
+// W = W Ri[kb] (Ri upper triangular) over the rows of every block with
+// gate[kb] set; columns that are not running are set to zero.
+__global__ __launch_bounds__(256) void k_bscale(BState bs, cplx* __restrict__ W,
+                                                const int32_t* __restrict__ gate) {
+  __shared__ cplx wt[BG_TILE * BG_SMAX];
+  __shared__ cplx cs[BG_SMAX * BG_SMAX];
+  const int t = threadIdx.x;
+  const int kb = bg_find(bs.btile, bs.NB, blockIdx.x);
+  if (!gate[kb]) return;
+  const int sb = bs.sb;
+  const int b = kb / bs.nbpi;
+  const int64_t Nb = bs.imode[b + 1] - bs.imode[b];
+  const int row0 = (blockIdx.x - bs.btile[kb]) * BG_TILE;
+  const int tl = (int)min((int64_t)BG_TILE, Nb - row0);
+  for (int e = t; e < sb * sb; e += 256) cs[e] = bs.Ri[(int64_t)kb * sb * sb + e];
+  for (int e = t; e < BG_TILE * sb; e += 256) {
+    const int col = e / BG_TILE, r = e - col * BG_TILE;
+    cplx v = cmk(0.0, 0.0);
+    int64_t base;
+    const int cc = bg_col(bs, kb, col, &base);
+    if (cc >= 0 && r < tl && bs.s.run[cc]) v = W[base + row0 + r];
+    wt[r * sb + col] = v;
+  }
+  __syncthreads();
+  const int rr = t & 63, cg = t >> 6;
+  if (rr >= tl) return;
+  for (int c = cg; c < sb; c += 4) {
+    int64_t base;
+    const int cc = bg_col(bs, kb, c, &base);
+    if (cc < 0) continue;
+    cplx acc = cmk(0.0, 0.0);
+    if (bs.s.run[cc])
+      for (int a = 0; a <= c; ++a) cmac(acc, wt[rr * sb + a], cs[a * sb + c]);
+    W[base + row0 + rr] = acc;
+  }
+}
+
+// Cholesky QR factor of one block: Gram matrix G = W^H W from the chunk
+// partials (slot 0), G = R^H R with R upper triangular, a pivot below 1e-14 of
+// its column's squared norm (or not positive) dropping that row of R, and
+// Ri = the inverse of R on the kept rows (zero elsewhere), so that W Ri has
+// orthonormal kept columns and zero dropped ones.  mode 0 (first pass): Rq = R.
+// mode 1 (second pass): the factor of the original W is R Rq; at step j >= 0 it
+// is the Hessenberg block H_{j+1,j}; at j < 0 (start of a cycle) it is the
+// first block of the right-hand sides (the rest of Gb is cleared).
+__global__ __launch_bounds__(256) void k_bchol(BState bs, int mode, int j,
+                                               const int32_t* __restrict__ gate) {
+  __shared__ cplx G[BG_SMAX * BG_SMAX];   // [a][c], becomes R
+  __shared__ cplx Ii[BG_SMAX * BG_SMAX];
+  __shared__ double dg[BG_SMAX];
+  __shared__ double piv[BG_SMAX];
+  const int kb = blockIdx.x, t = threadIdx.x;
+  if (!gate[kb]) return;
+  const int sb = bs.sb, np = sb * sb, ld = bg_ld(bs);
+  if (t < np) {
+    cplx sum = cmk(0.0, 0.0);
+    for (int g = bs.bckoff[kb]; g < bs.bckoff[kb + 1]; ++g)
+      sum = cadd(sum, bs.P[(int64_t)g * (bs.s.m + 1) * np + t]);
+    G[t] = sum;
+  }
+  __syncthreads();
+  if (t < sb) dg[t] = G[t * sb + t].x;
+  __syncthreads();
+  // right-looking Cholesky on the upper triangle
+  for (int k = 0; k < sb; ++k) {
+    if (t == 0) {
+      const double d = G[k * sb + k].x;
+      piv[k] = (d > 1e-14 * dg[k] && d > 0.0) ? sqrt(d) : 0.0;
+    }
+    __syncthreads();
+    const double rk = piv[k];
+    if (t < sb) {  // row k of R
+      const int c = t;
+      if (c < k) G[k * sb + c] = cmk(0.0, 0.0);
+      else if (c == k) G[k * sb + k] = cmk(rk, 0.0);
+      else G[k * sb + c] = rk > 0.0 ? cscale(G[k * sb + c], 1.0 / rk) : cmk(0.0, 0.0);
+    }
+    __syncthreads();
+    if (t < np) {  // trailing update G[a][c] -= conj(R[k][a]) R[k][c], a, c > k
+      const int a = t / sb, c = t % sb;
+      if (a > k && c > k) {
+        cplx acc = G[t];
+        const cplx ra = G[k * sb + a], rc = G[k * sb + c];
+        acc = csub(acc, cmul(cconj(ra), rc));
+        G[t] = acc;
+      }
+    }
+    __syncthreads();
+  }
+  // inverse on the kept rows: thread c solves R x = e_c by back substitution
+  if (t < sb) {
+    const int c = t;
+    for (int a = sb - 1; a >= 0; --a) {
+      cplx x = cmk(0.0, 0.0);
+      if (a <= c && piv[a] > 0.0) {
+        x = a == c ? cmk(1.0, 0.0) : cmk(0.0, 0.0);
+        for (int k = a + 1; k <= c; ++k) x = csub(x, cmul(G[a * sb + k], Ii[k * sb + c]));
+        x = cscale(x, 1.0 / piv[a]);
+      }
+      Ii[a * sb + c] = x;
+    }
+  }
+  __syncthreads();
+  cplx* Ri = bs.Ri + (int64_t)kb * np;
+  cplx* Rq = bs.Rq + (int64_t)kb * np;
+  if (t < np) Ri[t] = Ii[t];
+  if (mode == 0) {
+    if (t < np) Rq[t] = G[t];
+    return;
+  }
+  // R_total = R Rq (both upper triangular): [a][c] = sum_{a <= k <= c} R[a][k] Rq[k][c]
+  if (t < np) {
+    const int a = t / sb, c = t % sb;
+    cplx acc = cmk(0.0, 0.0);
+    for (int k = a; k <= c; ++k) cmac(acc, G[a * sb + k], Rq[k * sb + c]);
+    Ii[t] = acc;  // reuse: the inverse is already stored
+  }
+  __syncthreads();
+  if (j >= 0) {
+    cplx* h = bs.Hb + (int64_t)kb * ld * (bs.s.m * sb);
+    if (t < np) {
+      const int a = t / sb, c = t % sb;
+      h[(int64_t)(j * sb + c) * ld + (j + 1) * sb + a] = Ii[t];
+    }
+  } else {
+    cplx* gk = bs.Gb + (int64_t)kb * ld * sb;
+    for (int e = t; e < ld * sb; e += 256) {
+      const int c = e / ld, row = e - c * ld;
+      gk[e] = row < sb ? Ii[row * sb + c] : cmk(0.0, 0.0);
+    }
+  }
+}
+
+// Least-squares update of step j, one workgroup of 64 sb threads per block:
+// (A) wave w applies the reflectors of the earlier columns to Hessenberg
+// column j sb + w, its window of sb + 1 rows held across the lanes and moved
+// down one row per reflector; (B) the sb new reflectors are formed and applied
+// in LDS to the new columns and to the right-hand sides; (C) each column's
+// residual estimate, the stopping test and the next apply's column set.
+__global__ __launch_bounds__(1024) void k_blsq(BState bs, int j) {
+  __shared__ cplx Hl[2 * BG_SMAX * BG_SMAX];  // rows j sb .. (j + 2) sb - 1, [row][w]
+  __shared__ cplx Gl[2 * BG_SMAX * BG_SMAX];
+  __shared__ cplx vl[BG_SMAX + 1];
+  __shared__ cplx taul;
+  __shared__ double est[BG_SMAX];
+  __shared__ int cont;
+  const GState& s = bs.s;
+  const int kb = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
+  if (!bs.bin[kb]) return;
+  const int sb = bs.sb, ld = bg_ld(bs), m = s.m;
+  const int r0 = j * sb;  // first row of the new block (and number of earlier reflectors)
+  cplx* Hk = bs.Hb + (int64_t)kb * ld * (m * sb);
+  cplx* Gk = bs.Gb + (int64_t)kb * ld * sb;
+  cplx* hvk = bs.hv + (int64_t)kb * (m * sb) * (sb + 1);
+  cplx* htk = bs.htau + (int64_t)kb * (m * sb);
+  // (A)
+  {
+    cplx* hc = Hk + (int64_t)(r0 + w) * ld;
+    cplx x = lane <= sb ? hc[lane] : cmk(0.0, 0.0);
+    for (int r = 0; r < r0; ++r) {
+      const cplx v = lane <= sb ? hvk[(int64_t)r * (sb + 1) + lane] : cmk(0.0, 0.0);
+      const cplx tau = htk[r];
+      const cplx nxt = (lane == sb) ? hc[r + 1 + sb] : cmk(0.0, 0.0);
+      double dre = 0.0, dim = 0.0;
+      {  // d = v^H x over the window
+        const cplx p = cmul(cconj(v), x);
+        dre = wave_sum(p.x);
+        dim = wave_sum(p.y);
+      }
+      const cplx f = cmul(cconj(tau), cmk(dre, dim));
+      if (lane <= sb) x = csub(x, cmul(f, v));
+      if (lane == 0) hc[r] = x;
+      const double sx = __shfl_down(x.x, 1, 64), sy = __shfl_down(x.y, 1, 64);
+      x = lane == sb ? nxt : cmk(sx, sy);
+    }
+    if (lane <= sb) Hl[lane * sb + w] = x;                       // rows r0 .. r0 + sb
+    if (lane > sb && lane < 2 * sb) Hl[lane * sb + w] = hc[r0 + lane];  // rows below, untouched
+  }
+  for (int e = t; e < 2 * sb * sb; e += 64 * sb) {
+    const int row = e / sb, c = e - row * sb;
+    Gl[e] = Gk[(int64_t)c * ld + r0 + row];
+  }
+  __syncthreads();
+  // (B)
+  for (int q = 0; q < sb; ++q) {
+    if (w == 0) {
+      const cplx xv = lane <= sb ? Hl[(q + lane) * sb + q] : cmk(0.0, 0.0);
+      const double s2 = wave_sum(lane >= 1 ? cabs2(xv) : 0.0);
+      const cplx alpha = cmk(__shfl(xv.x, 0, 64), __shfl(xv.y, 0, 64));
+      cplx tau = cmk(0.0, 0.0), scale = cmk(0.0, 0.0);
+      double beta = alpha.x;
+      if (s2 > 0.0 || alpha.y != 0.0) {
+        const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + s2);
+        beta = alpha.x >= 0.0 ? -nrm : nrm;
+        tau = cmk((beta - alpha.x) / beta, -alpha.y / beta);
+        scale = cdiv(cmk(1.0, 0.0), csub(alpha, cmk(beta, 0.0)));
+      }
+      if (lane <= sb) {
+        const cplx v = lane == 0 ? cmk(1.0, 0.0) : cmul(xv, scale);
+        vl[lane] = (tau.x == 0.0 && tau.y == 0.0 && lane > 0) ? cmk(0.0, 0.0) : v;
+        Hl[(q + lane) * sb + q] = lane == 0 ? cmk(beta, 0.0) : cmk(0.0, 0.0);
+      }
+      if (lane == 0) taul = tau;
+    }
+    __syncthreads();
+    // y <- y - conj(tau) v (v^H y) for the columns q+1.. of Hl and every column of Gl
+    const int nt = (sb - q - 1) + sb;
+    if (t < nt) {
+      cplx* base = t < sb - q - 1 ? Hl + (q + 1 + t) : Gl + (t - (sb - q - 1));
+      cplx d = cmk(0.0, 0.0);
+      for (int l = 0; l <= sb; ++l) cmacc(d, vl[l], base[(q + l) * sb]);
+      const cplx f = cmul(cconj(taul), d);
+      for (int l = 0; l <= sb; ++l) base[(q + l) * sb] = csub(base[(q + l) * sb], cmul(f, vl[l]));
+    }
+    if (t <= sb) hvk[(int64_t)(r0 + q) * (sb + 1) + t] = vl[t];
+    if (t == 0) htk[r0 + q] = taul;
+    __syncthreads();
+  }
+  // write back the new block rows and the right-hand sides
+  for (int e = t; e < 2 * sb * sb; e += 64 * sb) {
+    const int row = e / sb, c = e - row * sb;
+    Hk[(int64_t)(r0 + c) * ld + r0 + row] = Hl[e];
+    Gk[(int64_t)c * ld + r0 + row] = Gl[e];
+  }
+  // (C) residual estimates |G[(j+1) sb .. (j+2) sb - 1][c]| / ||f_c||
+  if (t < sb) {
+    double a = 0.0;
+    for (int l = sb; l < 2 * sb; ++l) a += cabs2(Gl[l * sb + t]);
+    est[t] = sqrt(a);
+  }
+  if (t == 0) cont = 0;
+  __syncthreads();
+  if (t < sb) {
+    int64_t base;
+    const int c = bg_col(bs, kb, t, &base);
+    if (c >= 0 && s.run[c]) {
+      const int it = s.iters[c] + 1;
+      s.iters[c] = it;
+      const double rel = est[t] / s.normf[c];
+      if (s.resvec && it <= s.maxit) s.resvec[(int64_t)c * (s.maxit + 1) + it] = rel;
+      if (!isfinite(rel)) s.status[c] = ST_BREAK;
+      if (isfinite(rel) && rel > s.tol && it < s.maxit) atomicOr(&cont, 1);
+    }
+  }
+  __syncthreads();
+  const bool go = cont && j + 1 < m;
+  if (t == 0) {
+    bs.bsteps[kb] = j + 1;
+    if (!go) {
+      bs.bin[kb] = 0;
+      atomicSub(s.n_inner, 1);
+    }
+  }
+  if (!go && t < sb) {
+    int64_t base;
+    const int c = bg_col(bs, kb, t, &base);
+    if (c >= 0) bs.bact[c] = 0;
+  }
+}
+
+// End of a cycle: Y = R^{-1} G for every block that ran (R the triangularised
+// Hessenberg, n = steps * sb rows; zero pivots give zero), one workgroup per
+// (block, right-hand side), G's column staged in LDS.
+__global__ __launch_bounds__(256) void k_bsolve(BState bs) {
+  __shared__ cplx gl[BG_MAXDIM];
+  __shared__ cplx yi_s;
+  const int kb = blockIdx.x, c = blockIdx.y, t = threadIdx.x;
+  if (!bs.brun[kb]) return;
+  const int sb = bs.sb, ld = bg_ld(bs);
+  const int n = bs.bsteps[kb] * sb;
+  const cplx* Hk = bs.Hb + (int64_t)kb * ld * (bs.s.m * sb);
+  const cplx* gc = bs.Gb + (int64_t)kb * ld * sb + (int64_t)c * ld;
+  cplx* yc = bs.Y + (int64_t)kb * ld * sb + (int64_t)c * ld;
+  for (int k = t; k < n; k += 256) gl[k] = gc[k];
+  __syncthreads();
+  for (int i = n - 1; i >= 0; --i) {
+    const cplx* col = Hk + (int64_t)i * ld;
+    if (t == 0) {
+      const cplx d = col[i];
+      const cplx y = (d.x == 0.0 && d.y == 0.0) ? cmk(0.0, 0.0) : cdiv(gl[i], d);
+      yi_s = y;
+      yc[i] = y;
+    }
+    __syncthreads();
+    const cplx y = yi_s;
+    for (int k = t; k < i; k += 256) gl[k] = csub(gl[k], cmul(col[k], y));
+    __syncthreads();
+  }
+}
+
+// Start of a cycle, per column: the true residual norm decides convergence
+// (as k_cycle_begin; the residual block is normalised by its QR instead).
+__global__ void k_bcycle_begin(GState s) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= s.C) return;
+  if (!s.run[c] || s.status[c] != ST_RUN) {
+    s.run[c] = 0;
+    return;
+  }
+  const double rel = sqrt(s.red[c]) / s.normf[c];
+  if (s.resvec && s.iters[c] == 0) s.resvec[(int64_t)c * (s.maxit + 1)] = rel;
+  if (!isfinite(rel)) s.status[c] = ST_BREAK;
+  else if (rel <= s.tol) s.status[c] = ST_CONV;
+  else if (s.iters[c] >= s.maxit) s.status[c] = ST_MAXIT;
+  s.run[c] = s.status[c] == ST_RUN;
+}
+
+// Start of a cycle, per block: it runs if one of its columns does.
+__global__ void k_bblock_begin(BState bs) {
+  const int kb = blockIdx.x * blockDim.x + threadIdx.x;
+  if (kb >= bs.NB) return;
+  int any = 0;
+  for (int cl = 0; cl < bs.sb; ++cl) {
+    int64_t base;
+    const int c = bg_col(bs, kb, cl, &base);
+    if (c >= 0) {
+      bs.bact[c] = bs.s.run[c];
+      any |= bs.s.run[c];
+    }
+  }
+  bs.brun[kb] = any;
+  bs.bin[kb] = any;
+  bs.bsteps[kb] = 0;
+  if (any) atomicAdd(bs.s.n_inner, 1);
+}
+
+__global__ void k_zero_i(int32_t* p, int n) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < n) p[g] = 0;
+}
+
 // ------------------------------------------------------------------ host driver
 // Rows per reduction chunk: enough chunks over all columns to fill the chip
 // (about 2048), few enough per column (<= 128 where possible) that every
@@ -875,9 +1405,40 @@ struct GLayout {
   size_t V, f, apply, ck, ckmap, ckf, ckc, rowcol, P1, H, Hraw, htent, g, cs, sn, y, normf, red,
       inv, status, inner, run, jdone, iters, ninner, total;
   int64_t n_chunks, NT;
+  // block GMRES (sb > 0)
+  int sb = 0, nbpi = 0, NB = 0;
+  int64_t n_bck = 0, n_btile = 0;
+  size_t bck, bckoff, btile, bP, bT, bH, bG, bRq, bRi, bhv, btau, bY, bin, brun, bsteps, bact;
 };
 
-GLayout glayout(mudiff_ctx* h, int R, int m) {
+// Block geometry of block GMRES: reduction chunks and 64-row tiles of every
+// block (optional host outputs).
+void block_geometry(const mudiff_ctx* h, int R, int sb, int64_t* n_bck, int64_t* n_btile,
+                    std::vector<int32_t>* bck, std::vector<int32_t>* bckoff,
+                    std::vector<int32_t>* btile) {
+  const int nbpi = (R + sb - 1) / sb;
+  int64_t nc = 0, nt = 0;
+  for (int b = 0; b < h->B; ++b) {
+    const int64_t Nb = h->imode[b + 1] - h->imode[b];
+    for (int k = 0; k < nbpi; ++k) {
+      const int kb = b * nbpi + k;
+      if (bckoff) bckoff->push_back((int32_t)nc);
+      if (btile) btile->push_back((int32_t)nt);
+      for (int64_t r = 0; r < Nb; r += BG_CHUNK, ++nc)
+        if (bck) {
+          bck->push_back(kb);
+          bck->push_back((int32_t)r);
+        }
+      nt += (Nb + BG_TILE - 1) / BG_TILE;
+    }
+  }
+  if (bckoff) bckoff->push_back((int32_t)nc);
+  if (btile) btile->push_back((int32_t)nt);
+  *n_bck = nc;
+  *n_btile = nt;
+}
+
+GLayout glayout(mudiff_ctx* h, int R, int m, int sb = 0) {
   GLayout L{};
   const int64_t C = (int64_t)h->B * R;
   const int64_t NT = (int64_t)R * h->N_all;
@@ -920,15 +1481,56 @@ GLayout glayout(mudiff_ctx* h, int R, int m) {
   L.jdone = take(C * 4);
   L.iters = take(C * 4);
   L.ninner = take(256);
+  if (sb > 0) {
+    L.sb = sb;
+    L.nbpi = (R + sb - 1) / sb;
+    L.NB = h->B * L.nbpi;
+    block_geometry(h, R, sb, &L.n_bck, &L.n_btile, nullptr, nullptr, nullptr);
+    const size_t NB = (size_t)L.NB, ld = (size_t)(m + 1) * sb, np = (size_t)sb * sb;
+    L.bck = take(L.n_bck * 8);
+    L.bckoff = take((NB + 1) * 4);
+    L.btile = take((NB + 1) * 4);
+    L.bP = take((size_t)L.n_bck * (m + 1) * np * 16);
+    L.bT = take(NB * ld * sb * 16);
+    L.bH = take(NB * ld * m * sb * 16);
+    L.bG = take(NB * ld * sb * 16);
+    L.bRq = take(NB * np * 16);
+    L.bRi = take(NB * np * 16);
+    L.bhv = take(NB * m * sb * (sb + 1) * 16);
+    L.btau = take(NB * m * sb * 16);
+    L.bY = take(NB * ld * sb * 16);
+    L.bin = take(NB * 4);
+    L.brun = take(NB * 4);
+    L.bsteps = take(NB * 4);
+    L.bact = take(C * 4);
+  }
   L.total = o;
   return L;
 }
 }  // namespace
 
+// Columns per block of a MUDIFF_BLOCK solve (0: not a block solve; -1: invalid).
+static int block_size_of(int flags, int R, int restart) {
+  if (!(flags & MUDIFF_BLOCK)) return (flags & 0xff00) ? -1 : 0;
+  int sb = (flags >> 8) & 0xff;
+  if (sb == 0) sb = 8;
+  if (sb > BG_SMAX) return -1;
+  sb = std::min(sb, R);
+  if ((int64_t)restart * sb > BG_MAXDIM) return -1;
+  return sb;
+}
+
+static bool known_gmres_flags(int flags) {
+  return (flags & ~(MUDIFF_X0 | MUDIFF_GRAPH | MUDIFF_POINT_SOURCE | MUDIFF_NO_PRECOND |
+                    MUDIFF_BLOCK | 0xff00)) == 0;
+}
+
 extern "C" size_t mudiff_gmres_workspace_size(mudiff_t h, int R, int restart, int flags) {
-  (void)flags;
   if (!h || R < 1 || restart < 1 || restart > MUDIFF_MAX_RESTART) return 0;
-  return glayout(h, R, restart).total;
+  if (!known_gmres_flags(flags)) return 0;
+  const int sb = block_size_of(flags, R, restart);
+  if (sb < 0) return 0;
+  return glayout(h, R, restart, sb).total;
 }
 
 // Column of every row of a packed multivector.
@@ -962,6 +1564,7 @@ struct GmresRun {
   std::vector<int32_t> ckmap;   // chunks of the running columns (straggler phase)
   int n_compact = 0;            // running columns when the list was built (0: all chunks)
   int64_t ch = 256;             // rows per Gram-Schmidt chunk
+  BState bs{};                  // block GMRES (L.sb > 0)
 };
 
 // Straggler phase (few running columns): the Gram-Schmidt kernels run over
@@ -1057,6 +1660,64 @@ static int enqueue_cycle(GmresRun& G, int check_every, bool host_checks) {
   return MUDIFF_OK;
 }
 
+// One restart cycle of block GMRES: QR of the residual block, up to m block
+// Arnoldi steps with the least-squares update after each, the solution update
+// and the true residual that decides each column's next cycle.
+static int enqueue_bcycle(GmresRun& G, int check_every, bool host_checks) {
+  BState& bs = G.bs;
+  const GState& s = bs.s;
+  hipStream_t st = G.st;
+  const unsigned nbk = (unsigned)G.L.n_bck, ntl = (unsigned)G.L.n_btile, NB = (unsigned)G.L.NB;
+  const int64_t NT = s.NT;
+  auto cholqr = [&](cplx* W, int j, const int32_t* gate) {
+    for (int pass = 0; pass < 2; ++pass) {
+      hipLaunchKernelGGL(k_bdots, dim3(nbk, 1), dim3(256), 0, st, bs, (const cplx*)W, NT,
+                         (const cplx*)W, gate);
+      hipLaunchKernelGGL(k_bchol, dim3(NB), dim3(256), 0, st, bs, pass, j, gate);
+      hipLaunchKernelGGL(k_bscale, dim3(ntl), dim3(256), 0, st, bs, W, gate);
+    }
+  };
+  cholqr(s.V, -1, bs.brun);
+  HIP_TRY(hipGetLastError());
+  for (int j = 0; j < s.m; ++j) {
+    cplx* W = s.V + (int64_t)(j + 1) * NT;
+    int rc = apply_operator(G.h, s.R, s.V + (int64_t)j * NT, W, s.op, G.apply_part, G.apply_cnt,
+                            bs.bact, st);
+    if (rc != MUDIFF_OK) return rc;
+    for (int pass = 0; pass < 2; ++pass) {
+      hipLaunchKernelGGL(k_bdots, dim3(nbk, (unsigned)(j + 1)), dim3(256), 0, st, bs,
+                         (const cplx*)s.V, NT, (const cplx*)W, (const int32_t*)bs.bin);
+      hipLaunchKernelGGL(k_bsum, dim3(NB, (unsigned)(j + 1)), dim3(256), 0, st, bs, j, pass);
+      hipLaunchKernelGGL(k_bupdate, dim3(ntl), dim3(256), 0, st, bs, (const cplx*)s.V, NT, W,
+                         (const cplx*)bs.T, j + 1, (const int32_t*)nullptr,
+                         (const int32_t*)bs.bin, -1.0);
+    }
+    cholqr(W, j, bs.bin);
+    hipLaunchKernelGGL(k_blsq, dim3(NB), dim3(64 * bs.sb), 0, st, bs, j);
+    HIP_TRY(hipGetLastError());
+    if (host_checks && check_every > 0 && (j + 1) % check_every == 0 && j + 1 < s.m) {
+      int32_t n_in = 0;
+      HIP_TRY(hipMemcpyAsync(&n_in, s.n_inner, 4, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      if (n_in <= 0) break;
+    }
+  }
+  hipLaunchKernelGGL(k_bsolve, dim3(NB, (unsigned)bs.sb), dim3(256), 0, st, bs);
+  hipLaunchKernelGGL(k_bupdate, dim3(ntl), dim3(256), 0, st, bs, (const cplx*)s.V, NT, s.x,
+                     (const cplx*)bs.Y, 0, (const int32_t*)bs.bsteps, (const int32_t*)bs.brun, 1.0);
+  HIP_TRY(hipGetLastError());
+  int rc = apply_operator(G.h, s.R, s.x, s.V, s.op, G.apply_part, G.apply_cnt, s.run, st);
+  if (rc != MUDIFF_OK) return rc;
+  hipLaunchKernelGGL(k_resid, dim3((unsigned)G.L.n_chunks), dim3(GS_THREADS), 0, st, s, 2, 1,
+                     (const cplx*)nullptr);
+  hipLaunchKernelGGL(k_col_sum, dim3(s.C), dim3(64), 0, st, s, 1);
+  hipLaunchKernelGGL(k_bcycle_begin, dim3((unsigned)((s.C + 63) / 64)), dim3(64), 0, st, s);
+  hipLaunchKernelGGL(k_zero_i, dim3(1), dim3(64), 0, st, s.n_inner, 1);
+  hipLaunchKernelGGL(k_bblock_begin, dim3((NB + 63) / 64), dim3(64), 0, st, bs);
+  HIP_TRY(hipGetLastError());
+  return MUDIFF_OK;
+}
+
 extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* rhs, void* rho,
                             int restart, double tol, int maxit, int flags, void* workspace,
                             size_t ws_bytes, int32_t* flag, double* relres, int32_t* iters,
@@ -1067,7 +1728,12 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
   if (restart < 1 || restart > MUDIFF_MAX_RESTART) return fail(MUDIFF_ERR_INVALID, "restart out of range");
   if (!(tol > 0.0) || !std::isfinite(tol)) return fail(MUDIFF_ERR_INVALID, "tol must be > 0");
   if (maxit < 1) return fail(MUDIFF_ERR_INVALID, "maxit < 1");
-  GLayout L = glayout(h, R, restart);
+  if (!known_gmres_flags(flags)) return fail(MUDIFF_ERR_INVALID, "unknown flags");
+  const int sb = block_size_of(flags, R, restart);
+  if (sb < 0)
+    return fail(MUDIFF_ERR_INVALID, "block size must be 1.." + std::to_string(BG_SMAX) +
+                                        " with restart * block size <= " + std::to_string(BG_MAXDIM));
+  GLayout L = glayout(h, R, restart, sb);
   if (!workspace) return fail(MUDIFF_ERR_INVALID, "workspace is NULL");
   apply_forget_upload(h);
   if (ws_bytes < L.total) return fail(MUDIFF_ERR_NOMEM, "gmres workspace needs " + std::to_string(L.total) + " bytes");
@@ -1189,7 +1855,43 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
   hipLaunchKernelGGL(k_col_sum, dim3(s.C), dim3(64), 0, st, s, 1);
   HIP_TRY(hipGetLastError());
 
-  hipLaunchKernelGGL(k_cycle_begin, dim3(cb), dim3(64), 0, st, s);
+  if (sb > 0) {  // block GMRES: block tables, then the first cycle's column and block state
+    BState& bs = G.bs;
+    bs.s = s;
+    bs.imode = h->dv.imode;
+    bs.sb = sb;
+    bs.nbpi = L.nbpi;
+    bs.NB = L.NB;
+    std::vector<int32_t> bck, bckoff, btile;
+    int64_t n_bck = 0, n_btile = 0;
+    block_geometry(h, R, sb, &n_bck, &n_btile, &bck, &bckoff, &btile);
+    bs.bck = (const int32_t*)(w + L.bck);
+    bs.bckoff = (const int32_t*)(w + L.bckoff);
+    bs.btile = (const int32_t*)(w + L.btile);
+    bs.P = (cplx*)(w + L.bP);
+    bs.T = (cplx*)(w + L.bT);
+    bs.Hb = (cplx*)(w + L.bH);
+    bs.Gb = (cplx*)(w + L.bG);
+    bs.Rq = (cplx*)(w + L.bRq);
+    bs.Ri = (cplx*)(w + L.bRi);
+    bs.hv = (cplx*)(w + L.bhv);
+    bs.htau = (cplx*)(w + L.btau);
+    bs.Y = (cplx*)(w + L.bY);
+    bs.bin = (int32_t*)(w + L.bin);
+    bs.brun = (int32_t*)(w + L.brun);
+    bs.bsteps = (int32_t*)(w + L.bsteps);
+    bs.bact = (int32_t*)(w + L.bact);
+    HIP_TRY(hipMemcpyAsync((void*)bs.bck, bck.data(), bck.size() * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync((void*)bs.bckoff, bckoff.data(), bckoff.size() * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync((void*)bs.btile, btile.data(), btile.size() * 4, hipMemcpyHostToDevice, st));
+    // the host vectors go out of scope: wait for the copies
+    HIP_TRY(hipStreamSynchronize(st));
+    hipLaunchKernelGGL(k_bcycle_begin, dim3(cb), dim3(64), 0, st, s);
+    hipLaunchKernelGGL(k_zero_i, dim3(1), dim3(64), 0, st, s.n_inner, 1);
+    hipLaunchKernelGGL(k_bblock_begin, dim3((unsigned)((L.NB + 63) / 64)), dim3(64), 0, st, bs);
+  } else {
+    hipLaunchKernelGGL(k_cycle_begin, dim3(cb), dim3(64), 0, st, s);
+  }
   HIP_TRY(hipGetLastError());
 
   const bool use_graph = (flags & MUDIFF_GRAPH) != 0;
@@ -1204,7 +1906,8 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
     int n_run = 0;
     for (int c = 0; c < s.C; ++c) n_run += hstat[c] != 0;
     if (n_run == 0) break;
-    if (!use_graph && s.C >= 32 && n_run * 32 <= s.C && (G.n_compact == 0 || n_run * 2 <= G.n_compact)) {
+    if (sb == 0 && !use_graph && s.C >= 32 && n_run * 32 <= s.C &&
+        (G.n_compact == 0 || n_run * 2 <= G.n_compact)) {
       if ((result = compact_columns(G, hstat, n_run)) != MUDIFF_OK) break;
     }
     if (use_graph) {
@@ -1220,7 +1923,7 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
         }
         GmresRun Gc = G;
         Gc.st = cap;
-        int e = enqueue_cycle(Gc, 0, false);
+        int e = sb > 0 ? enqueue_bcycle(Gc, 0, false) : enqueue_cycle(Gc, 0, false);
         hipError_t ce = hipStreamEndCapture(cap, &graph);
         (void)hipStreamDestroy(cap);
         if (e != MUDIFF_OK || ce != hipSuccess) {
@@ -1236,7 +1939,8 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
       }
       HIP_TRY(hipGraphLaunch(exec, st));
     } else {
-      if ((result = enqueue_cycle(G, 10, true)) != MUDIFF_OK) break;
+      if ((result = sb > 0 ? enqueue_bcycle(G, 10, true) : enqueue_cycle(G, 10, true)) != MUDIFF_OK)
+        break;
     }
   }
   if (exec) {

@@ -315,6 +315,9 @@ extern "C" size_t mudiff_tables_workspace_size(int B, const int64_t* disk_off,
   int64_t N_all, P_all, T_all, D_all;
   if (flags & ~MUDIFF_TABLES_CIRCULANT) return 0;
   if (!sizes_of(B, disk_off, n_modes, &N_all, &P_all, &T_all, &D_all)) return 0;
+  if (flags & MUDIFF_TABLES_CIRCULANT)
+    for (int64_t p = 0; p < disk_off[B]; ++p)
+      if (n_modes[p] > 31) return 0;  // the circulant form needs N_p <= 31
   return make_layout(B, disk_off, n_modes, N_all, P_all, T_all, D_all, flags).total;
 }
 

@@ -163,6 +163,8 @@ def test_circulant_validation(lib):
     assert st == 1 and "flag" in msg
     st, msg = _tables(lib, c, [1, 1, 1], [4, 32, 4], 2.0, flags=1)
     assert st == 1 and "31" in msg                              # beyond the MFMA tile range
+    assert _sizes(lib, [0, 3], [4, 32, 4], flags=1) == 0
+    assert _sizes(lib, [0, 3], [4, 31, 4], flags=1) > _sizes(lib, [0, 3], [4, 31, 4])
     far, near = ctypes.c_int64(-1), ctypes.c_int64(-1)
     assert lib.mudiff_circulant_info(None, ctypes.byref(far), ctypes.byref(near), None) == 1
     assert lib.mudiff_set_circulant(None, 8, 1) == 1

@@ -79,9 +79,14 @@ enum {
   MUDIFF_GRAPH = 2,     /* replay each restart cycle as one captured HIP graph          */
   MUDIFF_POINT_SOURCE = 4, /* beta holds point-source positions [B][R][2] (Prop. 5)  */
   MUDIFF_NO_PRECOND = 8, /* GMRES on L rho = -U itself (no single-scattering preconditioner) */
-  MUDIFF_BLOCK = 16      /* block GMRES: blocks of consecutive columns of an instance share one
+  MUDIFF_BLOCK = 16,     /* block GMRES: blocks of consecutive columns of an instance share one
                             block Krylov space (block size: MUDIFF_BLOCK_SIZE, default 8) */
+  MUDIFF_SSTEP = 32      /* s-step GMRES: after the first cycle, the Krylov basis grows s vectors
+                            at a time (s: MUDIFF_SSTEP_SIZE, default 8) */
 };
+/* Newton vectors per block of a MUDIFF_SSTEP solve, or'ed into the flags:
+ * 2 <= s <= 16, restart <= 64. */
+#define MUDIFF_SSTEP_SIZE(s) (((s) & 0xff) << 16)
 /* Block size s of a MUDIFF_BLOCK solve, or'ed into the flags: 1 <= s <= 16 and
  * restart * s <= 2048 (a block never exceeds the instance's R columns). */
 #define MUDIFF_BLOCK_SIZE(s) (((s) & 0xff) << 8)
@@ -167,9 +172,10 @@ int mudiff_circulant_tile(mudiff_t h, int R, int* rows, int* cols, int* kstep, i
                           int* threads);
 
 /* Fixes that tile (one of the candidates for R, as listed by
- * Problem.circulant_tiles in the Python binding: for R >= 48, 64x64 K16 with
- * stages 1 or 2, 64x32 K16 with stages 2 or 3, 64x32 K32, 128x32 K16 on 256 or
- * 512 threads; fewer for smaller R) and switches the circulant form on for R.
+ * Problem.circulant_tiles in the Python binding: for R >= 48, 64x32 K16 or K8,
+ * 128x32 K16, K8 or K4 on 512 threads, 128x32 K8 on 1024 threads, 128x64 K8
+ * or K16, 256x32 K8; other sets for smaller R) and switches the circulant form
+ * on for R.
  * MUDIFF_ERR_INVALID for other tiles or when the form is not available. */
 int mudiff_set_circulant_tile(mudiff_t h, int R, int rows, int cols, int kstep, int stages,
                               int threads);
@@ -416,8 +422,21 @@ size_t mudiff_gmres_workspace_size(mudiff_t h, int R, int restart, int flags);
  * tol leave the block.  iters counts block steps, resvec the estimates.  The
  * restart cycle is one block step sequence of up to `restart` steps (block
  * Krylov dimension restart * s).  The straggler compaction of the lockstep
- * solver is not used.  Errors: MUDIFF_ERR_INVALID for a block size out of
- * range or unknown flags. */
+ * solver is not used.
+ * With MUDIFF_SSTEP (s-step GMRES; same iterates as the one-vector process up
+ * to rounding) the first cycle runs as above and gives each column s shifts,
+ * the Ritz values of its Hessenberg matrix in Leja order; every later cycle
+ * builds its basis s vectors at a time, v_i = (op - theta_i) v_{i-1} by s
+ * operator applies back to back, then orthogonalises the s vectors at once
+ * (classical Gram-Schmidt against the basis and Cholesky QR within, both
+ * twice) and derives the s Hessenberg columns from the coefficients; each
+ * column's residual estimate and stopping test still follow every column.
+ * Fewer, larger reductions per step: for latency-bound sizes (one right-hand
+ * side).  It runs on the one-lane and generic applies only (R < 8, or some
+ * N_p > 31); not with MUDIFF_BLOCK.
+ * Errors: MUDIFF_ERR_INVALID for a block or s-step size out of range, an
+ * s-step solve on the multi-right-hand-side (FP64-MFMA) apply, or unknown
+ * flags. */
 int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* rhs, void* rho,
                  int restart, double tol, int maxit, int flags,
                  void* workspace, size_t ws_bytes,

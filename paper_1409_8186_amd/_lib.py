@@ -64,12 +64,17 @@ SIGNATURES = {
 
 STATUS = {0: "OK", 1: "INVALID", 2: "OVERLAP", 3: "NOMEM", 4: "DEVICE", 5: "NOT_CONVERGED"}
 OP_L, OP_A, OP_LT = 0, 1, 2
-X0, GRAPH, POINT_SOURCE, NO_PRECOND, BLOCK = 1, 2, 4, 8, 16
+X0, GRAPH, POINT_SOURCE, NO_PRECOND, BLOCK, SSTEP = 1, 2, 4, 8, 16, 32
 
 
 def block_size(s: int) -> int:
     """Flag bits of the block size of a MUDIFF_BLOCK solve (MUDIFF_BLOCK_SIZE)."""
     return (s & 0xFF) << 8
+
+
+def sstep_size(s: int) -> int:
+    """Flag bits of the Newton vectors per block of a MUDIFF_SSTEP solve (MUDIFF_SSTEP_SIZE)."""
+    return (s & 0xFF) << 16
 TABLES_CIRCULANT = 1
 N_PHASES = 5
 PHASES = ("scale", "forward_transform", "frequency_products", "mfma_or_lane", "output_pass")

@@ -176,13 +176,18 @@ class Problem:
         L.check(self.lib.mudiff_set_circulant(self.h, R, mode))
 
     # per-frequency product tiles (rows, cols, kstep, stages, threads) timed for R
-    CIRCULANT_TILES = {48: [(64, 64, 16, 1, 256), (64, 64, 16, 2, 256), (64, 32, 16, 2, 256),
-                            (64, 32, 32, 2, 256), (128, 32, 16, 2, 256), (64, 32, 16, 3, 256),
-                            (128, 32, 16, 2, 512), (128, 32, 16, 3, 512)],
+    CIRCULANT_TILES = {48: [(64, 32, 16, 2, 256), (64, 32, 16, 3, 256), (128, 32, 16, 2, 512),
+                            (128, 32, 16, 3, 512), (128, 32, 8, 3, 512), (128, 32, 8, 2, 512),
+                            (64, 32, 8, 3, 256), (128, 64, 8, 3, 512), (128, 64, 16, 3, 512),
+                            (128, 32, 4, 2, 512), (128, 32, 8, 2, 1024), (64, 32, 8, 2, 256),
+                            (256, 32, 8, 2, 512)],
                        24: [(64, 32, 16, 2, 256), (64, 32, 32, 2, 256), (128, 32, 16, 2, 256),
-                            (64, 32, 16, 3, 256), (128, 32, 16, 2, 512), (128, 32, 16, 3, 512)],
-                       12: [(128, 16, 16, 2, 256), (128, 8, 16, 2, 256), (128, 16, 16, 3, 256)],
-                       1: [(128, 8, 16, 2, 256), (64, 8, 16, 2, 256)]}
+                            (64, 32, 16, 3, 256), (128, 32, 16, 2, 512), (128, 32, 16, 3, 512),
+                            (128, 32, 8, 3, 512), (128, 32, 8, 2, 512), (64, 32, 8, 3, 256),
+                            (64, 32, 8, 2, 256)],
+                       12: [(128, 16, 16, 2, 256), (128, 8, 16, 2, 256), (128, 16, 16, 3, 256),
+                            (128, 16, 8, 2, 256)],
+                       1: [(128, 8, 16, 2, 256), (64, 8, 16, 2, 256), (128, 8, 8, 2, 256)]}
 
     @classmethod
     def circulant_tiles(cls, R: int) -> list:
@@ -241,15 +246,18 @@ class Problem:
     def gmres(self, betas=None, rhs=None, R: int | None = None, restart: int = 50,
               tol: float = 1e-8, maxit: int = 20000, x0=None, graph: bool = False,
               want_resvec: bool = False, workspace=None, sources=None, precond: bool = True,
-              block: int = 0):
+              block: int = 0, sstep: int = 0):
         """Solves L rho = -U for plane waves (betas [B, R]), point sources
         (sources [B, R, 2]) or a given U (rhs), with the single-scattering
         preconditioner unless precond=False; block > 0 runs block GMRES with
-        blocks of that many consecutive columns.  Returns (rho, flag, relres,
+        blocks of that many consecutive columns, sstep > 0 s-step GMRES with
+        that many Newton vectors per block.  Returns (rho, flag, relres,
         iters, resvec)."""
         flags = 0 if precond else L.NO_PRECOND
         if block:
             flags |= L.BLOCK | L.block_size(block)
+        if sstep:
+            flags |= L.SSTEP | L.sstep_size(sstep)
         bt = None
         if sources is not None:
             bt = self._sources(sources)

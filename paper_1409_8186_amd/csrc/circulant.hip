@@ -17,6 +17,14 @@
 // would spread that rounding over every mode, so they stay in the direct form.
 #include "common.h"
 
+// Instances whose length L_b is a power of 3 take radix-3 fast transforms
+// (k_circ_fwd_fft3, k_circ_finish_fft3) instead of the direct sums.
+#define CF3_R 16   // right-hand sides per workgroup
+#define CF3_L 81   // longest radix-3 length (L_b <= 125)
+__host__ __device__ __forceinline__ bool circ_pow3(int L) {
+  return L == 3 || L == 9 || L == 27 || L == 81;
+}
+
 // Twiddles w^j = e^{2 pi i j / L_b}, j < L_b, of every instance.
 __global__ void k_circ_twiddles(DevView v, cplx* tw) {
   const int b = blockIdx.y;
@@ -98,7 +106,7 @@ __global__ __launch_bounds__(256) void k_circ_fwd(DevView v, int R, const cplx* 
   __shared__ cplx tw[128];
   const int q = blockIdx.x, tid = threadIdx.x;
   const int b = v.inst[q];
-  if (!con[b]) return;
+  if (!con[b] || circ_pow3(v.cL[b])) return;  // powers of 3: k_circ_fwd_fft3
   // columns per workgroup: 32, or 16 / 8 for fewer right-hand sides (the
   // frequencies then spread over more threads)
   const int cw = R >= CF_R ? CF_R : (R > 8 ? 16 : 8);
@@ -133,6 +141,90 @@ __global__ __launch_bounds__(256) void k_circ_fwd(DevView v, int R, const cplx* 
       if (idx >= Lb) idx -= Lb;
     }
     out[(int64_t)f * Mb * R] = acc;
+  }
+}
+
+// Lengths L_b = 3^P take radix-3 fast transforms instead of the direct sums
+// (Stockham order, so no digit reversal): stage s splits each sub-transform of
+// length n = L / 3^s into three of length n / 3 with the butterfly
+//   y_{3j}   = a + b + c,
+//   y_{3j+1} = (a + b zeta + c conj(zeta)) w^j,
+//   y_{3j+2} = (a + b conj(zeta) + c zeta) w^{2j},
+// a, b, c the entries j, j + n/3, j + 2n/3 of the sub-transform, w = e^{-+2 pi i / n}
+// and zeta = e^{-+2 pi i / 3} (sign - forward, + inverse), all read from the
+// instance's twiddle table.  The columns of a workgroup run side by side in LDS.
+
+// In-place (ping-pong) transform of the L x CF3_R block x[k][c] in LDS; returns
+// the buffer holding the result in natural order.
+__device__ cplx* fft3_lds(cplx* x, cplx* y, const cplx* tw, int L, bool inverse) {
+  const int tid = threadIdx.x;
+  const cplx zt = tw[L / 3];
+  const double sgn = inverse ? zt.y : -zt.y;  // Im(zeta)
+  int stride = 1;
+  for (int n = L; n > 1; n /= 3) {
+    const int m = n / 3;
+    for (int e = tid; e < m * stride * CF3_R; e += blockDim.x) {
+      const int c = e % CF3_R, t = e / CF3_R;
+      const int k = t % stride, j = t / stride;
+      const cplx a = x[((j)*stride + k) * CF3_R + c];
+      const cplx bb = x[((j + m) * stride + k) * CF3_R + c];
+      const cplx cc = x[((j + 2 * m) * stride + k) * CF3_R + c];
+      const cplx sm = cadd(bb, cc), df = csub(bb, cc);
+      const cplx tt = csub(a, cscale(sm, 0.5));
+      const cplx id = cmk(-sgn * df.y, sgn * df.x);  // i Im(zeta) (b - c)
+      cplx w1 = tw[j * stride], w2 = tw[2 * j * stride];
+      if (!inverse) {
+        w1 = cconj(w1);
+        w2 = cconj(w2);
+      }
+      y[((3 * j) * stride + k) * CF3_R + c] = cadd(a, sm);
+      y[((3 * j + 1) * stride + k) * CF3_R + c] = cmul(cadd(tt, id), w1);
+      y[((3 * j + 2) * stride + k) * CF3_R + c] = cmul(csub(tt, id), w2);
+    }
+    __syncthreads();
+    cplx* sw = x;
+    x = y;
+    y = sw;
+    stride *= 3;
+  }
+  return x;
+}
+
+// Forward transforms of the scaled input panels of one column disk q and 16
+// right-hand sides, for instances with L_b a power of 3.
+__global__ __launch_bounds__(256) void k_circ_fwd_fft3(DevView v, int R, const cplx* __restrict__ z,
+                                                       cplx* __restrict__ zh,
+                                                       const int32_t* __restrict__ con,
+                                                       const int32_t* __restrict__ active) {
+  __shared__ cplx buf[2 * CF3_L * CF3_R];
+  __shared__ cplx tw[CF3_L];
+  const int q = blockIdx.x, tid = threadIdx.x;
+  const int b = v.inst[q];
+  if (!con[b]) return;
+  const int Lb = v.cL[b];
+  if (!circ_pow3(Lb)) return;
+  const int r0 = blockIdx.y * CF3_R;
+  if (r0 >= R) return;
+  if (active) {
+    bool any = false;
+    for (int r = r0; r < min(R, r0 + CF3_R); ++r) any |= active[b * R + r] != 0;
+    if (!any) return;
+  }
+  const int nq = 2 * v.N[q] + 1;
+  const int64_t d0 = v.idisk[b], Mb = v.idisk[b + 1] - d0;
+  for (int e = tid; e < Lb * CF3_R; e += 256) {  // along the modes of a column: coalesced
+    const int c = e / Lb, k = e - (e / Lb) * Lb;
+    cplx val = cmk(0.0, 0.0);
+    if (k < nq && r0 + c < R) val = z[col_base(v.imode, b, R, r0 + c) + v.moff[q] + k];
+    buf[k * CF3_R + c] = val;
+  }
+  for (int e = tid; e < Lb; e += 256) tw[e] = v.ctw[v.cWo[b] + e];
+  __syncthreads();
+  const cplx* res = fft3_lds(buf, buf + CF3_L * CF3_R, tw, Lb, false);
+  cplx* out = zh + (int64_t)R * v.cZo[b] + (q - d0) * R + r0;
+  for (int e = tid; e < Lb * CF3_R; e += 256) {
+    const int f = e / CF3_R, c = e - (e / CF3_R) * CF3_R;
+    if (r0 + c < R) out[(int64_t)f * Mb * R + c] = res[e];
   }
 }
 
@@ -379,6 +471,7 @@ __global__ __launch_bounds__(256) void k_circ_finish_mfma(
   const int np = 2 * v.N[p] + 1;
   const int64_t d0 = v.idisk[b], Mb = v.idisk[b + 1] - d0;
   const bool circ = con[b] != 0;
+  if (circ && circ_pow3(v.cL[b])) return;  // k_circ_finish_fft3
   const int ldw = np + 1;
   if (circ) {
     const int Lb = v.cL[b];
@@ -427,6 +520,56 @@ __global__ __launch_bounds__(256) void k_circ_finish_mfma(
   }
 }
 
+// Output pass for instances in the form with L_b a power of 3: inverse radix-3
+// transform of the rows f of W^p for 16 right-hand sides (only the n_p modes
+// are kept), then, as in k_circ_finish_mfma, the close pairs' partial sums and
+// the epilogue, coalesced over the modes.
+__global__ __launch_bounds__(256) void k_circ_finish_fft3(
+    DevView v, int R, const cplx* __restrict__ x, cplx* __restrict__ y, int op,
+    const cplx* __restrict__ part, int64_t blk, int npad, int RC, const int32_t* __restrict__ dgrp,
+    const int32_t* __restrict__ drow, const int32_t* __restrict__ gnseg,
+    const int64_t* __restrict__ gbase, const int32_t* __restrict__ active,
+    const cplx* __restrict__ wh, const int32_t* __restrict__ con) {
+  __shared__ cplx buf[2 * CF3_L * CF3_R];
+  __shared__ cplx tw[CF3_L];
+  const int p = blockIdx.x, tid = threadIdx.x;
+  const int b = v.inst[p];
+  if (!con[b]) return;
+  const int Lb = v.cL[b];
+  if (!circ_pow3(Lb)) return;
+  const int r0 = blockIdx.y * CF3_R;
+  if (r0 >= R) return;
+  if (active) {
+    bool any = false;
+    for (int r = r0; r < min(R, r0 + CF3_R); ++r) any |= active[b * R + r] != 0;
+    if (!any) return;
+  }
+  const int np = 2 * v.N[p] + 1;
+  const int64_t d0 = v.idisk[b], Mb = v.idisk[b + 1] - d0;
+  const cplx* src = wh + (int64_t)R * v.cZo[b] + (p - d0) * R + r0;
+  for (int e = tid; e < Lb * CF3_R; e += 256) {
+    const int f = e / CF3_R, c = e - (e / CF3_R) * CF3_R;
+    buf[e] = r0 + c < R ? src[(int64_t)f * Mb * R + c] : cmk(0.0, 0.0);
+  }
+  for (int e = tid; e < Lb; e += 256) tw[e] = v.ctw[v.cWo[b] + e];
+  __syncthreads();
+  const cplx* res = fft3_lds(buf, buf + CF3_L * CF3_R, tw, Lb, true);
+  const int gr = dgrp[p];
+  const int ns = gnseg[gr];
+  const int64_t ip = v.imode[b] + v.moff[p];
+  for (int e = tid; e < CF3_R * np; e += 256) {
+    const int rr = e / np, m = e - (e / np) * np;
+    const int r = r0 + rr;
+    if (r >= R || (active && active[b * R + r] == 0)) continue;
+    const int t = r / RC, rc = r - (r / RC) * RC;
+    const cplx* pr = part + (gbase[gr] + (int64_t)t * ns) * blk + ((int64_t)drow[p] * npad + m) * RC + rc;
+    cplx w = res[m * CF3_R + rr];
+    for (int sg = 0; sg < ns; ++sg) w = cadd(w, pr[(int64_t)sg * blk]);
+    const int64_t g = col_base(v.imode, b, R, r) + v.moff[p] + m;
+    y[g] = finalize(v, op, ip + m, x[g], w);
+  }
+}
+
 // Product variants: tile (rows, complex columns), K step, LDS buffers
 // (3: two buffers and two register sets), workgroup size.
 struct CircVariant {
@@ -446,16 +589,27 @@ static const CircVariant kCircVar[] = {
     {128, 32, 16, 2, 512, k_circ_gemm<4, 2, 2, 2, 16, true, false>},
     {128, 32, 16, 3, 512, k_circ_gemm<4, 2, 2, 2, 16, true, true>},
     {128, 16, 16, 3, 256, k_circ_gemm<4, 1, 2, 2, 16, true, true>},
+    {128, 32, 8, 3, 512, k_circ_gemm<4, 2, 2, 2, 8, true, true>},
+    {128, 32, 8, 2, 512, k_circ_gemm<4, 2, 2, 2, 8, true, false>},
+    {64, 32, 8, 3, 256, k_circ_gemm<2, 2, 2, 2, 8, true, true>},
+    {128, 64, 8, 3, 512, k_circ_gemm<4, 2, 2, 4, 8, true, true>},
+    {128, 64, 16, 3, 512, k_circ_gemm<4, 2, 2, 4, 16, true, true>},
+    {128, 32, 4, 2, 512, k_circ_gemm<4, 2, 2, 2, 4, true, false>},
+    {128, 32, 8, 2, 1024, k_circ_gemm<8, 2, 1, 2, 8, true, false>},
+    {64, 32, 8, 2, 256, k_circ_gemm<2, 2, 2, 2, 8, true, false>},
+    {128, 16, 8, 2, 256, k_circ_gemm<4, 1, 2, 2, 8, true, false>},
+    {128, 8, 8, 2, 256, k_circ_gemm<4, 1, 2, 1, 8, true, false>},
+    {256, 32, 8, 2, 512, k_circ_gemm<4, 2, 4, 2, 8, true, false>},
 };
 #define N_CIRC_VAR ((int)(sizeof(kCircVar) / sizeof(kCircVar[0])))
 
 // Default product variant for R columns, and the variants worth timing.
 int circ_variant(int R) { return R >= 48 ? 2 : (R >= 24 ? 2 : (R >= 12 ? 5 : 6)); }
 std::vector<int> circ_variants(int R) {
-  if (R >= 48) return {0, 1, 2, 3, 4, 8, 9, 10};
-  if (R >= 24) return {2, 3, 4, 8, 9, 10};
-  if (R >= 12) return {5, 6, 11};
-  return {6, 7};
+  if (R >= 48) return {2, 8, 9, 10, 12, 13, 14, 15, 16, 17, 18, 19, 22};
+  if (R >= 24) return {2, 3, 4, 8, 9, 10, 12, 13, 14, 19};
+  if (R >= 12) return {5, 6, 11, 20};
+  return {6, 7, 21};
 }
 void circ_tile(int var, int* bm, int* bn) {
   *bm = kCircVar[var].bm;
@@ -471,11 +625,26 @@ void circ_var_dims(int var, int* bm, int* bn, int* bk, int* db, int* nt) {
 
 // Enqueue the transforms of the inputs and the per-frequency products.
 // z: inputs scaled by their column factors [B][R][N_b]; zh, wh: [sum_b L_b M_b][R].
+// Which transform kernels a launch needs: instances in the form with L_b a
+// power of 3 (fast transforms) and with other lengths (direct sums).
+static void circ_kinds(const mudiff_ctx* h, const int32_t* con_h, bool* fft, bool* dft) {
+  *fft = *dft = false;
+  for (int b = 0; b < h->B; ++b)
+    if (con_h[b]) (circ_pow3(h->cL[b]) ? *fft : *dft) = true;
+}
+
 int circ_launch(mudiff_ctx* h, int R, const cplx* z, cplx* zh, cplx* wh, const int32_t* citems,
-                int n_citems, int var, const int32_t* con, const int32_t* active, hipStream_t s) {
+                int n_citems, int var, const int32_t* con, const int32_t* con_h,
+                const int32_t* active, hipStream_t s) {
+  bool fft, dft;
+  circ_kinds(h, con_h, &fft, &dft);
   const int cw = R >= CF_R ? CF_R : (R > 8 ? 16 : 8);
-  hipLaunchKernelGGL(k_circ_fwd, dim3((unsigned)h->M_all, (unsigned)((R + cw - 1) / cw)), dim3(256), 0,
-                     s, h->dv, R, z, zh, con, active);
+  if (dft)
+    hipLaunchKernelGGL(k_circ_fwd, dim3((unsigned)h->M_all, (unsigned)((R + cw - 1) / cw)), dim3(256), 0,
+                       s, h->dv, R, z, zh, con, active);
+  if (fft)
+    hipLaunchKernelGGL(k_circ_fwd_fft3, dim3((unsigned)h->M_all, (unsigned)((R + CF3_R - 1) / CF3_R)),
+                       dim3(256), 0, s, h->dv, R, z, zh, con, active);
   HIP_TRY(hipGetLastError());
   prof_mark(h, s, 2);
   if (n_citems > 0) {
@@ -490,7 +659,18 @@ int circ_launch(mudiff_ctx* h, int R, const cplx* z, cplx* zh, cplx* wh, const i
 int circ_finish(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, const cplx* part, int64_t blk,
                 int npad, int RC, const int32_t* dgrp, const int32_t* drow, const int32_t* gnseg,
                 const int64_t* gbase, const int32_t* active, const cplx* wh, const int32_t* con,
-                hipStream_t s) {
+                const int32_t* con_h, hipStream_t s) {
+  bool fft, dft;
+  circ_kinds(h, con_h, &fft, &dft);
+  if (fft) {
+    hipLaunchKernelGGL(k_circ_finish_fft3, dim3((unsigned)h->M_all, (unsigned)((R + CF3_R - 1) / CF3_R)),
+                       dim3(256), 0, s, h->dv, R, x, y, op, part, blk, npad, RC, dgrp, drow, gnseg,
+                       gbase, active, wh, con);
+    HIP_TRY(hipGetLastError());
+  }
+  bool direct = dft;  // instances outside the form: partial sums only, in the MFMA finish
+  for (int b = 0; b < h->B && !direct; ++b) direct = con_h[b] == 0;
+  if (!direct) return MUDIFF_OK;
   int Lmax = 0;
   for (int32_t l : h->cL) Lmax = std::max(Lmax, (int)l);
   const int tm = (2 * h->Nmax + 1 + 15) / 16;  // row tiles: n_p <= 63 (N_p <= 31), L_b <= 125

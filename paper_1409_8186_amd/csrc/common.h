@@ -358,9 +358,12 @@ __device__ __forceinline__ void lane_reduce_scatter(double* val, int lane) {
 // ------------------------------------------------------------------ internal API
 // Operator apply on R columns. `part`/`counters` come from the caller's scratch
 // (mudiff_matvec_workspace_size); counters must be zero on entry and are left
-// zero. `active` (optional, [B*R]) skips columns whose entry is 0.
+// zero. `active` (optional, [B*R]) skips columns whose entry is 0.  `shift`
+// (optional, [B*R], one-lane and generic kernels only) subtracts shift[c] x
+// from column c of the result.
 int apply_operator(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, cplx* part,
-                   int32_t* counters, const int32_t* active, hipStream_t s);
+                   int32_t* counters, const int32_t* active, hipStream_t s,
+                   const cplx* shift = nullptr);
 // Same, except that on the one-lane-per-pair path only the chunk partial sums
 // are written (*pending = true): the caller adds them (lane_chunk_sum) and
 // applies finalize itself.
@@ -368,6 +371,8 @@ int apply_operator_split(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, c
                          int32_t* counters, const int32_t* active, hipStream_t s,
                          bool* pending);
 size_t apply_scratch_bytes(mudiff_ctx* h, int R);
+// True when the R-column apply runs on the FP64-MFMA work queue (R >= 8, N_p <= 31).
+bool apply_uses_mfma(const mudiff_ctx* h, int R);
 // Forget where the MFMA schedule was last uploaded: the next apply uploads it
 // into its scratch again.  Every entry point that takes an apply scratch from
 // the caller calls this first, so a buffer whose memory was used for anything

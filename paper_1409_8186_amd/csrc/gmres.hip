@@ -26,6 +26,7 @@
 #include <algorithm>
 
 #include "common.h"
+#include "ritz.h"
 
 #define GS_THREADS 256
 #define GS_WAVES (GS_THREADS / 64)
@@ -67,6 +68,14 @@ struct GState {
   int32_t* iters;           // [C] inner iterations so far
   int32_t* n_inner;         // [1] columns still active in the cycle
   double* resvec;           // [C][maxit+1] or NULL
+  // s-step GMRES (ss > 0)
+  int ss;                   // Newton vectors per block
+  int sl2;                  // partial-sum slots per chunk, (m + 1) ss
+  cplx* P2;                 // [n_chunks][(m + 1) ss]
+  cplx* theta;              // [ss][C] shifts
+  cplx* sC;                 // [C][2][(m + 1) ss] projections of the two passes
+  cplx* sR;                 // [C][2][ss ss] Cholesky factors of the two passes
+  cplx* sRi;                // [C][ss ss] inverse of the current pass's factor
 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -104,8 +113,10 @@ __device__ __forceinline__ ArnoldiPre arnoldi_preload(const GState& s, int c, in
   return ArnoldiPre{s.g[(int64_t)c * (s.m + 1) + j], s.iters[c], s.normf[c]};
 }
 
-__device__ void arnoldi_step(const GState& s, int c, int j, const cplx* hl, const double* csl,
-                             const cplx* snl, double hn, const ArnoldiPre& pre) {
+__device__ bool arnoldi_step(const GState& s, int c, int j, const cplx* hl, const double* csl,
+                             const cplx* snl, double hn, const ArnoldiPre& pre,
+                             ArnoldiPre* next = nullptr, double* cs_out = nullptr,
+                             cplx* sn_out = nullptr) {
   const int m1 = s.m + 1;
   cplx* hj = s.H + (int64_t)c * m1 * s.m + (int64_t)j * m1;  // column j
   cplx cur = hl[0];
@@ -134,6 +145,8 @@ __device__ void arnoldi_step(const GState& s, int c, int j, const cplx* hl, cons
   }
   s.cs[(int64_t)c * s.m + j] = cr;
   s.sn[(int64_t)c * s.m + j] = sr;
+  if (cs_out) *cs_out = cr;
+  if (sn_out) *sn_out = sr;
   hj[j] = cadd(cscale(aa, cr), cscale(sr, hn));
   cplx* gc = s.g + (int64_t)c * m1;
   const cplx gj = pre.gj;
@@ -147,10 +160,13 @@ __device__ void arnoldi_step(const GState& s, int c, int j, const cplx* hl, cons
   s.jdone[c] = j + 1;
   const bool finite = isfinite(rel) && isfinite(hn);
   if (!finite) s.status[c] = ST_BREAK;
+  if (next) *next = ArnoldiPre{gj1, it, pre.nf};
   if (!finite || rel <= s.tol || hn == 0.0 || it >= s.maxit || j + 1 >= s.m) {
     s.inner[c] = 0;
     atomicSub(s.n_inner, 1);
+    return true;
   }
+  return false;
 }
 
 // ------------------------------------------------------------------ delayed CGS2
@@ -1382,6 +1398,421 @@ __global__ void k_zero_i(int32_t* p, int n) {
   if (g < n) p[g] = 0;
 }
 
+// ------------------------------------------------------------------ s-step GMRES
+// With MUDIFF_SSTEP each restart cycle after the first builds its Krylov basis
+// ss vectors at a time (s-step, or communication-avoiding, GMRES): from the
+// last orthonormal basis vector q_j the operator is applied ss times back to
+// back in the Newton form v_i = (A - theta_i) v_{i-1}, with the shifts theta_i
+// the Ritz values of the first cycle's Hessenberg matrix in Leja order (so the
+// basis stays well conditioned), and the block [v_1 .. v_ss] is then
+// orthogonalised at once: against q_0..q_j by classical Gram-Schmidt and within
+// itself by Cholesky QR, both applied twice (each pass one reduction over the
+// rows and one sweep; the Gram matrix of the projected block follows from the
+// unprojected one minus C^H C).  With V = [Q, Q_new] R_hat (R_hat the
+// coefficients of the v_i) and A [v_0..v_{ss-1}] = [v_0..v_ss] B (theta_i on
+// the diagonal of B, ones below), the ss new Hessenberg columns are
+//   H_new = (R_hat B - [H_old R_top; 0]) R_s^{-1},
+// R_top the rows of R_hat on q_0..q_{j-1} and R_s the square block on
+// q_j..q_{j+ss-1}; they then enter the Givens update one by one, with the
+// residual estimate and stopping test of every column as in the one-vector
+// process.  Per ss steps: ss applies, four reduction/sweep launches and one
+// small per-column kernel, against 2 ss launches for delayed CGS2.
+#define SS_MAX 16
+#define SS_MREST 64    // longest restart of an s-step solve (LDS of the per-column kernels)
+#define SS_SUM_THREADS 1024
+#define SS_CL ((SS_MREST + 1) * SS_MAX)
+
+// P2[chunk][l ss + k] = sum over the chunk's rows of conj(V_l) V_{j0+1+k},
+// l < j0 + 1 + sb, k < sb: the projections on the basis and the block's Gram
+// matrix.  One wave per left vector l, lanes along the rows, the sb sums
+// reduce-scattered over the lanes.
+__global__ __launch_bounds__(GS_THREADS) void k_ss_dots(GState s, int j0, int sb) {
+  int c, len;
+  int64_t o;
+  const int gi = decode_chunk(s, &c, &len, &o);
+  if (!s.inner[c]) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nl = j0 + 1 + sb;
+  const cplx* wb = s.V + (int64_t)(j0 + 1) * s.NT + o;
+  for (int l = blockIdx.y * GS_WAVES + wv; l < nl; l += gridDim.y * GS_WAVES) {
+    cplx acc[SS_MAX];
+#pragma unroll
+    for (int k = 0; k < SS_MAX; ++k) acc[k] = cmk(0.0, 0.0);
+    const cplx* vl = s.V + (int64_t)l * s.NT + o;
+    for (int r = lane; r < len; r += 64) {
+      const cplx a = vl[r];
+#pragma unroll
+      for (int k = 0; k < SS_MAX; ++k)
+        if (k < sb) cmacc(acc[k], a, wb[(int64_t)k * s.NT + r]);
+    }
+    double val[2 * SS_MAX];
+#pragma unroll
+    for (int k = 0; k < SS_MAX; ++k) {
+      val[2 * k] = acc[k].x;
+      val[2 * k + 1] = acc[k].y;
+    }
+    lane_reduce_scatter<2 * SS_MAX>(val, lane);
+    const int vi = lane >> 1;
+    if ((lane & 1) == 0 && vi < 2 * sb) {
+      double* dst = reinterpret_cast<double*>(s.P2 + (int64_t)gi * s.sl2 + l * s.ss + (vi >> 1));
+      dst[vi & 1] = val[0];
+    }
+  }
+}
+
+// Per column: the chunk partials added in chunk order give C = Q^H W
+// ((j0 + 1) x sb) and G = W^H W; R = chol(G - C^H C) (a pivot below 1e-14 of
+// its diagonal entry, or not positive, drops that row), its inverse on the
+// kept rows, all stored for the sweep (pass 0 or 1).
+__global__ __launch_bounds__(SS_SUM_THREADS) void k_ss_sum(GState s, int j0, int sb, int pass) {
+  __shared__ cplx Cl[SS_CL];
+  __shared__ cplx G[SS_MAX * SS_MAX];
+  __shared__ cplx Ii[SS_MAX * SS_MAX];
+  __shared__ double dg[SS_MAX], piv[SS_MAX];
+  const int c = blockIdx.x, t = threadIdx.x;
+  if (!s.inner[c]) return;
+  const int nl = j0 + 1 + sb, ss = s.ss;
+  const int k0 = s.ckf[c], nck = s.ckc[c];
+  cplx* Cg = s.sC + ((int64_t)c * 2 + pass) * s.sl2;
+  for (int e = t; e < nl * sb; e += SS_SUM_THREADS) {
+    const int l = e / sb, k = e - (e / sb) * sb;
+    const cplx* src = s.P2 + (int64_t)k0 * s.sl2 + l * ss + k;
+    cplx a = cmk(0.0, 0.0);
+    int q = 0;
+    for (; q < nck; q += 16) {  // sixteen loads in flight, added in chunk order
+      cplx v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v[u] = q + u < nck ? src[(int64_t)(q + u) * s.sl2] : cmk(0.0, 0.0);
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (q + u < nck) a = cadd(a, v[u]);
+    }
+    if (l <= j0) {
+      Cl[e] = a;
+      Cg[l * ss + k] = a;
+    } else {
+      G[(l - j0 - 1) * SS_MAX + k] = a;
+    }
+  }
+  __syncthreads();
+  // G - C^H C
+  for (int e = t; e < sb * sb; e += SS_SUM_THREADS) {
+    const int a = e / sb, k = e - (e / sb) * sb;
+    cplx g = G[a * SS_MAX + k];
+    for (int l = 0; l <= j0; ++l) g = csub(g, cmul(cconj(Cl[l * sb + a]), Cl[l * sb + k]));
+    Ii[a * SS_MAX + k] = g;
+  }
+  __syncthreads();
+  for (int e = t; e < sb * sb; e += SS_SUM_THREADS) G[(e / sb) * SS_MAX + e % sb] = Ii[(e / sb) * SS_MAX + e % sb];
+  if (t < sb) dg[t] = G[t * SS_MAX + t].x;
+  __syncthreads();
+  for (int k = 0; k < sb; ++k) {
+    if (t == 0) {
+      const double d = G[k * SS_MAX + k].x;
+      piv[k] = (d > 1e-14 * dg[k] && d > 0.0) ? sqrt(d) : 0.0;
+    }
+    __syncthreads();
+    const double rk = piv[k];
+    if (t < sb) {
+      if (t < k) G[k * SS_MAX + t] = cmk(0.0, 0.0);
+      else if (t == k) G[k * SS_MAX + k] = cmk(rk, 0.0);
+      else G[k * SS_MAX + t] = rk > 0.0 ? cscale(G[k * SS_MAX + t], 1.0 / rk) : cmk(0.0, 0.0);
+    }
+    __syncthreads();
+    if (t < sb * sb) {
+      const int a = t / sb, cc = t % sb;
+      if (a > k && cc > k) G[a * SS_MAX + cc] = csub(G[a * SS_MAX + cc], cmul(cconj(G[k * SS_MAX + a]), G[k * SS_MAX + cc]));
+    }
+    __syncthreads();
+  }
+  if (t < sb) {  // column t of R^{-1} on the kept rows
+    for (int a = sb - 1; a >= 0; --a) {
+      cplx x = cmk(0.0, 0.0);
+      if (a <= t && piv[a] > 0.0) {
+        x = a == t ? cmk(1.0, 0.0) : cmk(0.0, 0.0);
+        for (int k = a + 1; k <= t; ++k) x = csub(x, cmul(G[a * SS_MAX + k], Ii[k * SS_MAX + t]));
+        x = cscale(x, 1.0 / piv[a]);
+      }
+      Ii[a * SS_MAX + t] = x;
+    }
+  }
+  __syncthreads();
+  cplx* Rg = s.sR + ((int64_t)c * 2 + pass) * ss * ss;
+  cplx* Rig = s.sRi + (int64_t)c * ss * ss;
+  for (int e = t; e < sb * sb; e += SS_SUM_THREADS) {
+    const int a = e / sb, k = e - (e / sb) * sb;
+    Rg[a * ss + k] = G[a * SS_MAX + k];
+    Rig[a * ss + k] = Ii[a * SS_MAX + k];
+  }
+}
+
+// Rows of the block: W_k <- (W_k - sum_{l <= j0} V_l C[l][k]) R^{-1} with the
+// current pass's C and R^{-1} staged in LDS.  64 rows per workgroup, four
+// threads per row splitting the basis vectors (l = g, g + 4, ...; eight loads
+// in flight), their sums added in LDS in a fixed order.
+#define SS_UR 64
+__global__ __launch_bounds__(GS_THREADS) void k_ss_update(GState s, int j0, int sb, int pass) {
+  __shared__ cplx Cl[SS_CL];
+  __shared__ cplx Ri[SS_MAX * SS_MAX];
+  __shared__ cplx part[3 * SS_UR * SS_MAX];
+  int c, len;
+  int64_t o;
+  decode_chunk(s, &c, &len, &o);
+  if (!s.inner[c]) return;
+  const int t = threadIdx.x, ss = s.ss;
+  const cplx* Cg = s.sC + ((int64_t)c * 2 + pass) * s.sl2;
+  for (int e = t; e < (j0 + 1) * sb; e += GS_THREADS) Cl[e] = Cg[(e / sb) * ss + e % sb];
+  for (int e = t; e < sb * sb; e += GS_THREADS) Ri[e] = s.sRi[(int64_t)c * ss * ss + (e / sb) * ss + e % sb];
+  __syncthreads();
+  const int rl = t & (SS_UR - 1), g = t / SS_UR;
+  const int r = blockIdx.y * SS_UR + rl;
+  const bool in = r < len;
+  cplx acc[SS_MAX];
+#pragma unroll
+  for (int k = 0; k < SS_MAX; ++k) acc[k] = cmk(0.0, 0.0);
+  if (in) {
+    const cplx* vr = s.V + o + r;
+    for (int l0 = g; l0 <= j0; l0 += 32) {
+      cplx v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int l = l0 + 4 * u;
+        v[u] = l <= j0 ? vr[(int64_t)l * s.NT] : cmk(0.0, 0.0);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int l = l0 + 4 * u;
+        if (l > j0) break;
+#pragma unroll
+        for (int k = 0; k < SS_MAX; ++k)
+          if (k < sb) cmac(acc[k], v[u], Cl[l * sb + k]);
+      }
+    }
+  }
+  if (g > 0) {
+#pragma unroll
+    for (int k = 0; k < SS_MAX; ++k)
+      if (k < sb) part[((g - 1) * SS_UR + rl) * SS_MAX + k] = acc[k];
+  }
+  __syncthreads();
+  if (g != 0 || !in) return;
+  cplx w[SS_MAX];
+  cplx* wb = s.V + (int64_t)(j0 + 1) * s.NT + o + r;
+#pragma unroll
+  for (int k = 0; k < SS_MAX; ++k) w[k] = k < sb ? wb[(int64_t)k * s.NT] : cmk(0.0, 0.0);
+#pragma unroll
+  for (int k = 0; k < SS_MAX; ++k) {
+    cplx a = acc[k];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) a = cadd(a, part[(q * SS_UR + rl) * SS_MAX + k]);
+    w[k] = csub(w[k], a);
+  }
+#pragma unroll
+  for (int k = 0; k < SS_MAX; ++k) {
+    cplx a = cmk(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q <= k; ++q)
+      if (k < sb) cmac(a, w[q], Ri[q * sb + k]);
+    if (k < sb) wb[(int64_t)k * s.NT] = a;
+  }
+}
+
+// Per column, after the second pass: the coefficients of the Newton vectors
+// (C = C1 + C2 R1, R = R2 R1), the new Hessenberg columns (all sb, or up to the
+// first dropped pivot of R and one more), written raw, then each through the
+// Givens update (arnoldi_step) until the column stops.
+#define SS_HT 256
+__global__ __launch_bounds__(SS_HT) void k_ss_hess(GState s, int j0, int sb) {
+  __shared__ cplx Cm[SS_CL];                                // C  [l][k], l <= j0
+  __shared__ cplx Rm[SS_MAX * SS_MAX];                      // R  [a][k]
+  __shared__ cplx X[(SS_MREST + SS_MAX + 1) * SS_MAX];      // new columns [row][k]
+  __shared__ cplx Ho[(SS_MREST + 1) * SS_MREST];            // earlier raw columns [q][row], rows <= j0
+  __shared__ cplx hl[SS_MREST + 1];
+  __shared__ double csl[SS_MREST];
+  __shared__ cplx snl[SS_MREST];
+  __shared__ int nuse;
+  const int c = blockIdx.x, t = threadIdx.x;
+  if (!s.inner[c]) return;
+  const int ss = s.ss, m1 = s.m + 1;
+  const cplx* C1 = s.sC + (int64_t)c * 2 * s.sl2;
+  const cplx* C2 = C1 + s.sl2;
+  const cplx* R1 = s.sR + (int64_t)c * 2 * ss * ss;
+  const cplx* R2 = R1 + ss * ss;
+  // stage C2 in X and R1, R2 in Rm / hl (scratch until used below)
+  for (int e = t; e < (j0 + 1) * sb; e += SS_HT) X[e] = C2[(e / sb) * ss + e % sb];
+  for (int e = t; e < sb * sb; e += SS_HT) {
+    Rm[e] = R1[(e / sb) * ss + e % sb];
+    Ho[e] = R2[(e / sb) * ss + e % sb];
+  }
+  __syncthreads();
+  for (int e = t; e < (j0 + 1) * sb; e += SS_HT) {  // C = C1 + C2 R1
+    const int l = e / sb, k = e - (e / sb) * sb;
+    cplx a = C1[l * ss + k];
+    for (int q = 0; q <= k; ++q) cmac(a, X[l * sb + q], Rm[q * sb + k]);
+    Cm[e] = a;
+  }
+  cplx rr = cmk(0.0, 0.0);
+  if (t < sb * sb) {  // R = R2 R1
+    const int a = t / sb, k = t % sb;
+    for (int q = a; q <= k; ++q) cmac(rr, Ho[a * sb + q], Rm[q * sb + k]);
+  }
+  __syncthreads();
+  if (t < sb * sb) Rm[t] = rr;
+  __syncthreads();
+  if (t == 0) {
+    int u = 0;
+    while (u < sb && (Rm[u * sb + u].x != 0.0 || Rm[u * sb + u].y != 0.0)) ++u;
+    nuse = u;
+  }
+  __syncthreads();
+  // columns: the su Newton vectors with kept pivots give su columns; past a
+  // dropped one (v_{su+1} in the span of the basis) one more column follows
+  // exactly, with a zero subdiagonal (the Krylov space is invariant there)
+  const int su = nuse < sb ? nuse + 1 : sb;
+  const int nrow = j0 + su + 1;
+  // R_hat column i (i = 0..sb) at row r: e_{j0} for i = 0; C[r][i-1] for r <= j0;
+  // R[r-j0-1][i-1] for j0 < r
+  auto rhat = [&](int r, int i) -> cplx {
+    if (i == 0) return r == j0 ? cmk(1.0, 0.0) : cmk(0.0, 0.0);
+    if (r <= j0) return Cm[r * sb + (i - 1)];
+    const int a = r - j0 - 1;
+    return a < sb && a <= i - 1 ? Rm[a * sb + (i - 1)] : cmk(0.0, 0.0);
+  };
+  const cplx* Hr = s.Hraw + (int64_t)c * m1 * s.m;  // column j at Hr + j m1, rows 0..j+1
+  const cplx* th = s.theta;
+  for (int e = t; e < j0 * (j0 + 1); e += SS_HT) {  // H_old columns 0..j0-1, rows 0..j0
+    const int q = e / (j0 + 1), r = e - (e / (j0 + 1)) * (j0 + 1);
+    Ho[e] = r <= q + 1 ? Hr[(int64_t)q * m1 + r] : cmk(0.0, 0.0);
+  }
+  __syncthreads();
+  // Y = R_hat B - [H_old R_top; 0] on rows 0..j0+su, columns 0..su-1 (R_top:
+  // rows q < j0 of R_hat, zero in column 0)
+  for (int e = t; e < nrow * su; e += SS_HT) {
+    const int r = e / su, i = e - (e / su) * su;
+    cplx y = cadd(cmul(th[(int64_t)i * s.C + c], rhat(r, i)), rhat(r, i + 1));
+    if (r <= j0 && i >= 1) {
+      cplx acc = cmk(0.0, 0.0);
+      for (int q = max(0, r - 1); q < j0; ++q) cmac(acc, Ho[q * (j0 + 1) + r], Cm[q * sb + (i - 1)]);
+      y = csub(y, acc);
+    }
+    X[r * SS_MAX + i] = y;
+  }
+  __syncthreads();
+  // X <- Y R_s^{-1}, R_s[a][i] = R_hat[j0 + a][i] (upper triangular): column by column
+  for (int i = 0; i < su; ++i) {
+    const cplx d = rhat(j0 + i, i);
+    for (int r = t; r < nrow; r += SS_HT) {
+      cplx y = X[r * SS_MAX + i];
+      for (int q = 0; q < i; ++q) y = csub(y, cmul(X[r * SS_MAX + q], rhat(j0 + q, i)));
+      X[r * SS_MAX + i] = cdiv(y, d);
+    }
+    __syncthreads();
+  }
+  // the new columns j0..j0+su-1: raw storage, then the Givens update (the
+  // rotations of the earlier columns staged once; thread 0 appends its own)
+  for (int q = t; q < j0; q += SS_HT) {
+    csl[q] = s.cs[(int64_t)c * s.m + q];
+    snl[q] = s.sn[(int64_t)c * s.m + q];
+  }
+  // raw columns: all at once (rows 0..j+1 of column j0 + i)
+  for (int e = t; e < su * (nrow); e += SS_HT) {
+    const int i = e / nrow, r = e - (e / nrow) * nrow;
+    if (r <= j0 + i + 1) s.Hraw[(int64_t)c * m1 * s.m + (int64_t)(j0 + i) * m1 + r] = X[r * SS_MAX + i];
+  }
+  __syncthreads();  // csl, snl staged
+  // Givens update of the block: thread i applies the rotations of the earlier
+  // columns to new column i (all columns at once), then the su new rotations
+  // follow one by one, each formed by thread 0 and applied by the threads of
+  // the later columns; the bookkeeping of every column is that of
+  // arnoldi_step (residual estimate, stopping test), and the first column that
+  // stops ends the block.
+  __shared__ double crs[SS_MAX];
+  __shared__ cplx srs[SS_MAX];
+  __shared__ int nstop;
+  if (t < su) {
+    cplx cur = X[t];
+    for (int q = 0; q < j0; ++q) {
+      const cplx nx = X[(q + 1) * SS_MAX + t];
+      const double ci = csl[q];
+      const cplx si = snl[q];
+      X[q * SS_MAX + t] = cadd(cscale(cur, ci), cmul(si, nx));
+      cur = csub(cscale(nx, ci), cmul(cconj(si), cur));
+    }
+    X[j0 * SS_MAX + t] = cur;
+  }
+  if (t == 0) nstop = su;
+  __syncthreads();
+  const int m = s.m;
+  cplx* Hc = s.H + (int64_t)c * m1 * m;
+  cplx* gc = s.g + (int64_t)c * m1;
+  cplx gcur = cmk(0.0, 0.0);  // thread 0: g_j, iterations, ||f|| carried in registers
+  int itc = 0;
+  double nf = 1.0;
+  if (t == 0) {
+    gcur = gc[j0];
+    itc = s.iters[c];
+    nf = s.normf[c];
+  }
+  for (int k = 0; k < su; ++k) {
+    const int j = j0 + k;
+    if (t == 0) {
+      const cplx aa = X[j * SS_MAX + k];
+      const double hn = X[(j + 1) * SS_MAX + k].x;  // real by construction
+      double cr;
+      cplx sr;
+      if (hn == 0.0) {
+        cr = 1.0;
+        sr = cmk(0.0, 0.0);
+      } else if (aa.x == 0.0 && aa.y == 0.0) {
+        cr = 0.0;
+        sr = cmk(1.0, 0.0);
+      } else {
+        const double na = sqrt(cabs2(aa));
+        const double rho = hypot(na, hn);
+        cr = na / rho;
+        sr = cscale(aa, hn / (na * rho));
+      }
+      crs[k] = cr;
+      srs[k] = sr;
+      s.cs[(int64_t)c * m + j] = cr;
+      s.sn[(int64_t)c * m + j] = sr;
+      X[j * SS_MAX + k] = cadd(cscale(aa, cr), cscale(sr, hn));
+      const cplx gj = gcur;
+      const cplx gj1 = cmul(cscale(cconj(sr), -1.0), gj);
+      gc[j + 1] = gj1;
+      gc[j] = cscale(gj, cr);
+      gcur = gj1;
+      const int it = ++itc;
+      s.iters[c] = it;
+      const double rel = sqrt(cabs2(gj1)) / nf;
+      if (s.resvec) s.resvec[(int64_t)c * (s.maxit + 1) + it] = rel;
+      s.jdone[c] = j + 1;
+      const bool finite = isfinite(rel) && isfinite(hn);
+      if (!finite) s.status[c] = ST_BREAK;
+      if (!finite || rel <= s.tol || hn == 0.0 || it >= s.maxit || j + 1 >= m) {
+        s.inner[c] = 0;
+        atomicSub(s.n_inner, 1);
+        nstop = k + 1;
+      }
+    }
+    __syncthreads();
+    if (k + 1 >= nstop) break;
+    if (t > k && t < su) {  // rotation k on rows j, j+1 of the later new columns
+      const double ci = crs[k];
+      const cplx si = srs[k];
+      const cplx u = X[j * SS_MAX + t], v = X[(j + 1) * SS_MAX + t];
+      X[j * SS_MAX + t] = cadd(cscale(u, ci), cmul(si, v));
+      X[(j + 1) * SS_MAX + t] = csub(cscale(v, ci), cmul(cconj(si), u));
+    }
+    __syncthreads();
+  }
+  // the rotated columns (rows 0..j) of the processed columns
+  for (int e = t; e < nstop * nrow; e += SS_HT) {
+    const int i = e / nrow, r = e - (e / nrow) * nrow;
+    if (r <= j0 + i) Hc[(int64_t)(j0 + i) * m1 + r] = X[r * SS_MAX + i];
+  }
+}
+
 // ------------------------------------------------------------------ host driver
 // Rows per reduction chunk: enough chunks over all columns to fill the chip
 // (about 2048), few enough per column (<= 128 where possible) that every
@@ -1409,6 +1840,9 @@ struct GLayout {
   int sb = 0, nbpi = 0, NB = 0;
   int64_t n_bck = 0, n_btile = 0;
   size_t bck, bckoff, btile, bP, bT, bH, bG, bRq, bRi, bhv, btau, bY, bin, brun, bsteps, bact;
+  // s-step GMRES (ss > 0)
+  int ss = 0;
+  size_t sP2, stheta, sC, sR, sRi;
 };
 
 // Block geometry of block GMRES: reduction chunks and 64-row tiles of every
@@ -1438,7 +1872,7 @@ void block_geometry(const mudiff_ctx* h, int R, int sb, int64_t* n_bck, int64_t*
   *n_btile = nt;
 }
 
-GLayout glayout(mudiff_ctx* h, int R, int m, int sb = 0) {
+GLayout glayout(mudiff_ctx* h, int R, int m, int sb = 0, int ss = 0) {
   GLayout L{};
   const int64_t C = (int64_t)h->B * R;
   const int64_t NT = (int64_t)R * h->N_all;
@@ -1504,6 +1938,14 @@ GLayout glayout(mudiff_ctx* h, int R, int m, int sb = 0) {
     L.bsteps = take(NB * 4);
     L.bact = take(C * 4);
   }
+  if (ss > 0) {
+    L.ss = ss;
+    L.sP2 = take((size_t)nck * (m + 1) * ss * 16);
+    L.stheta = take((size_t)ss * C * 16);
+    L.sC = take((size_t)C * 2 * (m + 1) * ss * 16);
+    L.sR = take((size_t)C * 2 * ss * ss * 16);
+    L.sRi = take((size_t)C * ss * ss * 16);
+  }
   L.total = o;
   return L;
 }
@@ -1520,17 +1962,28 @@ static int block_size_of(int flags, int R, int restart) {
   return sb;
 }
 
+// Newton vectors per block of a MUDIFF_SSTEP solve (0: not s-step; -1: invalid).
+static int sstep_size_of(int flags, int restart) {
+  if (!(flags & MUDIFF_SSTEP)) return (flags & 0xff0000) ? -1 : 0;
+  if (flags & MUDIFF_BLOCK) return -1;
+  int ss = (flags >> 16) & 0xff;
+  if (ss == 0) ss = 8;
+  if (ss < 2 || ss > SS_MAX || restart > SS_MREST) return -1;
+  return std::min(ss, restart);
+}
+
 static bool known_gmres_flags(int flags) {
   return (flags & ~(MUDIFF_X0 | MUDIFF_GRAPH | MUDIFF_POINT_SOURCE | MUDIFF_NO_PRECOND |
-                    MUDIFF_BLOCK | 0xff00)) == 0;
+                    MUDIFF_BLOCK | MUDIFF_SSTEP | 0xff00 | 0xff0000)) == 0;
 }
 
 extern "C" size_t mudiff_gmres_workspace_size(mudiff_t h, int R, int restart, int flags) {
   if (!h || R < 1 || restart < 1 || restart > MUDIFF_MAX_RESTART) return 0;
   if (!known_gmres_flags(flags)) return 0;
   const int sb = block_size_of(flags, R, restart);
-  if (sb < 0) return 0;
-  return glayout(h, R, restart, sb).total;
+  const int ss = sstep_size_of(flags, restart);
+  if (sb < 0 || ss < 0) return 0;
+  return glayout(h, R, restart, sb, ss).total;
 }
 
 // Column of every row of a packed multivector.
@@ -1718,6 +2171,85 @@ static int enqueue_bcycle(GmresRun& G, int check_every, bool host_checks) {
   return MUDIFF_OK;
 }
 
+// One restart cycle of s-step GMRES (after the first cycle has given the
+// shifts): blocks of ss Newton vectors, each orthogonalised by two
+// reduction/sweep passes and folded into the Hessenberg matrix, then the
+// solution update and the true residual as in enqueue_cycle.
+static int enqueue_sscycle(GmresRun& G, bool host_checks) {
+  GState& s = G.s;
+  hipStream_t st = G.st;
+  const unsigned eb = (unsigned)((s.NT + 255) / 256);
+  const unsigned cb = (unsigned)((s.C + 63) / 64);
+  const unsigned nb = (unsigned)G.L.n_chunks;
+  const unsigned ry = (unsigned)((G.ch + SS_UR - 1) / SS_UR);
+  hipLaunchKernelGGL(k_scale_v0, dim3(eb), dim3(256), 0, st, s, s.NT, G.d_rowcol);
+  HIP_TRY(hipGetLastError());
+  for (int j0 = 0; j0 < s.m; j0 += s.ss) {
+    const int sb = std::min(s.ss, s.m - j0);
+    for (int i = 0; i < sb; ++i) {
+      int rc = apply_operator(G.h, s.R, s.V + (int64_t)(j0 + i) * s.NT, s.V + (int64_t)(j0 + i + 1) * s.NT,
+                              s.op, G.apply_part, G.apply_cnt, s.inner, st, s.theta + (int64_t)i * s.C);
+      if (rc != MUDIFF_OK) return rc;
+    }
+    const unsigned nvg = (unsigned)((j0 + 1 + sb + GS_WAVES - 1) / GS_WAVES);
+    for (int pass = 0; pass < 2; ++pass) {
+      hipLaunchKernelGGL(k_ss_dots, dim3(nb, nvg), dim3(GS_THREADS), 0, st, s, j0, sb);
+      hipLaunchKernelGGL(k_ss_sum, dim3((unsigned)s.C), dim3(SS_SUM_THREADS), 0, st, s, j0, sb, pass);
+      hipLaunchKernelGGL(k_ss_update, dim3(nb, ry), dim3(GS_THREADS), 0, st, s, j0, sb, pass);
+    }
+    hipLaunchKernelGGL(k_ss_hess, dim3((unsigned)s.C), dim3(SS_HT), 0, st, s, j0, sb);
+    HIP_TRY(hipGetLastError());
+    if (host_checks && j0 + sb < s.m) {
+      int32_t n_in = 0;
+      HIP_TRY(hipMemcpyAsync(&n_in, s.n_inner, 4, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      if (n_in <= 0) break;
+    }
+  }
+  hipLaunchKernelGGL(k_cycle_solve, dim3(s.C), dim3(64), 0, st, s);
+  hipLaunchKernelGGL(k_update_x, dim3(eb), dim3(256), 0, st, s, s.NT, G.d_rowcol);
+  HIP_TRY(hipGetLastError());
+  int rc = apply_operator(G.h, s.R, s.x, s.V, s.op, G.apply_part, G.apply_cnt, s.run, st);
+  if (rc != MUDIFF_OK) return rc;
+  hipLaunchKernelGGL(k_resid, dim3(nb), dim3(GS_THREADS), 0, st, s, 2, 1, (const cplx*)nullptr);
+  hipLaunchKernelGGL(k_col_sum, dim3(s.C), dim3(64), 0, st, s, 1);
+  hipLaunchKernelGGL(k_cycle_begin, dim3(cb), dim3(64), 0, st, s);
+  HIP_TRY(hipGetLastError());
+  return MUDIFF_OK;
+}
+
+// Shifts of the s-step cycles from the first cycle: per running column, the
+// Ritz values (eigenvalues of the square Hessenberg matrix of its jdone steps)
+// in Leja order, ss of them (columns that stopped get zeros).
+static int sstep_shifts(GmresRun& G) {
+  GState& s = G.s;
+  const int m = s.m, m1 = m + 1, C = s.C, ss = s.ss;
+  std::vector<cplx> Hr((size_t)C * m1 * m);
+  std::vector<int32_t> run(C), jd(C);
+  HIP_TRY(hipMemcpyAsync(Hr.data(), s.Hraw, Hr.size() * 16, hipMemcpyDeviceToHost, G.st));
+  HIP_TRY(hipMemcpyAsync(run.data(), s.run, (size_t)C * 4, hipMemcpyDeviceToHost, G.st));
+  HIP_TRY(hipMemcpyAsync(jd.data(), s.jdone, (size_t)C * 4, hipMemcpyDeviceToHost, G.st));
+  HIP_TRY(hipStreamSynchronize(G.st));
+  std::vector<cplx> th((size_t)ss * C, cmk(0.0, 0.0));
+  std::vector<ritz::cd> Hc, ev;
+  for (int c = 0; c < C; ++c) {
+    const int n = jd[c];
+    if (!run[c] || n < 1) continue;
+    Hc.assign((size_t)n * n, ritz::cd(0.0));
+    for (int j = 0; j < n; ++j)
+      for (int r = 0; r <= std::min(j + 1, n - 1); ++r) {
+        const cplx v = Hr[(size_t)c * m1 * m + (size_t)j * m1 + r];
+        Hc[(size_t)j * n + r] = ritz::cd(v.x, v.y);
+      }
+    ritz::hessenberg_eigenvalues(n, Hc.data(), n, ev);
+    const std::vector<ritz::cd> lj = ritz::leja(ev, ss);
+    for (int i = 0; i < (int)lj.size(); ++i) th[(size_t)i * C + c] = cmk(lj[i].real(), lj[i].imag());
+  }
+  HIP_TRY(hipMemcpyAsync(s.theta, th.data(), th.size() * 16, hipMemcpyHostToDevice, G.st));
+  HIP_TRY(hipStreamSynchronize(G.st));
+  return MUDIFF_OK;
+}
+
 extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* rhs, void* rho,
                             int restart, double tol, int maxit, int flags, void* workspace,
                             size_t ws_bytes, int32_t* flag, double* relres, int32_t* iters,
@@ -1733,7 +2265,14 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
   if (sb < 0)
     return fail(MUDIFF_ERR_INVALID, "block size must be 1.." + std::to_string(BG_SMAX) +
                                         " with restart * block size <= " + std::to_string(BG_MAXDIM));
-  GLayout L = glayout(h, R, restart, sb);
+  const int ss = sstep_size_of(flags, restart);
+  if (ss < 0)
+    return fail(MUDIFF_ERR_INVALID, "s-step size must be 2.." + std::to_string(SS_MAX) +
+                                        " with restart <= " + std::to_string(SS_MREST) +
+                                        ", not with MUDIFF_BLOCK");
+  if (ss > 0 && apply_uses_mfma(h, R))
+    return fail(MUDIFF_ERR_INVALID, "s-step GMRES runs on the one-lane and generic applies (R < 8 or N_p > 31)");
+  GLayout L = glayout(h, R, restart, sb, ss);
   if (!workspace) return fail(MUDIFF_ERR_INVALID, "workspace is NULL");
   apply_forget_upload(h);
   if (ws_bytes < L.total) return fail(MUDIFF_ERR_NOMEM, "gmres workspace needs " + std::to_string(L.total) + " bytes");
@@ -1778,6 +2317,13 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
   s.iters = (int32_t*)(w + L.iters);
   s.n_inner = (int32_t*)(w + L.ninner);
   s.resvec = resvec;
+  s.ss = ss;
+  s.sl2 = (restart + 1) * ss;
+  s.P2 = ss ? (cplx*)(w + L.sP2) : nullptr;
+  s.theta = ss ? (cplx*)(w + L.stheta) : nullptr;
+  s.sC = ss ? (cplx*)(w + L.sC) : nullptr;
+  s.sR = ss ? (cplx*)(w + L.sR) : nullptr;
+  s.sRi = ss ? (cplx*)(w + L.sRi) : nullptr;
   G.d_ckf = (int32_t*)(w + L.ckf);
   G.d_ckc = (int32_t*)(w + L.ckc);
   G.d_rowcol = (int32_t*)(w + L.rowcol);
@@ -1906,7 +2452,14 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
     int n_run = 0;
     for (int c = 0; c < s.C; ++c) n_run += hstat[c] != 0;
     if (n_run == 0) break;
-    if (sb == 0 && !use_graph && s.C >= 32 && n_run * 32 <= s.C &&
+    if (ss > 0) {  // s-step: the first cycle by delayed CGS2 gives the shifts
+      if (cyc == 0) {
+        if ((result = enqueue_cycle(G, 10, true)) != MUDIFF_OK) break;
+        if ((result = sstep_shifts(G)) != MUDIFF_OK) break;
+        continue;
+      }
+    }
+    if (sb == 0 && ss == 0 && !use_graph && s.C >= 32 && n_run * 32 <= s.C &&
         (G.n_compact == 0 || n_run * 2 <= G.n_compact)) {
       if ((result = compact_columns(G, hstat, n_run)) != MUDIFF_OK) break;
     }
@@ -1923,7 +2476,8 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
         }
         GmresRun Gc = G;
         Gc.st = cap;
-        int e = sb > 0 ? enqueue_bcycle(Gc, 0, false) : enqueue_cycle(Gc, 0, false);
+        int e = sb > 0 ? enqueue_bcycle(Gc, 0, false)
+                       : (ss > 0 ? enqueue_sscycle(Gc, false) : enqueue_cycle(Gc, 0, false));
         hipError_t ce = hipStreamEndCapture(cap, &graph);
         (void)hipStreamDestroy(cap);
         if (e != MUDIFF_OK || ce != hipSuccess) {
@@ -1939,7 +2493,8 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
       }
       HIP_TRY(hipGraphLaunch(exec, st));
     } else {
-      if ((result = sb > 0 ? enqueue_bcycle(G, 10, true) : enqueue_cycle(G, 10, true)) != MUDIFF_OK)
+      if ((result = sb > 0 ? enqueue_bcycle(G, 10, true)
+                           : (ss > 0 ? enqueue_sscycle(G, true) : enqueue_cycle(G, 10, true))) != MUDIFF_OK)
         break;
     }
   }

@@ -69,7 +69,7 @@ __global__ __launch_bounds__(APPLY_THREADS) void k_apply(
     cplx* __restrict__ part, int64_t part_total, int32_t* __restrict__ counters,
     const int32_t* __restrict__ items, const int32_t* __restrict__ nchunk,
     const int64_t* __restrict__ partoff, const int32_t* __restrict__ active, int zs, int ts,
-    int ppcap) {
+    int ppcap, const cplx* __restrict__ shift) {
   extern __shared__ cplx lds[];
   __shared__ int s_last;
   const int it = blockIdx.x, r = blockIdx.y;
@@ -155,7 +155,9 @@ __global__ __launch_bounds__(APPLY_THREADS) void k_apply(
     for (int m = tid; m < np; m += APPLY_THREADS) {
       cplx w = cmk(0.0, 0.0);
       for (int k = 0; k < nslot_max; ++k) w = cadd(w, red[k * LB + m]);
-      yc[m] = finalize(v, op, ip + m, xp[m], w);
+      cplx o = finalize(v, op, ip + m, xp[m], w);
+      if (shift) o = csub(o, cmul(shift[b * R + r], xp[m]));
+      yc[m] = o;
     }
     return;
   }
@@ -181,7 +183,9 @@ __global__ __launch_bounds__(APPLY_THREADS) void k_apply(
     for (int k = 0; k < nch; ++k) {
       w = cadd(w, pr[(int64_t)k * np + m]);  // visible after the fence above
     }
-    yc[m] = finalize(v, op, ip + m, xp[m], w);
+    cplx o = finalize(v, op, ip + m, xp[m], w);
+    if (shift) o = csub(o, cmul(shift[b * R + r], xp[m]));
+    yc[m] = o;
   }
 }
 
@@ -274,7 +278,8 @@ __global__ void k_apply_finish(DevView v, int R, const cplx* __restrict__ x, cpl
                                int op, const cplx* __restrict__ part, int64_t part_total,
                                const int32_t* __restrict__ nchunk,
                                const int64_t* __restrict__ partoff,
-                               const int32_t* __restrict__ active) {
+                               const int32_t* __restrict__ active,
+                               const cplx* __restrict__ shift) {
   const int64_t total = (int64_t)R * v.N_all;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= total) return;
@@ -291,7 +296,9 @@ __global__ void k_apply_finish(DevView v, int R, const cplx* __restrict__ x, cpl
   if (active && active[b * R + r] == 0) return;
   const int64_t i = v.imode[b] + (rem - (int64_t)r * Nb);
   const cplx w = lane_chunk_sum(v, part + (int64_t)r * part_total, nchunk, partoff, b, i);
-  y[g] = finalize(v, op, i, x[g], w);
+  cplx o = finalize(v, op, i, x[g], w);
+  if (shift) o = csub(o, cmul(shift[b * R + r], x[g]));
+  y[g] = o;
 }
 
 // ------------------------------------------------------------------ multi-RHS (MFMA)
@@ -648,6 +655,7 @@ __global__ void k_apply_mfma_finish(DevView v, int R, const cplx* __restrict__ x
 static bool use_mfma(const mudiff_ctx* h, int R) {
   return R >= MFMA_MIN_R && h->Nmax <= 31 && h->mfma_enabled && h->T_all < ((int64_t)1 << 31);
 }
+bool apply_uses_mfma(const mudiff_ctx* h, int R) { return use_mfma(h, R); }
 
 int circ_variant(int R);
 std::vector<int> circ_variants(int R);
@@ -656,9 +664,10 @@ void circ_var_dims(int var, int* bm, int* bn, int* bk, int* db, int* nt);
 int circ_finish(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, const cplx* part, int64_t blk,
                 int npad, int RC, const int32_t* dgrp, const int32_t* drow, const int32_t* gnseg,
                 const int64_t* gbase, const int32_t* active, const cplx* wh, const int32_t* con,
-                hipStream_t s);
+                const int32_t* con_h, hipStream_t s);
 int circ_launch(mudiff_ctx* h, int R, const cplx* z, cplx* zh, cplx* wh, const int32_t* citems,
-                int n_citems, int var, const int32_t* con, const int32_t* active, hipStream_t s);
+                int n_citems, int var, const int32_t* con, const int32_t* con_h,
+                const int32_t* active, hipStream_t s);
 
 // Host schedule of the MFMA apply for one tile choice.  With c.circ, the
 // instances marked circ_on keep only their close pairs in the MFMA items
@@ -953,7 +962,7 @@ static int mfma_launch(mudiff_ctx* h, const MfmaSched& S, const cplx* x, cplx* y
     cplx* zh = (cplx*)(base + off[12]);
     wh = (cplx*)(base + off[13]);
     rc = circ_launch(h, S.R, z, zh, wh, (const int32_t*)(base + off[10]), S.n_citems, S.cvar, con,
-                     active, s);
+                     S.con.data(), active, s);
     if (rc != MUDIFF_OK) return rc;
   } else {
     prof_mark(h, s, 2);
@@ -983,7 +992,7 @@ const int TL = 4 * kt + 16 * mt - 1;
     rc = circ_finish(h, S.R, x, y, op, (const cplx*)part, S.blk, S.npad, RC,
                      (const int32_t*)(base + off[2]), (const int32_t*)(base + off[8]),
                      (const int32_t*)(base + off[4]), (const int64_t*)(base + off[5]), active,
-                     (const cplx*)wh, con, s);
+                     (const cplx*)wh, con, S.con.data(), s);
     prof_mark(h, s, 5);
     return rc;
   }
@@ -1141,7 +1150,8 @@ int apply_set_tail(mudiff_ctx* h, int R, bool tail, cplx* scratch, hipStream_t s
 // ------------------------------------------------------------------ planning
 namespace {
 typedef void (*apply_fn)(DevView, int, const cplx*, cplx*, int, cplx*, int64_t, int32_t*,
-                         const int32_t*, const int32_t*, const int64_t*, const int32_t*, int, int, int);
+                         const int32_t*, const int32_t*, const int64_t*, const int32_t*, int, int, int,
+                         const cplx*);
 typedef void (*lane_fn)(DevView, int, const cplx*, cplx*, int64_t, const int32_t*,
                         const int32_t*);
 
@@ -1389,8 +1399,9 @@ int apply_operator_split(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, c
 }
 
 int apply_operator(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, cplx* part,
-                   int32_t* counters, const int32_t* active, hipStream_t s) {
+                   int32_t* counters, const int32_t* active, hipStream_t s, const cplx* shift) {
   if (use_mfma(h, R)) {
+    if (shift) return fail(MUDIFF_ERR_INVALID, "shifted applies run on the one-lane and generic kernels only");
     int st = mfma_prepare(h, R, nullptr, nullptr, (char*)part, s);  // no-op when current
     if (st != MUDIFF_OK) return st;
     return mfma_launch(h, h->mfma_sched, x, y, op, active, s);
@@ -1414,7 +1425,7 @@ int apply_operator(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, cplx* p
     const int64_t total = (int64_t)R * h->N_all;
     hipLaunchKernelGGL(k_apply_finish, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
                        h->dv, R, x, y, op, (const cplx*)part, P.part_total, P.d_nchunk,
-                       P.d_partoff, active);
+                       P.d_partoff, active, shift);
     HIP_TRY(hipGetLastError());
     prof_mark(h, s, 5);
     return MUDIFF_OK;
@@ -1423,7 +1434,7 @@ int apply_operator(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, cplx* p
   if (!var) return fail(MUDIFF_ERR_INVALID, "no operator kernel variant");
   hipLaunchKernelGGL(var->fn, dim3(P.n_items, R), dim3(APPLY_THREADS), P.lds_bytes, s, h->dv, R, x,
                      y, op, part, P.part_total, counters, P.d_items, P.d_nchunk, P.d_partoff, active,
-                     P.zs, P.ts, P.ppcap);
+                     P.zs, P.ts, P.ppcap, shift);
   HIP_TRY(hipGetLastError());
   prof_mark(h, s, 4);
   prof_mark(h, s, 5);

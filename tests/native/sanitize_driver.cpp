@@ -467,7 +467,9 @@ static void gpu_circulant(std::mt19937_64& g) {
                                    {64, 32, 32, 2, 256},  {128, 32, 16, 3, 512},
                                    {64, 32, 16, 3, 256},  {128, 16, 16, 2, 256},
                                    {128, 16, 16, 3, 256}, {128, 8, 16, 2, 256},
-                                   {64, 8, 16, 2, 256}};
+                                   {64, 8, 16, 2, 256},   {128, 32, 8, 3, 512},
+                                   {128, 64, 8, 3, 512},  {128, 32, 8, 2, 1024},
+                                   {256, 32, 8, 2, 512},  {128, 8, 8, 2, 256}};
     for (const auto& tile : tiles) {
       const int st = mudiff_set_circulant_tile(H.h, R, tile[0], tile[1], tile[2], tile[3], tile[4]);
       if (st != MUDIFF_OK) continue;  // not a candidate for this R

@@ -139,6 +139,49 @@ def test_circulant_close_pair_lists_every_tile(P):
                     assert rel(Y.cpu().numpy(), ref) < 1e-12, (ct, waves, qs)
 
 
+def _radix3_batch():
+    """Instances whose embedding length is a power of 3 (fast radix-3
+    transforms): L = 2 (7 + 6) + 1 = 27 and L = 2 (20 + 20) + 1 = 81; next to
+    them one with L = 41 (direct sums) and one outside the form."""
+    c27 = synth.small_random(540, 24, 0.3, 0.8, 30.0, 0.2, 6.0, 2)
+    n27 = np.full(c27.M, 6, np.int32)
+    n27[3] = 7
+    c27 = synth.Cluster(c27.centers, c27.radii, n27, c27.k)
+    c81 = synth.small_random(541, 16, 0.8, 1.0, 40.0, 0.2, 10.0, 10)
+    c81 = synth.Cluster(c81.centers, c81.radii, np.full(c81.M, 20, np.int32), c81.k)
+    low = synth.small_random(505, 10, 0.5, 0.9, 6.0, 0.1, 1.0, 6)
+    return [c27, _mixed(501), c81, low]
+
+
+@pytest.mark.parametrize("R", [8, 16, 40])
+def test_circulant_radix3_lengths(P, R):
+    """Fast radix-3 transforms (L = 27, 81) beside direct sums (L = 41) and an
+    instance outside the form, in one launch: A, L and L^T against the dense
+    oracle, every product tile."""
+    cls = _radix3_batch()
+    pr = P.from_clusters(cls, circulant=True)
+    info = pr.circulant_info()
+    say("radix-3 lengths R", R, info)
+    assert info["L_max"] == 81
+    pr.set_circulant(R, 1)
+    rng = np.random.default_rng(900 + R)
+    Xs = [rng.normal(size=(R, c.n_tot)) + 1j * rng.normal(size=(R, c.n_tot)) for c in cls]
+    x = pr.pack(Xs)
+    dense = [_dense(c) for c in cls]
+    for op in (1, 0, 2):
+        y = pr.matvec(x, R=R, op=op)
+        assert pr.apply_config(R)["kind"] == "circulant"
+        for (L, A), X, Y in zip(dense, Xs, pr.split(y, R)):
+            Mx = {1: A, 0: L, 2: L.T}[op]
+            e = rel(Y.cpu().numpy(), X @ Mx.T)
+            assert e < 1e-12, (op, e)
+    for tile in pr.circulant_tiles(R):
+        pr.set_circulant_tile(R, *tile)
+        y = pr.matvec(x, R=R, op=1)
+        for (_, A), X, Y in zip(dense, Xs, pr.split(y, R)):
+            assert rel(Y.cpu().numpy(), X @ A.T) < 1e-12, tile
+
+
 def _lu(cl, betas):
     L = operator.efie_matrix(cl.centers, cl.radii, cl.n_modes, cl.k)
     U = rhs.planewave(cl.centers, cl.radii, cl.n_modes, cl.k, betas)

@@ -1,0 +1,115 @@
+"""GPU parity of s-step GMRES (MUDIFF_SSTEP): after a first cycle of the
+one-vector process, each cycle builds its basis ss Newton vectors at a time
+(shifts: the first cycle's Ritz values in Leja order) and orthogonalises them
+in one block.  The iterates are those of GMRES up to rounding, so every column
+must equal its dense LU solution (the oracle) to the parity bar, 1e-10, at
+tol 1e-12, with nearly the iteration count of the one-vector solver, on the
+one-lane apply (uniform N_p, R = 1) and the generic apply (uneven N_p, R = 3),
+eager and replayed as graphs, with and without the preconditioner."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import operator, rhs, solve
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_1409_8186_amd import Problem
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return Problem
+
+
+def _dense_uniform(seed=61, M=60, N=10):
+    """A crowded lattice-like cluster (about 25% area fraction) that needs a few
+    hundred iterations: several s-step cycles at restart 30."""
+    cl = synth.small_random(seed, M, 0.5, 0.5, 14.0, 0.2, 2 * np.pi, 0)
+    return synth.Cluster(cl.centers, cl.radii, np.full(cl.M, N, np.int32), cl.k)
+
+
+def _lu(cl, betas, precond=True):
+    L = operator.efie_matrix(cl.centers, cl.radii, cl.n_modes, cl.k)
+    U = rhs.planewave(cl.centers, cl.radii, cl.n_modes, cl.k, betas)
+    return solve.efie_solve_lu(L, U)
+
+
+@pytest.mark.parametrize("ss", [4, 8, 16])
+def test_sstep_one_lane_matches_lu(P, ss):
+    cl = _dense_uniform()
+    pr = P.from_cluster(cl)
+    betas = [[np.pi / 4]]
+    say("s-step one-lane, ss", ss)
+    rho1, flag1, _, it1, _ = pr.gmres(betas=betas, restart=30, tol=1e-12, maxit=5000)
+    rho, flag, relres, iters, resvec = pr.gmres(betas=betas, restart=30, tol=1e-12, maxit=5000,
+                                                sstep=ss, want_resvec=True)
+    n1, n = int(it1[0]), int(iters[0])
+    say("  iterations: one-vector", n1, "s-step", n)
+    assert int(flag[0]) == 0 and float(relres[0]) <= 1e-12
+    assert n > 60  # several s-step cycles ran
+    assert abs(n - n1) <= max(3, n1 // 50)
+    assert rel(rho.cpu().numpy(), _lu(cl, betas[0])[0]) < 1e-10
+    # the estimates decrease within every cycle (minimisation over a growing space)
+    e = resvec.cpu().numpy()[0, :n + 1]
+    for c0 in range(0, n, 30):
+        blk = e[c0 + 1:min(n, c0 + 30) + 1]
+        assert np.all(np.diff(blk) <= 1e-12 * blk[:-1] + 1e-16)
+
+
+def test_sstep_generic_path_graph_and_options(P):
+    """Uneven orders (the generic apply), three incidences, a ragged last block
+    (restart 20, ss 8), graph replays equal to the eager solve, and the solve
+    without the preconditioner."""
+    cl = synth.small_random(62, 40, 0.3, 0.9, 13.0, 0.15, 6.0, 3)
+    betas = [[0.3, 1.7, 4.0]]
+    pr = P.from_cluster(cl)
+    say("s-step generic path")
+    rho, flag, _, iters, _ = pr.gmres(betas=betas, restart=20, tol=1e-12, maxit=5000, sstep=8)
+    say("  iterations", iters.cpu().numpy().tolist())
+    assert torch.all(flag == 0) and int(iters.min()) > 40
+    ref = _lu(cl, betas[0])
+    assert rel(pr.split(rho, 3)[0].cpu().numpy(), ref) < 1e-10
+    for rep in range(3):
+        rho_g, flag_g, _, it_g, _ = pr.gmres(betas=betas, restart=20, tol=1e-12, maxit=5000, sstep=8,
+                                             graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(it_g, iters) and torch.equal(flag_g, flag) and torch.equal(rho_g, rho), rep
+    # without the preconditioner (L rho = -U itself), on a sparser cluster where
+    # restarted GMRES converges: the same iterations as the one-vector solver
+    cs = synth.small_random(64, 16, 0.3, 0.9, 16.0, 0.3, 4.0, 3)
+    ps = P.from_cluster(cs)
+    _, flag1, _, it1, _ = ps.gmres(betas=betas, restart=30, tol=1e-12, maxit=20000, precond=False)
+    rho3, flag3, _, it3, _ = ps.gmres(betas=betas, restart=30, tol=1e-12, maxit=20000, sstep=8,
+                                      precond=False)
+    say("  no preconditioner: one-vector", it1.cpu().numpy().tolist(), "s-step", it3.cpu().numpy().tolist())
+    assert torch.all(flag1 == 0) and torch.all(flag3 == 0)
+    assert int((it3 - it1).abs().max()) <= max(3, int(it1.max()) // 50)
+    assert rel(ps.split(rho3, 3)[0].cpu().numpy(), _lu(cs, betas[0])) < 1e-10
+
+
+def test_sstep_first_cycle_only_and_invalid(P):
+    """A problem that converges inside the first cycle never reaches the s-step
+    cycles; invalid sizes and the multi-right-hand-side apply are refused."""
+    cl = synth.small_random(63, 4, 0.4, 0.6, 10.0, 0.5, 2.0, 2)
+    pr = P.from_cluster(cl)
+    rho, flag, _, iters, _ = pr.gmres(betas=[[0.5]], restart=50, tol=1e-12, maxit=2000, sstep=8)
+    assert int(flag[0]) == 0 and int(iters[0]) < 50
+    assert rel(rho.cpu().numpy(), _lu(cl, [0.5])[0]) < 1e-10
+    from paper_1409_8186_amd import _lib
+    for kw in ({"sstep": 1}, {"sstep": 17}, {"sstep": 8, "restart": 200}, {"sstep": 8, "block": 4}):
+        args = {"restart": 30, **kw}
+        with pytest.raises(_lib.MudiffError):
+            pr.gmres(betas=[[0.5]], tol=1e-8, maxit=10, **args)
+    pm = P.from_cluster(_dense_uniform(M=12, N=6))
+    with pytest.raises(_lib.MudiffError):  # R = 8: the FP64-MFMA apply
+        pm.gmres(betas=[synth.uniform_angles(8)], restart=30, tol=1e-8, maxit=10, sstep=8)

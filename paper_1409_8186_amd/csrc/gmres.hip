@@ -1418,8 +1418,25 @@ __global__ void k_zero_i(int32_t* p, int n) {
 // process.  Per ss steps: ss applies, four reduction/sweep launches and one
 // small per-column kernel, against 2 ss launches for delayed CGS2.
 #define SS_MAX 16
+// dst[e] = src(e), e < n, for the nt threads of a block: eight loads in flight
+// per thread before the stores (a load-store loop would wait on every load).
+template <class F>
+__device__ __forceinline__ void ss_stage(cplx* dst, int n, int tid, int nt, F src) {
+  for (int e0 = tid; e0 < n; e0 += 8 * nt) {
+    cplx v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * nt;
+      v[u] = e < n ? src(e) : cmk(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * nt;
+      if (e < n) dst[e] = v[u];
+    }
+  }
+}
 #define SS_MREST 64    // longest restart of an s-step solve (LDS of the per-column kernels)
-#define SS_SUM_THREADS 1024
 #define SS_CL ((SS_MREST + 1) * SS_MAX)
 
 // P2[chunk][l ss + k] = sum over the chunk's rows of conj(V_l) V_{j0+1+k},
@@ -1461,50 +1478,58 @@ __global__ __launch_bounds__(GS_THREADS) void k_ss_dots(GState s, int j0, int sb
 }
 
 // Per column: the chunk partials added in chunk order give C = Q^H W
-// ((j0 + 1) x sb) and G = W^H W; R = chol(G - C^H C) (a pivot below 1e-14 of
-// its diagonal entry, or not positive, drops that row), its inverse on the
-// kept rows, all stored for the sweep (pass 0 or 1).
-__global__ __launch_bounds__(SS_SUM_THREADS) void k_ss_sum(GState s, int j0, int sb, int pass) {
+// ((j0 + 1) x sb) and G = W^H W, stored for k_ss_chol; one thread per slot,
+// sixteen chunk loads in flight.
+__global__ __launch_bounds__(GS_THREADS) void k_ss_red(GState s, int j0, int sb, int pass) {
+  const int c = blockIdx.x;
+  if (!s.inner[c]) return;
+  const int e = blockIdx.y * GS_THREADS + threadIdx.x;
+  const int nl = j0 + 1 + sb, ss = s.ss;
+  if (e >= nl * sb) return;
+  const int l = e / sb, k = e - (e / sb) * sb;
+  const int k0 = s.ckf[c], nck = s.ckc[c];
+  const cplx* src = s.P2 + (int64_t)k0 * s.sl2 + l * ss + k;
+  cplx a = cmk(0.0, 0.0);
+  for (int q = 0; q < nck; q += 16) {
+    cplx v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = q + u < nck ? src[(int64_t)(q + u) * s.sl2] : cmk(0.0, 0.0);
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (q + u < nck) a = cadd(a, v[u]);
+  }
+  // slots l <= j0: C (this pass); l > j0: the Gram matrix, kept in the R slot
+  if (l <= j0) s.sC[((int64_t)c * 2 + pass) * s.sl2 + l * ss + k] = a;
+  else s.sR[((int64_t)c * 2 + pass) * ss * ss + (l - j0 - 1) * ss + k] = a;
+}
+
+// Per column, one wavefront: R = chol(G - C^H C) (a pivot below 1e-14 of its
+// diagonal entry, or not positive, drops that row) and its inverse on the kept
+// rows, R over the Gram matrix in the R slot of this pass.
+__global__ __launch_bounds__(64) void k_ss_chol(GState s, int j0, int sb, int pass) {
   __shared__ cplx Cl[SS_CL];
   __shared__ cplx G[SS_MAX * SS_MAX];
   __shared__ cplx Ii[SS_MAX * SS_MAX];
   __shared__ double dg[SS_MAX], piv[SS_MAX];
   const int c = blockIdx.x, t = threadIdx.x;
   if (!s.inner[c]) return;
-  const int nl = j0 + 1 + sb, ss = s.ss;
-  const int k0 = s.ckf[c], nck = s.ckc[c];
-  cplx* Cg = s.sC + ((int64_t)c * 2 + pass) * s.sl2;
-  for (int e = t; e < nl * sb; e += SS_SUM_THREADS) {
-    const int l = e / sb, k = e - (e / sb) * sb;
-    const cplx* src = s.P2 + (int64_t)k0 * s.sl2 + l * ss + k;
-    cplx a = cmk(0.0, 0.0);
-    int q = 0;
-    for (; q < nck; q += 16) {  // sixteen loads in flight, added in chunk order
-      cplx v[16];
-#pragma unroll
-      for (int u = 0; u < 16; ++u) v[u] = q + u < nck ? src[(int64_t)(q + u) * s.sl2] : cmk(0.0, 0.0);
-#pragma unroll
-      for (int u = 0; u < 16; ++u)
-        if (q + u < nck) a = cadd(a, v[u]);
-    }
-    if (l <= j0) {
-      Cl[e] = a;
-      Cg[l * ss + k] = a;
-    } else {
-      G[(l - j0 - 1) * SS_MAX + k] = a;
-    }
-  }
+  const int ss = s.ss;
+  const cplx* Cg = s.sC + ((int64_t)c * 2 + pass) * s.sl2;
+  cplx* Rg = s.sR + ((int64_t)c * 2 + pass) * ss * ss;
+  ss_stage(Cl, (j0 + 1) * sb, t, 64, [&](int e) { return Cg[(e / sb) * ss + e % sb]; });
+  ss_stage(Ii, sb * sb, t, 64, [&](int e) { return Rg[(e / sb) * ss + e % sb]; });
   __syncthreads();
-  // G - C^H C
-  for (int e = t; e < sb * sb; e += SS_SUM_THREADS) {
+  for (int e = t; e < sb * sb; e += 64) G[(e / sb) * SS_MAX + e % sb] = Ii[e];
+  __syncthreads();
+  for (int e = t; e < sb * sb; e += 64) {  // G - C^H C
     const int a = e / sb, k = e - (e / sb) * sb;
     cplx g = G[a * SS_MAX + k];
     for (int l = 0; l <= j0; ++l) g = csub(g, cmul(cconj(Cl[l * sb + a]), Cl[l * sb + k]));
     Ii[a * SS_MAX + k] = g;
   }
   __syncthreads();
-  for (int e = t; e < sb * sb; e += SS_SUM_THREADS) G[(e / sb) * SS_MAX + e % sb] = Ii[(e / sb) * SS_MAX + e % sb];
-  if (t < sb) dg[t] = G[t * SS_MAX + t].x;
+  for (int e = t; e < sb * sb; e += 64) G[(e / sb) * SS_MAX + e % sb] = Ii[(e / sb) * SS_MAX + e % sb];
+  if (t < sb) dg[t] = Ii[t * SS_MAX + t].x;
   __syncthreads();
   for (int k = 0; k < sb; ++k) {
     if (t == 0) {
@@ -1519,8 +1544,8 @@ __global__ __launch_bounds__(SS_SUM_THREADS) void k_ss_sum(GState s, int j0, int
       else G[k * SS_MAX + t] = rk > 0.0 ? cscale(G[k * SS_MAX + t], 1.0 / rk) : cmk(0.0, 0.0);
     }
     __syncthreads();
-    if (t < sb * sb) {
-      const int a = t / sb, cc = t % sb;
+    for (int e = t; e < sb * sb; e += 64) {
+      const int a = e / sb, cc = e - (e / sb) * sb;
       if (a > k && cc > k) G[a * SS_MAX + cc] = csub(G[a * SS_MAX + cc], cmul(cconj(G[k * SS_MAX + a]), G[k * SS_MAX + cc]));
     }
     __syncthreads();
@@ -1537,9 +1562,8 @@ __global__ __launch_bounds__(SS_SUM_THREADS) void k_ss_sum(GState s, int j0, int
     }
   }
   __syncthreads();
-  cplx* Rg = s.sR + ((int64_t)c * 2 + pass) * ss * ss;
   cplx* Rig = s.sRi + (int64_t)c * ss * ss;
-  for (int e = t; e < sb * sb; e += SS_SUM_THREADS) {
+  for (int e = t; e < sb * sb; e += 64) {
     const int a = e / sb, k = e - (e / sb) * sb;
     Rg[a * ss + k] = G[a * SS_MAX + k];
     Rig[a * ss + k] = Ii[a * SS_MAX + k];
@@ -1561,8 +1585,9 @@ __global__ __launch_bounds__(GS_THREADS) void k_ss_update(GState s, int j0, int 
   if (!s.inner[c]) return;
   const int t = threadIdx.x, ss = s.ss;
   const cplx* Cg = s.sC + ((int64_t)c * 2 + pass) * s.sl2;
-  for (int e = t; e < (j0 + 1) * sb; e += GS_THREADS) Cl[e] = Cg[(e / sb) * ss + e % sb];
-  for (int e = t; e < sb * sb; e += GS_THREADS) Ri[e] = s.sRi[(int64_t)c * ss * ss + (e / sb) * ss + e % sb];
+  ss_stage(Cl, (j0 + 1) * sb, t, GS_THREADS, [&](int e) { return Cg[(e / sb) * ss + e % sb]; });
+  const cplx* Rig = s.sRi + (int64_t)c * ss * ss;
+  ss_stage(Ri, sb * sb, t, GS_THREADS, [&](int e) { return Rig[(e / sb) * ss + e % sb]; });
   __syncthreads();
   const int rl = t & (SS_UR - 1), g = t / SS_UR;
   const int r = blockIdx.y * SS_UR + rl;
@@ -1638,26 +1663,26 @@ __global__ __launch_bounds__(SS_HT) void k_ss_hess(GState s, int j0, int sb) {
   const cplx* C2 = C1 + s.sl2;
   const cplx* R1 = s.sR + (int64_t)c * 2 * ss * ss;
   const cplx* R2 = R1 + ss * ss;
-  // stage C2 in X and R1, R2 in Rm / hl (scratch until used below)
-  for (int e = t; e < (j0 + 1) * sb; e += SS_HT) X[e] = C2[(e / sb) * ss + e % sb];
-  for (int e = t; e < sb * sb; e += SS_HT) {
-    Rm[e] = R1[(e / sb) * ss + e % sb];
-    Ho[e] = R2[(e / sb) * ss + e % sb];
-  }
+  // stage C1 in Cm, C2 in X, R1 in Rm, R2 in Ho (scratch until used below)
+  ss_stage(Cm, (j0 + 1) * sb, t, SS_HT, [&](int e) { return C1[(e / sb) * ss + e % sb]; });
+  ss_stage(X, (j0 + 1) * sb, t, SS_HT, [&](int e) { return C2[(e / sb) * ss + e % sb]; });
+  ss_stage(Rm, sb * sb, t, SS_HT, [&](int e) { return R1[(e / sb) * ss + e % sb]; });
+  ss_stage(Ho, sb * sb, t, SS_HT, [&](int e) { return R2[(e / sb) * ss + e % sb]; });
   __syncthreads();
-  for (int e = t; e < (j0 + 1) * sb; e += SS_HT) {  // C = C1 + C2 R1
+  for (int e = t; e < (j0 + 1) * sb; e += SS_HT) {  // C = C1 + C2 R1 (in place: own entry)
     const int l = e / sb, k = e - (e / sb) * sb;
-    cplx a = C1[l * ss + k];
+    cplx a = Cm[e];
     for (int q = 0; q <= k; ++q) cmac(a, X[l * sb + q], Rm[q * sb + k]);
     Cm[e] = a;
   }
-  cplx rr = cmk(0.0, 0.0);
-  if (t < sb * sb) {  // R = R2 R1
-    const int a = t / sb, k = t % sb;
+  for (int e = t; e < sb * sb; e += SS_HT) {  // R = R2 R1, into the tail of Ho
+    const int a = e / sb, k = e - (e / sb) * sb;
+    cplx rr = cmk(0.0, 0.0);
     for (int q = a; q <= k; ++q) cmac(rr, Ho[a * sb + q], Rm[q * sb + k]);
+    Ho[SS_MAX * SS_MAX + e] = rr;
   }
   __syncthreads();
-  if (t < sb * sb) Rm[t] = rr;
+  for (int e = t; e < sb * sb; e += SS_HT) Rm[e] = Ho[SS_MAX * SS_MAX + e];
   __syncthreads();
   if (t == 0) {
     int u = 0;
@@ -1680,10 +1705,10 @@ __global__ __launch_bounds__(SS_HT) void k_ss_hess(GState s, int j0, int sb) {
   };
   const cplx* Hr = s.Hraw + (int64_t)c * m1 * s.m;  // column j at Hr + j m1, rows 0..j+1
   const cplx* th = s.theta;
-  for (int e = t; e < j0 * (j0 + 1); e += SS_HT) {  // H_old columns 0..j0-1, rows 0..j0
+  ss_stage(Ho, j0 * (j0 + 1), t, SS_HT, [&](int e) {  // H_old columns 0..j0-1, rows 0..j0
     const int q = e / (j0 + 1), r = e - (e / (j0 + 1)) * (j0 + 1);
-    Ho[e] = r <= q + 1 ? Hr[(int64_t)q * m1 + r] : cmk(0.0, 0.0);
-  }
+    return r <= q + 1 ? Hr[(int64_t)q * m1 + r] : cmk(0.0, 0.0);
+  });
   __syncthreads();
   // Y = R_hat B - [H_old R_top; 0] on rows 0..j0+su, columns 0..su-1 (R_top:
   // rows q < j0 of R_hat, zero in column 0)
@@ -2194,7 +2219,9 @@ static int enqueue_sscycle(GmresRun& G, bool host_checks) {
     const unsigned nvg = (unsigned)((j0 + 1 + sb + GS_WAVES - 1) / GS_WAVES);
     for (int pass = 0; pass < 2; ++pass) {
       hipLaunchKernelGGL(k_ss_dots, dim3(nb, nvg), dim3(GS_THREADS), 0, st, s, j0, sb);
-      hipLaunchKernelGGL(k_ss_sum, dim3((unsigned)s.C), dim3(SS_SUM_THREADS), 0, st, s, j0, sb, pass);
+      hipLaunchKernelGGL(k_ss_red, dim3((unsigned)s.C, (unsigned)(((j0 + 1 + sb) * sb + GS_THREADS - 1) / GS_THREADS)),
+                         dim3(GS_THREADS), 0, st, s, j0, sb, pass);
+      hipLaunchKernelGGL(k_ss_chol, dim3((unsigned)s.C), dim3(64), 0, st, s, j0, sb, pass);
       hipLaunchKernelGGL(k_ss_update, dim3(nb, ry), dim3(GS_THREADS), 0, st, s, j0, sb, pass);
     }
     hipLaunchKernelGGL(k_ss_hess, dim3((unsigned)s.C), dim3(SS_HT), 0, st, s, j0, sb);

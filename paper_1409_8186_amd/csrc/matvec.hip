@@ -970,7 +970,7 @@ static int mfma_launch(mudiff_ctx* h, const MfmaSched& S, const cplx* x, cplx* y
   }
   if (S.n_items > 0) {
     const int32_t* it = (const int32_t*)(base + off[1]);
-const int TL = 4 * kt + 16 * mt - 1;
+    const int TL = 4 * kt + 16 * mt - 1;
     auto pow2 = [](int v) { int r = 1; while (r < v) r <<= 1; return r; };
     const int zk = pow2((4 * kt * RC + S.c.threads - 1) / S.c.threads);
     const int tk = pow2((S.c.RP * TL + S.c.threads - 1) / S.c.threads);

@@ -182,6 +182,82 @@ def test_circulant_radix3_lengths(P, R):
             assert rel(Y.cpu().numpy(), X @ A.T) < 1e-12, tile
 
 
+def _close_counts(cl):
+    """Close neighbours of each disk (k b_pq < N_p + N_q), from the geometry."""
+    b, _ = geometry.pair_geometry(cl.centers)
+    near = cl.k * b < cl.n_modes[:, None] + cl.n_modes[None, :]
+    np.fill_diagonal(near, False)
+    return near.sum(axis=1)
+
+
+def _crowded27(seed):
+    """L = 27 (N_p = 6, one disk 7) with disk 0 ringed by ten close neighbours
+    at distance 1.6 (k b = 9.6 < 13) and 30 disks spread far from the ring."""
+    ring = [[1.6 * math.cos(2 * math.pi * j / 10), 1.6 * math.sin(2 * math.pi * j / 10)]
+            for j in range(10)]
+    far, fr = synth.random_disks(np.random.default_rng(seed), 30, 0.3, 0.5, 6.0, 40.0, 0.3)
+    centers = np.vstack([[[0.0, 0.0]], ring, far])
+    radii = np.concatenate([[0.4], np.full(10, 0.3), fr])
+    n = np.full(len(radii), 6, np.int32)
+    n[5] = 7
+    return synth.Cluster(centers, radii, n, 6.0)
+
+
+def _sparse_and_crowded_batch():
+    """Two L = 27 instances: one with at most a few close neighbours per disk
+    and one whose ringed disk has ten (a close-pair list longer than a row
+    group's mask of 8); and an L = 81 one with a few close pairs."""
+    c27 = synth.small_random(560, 30, 0.3, 0.6, 16.0, 0.2, 6.0, 2)
+    n27 = np.full(c27.M, 6, np.int32)
+    n27[0] = 7
+    c27 = synth.Cluster(c27.centers, c27.radii, n27, 6.0)
+    c81 = synth.small_random(561, 20, 0.8, 1.0, 28.0, 0.2, 10.0, 10)
+    c81 = synth.Cluster(c81.centers, c81.radii, np.full(c81.M, 20, np.int32), 10.0)
+    return [c27, _crowded27(562), c81]
+
+
+@pytest.mark.parametrize("R", [8, 24])
+def test_circulant_radix3_close_pairs(P, R):
+    """Radix-3 instances with sparse and crowded close pairs beside each other
+    in one launch, ragged 16-column blocks of the output pass: A, L and L^T
+    against the dense oracle, every product tile, and lockstep GMRES (columns
+    that stop early are skipped by the output pass) against LU."""
+    cls = _sparse_and_crowded_batch()
+    counts = [_close_counts(c) for c in cls]
+    say("close neighbours per disk (max)", [int(c.max()) for c in counts],
+        "close ordered pairs", [int(c.sum()) for c in counts])
+    assert counts[0].sum() > 0 and counts[0].max() <= 8
+    assert counts[1].max() > 8
+    assert counts[2].sum() > 0 and counts[2].max() <= 8
+    pr = P.from_clusters(cls, circulant=True)
+    info = pr.circulant_info()
+    assert info["L_max"] == 81 and info["near_pairs"] == sum(int(c.sum()) for c in counts)
+    pr.set_circulant(R, 1)
+    rng = np.random.default_rng(950 + R)
+    Xs = [rng.normal(size=(R, c.n_tot)) + 1j * rng.normal(size=(R, c.n_tot)) for c in cls]
+    x = pr.pack(Xs)
+    dense = [_dense(c) for c in cls]
+    for op in (1, 0, 2):
+        y = pr.matvec(x, R=R, op=op)
+        assert pr.apply_config(R)["kind"] == "circulant"
+        for (L, A), X, Y in zip(dense, Xs, pr.split(y, R)):
+            Mx = {1: A, 0: L, 2: L.T}[op]
+            e = rel(Y.cpu().numpy(), X @ Mx.T)
+            assert e < 1e-12, (op, e)
+    for tile in pr.circulant_tiles(R):
+        pr.set_circulant_tile(R, *tile)
+        y = pr.matvec(x, R=R, op=1)
+        for (_, A), X, Y in zip(dense, Xs, pr.split(y, R)):
+            assert rel(Y.cpu().numpy(), X @ A.T) < 1e-12, tile
+    betas = np.stack([synth.uniform_angles(R) + 0.1 * i for i in range(len(cls))])
+    rho, flag, _, iters, _ = pr.gmres(betas=betas, restart=30, tol=1e-12, maxit=3000)
+    say("  gmres iterations", iters.cpu().numpy().tolist())
+    assert torch.all(flag == 0), flag
+    assert len(set(iters.cpu().numpy().tolist())) > 1  # columns stop at different steps
+    for b, (c, Y) in enumerate(zip(cls, pr.split(rho, R))):
+        assert rel(Y.cpu().numpy(), _lu(c, betas[b])) < 1e-10
+
+
 def _lu(cl, betas):
     L = operator.efie_matrix(cl.centers, cl.radii, cl.n_modes, cl.k)
     U = rhs.planewave(cl.centers, cl.radii, cl.n_modes, cl.k, betas)

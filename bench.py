@@ -12,15 +12,15 @@ transforms and per-frequency FP64-MFMA products of the well-separated pairs
 value = N_tot * R / (mean step time).  Also printed: the phase times of the
 timed applies (HIP events on the launch stream), the roofline of the dominant
 kernel (the per-frequency products), time-to-1e-8 of the whole 256-column
-solve (tables + right-hand sides + lockstep GMRES(30)), the direct form's
+solve (tables + right-hand sides + s-step GMRES(30), s = 15), the direct form's
 apply time, the one-RHS workload's step (tables + GMRES(50) to 1e-8 + far
 field), and the CPU oracle timed on a bounded sample.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline] [--no-solve]
     python bench.py --workload one_rhs | uneven | differentiation | dort | formulations |
                                nearfield | penetrable      (documentation runs)
-    python bench.py --workload multi_rhs_block [--block-sizes 16,8]
-                               (the 256-column solve by lockstep and by block GMRES)
+    python bench.py --workload multi_rhs_block [--block-sizes 16,8] [--sstep-sizes 15,10]
+                               (the 256-column solve by lockstep, block and s-step GMRES)
 """
 from __future__ import annotations
 
@@ -40,6 +40,7 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6
 PEAK_FP64_MFMA_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_apply_one_rhs_traffic.txt")
+SOLVE_SSTEP = 15   # Newton vectors per block of the 256-column solve
 APPLY_SRC = [os.path.join(ROOT, "paper_1409_8186_amd", "csrc", f)
              for f in ("matvec.hip", "common.h", "tables.hip")]
 CIRC_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_circ_gemm_multi_rhs_traffic.txt")
@@ -214,9 +215,10 @@ def circ_split(insts, R):
 
 def block_workload(base, args):
     """The multi-RHS workload (1,000 disks, 256 incidences) solved to 1e-8 with
-    GMRES(30) by lockstep batched GMRES and by block GMRES for each block size
-    in --block-sizes (the circulant-form apply in every case): time, steps,
-    and the agreement of the solutions."""
+    GMRES(30) by lockstep batched GMRES, by block GMRES for each block size in
+    --block-sizes and by s-step GMRES for each size in --sstep-sizes (the
+    circulant-form apply in every case): time, steps, and the agreement of the
+    solutions with lockstep's."""
     import numpy as np
     import torch
 
@@ -243,14 +245,28 @@ def block_workload(base, args):
         runs.append(r)
         print(f"[bench] {label}: {t_s:.1f} s, steps <= {r['steps_max']}", file=sys.stderr, flush=True)
         del rho
+    for ss in [int(v) for v in args.sstep_sizes.split(",") if v]:
+        label = f"s-step {ss}"
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rho, flag, _, its, _ = P.gmres(betas=betas, restart=30, tol=1e-8, maxit=20000, sstep=ss)
+        torch.cuda.synchronize()
+        t_s = time.perf_counter() - t0
+        d = (rho - ref).reshape(R, -1)
+        runs.append({"solver": label, "time_s": t_s, "steps_max": int(its.max()),
+                     "steps_min": int(its.min()), "all_converged": bool((flag == 0).all()),
+                     "max_rel_diff_vs_lockstep": float((d.norm(dim=1) / ref.reshape(R, -1).norm(dim=1)).max())})
+        print(f"[bench] {label}: {t_s:.1f} s, steps <= {int(its.max())}", file=sys.stderr, flush=True)
+        del rho
     t_lock = runs[0]["time_s"]
     best = min(runs, key=lambda r: r["time_s"])
     out = dict(base)
     out.update({"metric": "time-to-1e-8 GMRES solve (all 256 columns)", "value": best["time_s"],
                 "unit": "s", "higher_is_better": False, "ms_per_step": best["time_s"] * 1e3,
-                "config": {"workload": "multi_rhs, block GMRES: M=1000 disks, k=10, N_p=ceil(10a)+10, "
-                                       "256 incidences, GMRES(30) to 1e-8, lockstep and block GMRES "
-                                       "(blocks of consecutive incidences), circulant-form apply",
+                "config": {"workload": "multi_rhs, GMRES variants: M=1000 disks, k=10, N_p=ceil(10a)+10, "
+                                       "256 incidences, GMRES(30) to 1e-8, lockstep, block GMRES "
+                                       "(blocks of consecutive incidences) and s-step GMRES, "
+                                       "circulant-form apply",
                            "n_unknowns": cl.n_tot, "R": R, "fastest": best["solver"]},
                 "runs": runs,
                 "speedup_vs_lockstep": {r["solver"]: t_lock / r["time_s"] for r in runs[1:]}})
@@ -918,11 +934,13 @@ def headline(args):
         t0 = time.perf_counter()
         P = Problem.from_cluster(cl, circulant=True)
         rho, flag, relres, iters, _ = P.gmres(betas=cl.betas[None, :], restart=30, tol=1e-8,
-                                              maxit=20000)
+                                              maxit=20000, sstep=SOLVE_SSTEP)
         torch.cuda.synchronize()
         out["time_to_1e8_s"] = time.perf_counter() - t0
-        out["solve"] = {"what": "tables + plane-wave right-hand sides + lockstep GMRES(30), x0 = 0, "
-                                "all 256 columns to 1e-8 (the first apply times the forms)",
+        out["solve"] = {"what": "tables + plane-wave right-hand sides + s-step GMRES(30) "
+                                f"(s = {SOLVE_SSTEP}: a first one-vector cycle, then Newton bases "
+                                "with its Ritz shifts), x0 = 0, all 256 columns to 1e-8 (the first "
+                                "apply times the forms)",
                         "gmres_iters_max": int(iters.max()), "gmres_iters_min": int(iters.min()),
                         "all_converged": bool((flag == 0).all()),
                         "relres_max": float(relres.max()),
@@ -959,6 +977,8 @@ def main():
                     choices=["multi_rhs", "multi_rhs_block", "one_rhs", "uneven", "differentiation", "dort",
                              "formulations", "nearfield", "penetrable"],
                     help="multi_rhs (default bench line) or a documentation run of another workload")
+    ap.add_argument("--sstep-sizes", default="15,10", metavar="S,S,...",
+                    help="multi_rhs_block workload: s-step sizes to run next to lockstep")
     ap.add_argument("--block-sizes", default="16,8", metavar="S,S,...",
                     help="multi_rhs_block: block sizes of the block GMRES solves")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",

@@ -432,11 +432,12 @@ size_t mudiff_gmres_workspace_size(mudiff_t h, int R, int restart, int flags);
  * twice) and derives the s Hessenberg columns from the coefficients; each
  * column's residual estimate and stopping test still follow every column.
  * Fewer, larger reductions per step: for latency-bound sizes (one right-hand
- * side).  It runs on the one-lane and generic applies only (R < 8, or some
- * N_p > 31); not with MUDIFF_BLOCK.
- * Errors: MUDIFF_ERR_INVALID for a block or s-step size out of range, an
- * s-step solve on the multi-right-hand-side (FP64-MFMA) apply, or unknown
- * flags. */
+ * side) the reductions, for bandwidth-bound ones (many right-hand sides) the
+ * sweeps over the basis (two per s steps instead of two per step).  Every
+ * apply path takes the shift (one-lane, generic, FP64-MFMA direct and
+ * circulant forms); not with MUDIFF_BLOCK.
+ * Errors: MUDIFF_ERR_INVALID for a block or s-step size out of range, or
+ * unknown flags. */
 int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* rhs, void* rho,
                  int restart, double tol, int maxit, int flags,
                  void* workspace, size_t ws_bytes,

@@ -453,7 +453,8 @@ __global__ __launch_bounds__(256) void k_circ_finish_mfma(
     const cplx* __restrict__ part, int64_t blk, int npad, int RC, const int32_t* __restrict__ dgrp,
     const int32_t* __restrict__ drow, const int32_t* __restrict__ gnseg,
     const int64_t* __restrict__ gbase, const int32_t* __restrict__ active,
-    const cplx* __restrict__ wh, const int32_t* __restrict__ con, int wpc) {
+    const cplx* __restrict__ wh, const int32_t* __restrict__ con, const cplx* __restrict__ shift,
+    int wpc) {
   extern __shared__ cplx lds[];
   cplx* tw = lds;                          // [L_b]
   cplx* ws = lds + 128;                    // W^p rows [f][r], then the results [r][j]
@@ -516,7 +517,9 @@ __global__ __launch_bounds__(256) void k_circ_finish_mfma(
     cplx w = circ ? ws[rr * ldw + m] : cmk(0.0, 0.0);
     for (int sg = 0; sg < ns; ++sg) w = cadd(w, pr[(int64_t)sg * blk]);
     const int64_t g = col_base(v.imode, b, R, r) + v.moff[p] + m;
-    y[g] = finalize(v, op, ip + m, x[g], w);
+    cplx o = finalize(v, op, ip + m, x[g], w);
+    if (shift) o = csub(o, cmul(shift[b * R + r], x[g]));
+    y[g] = o;
   }
 }
 
@@ -529,7 +532,8 @@ __global__ __launch_bounds__(256) void k_circ_finish_fft3(
     const cplx* __restrict__ part, int64_t blk, int npad, int RC, const int32_t* __restrict__ dgrp,
     const int32_t* __restrict__ drow, const int32_t* __restrict__ gnseg,
     const int64_t* __restrict__ gbase, const int32_t* __restrict__ active,
-    const cplx* __restrict__ wh, const int32_t* __restrict__ con) {
+    const cplx* __restrict__ wh, const int32_t* __restrict__ con,
+    const cplx* __restrict__ shift) {
   __shared__ cplx buf[2 * CF3_L * CF3_R];
   __shared__ cplx tw[CF3_L];
   const int p = blockIdx.x, tid = threadIdx.x;
@@ -566,7 +570,9 @@ __global__ __launch_bounds__(256) void k_circ_finish_fft3(
     cplx w = res[m * CF3_R + rr];
     for (int sg = 0; sg < ns; ++sg) w = cadd(w, pr[(int64_t)sg * blk]);
     const int64_t g = col_base(v.imode, b, R, r) + v.moff[p] + m;
-    y[g] = finalize(v, op, ip + m, x[g], w);
+    cplx o = finalize(v, op, ip + m, x[g], w);
+    if (shift) o = csub(o, cmul(shift[b * R + r], x[g]));
+    y[g] = o;
   }
 }
 
@@ -659,13 +665,13 @@ int circ_launch(mudiff_ctx* h, int R, const cplx* z, cplx* zh, cplx* wh, const i
 int circ_finish(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, const cplx* part, int64_t blk,
                 int npad, int RC, const int32_t* dgrp, const int32_t* drow, const int32_t* gnseg,
                 const int64_t* gbase, const int32_t* active, const cplx* wh, const int32_t* con,
-                const int32_t* con_h, hipStream_t s) {
+                const int32_t* con_h, const cplx* shift, hipStream_t s) {
   bool fft, dft;
   circ_kinds(h, con_h, &fft, &dft);
   if (fft) {
     hipLaunchKernelGGL(k_circ_finish_fft3, dim3((unsigned)h->M_all, (unsigned)((R + CF3_R - 1) / CF3_R)),
                        dim3(256), 0, s, h->dv, R, x, y, op, part, blk, npad, RC, dgrp, drow, gnseg,
-                       gbase, active, wh, con);
+                       gbase, active, wh, con, shift);
     HIP_TRY(hipGetLastError());
   }
   bool direct = dft;  // instances outside the form: partial sums only, in the MFMA finish
@@ -679,14 +685,15 @@ int circ_finish(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, const cplx
   const int tmw = (tm + wpc - 1) / wpc;
   typedef void (*fn_t)(DevView, int, const cplx*, cplx*, int, const cplx*, int64_t, int, int,
                        const int32_t*, const int32_t*, const int32_t*, const int64_t*, const int32_t*,
-                       const cplx*, const int32_t*, int);
+                       const cplx*, const int32_t*, const cplx*, int);
   static const fn_t fin[5] = {nullptr, k_circ_finish_mfma<1>, k_circ_finish_mfma<2>, k_circ_finish_mfma<3>,
                               k_circ_finish_mfma<4>};
   if (tm < 1 || tm > 4 || Lmax > 128) return fail(MUDIFF_ERR_INVALID, "circulant form: orders out of range");
   const size_t lds = (128 + (size_t)CT_R * std::max(Lmax, 2 * h->Nmax + 2)) * 16;
   const int ncol = 8 * (4 / wpc);
   hipLaunchKernelGGL(fin[tmw], dim3((unsigned)h->M_all, (unsigned)((R + ncol - 1) / ncol)), dim3(256), lds, s,
-                     h->dv, R, x, y, op, part, blk, npad, RC, dgrp, drow, gnseg, gbase, active, wh, con, wpc);
+                     h->dv, R, x, y, op, part, blk, npad, RC, dgrp, drow, gnseg, gbase, active, wh, con, shift,
+                     wpc);
   HIP_TRY(hipGetLastError());
   return MUDIFF_OK;
 }

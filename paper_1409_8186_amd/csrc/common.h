@@ -371,8 +371,6 @@ int apply_operator_split(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, c
                          int32_t* counters, const int32_t* active, hipStream_t s,
                          bool* pending);
 size_t apply_scratch_bytes(mudiff_ctx* h, int R);
-// True when the R-column apply runs on the FP64-MFMA work queue (R >= 8, N_p <= 31).
-bool apply_uses_mfma(const mudiff_ctx* h, int R);
 // Forget where the MFMA schedule was last uploaded: the next apply uploads it
 // into its scratch again.  Every entry point that takes an apply scratch from
 // the caller calls this first, so a buffer whose memory was used for anything

@@ -1642,6 +1642,137 @@ __global__ __launch_bounds__(GS_THREADS) void k_ss_update(GState s, int j0, int 
   }
 }
 
+// Wide variants of the two sweeps, for many chunks (many right-hand sides):
+// there the sweeps are bound by HBM bandwidth, and k_ss_dots, which re-reads
+// the block's new vectors once per basis vector, moves (j0 + 1 + sb) sb
+// vectors through L2 per pass.  k_ss_dots_w stages a tile of SSW_TR rows of
+// all nl = j0 + 1 + sb vectors in LDS (rows padded to SSW_TR + 1 against bank
+// conflicts); each thread accumulates a block of 2 basis vectors x 4 new
+// vectors over every ks-th row of the tile (ks row groups fill the
+// workgroup), and the row groups' sums are added in group order at the end:
+// every vector is read once from HBM.  k_ss_update_w: one thread per row
+// (SSW_RB rows per workgroup), the whole sweep of that row in registers.
+#define SSW_TR 32
+#define SSW_RB 1024
+#define SSW_MIN_CHUNKS 256  // chunks from which the wide variants run
+
+__global__ __launch_bounds__(GS_THREADS) void k_ss_dots_w(GState s, int j0, int sb) {
+  extern __shared__ cplx tile[];  // [nl][SSW_TR + 1], then the row groups' sums
+  int c, len;
+  int64_t o;
+  const int gi = decode_chunk(s, &c, &len, &o);
+  if (!s.inner[c]) return;
+  const int t = threadIdx.x, ld = SSW_TR + 1;
+  const int nl = j0 + 1 + sb;
+  const int nkb = (sb + 3) >> 2, nblk = ((nl + 1) >> 1) * nkb;  // <= 40 * 4 blocks
+  const int ks = max(1, GS_THREADS / nblk);
+  const int blk = t % nblk, g = t / nblk;
+  const bool act = g < ks;
+  const int l0 = 2 * (blk / nkb), k0 = 4 * (blk - (blk / nkb) * nkb);
+  cplx acc[2][4];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = cmk(0.0, 0.0);
+  const cplx* vb = s.V + o;
+  for (int r0 = 0; r0 < len; r0 += SSW_TR) {
+    const int tr = min(SSW_TR, len - r0);
+    __syncthreads();  // the previous tile is consumed
+    for (int e0 = t; e0 < nl * SSW_TR; e0 += 8 * GS_THREADS) {
+      cplx v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * GS_THREADS, l = e / SSW_TR, r = e - l * SSW_TR;
+        v[u] = (l < nl && r < tr) ? vb[(int64_t)l * s.NT + r0 + r] : cmk(0.0, 0.0);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * GS_THREADS, l = e / SSW_TR, r = e - l * SSW_TR;
+        if (l < nl) tile[l * ld + r] = v[u];
+      }
+    }
+    __syncthreads();
+    if (act) {
+      for (int r = g; r < tr; r += ks) {
+        cplx a[2], b[4];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) a[u] = l0 + u < nl ? tile[(l0 + u) * ld + r] : cmk(0.0, 0.0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) b[v] = k0 + v < sb ? tile[(j0 + 1 + k0 + v) * ld + r] : cmk(0.0, 0.0);
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) cmacc(acc[u][v], a[u], b[v]);
+      }
+    }
+  }
+  __syncthreads();  // the tile buffer now holds the row groups' sums [g][blk][8]
+  if (act) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) tile[(g * nblk + blk) * 8 + u * 4 + v] = acc[u][v];
+  }
+  __syncthreads();
+  cplx* part = s.P2 + (int64_t)gi * s.sl2;
+  for (int e = t; e < nblk * 8; e += GS_THREADS) {
+    const int bq = e >> 3, q = e & 7;
+    const int l = 2 * (bq / nkb) + (q >> 2), k = 4 * (bq - (bq / nkb) * nkb) + (q & 3);
+    if (l >= nl || k >= sb) continue;
+    cplx a = cmk(0.0, 0.0);
+    for (int gg = 0; gg < ks; ++gg) a = cadd(a, tile[(gg * nblk + bq) * 8 + q]);
+    part[l * s.ss + k] = a;
+  }
+}
+
+__global__ __launch_bounds__(GS_THREADS) void k_ss_update_w(GState s, int j0, int sb, int pass) {
+  __shared__ cplx Cl[SS_CL];
+  __shared__ cplx Ri[SS_MAX * SS_MAX];
+  int c, len;
+  int64_t o;
+  decode_chunk(s, &c, &len, &o);
+  if (!s.inner[c]) return;
+  const int t = threadIdx.x, ss = s.ss;
+  const int rb = (int)blockIdx.y * SSW_RB;
+  if (rb >= len) return;
+  const cplx* Cg = s.sC + ((int64_t)c * 2 + pass) * s.sl2;
+  ss_stage(Cl, (j0 + 1) * sb, t, GS_THREADS, [&](int e) { return Cg[(e / sb) * ss + e % sb]; });
+  const cplx* Rig = s.sRi + (int64_t)c * ss * ss;
+  ss_stage(Ri, sb * sb, t, GS_THREADS, [&](int e) { return Rig[(e / sb) * ss + e % sb]; });
+  __syncthreads();
+  const int re = min(len, rb + SSW_RB);
+  for (int r = rb + t; r < re; r += GS_THREADS) {
+    cplx acc[SS_MAX];
+#pragma unroll
+    for (int k = 0; k < SS_MAX; ++k) acc[k] = cmk(0.0, 0.0);
+    const cplx* vr = s.V + o + r;
+    for (int l0 = 0; l0 <= j0; l0 += 8) {
+      cplx v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = l0 + u <= j0 ? vr[(int64_t)(l0 + u) * s.NT] : cmk(0.0, 0.0);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (l0 + u > j0) break;
+#pragma unroll
+        for (int k = 0; k < SS_MAX; ++k)
+          if (k < sb) cmac(acc[k], v[u], Cl[(l0 + u) * sb + k]);
+      }
+    }
+    cplx w[SS_MAX];
+    cplx* wb = s.V + (int64_t)(j0 + 1) * s.NT + o + r;
+#pragma unroll
+    for (int k = 0; k < SS_MAX; ++k) w[k] = k < sb ? csub(wb[(int64_t)k * s.NT], acc[k]) : cmk(0.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < SS_MAX; ++k) {
+      cplx a = cmk(0.0, 0.0);
+#pragma unroll
+      for (int q = 0; q <= k; ++q)
+        if (k < sb) cmac(a, w[q], Ri[q * sb + k]);
+      if (k < sb) wb[(int64_t)k * s.NT] = a;
+    }
+  }
+}
+
 // Per column, after the second pass: the coefficients of the Newton vectors
 // (C = C1 + C2 R1, R = R2 R1), the new Hessenberg columns (all sb, or up to the
 // first dropped pivot of R and one more), written raw, then each through the
@@ -2207,6 +2338,8 @@ static int enqueue_sscycle(GmresRun& G, bool host_checks) {
   const unsigned cb = (unsigned)((s.C + 63) / 64);
   const unsigned nb = (unsigned)G.L.n_chunks;
   const unsigned ry = (unsigned)((G.ch + SS_UR - 1) / SS_UR);
+  const bool wide = nb >= SSW_MIN_CHUNKS;  // bandwidth-bound sweeps (many right-hand sides)
+  const unsigned ryw = (unsigned)((G.ch + SSW_RB - 1) / SSW_RB);
   hipLaunchKernelGGL(k_scale_v0, dim3(eb), dim3(256), 0, st, s, s.NT, G.d_rowcol);
   HIP_TRY(hipGetLastError());
   for (int j0 = 0; j0 < s.m; j0 += s.ss) {
@@ -2218,11 +2351,20 @@ static int enqueue_sscycle(GmresRun& G, bool host_checks) {
     }
     const unsigned nvg = (unsigned)((j0 + 1 + sb + GS_WAVES - 1) / GS_WAVES);
     for (int pass = 0; pass < 2; ++pass) {
-      hipLaunchKernelGGL(k_ss_dots, dim3(nb, nvg), dim3(GS_THREADS), 0, st, s, j0, sb);
+      if (wide) {
+        const int nl = j0 + 1 + sb;
+        const size_t lds = (size_t)std::max(nl * (SSW_TR + 1), GS_THREADS * 8) * 16;
+        hipLaunchKernelGGL(k_ss_dots_w, dim3(nb), dim3(GS_THREADS), lds, st, s, j0, sb);
+      } else {
+        hipLaunchKernelGGL(k_ss_dots, dim3(nb, nvg), dim3(GS_THREADS), 0, st, s, j0, sb);
+      }
       hipLaunchKernelGGL(k_ss_red, dim3((unsigned)s.C, (unsigned)(((j0 + 1 + sb) * sb + GS_THREADS - 1) / GS_THREADS)),
                          dim3(GS_THREADS), 0, st, s, j0, sb, pass);
       hipLaunchKernelGGL(k_ss_chol, dim3((unsigned)s.C), dim3(64), 0, st, s, j0, sb, pass);
-      hipLaunchKernelGGL(k_ss_update, dim3(nb, ry), dim3(GS_THREADS), 0, st, s, j0, sb, pass);
+      if (wide)
+        hipLaunchKernelGGL(k_ss_update_w, dim3(nb, ryw), dim3(GS_THREADS), 0, st, s, j0, sb, pass);
+      else
+        hipLaunchKernelGGL(k_ss_update, dim3(nb, ry), dim3(GS_THREADS), 0, st, s, j0, sb, pass);
     }
     hipLaunchKernelGGL(k_ss_hess, dim3((unsigned)s.C), dim3(SS_HT), 0, st, s, j0, sb);
     HIP_TRY(hipGetLastError());
@@ -2297,8 +2439,6 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
     return fail(MUDIFF_ERR_INVALID, "s-step size must be 2.." + std::to_string(SS_MAX) +
                                         " with restart <= " + std::to_string(SS_MREST) +
                                         ", not with MUDIFF_BLOCK");
-  if (ss > 0 && apply_uses_mfma(h, R))
-    return fail(MUDIFF_ERR_INVALID, "s-step GMRES runs on the one-lane and generic applies (R < 8 or N_p > 31)");
   GLayout L = glayout(h, R, restart, sb, ss);
   if (!workspace) return fail(MUDIFF_ERR_INVALID, "workspace is NULL");
   apply_forget_upload(h);

@@ -604,7 +604,8 @@ __global__ void k_apply_mfma_finish(DevView v, int R, const cplx* __restrict__ x
                                     const int64_t* __restrict__ gbase,
                                     const int32_t* __restrict__ active,
                                     const cplx* __restrict__ wh,
-                                    const int32_t* __restrict__ con) {
+                                    const int32_t* __restrict__ con,
+                                    const cplx* __restrict__ shift) {
   const int64_t total = (int64_t)R * v.N_all;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= total) return;
@@ -643,7 +644,9 @@ __global__ void k_apply_mfma_finish(DevView v, int R, const cplx* __restrict__ x
     }
     w = cadd(w, acc);
   }
-  y[g] = finalize(v, op, i, x[g], w);
+  cplx o = finalize(v, op, i, x[g], w);
+  if (shift) o = csub(o, cmul(shift[b * R + r], x[g]));
+  y[g] = o;
 }
 
 // R at and above which the MFMA kernel applies the operator (N_p <= 31).
@@ -655,7 +658,6 @@ __global__ void k_apply_mfma_finish(DevView v, int R, const cplx* __restrict__ x
 static bool use_mfma(const mudiff_ctx* h, int R) {
   return R >= MFMA_MIN_R && h->Nmax <= 31 && h->mfma_enabled && h->T_all < ((int64_t)1 << 31);
 }
-bool apply_uses_mfma(const mudiff_ctx* h, int R) { return use_mfma(h, R); }
 
 int circ_variant(int R);
 std::vector<int> circ_variants(int R);
@@ -664,7 +666,7 @@ void circ_var_dims(int var, int* bm, int* bn, int* bk, int* db, int* nt);
 int circ_finish(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, const cplx* part, int64_t blk,
                 int npad, int RC, const int32_t* dgrp, const int32_t* drow, const int32_t* gnseg,
                 const int64_t* gbase, const int32_t* active, const cplx* wh, const int32_t* con,
-                const int32_t* con_h, hipStream_t s);
+                const int32_t* con_h, const cplx* shift, hipStream_t s);
 int circ_launch(mudiff_ctx* h, int R, const cplx* z, cplx* zh, cplx* wh, const int32_t* citems,
                 int n_citems, int var, const int32_t* con, const int32_t* con_h,
                 const int32_t* active, hipStream_t s);
@@ -937,7 +939,7 @@ static mf_fn mf_select(int mt, int th, int zk, int tk) {
 #undef MF_TK3
 
 static int mfma_launch(mudiff_ctx* h, const MfmaSched& S, const cplx* x, cplx* y, int op,
-                       const int32_t* active, hipStream_t s) {
+                       const int32_t* active, hipStream_t s, const cplx* shift = nullptr) {
   size_t off[MF_NOFF];
   mfma_scratch_layout(h, S, off);
   char* base = (char*)S.dev_base;
@@ -992,7 +994,7 @@ static int mfma_launch(mudiff_ctx* h, const MfmaSched& S, const cplx* x, cplx* y
     rc = circ_finish(h, S.R, x, y, op, (const cplx*)part, S.blk, S.npad, RC,
                      (const int32_t*)(base + off[2]), (const int32_t*)(base + off[8]),
                      (const int32_t*)(base + off[4]), (const int64_t*)(base + off[5]), active,
-                     (const cplx*)wh, con, S.con.data(), s);
+                     (const cplx*)wh, con, S.con.data(), shift, s);
     prof_mark(h, s, 5);
     return rc;
   }
@@ -1001,7 +1003,7 @@ static int mfma_launch(mudiff_ctx* h, const MfmaSched& S, const cplx* x, cplx* y
                      h->dv, S.R, x, y, op, (const cplx*)part, S.blk, S.npad, RC,
                      (const int32_t*)(base + off[2]), (const int32_t*)(base + off[8]),
                      (const int32_t*)(base + off[4]), (const int64_t*)(base + off[5]), active,
-                     (const cplx*)wh, con);
+                     (const cplx*)wh, con, shift);
   HIP_TRY(hipGetLastError());
   prof_mark(h, s, 5);
   return MUDIFF_OK;
@@ -1401,10 +1403,9 @@ int apply_operator_split(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, c
 int apply_operator(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, cplx* part,
                    int32_t* counters, const int32_t* active, hipStream_t s, const cplx* shift) {
   if (use_mfma(h, R)) {
-    if (shift) return fail(MUDIFF_ERR_INVALID, "shifted applies run on the one-lane and generic kernels only");
     int st = mfma_prepare(h, R, nullptr, nullptr, (char*)part, s);  // no-op when current
     if (st != MUDIFF_OK) return st;
-    return mfma_launch(h, h->mfma_sched, x, y, op, active, s);
+    return mfma_launch(h, h->mfma_sched, x, y, op, active, s, shift);
   }
   int st = ensure_plan(h, s);
   if (st != MUDIFF_OK) return st;

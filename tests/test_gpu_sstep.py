@@ -4,8 +4,11 @@ one-vector process, each cycle builds its basis ss Newton vectors at a time
 in one block.  The iterates are those of GMRES up to rounding, so every column
 must equal its dense LU solution (the oracle) to the parity bar, 1e-10, at
 tol 1e-12, with nearly the iteration count of the one-vector solver, on the
-one-lane apply (uniform N_p, R = 1) and the generic apply (uneven N_p, R = 3),
-eager and replayed as graphs, with and without the preconditioner."""
+one-lane apply (uniform N_p, R = 1), the generic apply (uneven N_p, R = 3) and
+the multi-right-hand-side applies (FP64-MFMA direct form, R = 8; circulant form,
+R = 13), eager and replayed as graphs, with and without the preconditioner."""
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -97,9 +100,80 @@ def test_sstep_generic_path_graph_and_options(P):
     assert rel(ps.split(rho3, 3)[0].cpu().numpy(), _lu(cs, betas[0])) < 1e-10
 
 
+def test_sstep_mfma_direct_matches_lu(P):
+    """R = 8 on the FP64-MFMA direct form: the shift is applied in its epilogue;
+    every column equals LU and needs about the lockstep solver's iterations."""
+    cl = _dense_uniform()
+    R = 8
+    betas = [synth.uniform_angles(R) + 0.05]
+    pr = P.from_cluster(cl)
+    say("s-step MFMA direct form")
+    _, flag1, _, it1, _ = pr.gmres(betas=betas, restart=30, tol=1e-12, maxit=5000)
+    rho, flag, relres, iters, _ = pr.gmres(betas=betas, restart=30, tol=1e-12, maxit=5000, sstep=10)
+    assert pr.apply_config(R)["kind"] == "mfma"
+    n1, n = it1.cpu().numpy(), iters.cpu().numpy()
+    say("  iterations: lockstep", n1.tolist(), "s-step", n.tolist())
+    assert torch.all(flag1 == 0) and torch.all(flag == 0) and torch.all(relres <= 1e-12)
+    assert n.min() > 60
+    assert np.abs(n - n1).max() <= max(3, int(n1.max()) // 50)
+    assert rel(pr.split(rho, R)[0].cpu().numpy(), _lu(cl, betas[0])) < 1e-10
+
+
+def test_sstep_many_columns_wide_sweeps(P):
+    """R = 32 (320 Gram-Schmidt chunks): the sweeps run as their wide variants
+    (LDS-staged row tiles, one thread per row); LU parity for every column,
+    the lockstep solver's iterations, graph replays equal to the eager solve."""
+    cl = _dense_uniform()
+    R = 32
+    betas = [synth.uniform_angles(R) + 0.02]
+    pr = P.from_cluster(cl)
+    say("s-step wide sweeps, R", R)
+    _, _, _, it1, _ = pr.gmres(betas=betas, restart=30, tol=1e-12, maxit=5000)
+    rho, flag, relres, iters, _ = pr.gmres(betas=betas, restart=30, tol=1e-12, maxit=5000, sstep=15)
+    n1, n = it1.cpu().numpy(), iters.cpu().numpy()
+    say("  iterations: lockstep", int(n1.max()), "s-step", int(n.max()), int(n.min()))
+    assert torch.all(flag == 0) and torch.all(relres <= 1e-12)
+    assert n.min() > 60
+    assert np.abs(n - n1).max() <= max(3, int(n1.max()) // 50)
+    ref = _lu(cl, betas[0])
+    assert rel(pr.split(rho, R)[0].cpu().numpy(), ref) < 1e-10
+    rho_g, flag_g, _, it_g, _ = pr.gmres(betas=betas, restart=30, tol=1e-12, maxit=5000, sstep=15,
+                                         graph=True)
+    torch.cuda.synchronize()
+    assert torch.equal(it_g, iters) and torch.equal(flag_g, flag) and torch.equal(rho_g, rho)
+
+
+def test_sstep_circulant_graph_matches_lu(P):
+    """Two instances in the circulant form at R = 13 (ragged 8-column tiles),
+    restart 22 with blocks of 5 (a ragged last block of 2): LU parity for every
+    column, graph replays equal to the eager solve bit for bit."""
+    cls = [synth.small_random(501, 30, 0.3, 1.0, 3.6 * math.sqrt(30), 0.1, 6.0, 4),
+           synth.small_random(502, 18, 0.2, 0.8, 16.0, 0.1, 9.0, 3)]
+    R = 13
+    betas = np.stack([synth.uniform_angles(R), synth.uniform_angles(R) + 0.05])
+    pr = P.from_clusters(cls, circulant=True)
+    pr.set_circulant(R, 1)
+    say("s-step circulant form")
+    _, _, _, it1, _ = pr.gmres(betas=betas, restart=22, tol=1e-12, maxit=3000)
+    rho, flag, _, iters, _ = pr.gmres(betas=betas, restart=22, tol=1e-12, maxit=3000, sstep=5)
+    assert pr.apply_config(R)["kind"] == "circulant"
+    n1, n = it1.cpu().numpy(), iters.cpu().numpy()
+    say("  iterations: lockstep", n1.tolist(), "s-step", n.tolist())
+    assert torch.all(flag == 0)
+    assert n.max() > 44  # s-step cycles ran
+    assert np.abs(n - n1).max() <= max(3, int(n1.max()) // 50)
+    for b, (c, Y) in enumerate(zip(cls, pr.split(rho, R))):
+        assert rel(Y.cpu().numpy(), _lu(c, betas[b])) < 1e-10, b
+    for rep in range(3):
+        rho_g, flag_g, _, it_g, _ = pr.gmres(betas=betas, restart=22, tol=1e-12, maxit=3000, sstep=5,
+                                             graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(it_g, iters) and torch.equal(flag_g, flag) and torch.equal(rho_g, rho), rep
+
+
 def test_sstep_first_cycle_only_and_invalid(P):
     """A problem that converges inside the first cycle never reaches the s-step
-    cycles; invalid sizes and the multi-right-hand-side apply are refused."""
+    cycles; invalid sizes are refused."""
     cl = synth.small_random(63, 4, 0.4, 0.6, 10.0, 0.5, 2.0, 2)
     pr = P.from_cluster(cl)
     rho, flag, _, iters, _ = pr.gmres(betas=[[0.5]], restart=50, tol=1e-12, maxit=2000, sstep=8)
@@ -110,6 +184,3 @@ def test_sstep_first_cycle_only_and_invalid(P):
         args = {"restart": 30, **kw}
         with pytest.raises(_lib.MudiffError):
             pr.gmres(betas=[[0.5]], tol=1e-8, maxit=10, **args)
-    pm = P.from_cluster(_dense_uniform(M=12, N=6))
-    with pytest.raises(_lib.MudiffError):  # R = 8: the FP64-MFMA apply
-        pm.gmres(betas=[synth.uniform_angles(8)], restart=30, tol=1e-8, maxit=10, sstep=8)

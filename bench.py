@@ -395,9 +395,13 @@ def other_workload(args):
     target = PT.farfield(rho_t, th, R=betas.shape[1]).reshape(betas.shape[0], -1)
     PT.close()
 
+    from paper_1409_8186_amd import _lib as L
+    gflags = (L.SSTEP | L.sstep_size(args.grad_sstep)) if args.grad_sstep > 0 else 0
+
     def step(idx):
         P = Problem.from_clusters([bases[i] for i in idx], circulant=True)
-        out = P.grad(betas[idx], th, target[idx].reshape(-1), restart=50, tol=1e-8, maxit=20000)
+        out = P.grad(betas[idx], th, target[idx].reshape(-1), restart=50, tol=1e-8, maxit=20000,
+                     flags=gflags)
         P.close()
         return out
     allidx = list(range(len(bases)))
@@ -429,7 +433,9 @@ def other_workload(args):
                                    "k=8, N_p=ceil(8a)+8, 64 incidences x 64 receivers, forward + "
                                    "adjoint GMRES(50) to 1e-8, gradient w.r.t. 200 center "
                                    "coordinates, 100 radii and k per config",
-                       "configs_per_step": len(bases)},
+                       "configs_per_step": len(bases),
+                       "solver": (f"s-step GMRES(50), s = {args.grad_sstep}" if args.grad_sstep > 0
+                                  else "lockstep GMRES(50)")},
             "apply_ms": t_app * 1e3, "phases_ms": ph,
             "roofline": roof,
             "one_at_a_time": {"sample_configs": 4, "grads_per_s": 4 / t1,
@@ -977,6 +983,8 @@ def main():
                     choices=["multi_rhs", "multi_rhs_block", "one_rhs", "uneven", "differentiation", "dort",
                              "formulations", "nearfield", "penetrable"],
                     help="multi_rhs (default bench line) or a documentation run of another workload")
+    ap.add_argument("--grad-sstep", type=int, default=10, metavar="S",
+                    help="differentiation workload: s-step size of the gradient's solves (0: one-vector)")
     ap.add_argument("--sstep-sizes", default="15,10", metavar="S,S,...",
                     help="multi_rhs_block workload: s-step sizes to run next to lockstep")
     ap.add_argument("--block-sizes", default="16,8", metavar="S,S,...",

@@ -485,6 +485,8 @@ size_t mudiff_grad_workspace_size(mudiff_t h, int R, int n_rec, int restart, int
  *   target     device complex128 [B][R][n_rec]
  *   loss       device double [B]
  *   d_centers  device double [M_tot][2];  d_radii [M_tot];  d_k [B]
+ * flags: MUDIFF_GRAPH and MUDIFF_SSTEP (with MUDIFF_SSTEP_SIZE) apply to both
+ * solves as in mudiff_gmres; mudiff_grad_workspace_size takes the same flags.
  * Returns MUDIFF_ERR_NOT_CONVERGED (outputs undefined) if a solve fails to
  * reach tol within maxit. */
 int mudiff_grad(mudiff_t h, int R, const double* beta, int n_rec, const double* theta_rec,

@@ -427,6 +427,10 @@ struct GradLayout {
   int64_t OP;
 };
 
+// Flags of mudiff_grad that its two solves take over: graph replay and the
+// s-step variant with its size.
+#define GRAD_SOLVE_FLAGS (MUDIFF_GRAPH | MUDIFF_SSTEP | MUDIFF_SSTEP_SIZE(0xff))
+
 GradLayout grad_layout(mudiff_ctx* h, int R, int n_rec, int restart, int flags) {
   GradLayout L{};
   const int64_t NT = (int64_t)R * h->N_all, C = (int64_t)h->B * R;
@@ -467,7 +471,7 @@ GradLayout grad_layout(mudiff_ctx* h, int R, int n_rec, int restart, int flags) 
 
 extern "C" size_t mudiff_grad_workspace_size(mudiff_t h, int R, int n_rec, int restart, int flags) {
   if (!h || R < 1 || n_rec < 1 || restart < 1 || restart > MUDIFF_MAX_RESTART) return 0;
-  return grad_layout(h, R, n_rec, restart, flags & MUDIFF_GRAPH).total;
+  return grad_layout(h, R, n_rec, restart, flags & GRAD_SOLVE_FLAGS).total;
 }
 
 static int solve_ok(const int32_t* dflag, int C, hipStream_t s, bool* ok) {
@@ -491,7 +495,7 @@ extern "C" int mudiff_grad(mudiff_t h, int R, const double* beta, int n_rec, con
   if (h->dv.op_col) return fail(MUDIFF_ERR_INVALID, "the gradient is for the single-layer EFIE; reset the operator first");
   if (flags & MUDIFF_POINT_SOURCE) return fail(MUDIFF_ERR_INVALID, "the gradient is for plane-wave incidence");
   apply_forget_upload(h);
-  const int gflags = flags & MUDIFF_GRAPH;
+  const int gflags = flags & GRAD_SOLVE_FLAGS;
   GradLayout L = grad_layout(h, R, n_rec, restart, gflags);
   if (!workspace) return fail(MUDIFF_ERR_INVALID, "workspace is NULL");
   if (ws_bytes < L.total) return fail(MUDIFF_ERR_NOMEM, "grad workspace needs " + std::to_string(L.total) + " bytes");

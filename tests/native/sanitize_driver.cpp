@@ -503,14 +503,16 @@ static void gpu_circulant(std::mt19937_64& g) {
     EXPECT(n == 0, "second profile end %d", n);
   }
 
-  step("mixed batch: lockstep GMRES, circulant form, eager then graph");
+  step("mixed batch: lockstep, block and s-step GMRES, circulant form, eager then graph");
   {
     const int R = 8;
     std::vector<double> beta((size_t)b.B() * R);
     for (size_t i = 0; i < beta.size(); ++i) beta[i] = 0.37 * (double)i;
     double* betad = dev.put(beta);
-    std::vector<int32_t> it0;
-    for (int flags : {0, (int)MUDIFF_GRAPH}) {
+    std::vector<int32_t> it0, its0;
+    const int ssf = (int)(MUDIFF_SSTEP | MUDIFF_SSTEP_SIZE(5));
+    for (int flags : {0, (int)MUDIFF_GRAPH, (int)(MUDIFF_BLOCK | MUDIFF_BLOCK_SIZE(4)), ssf,
+                      ssf | (int)MUDIFF_GRAPH}) {
       const size_t ws = mudiff_gmres_workspace_size(H.h, R, 30, flags);
       void* w = dev.get(ws);
       void* rho = dev.get((size_t)R * H.total * 16);
@@ -521,12 +523,14 @@ static void gpu_circulant(std::mt19937_64& g) {
                           nullptr, nullptr),
              MUDIFF_OK);
       HIPCHK(hipDeviceSynchronize());
-      for (int32_t f : fetch<int32_t>(fl, b.B() * R)) EXPECT(f == 0, "gmres flag %d", f);
+      for (int32_t f : fetch<int32_t>(fl, b.B() * R)) EXPECT(f == 0, "gmres flag %d (flags %d)", f, flags);
       const auto its = fetch<int32_t>(it, b.B() * R);
-      if (it0.empty())
-        it0 = its;
+      std::vector<int32_t>& ref = (flags & MUDIFF_SSTEP) ? its0 : it0;
+      if (flags & MUDIFF_BLOCK) continue;
+      if (ref.empty())
+        ref = its;
       else
-        EXPECT(its == it0, "graph replay iteration counts");
+        EXPECT(its == ref, "graph replay iteration counts (flags %d)", flags);
     }
   }
 }

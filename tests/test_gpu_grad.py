@@ -108,3 +108,29 @@ def test_autograd_function(P):
     assert rel(centers.grad.cpu().numpy(), dc * wi[:, None]) < 1e-12
     assert rel(radii.grad.cpu().numpy(), da * wi) < 1e-12
     assert rel(k.grad.cpu().numpy(), dk * np.array([0.7, -1.3])) < 1e-12
+
+
+def test_grad_sstep_solves(P):
+    """The forward and adjoint solves as s-step GMRES (flags MUDIFF_SSTEP with
+    size 4, restart 8, so that several s-step cycles run), two instances of 8
+    incidences (the FP64-MFMA apply): the oracle's adjoint gradient to 1e-10."""
+    from paper_1409_8186_amd import _lib as L
+    cases = [_case(70 + i, M=5 + i, R=8, n_rec=6) for i in range(2)]
+    cls = [c for c, _ in cases]
+    pr = P.from_clusters(cls)
+    betas = np.stack([c.betas for c in cls])
+    tg = np.concatenate([t.reshape(-1) for _, t in cases])
+    say("grad s-step")
+    loss, dc, da, dk = pr.grad(betas, cls[0].thetas, tg, restart=8, tol=1e-13, maxit=5000,
+                               flags=L.SSTEP | L.sstep_size(4))
+    loss, dc, da, dk = (x.cpu().numpy() for x in (loss, dc, da, dk))
+    o = 0
+    for b, (c, t) in enumerate(cases):
+        l0, dc0, da0, dk0 = gradient.misfit_grad(c.centers, c.radii, c.n_modes, c.k, c.betas,
+                                                 c.thetas, t)
+        assert abs(loss[b] - l0) <= 1e-10 * l0
+        g = np.concatenate([dc[o:o + c.M].ravel(), da[o:o + c.M], [dk[b]]])
+        g0 = np.concatenate([dc0.ravel(), da0, [dk0]])
+        say("  instance", b, "rel", rel(g, g0))
+        assert rel(g, g0) < 1e-10
+        o += c.M

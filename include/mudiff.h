@@ -426,11 +426,15 @@ size_t mudiff_gmres_workspace_size(mudiff_t h, int R, int restart, int flags);
  * With MUDIFF_SSTEP (s-step GMRES; same iterates as the one-vector process up
  * to rounding) the first cycle runs as above and gives each column s shifts,
  * the Ritz values of its Hessenberg matrix in Leja order; every later cycle
- * builds its basis s vectors at a time, v_i = (op - theta_i) v_{i-1} by s
- * operator applies back to back, then orthogonalises the s vectors at once
+ * builds its basis s vectors at a time, v_i = (op - theta_i) v_{i-1} / sigma_i
+ * (sigma_i the largest distance from theta_i to a Ritz value) by s operator
+ * applies back to back, then orthogonalises the s vectors at once
  * (classical Gram-Schmidt against the basis and Cholesky QR within, both
  * twice) and derives the s Hessenberg columns from the coefficients; each
  * column's residual estimate and stopping test still follow every column.
+ * A cycle that raises some column's true residual (a basis that lost
+ * orthogonality) is undone for that column, and the solve continues with
+ * one-vector cycles.
  * Fewer, larger reductions per step: for latency-bound sizes (one right-hand
  * side) the reductions, for bandwidth-bound ones (many right-hand sides) the
  * sweeps over the basis (two per s steps instead of two per step).  Every

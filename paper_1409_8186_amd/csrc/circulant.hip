@@ -518,7 +518,7 @@ __global__ __launch_bounds__(256) void k_circ_finish_mfma(
     for (int sg = 0; sg < ns; ++sg) w = cadd(w, pr[(int64_t)sg * blk]);
     const int64_t g = col_base(v.imode, b, R, r) + v.moff[p] + m;
     cplx o = finalize(v, op, ip + m, x[g], w);
-    if (shift) o = csub(o, cmul(shift[b * R + r], x[g]));
+    if (shift) o = affine(shift, b * R + r, o, x[g]);
     y[g] = o;
   }
 }
@@ -571,7 +571,7 @@ __global__ __launch_bounds__(256) void k_circ_finish_fft3(
     for (int sg = 0; sg < ns; ++sg) w = cadd(w, pr[(int64_t)sg * blk]);
     const int64_t g = col_base(v.imode, b, R, r) + v.moff[p] + m;
     cplx o = finalize(v, op, ip + m, x[g], w);
-    if (shift) o = csub(o, cmul(shift[b * R + r], x[g]));
+    if (shift) o = affine(shift, b * R + r, o, x[g]);
     y[g] = o;
   }
 }

@@ -264,6 +264,12 @@ __device__ __forceinline__ cplx finalize(const DevView& v, int op, int64_t i, cp
   return cadd(cmul(v.Ldiag[i], xv), cmk(-f * w.y, f * w.x));
 }
 
+// Affine epilogue of a shifted apply: alpha_c y + beta_c x, (alpha, beta) the
+// pair of column c in ab.
+__device__ __forceinline__ cplx affine(const cplx* __restrict__ ab, int c, cplx y, cplx x) {
+  return cadd(cmul(ab[2 * c], y), cmul(ab[2 * c + 1], x));
+}
+
 // Input x_n scaled by the column factor of unknown i: sqrt(a_q) J_n(k a_q)
 // for the single layer, the set operator's factor otherwise.
 __device__ __forceinline__ cplx col_scale(const DevView& v, int64_t i, cplx x) {
@@ -359,8 +365,9 @@ __device__ __forceinline__ void lane_reduce_scatter(double* val, int lane) {
 // Operator apply on R columns. `part`/`counters` come from the caller's scratch
 // (mudiff_matvec_workspace_size); counters must be zero on entry and are left
 // zero. `active` (optional, [B*R]) skips columns whose entry is 0.  `shift`
-// (optional, [B*R], one-lane and generic kernels only) subtracts shift[c] x
-// from column c of the result.
+// (optional, [B*R][2]) makes column c of the result alpha_c (op x) + beta_c x
+// with (alpha_c, beta_c) = (shift[2c], shift[2c+1]): the scaled Newton steps
+// (A - theta) x / sigma of s-step GMRES.
 int apply_operator(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, cplx* part,
                    int32_t* counters, const int32_t* active, hipStream_t s,
                    const cplx* shift = nullptr);

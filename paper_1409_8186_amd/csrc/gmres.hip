@@ -73,6 +73,11 @@ struct GState {
   int sl2;                  // partial-sum slots per chunk, (m + 1) ss
   cplx* P2;                 // [n_chunks][(m + 1) ss]
   cplx* theta;              // [ss][C] shifts
+  cplx* sab;                // [ss][C][2] (1 / sigma, -theta / sigma) of each Newton step
+  cplx* xprev;              // [NT] iterate at the start of the s-step cycle
+  cplx* vprev;              // [NT] its residual f - A x (unscaled)
+  double* rprev;            // [C] its squared norm
+  int32_t* ssbad;           // [1] set when a cycle raised a column's true residual
   cplx* sC;                 // [C][2][(m + 1) ss] projections of the two passes
   cplx* sR;                 // [C][2][ss ss] Cholesky factors of the two passes
   cplx* sRi;                // [C][ss ss] inverse of the current pass's factor
@@ -1402,15 +1407,17 @@ __global__ void k_zero_i(int32_t* p, int n) {
 // With MUDIFF_SSTEP each restart cycle after the first builds its Krylov basis
 // ss vectors at a time (s-step, or communication-avoiding, GMRES): from the
 // last orthonormal basis vector q_j the operator is applied ss times back to
-// back in the Newton form v_i = (A - theta_i) v_{i-1}, with the shifts theta_i
-// the Ritz values of the first cycle's Hessenberg matrix in Leja order (so the
-// basis stays well conditioned), and the block [v_1 .. v_ss] is then
+// back in the scaled Newton form v_i = (A - theta_i) v_{i-1} / sigma_i, with
+// the shifts theta_i the Ritz values of the first cycle's Hessenberg matrix in
+// Leja order and sigma_i = max_k |lambda_k - theta_i| over those Ritz values
+// (so the basis stays well conditioned and its norms stay near one), and the
+// block [v_1 .. v_ss] is then
 // orthogonalised at once: against q_0..q_j by classical Gram-Schmidt and within
 // itself by Cholesky QR, both applied twice (each pass one reduction over the
 // rows and one sweep; the Gram matrix of the projected block follows from the
 // unprojected one minus C^H C).  With V = [Q, Q_new] R_hat (R_hat the
 // coefficients of the v_i) and A [v_0..v_{ss-1}] = [v_0..v_ss] B (theta_i on
-// the diagonal of B, ones below), the ss new Hessenberg columns are
+// the diagonal of B, sigma_i below), the ss new Hessenberg columns are
 //   H_new = (R_hat B - [H_old R_top; 0]) R_s^{-1},
 // R_top the rows of R_hat on q_0..q_{j-1} and R_s the square block on
 // q_j..q_{j+ss-1}; they then enter the Givens update one by one, with the
@@ -1845,7 +1852,8 @@ __global__ __launch_bounds__(SS_HT) void k_ss_hess(GState s, int j0, int sb) {
   // rows q < j0 of R_hat, zero in column 0)
   for (int e = t; e < nrow * su; e += SS_HT) {
     const int r = e / su, i = e - (e / su) * su;
-    cplx y = cadd(cmul(th[(int64_t)i * s.C + c], rhat(r, i)), rhat(r, i + 1));
+    const double sg = 1.0 / s.sab[2 * ((int64_t)i * s.C + c)].x;  // sigma_i
+    cplx y = cadd(cmul(th[(int64_t)i * s.C + c], rhat(r, i)), cscale(rhat(r, i + 1), sg));
     if (r <= j0 && i >= 1) {
       cplx acc = cmk(0.0, 0.0);
       for (int q = max(0, r - 1); q < j0; ++q) cmac(acc, Ho[q * (j0 + 1) + r], Cm[q * sb + (i - 1)]);
@@ -1998,7 +2006,7 @@ struct GLayout {
   size_t bck, bckoff, btile, bP, bT, bH, bG, bRq, bRi, bhv, btau, bY, bin, brun, bsteps, bact;
   // s-step GMRES (ss > 0)
   int ss = 0;
-  size_t sP2, stheta, sC, sR, sRi;
+  size_t sP2, stheta, ssab, sxprev, svprev, srprev, ssbad, sC, sR, sRi;
 };
 
 // Block geometry of block GMRES: reduction chunks and 64-row tiles of every
@@ -2098,6 +2106,11 @@ GLayout glayout(mudiff_ctx* h, int R, int m, int sb = 0, int ss = 0) {
     L.ss = ss;
     L.sP2 = take((size_t)nck * (m + 1) * ss * 16);
     L.stheta = take((size_t)ss * C * 16);
+    L.ssab = take((size_t)ss * C * 32);
+    L.sxprev = take((size_t)NT * 16);
+    L.svprev = take((size_t)NT * 16);
+    L.srprev = take((size_t)C * 8);
+    L.ssbad = take(4);
     L.sC = take((size_t)C * 2 * (m + 1) * ss * 16);
     L.sR = take((size_t)C * 2 * ss * ss * 16);
     L.sRi = take((size_t)C * ss * ss * 16);
@@ -2327,6 +2340,42 @@ static int enqueue_bcycle(GmresRun& G, int check_every, bool host_checks) {
   return MUDIFF_OK;
 }
 
+// Guard of an s-step cycle.  Restarted GMRES never raises a column's true
+// residual (the update minimises over a space that contains zero), but a
+// Newton basis built from poor shifts can lose orthogonality so far that the
+// computed update does.  Before the cycle: the iterate, its residual and the
+// squared norm of every column that runs are saved.  After it: a column whose
+// true residual grew (by more than 1e-10 relative, far above rounding) gets
+// them back, and the flag is raised; the solve then continues with the
+// one-vector process, which cannot do that.
+__global__ void k_ss_save(GState s, int64_t nrows_total, const int32_t* __restrict__ row_col) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < s.C) s.rprev[g] = s.red[g];
+  if (g >= nrows_total) return;
+  if (!s.inner[row_col[g]]) return;
+  s.xprev[g] = s.x[g];
+  s.vprev[g] = s.V[g];
+}
+
+__device__ __forceinline__ bool ss_cycle_failed(const GState& s, int c) {
+  return s.run[c] && s.red[c] > s.rprev[c] * (1.0 + 1e-10);
+}
+
+__global__ void k_ss_guard_rows(GState s, int64_t nrows_total, const int32_t* __restrict__ row_col) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nrows_total) return;
+  if (!ss_cycle_failed(s, row_col[g])) return;
+  s.x[g] = s.xprev[g];
+  s.V[g] = s.vprev[g];
+}
+
+__global__ void k_ss_guard_cols(GState s) {  // after k_ss_guard_rows
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= s.C || !ss_cycle_failed(s, c)) return;
+  s.red[c] = s.rprev[c];
+  atomicExch(s.ssbad, 1);
+}
+
 // One restart cycle of s-step GMRES (after the first cycle has given the
 // shifts): blocks of ss Newton vectors, each orthogonalised by two
 // reduction/sweep passes and folded into the Hessenberg matrix, then the
@@ -2340,13 +2389,15 @@ static int enqueue_sscycle(GmresRun& G, bool host_checks) {
   const unsigned ry = (unsigned)((G.ch + SS_UR - 1) / SS_UR);
   const bool wide = nb >= SSW_MIN_CHUNKS;  // bandwidth-bound sweeps (many right-hand sides)
   const unsigned ryw = (unsigned)((G.ch + SSW_RB - 1) / SSW_RB);
+  const unsigned sb_rows = (unsigned)((std::max<int64_t>(s.NT, s.C) + 255) / 256);
+  hipLaunchKernelGGL(k_ss_save, dim3(sb_rows), dim3(256), 0, st, s, s.NT, G.d_rowcol);
   hipLaunchKernelGGL(k_scale_v0, dim3(eb), dim3(256), 0, st, s, s.NT, G.d_rowcol);
   HIP_TRY(hipGetLastError());
   for (int j0 = 0; j0 < s.m; j0 += s.ss) {
     const int sb = std::min(s.ss, s.m - j0);
     for (int i = 0; i < sb; ++i) {
       int rc = apply_operator(G.h, s.R, s.V + (int64_t)(j0 + i) * s.NT, s.V + (int64_t)(j0 + i + 1) * s.NT,
-                              s.op, G.apply_part, G.apply_cnt, s.inner, st, s.theta + (int64_t)i * s.C);
+                              s.op, G.apply_part, G.apply_cnt, s.inner, st, s.sab + 2 * (int64_t)i * s.C);
       if (rc != MUDIFF_OK) return rc;
     }
     const unsigned nvg = (unsigned)((j0 + 1 + sb + GS_WAVES - 1) / GS_WAVES);
@@ -2382,6 +2433,8 @@ static int enqueue_sscycle(GmresRun& G, bool host_checks) {
   if (rc != MUDIFF_OK) return rc;
   hipLaunchKernelGGL(k_resid, dim3(nb), dim3(GS_THREADS), 0, st, s, 2, 1, (const cplx*)nullptr);
   hipLaunchKernelGGL(k_col_sum, dim3(s.C), dim3(64), 0, st, s, 1);
+  hipLaunchKernelGGL(k_ss_guard_rows, dim3(eb), dim3(256), 0, st, s, s.NT, G.d_rowcol);
+  hipLaunchKernelGGL(k_ss_guard_cols, dim3(cb), dim3(64), 0, st, s);
   hipLaunchKernelGGL(k_cycle_begin, dim3(cb), dim3(64), 0, st, s);
   HIP_TRY(hipGetLastError());
   return MUDIFF_OK;
@@ -2400,6 +2453,11 @@ static int sstep_shifts(GmresRun& G) {
   HIP_TRY(hipMemcpyAsync(jd.data(), s.jdone, (size_t)C * 4, hipMemcpyDeviceToHost, G.st));
   HIP_TRY(hipStreamSynchronize(G.st));
   std::vector<cplx> th((size_t)ss * C, cmk(0.0, 0.0));
+  std::vector<cplx> ab((size_t)2 * ss * C);  // (1 / sigma, -theta / sigma)
+  for (size_t e = 0; e < (size_t)ss * C; ++e) {
+    ab[2 * e] = cmk(1.0, 0.0);
+    ab[2 * e + 1] = cmk(0.0, 0.0);
+  }
   std::vector<ritz::cd> Hc, ev;
   for (int c = 0; c < C; ++c) {
     const int n = jd[c];
@@ -2412,9 +2470,16 @@ static int sstep_shifts(GmresRun& G) {
       }
     ritz::hessenberg_eigenvalues(n, Hc.data(), n, ev);
     const std::vector<ritz::cd> lj = ritz::leja(ev, ss);
-    for (int i = 0; i < (int)lj.size(); ++i) th[(size_t)i * C + c] = cmk(lj[i].real(), lj[i].imag());
+    const std::vector<double> sg = ritz::newton_scales(ev, lj);
+    for (int i = 0; i < (int)lj.size(); ++i) {
+      const size_t e = (size_t)i * C + c;
+      th[e] = cmk(lj[i].real(), lj[i].imag());
+      ab[2 * e] = cmk(1.0 / sg[i], 0.0);
+      ab[2 * e + 1] = cmk(-lj[i].real() / sg[i], -lj[i].imag() / sg[i]);
+    }
   }
   HIP_TRY(hipMemcpyAsync(s.theta, th.data(), th.size() * 16, hipMemcpyHostToDevice, G.st));
+  HIP_TRY(hipMemcpyAsync(s.sab, ab.data(), ab.size() * 16, hipMemcpyHostToDevice, G.st));
   HIP_TRY(hipStreamSynchronize(G.st));
   return MUDIFF_OK;
 }
@@ -2434,7 +2499,7 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
   if (sb < 0)
     return fail(MUDIFF_ERR_INVALID, "block size must be 1.." + std::to_string(BG_SMAX) +
                                         " with restart * block size <= " + std::to_string(BG_MAXDIM));
-  const int ss = sstep_size_of(flags, restart);
+  int ss = sstep_size_of(flags, restart);  // 0 from a fallback to one-vector cycles on
   if (ss < 0)
     return fail(MUDIFF_ERR_INVALID, "s-step size must be 2.." + std::to_string(SS_MAX) +
                                         " with restart <= " + std::to_string(SS_MREST) +
@@ -2488,6 +2553,11 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
   s.sl2 = (restart + 1) * ss;
   s.P2 = ss ? (cplx*)(w + L.sP2) : nullptr;
   s.theta = ss ? (cplx*)(w + L.stheta) : nullptr;
+  s.sab = ss ? (cplx*)(w + L.ssab) : nullptr;
+  s.xprev = ss ? (cplx*)(w + L.sxprev) : nullptr;
+  s.vprev = ss ? (cplx*)(w + L.svprev) : nullptr;
+  s.rprev = ss ? (double*)(w + L.srprev) : nullptr;
+  s.ssbad = ss ? (int32_t*)(w + L.ssbad) : nullptr;
   s.sC = ss ? (cplx*)(w + L.sC) : nullptr;
   s.sR = ss ? (cplx*)(w + L.sR) : nullptr;
   s.sRi = ss ? (cplx*)(w + L.sRi) : nullptr;
@@ -2623,7 +2693,22 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
       if (cyc == 0) {
         if ((result = enqueue_cycle(G, 10, true)) != MUDIFF_OK) break;
         if ((result = sstep_shifts(G)) != MUDIFF_OK) break;
+        hipLaunchKernelGGL(k_zero_i, dim3(1), dim3(64), 0, st, s.ssbad, 1);
         continue;
+      }
+      int32_t bad = 0;  // a cycle raised a true residual: one-vector cycles from here on
+      HIP_TRY(hipMemcpyAsync(&bad, s.ssbad, 4, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      if (bad) {
+        ss = 0;
+        if (exec) {
+          (void)hipGraphExecDestroy(exec);
+          exec = nullptr;
+        }
+        if (graph) {
+          (void)hipGraphDestroy(graph);
+          graph = nullptr;
+        }
       }
     }
     if (sb == 0 && ss == 0 && !use_graph && s.C >= 32 && n_run * 32 <= s.C &&

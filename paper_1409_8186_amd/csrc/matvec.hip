@@ -156,7 +156,7 @@ __global__ __launch_bounds__(APPLY_THREADS) void k_apply(
       cplx w = cmk(0.0, 0.0);
       for (int k = 0; k < nslot_max; ++k) w = cadd(w, red[k * LB + m]);
       cplx o = finalize(v, op, ip + m, xp[m], w);
-      if (shift) o = csub(o, cmul(shift[b * R + r], xp[m]));
+      if (shift) o = affine(shift, b * R + r, o, xp[m]);
       yc[m] = o;
     }
     return;
@@ -184,7 +184,7 @@ __global__ __launch_bounds__(APPLY_THREADS) void k_apply(
       w = cadd(w, pr[(int64_t)k * np + m]);  // visible after the fence above
     }
     cplx o = finalize(v, op, ip + m, xp[m], w);
-    if (shift) o = csub(o, cmul(shift[b * R + r], xp[m]));
+    if (shift) o = affine(shift, b * R + r, o, xp[m]);
     yc[m] = o;
   }
 }
@@ -297,7 +297,7 @@ __global__ void k_apply_finish(DevView v, int R, const cplx* __restrict__ x, cpl
   const int64_t i = v.imode[b] + (rem - (int64_t)r * Nb);
   const cplx w = lane_chunk_sum(v, part + (int64_t)r * part_total, nchunk, partoff, b, i);
   cplx o = finalize(v, op, i, x[g], w);
-  if (shift) o = csub(o, cmul(shift[b * R + r], x[g]));
+  if (shift) o = affine(shift, b * R + r, o, x[g]);
   y[g] = o;
 }
 
@@ -645,7 +645,7 @@ __global__ void k_apply_mfma_finish(DevView v, int R, const cplx* __restrict__ x
     w = cadd(w, acc);
   }
   cplx o = finalize(v, op, i, x[g], w);
-  if (shift) o = csub(o, cmul(shift[b * R + r], x[g]));
+  if (shift) o = affine(shift, b * R + r, o, x[g]);
   y[g] = o;
 }
 

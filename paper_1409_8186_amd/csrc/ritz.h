@@ -147,4 +147,18 @@ inline std::vector<cd> leja(const std::vector<cd>& vals, int s) {
   return out;
 }
 
+// Scale of each Newton step (A - theta_i) / sigma_i: sigma_i = max_k
+// |vals_k - theta_i|, the largest factor the step applies to an eigenvector
+// the Ritz values stand for, so the scaled basis keeps norms near one.  1 when
+// that is zero or not finite.
+inline std::vector<double> newton_scales(const std::vector<cd>& vals, const std::vector<cd>& shifts) {
+  std::vector<double> sg(shifts.size(), 1.0);
+  for (size_t i = 0; i < shifts.size(); ++i) {
+    double mx = 0.0;
+    for (const cd& v : vals) mx = std::max(mx, std::abs(v - shifts[i]));
+    if (mx > 0.0 && std::isfinite(mx)) sg[i] = mx;
+  }
+  return sg;
+}
+
 }  // namespace ritz

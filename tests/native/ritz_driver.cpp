@@ -1,6 +1,7 @@
 // Reads complex upper Hessenberg matrices from stdin ("n" then n*n entries
-// "re im", column-major) and prints their eigenvalues (ritz.h) and the Leja
-// ordering of them ("s" leading values), for a comparison with numpy.
+// "re im", column-major) and prints their eigenvalues (ritz.h), the Leja
+// ordering of them ("s" leading values) and the scale of the Newton step of
+// each of those shifts, for a comparison with numpy.
 #include <cstdio>
 #include <vector>
 
@@ -21,6 +22,7 @@ int main() {
     for (const auto& z : ev) std::printf("%.17g %.17g\n", z.real(), z.imag());
     const auto lj = ritz::leja(ev, s);
     for (const auto& z : lj) std::printf("%.17g %.17g\n", z.real(), z.imag());
+    for (double v : ritz::newton_scales(ev, lj)) std::printf("%.17g\n", v);
   }
   return 0;
 }

@@ -184,3 +184,30 @@ def test_sstep_first_cycle_only_and_invalid(P):
         args = {"restart": 30, **kw}
         with pytest.raises(_lib.MudiffError):
             pr.gmres(betas=[[0.5]], tol=1e-8, maxit=10, **args)
+
+
+def test_sstep_guard_on_a_hard_instance(P):
+    """Instance 93 of the uneven workload (62 disks, N_p up to 28, 8 incidences)
+    at restart 64 with blocks of 16: the Newton basis from its first cycle's
+    Ritz values loses orthogonality, and without the cycle guard the s-step
+    solve stalls near 1e-2.  With it, a cycle that raises a true residual is
+    undone and the solve goes on with one-vector cycles: it converges like the
+    lockstep solver, and the oracle's dense operator confirms the residual."""
+    cl = synth.uneven_instances()[93]
+    R = len(cl.betas)
+    pr = P.from_cluster(cl)
+    say("s-step guard, hard instance: M", cl.M, "unknowns", cl.n_tot)
+    _, flag1, _, it1, _ = pr.gmres(betas=[cl.betas], restart=64, tol=1e-8, maxit=4000)
+    rho, flag, relres, iters, _ = pr.gmres(betas=[cl.betas], restart=64, tol=1e-8, maxit=4000, sstep=16)
+    n1, n = int(it1.max()), int(iters.max())
+    say("  iterations: lockstep", n1, "s-step", n, "relres", float(relres.max()))
+    assert torch.all(flag1 == 0) and torch.all(flag == 0)
+    assert n <= 1.2 * n1
+    L = operator.efie_matrix(cl.centers, cl.radii, cl.n_modes, cl.k)
+    D = operator.efie_diagonal(cl.radii, cl.n_modes, cl.k)
+    A = operator.preconditioned(L, D)
+    F = -rhs.planewave(cl.centers, cl.radii, cl.n_modes, cl.k, cl.betas) / D[None, :]
+    X = pr.split(rho, R)[0].cpu().numpy()
+    res = np.linalg.norm(X @ A.T - F, axis=1) / np.linalg.norm(F, axis=1)
+    say("  oracle residual of D^-1 L rho = -D^-1 U", float(res.max()))
+    assert res.max() < 1.01e-8

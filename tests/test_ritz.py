@@ -2,7 +2,8 @@
 of complex upper Hessenberg matrices against numpy.linalg.eigvals, and the Leja
 ordering of the shifts (first the value of largest modulus, then each the
 maximiser of the product of distances to those before it), checked by brute
-force.  Built with g++ (plain C++, no device code)."""
+force, and the scales of the Newton steps (largest distance from the shift to
+a Ritz value).  Built with g++ (plain C++, no device code)."""
 import os
 import subprocess
 
@@ -38,7 +39,9 @@ def _run(exe, mats, s):
         i += m
         lj = np.array([complex(*map(float, out[i + k].split())) for k in range(s)])
         i += s
-        res.append((ok, ev, lj))
+        sg = np.array([float(out[i + k]) for k in range(s)])
+        i += s
+        res.append((ok, ev, lj, sg))
     return res
 
 
@@ -78,7 +81,7 @@ def test_hessenberg_eigenvalues_match_numpy(driver):
     # a matrix with a repeated eigenvalue (Jordan-like block) and a zero subdiagonal
     J = np.diag([2.0 + 1j] * 3 + [0.5, -1.0]).astype(complex) + np.diag([1.0, 0.0, 1.0, 1.0], 1)
     mats.append(J)
-    for H, (ok, ev, _) in zip(mats, _run(driver, mats, 1)):
+    for H, (ok, ev, _, _) in zip(mats, _run(driver, mats, 1)):
         assert ok and len(ev) == H.shape[0]
         ref = np.linalg.eigvals(H)
         tol = 1e-10 * max(1.0, np.abs(ref).max())
@@ -90,7 +93,7 @@ def test_hessenberg_eigenvalues_match_numpy(driver):
 def test_leja_order(driver):
     rng = np.random.default_rng(12)
     H = np.triu(rng.normal(size=(30, 30)) + 1j * rng.normal(size=(30, 30)), -1)
-    (ok, ev, lj), = _run(driver, [H], 8)
+    (ok, ev, lj, sg), = _run(driver, [H], 8)
     assert ok
     vals = list(ev)
     k = int(np.argmax(np.abs(vals)))
@@ -99,6 +102,12 @@ def test_leja_order(driver):
         score = [np.prod([abs(z - t) for t in pick]) for z in vals]
         pick.append(vals.pop(int(np.argmax(score))))
     assert np.allclose(lj, pick, rtol=0, atol=1e-12)
+    # Newton scales: the largest distance from each shift to a Ritz value
+    assert np.allclose(sg, [max(abs(z - t) for z in ev) for t in lj], rtol=1e-14, atol=0)
     # fewer values than shifts: the order repeats
-    (_, ev2, lj2), = _run(driver, [np.array([[1.0 + 0j, 2.0], [0.0, 3.0]])], 5)
+    (_, ev2, lj2, sg2), = _run(driver, [np.array([[1.0 + 0j, 2.0], [0.0, 3.0]])], 5)
     assert np.allclose(lj2, [3, 1, 3, 1, 3])
+    assert np.allclose(sg2, [2, 2, 2, 2, 2])
+    # a single Ritz value: every distance is zero, the scale falls back to 1
+    (_, _, lj3, sg3), = _run(driver, [np.array([[0.7 + 0.2j]])], 3)
+    assert np.allclose(lj3, [0.7 + 0.2j] * 3) and np.allclose(sg3, [1, 1, 1])

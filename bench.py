@@ -179,11 +179,22 @@ def _segmented_gmres(P, betas, restart, tol, label, seg_cycles=1, max_segments=2
     return rho, flag, its, time.perf_counter() - t0
 
 
+def embed_len(n_modes):
+    """Embedding length of an instance: L_min = 2 (N' + N'') + 1 over its two
+    largest orders, or the shortest 2^i 3^j >= L_min (fast transforms) when that
+    is at most 128 and at most 1.2 L_min."""
+    n = sorted((int(v) for v in n_modes), reverse=True)
+    lmin = 2 * (n[0] + n[1]) + 1
+    smooth = min(2 ** i * 3 ** j for i in range(9) for j in range(6) if 2 ** i * 3 ** j >= lmin)
+    return smooth if smooth <= 128 and 5 * smooth <= 6 * lmin else lmin
+
+
 def circ_split(insts, R):
     """Work of one batched apply in the form the library runs it: for the
     instances in the circulant form (far-pair work >= half of the direct form's,
     the library's rule), the per-frequency products, 8 R L_b per well-separated
-    ordered pair (L_b = 2 (N' + N'') + 1), and their minimal bytes (the
+    ordered pair (L_b the embedding length the tables pick, embed_len), and
+    their minimal bytes (the
     matrices T_f, 16 L_b M_b^2, and the transformed panels in and out,
     2 x 16 R L_b M_b); and the direct form's 8 R n_p n_q for all other pairs.
     Returns (product flops, product bytes, direct flops, instances in form)."""
@@ -201,8 +212,7 @@ def circ_split(insts, R):
         np.fill_diagonal(w, 0.0)
         far = ~near
         np.fill_diagonal(far, False)
-        Ns = np.sort(N)[::-1]
-        L = 2 * int(Ns[0] + Ns[1]) + 1 if len(N) > 1 else 0
+        L = embed_len(N) if len(N) > 1 else 0
         if L > 0 and (w * far).sum() >= 0.5 * w.sum():
             n_in += 1
             prod += 8.0 * R * L * far.sum()

@@ -125,9 +125,11 @@ size_t mudiff_tables_workspace_size(int B, const int64_t* disk_off /*[host] B+1*
  * upward recurrence for Y) and per unordered pair p<q the separation symbols
  * t^{pq}_s, |s| <= N_p + N_q.
  * With MUDIFF_TABLES_CIRCULANT (the Toeplitz products through FFTs of sec. 5):
- * every instance b with M_b >= 2 gets an embedding length L_b = 2 (N' + N'') + 1,
- * N' >= N'' its two largest orders (L_b >= n_p + n_q - 1 for every pair, so
- * the circulant of length L_b holds each Toeplitz block exactly), and for every
+ * every instance b with M_b >= 2 gets an embedding length L_b >= L_min =
+ * 2 (N' + N'') + 1, N' >= N'' its two largest orders (L_b >= n_p + n_q - 1 for
+ * every pair, so the circulant of length L_b holds each Toeplitz block
+ * exactly): the shortest 2^i 3^j >= L_min (fast transforms) when that is at
+ * most 128 and at most 1.2 L_min, else L_min itself; and for every
  * frequency f < L_b the matrix
  *   T_f[p][q] = (1/L_b) sum_{|s| <= N_p+N_q} t^{pq}_s w^{f (s + N_q - N_p)},
  *   w = e^{2 pi i / L_b},

@@ -17,12 +17,14 @@
 // would spread that rounding over every mode, so they stay in the direct form.
 #include "common.h"
 
-// Instances whose length L_b is a power of 3 take radix-3 fast transforms
-// (k_circ_fwd_fft3, k_circ_finish_fft3) instead of the direct sums.
-#define CF3_R 16   // right-hand sides per workgroup
-#define CF3_L 81   // longest radix-3 length (L_b <= 125)
-__host__ __device__ __forceinline__ bool circ_pow3(int L) {
-  return L == 3 || L == 9 || L == 27 || L == 81;
+// Instances whose length L_b is 2^a 3^b take mixed radix-2/3 fast transforms
+// (k_circ_fwd_fft, k_circ_finish_fft) instead of the direct sums; the tables
+// pick such a length where it costs little (see circ_len).
+#define CF_LMAX 128
+__host__ __device__ __forceinline__ bool circ_fft_len(int L) {
+  if (L < 2 || L > CF_LMAX) return false;
+  while (L % 3 == 0) L /= 3;
+  return (L & (L - 1)) == 0;
 }
 
 // Twiddles w^j = e^{2 pi i j / L_b}, j < L_b, of every instance.
@@ -106,7 +108,7 @@ __global__ __launch_bounds__(256) void k_circ_fwd(DevView v, int R, const cplx* 
   __shared__ cplx tw[128];
   const int q = blockIdx.x, tid = threadIdx.x;
   const int b = v.inst[q];
-  if (!con[b] || circ_pow3(v.cL[b])) return;  // powers of 3: k_circ_fwd_fft3
+  if (!con[b] || circ_fft_len(v.cL[b])) return;  // 2^a 3^b: k_circ_fwd_fft
   // columns per workgroup: 32, or 16 / 8 for fewer right-hand sides (the
   // frequencies then spread over more threads)
   const int cw = R >= CF_R ? CF_R : (R > 8 ? 16 : 8);
@@ -154,21 +156,26 @@ __global__ __launch_bounds__(256) void k_circ_fwd(DevView v, int R, const cplx* 
 // and zeta = e^{-+2 pi i / 3} (sign - forward, + inverse), all read from the
 // instance's twiddle table.  The columns of a workgroup run side by side in LDS.
 
-// In-place (ping-pong) transform of the L x CF3_R block x[k][c] in LDS; returns
-// the buffer holding the result in natural order.
-__device__ cplx* fft3_lds(cplx* x, cplx* y, const cplx* tw, int L, bool inverse) {
+// In-place (ping-pong) transform of the L x CR block x[k][c] in LDS; returns
+// the buffer holding the result in natural order.  Stockham stages: radix 3
+// while 3 divides the remaining length, then radix 4, then at most one radix
+// 2; a stage of radix p maps x[(j + s m) stride + k], s < p, to
+// y[(p j + r) stride + k] (the p-point DFT times the twiddle w^{r j stride}),
+// m = n / p, then stride *= p.
+template <int CR>
+__device__ cplx* fft3_only_lds(cplx* x, cplx* y, const cplx* tw, int L, bool inverse) {
   const int tid = threadIdx.x;
   const cplx zt = tw[L / 3];
   const double sgn = inverse ? zt.y : -zt.y;  // Im(zeta)
   int stride = 1;
   for (int n = L; n > 1; n /= 3) {
     const int m = n / 3;
-    for (int e = tid; e < m * stride * CF3_R; e += blockDim.x) {
-      const int c = e % CF3_R, t = e / CF3_R;
+    for (int e = tid; e < m * stride * CR; e += blockDim.x) {
+      const int c = e % CR, t = e / CR;
       const int k = t % stride, j = t / stride;
-      const cplx a = x[((j)*stride + k) * CF3_R + c];
-      const cplx bb = x[((j + m) * stride + k) * CF3_R + c];
-      const cplx cc = x[((j + 2 * m) * stride + k) * CF3_R + c];
+      const cplx a = x[((j)*stride + k) * CR + c];
+      const cplx bb = x[((j + m) * stride + k) * CR + c];
+      const cplx cc = x[((j + 2 * m) * stride + k) * CR + c];
       const cplx sm = cadd(bb, cc), df = csub(bb, cc);
       const cplx tt = csub(a, cscale(sm, 0.5));
       const cplx id = cmk(-sgn * df.y, sgn * df.x);  // i Im(zeta) (b - c)
@@ -177,9 +184,9 @@ __device__ cplx* fft3_lds(cplx* x, cplx* y, const cplx* tw, int L, bool inverse)
         w1 = cconj(w1);
         w2 = cconj(w2);
       }
-      y[((3 * j) * stride + k) * CF3_R + c] = cadd(a, sm);
-      y[((3 * j + 1) * stride + k) * CF3_R + c] = cmul(cadd(tt, id), w1);
-      y[((3 * j + 2) * stride + k) * CF3_R + c] = cmul(csub(tt, id), w2);
+      y[((3 * j) * stride + k) * CR + c] = cadd(a, sm);
+      y[((3 * j + 1) * stride + k) * CR + c] = cmul(cadd(tt, id), w1);
+      y[((3 * j + 2) * stride + k) * CR + c] = cmul(csub(tt, id), w2);
     }
     __syncthreads();
     cplx* sw = x;
@@ -190,40 +197,120 @@ __device__ cplx* fft3_lds(cplx* x, cplx* y, const cplx* tw, int L, bool inverse)
   return x;
 }
 
-// Forward transforms of the scaled input panels of one column disk q and 16
-// right-hand sides, for instances with L_b a power of 3.
-__global__ __launch_bounds__(256) void k_circ_fwd_fft3(DevView v, int R, const cplx* __restrict__ z,
-                                                       cplx* __restrict__ zh,
-                                                       const int32_t* __restrict__ con,
-                                                       const int32_t* __restrict__ active) {
-  __shared__ cplx buf[2 * CF3_L * CF3_R];
-  __shared__ cplx tw[CF3_L];
+template <int CR>
+__device__ cplx* fft23_lds(cplx* x, cplx* y, const cplx* tw, int L, bool inverse) {
+  int p3 = L;
+  while (p3 % 3 == 0) p3 /= 3;
+  if (p3 == 1) return fft3_only_lds<CR>(x, y, tw, L, inverse);  // powers of 3: one stage kind
+  const int tid = threadIdx.x;
+  int stride = 1;
+  for (int n = L; n > 1;) {
+    if (n % 3 == 0) {
+      const cplx zt = tw[L / 3];
+      const double sgn = inverse ? zt.y : -zt.y;  // Im(zeta)
+      const int m = n / 3;
+      for (int e = tid; e < m * stride * CR; e += blockDim.x) {
+        const int c = e % CR, t = e / CR;
+        const int k = t % stride, j = t / stride;
+        const cplx a = x[((j)*stride + k) * CR + c];
+        const cplx bb = x[((j + m) * stride + k) * CR + c];
+        const cplx cc = x[((j + 2 * m) * stride + k) * CR + c];
+        const cplx sm = cadd(bb, cc), df = csub(bb, cc);
+        const cplx tt = csub(a, cscale(sm, 0.5));
+        const cplx id = cmk(-sgn * df.y, sgn * df.x);  // i Im(zeta) (b - c)
+        cplx w1 = tw[j * stride], w2 = tw[2 * j * stride];
+        if (!inverse) {
+          w1 = cconj(w1);
+          w2 = cconj(w2);
+        }
+        y[((3 * j) * stride + k) * CR + c] = cadd(a, sm);
+        y[((3 * j + 1) * stride + k) * CR + c] = cmul(cadd(tt, id), w1);
+        y[((3 * j + 2) * stride + k) * CR + c] = cmul(csub(tt, id), w2);
+      }
+      n = m;
+      stride *= 3;
+    } else if (n % 4 == 0) {
+      const int m = n / 4;
+      for (int e = tid; e < m * stride * CR; e += blockDim.x) {
+        const int c = e % CR, t = e / CR;
+        const int k = t % stride, j = t / stride;
+        const cplx a0 = x[((j)*stride + k) * CR + c];
+        const cplx a1 = x[((j + m) * stride + k) * CR + c];
+        const cplx a2 = x[((j + 2 * m) * stride + k) * CR + c];
+        const cplx a3 = x[((j + 3 * m) * stride + k) * CR + c];
+        const cplx t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3), d = csub(a1, a3);
+        const cplx t3 = inverse ? cmk(-d.y, d.x) : cmk(d.y, -d.x);  // zeta (a1 - a3), zeta = -+i
+        cplx w1 = tw[j * stride], w2 = tw[2 * j * stride], w3 = tw[3 * j * stride];
+        if (!inverse) {
+          w1 = cconj(w1);
+          w2 = cconj(w2);
+          w3 = cconj(w3);
+        }
+        y[((4 * j) * stride + k) * CR + c] = cadd(t0, t2);
+        y[((4 * j + 1) * stride + k) * CR + c] = cmul(cadd(t1, t3), w1);
+        y[((4 * j + 2) * stride + k) * CR + c] = cmul(csub(t0, t2), w2);
+        y[((4 * j + 3) * stride + k) * CR + c] = cmul(csub(t1, t3), w3);
+      }
+      n = m;
+      stride *= 4;
+    } else {
+      const int m = n / 2;
+      for (int e = tid; e < m * stride * CR; e += blockDim.x) {
+        const int c = e % CR, t = e / CR;
+        const int k = t % stride, j = t / stride;
+        const cplx a = x[((j)*stride + k) * CR + c];
+        const cplx bb = x[((j + m) * stride + k) * CR + c];
+        cplx w = tw[j * stride];
+        if (!inverse) w = cconj(w);
+        y[((2 * j) * stride + k) * CR + c] = cadd(a, bb);
+        y[((2 * j + 1) * stride + k) * CR + c] = cmul(csub(a, bb), w);
+      }
+      n = m;
+      stride *= 2;
+    }
+    __syncthreads();
+    cplx* sw = x;
+    x = y;
+    y = sw;
+  }
+  return x;
+}
+
+// Forward transforms of the scaled input panels of one column disk q and CR
+// right-hand sides, for instances with L_b = 2^a 3^b <= LM.
+template <int CR, int LM>
+__global__ __launch_bounds__(256) void k_circ_fwd_fft(DevView v, int R, const cplx* __restrict__ z,
+                                                      cplx* __restrict__ zh,
+                                                      const int32_t* __restrict__ con,
+                                                      const int32_t* __restrict__ active) {
+  __shared__ cplx buf[2 * LM * CR];
+  __shared__ cplx tw[LM];
   const int q = blockIdx.x, tid = threadIdx.x;
   const int b = v.inst[q];
   if (!con[b]) return;
   const int Lb = v.cL[b];
-  if (!circ_pow3(Lb)) return;
-  const int r0 = blockIdx.y * CF3_R;
+  if (!circ_fft_len(Lb) || Lb > LM) return;
+  const int r0 = blockIdx.y * CR;
   if (r0 >= R) return;
   if (active) {
     bool any = false;
-    for (int r = r0; r < min(R, r0 + CF3_R); ++r) any |= active[b * R + r] != 0;
+    for (int r = r0; r < min(R, r0 + CR); ++r) any |= active[b * R + r] != 0;
     if (!any) return;
   }
   const int nq = 2 * v.N[q] + 1;
   const int64_t d0 = v.idisk[b], Mb = v.idisk[b + 1] - d0;
-  for (int e = tid; e < Lb * CF3_R; e += 256) {  // along the modes of a column: coalesced
+  for (int e = tid; e < Lb * CR; e += 256) {  // along the modes of a column: coalesced
     const int c = e / Lb, k = e - (e / Lb) * Lb;
     cplx val = cmk(0.0, 0.0);
     if (k < nq && r0 + c < R) val = z[col_base(v.imode, b, R, r0 + c) + v.moff[q] + k];
-    buf[k * CF3_R + c] = val;
+    buf[k * CR + c] = val;
   }
   for (int e = tid; e < Lb; e += 256) tw[e] = v.ctw[v.cWo[b] + e];
   __syncthreads();
-  const cplx* res = fft3_lds(buf, buf + CF3_L * CF3_R, tw, Lb, false);
+  const cplx* res = fft23_lds<CR>(buf, buf + LM * CR, tw, Lb, false);
   cplx* out = zh + (int64_t)R * v.cZo[b] + (q - d0) * R + r0;
-  for (int e = tid; e < Lb * CF3_R; e += 256) {
-    const int f = e / CF3_R, c = e - (e / CF3_R) * CF3_R;
+  for (int e = tid; e < Lb * CR; e += 256) {
+    const int f = e / CR, c = e - (e / CR) * CR;
     if (r0 + c < R) out[(int64_t)f * Mb * R + c] = res[e];
   }
 }
@@ -472,7 +559,7 @@ __global__ __launch_bounds__(256) void k_circ_finish_mfma(
   const int np = 2 * v.N[p] + 1;
   const int64_t d0 = v.idisk[b], Mb = v.idisk[b + 1] - d0;
   const bool circ = con[b] != 0;
-  if (circ && circ_pow3(v.cL[b])) return;  // k_circ_finish_fft3
+  if (circ && circ_fft_len(v.cL[b])) return;  // k_circ_finish_fft
   const int ldw = np + 1;
   if (circ) {
     const int Lb = v.cL[b];
@@ -523,51 +610,52 @@ __global__ __launch_bounds__(256) void k_circ_finish_mfma(
   }
 }
 
-// Output pass for instances in the form with L_b a power of 3: inverse radix-3
-// transform of the rows f of W^p for 16 right-hand sides (only the n_p modes
+// Output pass for instances in the form with L_b = 2^a 3^b <= LM: inverse
+// transform of the rows f of W^p for CR right-hand sides (only the n_p modes
 // are kept), then, as in k_circ_finish_mfma, the close pairs' partial sums and
 // the epilogue, coalesced over the modes.
-__global__ __launch_bounds__(256) void k_circ_finish_fft3(
+template <int CR, int LM>
+__global__ __launch_bounds__(256) void k_circ_finish_fft(
     DevView v, int R, const cplx* __restrict__ x, cplx* __restrict__ y, int op,
     const cplx* __restrict__ part, int64_t blk, int npad, int RC, const int32_t* __restrict__ dgrp,
     const int32_t* __restrict__ drow, const int32_t* __restrict__ gnseg,
     const int64_t* __restrict__ gbase, const int32_t* __restrict__ active,
     const cplx* __restrict__ wh, const int32_t* __restrict__ con,
     const cplx* __restrict__ shift) {
-  __shared__ cplx buf[2 * CF3_L * CF3_R];
-  __shared__ cplx tw[CF3_L];
+  __shared__ cplx buf[2 * LM * CR];
+  __shared__ cplx tw[LM];
   const int p = blockIdx.x, tid = threadIdx.x;
   const int b = v.inst[p];
   if (!con[b]) return;
   const int Lb = v.cL[b];
-  if (!circ_pow3(Lb)) return;
-  const int r0 = blockIdx.y * CF3_R;
+  if (!circ_fft_len(Lb) || Lb > LM) return;
+  const int r0 = blockIdx.y * CR;
   if (r0 >= R) return;
   if (active) {
     bool any = false;
-    for (int r = r0; r < min(R, r0 + CF3_R); ++r) any |= active[b * R + r] != 0;
+    for (int r = r0; r < min(R, r0 + CR); ++r) any |= active[b * R + r] != 0;
     if (!any) return;
   }
   const int np = 2 * v.N[p] + 1;
   const int64_t d0 = v.idisk[b], Mb = v.idisk[b + 1] - d0;
   const cplx* src = wh + (int64_t)R * v.cZo[b] + (p - d0) * R + r0;
-  for (int e = tid; e < Lb * CF3_R; e += 256) {
-    const int f = e / CF3_R, c = e - (e / CF3_R) * CF3_R;
+  for (int e = tid; e < Lb * CR; e += 256) {
+    const int f = e / CR, c = e - (e / CR) * CR;
     buf[e] = r0 + c < R ? src[(int64_t)f * Mb * R + c] : cmk(0.0, 0.0);
   }
   for (int e = tid; e < Lb; e += 256) tw[e] = v.ctw[v.cWo[b] + e];
   __syncthreads();
-  const cplx* res = fft3_lds(buf, buf + CF3_L * CF3_R, tw, Lb, true);
+  const cplx* res = fft23_lds<CR>(buf, buf + LM * CR, tw, Lb, true);
   const int gr = dgrp[p];
   const int ns = gnseg[gr];
   const int64_t ip = v.imode[b] + v.moff[p];
-  for (int e = tid; e < CF3_R * np; e += 256) {
+  for (int e = tid; e < CR * np; e += 256) {
     const int rr = e / np, m = e - (e / np) * np;
     const int r = r0 + rr;
     if (r >= R || (active && active[b * R + r] == 0)) continue;
     const int t = r / RC, rc = r - (r / RC) * RC;
     const cplx* pr = part + (gbase[gr] + (int64_t)t * ns) * blk + ((int64_t)drow[p] * npad + m) * RC + rc;
-    cplx w = res[m * CF3_R + rr];
+    cplx w = res[m * CR + rr];
     for (int sg = 0; sg < ns; ++sg) w = cadd(w, pr[(int64_t)sg * blk]);
     const int64_t g = col_base(v.imode, b, R, r) + v.moff[p] + m;
     cplx o = finalize(v, op, ip + m, x[g], w);
@@ -631,25 +719,38 @@ void circ_var_dims(int var, int* bm, int* bn, int* bk, int* db, int* nt) {
 
 // Enqueue the transforms of the inputs and the per-frequency products.
 // z: inputs scaled by their column factors [B][R][N_b]; zh, wh: [sum_b L_b M_b][R].
-// Which transform kernels a launch needs: instances in the form with L_b a
-// power of 3 (fast transforms) and with other lengths (direct sums).
-static void circ_kinds(const mudiff_ctx* h, const int32_t* con_h, bool* fft, bool* dft) {
+// Which transform kernels a launch needs: instances in the form with L_b =
+// 2^a 3^b (fast transforms; *fft_wide when one of them is longer than 81, so
+// that the launch takes 8 right-hand sides per workgroup instead of 16) and
+// with other lengths (direct sums).
+static void circ_kinds(const mudiff_ctx* h, const int32_t* con_h, bool* fft, bool* dft,
+                       bool* fft_wide = nullptr) {
   *fft = *dft = false;
-  for (int b = 0; b < h->B; ++b)
-    if (con_h[b]) (circ_pow3(h->cL[b]) ? *fft : *dft) = true;
+  bool wide = false;
+  for (int b = 0; b < h->B; ++b) {
+    if (!con_h[b]) continue;
+    const bool f = circ_fft_len(h->cL[b]);
+    (f ? *fft : *dft) = true;
+    wide |= f && h->cL[b] > 81;
+  }
+  if (fft_wide) *fft_wide = wide;
 }
 
 int circ_launch(mudiff_ctx* h, int R, const cplx* z, cplx* zh, cplx* wh, const int32_t* citems,
                 int n_citems, int var, const int32_t* con, const int32_t* con_h,
                 const int32_t* active, hipStream_t s) {
-  bool fft, dft;
-  circ_kinds(h, con_h, &fft, &dft);
+  bool fft, dft, wide;
+  circ_kinds(h, con_h, &fft, &dft, &wide);
+  wide |= R <= 8;  // 8 right-hand sides per workgroup: no idle half at R <= 8
   const int cw = R >= CF_R ? CF_R : (R > 8 ? 16 : 8);
   if (dft)
     hipLaunchKernelGGL(k_circ_fwd, dim3((unsigned)h->M_all, (unsigned)((R + cw - 1) / cw)), dim3(256), 0,
                        s, h->dv, R, z, zh, con, active);
-  if (fft)
-    hipLaunchKernelGGL(k_circ_fwd_fft3, dim3((unsigned)h->M_all, (unsigned)((R + CF3_R - 1) / CF3_R)),
+  if (fft && !wide)
+    hipLaunchKernelGGL((k_circ_fwd_fft<16, 81>), dim3((unsigned)h->M_all, (unsigned)((R + 15) / 16)),
+                       dim3(256), 0, s, h->dv, R, z, zh, con, active);
+  if (fft && wide)
+    hipLaunchKernelGGL((k_circ_fwd_fft<8, CF_LMAX>), dim3((unsigned)h->M_all, (unsigned)((R + 7) / 8)),
                        dim3(256), 0, s, h->dv, R, z, zh, con, active);
   HIP_TRY(hipGetLastError());
   prof_mark(h, s, 2);
@@ -666,14 +767,18 @@ int circ_finish(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, const cplx
                 int npad, int RC, const int32_t* dgrp, const int32_t* drow, const int32_t* gnseg,
                 const int64_t* gbase, const int32_t* active, const cplx* wh, const int32_t* con,
                 const int32_t* con_h, const cplx* shift, hipStream_t s) {
-  bool fft, dft;
-  circ_kinds(h, con_h, &fft, &dft);
-  if (fft) {
-    hipLaunchKernelGGL(k_circ_finish_fft3, dim3((unsigned)h->M_all, (unsigned)((R + CF3_R - 1) / CF3_R)),
+  bool fft, dft, wide;
+  circ_kinds(h, con_h, &fft, &dft, &wide);
+  wide |= R <= 8;
+  if (fft && !wide)
+    hipLaunchKernelGGL((k_circ_finish_fft<16, 81>), dim3((unsigned)h->M_all, (unsigned)((R + 15) / 16)),
                        dim3(256), 0, s, h->dv, R, x, y, op, part, blk, npad, RC, dgrp, drow, gnseg,
                        gbase, active, wh, con, shift);
-    HIP_TRY(hipGetLastError());
-  }
+  if (fft && wide)
+    hipLaunchKernelGGL((k_circ_finish_fft<8, CF_LMAX>), dim3((unsigned)h->M_all, (unsigned)((R + 7) / 8)),
+                       dim3(256), 0, s, h->dv, R, x, y, op, part, blk, npad, RC, dgrp, drow, gnseg,
+                       gbase, active, wh, con, shift);
+  HIP_TRY(hipGetLastError());
   bool direct = dft;  // instances outside the form: partial sums only, in the MFMA finish
   for (int b = 0; b < h->B && !direct; ++b) direct = con_h[b] == 0;
   if (!direct) return MUDIFF_OK;

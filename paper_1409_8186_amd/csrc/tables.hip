@@ -219,7 +219,15 @@ int64_t circ_len(const int32_t* n_modes, int64_t d0, int64_t d1) {
       c = n;
     }
   }
-  return 2 * (int64_t)(a + c) + 1;
+  // any L >= 2 (N' + N'') + 1 embeds every block; the shortest 2^i 3^j at or
+  // above it takes fast transforms, and is used when it adds at most a fifth
+  // to the per-frequency products (whose work grows with L)
+  const int64_t lmin = 2 * (int64_t)(a + c) + 1;
+  int64_t best = 0;
+  for (int64_t p2 = 1; p2 <= 4 * lmin; p2 *= 2)
+    for (int64_t l = p2; l <= 4 * lmin; l *= 3)
+      if (l >= lmin && (best == 0 || l < best)) best = l;
+  return (best <= 128 && 5 * best <= 6 * lmin) ? best : lmin;
 }
 
 namespace {

@@ -59,11 +59,17 @@ def test_workspace_size_queries(lib):
     # monotone in the number of modes
     assert _sizes(lib, [0, 4], [12] * 4) > _sizes(lib, [0, 4], [8] * 4)
     assert _sizes(lib, [0, 4], [30] * 4) > _sizes(lib, [0, 4], [20] * 4)
-    # the circulant form adds sum_b L_b M_b^2 complex values, L_b = 2 (N' + N'') + 1
+    # the circulant form adds sum_b L_b M_b^2 complex values: L_min = 2 (N' + N'') + 1
+    # = 41 is raised to 48 = 2^4 3 (at most 1.2 L_min: fast transforms) ...
     base = _sizes(lib, [0, 40], [10] * 40)
     circ = _sizes(lib, [0, 40], [10] * 40, flags=1)
-    assert circ - base >= 41 * 40 * 40 * 16
-    assert circ - base < 41 * 40 * 40 * 16 + 41 * 16 + 40 * 39 // 2 + 8 * 256
+    assert circ - base >= 48 * 40 * 40 * 16
+    assert circ - base < 48 * 40 * 40 * 16 + 48 * 16 + 40 * 39 // 2 + 8 * 256
+    # ... while L_min = 2 (10 + 8) + 1 = 37 stays (48 would add 30% to the products)
+    base = _sizes(lib, [0, 40], [10] + [8] * 39)
+    circ = _sizes(lib, [0, 40], [10] + [8] * 39, flags=1)
+    assert circ - base >= 37 * 40 * 40 * 16
+    assert circ - base < 37 * 40 * 40 * 16 + 37 * 16 + 40 * 39 // 2 + 8 * 256
     assert _sizes(lib, [0, 4], [3] * 4, flags=2) == 0         # unknown flag
 
 

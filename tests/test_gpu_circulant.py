@@ -53,6 +53,16 @@ def _mixed(seed, M=30):
     return synth.small_random(seed, M, 0.3, 1.0, 3.6 * math.sqrt(M), 0.1, 6.0, 4)
 
 
+def _embed_len(n_modes):
+    """Embedding length the tables pick: L_min = 2 (N' + N'') + 1 over the two
+    largest orders, raised to the shortest 2^i 3^j >= L_min when that is at most
+    128 and at most 1.2 L_min (fast transforms), else L_min itself."""
+    n = np.sort(np.asarray(n_modes))[::-1]
+    lmin = 2 * (int(n[0]) + int(n[1])) + 1
+    smooth = min(2 ** i * 3 ** j for i in range(9) for j in range(6) if 2 ** i * 3 ** j >= lmin)
+    return smooth if smooth <= 128 and 5 * smooth <= 6 * lmin else lmin
+
+
 def _batch():
     """A mixed instance, a dense low-frequency one (mostly close pairs: it stays
     in the direct form), another mixed one with other orders, and one disk."""
@@ -71,7 +81,7 @@ def test_circulant_classification(P):
     assert info["near_pairs"] == near and info["far_pairs"] == total - near
     assert 0 < near < total
     Ns = [np.sort(c.n_modes)[::-1] for c in cls if c.M > 1]
-    assert info["L_max"] == max(2 * (int(n[0]) + int(n[1])) + 1 for n in Ns)
+    assert info["L_max"] == max(_embed_len(c.n_modes) for c in cls if c.M > 1)
     assert P.from_clusters(cls).circulant_info() == {"far_pairs": 0, "near_pairs": 0, "L_max": 0}
 
 
@@ -139,29 +149,45 @@ def test_circulant_close_pair_lists_every_tile(P):
                     assert rel(Y.cpu().numpy(), ref) < 1e-12, (ct, waves, qs)
 
 
-def _radix3_batch():
-    """Instances whose embedding length is a power of 3 (fast radix-3
-    transforms): L = 2 (7 + 6) + 1 = 27 and L = 2 (20 + 20) + 1 = 81; next to
-    them one with L = 41 (direct sums) and one outside the form."""
-    c27 = synth.small_random(540, 24, 0.3, 0.8, 30.0, 0.2, 6.0, 2)
-    n27 = np.full(c27.M, 6, np.int32)
-    n27[3] = 7
-    c27 = synth.Cluster(c27.centers, c27.radii, n27, c27.k)
+def _fixed_orders(seed, M, box, k, first, rest):
+    """small_random placement with order `first` on disk 3 and `rest` elsewhere."""
+    c = synth.small_random(seed, M, 0.3, 0.8, box, 0.2, k, 2)
+    n = np.full(c.M, rest, np.int32)
+    n[3] = first
+    return synth.Cluster(c.centers, c.radii, n, k)
+
+
+def _fft_batch():
+    """Embedding lengths of every kind in one launch: L = 27 and 81 (radix 3),
+    L_min = 41 raised to 48 = 2^4 3 (radix 3 then radix 2), L_min = 37 kept
+    (48 would add 30% to the products: direct sums), and an instance outside
+    the form."""
+    c27 = _fixed_orders(540, 24, 30.0, 6.0, 7, 6)
     c81 = synth.small_random(541, 16, 0.8, 1.0, 40.0, 0.2, 10.0, 10)
     c81 = synth.Cluster(c81.centers, c81.radii, np.full(c81.M, 20, np.int32), c81.k)
+    c37 = _fixed_orders(542, 20, 32.0, 6.0, 10, 8)
     low = synth.small_random(505, 10, 0.5, 0.9, 6.0, 0.1, 1.0, 6)
-    return [c27, _mixed(501), c81, low]
+    return [c27, _mixed(501), c81, c37, low]
+
+
+def _wide_batch():
+    """A length above 81 (L_min = 97 raised to 108 = 2^2 3^3: the launch then
+    takes 8 right-hand sides per workgroup) beside L = 27 and L = 48."""
+    c108 = synth.small_random(543, 14, 0.8, 1.0, 46.0, 0.2, 9.0, 10)
+    c108 = synth.Cluster(c108.centers, c108.radii, np.full(c108.M, 24, np.int32), c108.k)
+    return [_fixed_orders(540, 24, 30.0, 6.0, 7, 6), c108, _mixed(503)]
 
 
 @pytest.mark.parametrize("R", [8, 16, 40])
-def test_circulant_radix3_lengths(P, R):
-    """Fast radix-3 transforms (L = 27, 81) beside direct sums (L = 41) and an
-    instance outside the form, in one launch: A, L and L^T against the dense
-    oracle, every product tile."""
-    cls = _radix3_batch()
+def test_circulant_fft_lengths(P, R):
+    """Fast transforms of lengths 27, 81 (radix 3) and 48 (radix 3, 2) beside
+    direct sums (L = 37) and an instance outside the form, in one launch: A, L
+    and L^T against the dense oracle, every product tile."""
+    cls = _fft_batch()
+    assert [_embed_len(c.n_modes) for c in cls[:4]] == [27, 48, 81, 37]
     pr = P.from_clusters(cls, circulant=True)
     info = pr.circulant_info()
-    say("radix-3 lengths R", R, info)
+    say("fft lengths R", R, info)
     assert info["L_max"] == 81
     pr.set_circulant(R, 1)
     rng = np.random.default_rng(900 + R)
@@ -180,6 +206,37 @@ def test_circulant_radix3_lengths(P, R):
         y = pr.matvec(x, R=R, op=1)
         for (_, A), X, Y in zip(dense, Xs, pr.split(y, R)):
             assert rel(Y.cpu().numpy(), X @ A.T) < 1e-12, tile
+
+
+@pytest.mark.parametrize("R", [8, 19])
+def test_circulant_lengths_above_81(P, R):
+    """L = 108 (2^2 3^3) in a launch with L = 27 and 48: every fast transform
+    of the launch runs 8 right-hand sides per workgroup; A, L and L^T against
+    the dense oracle, and lockstep GMRES against LU."""
+    cls = _wide_batch()
+    assert [_embed_len(c.n_modes) for c in cls] == [27, 108, 48]
+    pr = P.from_clusters(cls, circulant=True)
+    info = pr.circulant_info()
+    say("lengths above 81, R", R, info)
+    assert info["L_max"] == 108 and info["far_pairs"] > 0
+    pr.set_circulant(R, 1)
+    rng = np.random.default_rng(960 + R)
+    Xs = [rng.normal(size=(R, c.n_tot)) + 1j * rng.normal(size=(R, c.n_tot)) for c in cls]
+    x = pr.pack(Xs)
+    dense = [_dense(c) for c in cls]
+    for op in (1, 0, 2):
+        y = pr.matvec(x, R=R, op=op)
+        assert pr.apply_config(R)["kind"] == "circulant"
+        for (L, A), X, Y in zip(dense, Xs, pr.split(y, R)):
+            Mx = {1: A, 0: L, 2: L.T}[op]
+            e = rel(Y.cpu().numpy(), X @ Mx.T)
+            assert e < 1e-12, (op, e)
+    betas = np.stack([synth.uniform_angles(R) + 0.1 * i for i in range(len(cls))])
+    rho, flag, _, iters, _ = pr.gmres(betas=betas, restart=30, tol=1e-12, maxit=3000)
+    say("  gmres iterations", iters.cpu().numpy().tolist())
+    assert torch.all(flag == 0)
+    for b, (c, Y) in enumerate(zip(cls, pr.split(rho, R))):
+        assert rel(Y.cpu().numpy(), _lu(c, betas[b])) < 1e-10
 
 
 def _close_counts(cl):

@@ -181,6 +181,11 @@ struct MfmaSched {
   // the group rows close to q), per-frequency product items (instance,
   // frequency, row tile, column tile) and the instances that use the form
   std::vector<int32_t> qlist, citems, con;
+  // 8-column tiles in the circulant form: the close pairs run one wave per
+  // (row disk, tile) over the row's close list (nptr [M_all + 1] offsets into
+  // nq, global disk indices), not as work-queue items
+  bool close_rows = false;
+  std::vector<int32_t> nptr, nq;
   int n_citems = 0, cvar = 0;
   void* dev_base = nullptr;  // apply scratch the device copy lives in
 };

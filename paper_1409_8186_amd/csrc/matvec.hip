@@ -573,6 +573,90 @@ __global__ __launch_bounds__(THREADS) void k_apply_mfma(
   }
 }
 
+// Close pairs of the instances in the circulant form with 8-column tiles (few
+// right-hand sides): one wave per (row disk p, tile of 8 columns), no LDS and
+// no barriers.  The wave walks p's close list; per column disk q and k step it
+// loads the input panel element of its lane (B[k][j]: Re or Im of column j & 7
+// at mode 4 kt + k) and per row tile the symbol value of its lane (A[i][k]:
+// t_{(n - N_q) - (m - N_p)}, m = 16 mt + i), straight into the operand layout
+// of v_mfma_f64_16x16x4f64 (two MFMAs per complex product, as k_apply_mfma),
+// and accumulates the whole row in registers; the sum goes to segment 0 of the
+// row's group, which the output pass adds.  In the work queue the same pairs
+// cost two barriers and an LDS staging round per listed column disk, with only
+// the few waves whose row is close to it on the matrix cores.
+template <int MT>
+__global__ __launch_bounds__(64) void k_apply_close(
+    DevView v, int R, const cplx* __restrict__ z, cplx* __restrict__ part, int64_t blk, int npad,
+    const int32_t* __restrict__ dgrp, const int32_t* __restrict__ drow,
+    const int64_t* __restrict__ gbase, const int32_t* __restrict__ nptr,
+    const int32_t* __restrict__ nql, const int32_t* __restrict__ con,
+    const int32_t* __restrict__ active) {
+  const int p = blockIdx.x, t = blockIdx.y, lane = threadIdx.x;
+  const int b = v.inst[p];
+  if (!con[b]) return;
+  const int c0 = 8 * t;
+  if (c0 >= R) return;
+  if (active) {
+    bool any = false;
+    for (int r = c0; r < min(R, c0 + 8); ++r) any |= active[b * R + r] != 0;
+    if (!any) return;
+  }
+  const int j = lane & 15, kq = lane >> 4;
+  const int Np = v.N[p], np_ = 2 * Np + 1, mtp = (np_ + 15) >> 4;
+  mf_d4 acc1[MT], acc2[MT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    acc1[mt] = mf_d4{0.0, 0.0, 0.0, 0.0};
+    acc2[mt] = mf_d4{0.0, 0.0, 0.0, 0.0};
+  }
+  const int col = c0 + (j & 7);
+  const bool colok = col < R;
+  const int64_t cb = colok ? col_base(v.imode, b, R, col) : 0;
+  for (int e = nptr[p]; e < nptr[p + 1]; ++e) {
+    const int q = nql[e];
+    const int Nq = v.N[q], nq_ = 2 * Nq + 1, S = Np + Nq, KT = (nq_ + 3) >> 2;
+    const cplx* __restrict__ trow = v.t + v.toff[pair_index(v.idisk, v.ipair, b, p, q)] + S;
+    const bool flip = p > q;  // t^{pq}_s = (-1)^s t^{qp}_s
+    const cplx* __restrict__ zq = z + cb + v.moff[q];
+    for (int kt = 0; kt < KT; ++kt) {
+      const int n = 4 * kt + kq;
+      double bv = 0.0;
+      if (colok && n < nq_) {
+        const cplx zz = zq[n];
+        bv = j < 8 ? zz.x : zz.y;
+      }
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        if (mt < mtp) {  // wave-uniform
+          const int m = 16 * mt + j;
+          cplx a = cmk(0.0, 0.0);
+          if (m < np_ && n < nq_) {
+            const int sv = (n - Nq) - (m - Np);
+            a = trow[sv];
+            if (flip && (sv & 1)) a = cmk(-a.x, -a.y);
+          }
+          acc1[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, bv, acc1[mt], 0, 0, 0);
+          acc2[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, bv, acc2[mt], 0, 0, 0);
+        }
+      }
+    }
+  }
+  // segment 0 of the group's tile t: [RP][npad][8]
+  cplx* pbk = part + (gbase[dgrp[p]] + t) * blk + (int64_t)drow[p] * npad * 8 + (j & 7);
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+    for (int vv = 0; vv < 4; ++vv) {
+      const double a1 = acc1[mt][vv], a2 = acc2[mt][vv];
+      const double other = __shfl_xor(a2, 8, 64);
+      const double val = j < 8 ? a1 - other : a1 + other;  // Re W (j < 8), Im W (j >= 8)
+      const double im = __shfl_xor(val, 8, 64);
+      const int m = 16 * mt + 4 * vv + kq;
+      if (j < 8) pbk[(int64_t)m * 8] = cmk(val, im);
+    }
+  }
+}
+
 // z = x scaled by the column factor of its unknown (sqrt(a) J_n, or the
 // operator's column table), once per apply: the MFMA gathers then load one
 // value per panel element.
@@ -690,6 +774,9 @@ static void mfma_build(const mudiff_ctx* h, int R, const MfmaChoice& c, MfmaSche
   S.gbase.clear();
   S.qlist.clear();
   S.citems.clear();
+  S.nptr.clear();
+  S.nq.clear();
+  S.close_rows = c.circ && h->circ && c.CT == 1;
   S.con.assign(h->B, 0);
   S.dgrp.assign(h->M_all, 0);
   S.drow.assign(h->M_all, 0);
@@ -760,7 +847,9 @@ static void mfma_build(const mudiff_ctx* h, int R, const MfmaChoice& c, MfmaSche
       // close pairs of its rows (with the mask of the rows close to each)
       int64_t ncol = Mb, lbase = 0;
       std::vector<double> lw;  // column widths of the list entries
-      if (circ) {
+      if (circ && S.close_rows) {
+        ncol = 0;  // k_apply_close writes segment 0 of every tile
+      } else if (circ) {
         std::map<int32_t, int> mask;
         for (int k = 0; k < rp; ++k) {
           const int32_t pk = ord[(size_t)(o + k)];
@@ -774,12 +863,12 @@ static void mfma_build(const mudiff_ctx* h, int R, const MfmaChoice& c, MfmaSche
         ncol = (int64_t)mask.size();
       }
       const int64_t qsg = circ ? (c.QS > 0 ? c.QS : std::max<int64_t>(ncol, 1)) : qs;
-      const int nseg = (int)((ncol + qsg - 1) / qsg);
+      const int nseg = (circ && S.close_rows) ? 1 : (int)((ncol + qsg - 1) / qsg);
       S.gnseg.push_back(nseg);
       S.gbase.push_back(pb);
       for (int t = 0; t < S.ntile; ++t) {
         if (!tile_runs(b, t * RC, (t + 1) * RC)) continue;
-        for (int sg = 0; sg < nseg; ++sg) {
+        for (int sg = 0; sg < (circ && S.close_rows ? 0 : nseg); ++sg) {
           const int64_t i0 = sg * qsg, i1 = std::min<int64_t>(ncol, i0 + qsg);
           double cw = 0.0;
           for (int64_t i = i0; i < i1; ++i) cw += circ ? lw[(size_t)i] : 2.0 * h->N[d0 + i] + 1;
@@ -812,6 +901,14 @@ static void mfma_build(const mudiff_ctx* h, int R, const MfmaChoice& c, MfmaSche
     }
   }
   S.n_pb = pb;
+  if (S.close_rows) {
+    S.nptr.assign((size_t)h->M_all + 1, 0);
+    for (int p = 0; p < h->M_all; ++p) {
+      if (S.con[(size_t)h->inst[p]])
+        for (int64_t e = h->near_off[p]; e < h->near_off[p + 1]; ++e) S.nq.push_back(h->near[(size_t)e]);
+      S.nptr[(size_t)p + 1] = (int32_t)S.nq.size();
+    }
+  }
   std::stable_sort(its.begin(), its.end(), [](const It& a, const It& b) { return a.cost > b.cost; });
   S.items.resize(its.size() * MF_REC);
   for (size_t k = 0; k < its.size(); ++k)
@@ -823,7 +920,7 @@ static void mfma_build(const mudiff_ctx* h, int R, const MfmaChoice& c, MfmaSche
 // Byte layout of the MFMA schedule inside the apply scratch:
 // [head][items][dgrp][grow][gnseg][gbase][partial blocks][scaled input][drow]
 // [qlist][product items][con][transformed inputs][transformed outputs]
-#define MF_NOFF 14
+#define MF_NOFF 16
 static size_t mfma_scratch_layout(const mudiff_ctx* h, const MfmaSched& S, size_t* off) {
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -846,6 +943,8 @@ static size_t mfma_scratch_layout(const mudiff_ctx* h, const MfmaSched& S, size_
   const size_t zw = S.c.circ ? (size_t)S.R * h->cZ_all * 16 : 0;
   off[12] = take(zw);
   off[13] = take(zw);
+  off[14] = take(S.nptr.size() * 4);  // close lists of the 8-column tiles
+  off[15] = take(S.nq.size() * 4);
   return o;
 }
 
@@ -899,6 +998,10 @@ static int mfma_upload(mudiff_ctx* h, MfmaSched& S, char* base, hipStream_t s) {
   if (!S.citems.empty())
     HIP_TRY(hipMemcpyAsync(base + off[10], S.citems.data(), S.citems.size() * 4, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(base + off[11], S.con.data(), (size_t)h->B * 4, hipMemcpyHostToDevice, s));
+  if (!S.nptr.empty())
+    HIP_TRY(hipMemcpyAsync(base + off[14], S.nptr.data(), S.nptr.size() * 4, hipMemcpyHostToDevice, s));
+  if (!S.nq.empty())
+    HIP_TRY(hipMemcpyAsync(base + off[15], S.nq.data(), S.nq.size() * 4, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(base + off[1], S.items.data(), S.items.size() * 4, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(base + off[2], S.dgrp.data(), (size_t)h->M_all * 4, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(base + off[3], S.grow.data(), S.grow.size() * 4, hipMemcpyHostToDevice, s));
@@ -987,6 +1090,19 @@ static int mfma_launch(mudiff_ctx* h, const MfmaSched& S, const cplx* x, cplx* y
     hipLaunchKernelGGL(fn, dim3(grid), dim3(S.c.threads), lds, s, h->dv, S.R, (const cplx*)z, active, it,
                        S.n_items, head, part, S.blk, S.npad, kt, S.c.RP, S.c.CT,
                        (const int32_t*)(base + off[3]), (const int32_t*)(base + off[9]));
+    HIP_TRY(hipGetLastError());
+  }
+  if (S.close_rows) {  // every row of the form writes its segment (zeros without close pairs)
+    typedef void (*close_fn)(DevView, int, const cplx*, cplx*, int64_t, int, const int32_t*,
+                             const int32_t*, const int64_t*, const int32_t*, const int32_t*,
+                             const int32_t*, const int32_t*);
+    static const close_fn kClose[5] = {nullptr, k_apply_close<1>, k_apply_close<2>, k_apply_close<3>,
+                                       k_apply_close<4>};
+    if (mt < 1 || mt > 4) return fail(MUDIFF_ERR_INVALID, "close pairs: orders out of range");
+    hipLaunchKernelGGL(kClose[mt], dim3((unsigned)h->M_all, (unsigned)S.ntile), dim3(64), 0, s, h->dv,
+                       S.R, (const cplx*)z, part, S.blk, S.npad, (const int32_t*)(base + off[2]),
+                       (const int32_t*)(base + off[8]), (const int64_t*)(base + off[5]),
+                       (const int32_t*)(base + off[14]), (const int32_t*)(base + off[15]), con, active);
     HIP_TRY(hipGetLastError());
   }
   prof_mark(h, s, 4);

@@ -112,7 +112,7 @@ def circ_traffic_per_launch(tile):
     m = re.search(r"source_sha256_16[^:]*:\s*([0-9a-f]+)", txt)
     if not m or m.group(1) != apply_source_sha(CIRC_SRC):
         return None
-    pat = r"variant %dx%d K%d stages %d threads %d .*bytes_per_launch (\d+)" % tuple(tile)
+    pat = r"variant %dx%d K%d stages %d threads %d products %d .*bytes_per_launch (\d+)" % tuple(tile)
     v = re.search(pat, txt)
     return float(v.group(1)) if v else None
 
@@ -898,7 +898,8 @@ def headline(args):
         kern_s = phases_ms["frequency_products"] / 1e3
         flops = 8.0 * R * info["L_max"] * info["far_pairs"]
         kname = (f"k_circ_gemm (per-frequency products T_f Z_f, tile {tile[0]}x{tile[1]} "
-                 f"K{tile[2]}, staging depth {tile[3]}, {tile[4]} threads)")
+                 f"K{tile[2]}, staging depth {tile[3]}, {tile[4]} threads, {tile[5]} real "
+                 f"products per complex product)")
         traffic = circ_traffic_per_launch(tile)
         sha = apply_source_sha(CIRC_SRC)
     else:
@@ -924,8 +925,13 @@ def headline(args):
                         "algorithmic_flops_per_launch": flops,
                         "flops_note": ("8 R L per well-separated ordered pair (the products of "
                                        "the circulant form; the zero entries of T_f for the "
-                                       "diagonal and the close pairs are not counted)" if circ
+                                       "diagonal and the close pairs are not counted); a "
+                                       "complex multiply-add counts 8 flops in either product "
+                                       "form, and in Gauss's three-product form the matrix "
+                                       "cores execute 6 of them" if circ
                                        else "8 R n_p n_q per ordered pair"),
+                        "matrix_core_flops_per_launch": (flops * (6.0 if circ and tile[5] == 3 else 8.0)
+                                                         / 8.0),
                         "source_sha256_16": sha}}
     out["roofline"].update(measured_peaks(achieved, "fp64_mfma"))
     # the same apply in the direct form (every pair as Toeplitz tiles on MFMA)

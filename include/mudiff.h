@@ -168,19 +168,24 @@ int mudiff_set_circulant(mudiff_t h, int R, int mode);
  * circulant form (host outputs, any may be NULL; zeros otherwise): rows and
  * complex columns of a workgroup's output tile, K step (column disks staged
  * per step), staging depth (1: one LDS buffer; 2: two LDS buffers; 3: two LDS
- * buffers and two register sets, loads two steps ahead) and workgroup size.
+ * buffers and two register sets, loads two steps ahead), workgroup size, and
+ * real matrix products per complex product: 4 (Re and Im of T against
+ * [Re Z | Im Z]) or 3 (Gauss's form: Re T Re Z, Im T Im Z and
+ * (Re T + Im T)(Re Z + Im Z); a quarter fewer matrix-core operations, rounding
+ * error normwise of the same order).
  * The candidates for R are timed with the rest of the apply on first use. */
 int mudiff_circulant_tile(mudiff_t h, int R, int* rows, int* cols, int* kstep, int* stages,
-                          int* threads);
+                          int* threads, int* mults);
 
 /* Fixes that tile (one of the candidates for R, as listed by
- * Problem.circulant_tiles in the Python binding: for R >= 48, 64x32 K16 or K8,
- * 128x32 K16, K8 or K4 on 512 threads, 128x32 K8 on 1024 threads, 128x64 K8
- * or K16, 256x32 K8; other sets for smaller R) and switches the circulant form
- * on for R.
+ * Problem.circulant_tiles in the Python binding: for R >= 48 with four
+ * products, 64x32 K16 or K8, 128x32 K16, K8 or K4 on 512 threads, 128x32 K8 on
+ * 1024 threads, 128x64 K8 or K16, 256x32 K8, and with three, 128x32 K8 or K16,
+ * 128x64 K8, 256x32 K8, 64x32 K8; other sets for smaller R) and switches the
+ * circulant form on for R.
  * MUDIFF_ERR_INVALID for other tiles or when the form is not available. */
 int mudiff_set_circulant_tile(mudiff_t h, int R, int rows, int cols, int kstep, int stages,
-                              int threads);
+                              int threads, int mults);
 
 /* Releases the host handle (not the caller's device memory); NULL is a no-op. */
 int mudiff_destroy(mudiff_t h);

@@ -23,8 +23,8 @@ SIGNATURES = {
     "mudiff_tables": (_i32, [_i32, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _i32, _vp, ctypes.POINTER(_vp)]),
     "mudiff_circulant_info": (_i32, [_vp, _i64p, _i64p, ctypes.POINTER(_i32)]),
     "mudiff_set_circulant": (_i32, [_vp, _i32, _i32]),
-    "mudiff_circulant_tile": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp]),
-    "mudiff_set_circulant_tile": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32, _i32]),
+    "mudiff_circulant_tile": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "mudiff_set_circulant_tile": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _i32]),
     "mudiff_destroy": (_i32, [_vp]),
     "mudiff_sizes": (_i32, [_vp, _i64p]),
     "mudiff_disk_tables": (_i32, [_vp, _vp, _vp, _vp]),

@@ -175,19 +175,23 @@ class Problem:
         """Form of the R-column apply: -1 timed, 0 direct only, 1 circulant."""
         L.check(self.lib.mudiff_set_circulant(self.h, R, mode))
 
-    # per-frequency product tiles (rows, cols, kstep, stages, threads) timed for R
-    CIRCULANT_TILES = {48: [(64, 32, 16, 2, 256), (64, 32, 16, 3, 256), (128, 32, 16, 2, 512),
-                            (128, 32, 16, 3, 512), (128, 32, 8, 3, 512), (128, 32, 8, 2, 512),
-                            (64, 32, 8, 3, 256), (128, 64, 8, 3, 512), (128, 64, 16, 3, 512),
-                            (128, 32, 4, 2, 512), (128, 32, 8, 2, 1024), (64, 32, 8, 2, 256),
-                            (256, 32, 8, 2, 512)],
-                       24: [(64, 32, 16, 2, 256), (64, 32, 32, 2, 256), (128, 32, 16, 2, 256),
-                            (64, 32, 16, 3, 256), (128, 32, 16, 2, 512), (128, 32, 16, 3, 512),
-                            (128, 32, 8, 3, 512), (128, 32, 8, 2, 512), (64, 32, 8, 3, 256),
-                            (64, 32, 8, 2, 256)],
-                       12: [(128, 16, 16, 2, 256), (128, 8, 16, 2, 256), (128, 16, 16, 3, 256),
-                            (128, 16, 8, 2, 256)],
-                       1: [(128, 8, 16, 2, 256), (64, 8, 16, 2, 256), (128, 8, 8, 2, 256)]}
+    # per-frequency product tiles (rows, cols, kstep, stages, threads, real products per
+    # complex product) timed for R
+    CIRCULANT_TILES = {48: [(64, 32, 16, 2, 256, 4), (64, 32, 16, 3, 256, 4), (128, 32, 16, 2, 512, 4),
+                            (128, 32, 16, 3, 512, 4), (128, 32, 8, 3, 512, 4), (128, 32, 8, 2, 512, 4),
+                            (64, 32, 8, 3, 256, 4), (128, 64, 8, 3, 512, 4), (128, 64, 16, 3, 512, 4),
+                            (128, 32, 4, 2, 512, 4), (128, 32, 8, 2, 1024, 4), (64, 32, 8, 2, 256, 4),
+                            (256, 32, 8, 2, 512, 4), (128, 32, 8, 2, 512, 3), (128, 32, 16, 2, 512, 3),
+                            (128, 32, 8, 3, 512, 3), (128, 64, 8, 2, 512, 3), (256, 32, 8, 2, 512, 3),
+                            (64, 32, 8, 2, 256, 3)],
+                       24: [(64, 32, 16, 2, 256, 4), (64, 32, 32, 2, 256, 4), (128, 32, 16, 2, 256, 4),
+                            (64, 32, 16, 3, 256, 4), (128, 32, 16, 2, 512, 4), (128, 32, 16, 3, 512, 4),
+                            (128, 32, 8, 3, 512, 4), (128, 32, 8, 2, 512, 4), (64, 32, 8, 3, 256, 4),
+                            (64, 32, 8, 2, 256, 4), (128, 32, 8, 2, 512, 3), (128, 32, 16, 2, 512, 3),
+                            (64, 32, 8, 2, 256, 3)],
+                       12: [(128, 16, 16, 2, 256, 4), (128, 8, 16, 2, 256, 4), (128, 16, 16, 3, 256, 4),
+                            (128, 16, 8, 2, 256, 4), (128, 16, 8, 2, 256, 3), (128, 16, 16, 2, 256, 3)],
+                       1: [(128, 8, 16, 2, 256, 4), (64, 8, 16, 2, 256, 4), (128, 8, 8, 2, 256, 4)]}
 
     @classmethod
     def circulant_tiles(cls, R: int) -> list:
@@ -210,13 +214,14 @@ class Problem:
         return out
 
     def circulant_tile(self, R: int) -> tuple:
-        v = [ctypes.c_int(0) for _ in range(5)]
+        v = [ctypes.c_int(0) for _ in range(6)]
         L.check(self.lib.mudiff_circulant_tile(self.h, R, *[ctypes.byref(x) for x in v]))
         return tuple(x.value for x in v)
 
     def set_circulant_tile(self, R: int, rows: int, cols: int, kstep: int, stages: int,
-                           threads: int) -> None:
-        L.check(self.lib.mudiff_set_circulant_tile(self.h, R, rows, cols, kstep, stages, threads))
+                           threads: int, mults: int = 4) -> None:
+        L.check(self.lib.mudiff_set_circulant_tile(self.h, R, rows, cols, kstep, stages, threads,
+                                                   mults))
 
     def rhs(self, betas=None, precond: bool = False, sources=None) -> torch.Tensor:
         """betas: [B, R] incidence angles, or sources: [B, R, 2] point-source

@@ -330,13 +330,25 @@ typedef double cg_d4 __attribute__((ext_vector_type(4)));
 
 // PF2: two register sets for the staged K steps, so that step kc + 2 is
 // loaded while step kc is on the matrix cores (two steps of latency hiding).
-template <int WR, int WC, int WM, int WN, int BK, bool DB, bool PF2>
+// G3: Gauss's three-product form of the complex product.  A wave tile is then
+// 16 rows x 16 complex columns, and per k-step of 4 it issues three real MFMAs
+// instead of four:
+//   P1 = Re T Re Z,  P2 = Im T Im Z,  P3 = (Re T + Im T)(Re Z + Im Z),
+//   Re W = P1 - P2,  Im W = P3 - P1 - P2,
+// with B[k][j] the j-th complex column itself (no [Re | Im] split), so every
+// lane holds whole output elements and the epilogue needs no lane exchange.
+// The rounding error of Im W is bounded by a small multiple of eps times
+// sum |T| |Z| over the contraction (N. J. Higham, "Stability of a method for
+// multiplying complex matrices with three real matrix multiplications", SIAM
+// J. Matrix Anal. Appl. 13, 1992): normwise as accurate as the four-product form.
+template <int WR, int WC, int WM, int WN, int BK, bool DB, bool PF2, bool G3 = false>
 __global__ __launch_bounds__(WR * WC * 64) void k_circ_gemm(DevView v, int R, const cplx* __restrict__ zh,
                                                    cplx* __restrict__ wh,
                                                    const int32_t* __restrict__ items, int n_items,
                                                    const int32_t* __restrict__ active) {
   constexpr int NT = WR * WC * 64;
-  constexpr int BM = WR * 16 * WM, BN = WC * 8 * WN;
+  constexpr int CW = G3 ? 16 : 8;  // complex columns of a wave's MFMA tile
+  constexpr int BM = WR * 16 * WM, BN = WC * CW * WN;
   constexpr int AS = BK + 1, BS = BN + 1;  // LDS row strides (complex)
   constexpr int NA = BM * BK / NT, NB = (BK * BN + NT - 1) / NT;
   constexpr int ASZ = BM * AS, BSZ = BK * BS;
@@ -395,13 +407,16 @@ __global__ __launch_bounds__(WR * WC * 64) void k_circ_gemm(DevView v, int R, co
       if (e < BK * BN) bs[(e / BN) * BS + (e % BN)] = xb[u];
     }
   };
-  cg_d4 acc1[WM][WN], acc2[WM][WN];
+  // four-product form: acc1 = Re T [Re Z | Im Z], acc2 = Im T [Re Z | Im Z];
+  // G3: acc1 = P1, acc2 = P2, acc3 = P3
+  cg_d4 acc1[WM][WN], acc2[WM][WN], acc3[G3 ? WM : 1][G3 ? WN : 1];
 #pragma unroll
   for (int mt = 0; mt < WM; ++mt)
 #pragma unroll
     for (int nt = 0; nt < WN; ++nt) {
       acc1[mt][nt] = cg_d4{0.0, 0.0, 0.0, 0.0};
       acc2[mt][nt] = cg_d4{0.0, 0.0, 0.0, 0.0};
+      if constexpr (G3) acc3[mt][nt] = cg_d4{0.0, 0.0, 0.0, 0.0};
     }
   auto compute = [&](int buf) {
     const cplx* as = As + buf * ASZ;
@@ -409,21 +424,38 @@ __global__ __launch_bounds__(WR * WC * 64) void k_circ_gemm(DevView v, int R, co
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
       cplx a[WM];
-      double bv[WN];
 #pragma unroll
       for (int mt = 0; mt < WM; ++mt) a[mt] = as[(wr * 16 * WM + 16 * mt + j) * AS + 4 * kk + kq];
+      if constexpr (G3) {
+        cplx bz[WN];
 #pragma unroll
-      for (int nt = 0; nt < WN; ++nt) {
-        const cplx zz = bs[(4 * kk + kq) * BS + wc * 8 * WN + 8 * nt + (j & 7)];
-        bv[nt] = j < 8 ? zz.x : zz.y;
-      }
+        for (int nt = 0; nt < WN; ++nt) bz[nt] = bs[(4 * kk + kq) * BS + wc * 16 * WN + 16 * nt + j];
 #pragma unroll
-      for (int mt = 0; mt < WM; ++mt)
+        for (int mt = 0; mt < WM; ++mt) {
+          const double asum = a[mt].x + a[mt].y;
+#pragma unroll
+          for (int nt = 0; nt < WN; ++nt) {
+            const double bsum = bz[nt].x + bz[nt].y;
+            acc1[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mt].x, bz[nt].x, acc1[mt][nt], 0, 0, 0);
+            acc2[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mt].y, bz[nt].y, acc2[mt][nt], 0, 0, 0);
+            acc3[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(asum, bsum, acc3[mt][nt], 0, 0, 0);
+          }
+        }
+      } else {
+        double bv[WN];
 #pragma unroll
         for (int nt = 0; nt < WN; ++nt) {
-          acc1[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mt].x, bv[nt], acc1[mt][nt], 0, 0, 0);
-          acc2[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mt].y, bv[nt], acc2[mt][nt], 0, 0, 0);
+          const cplx zz = bs[(4 * kk + kq) * BS + wc * 8 * WN + 8 * nt + (j & 7)];
+          bv[nt] = j < 8 ? zz.x : zz.y;
         }
+#pragma unroll
+        for (int mt = 0; mt < WM; ++mt)
+#pragma unroll
+          for (int nt = 0; nt < WN; ++nt) {
+            acc1[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mt].x, bv[nt], acc1[mt][nt], 0, 0, 0);
+            acc2[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mt].y, bv[nt], acc2[mt][nt], 0, 0, 0);
+          }
+      }
     }
   };
   const int64_t nk = (Mb + BK - 1) / BK;
@@ -473,13 +505,19 @@ __global__ __launch_bounds__(WR * WC * 64) void k_circ_gemm(DevView v, int R, co
     for (int nt = 0; nt < WN; ++nt)
 #pragma unroll
       for (int vv = 0; vv < 4; ++vv) {
-        const double a1 = acc1[mt][nt][vv], a2 = acc2[mt][nt][vv];
-        const double other = __shfl_xor(a2, 8, 64);
-        const double val = j < 8 ? a1 - other : a1 + other;  // Re W (j < 8), Im W (j >= 8)
-        const double im = __shfl_xor(val, 8, 64);
         const int64_t row = row0 + wr * 16 * WM + 16 * mt + 4 * vv + kq;
-        const int col = col0 + wc * 8 * WN + 8 * nt + (j & 7);
-        if (j < 8 && row < Mb && col < R) C[row * R + col] = cmk(val, im);
+        if constexpr (G3) {
+          const double p1 = acc1[mt][nt][vv], p2 = acc2[mt][nt][vv];
+          const int col = col0 + wc * 16 * WN + 16 * nt + j;
+          if (row < Mb && col < R) C[row * R + col] = cmk(p1 - p2, acc3[mt][nt][vv] - p1 - p2);
+        } else {
+          const double a1 = acc1[mt][nt][vv], a2 = acc2[mt][nt][vv];
+          const double other = __shfl_xor(a2, 8, 64);
+          const double val = j < 8 ? a1 - other : a1 + other;  // Re W (j < 8), Im W (j >= 8)
+          const double im = __shfl_xor(val, 8, 64);
+          const int col = col0 + wc * 8 * WN + 8 * nt + (j & 7);
+          if (j < 8 && row < Mb && col < R) C[row * R + col] = cmk(val, im);
+        }
       }
 }
 
@@ -665,56 +703,67 @@ __global__ __launch_bounds__(256) void k_circ_finish_fft(
 }
 
 // Product variants: tile (rows, complex columns), K step, LDS buffers
-// (3: two buffers and two register sets), workgroup size.
+// (3: two buffers and two register sets), workgroup size, real products per
+// complex product (4, or 3 in Gauss's form).
 struct CircVariant {
-  int bm, bn, bk, db, nt;
+  int bm, bn, bk, db, nt, mult;
   void (*fn)(DevView, int, const cplx*, cplx*, const int32_t*, int, const int32_t*);
 };
 static const CircVariant kCircVar[] = {
-    {64, 64, 16, 1, 256, k_circ_gemm<2, 2, 2, 4, 16, false, false>},
-    {64, 64, 16, 2, 256, k_circ_gemm<2, 2, 2, 4, 16, true, false>},
-    {64, 32, 16, 2, 256, k_circ_gemm<2, 2, 2, 2, 16, true, false>},
-    {64, 32, 32, 2, 256, k_circ_gemm<2, 2, 2, 2, 32, true, false>},
-    {128, 32, 16, 2, 256, k_circ_gemm<2, 2, 4, 2, 16, true, false>},
-    {128, 16, 16, 2, 256, k_circ_gemm<4, 1, 2, 2, 16, true, false>},
-    {128, 8, 16, 2, 256, k_circ_gemm<4, 1, 2, 1, 16, true, false>},
-    {64, 8, 16, 2, 256, k_circ_gemm<4, 1, 1, 1, 16, true, false>},
-    {64, 32, 16, 3, 256, k_circ_gemm<2, 2, 2, 2, 16, true, true>},
-    {128, 32, 16, 2, 512, k_circ_gemm<4, 2, 2, 2, 16, true, false>},
-    {128, 32, 16, 3, 512, k_circ_gemm<4, 2, 2, 2, 16, true, true>},
-    {128, 16, 16, 3, 256, k_circ_gemm<4, 1, 2, 2, 16, true, true>},
-    {128, 32, 8, 3, 512, k_circ_gemm<4, 2, 2, 2, 8, true, true>},
-    {128, 32, 8, 2, 512, k_circ_gemm<4, 2, 2, 2, 8, true, false>},
-    {64, 32, 8, 3, 256, k_circ_gemm<2, 2, 2, 2, 8, true, true>},
-    {128, 64, 8, 3, 512, k_circ_gemm<4, 2, 2, 4, 8, true, true>},
-    {128, 64, 16, 3, 512, k_circ_gemm<4, 2, 2, 4, 16, true, true>},
-    {128, 32, 4, 2, 512, k_circ_gemm<4, 2, 2, 2, 4, true, false>},
-    {128, 32, 8, 2, 1024, k_circ_gemm<8, 2, 1, 2, 8, true, false>},
-    {64, 32, 8, 2, 256, k_circ_gemm<2, 2, 2, 2, 8, true, false>},
-    {128, 16, 8, 2, 256, k_circ_gemm<4, 1, 2, 2, 8, true, false>},
-    {128, 8, 8, 2, 256, k_circ_gemm<4, 1, 2, 1, 8, true, false>},
-    {256, 32, 8, 2, 512, k_circ_gemm<4, 2, 4, 2, 8, true, false>},
+    {64, 64, 16, 1, 256, 4, k_circ_gemm<2, 2, 2, 4, 16, false, false>},
+    {64, 64, 16, 2, 256, 4, k_circ_gemm<2, 2, 2, 4, 16, true, false>},
+    {64, 32, 16, 2, 256, 4, k_circ_gemm<2, 2, 2, 2, 16, true, false>},
+    {64, 32, 32, 2, 256, 4, k_circ_gemm<2, 2, 2, 2, 32, true, false>},
+    {128, 32, 16, 2, 256, 4, k_circ_gemm<2, 2, 4, 2, 16, true, false>},
+    {128, 16, 16, 2, 256, 4, k_circ_gemm<4, 1, 2, 2, 16, true, false>},
+    {128, 8, 16, 2, 256, 4, k_circ_gemm<4, 1, 2, 1, 16, true, false>},
+    {64, 8, 16, 2, 256, 4, k_circ_gemm<4, 1, 1, 1, 16, true, false>},
+    {64, 32, 16, 3, 256, 4, k_circ_gemm<2, 2, 2, 2, 16, true, true>},
+    {128, 32, 16, 2, 512, 4, k_circ_gemm<4, 2, 2, 2, 16, true, false>},
+    {128, 32, 16, 3, 512, 4, k_circ_gemm<4, 2, 2, 2, 16, true, true>},
+    {128, 16, 16, 3, 256, 4, k_circ_gemm<4, 1, 2, 2, 16, true, true>},
+    {128, 32, 8, 3, 512, 4, k_circ_gemm<4, 2, 2, 2, 8, true, true>},
+    {128, 32, 8, 2, 512, 4, k_circ_gemm<4, 2, 2, 2, 8, true, false>},
+    {64, 32, 8, 3, 256, 4, k_circ_gemm<2, 2, 2, 2, 8, true, true>},
+    {128, 64, 8, 3, 512, 4, k_circ_gemm<4, 2, 2, 4, 8, true, true>},
+    {128, 64, 16, 3, 512, 4, k_circ_gemm<4, 2, 2, 4, 16, true, true>},
+    {128, 32, 4, 2, 512, 4, k_circ_gemm<4, 2, 2, 2, 4, true, false>},
+    {128, 32, 8, 2, 1024, 4, k_circ_gemm<8, 2, 1, 2, 8, true, false>},
+    {64, 32, 8, 2, 256, 4, k_circ_gemm<2, 2, 2, 2, 8, true, false>},
+    {128, 16, 8, 2, 256, 4, k_circ_gemm<4, 1, 2, 2, 8, true, false>},
+    {128, 8, 8, 2, 256, 4, k_circ_gemm<4, 1, 2, 1, 8, true, false>},
+    {256, 32, 8, 2, 512, 4, k_circ_gemm<4, 2, 4, 2, 8, true, false>},
+    // Gauss's three-product form (16-column wave tiles)
+    {128, 32, 8, 2, 512, 3, k_circ_gemm<4, 2, 2, 1, 8, true, false, true>},
+    {128, 32, 16, 2, 512, 3, k_circ_gemm<4, 2, 2, 1, 16, true, false, true>},
+    {128, 32, 8, 3, 512, 3, k_circ_gemm<4, 2, 2, 1, 8, true, true, true>},
+    {128, 64, 8, 2, 512, 3, k_circ_gemm<4, 2, 2, 2, 8, true, false, true>},
+    {256, 32, 8, 2, 512, 3, k_circ_gemm<4, 2, 4, 1, 8, true, false, true>},
+    {64, 32, 8, 2, 256, 3, k_circ_gemm<2, 2, 2, 1, 8, true, false, true>},
+    {128, 16, 8, 2, 256, 3, k_circ_gemm<4, 1, 2, 1, 8, true, false, true>},
+    {128, 16, 16, 2, 256, 3, k_circ_gemm<4, 1, 2, 1, 16, true, false, true>},
 };
 #define N_CIRC_VAR ((int)(sizeof(kCircVar) / sizeof(kCircVar[0])))
 
 // Default product variant for R columns, and the variants worth timing.
 int circ_variant(int R) { return R >= 48 ? 2 : (R >= 24 ? 2 : (R >= 12 ? 5 : 6)); }
 std::vector<int> circ_variants(int R) {
-  if (R >= 48) return {2, 8, 9, 10, 12, 13, 14, 15, 16, 17, 18, 19, 22};
-  if (R >= 24) return {2, 3, 4, 8, 9, 10, 12, 13, 14, 19};
-  if (R >= 12) return {5, 6, 11, 20};
+  if (R >= 48) return {2, 8, 9, 10, 12, 13, 14, 15, 16, 17, 18, 19, 22, 23, 24, 25, 26, 27, 28};
+  if (R >= 24) return {2, 3, 4, 8, 9, 10, 12, 13, 14, 19, 23, 24, 28};
+  if (R >= 12) return {5, 6, 11, 20, 29, 30};
   return {6, 7, 21};
 }
 void circ_tile(int var, int* bm, int* bn) {
   *bm = kCircVar[var].bm;
   *bn = kCircVar[var].bn;
 }
-void circ_var_dims(int var, int* bm, int* bn, int* bk, int* db, int* nt) {
+void circ_var_dims(int var, int* bm, int* bn, int* bk, int* db, int* nt, int* mult) {
   *bm = kCircVar[var].bm;
   *bn = kCircVar[var].bn;
   *bk = kCircVar[var].bk;
   *db = kCircVar[var].db;
   *nt = kCircVar[var].nt;
+  *mult = kCircVar[var].mult;
 }
 
 // Enqueue the transforms of the inputs and the per-frequency products.

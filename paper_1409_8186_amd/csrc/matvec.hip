@@ -746,7 +746,7 @@ static bool use_mfma(const mudiff_ctx* h, int R) {
 int circ_variant(int R);
 std::vector<int> circ_variants(int R);
 void circ_tile(int var, int* bm, int* bn);
-void circ_var_dims(int var, int* bm, int* bn, int* bk, int* db, int* nt);
+void circ_var_dims(int var, int* bm, int* bn, int* bk, int* db, int* nt, int* mult);
 int circ_finish(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, const cplx* part, int64_t blk,
                 int npad, int RC, const int32_t* dgrp, const int32_t* drow, const int32_t* gnseg,
                 const int64_t* gbase, const int32_t* active, const cplx* wh, const int32_t* con,
@@ -1702,34 +1702,35 @@ extern "C" int mudiff_set_circulant(mudiff_t h, int R, int mode) {
 }
 
 extern "C" int mudiff_circulant_tile(mudiff_t h, int R, int* rows, int* cols, int* kstep,
-                                     int* stages, int* threads) {
+                                     int* stages, int* threads, int* mults) {
   if (!h) return fail(MUDIFF_ERR_INVALID, "NULL handle");
   if (R < 1) return fail(MUDIFF_ERR_INVALID, "R < 1");
-  int bm = 0, bn = 0, bk = 0, db = 0, nt = 0;
+  int bm = 0, bn = 0, bk = 0, db = 0, nt = 0, mu = 0;
   if (use_mfma(h, R)) {
     auto f = h->mfma_choice.find(R);
     MfmaChoice ch = f != h->mfma_choice.end() ? f->second : mfma_default(R);
     if (f == h->mfma_choice.end()) ch.circ = circ_usable(h, R);
-    if (ch.circ) circ_var_dims(ch.cvar >= 0 ? ch.cvar : circ_variant(R), &bm, &bn, &bk, &db, &nt);
+    if (ch.circ) circ_var_dims(ch.cvar >= 0 ? ch.cvar : circ_variant(R), &bm, &bn, &bk, &db, &nt, &mu);
   }
   if (rows) *rows = bm;
   if (cols) *cols = bn;
   if (kstep) *kstep = bk;
   if (stages) *stages = db;
   if (threads) *threads = nt;
+  if (mults) *mults = mu;
   return MUDIFF_OK;
 }
 
 extern "C" int mudiff_set_circulant_tile(mudiff_t h, int R, int rows, int cols, int kstep,
-                                         int stages, int threads) {
+                                         int stages, int threads, int mults) {
   if (!h) return fail(MUDIFF_ERR_INVALID, "NULL handle");
   if (R < 1) return fail(MUDIFF_ERR_INVALID, "R < 1");
   if (!use_mfma(h, R) || !circ_usable(h, R))
     return fail(MUDIFF_ERR_INVALID, "this apply does not use the circulant form");
   for (int v : circ_variants(R)) {
-    int bm, bn, bk, db, nt;
-    circ_var_dims(v, &bm, &bn, &bk, &db, &nt);
-    if (bm == rows && bn == cols && bk == kstep && db == stages && nt == threads) {
+    int bm, bn, bk, db, nt, mu;
+    circ_var_dims(v, &bm, &bn, &bk, &db, &nt, &mu);
+    if (bm == rows && bn == cols && bk == kstep && db == stages && nt == threads && mu == mults) {
       auto f = h->mfma_choice.find(R);
       MfmaChoice ch = f != h->mfma_choice.end() ? f->second : mfma_default(R);
       ch.circ = true;

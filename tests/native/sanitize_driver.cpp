@@ -241,8 +241,8 @@ static void cpu_mode() {
   STATUS(mudiff_sizes(nullptr, &i64), MUDIFF_ERR_INVALID);
   STATUS(mudiff_circulant_info(nullptr, &i64, &i64, &i32), MUDIFF_ERR_INVALID);
   STATUS(mudiff_set_circulant(nullptr, 8, 1), MUDIFF_ERR_INVALID);
-  STATUS(mudiff_circulant_tile(nullptr, 8, &i32, &i32, &i32, &i32, &i32), MUDIFF_ERR_INVALID);
-  STATUS(mudiff_set_circulant_tile(nullptr, 8, 64, 32, 16, 2, 256), MUDIFF_ERR_INVALID);
+  STATUS(mudiff_circulant_tile(nullptr, 8, &i32, &i32, &i32, &i32, &i32, &i32), MUDIFF_ERR_INVALID);
+  STATUS(mudiff_set_circulant_tile(nullptr, 8, 64, 32, 16, 2, 256, 4), MUDIFF_ERR_INVALID);
   STATUS(mudiff_disk_tables(nullptr, nullptr, nullptr, nullptr), MUDIFF_ERR_INVALID);
   STATUS(mudiff_pair_tables(nullptr, nullptr, &i64, nullptr), MUDIFF_ERR_INVALID);
   STATUS(mudiff_apply_config(nullptr, 1, &i32, &i32, &i32, &i32, &i32, nullptr),
@@ -465,23 +465,27 @@ static void gpu_circulant(std::mt19937_64& g) {
     float ms = 0;
     STATUS(mudiff_apply_config(H.h, R, &kind, &ct, &rp, &qs, &th, &ms), MUDIFF_OK);
     EXPECT(kind == 3, "circulant kind at R=%d: %d", R, kind);
-    static const int tiles[][5] = {{64, 64, 16, 1, 256},  {64, 64, 16, 2, 256},
-                                   {64, 32, 32, 2, 256},  {128, 32, 16, 3, 512},
-                                   {64, 32, 16, 3, 256},  {128, 16, 16, 2, 256},
-                                   {128, 16, 16, 3, 256}, {128, 8, 16, 2, 256},
-                                   {64, 8, 16, 2, 256},   {128, 32, 8, 3, 512},
-                                   {128, 64, 8, 3, 512},  {128, 32, 8, 2, 1024},
-                                   {256, 32, 8, 2, 512},  {128, 8, 8, 2, 256}};
+    static const int tiles[][6] = {{64, 64, 16, 1, 256, 4},  {64, 64, 16, 2, 256, 4},
+                                   {64, 32, 32, 2, 256, 4},  {128, 32, 16, 3, 512, 4},
+                                   {64, 32, 16, 3, 256, 4},  {128, 16, 16, 2, 256, 4},
+                                   {128, 16, 16, 3, 256, 4}, {128, 8, 16, 2, 256, 4},
+                                   {64, 8, 16, 2, 256, 4},   {128, 32, 8, 3, 512, 4},
+                                   {128, 64, 8, 3, 512, 4},  {128, 32, 8, 2, 1024, 4},
+                                   {256, 32, 8, 2, 512, 4},  {128, 8, 8, 2, 256, 4},
+                                   {128, 32, 8, 2, 512, 3},  {128, 64, 8, 2, 512, 3},
+                                   {128, 16, 8, 2, 256, 3},  {64, 32, 8, 2, 256, 3}};
     for (const auto& tile : tiles) {
-      const int st = mudiff_set_circulant_tile(H.h, R, tile[0], tile[1], tile[2], tile[3], tile[4]);
+      const int st = mudiff_set_circulant_tile(H.h, R, tile[0], tile[1], tile[2], tile[3], tile[4],
+                                               tile[5]);
       if (st != MUDIFF_OK) continue;  // not a candidate for this R
       const auto y = apply(H, dev, R, x, MUDIFF_OP_A);
-      EXPECT(rel_diff(y, y_dir) < 1e-12, "tile %dx%d at R=%d", tile[0], tile[1], R);
-      int r2 = 0, c2 = 0, k2 = 0, s2 = 0, t2 = 0;
-      STATUS(mudiff_circulant_tile(H.h, R, &r2, &c2, &k2, &s2, &t2), MUDIFF_OK);
-      EXPECT(r2 == tile[0] && c2 == tile[1], "tile readback");
+      EXPECT(rel_diff(y, y_dir) < 1e-12, "tile %dx%d (%d products) at R=%d", tile[0], tile[1], tile[5], R);
+      int r2 = 0, c2 = 0, k2 = 0, s2 = 0, t2 = 0, m2 = 0;
+      STATUS(mudiff_circulant_tile(H.h, R, &r2, &c2, &k2, &s2, &t2, &m2), MUDIFF_OK);
+      EXPECT(r2 == tile[0] && c2 == tile[1] && m2 == tile[5], "tile readback");
     }
-    STATUS(mudiff_set_circulant_tile(H.h, R, 48, 48, 16, 2, 256), MUDIFF_ERR_INVALID);
+    STATUS(mudiff_set_circulant_tile(H.h, R, 48, 48, 16, 2, 256, 4), MUDIFF_ERR_INVALID);
+    STATUS(mudiff_set_circulant_tile(H.h, R, 128, 32, 8, 2, 512, 2), MUDIFF_ERR_INVALID);
     STATUS(mudiff_set_apply_config(H.h, R, 1, 8, 32, 512), MUDIFF_OK);
     const auto y_cfg = apply(H, dev, R, x, MUDIFF_OP_A);
     EXPECT(rel_diff(y_cfg, y_dir) < 1e-12, "apply config at R=%d", R);

@@ -769,9 +769,9 @@ void circ_var_dims(int var, int* bm, int* bn, int* bk, int* db, int* nt, int* mu
 // Enqueue the transforms of the inputs and the per-frequency products.
 // z: inputs scaled by their column factors [B][R][N_b]; zh, wh: [sum_b L_b M_b][R].
 // Which transform kernels a launch needs: instances in the form with L_b =
-// 2^a 3^b (fast transforms; *fft_wide when one of them is longer than 81, so
-// that the launch takes 8 right-hand sides per workgroup instead of 16) and
-// with other lengths (direct sums).
+// 2^a 3^b (fast transforms, 8 right-hand sides per workgroup; *fft_wide when
+// one of them is longer than 81, so that the launch sizes its LDS for 128
+// frequencies instead of 81) and with other lengths (direct sums).
 static void circ_kinds(const mudiff_ctx* h, const int32_t* con_h, bool* fft, bool* dft,
                        bool* fft_wide = nullptr) {
   *fft = *dft = false;
@@ -790,13 +790,12 @@ int circ_launch(mudiff_ctx* h, int R, const cplx* z, cplx* zh, cplx* wh, const i
                 const int32_t* active, hipStream_t s) {
   bool fft, dft, wide;
   circ_kinds(h, con_h, &fft, &dft, &wide);
-  wide |= R <= 8;  // 8 right-hand sides per workgroup: no idle half at R <= 8
   const int cw = R >= CF_R ? CF_R : (R > 8 ? 16 : 8);
   if (dft)
     hipLaunchKernelGGL(k_circ_fwd, dim3((unsigned)h->M_all, (unsigned)((R + cw - 1) / cw)), dim3(256), 0,
                        s, h->dv, R, z, zh, con, active);
   if (fft && !wide)
-    hipLaunchKernelGGL((k_circ_fwd_fft<16, 81>), dim3((unsigned)h->M_all, (unsigned)((R + 15) / 16)),
+    hipLaunchKernelGGL((k_circ_fwd_fft<8, 81>), dim3((unsigned)h->M_all, (unsigned)((R + 7) / 8)),
                        dim3(256), 0, s, h->dv, R, z, zh, con, active);
   if (fft && wide)
     hipLaunchKernelGGL((k_circ_fwd_fft<8, CF_LMAX>), dim3((unsigned)h->M_all, (unsigned)((R + 7) / 8)),
@@ -818,9 +817,8 @@ int circ_finish(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, const cplx
                 const int32_t* con_h, const cplx* shift, hipStream_t s) {
   bool fft, dft, wide;
   circ_kinds(h, con_h, &fft, &dft, &wide);
-  wide |= R <= 8;
   if (fft && !wide)
-    hipLaunchKernelGGL((k_circ_finish_fft<16, 81>), dim3((unsigned)h->M_all, (unsigned)((R + 15) / 16)),
+    hipLaunchKernelGGL((k_circ_finish_fft<8, 81>), dim3((unsigned)h->M_all, (unsigned)((R + 7) / 8)),
                        dim3(256), 0, s, h->dv, R, x, y, op, part, blk, npad, RC, dgrp, drow, gnseg,
                        gbase, active, wh, con, shift);
   if (fft && wide)

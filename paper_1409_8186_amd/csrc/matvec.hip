@@ -1174,31 +1174,32 @@ static int mfma_autotune(mudiff_ctx* h, int R, const cplx* x, cplx* y, char* scr
     }
   if (cmode != 1 || !cu)
     for (const MfmaChoice& c : mfma_candidates(R)) cands.push_back(c);
-  // one warm-up and two timed applies of candidate c; keeps the fastest
-  auto time_one = [&](const MfmaChoice& c) {
+  // one warm-up and two timed applies of candidate c; keeps the fastest (and
+  // returns the time, 0 when skipped or failed)
+  auto time_one = [&](const MfmaChoice& c) -> float {
     MfmaSched S;
     mfma_build(h, R, c, S);
     struct Drain {  // the local schedule's copies finish before it is released
       hipStream_t st;
       ~Drain() { (void)hipStreamSynchronize(st); }
     } drain{s};
-    if ((rc = mfma_upload(h, S, scratch, s)) != MUDIFF_OK) return;
+    if ((rc = mfma_upload(h, S, scratch, s)) != MUDIFF_OK) return 0.0f;
     (void)hipEventRecord(e0, s);
-    if ((rc = mfma_launch(h, S, x, y, MUDIFF_OP_A, nullptr, s)) != MUDIFF_OK) return;  // warm-up
+    if ((rc = mfma_launch(h, S, x, y, MUDIFF_OP_A, nullptr, s)) != MUDIFF_OK) return 0.0f;  // warm-up
     (void)hipEventRecord(e1, s);
     if (best > 0.0f) {  // a warm-up already twice as slow as the best pair of applies: no contender
       float w = 0.0f;
       if (hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&w, e0, e1) == hipSuccess &&
           w > best)
-        return;
+        return 0.0f;
     }
     (void)hipEventRecord(e0, s);
     for (int k = 0; k < 2 && rc == MUDIFF_OK; ++k) rc = mfma_launch(h, S, x, y, MUDIFF_OP_A, nullptr, s);
     (void)hipEventRecord(e1, s);
-    if (rc != MUDIFF_OK) return;
+    if (rc != MUDIFF_OK) return 0.0f;
     if (hipEventSynchronize(e1) != hipSuccess) {
       rc = fail(MUDIFF_ERR_DEVICE, "autotune: event synchronisation failed");
-      return;
+      return 0.0f;
     }
     float ms = 0.0f;
     (void)hipEventElapsedTime(&ms, e0, e1);
@@ -1206,6 +1207,7 @@ static int mfma_autotune(mudiff_ctx* h, int R, const cplx* x, cplx* y, char* scr
       best = ms;
       bc = c;
     }
+    return ms;
   };
   for (const MfmaChoice& c : cands) {
     if (c.QS > 0 && mmax <= c.QS) continue;
@@ -1214,12 +1216,41 @@ static int mfma_autotune(mudiff_ctx* h, int R, const cplx* x, cplx* y, char* scr
   }
   if (rc == MUDIFF_OK && bc.circ) {  // then the per-frequency product variants on that tile
     const MfmaChoice base = bc;
+    std::vector<std::pair<float, MfmaChoice>> seen{{best, base}};
     for (int cv : circ_variants(R)) {
       if (cv == circ_variant(R)) continue;
       MfmaChoice c = base;
       c.cvar = cv;
-      time_one(c);
+      const float ms = time_one(c);
       if (rc != MUDIFF_OK) break;
+      if (ms > 0.0f) seen.push_back({ms, c});
+    }
+    // variants a few percent apart swap places from one timing to the next:
+    // the three fastest are timed three times more and ranked by their mean
+    if (rc == MUDIFF_OK && seen.size() > 1) {
+      std::stable_sort(seen.begin(), seen.end(),
+                       [](const std::pair<float, MfmaChoice>& a, const std::pair<float, MfmaChoice>& b) {
+                         return a.first < b.first;
+                       });
+      seen.resize(std::min<size_t>(seen.size(), 3));
+      float bmean = 0.0f;
+      MfmaChoice bbest = bc;
+      for (const auto& sc : seen) {
+        float sum = 0.0f;
+        for (int rep = 0; rep < 3 && rc == MUDIFF_OK; ++rep) {
+          best = 0.0f;  // time every repetition in full
+          sum += time_one(sc.second);
+        }
+        if (rc != MUDIFF_OK) break;
+        if (bmean == 0.0f || sum / 3.0f < bmean) {
+          bmean = sum / 3.0f;
+          bbest = sc.second;
+        }
+      }
+      if (rc == MUDIFF_OK) {
+        bc = bbest;
+        best = bmean;
+      }
     }
   }
   (void)hipEventDestroy(e0);

@@ -583,9 +583,11 @@ __global__ __launch_bounds__(THREADS) void k_apply_mfma(
 // and accumulates the whole row in registers; the sum goes to segment 0 of the
 // row's group, which the output pass adds.  In the work queue the same pairs
 // cost two barriers and an LDS staging round per listed column disk, with only
-// the few waves whose row is close to it on the matrix cores.
+// the few waves whose row is close to it on the matrix cores.  The kernel is
+// bound by load latency, so its register budget is held to five waves per SIMD
+// (without it the four-tile instance takes four).
 template <int MT>
-__global__ __launch_bounds__(64) void k_apply_close(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_apply_close(
     DevView v, int R, const cplx* __restrict__ z, cplx* __restrict__ part, int64_t blk, int npad,
     const int32_t* __restrict__ dgrp, const int32_t* __restrict__ drow,
     const int64_t* __restrict__ gbase, const int32_t* __restrict__ nptr,

@@ -574,8 +574,8 @@ __global__ __launch_bounds__(THREADS) void k_apply_mfma(
 }
 
 // Close pairs of the instances in the circulant form with 8-column tiles (few
-// right-hand sides): one wave per (row disk p, tile of 8 columns), no LDS and
-// no barriers.  The wave walks p's close list; per column disk q and k step it
+// right-hand sides): one wave per (row disk p, tile of 8 columns, group of row
+// tiles), no LDS and no barriers.  The wave walks p's close list; per column disk q and k step it
 // loads the input panel element of its lane (B[k][j]: Re or Im of column j & 7
 // at mode 4 kt + k) and per row tile the symbol value of its lane (A[i][k]:
 // t_{(n - N_q) - (m - N_p)}, m = 16 mt + i), straight into the operand layout
@@ -584,32 +584,37 @@ __global__ __launch_bounds__(THREADS) void k_apply_mfma(
 // row's group, which the output pass adds.  In the work queue the same pairs
 // cost two barriers and an LDS staging round per listed column disk, with only
 // the few waves whose row is close to it on the matrix cores.  The kernel is
-// bound by load latency, so its register budget is held to five waves per SIMD
-// (without it the four-tile instance takes four).
-template <int MT>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_apply_close(
+// bound by load latency, so the row tiles of a row disk are split over waves
+// (MTW tiles each, blockIdx.z the group): with the accumulators of two tiles
+// the register budget is held to eight waves per SIMD, at one more input load
+// per k step.
+template <int MT, int MTW>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_apply_close(
     DevView v, int R, const cplx* __restrict__ z, cplx* __restrict__ part, int64_t blk, int npad,
     const int32_t* __restrict__ dgrp, const int32_t* __restrict__ drow,
     const int64_t* __restrict__ gbase, const int32_t* __restrict__ nptr,
     const int32_t* __restrict__ nql, const int32_t* __restrict__ con,
     const int32_t* __restrict__ active) {
   const int p = blockIdx.x, t = blockIdx.y, lane = threadIdx.x;
+  const int mt0 = MTW * (int)blockIdx.z;  // first row tile of this wave
   const int b = v.inst[p];
   if (!con[b]) return;
   const int c0 = 8 * t;
   if (c0 >= R) return;
+  const int Np = v.N[p], np_ = 2 * Np + 1, mtp = (np_ + 15) >> 4;
+  // tiles from 16 mtp on hold no mode of p and are never read
+  if (mt0 >= mtp) return;
   if (active) {
     bool any = false;
     for (int r = c0; r < min(R, c0 + 8); ++r) any |= active[b * R + r] != 0;
     if (!any) return;
   }
   const int j = lane & 15, kq = lane >> 4;
-  const int Np = v.N[p], np_ = 2 * Np + 1, mtp = (np_ + 15) >> 4;
-  mf_d4 acc1[MT], acc2[MT];
+  mf_d4 acc1[MTW], acc2[MTW];
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt) {
-    acc1[mt] = mf_d4{0.0, 0.0, 0.0, 0.0};
-    acc2[mt] = mf_d4{0.0, 0.0, 0.0, 0.0};
+  for (int i = 0; i < MTW; ++i) {
+    acc1[i] = mf_d4{0.0, 0.0, 0.0, 0.0};
+    acc2[i] = mf_d4{0.0, 0.0, 0.0, 0.0};
   }
   const int col = c0 + (j & 7);
   const bool colok = col < R;
@@ -628,7 +633,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
         bv = j < 8 ? zz.x : zz.y;
       }
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
+      for (int i = 0; i < MTW; ++i) {
+        const int mt = mt0 + i;
         if (mt < mtp) {  // wave-uniform
           const int m = 16 * mt + j;
           cplx a = cmk(0.0, 0.0);
@@ -637,8 +643,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
             a = trow[sv];
             if (flip && (sv & 1)) a = cmk(-a.x, -a.y);
           }
-          acc1[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, bv, acc1[mt], 0, 0, 0);
-          acc2[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, bv, acc2[mt], 0, 0, 0);
+          acc1[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, bv, acc1[i], 0, 0, 0);
+          acc2[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, bv, acc2[i], 0, 0, 0);
         }
       }
     }
@@ -646,10 +652,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
   // segment 0 of the group's tile t: [RP][npad][8]
   cplx* pbk = part + (gbase[dgrp[p]] + t) * blk + (int64_t)drow[p] * npad * 8 + (j & 7);
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt) {
+  for (int i = 0; i < MTW; ++i) {
+    const int mt = mt0 + i;
+    if (mt >= MT) break;
 #pragma unroll
     for (int vv = 0; vv < 4; ++vv) {
-      const double a1 = acc1[mt][vv], a2 = acc2[mt][vv];
+      const double a1 = acc1[i][vv], a2 = acc2[i][vv];
       const double other = __shfl_xor(a2, 8, 64);
       const double val = j < 8 ? a1 - other : a1 + other;  // Re W (j < 8), Im W (j >= 8)
       const double im = __shfl_xor(val, 8, 64);
@@ -1098,10 +1106,11 @@ static int mfma_launch(mudiff_ctx* h, const MfmaSched& S, const cplx* x, cplx* y
     typedef void (*close_fn)(DevView, int, const cplx*, cplx*, int64_t, int, const int32_t*,
                              const int32_t*, const int64_t*, const int32_t*, const int32_t*,
                              const int32_t*, const int32_t*);
-    static const close_fn kClose[5] = {nullptr, k_apply_close<1>, k_apply_close<2>, k_apply_close<3>,
-                                       k_apply_close<4>};
+    static const close_fn kClose[5] = {nullptr, k_apply_close<1, 1>, k_apply_close<2, 2>,
+                                       k_apply_close<3, 2>, k_apply_close<4, 2>};
     if (mt < 1 || mt > 4) return fail(MUDIFF_ERR_INVALID, "close pairs: orders out of range");
-    hipLaunchKernelGGL(kClose[mt], dim3((unsigned)h->M_all, (unsigned)S.ntile), dim3(64), 0, s, h->dv,
+    const unsigned zg = mt > 2 ? 2u : 1u;  // groups of two row tiles
+    hipLaunchKernelGGL(kClose[mt], dim3((unsigned)h->M_all, (unsigned)S.ntile, zg), dim3(64), 0, s, h->dv,
                        S.R, (const cplx*)z, part, S.blk, S.npad, (const int32_t*)(base + off[2]),
                        (const int32_t*)(base + off[8]), (const int64_t*)(base + off[5]),
                        (const int32_t*)(base + off[14]), (const int32_t*)(base + off[15]), con, active);

@@ -289,7 +289,7 @@ __global__ __launch_bounds__(256) void k_circ_fwd_fft(DevView v, int R, const cp
   const int b = v.inst[q];
   if (!con[b]) return;
   const int Lb = v.cL[b];
-  if (!circ_fft_len(Lb) || Lb > LM) return;
+  if (!circ_fft_len(Lb) || Lb > LM || Lb <= (LM > 81 ? 81 : 0)) return;  // this launch's length class
   const int r0 = blockIdx.y * CR;
   if (r0 >= R) return;
   if (active) {
@@ -666,7 +666,7 @@ __global__ __launch_bounds__(256) void k_circ_finish_fft(
   const int b = v.inst[p];
   if (!con[b]) return;
   const int Lb = v.cL[b];
-  if (!circ_fft_len(Lb) || Lb > LM) return;
+  if (!circ_fft_len(Lb) || Lb > LM || Lb <= (LM > 81 ? 81 : 0)) return;  // this launch's length class
   const int r0 = blockIdx.y * CR;
   if (r0 >= R) return;
   if (active) {
@@ -769,20 +769,18 @@ void circ_var_dims(int var, int* bm, int* bn, int* bk, int* db, int* nt, int* mu
 // Enqueue the transforms of the inputs and the per-frequency products.
 // z: inputs scaled by their column factors [B][R][N_b]; zh, wh: [sum_b L_b M_b][R].
 // Which transform kernels a launch needs: instances in the form with L_b =
-// 2^a 3^b (fast transforms, 8 right-hand sides per workgroup; *fft_wide when
-// one of them is longer than 81, so that the launch sizes its LDS for 128
-// frequencies instead of 81) and with other lengths (direct sums).
+// 2^a 3^b (fast transforms, 8 right-hand sides per workgroup, in two length
+// classes with their own LDS size: *fft for L_b <= 81, *fft_wide for longer
+// ones) and with other lengths (direct sums).
 static void circ_kinds(const mudiff_ctx* h, const int32_t* con_h, bool* fft, bool* dft,
-                       bool* fft_wide = nullptr) {
-  *fft = *dft = false;
-  bool wide = false;
+                       bool* fft_wide) {
+  *fft = *dft = *fft_wide = false;
   for (int b = 0; b < h->B; ++b) {
     if (!con_h[b]) continue;
-    const bool f = circ_fft_len(h->cL[b]);
-    (f ? *fft : *dft) = true;
-    wide |= f && h->cL[b] > 81;
+    if (!circ_fft_len(h->cL[b])) *dft = true;
+    else if (h->cL[b] > 81) *fft_wide = true;
+    else *fft = true;
   }
-  if (fft_wide) *fft_wide = wide;
 }
 
 int circ_launch(mudiff_ctx* h, int R, const cplx* z, cplx* zh, cplx* wh, const int32_t* citems,
@@ -794,10 +792,10 @@ int circ_launch(mudiff_ctx* h, int R, const cplx* z, cplx* zh, cplx* wh, const i
   if (dft)
     hipLaunchKernelGGL(k_circ_fwd, dim3((unsigned)h->M_all, (unsigned)((R + cw - 1) / cw)), dim3(256), 0,
                        s, h->dv, R, z, zh, con, active);
-  if (fft && !wide)
+  if (fft)
     hipLaunchKernelGGL((k_circ_fwd_fft<8, 81>), dim3((unsigned)h->M_all, (unsigned)((R + 7) / 8)),
                        dim3(256), 0, s, h->dv, R, z, zh, con, active);
-  if (fft && wide)
+  if (wide)
     hipLaunchKernelGGL((k_circ_fwd_fft<8, CF_LMAX>), dim3((unsigned)h->M_all, (unsigned)((R + 7) / 8)),
                        dim3(256), 0, s, h->dv, R, z, zh, con, active);
   HIP_TRY(hipGetLastError());
@@ -817,11 +815,11 @@ int circ_finish(mudiff_ctx* h, int R, const cplx* x, cplx* y, int op, const cplx
                 const int32_t* con_h, const cplx* shift, hipStream_t s) {
   bool fft, dft, wide;
   circ_kinds(h, con_h, &fft, &dft, &wide);
-  if (fft && !wide)
+  if (fft)
     hipLaunchKernelGGL((k_circ_finish_fft<8, 81>), dim3((unsigned)h->M_all, (unsigned)((R + 7) / 8)),
                        dim3(256), 0, s, h->dv, R, x, y, op, part, blk, npad, RC, dgrp, drow, gnseg,
                        gbase, active, wh, con, shift);
-  if (fft && wide)
+  if (wide)
     hipLaunchKernelGGL((k_circ_finish_fft<8, CF_LMAX>), dim3((unsigned)h->M_all, (unsigned)((R + 7) / 8)),
                        dim3(256), 0, s, h->dv, R, x, y, op, part, blk, npad, RC, dgrp, drow, gnseg,
                        gbase, active, wh, con, shift);

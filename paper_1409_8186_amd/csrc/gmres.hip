@@ -2711,9 +2711,19 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
         }
       }
     }
-    if (sb == 0 && ss == 0 && !use_graph && s.C >= 32 && n_run * 32 <= s.C &&
+    if (sb == 0 && ss == 0 && s.C >= 32 && n_run * 32 <= s.C &&
         (G.n_compact == 0 || n_run * 2 <= G.n_compact)) {
       if ((result = compact_columns(G, hstat, n_run)) != MUDIFF_OK) break;
+      // the captured cycle launches the full apply and sweeps: capture it again
+      // on the running columns (the stream is idle since the status copy)
+      if (exec) {
+        (void)hipGraphExecDestroy(exec);
+        exec = nullptr;
+      }
+      if (graph) {
+        (void)hipGraphDestroy(graph);
+        graph = nullptr;
+      }
     }
     if (use_graph) {
       if (!exec) {

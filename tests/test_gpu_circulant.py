@@ -356,3 +356,9 @@ def test_circulant_gmres_graph_and_stragglers(P):
     assert it[B // 2].min() > 4 * np.delete(it, B // 2, axis=0).max()
     for c, b, Y in zip(allc, bet, pr2.split(rho, R)):
         assert rel(Y.cpu().numpy(), _lu(c, b)) < 1e-10
+    # replayed cycles with the straggler phase: the graph is captured again after
+    # each compaction, and the solve is bit-identical to the eager one
+    for rep in range(2):
+        rho_g, flag_g, _, iters_g, _ = pr2.gmres(betas=bet, restart=10, tol=1e-12, maxit=5000, graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(iters_g, iters) and torch.equal(flag_g, flag) and torch.equal(rho_g, rho), rep

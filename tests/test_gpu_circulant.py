@@ -172,7 +172,8 @@ def _fft_batch():
 
 def _wide_batch():
     """A length above 81 (L_min = 97 raised to 108 = 2^2 3^3: the launch then
-    takes 8 right-hand sides per workgroup) beside L = 27 and L = 48."""
+    runs the transforms of both length classes, 108 in the 128-length kernels
+    and 27, 48 in the 81-length ones) beside L = 27 and L = 48."""
     c108 = synth.small_random(543, 14, 0.8, 1.0, 46.0, 0.2, 9.0, 10)
     c108 = synth.Cluster(c108.centers, c108.radii, np.full(c108.M, 24, np.int32), c108.k)
     return [_fixed_orders(540, 24, 30.0, 6.0, 7, 6), c108, _mixed(503)]
@@ -210,9 +211,9 @@ def test_circulant_fft_lengths(P, R):
 
 @pytest.mark.parametrize("R", [8, 19])
 def test_circulant_lengths_above_81(P, R):
-    """L = 108 (2^2 3^3) in a launch with L = 27 and 48: every fast transform
-    of the launch runs 8 right-hand sides per workgroup; A, L and L^T against
-    the dense oracle, and lockstep GMRES against LU."""
+    """L = 108 (2^2 3^3) in a launch with L = 27 and 48: the fast transforms
+    of the launch run in two length classes (up to 81, and 128); A, L and L^T
+    against the dense oracle, and lockstep GMRES against LU."""
     cls = _wide_batch()
     assert [_embed_len(c.n_modes) for c in cls] == [27, 108, 48]
     pr = P.from_clusters(cls, circulant=True)

@@ -212,6 +212,11 @@ struct mudiff_ctx {
   std::map<int, size_t> mfma_bytes;       // apply scratch per R (largest candidate)
   MfmaSched mfma_sched;                   // current schedule (host copy + upload location)
   hipEvent_t sched_ev = nullptr;          // recorded after the last schedule upload
+  // in the straggler phase the circulant form's close pairs run beside its
+  // transforms and products: a second stream (default priority) forked after
+  // the input scaling and joined before the output pass
+  hipStream_t aux = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   bool sched_pending = false;             // its copies may still read the host vectors
   bool mfma_tail = false;                 // straggler schedule (few columns still iterating)
   std::vector<int32_t> mfma_tail_cols;    // columns of the straggler schedule

@@ -1019,6 +1019,11 @@ static int mfma_upload(mudiff_ctx* h, MfmaSched& S, char* base, hipStream_t s) {
   HIP_TRY(hipMemcpyAsync(base + off[4], S.gnseg.data(), S.gnseg.size() * 4, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(base + off[5], S.gbase.data(), S.gbase.size() * 8, hipMemcpyHostToDevice, s));
   if (!h->sched_ev) HIP_TRY(hipEventCreateWithFlags(&h->sched_ev, hipEventDisableTiming));
+  if (S.c.circ && !h->aux) {
+    HIP_TRY(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming));
+  }
   HIP_TRY(hipEventRecord(h->sched_ev, s));
   h->sched_pending = true;
   S.dev_base = base;
@@ -1073,6 +1078,61 @@ static int mfma_launch(mudiff_ctx* h, const MfmaSched& S, const cplx* x, cplx* y
   prof_mark(h, s, 1);
   cplx* wh = nullptr;
   const int32_t* con = (const int32_t*)(base + off[11]);
+  // direct-form work (the work queue and the close-pair rows): in the straggler
+  // phase of a solve with the circulant form it runs on the second stream,
+  // beside the transforms and products, which share none of its outputs (there
+  // every launch is small and latency-bound; on a full batch the close-pair
+  // waves would crowd the products and transforms out of the compute units)
+  mf_fn fn = nullptr;  // checked before the fork, so that every error leaves the streams joined
+  if (S.n_items > 0) {
+    const int TL = 4 * kt + 16 * mt - 1;
+    auto pow2 = [](int v) { int r = 1; while (r < v) r <<= 1; return r; };
+    const int zk = pow2((4 * kt * RC + S.c.threads - 1) / S.c.threads);
+    const int tk = pow2((S.c.RP * TL + S.c.threads - 1) / S.c.threads);
+    fn = mf_select(mt, S.c.threads, zk, tk);
+    if (!fn) return fail(MUDIFF_ERR_INVALID, "no MFMA apply variant for this tile");
+  }
+  if (S.close_rows && (mt < 1 || mt > 4)) return fail(MUDIFF_ERR_INVALID, "close pairs: orders out of range");
+  hipStream_t cs = s;
+  const bool fork = h->mfma_tail && S.c.circ && (S.n_items > 0 || S.close_rows) && h->aux;
+  if (fork) {
+    HIP_TRY(hipEventRecord(h->fork_ev, s));
+    HIP_TRY(hipStreamWaitEvent(h->aux, h->fork_ev, 0));
+    cs = h->aux;
+  }
+  auto launch_direct = [&]() -> int {
+    if (S.n_items > 0) {
+      const int32_t* it = (const int32_t*)(base + off[1]);
+      // persistent grid: as many workgroups as are resident at once
+      int per_cu = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, S.c.threads, lds) !=
+              hipSuccess || per_cu < 1)
+        per_cu = 1;
+      const int grid = std::max(1, std::min(S.n_items, per_cu * h->n_cu));
+      hipLaunchKernelGGL(fn, dim3(grid), dim3(S.c.threads), lds, cs, h->dv, S.R, (const cplx*)z, active, it,
+                         S.n_items, head, part, S.blk, S.npad, kt, S.c.RP, S.c.CT,
+                         (const int32_t*)(base + off[3]), (const int32_t*)(base + off[9]));
+      HIP_TRY(hipGetLastError());
+    }
+    if (S.close_rows) {  // every row of the form writes its segment (zeros without close pairs)
+      typedef void (*close_fn)(DevView, int, const cplx*, cplx*, int64_t, int, const int32_t*,
+                               const int32_t*, const int64_t*, const int32_t*, const int32_t*,
+                               const int32_t*, const int32_t*);
+      static const close_fn kClose[5] = {nullptr, k_apply_close<1, 1>, k_apply_close<2, 2>,
+                                         k_apply_close<3, 2>, k_apply_close<4, 2>};
+      const unsigned zg = mt > 2 ? 2u : 1u;  // groups of two row tiles
+      hipLaunchKernelGGL(kClose[mt], dim3((unsigned)h->M_all, (unsigned)S.ntile, zg), dim3(64), 0, cs, h->dv,
+                         S.R, (const cplx*)z, part, S.blk, S.npad, (const int32_t*)(base + off[2]),
+                         (const int32_t*)(base + off[8]), (const int64_t*)(base + off[5]),
+                         (const int32_t*)(base + off[14]), (const int32_t*)(base + off[15]), con, active);
+      HIP_TRY(hipGetLastError());
+    }
+    return MUDIFF_OK;
+  };
+  if (fork) {
+    if ((rc = launch_direct()) != MUDIFF_OK) return rc;
+    HIP_TRY(hipEventRecord(h->join_ev, cs));
+  }
   if (S.c.circ) {  // well-separated pairs of the marked instances
     cplx* zh = (cplx*)(base + off[12]);
     wh = (cplx*)(base + off[13]);
@@ -1083,39 +1143,8 @@ static int mfma_launch(mudiff_ctx* h, const MfmaSched& S, const cplx* x, cplx* y
     prof_mark(h, s, 2);
     prof_mark(h, s, 3);
   }
-  if (S.n_items > 0) {
-    const int32_t* it = (const int32_t*)(base + off[1]);
-    const int TL = 4 * kt + 16 * mt - 1;
-    auto pow2 = [](int v) { int r = 1; while (r < v) r <<= 1; return r; };
-    const int zk = pow2((4 * kt * RC + S.c.threads - 1) / S.c.threads);
-    const int tk = pow2((S.c.RP * TL + S.c.threads - 1) / S.c.threads);
-    const mf_fn fn = mf_select(mt, S.c.threads, zk, tk);
-    if (!fn) return fail(MUDIFF_ERR_INVALID, "no MFMA apply variant for this tile");
-    // persistent grid: as many workgroups as are resident at once
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, S.c.threads, lds) !=
-            hipSuccess || per_cu < 1)
-      per_cu = 1;
-    const int grid = std::max(1, std::min(S.n_items, per_cu * h->n_cu));
-    hipLaunchKernelGGL(fn, dim3(grid), dim3(S.c.threads), lds, s, h->dv, S.R, (const cplx*)z, active, it,
-                       S.n_items, head, part, S.blk, S.npad, kt, S.c.RP, S.c.CT,
-                       (const int32_t*)(base + off[3]), (const int32_t*)(base + off[9]));
-    HIP_TRY(hipGetLastError());
-  }
-  if (S.close_rows) {  // every row of the form writes its segment (zeros without close pairs)
-    typedef void (*close_fn)(DevView, int, const cplx*, cplx*, int64_t, int, const int32_t*,
-                             const int32_t*, const int64_t*, const int32_t*, const int32_t*,
-                             const int32_t*, const int32_t*);
-    static const close_fn kClose[5] = {nullptr, k_apply_close<1, 1>, k_apply_close<2, 2>,
-                                       k_apply_close<3, 2>, k_apply_close<4, 2>};
-    if (mt < 1 || mt > 4) return fail(MUDIFF_ERR_INVALID, "close pairs: orders out of range");
-    const unsigned zg = mt > 2 ? 2u : 1u;  // groups of two row tiles
-    hipLaunchKernelGGL(kClose[mt], dim3((unsigned)h->M_all, (unsigned)S.ntile, zg), dim3(64), 0, s, h->dv,
-                       S.R, (const cplx*)z, part, S.blk, S.npad, (const int32_t*)(base + off[2]),
-                       (const int32_t*)(base + off[8]), (const int64_t*)(base + off[5]),
-                       (const int32_t*)(base + off[14]), (const int32_t*)(base + off[15]), con, active);
-    HIP_TRY(hipGetLastError());
-  }
+  if (fork) HIP_TRY(hipStreamWaitEvent(s, h->join_ev, 0));
+  else if ((rc = launch_direct()) != MUDIFF_OK) return rc;
   prof_mark(h, s, 4);
   if (S.c.circ) {
     rc = circ_finish(h, S.R, x, y, op, (const cplx*)part, S.blk, S.npad, RC,

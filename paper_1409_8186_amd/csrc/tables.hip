@@ -585,6 +585,12 @@ extern "C" int mudiff_destroy(mudiff_t h) {
   if (h) {
     sched_wait(h);  // no schedule upload still reads the handle's host vectors
     if (h->sched_ev) (void)hipEventDestroy(h->sched_ev);
+    if (h->aux) {
+      (void)hipStreamSynchronize(h->aux);
+      (void)hipStreamDestroy(h->aux);
+    }
+    if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
+    if (h->join_ev) (void)hipEventDestroy(h->join_ev);
     for (hipEvent_t e : h->prof_ev) (void)hipEventDestroy(e);
   }
   delete h;

@@ -29,7 +29,12 @@
  *               validate on the host, enqueue on `stream` and return; device
  *               outputs are valid after the stream is synchronised.
  *               mudiff_gmres and mudiff_grad synchronise `stream` themselves
- *               (once per restart cycle) to test convergence.
+ *               (once per restart cycle) to test convergence.  In the
+ *               straggler phase of a solve on the circulant form, part of an
+ *               apply runs on a second stream of the handle, forked from and
+ *               joined back into `stream` by events (so still ordered with
+ *               the caller's work); a handle is used by one host thread at a
+ *               time.
  *   batching    B independent instances (own disks, own k) share one handle.
  *               Instance b owns disks [disk_off[b], disk_off[b+1]).  Vectors
  *               are packed [B][R][N_b] with N_b = sum_{p in b} (2 N_p + 1):

@@ -2765,7 +2765,11 @@ extern "C" int mudiff_gmres(mudiff_t h, int R, const double* beta, const void* r
     (void)hipGraphExecDestroy(exec);
   }
   if (graph) (void)hipGraphDestroy(graph);
-  if (result != MUDIFF_OK) return result;
+  if (result != MUDIFF_OK) {
+    // later applies on the handle must not keep the straggler schedule
+    (void)apply_set_tail(h, R, false, G.apply_part, st, nullptr);
+    return result;
+  }
   hipLaunchKernelGGL(k_finish, dim3(cb), dim3(64), 0, st, s, flag, relres, iters);
   HIP_TRY(hipGetLastError());
   return apply_set_tail(h, R, false, G.apply_part, st, nullptr);  // back to the tuned schedule

@@ -1214,6 +1214,21 @@ static int mfma_autotune(mudiff_ctx* h, int R, const cplx* x, cplx* y, char* scr
     }
   if (cmode != 1 || !cu)
     for (const MfmaChoice& c : mfma_candidates(R)) cands.push_back(c);
+  // The direct form's work (8 flops per complex multiply-add over every
+  // ordered pair) at the FP64 matrix-core peak, 78.6 TFLOP/s: no direct tile
+  // beats it, so once a candidate's pair of applies is faster than twice that,
+  // the direct tiles are not timed.
+  double dflops = 0.0;
+  for (int b = 0; b < h->B; ++b) {
+    double sn = 0.0, sn2 = 0.0;
+    for (int64_t p = h->idisk[b]; p < h->idisk[b + 1]; ++p) {
+      const double n = 2.0 * h->N[(size_t)p] + 1.0;
+      sn += n;
+      sn2 += n * n;
+    }
+    dflops += 8.0 * R * (sn * sn - sn2);
+  }
+  const float direct_floor_ms = (float)(2.0 * dflops / 78.6e12 * 1e3);
   // one warm-up and two timed applies of candidate c; keeps the fastest (and
   // returns the time, 0 when skipped or failed)
   auto time_one = [&](const MfmaChoice& c) -> float {
@@ -1251,6 +1266,7 @@ static int mfma_autotune(mudiff_ctx* h, int R, const cplx* x, cplx* y, char* scr
   };
   for (const MfmaChoice& c : cands) {
     if (c.QS > 0 && mmax <= c.QS) continue;
+    if (!c.circ && best > 0.0f && direct_floor_ms > best) continue;
     time_one(c);
     if (rc != MUDIFF_OK) break;
   }

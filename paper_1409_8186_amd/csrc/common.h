@@ -186,6 +186,7 @@ struct MfmaSched {
   // nq, global disk indices), not as work-queue items
   bool close_rows = false;
   std::vector<int32_t> nptr, nq;
+  std::vector<int32_t> rord;  // row disks by decreasing close-pair work (launch order)
   int n_citems = 0, cvar = 0;
   void* dev_base = nullptr;  // apply scratch the device copy lives in
 };

@@ -594,8 +594,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_
     const int32_t* __restrict__ dgrp, const int32_t* __restrict__ drow,
     const int64_t* __restrict__ gbase, const int32_t* __restrict__ nptr,
     const int32_t* __restrict__ nql, const int32_t* __restrict__ con,
-    const int32_t* __restrict__ active) {
-  const int p = blockIdx.x, t = blockIdx.y, lane = threadIdx.x;
+    const int32_t* __restrict__ active, const int32_t* __restrict__ rord) {
+  // rows by decreasing work, so that the longest lists do not end the launch
+  const int p = rord[blockIdx.x], t = blockIdx.y, lane = threadIdx.x;
   const int mt0 = MTW * (int)blockIdx.z;  // first row tile of this wave
   const int b = v.inst[p];
   if (!con[b]) return;
@@ -672,20 +673,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_
 // value per panel element.
 __global__ void k_apply_mfma_scale(DevView v, int R, const cplx* __restrict__ x, cplx* __restrict__ z,
                                    const int32_t* __restrict__ active) {
-  const int64_t total = (int64_t)R * v.N_all;
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= total) return;
-  int lo = 0, hi = v.B;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if ((int64_t)R * v.imode[mid] <= g) lo = mid; else hi = mid;
-  }
-  const int64_t Nb = v.imode[lo + 1] - v.imode[lo];
-  const int64_t rem = g - (int64_t)R * v.imode[lo];
-  const int r = (int)(rem / Nb);
-  if (active && active[lo * R + r] == 0) return;  // columns that no longer iterate
-  const int64_t i = v.imode[lo] + (rem - (int64_t)r * Nb);
-  z[g] = col_scale(v, i, x[g]);
+  // blockIdx.x: column (b, r); blockIdx.y: 256-unknown slice of that column
+  const int col = blockIdx.x, b = col / R;
+  if (active && active[col] == 0) return;  // columns that no longer iterate
+  const int64_t Nb = v.imode[b + 1] - v.imode[b];
+  const int64_t k = (int64_t)blockIdx.y * 256 + threadIdx.x;
+  if (k >= Nb) return;
+  const int64_t g = (int64_t)R * v.imode[b] + (int64_t)(col - b * R) * Nb + k;
+  z[g] = col_scale(v, v.imode[b] + k, x[g]);
 }
 
 // y = finalize(sum over the segments of the MFMA partial blocks), one thread
@@ -786,6 +781,7 @@ static void mfma_build(const mudiff_ctx* h, int R, const MfmaChoice& c, MfmaSche
   S.citems.clear();
   S.nptr.clear();
   S.nq.clear();
+  S.rord.clear();
   S.close_rows = c.circ && h->circ && c.CT == 1;
   S.con.assign(h->B, 0);
   S.dgrp.assign(h->M_all, 0);
@@ -913,11 +909,20 @@ static void mfma_build(const mudiff_ctx* h, int R, const MfmaChoice& c, MfmaSche
   S.n_pb = pb;
   if (S.close_rows) {
     S.nptr.assign((size_t)h->M_all + 1, 0);
+    std::vector<int64_t> work((size_t)h->M_all, 0);  // k steps x row tiles of each row's list
     for (int p = 0; p < h->M_all; ++p) {
       if (S.con[(size_t)h->inst[p]])
-        for (int64_t e = h->near_off[p]; e < h->near_off[p + 1]; ++e) S.nq.push_back(h->near[(size_t)e]);
+        for (int64_t e = h->near_off[p]; e < h->near_off[p + 1]; ++e) {
+          const int32_t q = h->near[(size_t)e];
+          S.nq.push_back(q);
+          work[(size_t)p] += (int64_t)((2 * h->N[q] + 4) / 4) * ((2 * h->N[p] + 16) / 16);
+        }
       S.nptr[(size_t)p + 1] = (int32_t)S.nq.size();
     }
+    S.rord.resize((size_t)h->M_all);
+    for (int p = 0; p < h->M_all; ++p) S.rord[(size_t)p] = p;
+    std::stable_sort(S.rord.begin(), S.rord.end(),
+                     [&](int32_t u, int32_t w) { return work[(size_t)u] > work[(size_t)w]; });
   }
   std::stable_sort(its.begin(), its.end(), [](const It& a, const It& b) { return a.cost > b.cost; });
   S.items.resize(its.size() * MF_REC);
@@ -930,7 +935,7 @@ static void mfma_build(const mudiff_ctx* h, int R, const MfmaChoice& c, MfmaSche
 // Byte layout of the MFMA schedule inside the apply scratch:
 // [head][items][dgrp][grow][gnseg][gbase][partial blocks][scaled input][drow]
 // [qlist][product items][con][transformed inputs][transformed outputs]
-#define MF_NOFF 16
+#define MF_NOFF 17
 static size_t mfma_scratch_layout(const mudiff_ctx* h, const MfmaSched& S, size_t* off) {
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -955,6 +960,7 @@ static size_t mfma_scratch_layout(const mudiff_ctx* h, const MfmaSched& S, size_
   off[13] = take(zw);
   off[14] = take(S.nptr.size() * 4);  // close lists of the 8-column tiles
   off[15] = take(S.nq.size() * 4);
+  off[16] = take(S.rord.size() * 4);
   return o;
 }
 
@@ -1012,6 +1018,8 @@ static int mfma_upload(mudiff_ctx* h, MfmaSched& S, char* base, hipStream_t s) {
     HIP_TRY(hipMemcpyAsync(base + off[14], S.nptr.data(), S.nptr.size() * 4, hipMemcpyHostToDevice, s));
   if (!S.nq.empty())
     HIP_TRY(hipMemcpyAsync(base + off[15], S.nq.data(), S.nq.size() * 4, hipMemcpyHostToDevice, s));
+  if (!S.rord.empty())
+    HIP_TRY(hipMemcpyAsync(base + off[16], S.rord.data(), S.rord.size() * 4, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(base + off[1], S.items.data(), S.items.size() * 4, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(base + off[2], S.dgrp.data(), (size_t)h->M_all * 4, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(base + off[3], S.grow.data(), S.grow.size() * 4, hipMemcpyHostToDevice, s));
@@ -1071,9 +1079,11 @@ static int mfma_launch(mudiff_ctx* h, const MfmaSched& S, const cplx* x, cplx* y
   int rc = launch_fill_zero(head, 4, s);
   if (rc != MUDIFF_OK) return rc;
   cplx* z = (cplx*)(base + off[7]);
-  const int64_t nz = (int64_t)S.R * h->N_all;
-  hipLaunchKernelGGL(k_apply_mfma_scale, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, s, h->dv,
-                     S.R, x, z, active);
+  int64_t nbmax = 0;  // longest instance vector
+  for (int b = 0; b < h->B; ++b) nbmax = std::max(nbmax, h->imode[b + 1] - h->imode[b]);
+  if ((nbmax + 255) / 256 > 65535) return fail(MUDIFF_ERR_INVALID, "instance too large for the input scaling grid");
+  hipLaunchKernelGGL(k_apply_mfma_scale, dim3((unsigned)(h->B * S.R), (unsigned)((nbmax + 255) / 256)), dim3(256),
+                     0, s, h->dv, S.R, x, z, active);
   HIP_TRY(hipGetLastError());
   prof_mark(h, s, 1);
   cplx* wh = nullptr;
@@ -1117,14 +1127,15 @@ static int mfma_launch(mudiff_ctx* h, const MfmaSched& S, const cplx* x, cplx* y
     if (S.close_rows) {  // every row of the form writes its segment (zeros without close pairs)
       typedef void (*close_fn)(DevView, int, const cplx*, cplx*, int64_t, int, const int32_t*,
                                const int32_t*, const int64_t*, const int32_t*, const int32_t*,
-                               const int32_t*, const int32_t*);
+                               const int32_t*, const int32_t*, const int32_t*);
       static const close_fn kClose[5] = {nullptr, k_apply_close<1, 1>, k_apply_close<2, 2>,
                                          k_apply_close<3, 2>, k_apply_close<4, 2>};
       const unsigned zg = mt > 2 ? 2u : 1u;  // groups of two row tiles
       hipLaunchKernelGGL(kClose[mt], dim3((unsigned)h->M_all, (unsigned)S.ntile, zg), dim3(64), 0, cs, h->dv,
                          S.R, (const cplx*)z, part, S.blk, S.npad, (const int32_t*)(base + off[2]),
                          (const int32_t*)(base + off[8]), (const int64_t*)(base + off[5]),
-                         (const int32_t*)(base + off[14]), (const int32_t*)(base + off[15]), con, active);
+                         (const int32_t*)(base + off[14]), (const int32_t*)(base + off[15]), con, active,
+                         (const int32_t*)(base + off[16]));
       HIP_TRY(hipGetLastError());
     }
     return MUDIFF_OK;
